@@ -1,0 +1,190 @@
+"""Pins of the oracle's full scheme: invariants the paper states and exact
+solutions it compares against."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from exact_riemann import sample, star_state  # noqa: E402
+
+from oracle.scheme import Config, GTSSolver, Solver  # noqa: E402
+from workloads import (cell_average, sod_primitive, square_graded_mesh, strip_mesh,  # noqa: E402
+                       vortex_case)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def graded():
+    return square_graded_mesh(0.3, seed=2)
+
+
+def test_golden_sod_star_state():
+    vals = {}
+    for line in open(os.path.join(GOLDEN, "sod_star_state.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = float(v)
+    p, u, rl, rr = star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert abs(p - vals["p_star"]) < 1e-5
+    assert abs(u - vals["u_star"]) < 1e-5
+    assert abs(rl - vals["rho_star_left"]) < 1e-5
+    assert abs(rr - vals["rho_star_right"]) < 1e-5
+
+
+@pytest.mark.parametrize("M", [1, 2])
+def test_lts_one_level_equals_gts(M):
+    """LTS with a single level is global time stepping (separate driver)."""
+    mesh, Q0 = vortex_case(900, seed=5)
+    cfg = Config(M=M, levels=1)
+    lts = Solver(mesh.nodes, mesh.tris, Q0, cfg)
+    lts.run(1.0, max_macro_steps=4)
+    gts = GTSSolver(mesh.nodes, mesh.tris, Q0, cfg, topo=lts.topo)
+    gts.run(1.0, max_steps=4)
+    assert abs(gts.T - lts.st.T) < 1e-15
+    assert np.abs(gts.Q - lts.st.Q).max() < 1e-14 * np.abs(gts.Q).max()
+    assert np.abs(gts.X - lts.st.X).max() < 1e-14
+
+
+def test_lts_one_level_equals_gts_with_walls():
+    """Same check on the shock tube with slip walls and transmissive ends."""
+    mesh = strip_mesh(-0.5, 0.5, 0.0, 0.1, 0.02, seed=3, slip_y=True)
+    Q0 = cell_average(mesh, sod_primitive, 1.4)
+    cfg = Config(M=2, levels=1)
+    lts = Solver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+    lts.run(1.0, max_macro_steps=4)
+    gts = GTSSolver(mesh.nodes, mesh.tris, Q0, cfg, topo=lts.topo)
+    gts.run(1.0, max_steps=4)
+    assert np.abs(gts.Q - lts.st.Q).max() < 1e-14 * np.abs(gts.Q).max()
+    assert np.abs(gts.X - lts.st.X).max() < 1e-14
+    # wall nodes slide along the walls
+    on_wall = (mesh.nodes[:, 1] == 0.0) | (mesh.nodes[:, 1] == 0.1)
+    assert np.array_equal(lts.st.X[on_wall, 1], mesh.nodes[on_wall, 1])
+
+
+def _swirl(x, y, t):
+    return (0.3 + 0.2 * np.sin(0.9 * x) * np.cos(0.7 * y + t),
+            -0.2 + 0.2 * np.cos(0.8 * x + 0.5 * t) * np.sin(0.6 * y))
+
+
+@pytest.mark.parametrize("M", [1, 2])
+def test_free_stream_on_deforming_mesh_lts(graded, M):
+    """A constant state stays constant on a mesh deformed by a prescribed
+    velocity, with hanging nodes in time (3 levels): the discrete GCL
+    (eq. eqn.gcl) holds to round-off."""
+    Q = np.array([1.2, 0.3, -0.1, 2.7])
+    Q0 = np.tile(Q, (graded.n_elems, 1))
+    cfg = Config(M=M, levels=3, mesh_velocity=_swirl)
+    s = Solver(graded.nodes, graded.tris, Q0, cfg)
+    s.macro_begin(10.0)
+    assert len(np.unique(s.st.s)) >= 2                    # several levels in use
+    s.run(10.0, max_macro_steps=2)
+    st = s.st
+    assert st.updates < st.cycles * graded.n_elems       # genuinely local steps
+    assert np.abs(st.Q - Q).max() < 1e-13
+    assert st.max_gcl < 1e-14
+    assert np.abs(st.X - graded.nodes).max() > 1e-3      # the mesh really moved
+
+
+def test_conservation_and_gcl_every_cycle():
+    """sum(|T|Q + Q^M) + boundary outflow is constant at every cycle (memory
+    variables keep the scheme conservative, Sec. 2.5)."""
+    mesh, Q0 = vortex_case(1200, seed=4)
+    s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=2, levels=3))
+    c0 = s.conserved_total()
+    s.macro_begin(1.0)
+    ncyc = 0
+    while (s.st.n < s.st.N).any():
+        s.cycle()
+        ncyc += 1
+        drift = np.abs(s.conserved_total() - c0) / np.abs(c0).max()
+        assert drift.max() < 1e-13
+    assert ncyc >= 4
+    assert s.st.max_gcl < 1e-13
+
+
+def test_no_deadlock_with_random_levels(graded):
+    """With symmetric scheduling stencils some element is always active and
+    co-active elements sharing a node agree on its new time (discussion after
+    eq. eqn.WENOupdate)."""
+    rng = np.random.default_rng(0)
+    s = Solver(graded.nodes, graded.tris, np.tile([1.0, 0, 0, 2.5], (graded.n_elems, 1)),
+               Config(M=1, levels=4))
+    st, topo = s.st, s.topo
+    st.N = 8
+    for trial in range(3):
+        st.n[:] = 0
+        st.s[:] = rng.choice([1, 2, 4, 8], size=topo.n_elems)
+        cycles = 0
+        while (st.n < st.N).any():
+            act = s.active_set()
+            assert act.size > 0
+            fut = st.n + st.s
+            owner = {}
+            for i in act:
+                for k in topo.tris[i]:
+                    if k in owner:
+                        assert owner[k] == fut[i]
+                    owner[k] = fut[i]
+            st.n[act] = fut[act]
+            for i in act:
+                n = int(st.n[i])
+                st.s[i] = 0 if n >= st.N else min(int(rng.choice([1, 2, 4, 8])), n & -n)
+            cycles += 1
+            assert cycles < 200
+        assert (st.n == st.N).all()
+
+
+def _l1_density_error(mesh_h, M, t_end):
+    mesh = strip_mesh(-0.5, 0.5, 0.0, 0.1, mesh_h, seed=1408, slip_y=True)
+    Q0 = cell_average(mesh, sod_primitive, 1.4)
+    s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=M, levels=1), bedges=mesh.bedges)
+    s.run(t_end)
+    xc = s.st.Xe.mean(axis=1)[:, 0]
+    ex = sample((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), xc / t_end)
+    return float((np.abs(s.st.Q[:, 0] - ex[:, 0]) * s.st.A).sum() / s.st.A.sum()), s
+
+
+def test_sod_against_exact_solution():
+    """RP1 (paper Sec. 3.2): density approaches the exact Riemann solution and
+    the L1 error drops under mesh refinement; mass is conserved exactly."""
+    e1, s1 = _l1_density_error(0.03, 2, 0.04)
+    e2, s2 = _l1_density_error(0.02, 2, 0.04)
+    assert e2 < 0.9 * e1, (e1, e2)
+    assert e2 < 0.01, e2
+    # the star-region velocity plateau of the exact solution
+    u = s2.st.Q[:, 1] / s2.st.Q[:, 0]
+    xc = s2.st.Xe.mean(axis=1)[:, 0] / 0.04
+    plateau = (xc > 0.2) & (xc < 0.8)
+    _, ustar, _, _ = star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert abs(np.median(u[plateau]) - ustar) < 0.1     # plateau is 1-2 cells wide here
+    mass0 = 0.5 * 0.1 * 1.0 + 0.5 * 0.1 * 0.125
+    tot = s2.conserved_total()[0]
+    assert abs(tot - mass0) < 1e-3            # initial averaging of the jump
+    assert s2.st.max_gcl < 1e-13
+
+
+@pytest.mark.slow
+def test_vortex_convergence_order():
+    """Smooth isentropic vortex (paper Sec. 3.1): L2(rho) order close to M+1."""
+    from oracle import tables as tb
+    from oracle.scheme import affine_map
+    from workloads import vortex_primitive
+    errs = []
+    hs = []
+    for n in (1000, 4000):
+        mesh, Q0 = vortex_case(n, seed=1)
+        s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=2, levels=3))
+        s.run(0.2)
+        xi, eta, w = tb.duffy_rule(4)
+        x = affine_map(s.st.Xe, xi, eta)
+        ex = vortex_primitive(x[..., 0] - 0.2, x[..., 1] - 0.2)[..., 0]
+        psi_nodes = tb.eval_phi(2, xi, eta)          # nodal reconstruction
+        wh = np.einsum("qm,em->eq", psi_nodes, s.st.wnod[..., 0])
+        e2 = (((wh - ex) ** 2) * w[None, :]).sum(axis=1) * 2 * s.st.A
+        errs.append(np.sqrt(e2.sum()))
+        hs.append(np.sqrt(s.st.A.mean()))
+    order = np.log(errs[0] / errs[1]) / np.log(hs[0] / hs[1])
+    assert order > 2.3, (errs, order)
