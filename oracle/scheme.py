@@ -338,7 +338,7 @@ def patch_batch(M, cfg: Config, P, ticks, nL, sL, trL, nR, sR, trR, hasR, bc=Non
                 sRs = np.where(hasR, sR, 1)
                 lR = tb.lagrange_time(M, (tk - nR) / sRs)
                 qrr = np.einsum("eq,eqv->ev", lR, trR[:, nG - 1 - g])
-                qr = np.where(hasR[:, None], qrr, ql)
+                qr = np.where(hasR[:, None], qrr, qr)
             wgt = wc[g] * wc[h]
             G += wgt * rusanov_flux(ql, qr, N, cfg.gamma)
             Nint += wgt * N

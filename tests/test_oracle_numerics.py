@@ -245,3 +245,25 @@ def test_rusanov_reduces_to_eulerian_flux():
     N = np.array([n[0], n[1], -0.3])
     F2 = rusanov_flux(ql, ql, N, GAMMA)
     assert np.allclose(F2, fn(ql) - 0.3 * ql, atol=1e-15)
+
+
+def test_slip_wall_carries_no_mass_or_energy_flux():
+    """A static slip wall (mirror state) passes only the pressure force, also
+    when the same batch holds interior edges."""
+    M = 1
+    Q = np.array([1.3, 0.4, -0.7, 3.1])
+    dt = 0.2
+    a, b = np.array([0.0, 0.0]), np.array([1.0, 0.0])
+    P = np.array([[[*a, 0], [*b, 0], [*b, dt], [*a, dt]]] * 2)
+    ticks = np.tile([0.0, 0.0, 4.0, 4.0], (2, 1))
+    tr = _const_trace(Q, M, E=2)
+    one = np.ones(2, np.int64) * 4
+    zero = np.zeros(2, np.int64)
+    hasR = np.array([False, True])
+    bc = np.array([2, 0])
+    G, Nint = patch_batch(M, Config(M=M), P, ticks, zero, one, tr, zero, one, tr, hasR, bc)
+    p = (GAMMA - 1) * (Q[3] - 0.5 * (Q[1] ** 2 + Q[2] ** 2) / Q[0])
+    assert abs(G[0, 0]) < 1e-15 and abs(G[0, 3]) < 1e-15          # no mass, no work
+    assert abs(G[0, 1]) < 1e-15                                    # no tangential force
+    assert G[0, 2] / Nint[0, 1] > p                                # pressure plus impact
+    assert abs(G[1, 0] - Q[2] * Nint[1, 1]) < 1e-15                # interior edge unaffected
