@@ -1,0 +1,192 @@
+/*
+ * aderweno.h -- C ABI of the MI355X (gfx950) implementation of the cell-centred
+ * direct ALE ADER-WENO finite volume scheme with time-accurate local time
+ * stepping (LTS) for the 2D Euler equations on moving triangular meshes
+ * (Boscheri, Dumbser, Zanotti, arXiv:1408.3719).
+ *
+ * Problem statement (paper Sec. 2.1, eqs. PDE, trian, xietaTransf,
+ * eqn.cellaverage): a conforming triangulation whose elements carry cell
+ * averages Q = (rho, rho u, rho v, rho E) of the Euler equations (Sec. 3,
+ * eqs. eulerTerms, eqn.eos); the mesh moves with the local fluid velocity
+ * (V = v, Sec. 3) and every element advances with its own time step.
+ *
+ * Conventions
+ *   - Ownership: the library owns the context and its host copy of the
+ *     topology.  The caller owns the device workspace and every *_dev buffer
+ *     (FP64, contiguous); the library never frees caller memory.
+ *   - Streams: all device work is queued on the HIP stream given at
+ *     creation.  Calls that return host values synchronise that stream.
+ *   - Errors: every int-returning call returns 0 on success or a negative
+ *     ADER_E_* code; ader_last_error() then holds a message.  Nothing throws
+ *     across the ABI.  After a stepping error the device state is undefined;
+ *     restore a saved state with ader_upload_state.
+ *   - Threads: one context per host thread.
+ *   - Call order: ader_create -> ader_upload_mesh -> ader_workspace_size ->
+ *     ader_bind_workspace -> ader_upload_state -> ader_step_* ...;
+ *     out-of-order calls return ADER_E_ORDER.
+ */
+#ifndef ADERWENO_H
+#define ADERWENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ADER_OK = 0,
+  ADER_E_ARG = -1,      /* invalid argument (null pointer, size, range)              */
+  ADER_E_MESH = -2,     /* clockwise/degenerate triangle, non-manifold, bad boundary */
+  ADER_E_STATE = -3,    /* rho <= 0, p <= 0 or NaN after an update                   */
+  ADER_E_GEOM = -4,     /* element inverted by the mesh motion                        */
+  ADER_E_GCL = -5,      /* space-time volume not closed (geometric conservation law) */
+  ADER_E_DEADLOCK = -6, /* no element satisfies the update criterion                  */
+  ADER_E_HIP = -7,      /* HIP runtime error                                          */
+  ADER_E_ORDER = -8     /* call out of sequence                                       */
+};
+
+/* Boundary tags of ader_upload_mesh. */
+enum { ADER_BC_TRANSMISSIVE = 1, ADER_BC_SLIP = 2 };
+
+typedef struct ader_ctx ader_ctx;
+
+/* Scheme parameters (paper Sec. 2.2 after eq. Sigma, eq. eqn.timestep). */
+typedef struct {
+  int32_t M;             /* polynomial degree 1..3; order of accuracy M+1              */
+  int32_t flux;          /* 0 = Rusanov ALE flux (eq. eqn.rusanov); others rejected    */
+  double gamma;          /* ratio of specific heats (eq. eqn.eos)                      */
+  double cfl;            /* CFL number of eq. eqn.timestep, (0, 0.5]                   */
+  int32_t lts_levels;    /* L in 1..8: dyadic levels used by ader_step_lts             */
+  int32_t n_picard;      /* Picard sweeps of the predictor; 0 -> M+1                   */
+  int32_t mesh_velocity; /* 0 = Lagrangian (V = v), 1 = Eulerian (V = 0)               */
+  double weno_eps;       /* epsilon of the WENO weights (paper: 1e-14)                 */
+  double weno_r;         /* exponent r (paper: 8; only 8 is supported)                 */
+  double weno_lambda;    /* central-stencil linear weight lambda_1 (paper: 1e5)        */
+} ader_config;
+
+typedef struct {
+  int64_t element_updates; /* sum over cycles of the active-set size                   */
+  int64_t cycles;          /* cycles run (a cycle = one pass of the update criterion)  */
+  int64_t macro_steps;     /* dyadic macro steps completed                             */
+  int64_t cfl_overshoots;  /* element steps longer than their CFL bound (level capped) */
+  double max_gcl_residual; /* max |closure of the space-time volume| / (|T|+|T'|)      */
+  double t;                /* common time of all elements (they meet at macro steps)   */
+  double delta;            /* tick length of the last macro step                       */
+  int64_t predictor_evals; /* element predictors computed                              */
+  int64_t patches;         /* space-time patches integrated                            */
+  int64_t node_moves;      /* node motions                                             */
+} ader_stats;
+
+/* Create a context.  hip_stream: a hipStream_t (NULL = default stream).
+ * Allocates host memory only; no device call is made. */
+int ader_create(const ader_config* cfg, void* hip_stream, ader_ctx** out);
+
+/* Mesh topology and initial node positions (paper eqs. trian, xietaTransf).
+ * node_xy: host [n_nodes][2]; tri: host [n_elems][3], counter-clockwise;
+ * bedge: host [n_bedges][3] = (node a, node b, tag) for every boundary edge,
+ * oriented with the interior on the left of a->b.  Builds, on the host, the
+ * edges, node rings, the 7 WENO stencils of n_e = (M+1)(M+2) elements and
+ * the symmetric scheduling stencils (eqs. stencil, eqn.WENOstencil and the
+ * discussion after eqn.WENOupdate).  No device call.  ADER_E_MESH on a
+ * clockwise or degenerate triangle, a non-manifold edge, a boundary list
+ * that does not match the mesh, or a mesh too small for the central stencil. */
+int ader_upload_mesh(ader_ctx* ctx, int32_t n_nodes, const double* node_xy,
+                     int32_t n_elems, const int32_t* tri,
+                     int32_t n_bedges, const int32_t* bedge);
+
+/* Device bytes needed for state, topology and scratch of this mesh. */
+int ader_workspace_size(const ader_ctx* ctx, size_t* bytes);
+
+/* Hand the library a caller-owned device buffer of at least
+ * ader_workspace_size bytes (256-byte aligned).  It must outlive the context.
+ * Copies the topology and tables to it (synchronises the stream). */
+int ader_bind_workspace(ader_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Initial cell averages, device [4][n_elems] SoA (rho, rho u, rho v, rho E),
+ * at time t0, on the mesh of ader_upload_mesh.  Runs the pre-processing of
+ * the paper (Sec. 2.6): first reconstruction without projection and first
+ * CFL time step of every element.  ADER_E_STATE on rho <= 0 or p <= 0. */
+int ader_upload_state(ader_ctx* ctx, const double* Q_dev, double t0);
+
+/* Global time stepping up to t_target (at most max_steps steps; <= 0 means
+ * no limit): one level, every element updates in every step. */
+int ader_step_gts(ader_ctx* ctx, double t_target, int32_t max_steps, ader_stats* st);
+
+/* Local time stepping up to t_target in at most max_macro_steps macro steps
+ * (<= 0: no limit).  A macro step has 2^(L-1) ticks of length delta = the
+ * smallest CFL step at its start; each element steps 2^(L-1-level) ticks
+ * under the update criterion of eq. eqn.WENOupdate over its scheduling
+ * stencil; all elements meet again at the end of the macro step. */
+int ader_step_lts(ader_ctx* ctx, double t_target, int32_t max_macro_steps, ader_stats* st);
+
+/* Current state into caller device buffers (any may be NULL):
+ * Q_dev [4][n_elems] SoA, node_xy_dev [n_nodes][2], elem_t_dev [n_elems]. */
+int ader_download_state(ader_ctx* ctx, double* Q_dev, double* node_xy_dev, double* elem_t_dev);
+
+/* Cumulative statistics since ader_upload_state (synchronises). */
+int ader_get_stats(ader_ctx* ctx, ader_stats* st);
+
+/* ---- Test hooks: raw access to internal arrays ----------------------------
+ * ader_debug_dump copies the array `what` to host memory; ader_debug_inject
+ * overwrites it from host memory.  `bytes` must equal the array size returned
+ * by ader_debug_size.  Topology arrays (ADER_DBG_TOPO_*, ADER_DBG_TAB_*) live
+ * on the host and are available right after ader_upload_mesh with no device.
+ * Layouts (NE elements, NV nodes, NF edges, nb = (M+1)(M+2)/2, T = M+1, nG = M+1):
+ *   Q [4][NE]  A [NE]  XE [6][NE] (x0 y0 x1 y1 x2 y2)  TICK, STEP [NE] int32
+ *   DTCFL [NE]  QM [4][NE]  HM [3][NE]  WNOD [nb][4][NE]  AVG [T][4][NE]
+ *   TRACE [3][nG][T][4][NE]  VVEL [3][T][2][NE]  X [2][NV]  NTICK [NV] int32
+ *   SCAL [4] double: T, delta, N (as double), t_end
+ *   TOPO_EDGES [NF][6] int32: a, b, L, R, local edge in L, in R (-1)
+ *   TOPO_STENCILS [NE][7][n_e] int32 (-1 rows: dropped sector stencil)
+ *   TOPO_SCHED_PTR [NE+1] int32, TOPO_SCHED_IDX [nnz] int32
+ *   TAB_* host tables: see ader_debug_size. */
+enum {
+  ADER_DBG_Q = 0, ADER_DBG_A, ADER_DBG_XE, ADER_DBG_TICK, ADER_DBG_STEP, ADER_DBG_DTCFL,
+  ADER_DBG_QM, ADER_DBG_HM, ADER_DBG_WNOD, ADER_DBG_AVG, ADER_DBG_TRACE, ADER_DBG_VVEL,
+  ADER_DBG_X, ADER_DBG_NTICK, ADER_DBG_SCAL,
+  ADER_DBG_TOPO_EDGES = 32, ADER_DBG_TOPO_STENCILS, ADER_DBG_TOPO_SCHED_PTR,
+  ADER_DBG_TOPO_SCHED_IDX,
+  ADER_DBG_TAB_DXI = 48, ADER_DBG_TAB_DETA, ADER_DBG_TAB_AMEAN, ADER_DBG_TAB_EDGE,
+  ADER_DBG_TAB_AT, ADER_DBG_TAB_BT, ADER_DBG_TAB_DT, ADER_DBG_TAB_PSIC, ADER_DBG_TAB_SIGMA,
+  ADER_DBG_TAB_GAUSS
+};
+int ader_debug_size(const ader_ctx* ctx, int32_t what, size_t* bytes);
+int ader_debug_dump(ader_ctx* ctx, int32_t what, void* host, size_t bytes);
+int ader_debug_inject(ader_ctx* ctx, int32_t what, const void* host, size_t bytes);
+
+/* Test hook: run `n` cycles of the current macro step (no macro boundary
+ * handling), or begin a macro step (levels and predictors) toward t_end. */
+int ader_debug_cycles(ader_ctx* ctx, int32_t n);
+int ader_debug_macro_begin(ader_ctx* ctx, double t_end, int32_t levels);
+
+/* Per-kernel timing for benchmarks: HIP events recorded around every kernel
+ * launch on the context's stream.  ader_set_profiling(ctx, 1) clears the
+ * totals and starts recording, 0 stops.  ader_kernel_times synchronises and
+ * writes, for each kernel id k < n (ADER_K_*), the summed milliseconds and
+ * the number of launches since profiling was switched on. */
+enum {
+  ADER_K_SCHED = 0,   /* update criterion and active-list compaction            */
+  ADER_K_NODE,        /* node solver and node motion                            */
+  ADER_K_PATCH,       /* space-time patch fluxes                                */
+  ADER_K_UPDATE,      /* memory variables and conservative update               */
+  ADER_K_RECON,       /* virtual projection, WENO, CFL step and level           */
+  ADER_K_PREDICT,     /* space-time predictor                                   */
+  ADER_K_MACRO,       /* macro-step boundary: min CFL step, levels              */
+  ADER_K_STATUS,      /* unfinished-element count                               */
+  ADER_K_COUNT
+};
+int ader_set_profiling(ader_ctx* ctx, int32_t on);
+int ader_kernel_times(ader_ctx* ctx, int32_t n, double* total_ms, int64_t* launches);
+
+/* Message of the last error on this context (never NULL). */
+const char* ader_last_error(const ader_ctx* ctx);
+
+/* Free the context (not the caller's workspace). */
+void ader_destroy(ader_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADERWENO_H */

@@ -569,12 +569,15 @@ class Solver:
         st.nk = newtick
         Xn = st.X[topo.tris[act]]
         An = tri_area(Xn)
-        if (An <= 0).any():
-            raise FloatingPointError("element inverted during the update")
+        if not (An > 0).all():
+            raise FloatingPointError("element inverted (or not finite) during the update")
         gcl = st.HM[act] - np.stack([np.zeros_like(An), np.zeros_like(An), An - st.A[act]], 1)
         rel = np.abs(gcl).max(axis=1) / (An + st.A[act])
         st.max_gcl = max(st.max_gcl, float(rel.max()))
         st.Q[act] = (st.A[act, None] * st.Q[act] + st.QM[act]) / An[:, None]
+        _, _, _, pn = euler.primitives(st.Q[act], cfg.gamma)
+        if not ((st.Q[act, 0] > 0).all() and (pn > 0).all()):
+            raise FloatingPointError("non-physical state (rho <= 0, p <= 0 or not finite)")
         st.QM[act] = 0.0
         st.HM[act] = 0.0
         st.A[act] = An

@@ -1,0 +1,652 @@
+// C ABI of the aderweno library: context, workspace, upload/download and the
+// host side of the time stepping loops.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/aderweno.h"
+#include "common.h"
+#include "host.h"
+
+struct ader_ctx {
+  ader_config cfg{};
+  aw::Params prm{};
+  hipStream_t stream = nullptr;
+  bool has_mesh = false, bound = false, has_state = false;
+  aw::Topology topo;
+  aw::Tables tab{};
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  aw::Dev dev{};
+  std::string err;
+  int cycle = 0;            // stamp of the last cycle launched (never reused)
+  int64_t cycles = 0, macro_steps = 0;
+  // profiling
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ADER_K_COUNT];
+  double kms[ADER_K_COUNT] = {};
+  int64_t klaunch[ADER_K_COUNT] = {};
+};
+
+namespace {
+
+int fail(ader_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(ader_ctx* c, int e, const char* where) {
+  return fail(c, ADER_E_HIP, std::string(where) + ": " + hipGetErrorString(hipError_t(e)));
+}
+
+#define HIPCHK(ctx, expr)                                          \
+  do {                                                             \
+    hipError_t _e = (expr);                                        \
+    if (_e != hipSuccess) return hip_fail(ctx, int(_e), #expr);    \
+  } while (0)
+
+#define LCHK(ctx, expr)                                            \
+  do {                                                             \
+    int _e = (expr);                                               \
+    if (_e != 0) return hip_fail(ctx, _e, #expr);                  \
+  } while (0)
+
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    size_t off = total;
+    total += (bytes + 255) & ~size_t(255);
+    return off;
+  }
+};
+
+// Workspace carving; when base == nullptr only the size is computed.
+size_t carve(ader_ctx* c, char* base) {
+  const aw::Topology& t = c->topo;
+  const int M = c->cfg.M;
+  const int nb = (M + 1) * (M + 2) / 2, nt = M + 1, nG = M + 1, ne = 2 * nb;
+  const size_t NE = t.NE, NV = t.NV, NF = t.NF, D = sizeof(double), I = sizeof(int);
+  Layout L;
+  aw::Dev& d = c->dev;
+  auto pd = [&](size_t n) { size_t o = L.take(n * D); return base ? (double*)(base + o) : nullptr; };
+  auto pi = [&](size_t n) { size_t o = L.take(n * I); return base ? (int*)(base + o) : nullptr; };
+  size_t o_scal = L.take(sizeof(aw::Scal));
+  size_t o_tab = L.take(sizeof(aw::Tables));
+  d.NE = t.NE;
+  d.NV = t.NV;
+  d.NF = t.NF;
+  d.nsched = int(t.sched_idx.size());
+  d.nring = int(t.ring_ent.size());
+  d.scal = base ? (aw::Scal*)(base + o_scal) : nullptr;
+  d.tab = base ? (const aw::Tables*)(base + o_tab) : nullptr;
+  d.Q = pd(4 * NE);
+  d.A = pd(NE);
+  d.Xe = pd(6 * NE);
+  d.dtcfl = pd(NE);
+  d.QM = pd(4 * NE);
+  d.HM = pd(3 * NE);
+  d.wnod = pd(size_t(nb) * 4 * NE);
+  d.avg = pd(size_t(nt) * 4 * NE);
+  d.trace = pd(size_t(3) * nG * nt * 4 * NE);
+  d.vvel = pd(size_t(3) * nt * 2 * NE);
+  d.tick = pi(NE);
+  d.step = pi(NE);
+  d.act_stamp = pi(NE);
+  d.act_list = pi(NE);
+  d.tri = pi(3 * NE);
+  d.elem_edges = pi(3 * NE);
+  d.neigh = pi(3 * NE);
+  d.sten = pi(size_t(aw::NSTEN) * ne * NE);
+  d.sched_ptr = pi(NE + 1);
+  d.sched_idx = pi(t.sched_idx.size());
+  d.X = pd(2 * NV);
+  d.Xnew = pd(2 * NV);
+  d.ntick = pi(NV);
+  d.ntick_new = pi(NV);
+  d.node_stamp = pi(NV);
+  d.ring_ptr = pi(NV + 1);
+  d.ring_ent = pi(t.ring_ent.size());
+  d.wall_n = pd(2 * NV);
+  d.wall_pin = pi(NV);
+  d.e_a = pi(NF);
+  d.e_b = pi(NF);
+  d.e_L = pi(NF);
+  d.e_R = pi(NF);
+  d.e_el = pi(NF);
+  d.e_er = pi(NF);
+  d.e_bc = pi(NF);
+  d.G = pd(4 * NF);
+  d.Nint = pd(3 * NF);
+  d.edge_stamp = pi(NF);
+  d.out_xy = nullptr;
+  return L.total;
+}
+
+template <class T>
+std::vector<T> to_soa(const std::vector<T>& aos, size_t n, size_t f) {
+  std::vector<T> out(aos.size());
+  for (size_t i = 0; i < n; ++i)
+    for (size_t k = 0; k < f; ++k) out[k * n + i] = aos[i * f + k];
+  return out;
+}
+
+int h2d(ader_ctx* c, const void* dst, const void* src, size_t bytes) {
+  HIPCHK(c, hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyHostToDevice, c->stream));
+  return 0;
+}
+
+// Fold finished event pairs into the per-kernel totals (stream synchronised).
+void flush_events(ader_ctx* c) {
+  for (int k = 0; k < ADER_K_COUNT; ++k) {
+    for (auto& p : c->ev[k]) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) c->kms[k] += ms;
+      c->klaunch[k]++;
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+    c->ev[k].clear();
+  }
+}
+
+template <class F>
+int timed(ader_ctx* c, int k, F launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c->prof) {
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return int(hipErrorOutOfMemory);
+    (void)hipEventRecord(a, c->stream);
+  }
+  int r = launch();
+  if (c->prof) {
+    (void)hipEventRecord(b, c->stream);
+    c->ev[k].push_back({a, b});
+  }
+  return r;
+}
+
+int read_scal(ader_ctx* c, aw::Scal& s) {
+  HIPCHK(c, hipMemcpyAsync(&s, c->dev.scal, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->prof) flush_events(c);
+  return 0;
+}
+
+int check_err(ader_ctx* c, const aw::Scal& s) {
+  if (s.err & aw::ERR_GEOM) return fail(c, ADER_E_GEOM, "an element was inverted by the mesh motion");
+  if (s.err & aw::ERR_GCL) return fail(c, ADER_E_GCL, "space-time control volume not closed (GCL residual above tolerance)");
+  if (s.err & aw::ERR_STATE) return fail(c, ADER_E_STATE, "non-physical state (rho <= 0, p <= 0 or NaN)");
+  if (s.err & aw::ERR_PRED) return fail(c, ADER_E_STATE, "a predictor was read outside its time slab");
+  return 0;
+}
+
+int run_cycles(ader_ctx* c, int n) {
+  const aw::Dev& d = c->dev;
+  const aw::Params& p = c->prm;
+  const int M = c->cfg.M;
+  void* s = c->stream;
+  for (int k = 0; k < n; ++k) {
+    const int cy = ++c->cycle;
+    LCHK(c, timed(c, ADER_K_SCHED, [&] {
+      int r = aw::launch_cycle_begin(d, s);
+      return r ? r : aw::launch_sched(d, cy, s);
+    }));
+    LCHK(c, timed(c, ADER_K_NODE, [&] { return aw::launch_node(d, p, M, cy, s); }));
+    LCHK(c, timed(c, ADER_K_PATCH, [&] { return aw::launch_patch(d, p, M, cy, s); }));
+    LCHK(c, timed(c, ADER_K_UPDATE, [&] { return aw::launch_update(d, p, cy, s); }));
+    LCHK(c, timed(c, ADER_K_RECON, [&] { return aw::launch_reconstruct(d, p, M, 1, 1, s); }));
+    LCHK(c, timed(c, ADER_K_PREDICT, [&] { return aw::launch_predict(d, p, M, 1, s); }));
+    c->cycles++;
+  }
+  return 0;
+}
+
+int macro_begin(ader_ctx* c, double t_end, int N) {
+  LCHK(c, timed(c, ADER_K_MACRO, [&] { return aw::launch_macro_begin(c->dev, t_end, N, c->stream); }));
+  LCHK(c, timed(c, ADER_K_PREDICT, [&] { return aw::launch_predict(c->dev, c->prm, c->cfg.M, 0, c->stream); }));
+  return 0;
+}
+
+// Macro steps of N ticks until t_target; returns 0 or an error code.
+int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
+  aw::Scal s;
+  int r;
+  for (int k = 0; max_macro <= 0 || k < max_macro; ++k) {
+    if ((r = read_scal(c, s))) return r;
+    if ((r = check_err(c, s))) return r;
+    if (t_target - s.T <= 1e-12 * std::fmax(1.0, std::fabs(t_target))) break;
+    if ((r = macro_begin(c, t_target, N))) return r;
+    if ((r = run_cycles(c, N))) return r;
+    long long last = -1;
+    for (;;) {
+      LCHK(c, timed(c, ADER_K_STATUS, [&] { return aw::launch_status(c->dev, c->stream); }));
+      if ((r = read_scal(c, s))) return r;
+      if ((r = check_err(c, s))) return r;
+      if (!(s.delta > 0.0)) return fail(c, ADER_E_STATE, "time step is not positive");
+      if (s.n_unfinished == 0) break;
+      if ((long long)s.updates == last) return fail(c, ADER_E_DEADLOCK, "no element satisfies the update criterion");
+      last = (long long)s.updates;
+      if ((r = run_cycles(c, 1))) return r;
+    }
+    LCHK(c, aw::launch_macro_end(c->dev, c->stream));
+    c->macro_steps++;
+  }
+  return 0;
+}
+
+void fill_stats(ader_ctx* c, const aw::Scal& s, ader_stats* st) {
+  st->element_updates = s.updates;
+  st->cycles = c->cycles;
+  st->macro_steps = c->macro_steps;
+  st->cfl_overshoots = s.overshoots;
+  unsigned long long b = s.max_gcl_bits;
+  double g;
+  std::memcpy(&g, &b, sizeof(g));
+  st->max_gcl_residual = g;
+  st->t = s.T;
+  st->delta = s.delta;
+  st->predictor_evals = (int64_t)s.n_pred;
+  st->patches = (int64_t)s.n_patch;
+  st->node_moves = (int64_t)s.n_node;
+}
+
+struct Arr {
+  void* dev = nullptr;          // device array
+  const void* host = nullptr;   // host array (topology and tables)
+  size_t bytes = 0;
+};
+
+Arr lookup(ader_ctx* c, int what) {
+  Arr a;
+  const aw::Topology& t = c->topo;
+  const int M = c->cfg.M;
+  const size_t nb = (M + 1) * (M + 2) / 2, nt = M + 1, nG = M + 1;
+  const size_t NE = t.NE, NV = t.NV, D = sizeof(double), I = sizeof(int);
+  const aw::Dev& d = c->dev;
+  switch (what) {
+    case ADER_DBG_Q: a.dev = d.Q; a.bytes = 4 * NE * D; break;
+    case ADER_DBG_A: a.dev = d.A; a.bytes = NE * D; break;
+    case ADER_DBG_XE: a.dev = d.Xe; a.bytes = 6 * NE * D; break;
+    case ADER_DBG_TICK: a.dev = d.tick; a.bytes = NE * I; break;
+    case ADER_DBG_STEP: a.dev = d.step; a.bytes = NE * I; break;
+    case ADER_DBG_DTCFL: a.dev = d.dtcfl; a.bytes = NE * D; break;
+    case ADER_DBG_QM: a.dev = d.QM; a.bytes = 4 * NE * D; break;
+    case ADER_DBG_HM: a.dev = d.HM; a.bytes = 3 * NE * D; break;
+    case ADER_DBG_WNOD: a.dev = d.wnod; a.bytes = nb * 4 * NE * D; break;
+    case ADER_DBG_AVG: a.dev = d.avg; a.bytes = nt * 4 * NE * D; break;
+    case ADER_DBG_TRACE: a.dev = d.trace; a.bytes = 3 * nG * nt * 4 * NE * D; break;
+    case ADER_DBG_VVEL: a.dev = d.vvel; a.bytes = 3 * nt * 2 * NE * D; break;
+    case ADER_DBG_X: a.dev = d.X; a.bytes = 2 * NV * D; break;
+    case ADER_DBG_NTICK: a.dev = d.ntick; a.bytes = NV * I; break;
+    case ADER_DBG_SCAL: a.bytes = 4 * D; break;
+    case ADER_DBG_TOPO_EDGES: a.bytes = size_t(t.NF) * 6 * I; break;
+    case ADER_DBG_TOPO_STENCILS: a.host = t.sten.data(); a.bytes = t.sten.size() * I; break;
+    case ADER_DBG_TOPO_SCHED_PTR: a.host = t.sched_ptr.data(); a.bytes = t.sched_ptr.size() * I; break;
+    case ADER_DBG_TOPO_SCHED_IDX: a.host = t.sched_idx.data(); a.bytes = t.sched_idx.size() * I; break;
+    case ADER_DBG_TAB_DXI: a.bytes = nb * nb * D; break;
+    case ADER_DBG_TAB_DETA: a.bytes = nb * nb * D; break;
+    case ADER_DBG_TAB_AMEAN: a.bytes = nb * D; break;
+    case ADER_DBG_TAB_EDGE: a.bytes = 3 * nG * nb * D; break;
+    case ADER_DBG_TAB_AT: a.bytes = M * nt * D; break;
+    case ADER_DBG_TAB_BT: a.bytes = M * D; break;
+    case ADER_DBG_TAB_DT: a.bytes = nt * nt * D; break;
+    case ADER_DBG_TAB_PSIC: a.bytes = nb * nb * D; break;
+    case ADER_DBG_TAB_SIGMA: a.bytes = nb * nb * D; break;
+    case ADER_DBG_TAB_GAUSS: a.bytes = 2 * nG * D; break;
+    default: break;
+  }
+  return a;
+}
+
+// host tables and edges packed densely
+std::vector<char> host_pack(ader_ctx* c, int what) {
+  const aw::Tables& T = c->tab;
+  const int nb = T.nb, nt = T.nt, nG = T.nG, M = T.M;
+  std::vector<double> v;
+  switch (what) {
+    case ADER_DBG_TAB_DXI:
+      for (int a = 0; a < nb; ++a) for (int b = 0; b < nb; ++b) v.push_back(T.Dxi[a][b]);
+      break;
+    case ADER_DBG_TAB_DETA:
+      for (int a = 0; a < nb; ++a) for (int b = 0; b < nb; ++b) v.push_back(T.Deta[a][b]);
+      break;
+    case ADER_DBG_TAB_AMEAN:
+      for (int a = 0; a < nb; ++a) v.push_back(T.amean[a]);
+      break;
+    case ADER_DBG_TAB_EDGE:
+      for (int e = 0; e < 3; ++e) for (int g = 0; g < nG; ++g) for (int m = 0; m < nb; ++m) v.push_back(T.edge[e][g][m]);
+      break;
+    case ADER_DBG_TAB_AT:
+      for (int r = 0; r < M; ++r) for (int q = 0; q < nt; ++q) v.push_back(T.At[r][q]);
+      break;
+    case ADER_DBG_TAB_BT:
+      for (int r = 0; r < M; ++r) v.push_back(T.Bt[r]);
+      break;
+    case ADER_DBG_TAB_DT:
+      for (int a = 0; a < nt; ++a) for (int b = 0; b < nt; ++b) v.push_back(T.Dt[a][b]);
+      break;
+    case ADER_DBG_TAB_PSIC:
+      for (int a = 0; a < nb; ++a) for (int b = 0; b < nb; ++b) v.push_back(T.psiC[a][b]);
+      break;
+    case ADER_DBG_TAB_SIGMA:
+      for (int a = 0; a < nb; ++a) for (int b = 0; b < nb; ++b) v.push_back(T.Sigma[a][b]);
+      break;
+    case ADER_DBG_TAB_GAUSS:
+      for (int g = 0; g < nG; ++g) v.push_back(T.gchi[g]);
+      for (int g = 0; g < nG; ++g) v.push_back(T.gw[g]);
+      break;
+    case ADER_DBG_TOPO_EDGES: {
+      std::vector<char> out(size_t(c->topo.NF) * 6 * sizeof(int));
+      int* p = (int*)out.data();
+      const aw::Topology& t = c->topo;
+      for (int e = 0; e < t.NF; ++e) {
+        p[6 * e] = t.e_a[e];
+        p[6 * e + 1] = t.e_b[e];
+        p[6 * e + 2] = t.e_L[e];
+        p[6 * e + 3] = t.e_R[e];
+        p[6 * e + 4] = t.e_el[e];
+        p[6 * e + 5] = t.e_er[e];
+      }
+      return out;
+    }
+    default: break;
+  }
+  std::vector<char> out(v.size() * sizeof(double));
+  std::memcpy(out.data(), v.data(), out.size());
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ader_create(const ader_config* cfg, void* hip_stream, ader_ctx** out) {
+  if (!cfg || !out) return ADER_E_ARG;
+  *out = nullptr;
+  if (cfg->M < 1 || cfg->M > 3) return ADER_E_ARG;
+  if (cfg->flux != 0) return ADER_E_ARG;
+  if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return ADER_E_ARG;
+  if (!(cfg->gamma > 1.0)) return ADER_E_ARG;
+  if (cfg->lts_levels < 1 || cfg->lts_levels > 8) return ADER_E_ARG;
+  if (cfg->weno_r != 8.0) return ADER_E_ARG;
+  if (cfg->mesh_velocity != 0 && cfg->mesh_velocity != 1) return ADER_E_ARG;
+  ader_ctx* c = new (std::nothrow) ader_ctx();
+  if (!c) return ADER_E_ARG;
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)hip_stream;
+  c->prm.gamma = cfg->gamma;
+  c->prm.cfl = cfg->cfl;
+  c->prm.eps = cfg->weno_eps;
+  c->prm.lambda = cfg->weno_lambda;
+  c->prm.gcl_tol = 1e-12;
+  c->prm.npic = cfg->n_picard > 0 ? cfg->n_picard : cfg->M + 1;
+  c->prm.lagrangian = cfg->mesh_velocity == 0;
+  try {
+    aw::build_tables(cfg->M, c->tab);
+  } catch (const std::exception& e) {
+    delete c;
+    return ADER_E_ARG;
+  }
+  *out = c;
+  return ADER_OK;
+}
+
+int ader_upload_mesh(ader_ctx* c, int32_t n_nodes, const double* node_xy, int32_t n_elems,
+                     const int32_t* tri, int32_t n_bedges, const int32_t* bedge) {
+  if (!c) return ADER_E_ARG;
+  if (n_nodes <= 0 || n_elems <= 0 || n_bedges < 0 || !node_xy || !tri || (n_bedges > 0 && !bedge))
+    return fail(c, ADER_E_ARG, "invalid mesh arguments");
+  if (c->bound) return fail(c, ADER_E_ORDER, "mesh already bound to a workspace");
+  try {
+    aw::build_topology(c->cfg.M, n_nodes, node_xy, n_elems, tri, n_bedges, bedge, c->topo);
+  } catch (const std::exception& e) {
+    c->has_mesh = false;
+    return fail(c, ADER_E_MESH, e.what());
+  }
+  c->has_mesh = true;
+  return ADER_OK;
+}
+
+int ader_workspace_size(const ader_ctx* cc, size_t* bytes) {
+  ader_ctx* c = const_cast<ader_ctx*>(cc);
+  if (!c || !bytes) return ADER_E_ARG;
+  if (!c->has_mesh) return fail(c, ADER_E_ORDER, "no mesh uploaded");
+  aw::Dev keep = c->dev;
+  *bytes = carve(c, nullptr);
+  c->dev = keep;
+  return ADER_OK;
+}
+
+int ader_bind_workspace(ader_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c || !dev_ptr) return ADER_E_ARG;
+  if (!c->has_mesh) return fail(c, ADER_E_ORDER, "no mesh uploaded");
+  if ((reinterpret_cast<uintptr_t>(dev_ptr) & 255) != 0) return fail(c, ADER_E_ARG, "workspace not 256-byte aligned");
+  size_t need = carve(c, nullptr);
+  if (bytes < need) return fail(c, ADER_E_ARG, "workspace too small");
+  c->ws = (char*)dev_ptr;
+  c->ws_bytes = bytes;
+  carve(c, c->ws);
+  const aw::Topology& t = c->topo;
+  aw::Dev& d = c->dev;
+  const size_t NE = t.NE, NV = t.NV, NF = t.NF;
+  // staging vectors must outlive the asynchronous copies: keep them until the sync
+  std::vector<int> tri = to_soa(t.tri, NE, 3), ee = to_soa(t.elem_edges, NE, 3), nb = to_soa(t.neigh, NE, 3);
+  std::vector<int> st = to_soa(t.sten, NE, size_t(aw::NSTEN) * t.ne);
+  std::vector<double> wn = to_soa(t.wall_n, NV, 2);
+  int r;
+  if ((r = h2d(c, d.tab, &c->tab, sizeof(aw::Tables)))) return r;
+  if ((r = h2d(c, d.tri, tri.data(), tri.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.elem_edges, ee.data(), ee.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.neigh, nb.data(), nb.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.sten, st.data(), st.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.sched_ptr, t.sched_ptr.data(), t.sched_ptr.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.sched_idx, t.sched_idx.data(), t.sched_idx.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.ring_ptr, t.ring_ptr.data(), t.ring_ptr.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.ring_ent, t.ring_ent.data(), t.ring_ent.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.wall_n, wn.data(), wn.size() * sizeof(double)))) return r;
+  if ((r = h2d(c, d.wall_pin, t.wall_pin.data(), NV * sizeof(int)))) return r;
+  if ((r = h2d(c, d.e_a, t.e_a.data(), NF * sizeof(int)))) return r;
+  if ((r = h2d(c, d.e_b, t.e_b.data(), NF * sizeof(int)))) return r;
+  if ((r = h2d(c, d.e_L, t.e_L.data(), NF * sizeof(int)))) return r;
+  if ((r = h2d(c, d.e_R, t.e_R.data(), NF * sizeof(int)))) return r;
+  if ((r = h2d(c, d.e_el, t.e_el.data(), NF * sizeof(int)))) return r;
+  if ((r = h2d(c, d.e_er, t.e_er.data(), NF * sizeof(int)))) return r;
+  if ((r = h2d(c, d.e_bc, t.e_bc.data(), NF * sizeof(int)))) return r;
+  aw::Scal s{};
+  s.N = 1;
+  if ((r = h2d(c, d.scal, &s, sizeof(s)))) return r;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->bound = true;
+  return ADER_OK;
+}
+
+int ader_upload_state(ader_ctx* c, const double* Q_dev, double t0) {
+  if (!c || !Q_dev) return ADER_E_ARG;
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  const aw::Topology& t = c->topo;
+  aw::Dev& d = c->dev;
+  std::vector<double> xy = to_soa(t.xy, t.NV, 2);
+  int r;
+  HIPCHK(c, hipMemcpyAsync(d.Q, Q_dev, 4 * size_t(t.NE) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if ((r = h2d(c, d.X, xy.data(), xy.size() * sizeof(double)))) return r;
+  aw::Scal s{};
+  s.T = t0;
+  s.N = 1;
+  if ((r = h2d(c, d.scal, &s, sizeof(s)))) return r;
+  c->cycles = 0;
+  c->macro_steps = 0;
+  LCHK(c, aw::launch_init_geometry(d, c->stream));
+  LCHK(c, aw::launch_check_state(d, c->prm.gamma, c->stream));
+  LCHK(c, aw::launch_reconstruct(d, c->prm, c->cfg.M, 0, 0, c->stream));
+  aw::Scal back;
+  if ((r = read_scal(c, back))) return r;
+  if (back.err) return fail(c, ADER_E_STATE, "initial state has rho <= 0 or p <= 0");
+  c->has_state = true;
+  return ADER_OK;
+}
+
+int ader_step_gts(ader_ctx* c, double t_target, int32_t max_steps, ader_stats* st) {
+  if (!c) return ADER_E_ARG;
+  int r = run_macro(c, t_target, max_steps, 1);
+  if (r) return r;
+  return st ? ader_get_stats(c, st) : ADER_OK;
+}
+
+int ader_step_lts(ader_ctx* c, double t_target, int32_t max_macro_steps, ader_stats* st) {
+  if (!c) return ADER_E_ARG;
+  int r = run_macro(c, t_target, max_macro_steps, 1 << (c->cfg.lts_levels - 1));
+  if (r) return r;
+  return st ? ader_get_stats(c, st) : ADER_OK;
+}
+
+int ader_download_state(ader_ctx* c, double* Q_dev, double* node_xy_dev, double* elem_t_dev) {
+  if (!c) return ADER_E_ARG;
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  const aw::Dev& d = c->dev;
+  if (Q_dev)
+    HIPCHK(c, hipMemcpyAsync(Q_dev, d.Q, 4 * size_t(d.NE) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (node_xy_dev) LCHK(c, aw::launch_download_xy(d, node_xy_dev, c->stream));
+  if (elem_t_dev) LCHK(c, aw::launch_elem_times(d, elem_t_dev, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ADER_OK;
+}
+
+int ader_get_stats(ader_ctx* c, ader_stats* st) {
+  if (!c || !st) return ADER_E_ARG;
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  aw::Scal s;
+  int r = read_scal(c, s);
+  if (r) return r;
+  fill_stats(c, s, st);
+  return ADER_OK;
+}
+
+int ader_debug_size(const ader_ctx* cc, int32_t what, size_t* bytes) {
+  ader_ctx* c = const_cast<ader_ctx*>(cc);
+  if (!c || !bytes) return ADER_E_ARG;
+  if (!c->has_mesh) return fail(c, ADER_E_ORDER, "no mesh uploaded");
+  Arr a = lookup(c, what);
+  if (a.bytes == 0) return fail(c, ADER_E_ARG, "unknown array");
+  *bytes = a.bytes;
+  return ADER_OK;
+}
+
+int ader_debug_dump(ader_ctx* c, int32_t what, void* host, size_t bytes) {
+  if (!c || !host) return ADER_E_ARG;
+  if (!c->has_mesh) return fail(c, ADER_E_ORDER, "no mesh uploaded");
+  Arr a = lookup(c, what);
+  if (a.bytes == 0 || bytes != a.bytes) return fail(c, ADER_E_ARG, "size mismatch");
+  if (what >= ADER_DBG_TOPO_EDGES) {
+    if (a.host) {
+      std::memcpy(host, a.host, bytes);
+    } else {
+      std::vector<char> p = host_pack(c, what);
+      if (p.size() != bytes) return fail(c, ADER_E_ARG, "size mismatch");
+      std::memcpy(host, p.data(), bytes);
+    }
+    return ADER_OK;
+  }
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  if (what == ADER_DBG_SCAL) {
+    aw::Scal s;
+    int r = read_scal(c, s);
+    if (r) return r;
+    double v[4] = {s.T, s.delta, double(s.N), s.t_end};
+    std::memcpy(host, v, sizeof(v));
+    return ADER_OK;
+  }
+  HIPCHK(c, hipMemcpyAsync(host, a.dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ADER_OK;
+}
+
+int ader_debug_inject(ader_ctx* c, int32_t what, const void* host, size_t bytes) {
+  if (!c || !host) return ADER_E_ARG;
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  if (what >= ADER_DBG_TOPO_EDGES) return fail(c, ADER_E_ARG, "topology and tables are read-only");
+  Arr a = lookup(c, what);
+  if (a.bytes == 0 || bytes != a.bytes) return fail(c, ADER_E_ARG, "size mismatch");
+  if (what == ADER_DBG_SCAL) {
+    aw::Scal s;
+    int r = read_scal(c, s);
+    if (r) return r;
+    double v[4];
+    std::memcpy(v, host, sizeof(v));
+    s.T = v[0];
+    s.delta = v[1];
+    s.N = int(v[2]);
+    s.t_end = v[3];
+    if ((r = h2d(c, c->dev.scal, &s, sizeof(s)))) return r;
+  } else {
+    HIPCHK(c, hipMemcpyAsync(a.dev, host, bytes, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->has_state = true;
+  return ADER_OK;
+}
+
+int ader_debug_cycles(ader_ctx* c, int32_t n) {
+  if (!c || n < 0) return ADER_E_ARG;
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  int r = run_cycles(c, n);
+  if (r) return r;
+  aw::Scal s;
+  if ((r = read_scal(c, s))) return r;
+  return check_err(c, s);
+}
+
+int ader_debug_macro_begin(ader_ctx* c, double t_end, int32_t levels) {
+  if (!c || levels < 1 || levels > 8) return ADER_E_ARG;
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  int r = macro_begin(c, t_end, 1 << (levels - 1));
+  if (r) return r;
+  aw::Scal s;
+  if ((r = read_scal(c, s))) return r;
+  return check_err(c, s);
+}
+
+int ader_set_profiling(ader_ctx* c, int32_t on) {
+  if (!c) return ADER_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  flush_events(c);
+  for (int k = 0; k < ADER_K_COUNT; ++k) {
+    c->kms[k] = 0.0;
+    c->klaunch[k] = 0;
+  }
+  c->prof = on != 0;
+  return ADER_OK;
+}
+
+int ader_kernel_times(ader_ctx* c, int32_t n, double* total_ms, int64_t* launches) {
+  if (!c || n < 0 || (n > 0 && (!total_ms || !launches))) return ADER_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  flush_events(c);
+  for (int k = 0; k < n; ++k) {
+    total_ms[k] = k < ADER_K_COUNT ? c->kms[k] : 0.0;
+    launches[k] = k < ADER_K_COUNT ? c->klaunch[k] : 0;
+  }
+  return ADER_OK;
+}
+
+const char* ader_last_error(const ader_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+void ader_destroy(ader_ctx* c) {
+  if (!c) return;
+  if (c->bound) (void)hipStreamSynchronize(c->stream);
+  for (int k = 0; k < ADER_K_COUNT; ++k)
+    for (auto& p : c->ev[k]) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+  delete c;
+}
+
+}  // extern "C"

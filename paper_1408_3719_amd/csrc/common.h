@@ -1,0 +1,107 @@
+// Shared host/device definitions of the aderweno library.
+#pragma once
+#include <cstdint>
+
+namespace aw {
+
+constexpr int MAXM = 3;
+constexpr int MAXNB = 10;   // (M+1)(M+2)/2
+constexpr int MAXT = 4;     // time nodes M+1
+constexpr int MAXG = 4;     // Gauss points per patch direction, M+1
+constexpr int MAXRQ = 7;    // points of the reconstruction triangle rule
+constexpr int NSTEN = 7;    // 1 central + 3 primary + 3 reverse sector stencils
+
+// Reference-element tables (built on the host, read by every kernel through
+// the scalar cache).  Index conventions:
+//   monomial k <-> xi^monoA[k] eta^monoB[k], ordered by total degree;
+//   lattice node m = (i/M, j/M), i+j <= M, ordered by j then i;
+//   psi_0 = 1, every other psi_l has zero mean on the reference triangle.
+struct Tables {
+  int M, nb, nt, nG, ne, nrq;
+  int vtx[3];                       // lattice index of the reference vertices
+  int monoA[MAXNB], monoB[MAXNB];
+  double psiC[MAXNB][MAXNB];        // psi_l = sum_k psiC[l][k] mono_k
+  double Sigma[MAXNB][MAXNB];       // oscillation indicator matrix
+  double psiNodes[MAXNB][MAXNB];    // psi_l at lattice node m: [m][l]
+  double Dxi[MAXNB][MAXNB];         // d/dxi of the nodal interpolant at node m': [m'][m]
+  double Deta[MAXNB][MAXNB];
+  double amean[MAXNB];              // mean over T_e of the nodal basis function m
+  double edge[3][MAXG][MAXNB];      // nodal basis at Gauss point g of reference edge e
+  double At[MAXT][MAXT];            // rows r = 0..M-1 <-> time nodes 1..M
+  double Bt[MAXT];
+  double Dt[MAXT][MAXT];            // d/dtau of the time interpolant at node q': [q'][q]
+  double lag[MAXT][MAXT + 1];       // l_q(tau) = sum_k lag[q][k] tau^k
+  double Lint[MAXT][MAXT + 2];      // int_0^tau l_q = sum_k Lint[q][k] tau^k
+  double gchi[MAXG], gw[MAXG];      // Gauss-Legendre on [0,1]
+  double rqw[MAXRQ];                // triangle rule, exact to degree M (barycentric)
+  double rqb[MAXRQ][3];
+};
+
+struct Params {
+  double gamma, cfl, eps, lambda, gcl_tol;
+  int npic;
+  int lagrangian;
+};
+
+// Device-resident scalars of the running simulation.
+struct Scal {
+  double T;         // common time at the start of the macro step
+  double delta;     // tick length
+  double t_end;     // target time of the current call
+  int N;            // ticks per macro step 2^(L-1)
+  int n_active;     // active elements of the current cycle
+  int n_unfinished; // elements that have not reached tick N
+  int err;          // sticky error bits (ERR_*)
+  unsigned long long min_dt_bits;   // min CFL step (positive doubles order as integers)
+  unsigned long long max_gcl_bits;  // max relative GCL residual
+  unsigned long long updates;
+  unsigned long long overshoots;
+  unsigned long long n_pred;    // predictor evaluations
+  unsigned long long n_patch;   // space-time patches integrated
+  unsigned long long n_node;    // node moves
+};
+
+enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8 };
+
+// Pointers into the caller's workspace.  SoA: field f of item i at [f * count + i].
+struct Dev {
+  int NE, NV, NF, nsched, nring;
+  Scal* scal;
+  const Tables* tab;
+  // elements
+  double *Q, *A, *Xe, *dtcfl, *QM, *HM, *wnod, *avg, *trace, *vvel;
+  int *tick, *step, *act_stamp, *act_list;
+  const int *tri, *elem_edges, *neigh, *sten, *sched_ptr, *sched_idx;
+  // nodes
+  double *X, *Xnew;
+  int *ntick, *ntick_new, *node_stamp;
+  const int *ring_ptr, *ring_ent;   // ring entry = element * 4 + local vertex
+  const double* wall_n;             // [2][NV] slip-wall normal (0 off walls)
+  const int* wall_pin;              // node held fixed (two walls meet)
+  // edges
+  const int *e_a, *e_b, *e_L, *e_R, *e_el, *e_er, *e_bc;
+  double *G, *Nint;
+  int* edge_stamp;
+  // download staging
+  double* out_xy;
+};
+
+// Kernel launchers (kernels.hip).  All launch on `stream`, return a
+// hipError_t as int.
+int launch_init_geometry(const Dev& d, void* stream);
+int launch_reconstruct(const Dev& d, const Params& p, int M, int use_list, int set_level,
+                       void* stream);
+int launch_predict(const Dev& d, const Params& p, int M, int use_list, void* stream);
+int launch_macro_begin(const Dev& d, double t_end, int N, void* stream);
+int launch_cycle_begin(const Dev& d, void* stream);
+int launch_sched(const Dev& d, int cycle, void* stream);
+int launch_node(const Dev& d, const Params& p, int M, int cycle, void* stream);
+int launch_patch(const Dev& d, const Params& p, int M, int cycle, void* stream);
+int launch_update(const Dev& d, const Params& p, int cycle, void* stream);
+int launch_status(const Dev& d, void* stream);
+int launch_macro_end(const Dev& d, void* stream);
+int launch_download_xy(const Dev& d, double* out, void* stream);
+int launch_elem_times(const Dev& d, double* out, void* stream);
+int launch_check_state(const Dev& d, double gamma, void* stream);
+
+}  // namespace aw

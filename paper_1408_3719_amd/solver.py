@@ -1,0 +1,189 @@
+"""Python binding of the aderweno library: argument marshalling only.
+
+Every step of the scheme runs in the HIP kernels of libaderweno.so; PyTorch
+supplies the device workspace and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+
+from . import _lib
+
+MESH_VELOCITY = {"lagrangian": 0, "eulerian": 1}
+
+
+@dataclasses.dataclass
+class Config:
+    M: int = 2
+    gamma: float = 1.4
+    cfl: float = 0.5
+    levels: int = 1
+    n_picard: int = 0
+    mesh_velocity: str = "lagrangian"
+    weno_eps: float = 1e-14
+    weno_r: float = 8.0
+    weno_lambda: float = 1e5
+
+    def to_c(self) -> _lib.AderConfig:
+        return _lib.AderConfig(self.M, 0, self.gamma, self.cfl, self.levels, self.n_picard,
+                               MESH_VELOCITY[self.mesh_velocity], self.weno_eps, self.weno_r,
+                               self.weno_lambda)
+
+
+def _check(lib, ctx, code):
+    if code != 0:
+        msg = lib.ader_last_error(ctx).decode() if ctx else ""
+        raise _lib.AderError(code, msg)
+
+
+def _shape(what, M, NE, NV, NF, ne):
+    nb = (M + 1) * (M + 2) // 2
+    T = nG = M + 1
+    return {
+        "Q": (4, NE), "A": (NE,), "XE": (6, NE), "TICK": (NE,), "STEP": (NE,), "DTCFL": (NE,),
+        "QM": (4, NE), "HM": (3, NE), "WNOD": (nb, 4, NE), "AVG": (T, 4, NE),
+        "TRACE": (3, nG, T, 4, NE), "VVEL": (3, T, 2, NE), "X": (2, NV), "NTICK": (NV,),
+        "SCAL": (4,), "TOPO_EDGES": (NF, 6), "TOPO_STENCILS": (NE, 7, ne),
+        "TAB_DXI": (nb, nb), "TAB_DETA": (nb, nb), "TAB_AMEAN": (nb,), "TAB_EDGE": (3, nG, nb),
+        "TAB_AT": (M, T), "TAB_BT": (M,), "TAB_DT": (T, T), "TAB_PSIC": (nb, nb),
+        "TAB_SIGMA": (nb, nb), "TAB_GAUSS": (2, nG),
+    }.get(what)
+
+
+class _Base:
+    def __init__(self, nodes, tris, bedges, cfg: Config, stream=None):
+        self.lib = _lib.load()
+        self.cfg = cfg
+        self.ctx = ctypes.c_void_p()
+        c = cfg.to_c()
+        rc = self.lib.ader_create(ctypes.byref(c), ctypes.c_void_p(stream or 0), ctypes.byref(self.ctx))
+        if rc != 0:
+            raise _lib.AderError(rc, "ader_create rejected the configuration")
+        self._nodes = np.ascontiguousarray(nodes, np.float64)
+        self._tris = np.ascontiguousarray(tris, np.int32)
+        be = np.zeros((0, 3), np.int32) if bedges is None else bedges
+        self._bedges = np.ascontiguousarray(be, np.int32)
+        self.NV, self.NE = self._nodes.shape[0], self._tris.shape[0]
+        _check(self.lib, self.ctx, self.lib.ader_upload_mesh(
+            self.ctx, self.NV, self._nodes.ctypes.data, self.NE, self._tris.ctypes.data,
+            self._bedges.shape[0], self._bedges.ctypes.data if self._bedges.size else None))
+        self.NF = self._size("TOPO_EDGES") // (6 * 4)
+        self.ne = (cfg.M + 1) * (cfg.M + 2)
+
+    def _size(self, what):
+        n = ctypes.c_size_t()
+        _check(self.lib, self.ctx, self.lib.ader_debug_size(self.ctx, _lib.DBG[what], ctypes.byref(n)))
+        return n.value
+
+    def dump(self, what):
+        nbytes = self._size(what)
+        dt = np.int32 if what in _lib.INT_ARRAYS else np.float64
+        out = np.empty(nbytes // np.dtype(dt).itemsize, dt)
+        _check(self.lib, self.ctx, self.lib.ader_debug_dump(self.ctx, _lib.DBG[what],
+                                                            out.ctypes.data, nbytes))
+        shp = _shape(what, self.cfg.M, self.NE, self.NV, self.NF, self.ne)
+        return out.reshape(shp) if shp is not None else out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.ader_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostTopology(_Base):
+    """Host-only view of the library's topology, stencils and tables (no GPU)."""
+
+
+class Solver(_Base):
+    """Moving-mesh ADER-WENO solver on one GPU.
+
+    nodes (NV,2), tris (NE,3) CCW, bedges (NB,3) = (a, b, tag); tags 1 =
+    transmissive, 2 = slip wall.  Q0 (NE,4) conserved initial averages.
+    """
+
+    def __init__(self, nodes, tris, bedges, Q0, cfg: Config, t0: float = 0.0, device="cuda:0"):
+        import torch   # loaded before the library so both share one HIP runtime
+        self.torch = torch
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        super().__init__(nodes, tris, bedges, cfg, stream=self.stream.cuda_stream)
+        n = ctypes.c_size_t()
+        _check(self.lib, self.ctx, self.lib.ader_workspace_size(self.ctx, ctypes.byref(n)))
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        _check(self.lib, self.ctx, self.lib.ader_bind_workspace(self.ctx, ctypes.c_void_p(aligned), n.value))
+        self.upload_state(Q0, t0)
+
+    def upload_state(self, Q0, t0=0.0):
+        torch = self.torch
+        q = torch.as_tensor(np.ascontiguousarray(np.asarray(Q0, np.float64).T), device=self.device)
+        q = q.contiguous()
+        _check(self.lib, self.ctx, self.lib.ader_upload_state(self.ctx, ctypes.c_void_p(q.data_ptr()), t0))
+        self.stream.synchronize()
+
+    def _stats(self, st):
+        return {f: getattr(st, f) for f, _ in _lib.AderStats._fields_}
+
+    def step_gts(self, t_target, max_steps=0):
+        st = _lib.AderStats()
+        _check(self.lib, self.ctx, self.lib.ader_step_gts(self.ctx, t_target, max_steps, ctypes.byref(st)))
+        return self._stats(st)
+
+    def step_lts(self, t_target, max_macro_steps=0):
+        st = _lib.AderStats()
+        _check(self.lib, self.ctx, self.lib.ader_step_lts(self.ctx, t_target, max_macro_steps,
+                                                          ctypes.byref(st)))
+        return self._stats(st)
+
+    def stats(self):
+        st = _lib.AderStats()
+        _check(self.lib, self.ctx, self.lib.ader_get_stats(self.ctx, ctypes.byref(st)))
+        return self._stats(st)
+
+    def download(self):
+        """(Q (NE,4), node positions (NV,2), element times (NE,)) as numpy."""
+        torch = self.torch
+        Q = torch.empty((4, self.NE), dtype=torch.float64, device=self.device)
+        X = torch.empty((self.NV, 2), dtype=torch.float64, device=self.device)
+        t = torch.empty((self.NE,), dtype=torch.float64, device=self.device)
+        _check(self.lib, self.ctx, self.lib.ader_download_state(
+            self.ctx, ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+            ctypes.c_void_p(t.data_ptr())))
+        return Q.T.cpu().numpy().copy(), X.cpu().numpy(), t.cpu().numpy()
+
+    def inject(self, what, arr):
+        dt = np.int32 if what in _lib.INT_ARRAYS else np.float64
+        a = np.ascontiguousarray(arr, dt)
+        nbytes = self._size(what)
+        if a.nbytes != nbytes:
+            raise ValueError(f"{what}: {a.nbytes} bytes given, {nbytes} expected")
+        _check(self.lib, self.ctx, self.lib.ader_debug_inject(self.ctx, _lib.DBG[what],
+                                                              a.ctypes.data, nbytes))
+
+    def set_profiling(self, on: bool):
+        _check(self.lib, self.ctx, self.lib.ader_set_profiling(self.ctx, 1 if on else 0))
+
+    def kernel_times(self):
+        """{kernel: (total ms, launches)} since profiling was switched on."""
+        n = len(_lib.KERNELS)
+        ms = np.zeros(n)
+        cnt = np.zeros(n, np.int64)
+        _check(self.lib, self.ctx, self.lib.ader_kernel_times(self.ctx, n, ms.ctypes.data, cnt.ctypes.data))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(_lib.KERNELS)}
+
+    def debug_cycles(self, n=1):
+        _check(self.lib, self.ctx, self.lib.ader_debug_cycles(self.ctx, n))
+
+    def debug_macro_begin(self, t_end, levels):
+        _check(self.lib, self.ctx, self.lib.ader_debug_macro_begin(self.ctx, t_end, levels))
