@@ -68,7 +68,7 @@ struct Layout {
 size_t carve(ader_ctx* c, char* base) {
   const aw::Topology& t = c->topo;
   const int M = c->cfg.M;
-  const int nb = (M + 1) * (M + 2) / 2, nt = M + 1, nG = M + 1, ne = 2 * nb;
+  const int nb = (M + 1) * (M + 2) / 2, ne = 2 * nb;
   const size_t NE = t.NE, NV = t.NV, NF = t.NF, D = sizeof(double), I = sizeof(int);
   Layout L;
   aw::Dev& d = c->dev;
@@ -76,25 +76,20 @@ size_t carve(ader_ctx* c, char* base) {
   auto pi = [&](size_t n) { size_t o = L.take(n * I); return base ? (int*)(base + o) : nullptr; };
   size_t o_scal = L.take(sizeof(aw::Scal));
   size_t o_tab = L.take(sizeof(aw::Tables));
+  size_t o_ts = L.take(NE * sizeof(aw::TickStep));
   d.NE = t.NE;
   d.NV = t.NV;
   d.NF = t.NF;
-  d.nsched = int(t.sched_idx.size());
-  d.nring = int(t.ring_ent.size());
+  d.M = M;
   d.scal = base ? (aw::Scal*)(base + o_scal) : nullptr;
   d.tab = base ? (const aw::Tables*)(base + o_tab) : nullptr;
-  d.Q = pd(4 * NE);
-  d.A = pd(NE);
-  d.Xe = pd(6 * NE);
+  d.ts = base ? (aw::TickStep*)(base + o_ts) : nullptr;
+  d.rec = pd(NE * aw::rec_stride(M));
+  d.trace = pd(NE * aw::trace_stride(M));
+  d.wnod = pd(NE * aw::wnod_stride(M));
   d.dtcfl = pd(NE);
   d.QM = pd(4 * NE);
   d.HM = pd(3 * NE);
-  d.wnod = pd(size_t(nb) * 4 * NE);
-  d.avg = pd(size_t(nt) * 4 * NE);
-  d.trace = pd(size_t(3) * nG * nt * 4 * NE);
-  d.vvel = pd(size_t(3) * nt * 2 * NE);
-  d.tick = pi(NE);
-  d.step = pi(NE);
   d.act_stamp = pi(NE);
   d.act_list = pi(NE);
   d.tri = pi(3 * NE);
@@ -122,7 +117,6 @@ size_t carve(ader_ctx* c, char* base) {
   d.G = pd(4 * NF);
   d.Nint = pd(3 * NF);
   d.edge_stamp = pi(NF);
-  d.out_xy = nullptr;
   return L.total;
 }
 
@@ -269,18 +263,18 @@ Arr lookup(ader_ctx* c, int what) {
   const size_t NE = t.NE, NV = t.NV, D = sizeof(double), I = sizeof(int);
   const aw::Dev& d = c->dev;
   switch (what) {
-    case ADER_DBG_Q: a.dev = d.Q; a.bytes = 4 * NE * D; break;
-    case ADER_DBG_A: a.dev = d.A; a.bytes = NE * D; break;
-    case ADER_DBG_XE: a.dev = d.Xe; a.bytes = 6 * NE * D; break;
-    case ADER_DBG_TICK: a.dev = d.tick; a.bytes = NE * I; break;
-    case ADER_DBG_STEP: a.dev = d.step; a.bytes = NE * I; break;
+    case ADER_DBG_Q: a.bytes = 4 * NE * D; break;
+    case ADER_DBG_A: a.bytes = NE * D; break;
+    case ADER_DBG_XE: a.bytes = 6 * NE * D; break;
+    case ADER_DBG_TICK: a.bytes = NE * I; break;
+    case ADER_DBG_STEP: a.bytes = NE * I; break;
     case ADER_DBG_DTCFL: a.dev = d.dtcfl; a.bytes = NE * D; break;
     case ADER_DBG_QM: a.dev = d.QM; a.bytes = 4 * NE * D; break;
     case ADER_DBG_HM: a.dev = d.HM; a.bytes = 3 * NE * D; break;
-    case ADER_DBG_WNOD: a.dev = d.wnod; a.bytes = nb * 4 * NE * D; break;
-    case ADER_DBG_AVG: a.dev = d.avg; a.bytes = nt * 4 * NE * D; break;
-    case ADER_DBG_TRACE: a.dev = d.trace; a.bytes = 3 * nG * nt * 4 * NE * D; break;
-    case ADER_DBG_VVEL: a.dev = d.vvel; a.bytes = 3 * nt * 2 * NE * D; break;
+    case ADER_DBG_WNOD: a.bytes = nb * 4 * NE * D; break;
+    case ADER_DBG_AVG: a.bytes = nt * 4 * NE * D; break;
+    case ADER_DBG_TRACE: a.bytes = 3 * nG * nt * 4 * NE * D; break;
+    case ADER_DBG_VVEL: a.bytes = 3 * nt * 2 * NE * D; break;
     case ADER_DBG_X: a.dev = d.X; a.bytes = 2 * NV * D; break;
     case ADER_DBG_NTICK: a.dev = d.ntick; a.bytes = NV * I; break;
     case ADER_DBG_SCAL: a.bytes = 4 * D; break;
@@ -301,6 +295,77 @@ Arr lookup(ader_ctx* c, int what) {
     default: break;
   }
   return a;
+}
+
+// Element arrays kept per element on the device (records, traces, nodal
+// reconstruction, tick/step): field f of element i in the documented
+// field-major layout [f][NE] maps to (buffer, stride, offset f').
+struct Packed {
+  void* dev = nullptr;
+  size_t stride = 0;                     // doubles (or ints) per element
+  std::vector<size_t> off;               // device offset of documented field f
+  bool ints = false;
+};
+
+Packed packed(ader_ctx* c, int what) {
+  Packed p;
+  const int M = c->cfg.M;
+  const int nb = (M + 1) * (M + 2) / 2, T = M + 1, nG = M + 1;
+  const aw::Dev& d = c->dev;
+  auto rec = [&](int first, int count) {
+    p.dev = d.rec;
+    p.stride = aw::rec_stride(M);
+    for (int k = 0; k < count; ++k) p.off.push_back(first + k);
+  };
+  switch (what) {
+    case ADER_DBG_Q: rec(aw::rec_off_q(), 4); break;
+    case ADER_DBG_A: rec(aw::rec_off_a(), 1); break;
+    case ADER_DBG_XE: rec(aw::rec_off_xe(), 6); break;
+    case ADER_DBG_AVG: rec(aw::rec_off_avg(), 4 * T); break;
+    case ADER_DBG_VVEL: rec(aw::rec_off_vv(M), 6 * T); break;
+    case ADER_DBG_TRACE:
+      p.dev = d.trace;
+      p.stride = aw::trace_stride(M);
+      for (int k = 0; k < 3 * nG * T * 4; ++k) p.off.push_back(k);
+      break;
+    case ADER_DBG_WNOD:
+      p.dev = d.wnod;
+      p.stride = aw::wnod_stride(M);
+      for (int k = 0; k < nb * 4; ++k) p.off.push_back(k);
+      break;
+    case ADER_DBG_TICK:
+    case ADER_DBG_STEP:
+      p.dev = d.ts;
+      p.stride = 2;
+      p.off.push_back(what == ADER_DBG_TICK ? 0 : 1);
+      p.ints = true;
+      break;
+    default: break;
+  }
+  return p;
+}
+
+int packed_io(ader_ctx* c, int what, void* host, const void* in, size_t bytes) {
+  Packed p = packed(c, what);
+  const size_t NE = c->topo.NE, es = p.ints ? sizeof(int) : sizeof(double);
+  std::vector<char> buf(NE * p.stride * es);
+  HIPCHK(c, hipMemcpyAsync(buf.data(), p.dev, buf.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const size_t nf = p.off.size();
+  if (bytes != nf * NE * es) return fail(c, ADER_E_ARG, "size mismatch");
+  for (size_t f = 0; f < nf; ++f)
+    for (size_t i = 0; i < NE; ++i) {
+      char* dev_el = buf.data() + (i * p.stride + p.off[f]) * es;
+      if (host)
+        std::memcpy((char*)host + (f * NE + i) * es, dev_el, es);
+      else
+        std::memcpy(dev_el, (const char*)in + (f * NE + i) * es, es);
+    }
+  if (!host) {
+    HIPCHK(c, hipMemcpyAsync(p.dev, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return 0;
 }
 
 // host tables and edges packed densely
@@ -472,7 +537,6 @@ int ader_upload_state(ader_ctx* c, const double* Q_dev, double t0) {
   aw::Dev& d = c->dev;
   std::vector<double> xy = to_soa(t.xy, t.NV, 2);
   int r;
-  HIPCHK(c, hipMemcpyAsync(d.Q, Q_dev, 4 * size_t(t.NE) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if ((r = h2d(c, d.X, xy.data(), xy.size() * sizeof(double)))) return r;
   aw::Scal s{};
   s.T = t0;
@@ -481,6 +545,7 @@ int ader_upload_state(ader_ctx* c, const double* Q_dev, double t0) {
   c->cycles = 0;
   c->macro_steps = 0;
   LCHK(c, aw::launch_init_geometry(d, c->stream));
+  LCHK(c, aw::launch_upload_q(d, Q_dev, c->stream));
   LCHK(c, aw::launch_check_state(d, c->prm.gamma, c->stream));
   LCHK(c, aw::launch_reconstruct(d, c->prm, c->cfg.M, 0, 0, c->stream));
   aw::Scal back;
@@ -508,8 +573,7 @@ int ader_download_state(ader_ctx* c, double* Q_dev, double* node_xy_dev, double*
   if (!c) return ADER_E_ARG;
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   const aw::Dev& d = c->dev;
-  if (Q_dev)
-    HIPCHK(c, hipMemcpyAsync(Q_dev, d.Q, 4 * size_t(d.NE) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (Q_dev) LCHK(c, aw::launch_download_q(d, Q_dev, c->stream));
   if (node_xy_dev) LCHK(c, aw::launch_download_xy(d, node_xy_dev, c->stream));
   if (elem_t_dev) LCHK(c, aw::launch_elem_times(d, elem_t_dev, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -560,6 +624,7 @@ int ader_debug_dump(ader_ctx* c, int32_t what, void* host, size_t bytes) {
     std::memcpy(host, v, sizeof(v));
     return ADER_OK;
   }
+  if (!a.dev) return packed_io(c, what, host, nullptr, bytes);
   HIPCHK(c, hipMemcpyAsync(host, a.dev, bytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return ADER_OK;
@@ -582,6 +647,9 @@ int ader_debug_inject(ader_ctx* c, int32_t what, const void* host, size_t bytes)
     s.N = int(v[2]);
     s.t_end = v[3];
     if ((r = h2d(c, c->dev.scal, &s, sizeof(s)))) return r;
+  } else if (!a.dev) {
+    int r = packed_io(c, what, nullptr, host, bytes);
+    if (r) return r;
   } else {
     HIPCHK(c, hipMemcpyAsync(a.dev, host, bytes, hipMemcpyHostToDevice, c->stream));
   }

@@ -63,27 +63,51 @@ struct Scal {
 
 enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8 };
 
-// Pointers into the caller's workspace.  SoA: field f of item i at [f * count + i].
+// Per-element storage.  Data that other elements gather (vertices, average,
+// area, the predictor's time-node averages and vertex velocities) sits in one
+// contiguous record per element, so a neighbour costs a few cache lines
+// instead of one line per field; edge traces are contiguous per element too.
+//   record: [0,6) vertices x0 y0 x1 y1 x2 y2 | [6,10) Q | 10 area |
+//           [11, 11+4T) averages at time node t (t*4+v) |
+//           [11+4T, 11+10T) vertex velocities ((k*T+t)*2+c)
+//   trace:  ((e*nG+g)*T+t)*4+v        wnod: m*4+v
+constexpr int rec_off_xe() { return 0; }
+constexpr int rec_off_q() { return 6; }
+constexpr int rec_off_a() { return 10; }
+constexpr int rec_off_avg() { return 11; }
+constexpr int rec_off_vv(int M) { return 11 + 4 * (M + 1); }
+constexpr int round16(int n) { return (n + 15) / 16 * 16; }
+constexpr int rec_stride(int M) { return round16(11 + 10 * (M + 1)); }
+constexpr int trace_stride(int M) { return round16(3 * (M + 1) * (M + 1) * 4); }
+constexpr int wnod_stride(int M) { return (M + 1) * (M + 2) / 2 * 4; }
+
+struct TickStep {   // tick in the macro step and step length in ticks (0: finished)
+  int tick, step;
+};
+
+// Pointers into the caller's workspace.
 struct Dev {
-  int NE, NV, NF, nsched, nring;
+  int NE, NV, NF, M;
   Scal* scal;
   const Tables* tab;
   // elements
-  double *Q, *A, *Xe, *dtcfl, *QM, *HM, *wnod, *avg, *trace, *vvel;
-  int *tick, *step, *act_stamp, *act_list;
-  const int *tri, *elem_edges, *neigh, *sten, *sched_ptr, *sched_idx;
+  double* rec;        // [NE][rec_stride]
+  double* trace;      // [NE][trace_stride]
+  double* wnod;       // [NE][wnod_stride]
+  TickStep* ts;       // [NE]
+  double *dtcfl, *QM, *HM;   // SoA: [NE], [4][NE], [3][NE]
+  int *act_stamp, *act_list;
+  const int *tri, *elem_edges, *neigh, *sten, *sched_ptr, *sched_idx;   // SoA [k][NE]
   // nodes
-  double *X, *Xnew;
+  double *X, *Xnew;   // [2][NV]
   int *ntick, *ntick_new, *node_stamp;
   const int *ring_ptr, *ring_ent;   // ring entry = element * 4 + local vertex
   const double* wall_n;             // [2][NV] slip-wall normal (0 off walls)
   const int* wall_pin;              // node held fixed (two walls meet)
   // edges
   const int *e_a, *e_b, *e_L, *e_R, *e_el, *e_er, *e_bc;
-  double *G, *Nint;
+  double *G, *Nint;   // [4][NF], [3][NF]
   int* edge_stamp;
-  // download staging
-  double* out_xy;
 };
 
 // Kernel launchers (kernels.hip).  All launch on `stream`, return a
@@ -101,6 +125,8 @@ int launch_update(const Dev& d, const Params& p, int cycle, void* stream);
 int launch_status(const Dev& d, void* stream);
 int launch_macro_end(const Dev& d, void* stream);
 int launch_download_xy(const Dev& d, double* out, void* stream);
+int launch_download_q(const Dev& d, double* out, void* stream);
+int launch_upload_q(const Dev& d, const double* in, void* stream);
 int launch_elem_times(const Dev& d, double* out, void* stream);
 int launch_check_state(const Dev& d, double gamma, void* stream);
 

@@ -2,20 +2,28 @@
 //
 // One cycle of the local time stepping (paper Sec. 2.6, "computational phase"),
 // read data-parallel: the active set is fixed from the cycle-start ticks, then
-//   k_sched      update criterion (eq. eqn.WENOupdate) over the symmetric
-//                scheduling stencil, compacted active list
-//   k_node       node solver NS_cs (eqs. eqnNScs, eqn.NScs.weights, eqn.dtau,
-//                NodesVel) and node motion (eq. eqn.newVertex)
-//   k_patch      flux through every space-time patch swept by a moved edge
-//                (eqs. eqn.spacetimenodes, G_ij, eqn.rusanov, A_n^V, eqn.STint)
-//   k_update     memory variables (eq. eqn.Qm2 and the geometric memory) and
-//                the one-step update (eq. PDEfinal) with the GCL check (eqn.gcl)
-//   k_reconstruct virtual projection of the stencil (eqs. eqn.virtGeom,
-//                eqn.virtCellaverage), WENO (eqs. intConsRec .. eqn.weno), local
-//                time step (eq. eqn.timestep) and dyadic level
-//   k_predict    space-time Galerkin predictor of the PDE and of the mesh ODE
-//                (eqs. timeTransf .. newVertPos)
+//   k_sched       update criterion (eq. eqn.WENOupdate) over the symmetric
+//                 scheduling stencil, compacted active list
+//   k_node        node solver NS_cs (eqs. eqnNScs, eqn.NScs.weights, eqn.dtau,
+//                 NodesVel) and node motion (eq. eqn.newVertex)
+//   k_patch       flux through every space-time patch swept by a moved edge
+//                 (eqs. eqn.spacetimenodes, G_ij, eqn.rusanov, A_n^V, eqn.STint)
+//   k_update      memory variables (eq. eqn.Qm2 and the geometric memory) and
+//                 the one-step update (eq. PDEfinal) with the GCL check (eqn.gcl)
+//   k_reconstruct virtual projection of the stencils (eqs. eqn.virtGeom,
+//                 eqn.virtCellaverage), WENO (eqs. intConsRec .. eqn.weno), local
+//                 time step (eq. eqn.timestep) and dyadic level
+//   k_predict     space-time Galerkin predictor of the PDE and of the mesh ODE
+//                 (eqs. timeTransf .. newVertPos)
 // Every write target has a single writer per kernel: no atomics on state.
+//
+// Lane mappings (64-wide wavefronts):
+//   k_reconstruct: 8 lanes per element, lane s solves stencil s (s < 7), lane 7
+//                  computes the CFL step; the WENO sum is a 3-step butterfly.
+//   k_predict:     G lanes per element (G >= nb), lane m owns spatial node m for
+//                  all time nodes; spatial derivatives read the other nodes of the
+//                  same time slice from LDS.
+//   others:        one lane per node, edge or element.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -35,7 +43,14 @@ struct Sz {
   static constexpr int nG = M + 1;
   static constexpr int ne = 2 * nb;
   static constexpr int nu = nb - 1;
+  static constexpr int RS = rec_stride(M);
+  static constexpr int TS = trace_stride(M);
+  static constexpr int WS = wnod_stride(M);
+  static constexpr int VV = rec_off_vv(M);
+  static constexpr int G = nb <= 4 ? 4 : (nb <= 8 ? 8 : 16);   // predictor lanes per element
 };
+
+constexpr int XE = rec_off_xe(), QO = rec_off_q(), AO = rec_off_a(), AVG = rec_off_avg();
 
 __device__ inline void set_err(const Dev& d, int bits) { atomicOr(&d.scal->err, bits); }
 
@@ -92,24 +107,30 @@ __device__ inline void time_antideriv(const Tables* tb, double tau, double L[M +
   }
 }
 
-// Geometry (x0 y0 x1 y1 x2 y2) and average of element j projected to tick nt.
+template <int M>
+__device__ inline const double* rec(const Dev& d, int i) {
+  return d.rec + size_t(i) * Sz<M>::RS;
+}
+
+// Geometry (x0 y0 x1 y1 x2 y2) and average of element j at tick nt: the real
+// data when j is at that tick, else its predictor projected there.
 template <int M>
 __device__ inline bool project(const Dev& d, const Tables* tb, int j, int nt, double delta,
                                double X[6], double Qv[4]) {
-  const int NE = d.NE;
-  int nj = d.tick[j];
-  if (nj == nt) {
+  constexpr int T = M + 1, VV = Sz<M>::VV;
+  const TickStep tsj = d.ts[j];
+  const double* r = rec<M>(d, j);
+  if (tsj.tick == nt) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) X[c] = d.Xe[c * NE + j];
+    for (int c = 0; c < 6; ++c) X[c] = r[XE + c];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Qv[v] = d.Q[v * NE + j];
+    for (int v = 0; v < 4; ++v) Qv[v] = r[QO + v];
     return true;
   }
-  int sj = d.step[j];
-  if (sj <= 0) return false;
-  double tau = double(nt - nj) / double(sj);
-  double dtj = double(sj) * delta;
-  double L[M + 1], l[M + 1];
+  if (tsj.step <= 0) return false;
+  const double tau = double(nt - tsj.tick) / double(tsj.step);
+  const double dtj = double(tsj.step) * delta;
+  double L[T], l[T];
   time_antideriv<M>(tb, tau, L);
   time_basis<M>(tb, tau, l);
 #pragma unroll
@@ -118,14 +139,14 @@ __device__ inline bool project(const Dev& d, const Tables* tb, int j, int nt, do
     for (int c = 0; c < 2; ++c) {
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q <= M; ++q) s += L[q] * d.vvel[((k * (M + 1) + q) * 2 + c) * NE + j];
-      X[2 * k + c] = d.Xe[(2 * k + c) * NE + j] + dtj * s;
+      for (int q = 0; q < T; ++q) s += L[q] * r[VV + (k * T + q) * 2 + c];
+      X[2 * k + c] = r[XE + 2 * k + c] + dtj * s;
     }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q <= M; ++q) s += l[q] * d.avg[(q * 4 + v) * NE + j];
+    for (int q = 0; q < T; ++q) s += l[q] * r[AVG + q * 4 + v];
     Qv[v] = s;
   }
   return true;
@@ -160,25 +181,35 @@ __device__ inline int level_step(double dtcfl, double delta, int N, int tick, in
   return p;
 }
 
+__device__ inline double group8_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+
 // ---------------------------------------------------------------------------
-// Reconstruction + local time step
+// Reconstruction + local time step: 8 lanes per element
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __restrict__ tb, Params P,
                                                      int use_list, int set_level) {
   using S = Sz<M>;
-  constexpr int nb = S::nb, ne = S::ne, nu = S::nu;
+  constexpr int nb = S::nb, ne = S::ne, nu = S::nu, WS = S::WS;
   const int NE = d.NE;
   const int nitems = use_list ? d.scal->n_active : NE;
   const double delta = d.scal->delta;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nitems; idx += gridDim.x * blockDim.x) {
+  const int sl = threadIdx.x & 7;
+  const int ngroups = (gridDim.x * blockDim.x) >> 3;
+  for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; idx < nitems; idx += ngroups) {
     const int i = use_list ? d.act_list[idx] : idx;
-    const int nt = d.tick[i];
+    const int nt = d.ts[i].tick;
+    const double* ri = rec<M>(d, i);
     double Xi[6], Qi[4];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Xi[c] = d.Xe[c * NE + i];
+    for (int c = 0; c < 6; ++c) Xi[c] = ri[XE + c];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Qi[v] = d.Q[v * NE + i];
+    for (int v = 0; v < 4; ++v) Qi[v] = ri[QO + v];
     const double e1x = Xi[2] - Xi[0], e1y = Xi[3] - Xi[1];
     const double e2x = Xi[4] - Xi[0], e2y = Xi[5] - Xi[1];
     const double idet = 1.0 / (e1x * e2y - e2x * e1y);
@@ -187,10 +218,9 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
     for (int l = 0; l < nu; ++l)
 #pragma unroll
       for (int v = 0; v < 4; ++v) W[l][v] = 0.0;
-    double Wsum = 0.0;
+    double om = 0.0;
     bool ok = true;
-    for (int s = 0; s < NSTEN; ++s) {
-      if (d.sten[(s * ne) * NE + i] < 0) continue;
+    if (sl < NSTEN && d.sten[(sl * ne) * NE + i] >= 0) {
       double R[nu][nu], z[nu][4];
 #pragma unroll
       for (int a = 0; a < nu; ++a) {
@@ -200,7 +230,7 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
         for (int v = 0; v < 4; ++v) z[a][v] = 0.0;
       }
       for (int c = 1; c < ne; ++c) {
-        const int j = d.sten[(s * ne + c) * NE + i];
+        const int j = d.sten[(sl * ne + c) * NE + i];
         double Xv[6], Qv[4];
         ok &= project<M>(d, tb, j, nt, delta, Xv, Qv);
         // vertices of the virtual element in the reference frame of element i
@@ -216,9 +246,9 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
 #pragma unroll
         for (int k = 0; k < nb; ++k) mm[k] = 0.0;
         for (int r = 0; r < tb->nrq; ++r) {
-          double px = tb->rqb[r][0] * rx[0] + tb->rqb[r][1] * rx[1] + tb->rqb[r][2] * rx[2];
-          double py = tb->rqb[r][0] * ry[0] + tb->rqb[r][1] * ry[1] + tb->rqb[r][2] * ry[2];
-          double w = tb->rqw[r];
+          const double px = tb->rqb[r][0] * rx[0] + tb->rqb[r][1] * rx[1] + tb->rqb[r][2] * rx[2];
+          const double py = tb->rqb[r][0] * ry[0] + tb->rqb[r][1] * ry[1] + tb->rqb[r][2] * ry[2];
+          const double w = tb->rqw[r];
           double xp[M + 1], yp[M + 1];
           xp[0] = 1.0;
           yp[0] = 1.0;
@@ -249,20 +279,20 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
         // Givens rotations fold the row into the triangular factor
 #pragma unroll
         for (int k = 0; k < nu; ++k) {
-          double rkk = R[k][k], ak = a[k];
-          double h = sqrt(rkk * rkk + ak * ak);
+          const double rkk = R[k][k], ak = a[k];
+          const double h = sqrt(rkk * rkk + ak * ak);
           if (h == 0.0) continue;
-          double cs = rkk / h, sn = ak / h;
+          const double cs = rkk / h, sn = ak / h;
           R[k][k] = h;
 #pragma unroll
           for (int c2 = k + 1; c2 < nu; ++c2) {
-            double t = cs * R[k][c2] + sn * a[c2];
+            const double t = cs * R[k][c2] + sn * a[c2];
             a[c2] = cs * a[c2] - sn * R[k][c2];
             R[k][c2] = t;
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            double t = cs * z[k][v] + sn * b[v];
+            const double t = cs * z[k][v] + sn * b[v];
             b[v] = cs * b[v] - sn * z[k][v];
             z[k][v] = t;
           }
@@ -288,216 +318,256 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
           for (int m = 0; m < nu; ++m) t += tb->Sigma[l + 1][m + 1] * w[m][v];
           sigma += w[l][v] * t;
         }
-      double x = sigma + P.eps;
-      double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
-      double om = (s == 0 ? P.lambda : 1.0) / x8;
-      Wsum += om;
+      const double x = sigma + P.eps;
+      const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
+      om = (sl == 0 ? P.lambda : 1.0) / x8;
 #pragma unroll
       for (int l = 0; l < nu; ++l)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) W[l][v] += om * w[l][v];
+        for (int v = 0; v < 4; ++v) W[l][v] = om * w[l][v];
+    }
+    double dt = 0.0;
+    if (sl == 7) {
+      // local CFL time step over the element and its face neighbours (eq. eqn.timestep)
+      double rmin = cfl_ratio(Xi, Qi, P.gamma);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int j = d.neigh[k * NE + i];
+        if (j < 0) continue;
+        double Xv[6], Qv[4];
+        ok &= project<M>(d, tb, j, nt, delta, Xv, Qv);
+        rmin = fmin(rmin, cfl_ratio(Xv, Qv, P.gamma));
+      }
+      dt = P.cfl * rmin;
     }
     if (!ok) set_err(d, ERR_PRED);
-    const double iw = 1.0 / Wsum;
+    // nonlinear combination of eq. weno: sum over the stencil lanes
+#pragma unroll
+    for (int l = 0; l < nu; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[l][v] = group8_sum(W[l][v]);
+    const double iw = 1.0 / group8_sum(om);
+    double* wo = d.wnod + size_t(i) * WS;
 #pragma unroll
     for (int m = 0; m < nb; ++m)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        if (((m * 4 + v) & 7) != sl) continue;
         double t = tb->psiNodes[m][0] * Qi[v];
 #pragma unroll
         for (int l = 0; l < nu; ++l) t += tb->psiNodes[m][l + 1] * (W[l][v] * iw);
-        d.wnod[(m * 4 + v) * NE + i] = t;
+        wo[m * 4 + v] = t;
       }
-    // local CFL time step over the element and its face neighbours (eq. eqn.timestep)
-    double rmin = cfl_ratio(Xi, Qi, P.gamma);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      int j = d.neigh[k * NE + i];
-      if (j < 0) continue;
-      double Xv[6], Qv[4];
-      if (!project<M>(d, tb, j, nt, delta, Xv, Qv)) set_err(d, ERR_PRED);
-      rmin = fmin(rmin, cfl_ratio(Xv, Qv, P.gamma));
-    }
-    const double dt = P.cfl * rmin;
-    d.dtcfl[i] = dt;
-    if (set_level) {
-      const int N = d.scal->N;
-      if (nt >= N) {
-        d.step[i] = 0;
-      } else {
-        int over;
-        d.step[i] = level_step(dt, delta, N, nt, &over);
-        if (over) atomicAdd(&d.scal->overshoots, 1ull);
+    if (sl == 7) {
+      d.dtcfl[i] = dt;
+      if (set_level) {
+        const int N = d.scal->N;
+        if (nt >= N) {
+          d.ts[i].step = 0;
+        } else {
+          int over;
+          d.ts[i].step = level_step(dt, delta, N, nt, &over);
+          if (over) atomicAdd(&d.scal->overshoots, 1ull);
+        }
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Space-time Galerkin predictor
+// Space-time Galerkin predictor: G lanes per element, lane m = spatial node m
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict__ tb, Params P,
                                                  int use_list) {
   using S = Sz<M>;
-  constexpr int nb = S::nb, nt = S::nt, nG = S::nG;
+  constexpr int nb = S::nb, T = S::nt, nG = S::nG, G = S::G, RS = S::RS, TS = S::TS, WS = S::WS;
+  constexpr int SLOTS = TPB / G;
+  constexpr int NF = 14;                 // exchanged fields per node: q(4) f(4) g(4) x(2)
+  constexpr int NOUT = 4 + 3 * nG * 4;   // per time slice: averages + traces
+  __shared__ double lds[SLOTS][NF][G];
   const int NE = d.NE;
   const int nitems = use_list ? d.scal->n_active : NE;
   const double delta = d.scal->delta;
   const double g = P.gamma;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nitems; idx += gridDim.x * blockDim.x) {
-    const int i = use_list ? d.act_list[idx] : idx;
-    const int st = d.step[i];
-    if (st <= 0) continue;
-    wave_count(&d.scal->n_pred);
-    const double dt = double(st) * delta;
-    double q[nb][nt][4], x[nb][nt][2];
-    {
-      double X[6];
+  const int slot = threadIdx.x / G;
+  const int m = threadIdx.x % G;
+  const bool node = m < nb;
+  const int mm = node ? m : 0;
+  // this lane's rows of the spatial derivative matrices
+  double Dx[nb], De[nb];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) X[c] = d.Xe[c * NE + i];
-      int m = 0;
+  for (int k = 0; k < nb; ++k) {
+    Dx[k] = tb->Dxi[mm][k];
+    De[k] = tb->Deta[mm][k];
+  }
+  // lattice coordinates of node m (ordered by j then i)
+  int jj = 0, ii = mm;
+  while (ii > M - jj) {
+    ii -= M + 1 - jj;
+    ++jj;
+  }
+  const double nxi = double(ii) / M, neta = double(jj) / M;
+  for (int base = blockIdx.x * SLOTS; base < nitems; base += gridDim.x * SLOTS) {
+    const int idx = base + slot;
+    const int i = idx < nitems ? (use_list ? d.act_list[idx] : idx) : -1;
+    const int st = i >= 0 ? d.ts[i].step : 0;
+    const bool live = st > 0;           // uniform across the G lanes of the element
+    const bool act = live && node;
+    if (live && m == 0) wave_count(&d.scal->n_pred);
+    const double dt = live ? double(st) * delta : 1.0;
+    double q[T][4], x[T][2];
+    if (act) {
+      const double* r = rec<M>(d, i);
+      const double px = r[XE + 0] + (r[XE + 2] - r[XE + 0]) * nxi + (r[XE + 4] - r[XE + 0]) * neta;
+      const double py = r[XE + 1] + (r[XE + 3] - r[XE + 1]) * nxi + (r[XE + 5] - r[XE + 1]) * neta;
+      const double* w = d.wnod + size_t(i) * WS + m * 4;
 #pragma unroll
-      for (int jj = 0; jj <= M; ++jj)
+      for (int t = 0; t < T; ++t) {
+        x[t][0] = px;
+        x[t][1] = py;
 #pragma unroll
-        for (int ii = 0; ii + jj <= M; ++ii) {
-          double xi = double(ii) / M, eta = double(jj) / M;
-          double px = X[0] + (X[2] - X[0]) * xi + (X[4] - X[0]) * eta;
-          double py = X[1] + (X[3] - X[1]) * xi + (X[5] - X[1]) * eta;
+        for (int v = 0; v < 4; ++v) q[t][v] = w[v];
+      }
+    } else {
+      // idle lanes carry a harmless state through the exchange
 #pragma unroll
-          for (int t = 0; t < nt; ++t) {
-            x[m][t][0] = px;
-            x[m][t][1] = py;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) q[m][t][v] = d.wnod[(m * 4 + v) * NE + i];
-          }
-          ++m;
-        }
+      for (int t = 0; t < T; ++t) {
+        x[t][0] = x[t][1] = 0.0;
+        q[t][0] = 1.0;
+        q[t][1] = q[t][2] = 0.0;
+        q[t][3] = 1.0;
+      }
     }
     for (int it = 0; it < P.npic; ++it) {
-      // mesh ODE: x_{m,1:} = Bt x_{m,0} + dt At V_m
+      // mesh ODE at this node: x_{1:} = Bt x_0 + dt At V
       if (P.lagrangian) {
+        double V[T][2];
 #pragma unroll
-        for (int m = 0; m < nb; ++m) {
-          double V[nt][2];
-#pragma unroll
-          for (int t = 0; t < nt; ++t) {
-            V[t][0] = q[m][t][1] / q[m][t][0];
-            V[t][1] = q[m][t][2] / q[m][t][0];
-          }
-#pragma unroll
-          for (int r = 0; r < M; ++r)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              double s = 0.0;
-#pragma unroll
-              for (int t = 0; t < nt; ++t) s += tb->At[r][t] * V[t][c];
-              x[m][r + 1][c] = tb->Bt[r] * x[m][0][c] + dt * s;
-            }
+        for (int t = 0; t < T; ++t) {
+          V[t][0] = q[t][1] / q[t][0];
+          V[t][1] = q[t][2] / q[t][0];
         }
-      }
-      double qn[nb][M][4];
-#pragma unroll
-      for (int m = 0; m < nb; ++m)
 #pragma unroll
         for (int r = 0; r < M; ++r)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) qn[m][r][v] = tb->Bt[r] * q[m][0][v];
-#pragma unroll
-      for (int t = 0; t < nt; ++t) {
-        double f[nb][4], gg[nb][4];
-#pragma unroll
-        for (int m = 0; m < nb; ++m) {
-          double u = q[m][t][1] / q[m][t][0], v = q[m][t][2] / q[m][t][0];
-          double p = pressure(q[m][t], g);
-          f[m][0] = q[m][t][1];
-          f[m][1] = q[m][t][1] * u + p;
-          f[m][2] = q[m][t][1] * v;
-          f[m][3] = u * (q[m][t][3] + p);
-          gg[m][0] = q[m][t][2];
-          gg[m][1] = q[m][t][2] * u;
-          gg[m][2] = q[m][t][2] * v + p;
-          gg[m][3] = v * (q[m][t][3] + p);
-        }
-#pragma unroll
-        for (int m = 0; m < nb; ++m) {
-          double xx = 0, xe = 0, yx = 0, ye = 0, xtau = 0, ytau = 0;
-#pragma unroll
-          for (int k = 0; k < nb; ++k) {
-            xx += tb->Dxi[m][k] * x[k][t][0];
-            yx += tb->Dxi[m][k] * x[k][t][1];
-            xe += tb->Deta[m][k] * x[k][t][0];
-            ye += tb->Deta[m][k] * x[k][t][1];
-          }
-#pragma unroll
-          for (int r = 0; r < nt; ++r) {
-            xtau += tb->Dt[t][r] * x[m][r][0];
-            ytau += tb->Dt[t][r] * x[m][r][1];
-          }
-          double det = xx * ye - xe * yx;
-          double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
-          double xt = xtau / dt, yt = ytau / dt;
-          double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            double qxi = 0, qeta = 0, fxi = 0, feta = 0, gxi = 0, geta = 0;
-#pragma unroll
-            for (int k = 0; k < nb; ++k) {
-              qxi += tb->Dxi[m][k] * q[k][t][v];
-              qeta += tb->Deta[m][k] * q[k][t][v];
-              fxi += tb->Dxi[m][k] * f[k][v];
-              feta += tb->Deta[m][k] * f[k][v];
-              gxi += tb->Dxi[m][k] * gg[k][v];
-              geta += tb->Deta[m][k] * gg[k][v];
-            }
-            double Pv = -(qxi * xi_t + qeta * eta_t + fxi * xi_x + feta * eta_x + gxi * xi_y + geta * eta_y);
-#pragma unroll
-            for (int r = 0; r < M; ++r) qn[m][r][v] += dt * tb->At[r][t] * Pv;
-          }
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < nb; ++m)
-#pragma unroll
-        for (int r = 0; r < M; ++r)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) q[m][r + 1][v] = qn[m][r][v];
-    }
-    // publish: reference means, edge traces, vertex velocities of the final iterate
-#pragma unroll
-    for (int t = 0; t < nt; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < nb; ++m) s += tb->amean[m] * q[m][t][v];
-        d.avg[(t * 4 + v) * NE + i] = s;
-      }
-#pragma unroll
-    for (int e = 0; e < 3; ++e)
-#pragma unroll
-      for (int gq = 0; gq < nG; ++gq)
-#pragma unroll
-        for (int t = 0; t < nt; ++t)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
+          for (int c = 0; c < 2; ++c) {
             double s = 0.0;
 #pragma unroll
-            for (int m = 0; m < nb; ++m) s += tb->edge[e][gq][m] * q[m][t][v];
-            d.trace[(((e * nG + gq) * nt + t) * 4 + v) * NE + i] = s;
+            for (int t = 0; t < T; ++t) s += tb->At[r][t] * V[t][c];
+            x[r + 1][c] = tb->Bt[r] * x[0][c] + dt * s;
           }
+      }
+      double qn[M][4];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int m = tb->vtx[k];
+      for (int r = 0; r < M; ++r)
 #pragma unroll
-      for (int t = 0; t < nt; ++t) {
-        double vx = 0.0, vy = 0.0;
-        if (P.lagrangian) {
-          vx = q[m][t][1] / q[m][t][0];
-          vy = q[m][t][2] / q[m][t][0];
+        for (int v = 0; v < 4; ++v) qn[r][v] = tb->Bt[r] * q[0][v];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        // publish this node's fields of time slice t
+        {
+          const double u = q[t][1] / q[t][0], v = q[t][2] / q[t][0];
+          const double p = pressure(q[t], g);
+          lds[slot][0][m] = q[t][0];
+          lds[slot][1][m] = q[t][1];
+          lds[slot][2][m] = q[t][2];
+          lds[slot][3][m] = q[t][3];
+          lds[slot][4][m] = q[t][1];
+          lds[slot][5][m] = q[t][1] * u + p;
+          lds[slot][6][m] = q[t][1] * v;
+          lds[slot][7][m] = u * (q[t][3] + p);
+          lds[slot][8][m] = q[t][2];
+          lds[slot][9][m] = q[t][2] * u;
+          lds[slot][10][m] = q[t][2] * v + p;
+          lds[slot][11][m] = v * (q[t][3] + p);
+          lds[slot][12][m] = x[t][0];
+          lds[slot][13][m] = x[t][1];
         }
-        d.vvel[((k * nt + t) * 2 + 0) * NE + i] = vx;
-        d.vvel[((k * nt + t) * 2 + 1) * NE + i] = vy;
+        __syncthreads();
+        double dxi[NF], deta[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          double a = 0.0, b = 0.0;
+#pragma unroll
+          for (int k = 0; k < nb; ++k) {
+            const double val = lds[slot][f][k];
+            a += Dx[k] * val;
+            b += De[k] * val;
+          }
+          dxi[f] = a;
+          deta[f] = b;
+        }
+        __syncthreads();
+        double xtau = 0.0, ytau = 0.0;
+#pragma unroll
+        for (int r = 0; r < T; ++r) {
+          xtau += tb->Dt[t][r] * x[r][0];
+          ytau += tb->Dt[t][r] * x[r][1];
+        }
+        const double xx = dxi[12], yx = dxi[13], xe = deta[12], ye = deta[13];
+        const double det = xx * ye - xe * yx;
+        const double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
+        const double xt = xtau / dt, yt = ytau / dt;
+        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double Pv = -(dxi[v] * xi_t + deta[v] * eta_t + dxi[4 + v] * xi_x + deta[4 + v] * eta_x +
+                              dxi[8 + v] * xi_y + deta[8 + v] * eta_y);
+#pragma unroll
+          for (int r = 0; r < M; ++r) qn[r][v] += dt * tb->At[r][t] * Pv;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q[r + 1][v] = qn[r][v];
+    }
+    // publish: reference means and edge traces (one slice at a time through
+    // LDS), vertex velocities of the final iterate
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) lds[slot][c][m] = q[t][c];
+      __syncthreads();
+      if (live) {
+        double* rw = d.rec + size_t(i) * RS;
+        double* tw = d.trace + size_t(i) * TS;
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+          if (o % G != m) continue;
+          const int v = o & 3;
+          double s = 0.0;
+          if (o < 4) {
+#pragma unroll
+            for (int k = 0; k < nb; ++k) s += tb->amean[k] * lds[slot][v][k];
+            rw[AVG + t * 4 + v] = s;
+          } else {
+            const int eg = (o - 4) >> 2;      // e * nG + gq
+            const int e = eg / nG, gq = eg % nG;
+#pragma unroll
+            for (int k = 0; k < nb; ++k) s += tb->edge[e][gq][k] * lds[slot][v][k];
+            tw[(eg * T + t) * 4 + v] = s;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (act) {
+      double* rw = d.rec + size_t(i) * RS;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (tb->vtx[k] != m) continue;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          double vx = 0.0, vy = 0.0;
+          if (P.lagrangian) {
+            vx = q[t][1] / q[t][0];
+            vy = q[t][2] / q[t][0];
+          }
+          rw[S::VV + (k * T + t) * 2 + 0] = vx;
+          rw[S::VV + (k * T + t) * 2 + 1] = vy;
+        }
       }
     }
   }
@@ -519,22 +589,21 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int cycle) {
     const int i = base + threadIdx.x;
     bool act = false, unf = false;
     if (i < NE) {
-      const int n = d.tick[i];
-      if (n < N) {
+      const TickStep me = d.ts[i];
+      if (me.tick < N) {
         unf = true;
-        const int fut = n + d.step[i];
+        const int fut = me.tick + me.step;
         int mx = 0, mn = 1 << 30;
         for (int r = d.sched_ptr[i]; r < d.sched_ptr[i + 1]; ++r) {
-          int j = d.sched_idx[r];
-          int nj = d.tick[j];
-          mx = max(mx, nj);
-          mn = min(mn, nj + d.step[j]);
+          const TickStep o = d.ts[d.sched_idx[r]];
+          mx = max(mx, o.tick);
+          mn = min(mn, o.tick + o.step);
         }
         act = (mx <= fut) && (fut <= mn);
       }
     }
-    unsigned long long ma = __ballot(act);
-    unsigned long long mu = __ballot(unf);
+    const unsigned long long ma = __ballot(act);
+    const unsigned long long mu = __ballot(unf);
     int base_slot = 0;
     if (lane == 0) {
       if (ma) base_slot = atomicAdd(&d.scal->n_active, __popcll(ma));
@@ -543,7 +612,7 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int cycle) {
     }
     base_slot = __shfl(base_slot, 0);
     if (act) {
-      int pos = base_slot + __popcll(ma & ((1ull << lane) - 1ull));
+      const int pos = base_slot + __popcll(ma & ((1ull << lane) - 1ull));
       d.act_list[pos] = i;
       d.act_stamp[i] = cycle;
     }
@@ -555,16 +624,17 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int cycle) {
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ tb, Params P, int cycle) {
-  constexpr int nt = M + 1;
-  const int NE = d.NE, NV = d.NV;
+  constexpr int T = M + 1, VV = Sz<M>::VV;
+  const int NV = d.NV;
   const double delta = d.scal->delta;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
     const int r0 = d.ring_ptr[k], r1 = d.ring_ptr[k + 1];
     int newt = -1;
     for (int r = r0; r < r1; ++r) {
-      int j = d.ring_ent[r] >> 2;
+      const int j = d.ring_ent[r] >> 2;
       if (d.act_stamp[j] == cycle) {
-        newt = d.tick[j] + d.step[j];
+        const TickStep tsj = d.ts[j];
+        newt = tsj.tick + tsj.step;
         break;
       }
     }
@@ -575,24 +645,26 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
     for (int r = r0; r < r1; ++r) {
       const int ent = d.ring_ent[r];
       const int j = ent >> 2, lv = ent & 3;
-      const int nj = d.tick[j], sj = d.step[j];
-      if (sj <= 0) {
+      const TickStep tsj = d.ts[j];
+      if (tsj.step <= 0) {
         ok = false;
         continue;
       }
-      const double tau0 = double(nk - nj) / double(sj), tau1 = double(newt - nj) / double(sj);
-      double L0[nt], L1[nt];
+      const double tau0 = double(nk - tsj.tick) / double(tsj.step);
+      const double tau1 = double(newt - tsj.tick) / double(tsj.step);
+      double L0[T], L1[T];
       time_antideriv<M>(tb, tau0, L0);
       time_antideriv<M>(tb, tau1, L1);
+      const double* rj = rec<M>(d, j);
       double vx = 0.0, vy = 0.0;
 #pragma unroll
-      for (int q = 0; q < nt; ++q) {
-        double I = L1[q] - L0[q];
-        vx += I * d.vvel[((lv * nt + q) * 2 + 0) * NE + j];
-        vy += I * d.vvel[((lv * nt + q) * 2 + 1) * NE + j];
+      for (int q = 0; q < T; ++q) {
+        const double I = L1[q] - L0[q];
+        vx += I * rj[VV + (lv * T + q) * 2 + 0];
+        vy += I * rj[VV + (lv * T + q) * 2 + 1];
       }
       const double inv = 1.0 / (tau1 - tau0);
-      const double mu = d.Q[j] * d.A[j];
+      const double mu = rj[QO] * rj[AO];
       Vx += mu * (vx * inv);
       Vy += mu * (vy * inv);
       mu_sum += mu;
@@ -619,12 +691,12 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Space-time patch fluxes
+// Space-time patch fluxes: one lane per swept edge
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__ tb, Params P, int cycle) {
-  constexpr int nt = M + 1, nG = M + 1;
-  const int NE = d.NE, NV = d.NV, NF = d.NF;
+  constexpr int T = M + 1, nG = M + 1, TS = Sz<M>::TS;
+  const int NV = d.NV, NF = d.NF;
   const double delta = d.scal->delta;
   const double g = P.gamma;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
@@ -647,28 +719,25 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
     P4[1] = ma ? d.Xnew[NV + a] : P1[1];
     P4[2] = n4 * delta;
     const int L = d.e_L[e], el = d.e_el[e], R = d.e_R[e], er = d.e_er[e], bc = d.e_bc[e];
-    const int sL = d.step[L];
-    const double nL = d.tick[L];
-    int sR = 1;
-    double nR = 0.0;
-    if (R >= 0) {
-      sR = d.step[R];
-      nR = d.tick[R];
-    }
-    if (sL <= 0 || sR <= 0) {
+    const TickStep tL = d.ts[L];
+    TickStep tR{0, 1};
+    if (R >= 0) tR = d.ts[R];
+    if (tL.step <= 0 || tR.step <= 0) {
       set_err(d, ERR_PRED);
       continue;
     }
+    const double* trL = d.trace + size_t(L) * TS + el * nG * T * 4;
+    const double* trR = R >= 0 ? d.trace + size_t(R) * TS + er * nG * T * 4 : trL;
     double G[4] = {0, 0, 0, 0}, Nn[3] = {0, 0, 0};
-#pragma unroll
+#pragma unroll 1
     for (int gq = 0; gq < nG; ++gq) {
-      double trL[nt][4], trR[nt][4];
+      double qL[T][4], qR[T][4];
 #pragma unroll
-      for (int t = 0; t < nt; ++t)
+      for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          trL[t][v] = d.trace[(((el * nG + gq) * nt + t) * 4 + v) * NE + L];
-          trR[t][v] = R >= 0 ? d.trace[(((er * nG + (nG - 1 - gq)) * nt + t) * 4 + v) * NE + R] : 0.0;
+          qL[t][v] = trL[(gq * T + t) * 4 + v];
+          qR[t][v] = trR[((nG - 1 - gq) * T + t) * 4 + v];
         }
       const double c = tb->gchi[gq];
 #pragma unroll
@@ -685,27 +754,28 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
         N[1] = dchi[2] * dtau[0] - dchi[0] * dtau[2];
         N[2] = dchi[0] * dtau[1] - dchi[1] * dtau[0];
         const double tk = (1.0 - c) * (1.0 - tt) * n1 + c * (1.0 - tt) * n2 + c * tt * n3 + (1.0 - c) * tt * n4;
-        double lL[nt];
-        time_basis<M>(tb, (tk - nL) / double(sL), lL);
+        double lL[T];
+        time_basis<M>(tb, (tk - tL.tick) / double(tL.step), lL);
         double ql[4], qr[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           double s = 0.0;
 #pragma unroll
-          for (int t = 0; t < nt; ++t) s += lL[t] * trL[t][v];
+          for (int t = 0; t < T; ++t) s += lL[t] * qL[t][v];
           ql[v] = s;
         }
         if (R >= 0) {
-          double lR[nt];
-          time_basis<M>(tb, (tk - nR) / double(sR), lR);
+          double lR[T];
+          time_basis<M>(tb, (tk - tR.tick) / double(tR.step), lR);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             double s = 0.0;
 #pragma unroll
-            for (int t = 0; t < nt; ++t) s += lR[t] * trR[t][v];
+            for (int t = 0; t < T; ++t) s += lR[t] * qR[t][v];
             qr[v] = s;
           }
         } else if (bc == 2) {
+          // slip wall: mirror the normal momentum
           const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
           const double nx = N[0] / nxy, ny = N[1] / nxy;
           const double mn = ql[1] * nx + ql[2] * ny;
@@ -739,6 +809,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
 // ---------------------------------------------------------------------------
 // Memory variables and conservative update
 // ---------------------------------------------------------------------------
+template <int M>
 __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P, int cycle) {
   const int NE = d.NE, NV = d.NV, NF = d.NF;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
@@ -784,29 +855,32 @@ __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P, int cycle) {
       X[2 * k] = mv[k] ? d.Xnew[nd[k]] : d.X[nd[k]];
       X[2 * k + 1] = mv[k] ? d.Xnew[NV + nd[k]] : d.X[NV + nd[k]];
     }
+    double* r = d.rec + size_t(i) * Sz<M>::RS;
     const double An = tri_area(X);
-    const double A0 = d.A[i];
+    const double A0 = r[AO];
     if (!(An > 0.0)) set_err(d, ERR_GEOM);
-    const double r = fmax(fmax(fabs(hm[0]), fabs(hm[1])), fabs(hm[2] - (An - A0)));
-    const double rel = r / (A0 + An);
+    const double res = fmax(fmax(fabs(hm[0]), fabs(hm[1])), fabs(hm[2] - (An - A0)));
+    const double rel = res / (A0 + An);
     atomic_max_pos(&d.scal->max_gcl_bits, rel);
     if (!(rel <= P.gcl_tol)) set_err(d, ERR_GCL);
     double qn[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) qn[v] = (A0 * d.Q[v * NE + i] + qm[v]) / An;
+    for (int v = 0; v < 4; ++v) qn[v] = (A0 * r[QO + v] + qm[v]) / An;
     const double pn = pressure(qn, P.gamma);
     if (!(qn[0] > 0.0) || !(pn > 0.0)) set_err(d, ERR_STATE);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      d.Q[v * NE + i] = qn[v];
+      r[QO + v] = qn[v];
       d.QM[v * NE + i] = 0.0;
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) d.HM[c * NE + i] = 0.0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) d.Xe[c * NE + i] = X[c];
-    d.A[i] = An;
-    d.tick[i] = d.tick[i] + d.step[i];
+    for (int c = 0; c < 6; ++c) r[XE + c] = X[c];
+    r[AO] = An;
+    TickStep me = d.ts[i];
+    me.tick += me.step;
+    d.ts[i] = me;
     // commit the moved nodes (every writer stores the same value)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -840,8 +914,8 @@ __global__ void __launch_bounds__(TPB) k_min_dt(Dev d) {
 
 __global__ void k_macro_setup(Dev d, double t_end, int N) {
   Scal* s = d.scal;
-  double dmin = __longlong_as_double((long long)s->min_dt_bits);
-  double rest = (t_end - s->T) / double(N);
+  const double dmin = __longlong_as_double((long long)s->min_dt_bits);
+  const double rest = (t_end - s->T) / double(N);
   s->delta = fmin(dmin, rest);
   s->N = N;
   s->t_end = t_end;
@@ -854,8 +928,10 @@ __global__ void __launch_bounds__(TPB) k_levels(Dev d) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     if (i < d.NE) {
       int over;
-      d.tick[i] = 0;
-      d.step[i] = level_step(d.dtcfl[i], delta, N, 0, &over);
+      TickStep me;
+      me.tick = 0;
+      me.step = level_step(d.dtcfl[i], delta, N, 0, &over);
+      d.ts[i] = me;
       if (over) atomicAdd(&d.scal->overshoots, 1ull);
     }
     if (i < d.NV) d.ntick[i] = 0;
@@ -871,7 +947,7 @@ __global__ void __launch_bounds__(TPB) k_macro_end(Dev d) {
     s->T = s->T + double(s->N) * s->delta;
   }
   for (int i = gid; i < n; i += gridDim.x * blockDim.x) {
-    if (i < d.NE) d.tick[i] = 0;
+    if (i < d.NE) d.ts[i].tick = 0;
     if (i < d.NV) d.ntick[i] = 0;
   }
 }
@@ -882,8 +958,8 @@ __global__ void __launch_bounds__(TPB) k_count(Dev d) {
   const int N = d.scal->N;
   for (int base = blockIdx.x * blockDim.x; base < d.NE; base += gridDim.x * blockDim.x) {
     const int i = base + threadIdx.x;
-    bool unf = i < d.NE && d.tick[i] < N;
-    unsigned long long m = __ballot(unf);
+    const bool unf = i < d.NE && d.ts[i].tick < N;
+    const unsigned long long m = __ballot(unf);
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(&d.scal->n_unfinished, __popcll(m));
   }
 }
@@ -891,6 +967,7 @@ __global__ void __launch_bounds__(TPB) k_count(Dev d) {
 // ---------------------------------------------------------------------------
 // Set-up and I/O
 // ---------------------------------------------------------------------------
+template <int M>
 __global__ void __launch_bounds__(TPB) k_init_geometry(Dev d) {
   const int NE = d.NE, NV = d.NV, NF = d.NF;
   const int n = max(max(NE, NV), NF);
@@ -899,15 +976,15 @@ __global__ void __launch_bounds__(TPB) k_init_geometry(Dev d) {
       double X[6];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        int nd = d.tri[k * NE + i];
+        const int nd = d.tri[k * NE + i];
         X[2 * k] = d.X[nd];
         X[2 * k + 1] = d.X[NV + nd];
       }
+      double* r = d.rec + size_t(i) * Sz<M>::RS;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) d.Xe[c * NE + i] = X[c];
-      d.A[i] = tri_area(X);
-      d.tick[i] = 0;
-      d.step[i] = 0;
+      for (int c = 0; c < 6; ++c) r[XE + c] = X[c];
+      r[AO] = tri_area(X);
+      d.ts[i] = TickStep{0, 0};
       d.act_stamp[i] = -1;
 #pragma unroll
       for (int v = 0; v < 4; ++v) d.QM[v * NE + i] = 0.0;
@@ -922,13 +999,32 @@ __global__ void __launch_bounds__(TPB) k_init_geometry(Dev d) {
   }
 }
 
+template <int M>
 __global__ void __launch_bounds__(TPB) k_check_state(Dev d, double g) {
-  const int NE = d.NE;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x) {
+    const double* r = d.rec + size_t(i) * Sz<M>::RS;
     double q[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) q[v] = d.Q[v * NE + i];
+    for (int v = 0; v < 4; ++v) q[v] = r[QO + v];
     if (!(q[0] > 0.0) || !(pressure(q, g) > 0.0)) set_err(d, ERR_STATE);
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(TPB) k_download_q(Dev d, double* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x) {
+    const double* r = d.rec + size_t(i) * Sz<M>::RS;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[size_t(v) * d.NE + i] = r[QO + v];
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(TPB) k_upload_q(Dev d, const double* in) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x) {
+    double* r = d.rec + size_t(i) * Sz<M>::RS;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) r[QO + v] = in[size_t(v) * d.NE + i];
   }
 }
 
@@ -942,23 +1038,24 @@ __global__ void __launch_bounds__(TPB) k_download_xy(Dev d, double* out) {
 __global__ void __launch_bounds__(TPB) k_elem_times(Dev d, double* out) {
   const double T = d.scal->T, delta = d.scal->delta;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x)
-    out[i] = T + double(d.tick[i]) * delta;
+    out[i] = T + double(d.ts[i].tick) * delta;
 }
 
-int grid_for(int n) {
-  int b = (n + TPB - 1) / TPB;
+int grid_for(long n) {
+  long b = (n + TPB - 1) / TPB;
   if (b < 1) b = 1;
-  if (b > 8192) b = 8192;
-  return b;
+  if (b > 16384) b = 16384;
+  return int(b);
 }
 
-#define AW_LAUNCH(kern, n, stream, ...)                                                   \
-  do {                                                                                    \
-    hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(TPB), 0, (hipStream_t)(stream),      \
-                       __VA_ARGS__);                                                      \
-    hipError_t _e = hipGetLastError();                                                    \
-    if (_e != hipSuccess) return int(_e);                                                 \
+#define AW_LAUNCH_G(kern, grid, stream, ...)                                                \
+  do {                                                                                      \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(TPB), 0, (hipStream_t)(stream), __VA_ARGS__); \
+    hipError_t _e = hipGetLastError();                                                      \
+    if (_e != hipSuccess) return int(_e);                                                   \
   } while (0)
+
+#define AW_LAUNCH(kern, n, stream, ...) AW_LAUNCH_G(kern, grid_for(n), stream, __VA_ARGS__)
 
 #define AW_LAUNCH1(kern, stream, ...)                                                     \
   do {                                                                                    \
@@ -967,55 +1064,32 @@ int grid_for(int n) {
     if (_e != hipSuccess) return int(_e);                                                 \
   } while (0)
 
-template <int M>
-int reconstruct_m(const Dev& d, const Params& p, int use_list, int set_level, void* s) {
-  AW_LAUNCH(k_reconstruct<M>, d.NE, s, d, d.tab, p, use_list, set_level);
-  return 0;
-}
-
-template <int M>
-int predict_m(const Dev& d, const Params& p, int use_list, void* s) {
-  AW_LAUNCH(k_predict<M>, d.NE, s, d, d.tab, p, use_list);
-  return 0;
-}
-
-template <int M>
-int node_m(const Dev& d, const Params& p, int cycle, void* s) {
-  AW_LAUNCH(k_node<M>, d.NV, s, d, d.tab, p, cycle);
-  return 0;
-}
-
-template <int M>
-int patch_m(const Dev& d, const Params& p, int cycle, void* s) {
-  AW_LAUNCH(k_patch<M>, d.NF, s, d, d.tab, p, cycle);
-  return 0;
-}
+#define AW_DISPATCH(M, ...)                                    \
+  switch (M) {                                                 \
+    case 1: { constexpr int MM = 1; __VA_ARGS__; } break;      \
+    case 2: { constexpr int MM = 2; __VA_ARGS__; } break;      \
+    case 3: { constexpr int MM = 3; __VA_ARGS__; } break;      \
+    default: return int(hipErrorInvalidValue);                 \
+  }
 
 }  // namespace
 
 int launch_init_geometry(const Dev& d, void* s) {
   int n = d.NE > d.NV ? d.NE : d.NV;
   if (d.NF > n) n = d.NF;
-  AW_LAUNCH(k_init_geometry, n, s, d);
+  AW_DISPATCH(d.M, AW_LAUNCH(k_init_geometry<MM>, n, s, d));
   return 0;
 }
 
 int launch_reconstruct(const Dev& d, const Params& p, int M, int use_list, int set_level, void* s) {
-  switch (M) {
-    case 1: return reconstruct_m<1>(d, p, use_list, set_level, s);
-    case 2: return reconstruct_m<2>(d, p, use_list, set_level, s);
-    case 3: return reconstruct_m<3>(d, p, use_list, set_level, s);
-  }
-  return int(hipErrorInvalidValue);
+  // 8 lanes per element
+  AW_DISPATCH(M, AW_LAUNCH(k_reconstruct<MM>, 8L * d.NE, s, d, d.tab, p, use_list, set_level));
+  return 0;
 }
 
 int launch_predict(const Dev& d, const Params& p, int M, int use_list, void* s) {
-  switch (M) {
-    case 1: return predict_m<1>(d, p, use_list, s);
-    case 2: return predict_m<2>(d, p, use_list, s);
-    case 3: return predict_m<3>(d, p, use_list, s);
-  }
-  return int(hipErrorInvalidValue);
+  AW_DISPATCH(M, AW_LAUNCH(k_predict<MM>, long(Sz<MM>::G) * d.NE, s, d, d.tab, p, use_list));
+  return 0;
 }
 
 int launch_macro_begin(const Dev& d, double t_end, int N, void* s) {
@@ -1037,25 +1111,17 @@ int launch_sched(const Dev& d, int cycle, void* s) {
 }
 
 int launch_node(const Dev& d, const Params& p, int M, int cycle, void* s) {
-  switch (M) {
-    case 1: return node_m<1>(d, p, cycle, s);
-    case 2: return node_m<2>(d, p, cycle, s);
-    case 3: return node_m<3>(d, p, cycle, s);
-  }
-  return int(hipErrorInvalidValue);
+  AW_DISPATCH(M, AW_LAUNCH(k_node<MM>, d.NV, s, d, d.tab, p, cycle));
+  return 0;
 }
 
 int launch_patch(const Dev& d, const Params& p, int M, int cycle, void* s) {
-  switch (M) {
-    case 1: return patch_m<1>(d, p, cycle, s);
-    case 2: return patch_m<2>(d, p, cycle, s);
-    case 3: return patch_m<3>(d, p, cycle, s);
-  }
-  return int(hipErrorInvalidValue);
+  AW_DISPATCH(M, AW_LAUNCH(k_patch<MM>, d.NF, s, d, d.tab, p, cycle));
+  return 0;
 }
 
 int launch_update(const Dev& d, const Params& p, int cycle, void* s) {
-  AW_LAUNCH(k_update, d.NE, s, d, p, cycle);
+  AW_DISPATCH(d.M, AW_LAUNCH(k_update<MM>, d.NE, s, d, p, cycle));
   return 0;
 }
 
@@ -1075,13 +1141,23 @@ int launch_download_xy(const Dev& d, double* out, void* s) {
   return 0;
 }
 
+int launch_download_q(const Dev& d, double* out, void* s) {
+  AW_DISPATCH(d.M, AW_LAUNCH(k_download_q<MM>, d.NE, s, d, out));
+  return 0;
+}
+
+int launch_upload_q(const Dev& d, const double* in, void* s) {
+  AW_DISPATCH(d.M, AW_LAUNCH(k_upload_q<MM>, d.NE, s, d, in));
+  return 0;
+}
+
 int launch_elem_times(const Dev& d, double* out, void* s) {
   AW_LAUNCH(k_elem_times, d.NE, s, d, out);
   return 0;
 }
 
 int launch_check_state(const Dev& d, double gamma, void* s) {
-  AW_LAUNCH(k_check_state, d.NE, s, d, gamma);
+  AW_DISPATCH(d.M, AW_LAUNCH(k_check_state<MM>, d.NE, s, d, gamma));
   return 0;
 }
 
