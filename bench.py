@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=5000)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); "
@@ -186,6 +188,14 @@ def main():
                     frac=achieved / PEAK_HBM_GBS, traffic=None, kernel=f"k_{dom}",
                     bytes_per_unit=per, avg_launch_us=avg_s * 1e6)
     total_ms = sum(v[0] for v in kt.values())
+
+    if a.calib_copy_mib:
+        n = a.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        sync()
 
     cpu = None
     if not a.no_cpu_baseline:

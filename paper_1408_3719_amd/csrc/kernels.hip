@@ -68,21 +68,25 @@ __device__ inline double pressure(const double q[4], double g) {
   return (g - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
 }
 
-// F~(q) . N = f N_x + g N_y + q N_t (eq. PDEdiv3D)
-__device__ inline void stflux(const double q[4], const double N[3], double g, double out[4]) {
-  double u = q[1] / q[0], v = q[2] / q[0];
-  double p = pressure(q, g);
-  double un = u * N[0] + v * N[1] + N[2];
+// Space-time flux F~(q) . N = f N_x + g N_y + q N_t (eq. PDEdiv3D) and the
+// largest |eigenvalue| of the ALE Jacobian along N (eq. A_n^V); nxy = |N_xy|.
+__device__ inline double stflux_speed(const double q[4], const double N[3], double nxy, double g,
+                                      double out[4]) {
+  const double ir = 1.0 / q[0];
+  const double u = q[1] * ir, v = q[2] * ir;
+  const double p = (g - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+  const double uxy = u * N[0] + v * N[1];
+  const double un = uxy + N[2];
   out[0] = q[0] * un;
   out[1] = q[1] * un + p * N[0];
   out[2] = q[2] * un + p * N[1];
-  out[3] = q[3] * un + p * (u * N[0] + v * N[1]);
+  out[3] = q[3] * un + p * uxy;
+  return fabs(un) + sqrt(g * p * ir) * nxy;
 }
 
-__device__ inline double stspeed(const double q[4], const double N[3], double g) {
-  double u = q[1] / q[0], v = q[2] / q[0];
-  double c = sqrt(g * pressure(q, g) / q[0]);
-  return fabs(u * N[0] + v * N[1] + N[2]) + c * sqrt(N[0] * N[0] + N[1] * N[1]);
+// (a - b) / step for a power-of-two step, exactly
+__device__ inline double tick_ratio(double a_minus_b, int step) {
+  return ldexp(a_minus_b, -__builtin_ctz(step));
 }
 
 template <int M>
@@ -128,7 +132,7 @@ __device__ inline bool project(const Dev& d, const Tables* tb, int j, int nt, do
     return true;
   }
   if (tsj.step <= 0) return false;
-  const double tau = double(nt - tsj.tick) / double(tsj.step);
+  const double tau = tick_ratio(double(nt - tsj.tick), tsj.step);
   const double dtj = double(tsj.step) * delta;
   double L[T], l[T];
   time_antideriv<M>(tb, tau, L);
@@ -229,6 +233,7 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
 #pragma unroll
         for (int v = 0; v < 4; ++v) z[a][v] = 0.0;
       }
+#pragma unroll 1
       for (int c = 1; c < ne; ++c) {
         const int j = d.sten[(sl * ne + c) * NE + i];
         double Xv[6], Qv[4];
@@ -280,10 +285,11 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
 #pragma unroll
         for (int k = 0; k < nu; ++k) {
           const double rkk = R[k][k], ak = a[k];
-          const double h = sqrt(rkk * rkk + ak * ak);
-          if (h == 0.0) continue;
-          const double cs = rkk / h, sn = ak / h;
-          R[k][k] = h;
+          const double h2 = rkk * rkk + ak * ak;
+          if (h2 == 0.0) continue;
+          const double rh = rsqrt(h2);
+          const double cs = rkk * rh, sn = ak * rh;
+          R[k][k] = h2 * rh;
 #pragma unroll
           for (int c2 = k + 1; c2 < nu; ++c2) {
             const double t = cs * R[k][c2] + sn * a[c2];
@@ -300,14 +306,16 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
       }
       double w[nu][4];
 #pragma unroll
-      for (int k = nu - 1; k >= 0; --k)
+      for (int k = nu - 1; k >= 0; --k) {
+        const double rinv = 1.0 / R[k][k];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           double t = z[k][v];
 #pragma unroll
           for (int c2 = k + 1; c2 < nu; ++c2) t -= R[k][c2] * w[c2][v];
-          w[k][v] = t / R[k][k];
+          w[k][v] = t * rinv;
         }
+      }
       double sigma = 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
@@ -416,6 +424,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
     const bool act = live && node;
     if (live && m == 0) wave_count(&d.scal->n_pred);
     const double dt = live ? double(st) * delta : 1.0;
+    const double idt = 1.0 / dt;
     double q[T][4], x[T][2];
     if (act) {
       const double* r = rec<M>(d, i);
@@ -445,8 +454,9 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
         double V[T][2];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-          V[t][0] = q[t][1] / q[t][0];
-          V[t][1] = q[t][2] / q[t][0];
+          const double ir = 1.0 / q[t][0];
+          V[t][0] = q[t][1] * ir;
+          V[t][1] = q[t][2] * ir;
         }
 #pragma unroll
         for (int r = 0; r < M; ++r)
@@ -467,8 +477,9 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
       for (int t = 0; t < T; ++t) {
         // publish this node's fields of time slice t
         {
-          const double u = q[t][1] / q[t][0], v = q[t][2] / q[t][0];
-          const double p = pressure(q[t], g);
+          const double ir = 1.0 / q[t][0];
+          const double u = q[t][1] * ir, v = q[t][2] * ir;
+          const double p = (g - 1.0) * (q[t][3] - 0.5 * (q[t][1] * u + q[t][2] * v));
           lds[slot][0][m] = q[t][0];
           lds[slot][1][m] = q[t][1];
           lds[slot][2][m] = q[t][2];
@@ -485,9 +496,30 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
           lds[slot][13][m] = x[t][1];
         }
         __syncthreads();
-        double dxi[NF], deta[NF];
+        // metric of the isoparametric map at this node (eq. Jac)
+        double xx = 0.0, xe = 0.0, yx = 0.0, ye = 0.0;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
+        for (int k = 0; k < nb; ++k) {
+          const double vx = lds[slot][12][k], vy = lds[slot][13][k];
+          xx += Dx[k] * vx;
+          xe += De[k] * vx;
+          yx += Dx[k] * vy;
+          ye += De[k] * vy;
+        }
+        double xtau = 0.0, ytau = 0.0;
+#pragma unroll
+        for (int r = 0; r < T; ++r) {
+          xtau += tb->Dt[t][r] * x[r][0];
+          ytau += tb->Dt[t][r] * x[r][1];
+        }
+        const double idet = 1.0 / (xx * ye - xe * yx);
+        const double xi_x = ye * idet, xi_y = -xe * idet, eta_x = -yx * idet, eta_y = xx * idet;
+        const double xt = xtau * idt, yt = ytau * idt;
+        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
+        // P = -(q_xi xi_t + q_eta eta_t + f_xi xi_x + f_eta eta_x + g_xi xi_y + g_eta eta_y)
+        double Pv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int f = 0; f < 12; ++f) {
           double a = 0.0, b = 0.0;
 #pragma unroll
           for (int k = 0; k < nb; ++k) {
@@ -495,28 +527,15 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
             a += Dx[k] * val;
             b += De[k] * val;
           }
-          dxi[f] = a;
-          deta[f] = b;
+          const double cx = f < 4 ? xi_t : (f < 8 ? xi_x : xi_y);
+          const double ce = f < 4 ? eta_t : (f < 8 ? eta_x : eta_y);
+          Pv[f & 3] -= a * cx + b * ce;
         }
         __syncthreads();
-        double xtau = 0.0, ytau = 0.0;
 #pragma unroll
-        for (int r = 0; r < T; ++r) {
-          xtau += tb->Dt[t][r] * x[r][0];
-          ytau += tb->Dt[t][r] * x[r][1];
-        }
-        const double xx = dxi[12], yx = dxi[13], xe = deta[12], ye = deta[13];
-        const double det = xx * ye - xe * yx;
-        const double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
-        const double xt = xtau / dt, yt = ytau / dt;
-        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double Pv = -(dxi[v] * xi_t + deta[v] * eta_t + dxi[4 + v] * xi_x + deta[4 + v] * eta_x +
-                              dxi[8 + v] * xi_y + deta[8 + v] * eta_y);
-#pragma unroll
-          for (int r = 0; r < M; ++r) qn[r][v] += dt * tb->At[r][t] * Pv;
-        }
+          for (int r = 0; r < M; ++r) qn[r][v] += dt * tb->At[r][t] * Pv[v];
       }
 #pragma unroll
       for (int r = 0; r < M; ++r)
@@ -562,8 +581,9 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
         for (int t = 0; t < T; ++t) {
           double vx = 0.0, vy = 0.0;
           if (P.lagrangian) {
-            vx = q[t][1] / q[t][0];
-            vy = q[t][2] / q[t][0];
+            const double ir = 1.0 / q[t][0];
+            vx = q[t][1] * ir;
+            vy = q[t][2] * ir;
           }
           rw[S::VV + (k * T + t) * 2 + 0] = vx;
           rw[S::VV + (k * T + t) * 2 + 1] = vy;
@@ -581,42 +601,53 @@ __global__ void k_cycle_begin(Dev d) {
   d.scal->n_unfinished = 0;
 }
 
-__global__ void __launch_bounds__(TPB) k_sched(Dev d, int cycle) {
+// Each block owns a contiguous chunk of at most SCHED_CHUNK elements; 8 lanes
+// per element share the scan of its scheduling stencil; the block gathers its
+// active elements in LDS and reserves list space with one global atomic.
+constexpr int SCHED_CHUNK = 1024;
+
+__global__ void __launch_bounds__(TPB) k_sched(Dev d, int cycle, int chunk) {
+  constexpr int PER_PASS = TPB / 8;
+  __shared__ int local[SCHED_CHUNK];
+  __shared__ int count, gbase;
   const int NE = d.NE;
   const int N = d.scal->N;
-  const int lane = threadIdx.x & 63;
-  for (int base = blockIdx.x * blockDim.x; base < NE; base += gridDim.x * blockDim.x) {
-    const int i = base + threadIdx.x;
-    bool act = false, unf = false;
-    if (i < NE) {
+  const int sub = threadIdx.x & 7;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  const int begin = blockIdx.x * chunk;
+  const int end = min(NE, begin + chunk);
+  for (int base = begin; base < end; base += PER_PASS) {
+    const int i = base + (threadIdx.x >> 3);
+    int fut = 0, mx = 0, mn = 1 << 30;
+    bool unf = false;
+    if (i < end) {
       const TickStep me = d.ts[i];
       if (me.tick < N) {
         unf = true;
-        const int fut = me.tick + me.step;
-        int mx = 0, mn = 1 << 30;
-        for (int r = d.sched_ptr[i]; r < d.sched_ptr[i + 1]; ++r) {
+        fut = me.tick + me.step;
+        const int r1 = d.sched_ptr[i + 1];
+        for (int r = d.sched_ptr[i] + sub; r < r1; r += 8) {
           const TickStep o = d.ts[d.sched_idx[r]];
           mx = max(mx, o.tick);
           mn = min(mn, o.tick + o.step);
         }
-        act = (mx <= fut) && (fut <= mn);
       }
     }
-    const unsigned long long ma = __ballot(act);
-    const unsigned long long mu = __ballot(unf);
-    int base_slot = 0;
-    if (lane == 0) {
-      if (ma) base_slot = atomicAdd(&d.scal->n_active, __popcll(ma));
-      if (mu) atomicAdd(&d.scal->n_unfinished, __popcll(mu));
-      if (ma) atomicAdd(&d.scal->updates, (unsigned long long)__popcll(ma));
+#pragma unroll
+    for (int s = 1; s < 8; s <<= 1) {
+      mx = max(mx, __shfl_xor(mx, s));
+      mn = min(mn, __shfl_xor(mn, s));
     }
-    base_slot = __shfl(base_slot, 0);
-    if (act) {
-      const int pos = base_slot + __popcll(ma & ((1ull << lane) - 1ull));
-      d.act_list[pos] = i;
+    if (unf && sub == 0 && mx <= fut && fut <= mn) {
+      local[atomicAdd(&count, 1)] = i;
       d.act_stamp[i] = cycle;
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) gbase = count ? atomicAdd(&d.scal->n_active, count) : 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < count; k += TPB) d.act_list[gbase + k] = local[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -627,6 +658,7 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
   constexpr int T = M + 1, VV = Sz<M>::VV;
   const int NV = d.NV;
   const double delta = d.scal->delta;
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.scal->updates += (unsigned long long)d.scal->n_active;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
     const int r0 = d.ring_ptr[k], r1 = d.ring_ptr[k + 1];
     int newt = -1;
@@ -650,8 +682,8 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
         ok = false;
         continue;
       }
-      const double tau0 = double(nk - tsj.tick) / double(tsj.step);
-      const double tau1 = double(newt - tsj.tick) / double(tsj.step);
+      const double tau0 = tick_ratio(double(nk - tsj.tick), tsj.step);
+      const double tau1 = tick_ratio(double(newt - tsj.tick), tsj.step);
       double L0[T], L1[T];
       time_antideriv<M>(tb, tau0, L0);
       time_antideriv<M>(tb, tau1, L1);
@@ -740,7 +772,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
           qR[t][v] = trR[((nG - 1 - gq) * T + t) * 4 + v];
         }
       const double c = tb->gchi[gq];
-#pragma unroll
+#pragma unroll 1
       for (int h = 0; h < nG; ++h) {
         const double tt = tb->gchi[h];
         const double w = tb->gw[gq] * tb->gw[h];
@@ -755,7 +787,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
         N[2] = dchi[0] * dtau[1] - dchi[1] * dtau[0];
         const double tk = (1.0 - c) * (1.0 - tt) * n1 + c * (1.0 - tt) * n2 + c * tt * n3 + (1.0 - c) * tt * n4;
         double lL[T];
-        time_basis<M>(tb, (tk - tL.tick) / double(tL.step), lL);
+        time_basis<M>(tb, tick_ratio(tk - tL.tick, tL.step), lL);
         double ql[4], qr[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -766,7 +798,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
         }
         if (R >= 0) {
           double lR[T];
-          time_basis<M>(tb, (tk - tR.tick) / double(tR.step), lR);
+          time_basis<M>(tb, tick_ratio(tk - tR.tick, tR.step), lR);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             double s = 0.0;
@@ -776,8 +808,8 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
           }
         } else if (bc == 2) {
           // slip wall: mirror the normal momentum
-          const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
-          const double nx = N[0] / nxy, ny = N[1] / nxy;
+          const double inxy = rsqrt(N[0] * N[0] + N[1] * N[1]);
+          const double nx = N[0] * inxy, ny = N[1] * inxy;
           const double mn = ql[1] * nx + ql[2] * ny;
           qr[0] = ql[0];
           qr[1] = ql[1] - 2.0 * mn * nx;
@@ -788,9 +820,8 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
           for (int v = 0; v < 4; ++v) qr[v] = ql[v];
         }
         double fl[4], fr[4];
-        stflux(ql, N, g, fl);
-        stflux(qr, N, g, fr);
-        const double smax = fmax(stspeed(ql, N, g), stspeed(qr, N, g));
+        const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
+        const double smax = fmax(stflux_speed(ql, N, nxy, g, fl), stflux_speed(qr, N, nxy, g, fr));
 #pragma unroll
         for (int v = 0; v < 4; ++v) G[v] += w * (0.5 * (fl[v] + fr[v]) - 0.5 * smax * (qr[v] - ql[v]));
 #pragma unroll
@@ -1106,7 +1137,11 @@ int launch_cycle_begin(const Dev& d, void* s) {
 }
 
 int launch_sched(const Dev& d, int cycle, void* s) {
-  AW_LAUNCH(k_sched, d.NE, s, d, cycle);
+  // chunks of at most SCHED_CHUNK elements, at least ~1024 blocks when possible
+  int chunk = (d.NE + 1023) / 1024;
+  chunk = chunk < TPB / 8 ? TPB / 8 : (chunk > SCHED_CHUNK ? SCHED_CHUNK : chunk);
+  const int blocks = (d.NE + chunk - 1) / chunk;
+  AW_LAUNCH_G(k_sched, blocks, s, d, cycle, chunk);
   return 0;
 }
 
