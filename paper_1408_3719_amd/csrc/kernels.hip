@@ -116,19 +116,43 @@ __device__ inline const double* rec(const Dev& d, int i) {
   return d.rec + size_t(i) * Sz<M>::RS;
 }
 
+// Stored data of element j needed to place it at tick nt: its vertices and
+// either its average (j at tick nt) or its predictor's nodal averages in time;
+// the predictor's vertex velocities are read where they are used.
+template <int M>
+struct NbrRaw {
+  double xe[6];
+  double av[4 * (M + 1)];
+  const double* vv;
+};
+
+template <int M>
+__device__ inline void fetch_nbr(const Dev& d, int j, TickStep tsj, int nt, NbrRaw<M>& r) {
+  constexpr int T = M + 1, VV = Sz<M>::VV;
+  const double* p = rec<M>(d, j);
+  r.vv = p + VV;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) r.xe[c] = p[XE + c];
+  if (tsj.tick == nt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) r.av[v] = p[QO + v];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4 * T; ++c) r.av[c] = p[AVG + c];
+  }
+}
+
 // Geometry (x0 y0 x1 y1 x2 y2) and average of element j at tick nt: the real
 // data when j is at that tick, else its predictor projected there.
 template <int M>
-__device__ inline bool project(const Dev& d, const Tables* tb, int j, int nt, double delta,
-                               double X[6], double Qv[4]) {
-  constexpr int T = M + 1, VV = Sz<M>::VV;
-  const TickStep tsj = d.ts[j];
-  const double* r = rec<M>(d, j);
+__device__ inline bool place_nbr(const Tables* tb, const NbrRaw<M>& r, TickStep tsj, int nt,
+                                 double delta, double X[6], double Qv[4]) {
+  constexpr int T = M + 1;
   if (tsj.tick == nt) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) X[c] = r[XE + c];
+    for (int c = 0; c < 6; ++c) X[c] = r.xe[c];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Qv[v] = r[QO + v];
+    for (int v = 0; v < 4; ++v) Qv[v] = r.av[v];
     return true;
   }
   if (tsj.step <= 0) return false;
@@ -143,17 +167,26 @@ __device__ inline bool project(const Dev& d, const Tables* tb, int j, int nt, do
     for (int c = 0; c < 2; ++c) {
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < T; ++q) s += L[q] * r[VV + (k * T + q) * 2 + c];
-      X[2 * k + c] = r[XE + 2 * k + c] + dtj * s;
+      for (int q = 0; q < T; ++q) s += L[q] * r.vv[(k * T + q) * 2 + c];
+      X[2 * k + c] = r.xe[2 * k + c] + dtj * s;
     }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < T; ++q) s += l[q] * r[AVG + q * 4 + v];
+    for (int q = 0; q < T; ++q) s += l[q] * r.av[q * 4 + v];
     Qv[v] = s;
   }
   return true;
+}
+
+template <int M>
+__device__ inline bool project(const Dev& d, const Tables* tb, int j, int nt, double delta,
+                               double X[6], double Qv[4]) {
+  const TickStep tsj = d.ts[j];
+  NbrRaw<M> r;
+  fetch_nbr<M>(d, j, tsj, nt, r);
+  return place_nbr<M>(tb, r, tsj, nt, delta, X, Qv);
 }
 
 __device__ inline double tri_area(const double X[6]) {
@@ -183,6 +216,16 @@ __device__ inline int level_step(double dtcfl, double delta, int N, int tick, in
     if (low < p) p = low;
   }
   return p;
+}
+
+// Orders LDS accesses among the lanes of one wavefront. The lanes that share a
+// predictor's nodal data always lie in one wavefront, and the LDS executes the
+// accesses of a wavefront in issue order, so only the compiler's reordering has
+// to be fenced; no workgroup barrier is needed.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ inline double group8_sum(double v) {
@@ -233,11 +276,23 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
 #pragma unroll
         for (int v = 0; v < 4; ++v) z[a][v] = 0.0;
       }
+      // Rows are software-pipelined: while row c is folded in, the neighbour
+      // data of row c+1, the tick of row c+2 and the index of row c+3 are in
+      // flight, each load depending only on values that arrived one row earlier.
+      const int* sidx = d.sten + size_t(sl * ne) * NE + i;   // row c at sidx[c * NE]
+      int jn = sidx[2 * NE], jnn = sidx[3 * NE];              // ne >= 6
+      TickStep tc = d.ts[sidx[NE]], tn = d.ts[jn];
+      NbrRaw<M> rc;
+      fetch_nbr<M>(d, sidx[NE], tc, nt, rc);
 #pragma unroll 1
       for (int c = 1; c < ne; ++c) {
-        const int j = d.sten[(sl * ne + c) * NE + i];
         double Xv[6], Qv[4];
-        ok &= project<M>(d, tb, j, nt, delta, Xv, Qv);
+        ok &= place_nbr<M>(tb, rc, tc, nt, delta, Xv, Qv);
+        if (c + 1 < ne) fetch_nbr<M>(d, jn, tn, nt, rc);
+        tc = tn;
+        if (c + 2 < ne) tn = d.ts[jnn];
+        jn = jnn;
+        if (c + 3 < ne) jnn = sidx[(c + 3) * NE];
         // vertices of the virtual element in the reference frame of element i
         double rx[3], ry[3];
 #pragma unroll
@@ -391,15 +446,22 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
   using S = Sz<M>;
   constexpr int nb = S::nb, T = S::nt, nG = S::nG, G = S::G, RS = S::RS, TS = S::TS, WS = S::WS;
   constexpr int SLOTS = TPB / G;
-  constexpr int NF = 14;                 // exchanged fields per node: q(4) f(4) g(4) x(2)
-  constexpr int NOUT = 4 + 3 * nG * 4;   // per time slice: averages + traces
-  __shared__ double lds[SLOTS][NF][G];
+  // exchanged fields per node: q(4), f1..f3, g1..g3 (f0 = q1 and g0 = q2 are
+  // not repeated), x, y; the per-element stride is padded by 16 bytes so that
+  // the broadcast reads of the elements of one wavefront fall in distinct banks
+  constexpr int NF = 12;
+  constexpr int LSTR = NF * G + 2;
+  constexpr int NPT = 1 + 3 * nG;        // element mean + edge Gauss points
+  constexpr int PPL = (NPT + G - 1) / G; // points per lane
+  static_assert(64 % G == 0 && TPB % 64 == 0, "an element's lanes must share a wavefront");
+  __shared__ double lds[SLOTS * LSTR];
   const int NE = d.NE;
   const int nitems = use_list ? d.scal->n_active : NE;
   const double delta = d.scal->delta;
   const double g = P.gamma;
   const int slot = threadIdx.x / G;
   const int m = threadIdx.x % G;
+  double* const my = lds + slot * LSTR;
   const bool node = m < nb;
   const int mm = node ? m : 0;
   // this lane's rows of the spatial derivative matrices
@@ -480,27 +542,26 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
           const double ir = 1.0 / q[t][0];
           const double u = q[t][1] * ir, v = q[t][2] * ir;
           const double p = (g - 1.0) * (q[t][3] - 0.5 * (q[t][1] * u + q[t][2] * v));
-          lds[slot][0][m] = q[t][0];
-          lds[slot][1][m] = q[t][1];
-          lds[slot][2][m] = q[t][2];
-          lds[slot][3][m] = q[t][3];
-          lds[slot][4][m] = q[t][1];
-          lds[slot][5][m] = q[t][1] * u + p;
-          lds[slot][6][m] = q[t][1] * v;
-          lds[slot][7][m] = u * (q[t][3] + p);
-          lds[slot][8][m] = q[t][2];
-          lds[slot][9][m] = q[t][2] * u;
-          lds[slot][10][m] = q[t][2] * v + p;
-          lds[slot][11][m] = v * (q[t][3] + p);
-          lds[slot][12][m] = x[t][0];
-          lds[slot][13][m] = x[t][1];
+          const double h = q[t][3] + p;
+          my[0 * G + m] = q[t][0];
+          my[1 * G + m] = q[t][1];
+          my[2 * G + m] = q[t][2];
+          my[3 * G + m] = q[t][3];
+          my[4 * G + m] = q[t][1] * u + p;
+          my[5 * G + m] = q[t][1] * v;
+          my[6 * G + m] = u * h;
+          my[7 * G + m] = q[t][2] * u;
+          my[8 * G + m] = q[t][2] * v + p;
+          my[9 * G + m] = v * h;
+          my[10 * G + m] = x[t][0];
+          my[11 * G + m] = x[t][1];
         }
-        __syncthreads();
+        wave_sync();
         // metric of the isoparametric map at this node (eq. Jac)
         double xx = 0.0, xe = 0.0, yx = 0.0, ye = 0.0;
 #pragma unroll
         for (int k = 0; k < nb; ++k) {
-          const double vx = lds[slot][12][k], vy = lds[slot][13][k];
+          const double vx = my[10 * G + k], vy = my[11 * G + k];
           xx += Dx[k] * vx;
           xe += De[k] * vx;
           yx += Dx[k] * vy;
@@ -519,19 +580,23 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
         // P = -(q_xi xi_t + q_eta eta_t + f_xi xi_x + f_eta eta_x + g_xi xi_y + g_eta eta_y)
         double Pv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int f = 0; f < 12; ++f) {
+        for (int f = 0; f < 10; ++f) {
           double a = 0.0, b = 0.0;
 #pragma unroll
           for (int k = 0; k < nb; ++k) {
-            const double val = lds[slot][f][k];
+            const double val = my[f * G + k];
             a += Dx[k] * val;
             b += De[k] * val;
           }
-          const double cx = f < 4 ? xi_t : (f < 8 ? xi_x : xi_y);
-          const double ce = f < 4 ? eta_t : (f < 8 ? eta_x : eta_y);
-          Pv[f & 3] -= a * cx + b * ce;
+          // q_v enters through xi_t/eta_t; q1 = f0 and q2 = g0 also through the
+          // spatial metric of the mass row; f1..f3 and g1..g3 through xi_x, xi_y
+          if (f < 4) Pv[f] -= a * xi_t + b * eta_t;
+          if (f == 1) Pv[0] -= a * xi_x + b * eta_x;
+          if (f == 2) Pv[0] -= a * xi_y + b * eta_y;
+          if (f >= 4 && f < 7) Pv[f - 3] -= a * xi_x + b * eta_x;
+          if (f >= 7) Pv[f - 6] -= a * xi_y + b * eta_y;
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -542,35 +607,44 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
 #pragma unroll
         for (int v = 0; v < 4; ++v) q[r + 1][v] = qn[r][v];
     }
-    // publish: reference means and edge traces (one slice at a time through
-    // LDS), vertex velocities of the final iterate
+    // publish: reference means and edge traces, one time slice at a time
+    // through LDS; lane m evaluates points m, m + G, ... (point 0 is the
+    // element mean, point 1 + e*nG + gq the Gauss point gq of edge e), all four
+    // variables each
+    double cw[PPL][nb];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const int pt = m + G * j;
+      const int eg = pt > 0 ? pt - 1 : 0;
+      const double* c = pt == 0 ? tb->amean : tb->edge[eg / nG][eg % nG];
+#pragma unroll
+      for (int k = 0; k < nb; ++k) cw[j][k] = pt < NPT ? c[k] : 0.0;
+    }
 #pragma unroll
     for (int t = 0; t < T; ++t) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) lds[slot][c][m] = q[t][c];
-      __syncthreads();
+      for (int c = 0; c < 4; ++c) my[c * G + m] = q[t][c];
+      wave_sync();
       if (live) {
-        double* rw = d.rec + size_t(i) * RS;
-        double* tw = d.trace + size_t(i) * TS;
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o) {
-          if (o % G != m) continue;
-          const int v = o & 3;
-          double s = 0.0;
-          if (o < 4) {
+        for (int j = 0; j < PPL; ++j) {
+          const int pt = m + G * j;
+          if (pt >= NPT) continue;
+          double* out = pt == 0 ? d.rec + size_t(i) * RS + AVG + t * 4
+                                : d.trace + size_t(i) * TS + ((pt - 1) * T + t) * 4;
+          double s4[4];
 #pragma unroll
-            for (int k = 0; k < nb; ++k) s += tb->amean[k] * lds[slot][v][k];
-            rw[AVG + t * 4 + v] = s;
-          } else {
-            const int eg = (o - 4) >> 2;      // e * nG + gq
-            const int e = eg / nG, gq = eg % nG;
+          for (int v = 0; v < 4; ++v) {
+            double s = 0.0;
 #pragma unroll
-            for (int k = 0; k < nb; ++k) s += tb->edge[e][gq][k] * lds[slot][v][k];
-            tw[(eg * T + t) * 4 + v] = s;
+            for (int k = 0; k < nb; ++k) s += cw[j][k] * my[v * G + k];
+            s4[v] = s;
           }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) out[v] = s4[v];
         }
       }
-      __syncthreads();
+      wave_sync();
     }
     if (act) {
       double* rw = d.rec + size_t(i) * RS;
