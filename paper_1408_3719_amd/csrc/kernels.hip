@@ -455,6 +455,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
   constexpr int PPL = (NPT + G - 1) / G; // points per lane
   static_assert(64 % G == 0 && TPB % 64 == 0, "an element's lanes must share a wavefront");
   __shared__ double lds[SLOTS * LSTR];
+  __shared__ double c0[16][TPB];         // per lane: fixed parts of slice t = 0
   const int NE = d.NE;
   const int nitems = use_list ? d.scal->n_active : NE;
   const double delta = d.scal->delta;
@@ -510,6 +511,95 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
         q[t][3] = 1.0;
       }
     }
+    // this node's fields of slice t into the element's exchange buffer
+    auto put_fields = [&](int t) {
+      const double ir = 1.0 / q[t][0];
+      const double u = q[t][1] * ir, v = q[t][2] * ir;
+      const double p = (g - 1.0) * (q[t][3] - 0.5 * (q[t][1] * u + q[t][2] * v));
+      const double h = q[t][3] + p;
+      my[0 * G + m] = q[t][0];
+      my[1 * G + m] = q[t][1];
+      my[2 * G + m] = q[t][2];
+      my[3 * G + m] = q[t][3];
+      my[4 * G + m] = q[t][1] * u + p;
+      my[5 * G + m] = q[t][1] * v;
+      my[6 * G + m] = u * h;
+      my[7 * G + m] = q[t][2] * u;
+      my[8 * G + m] = q[t][2] * v + p;
+      my[9 * G + m] = v * h;
+      my[10 * G + m] = x[t][0];
+      my[11 * G + m] = x[t][1];
+    };
+    // spatial metric of the isoparametric map at this node (eq. Jac) from the
+    // exchanged coordinates: xi_x, xi_y, eta_x, eta_y
+    auto spatial_metric = [&](double mt[4]) {
+      double xx = 0.0, xe = 0.0, yx = 0.0, ye = 0.0;
+#pragma unroll
+      for (int k = 0; k < nb; ++k) {
+        const double vx = my[10 * G + k], vy = my[11 * G + k];
+        xx += Dx[k] * vx;
+        xe += De[k] * vx;
+        yx += Dx[k] * vy;
+        ye += De[k] * vy;
+      }
+      const double idet = 1.0 / (xx * ye - xe * yx);
+      mt[0] = ye * idet;
+      mt[1] = -xe * idet;
+      mt[2] = -yx * idet;
+      mt[3] = xx * idet;
+    };
+    // xi_t, eta_t at this node and slice t from its own trajectory
+    auto time_metric = [&](int t, const double mt[4], double& xi_t, double& eta_t) {
+      double xtau = 0.0, ytau = 0.0;
+#pragma unroll
+      for (int r = 0; r < T; ++r) {
+        xtau += tb->Dt[t][r] * x[r][0];
+        ytau += tb->Dt[t][r] * x[r][1];
+      }
+      const double xt = xtau * idt, yt = ytau * idt;
+      xi_t = -(mt[0] * xt + mt[1] * yt);
+      eta_t = -(mt[2] * xt + mt[3] * yt);
+    };
+    // d/dxi (a) and d/deta (b) at this node of the exchanged fields 0..9
+    auto field_derivs = [&](double da[10], double db[10]) {
+#pragma unroll
+      for (int f = 0; f < 10; ++f) {
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int k = 0; k < nb; ++k) {
+          const double val = my[f * G + k];
+          sa += Dx[k] * val;
+          sb += De[k] * val;
+        }
+        da[f] = sa;
+        db[f] = sb;
+      }
+    };
+    // spatial flux part of P: f_xi xi_x + f_eta eta_x + g_xi xi_y + g_eta eta_y
+    // (f0 = q1 and g0 = q2 are fields 1 and 2; f1..f3 are 4..6, g1..g3 7..9)
+    auto spatial_part = [&](const double da[10], const double db[10], const double mt[4],
+                            double sp[4]) {
+      sp[0] = da[1] * mt[0] + db[1] * mt[2] + da[2] * mt[1] + db[2] * mt[3];
+#pragma unroll
+      for (int v = 1; v < 4; ++v)
+        sp[v] = da[3 + v] * mt[0] + db[3 + v] * mt[2] + da[6 + v] * mt[1] + db[6 + v] * mt[3];
+    };
+    // P = -(q_xi xi_t + q_eta eta_t + spatial part), accumulated into the sweep
+    auto accumulate = [&](int t, const double da[4], const double db[4], const double sp[4],
+                          double xi_t, double eta_t, double qn[M][4]) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double Pv = -(da[v] * xi_t + db[v] * eta_t + sp[v]);
+#pragma unroll
+        for (int r = 0; r < M; ++r) qn[r][v] += dt * tb->At[r][t] * Pv;
+      }
+    };
+    // The slice t = 0 (q_0, x_0) is the same in every sweep, and in the first
+    // sweep every slice carries q_0. So the spatial derivatives of the fields
+    // at t = 0 are taken once, in the first sweep, and serve all of its slices;
+    // later sweeps keep from them the derivatives of q, the spatial flux part
+    // and the spatial metric at t = 0 (per lane, in LDS), and exchange only
+    // their slices t >= 1.
     for (int it = 0; it < P.npic; ++it) {
       // mesh ODE at this node: x_{1:} = Bt x_0 + dt At V
       if (P.lagrangian) {
@@ -535,72 +625,66 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
       for (int r = 0; r < M; ++r)
 #pragma unroll
         for (int v = 0; v < 4; ++v) qn[r][v] = tb->Bt[r] * q[0][v];
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        // publish this node's fields of time slice t
-        {
-          const double ir = 1.0 / q[t][0];
-          const double u = q[t][1] * ir, v = q[t][2] * ir;
-          const double p = (g - 1.0) * (q[t][3] - 0.5 * (q[t][1] * u + q[t][2] * v));
-          const double h = q[t][3] + p;
-          my[0 * G + m] = q[t][0];
-          my[1 * G + m] = q[t][1];
-          my[2 * G + m] = q[t][2];
-          my[3 * G + m] = q[t][3];
-          my[4 * G + m] = q[t][1] * u + p;
-          my[5 * G + m] = q[t][1] * v;
-          my[6 * G + m] = u * h;
-          my[7 * G + m] = q[t][2] * u;
-          my[8 * G + m] = q[t][2] * v + p;
-          my[9 * G + m] = v * h;
-          my[10 * G + m] = x[t][0];
-          my[11 * G + m] = x[t][1];
-        }
+      if (it == 0) {
+        put_fields(0);
         wave_sync();
-        // metric of the isoparametric map at this node (eq. Jac)
-        double xx = 0.0, xe = 0.0, yx = 0.0, ye = 0.0;
+        double da[10], db[10], mt0[4], sp0[4];
+        field_derivs(da, db);
+        spatial_metric(mt0);
+        wave_sync();
+        spatial_part(da, db, mt0, sp0);
 #pragma unroll
-        for (int k = 0; k < nb; ++k) {
-          const double vx = my[10 * G + k], vy = my[11 * G + k];
-          xx += Dx[k] * vx;
-          xe += De[k] * vx;
-          yx += Dx[k] * vy;
-          ye += De[k] * vy;
+        for (int v = 0; v < 4; ++v) {
+          c0[v][threadIdx.x] = da[v];
+          c0[4 + v][threadIdx.x] = db[v];
+          c0[8 + v][threadIdx.x] = sp0[v];
+          c0[12 + v][threadIdx.x] = mt0[v];
         }
-        double xtau = 0.0, ytau = 0.0;
 #pragma unroll
-        for (int r = 0; r < T; ++r) {
-          xtau += tb->Dt[t][r] * x[r][0];
-          ytau += tb->Dt[t][r] * x[r][1];
-        }
-        const double idet = 1.0 / (xx * ye - xe * yx);
-        const double xi_x = ye * idet, xi_y = -xe * idet, eta_x = -yx * idet, eta_y = xx * idet;
-        const double xt = xtau * idt, yt = ytau * idt;
-        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
-        // P = -(q_xi xi_t + q_eta eta_t + f_xi xi_x + f_eta eta_x + g_xi xi_y + g_eta eta_y)
-        double Pv[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < T; ++t) {
+          double mt[4], sp[4], xi_t, eta_t;
+          if (t == 0) {
 #pragma unroll
-        for (int f = 0; f < 10; ++f) {
-          double a = 0.0, b = 0.0;
-#pragma unroll
-          for (int k = 0; k < nb; ++k) {
-            const double val = my[f * G + k];
-            a += Dx[k] * val;
-            b += De[k] * val;
+            for (int c = 0; c < 4; ++c) {
+              mt[c] = mt0[c];
+              sp[c] = sp0[c];
+            }
+          } else {
+            my[10 * G + m] = x[t][0];
+            my[11 * G + m] = x[t][1];
+            wave_sync();
+            spatial_metric(mt);
+            wave_sync();
+            spatial_part(da, db, mt, sp);
           }
-          // q_v enters through xi_t/eta_t; q1 = f0 and q2 = g0 also through the
-          // spatial metric of the mass row; f1..f3 and g1..g3 through xi_x, xi_y
-          if (f < 4) Pv[f] -= a * xi_t + b * eta_t;
-          if (f == 1) Pv[0] -= a * xi_x + b * eta_x;
-          if (f == 2) Pv[0] -= a * xi_y + b * eta_y;
-          if (f >= 4 && f < 7) Pv[f - 3] -= a * xi_x + b * eta_x;
-          if (f >= 7) Pv[f - 6] -= a * xi_y + b * eta_y;
+          time_metric(t, mt, xi_t, eta_t);
+          accumulate(t, da, db, sp, xi_t, eta_t, qn);
         }
-        wave_sync();
+      } else {
+        {
+          double da[4], db[4], sp[4], mt[4], xi_t, eta_t;
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+          for (int v = 0; v < 4; ++v) {
+            da[v] = c0[v][threadIdx.x];
+            db[v] = c0[4 + v][threadIdx.x];
+            sp[v] = c0[8 + v][threadIdx.x];
+            mt[v] = c0[12 + v][threadIdx.x];
+          }
+          time_metric(0, mt, xi_t, eta_t);
+          accumulate(0, da, db, sp, xi_t, eta_t, qn);
+        }
 #pragma unroll
-          for (int r = 0; r < M; ++r) qn[r][v] += dt * tb->At[r][t] * Pv[v];
+        for (int t = 1; t < T; ++t) {
+          put_fields(t);
+          wave_sync();
+          double da[10], db[10], mt[4], sp[4], xi_t, eta_t;
+          field_derivs(da, db);
+          spatial_metric(mt);
+          wave_sync();
+          spatial_part(da, db, mt, sp);
+          time_metric(t, mt, xi_t, eta_t);
+          accumulate(t, da, db, sp, xi_t, eta_t, qn);
+        }
       }
 #pragma unroll
       for (int r = 0; r < M; ++r)
