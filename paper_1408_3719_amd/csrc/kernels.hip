@@ -218,6 +218,24 @@ __device__ inline int level_step(double dtcfl, double delta, int N, int tick, in
   return p;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// This renumbering gives every XCD a contiguous range of logical blocks, so
+// that with Hilbert-ordered elements, nodes and edges the neighbours that a
+// block gathers were mostly fetched into the same L2 by nearby blocks.
+// Only the first nwork blocks (those with work) are renumbered, among
+// themselves, so that a grid sized for all elements and running a shorter
+// active list still spreads its work over every XCD.
+constexpr int NXCD = 8;
+__device__ inline int xcd_block(int nwork) {
+  const int b = blockIdx.x;
+  if (nwork > (int)gridDim.x) nwork = gridDim.x;
+  if (b >= nwork) return b;
+  const int x = b % NXCD, r = b / NXCD;
+  const int q = nwork / NXCD, rem = nwork % NXCD;
+  return x * q + (x < rem ? x : rem) + r;
+}
+__device__ inline int xcd_block() { return xcd_block(gridDim.x); }
+
 // Orders LDS accesses among the lanes of one wavefront. The lanes that share a
 // predictor's nodal data always lie in one wavefront, and the LDS executes the
 // accesses of a wavefront in issue order, so only the compiler's reordering has
@@ -248,7 +266,8 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
   const double delta = d.scal->delta;
   const int sl = threadIdx.x & 7;
   const int ngroups = (gridDim.x * blockDim.x) >> 3;
-  for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; idx < nitems; idx += ngroups) {
+  const int nwork = int((8L * nitems + blockDim.x - 1) / blockDim.x);
+  for (int idx = (xcd_block(nwork) * blockDim.x + threadIdx.x) >> 3; idx < nitems; idx += ngroups) {
     const int i = use_list ? d.act_list[idx] : idx;
     const int nt = d.ts[i].tick;
     const double* ri = rec<M>(d, i);
@@ -479,7 +498,8 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
     ++jj;
   }
   const double nxi = double(ii) / M, neta = double(jj) / M;
-  for (int base = blockIdx.x * SLOTS; base < nitems; base += gridDim.x * SLOTS) {
+  for (int base = xcd_block((nitems + SLOTS - 1) / SLOTS) * SLOTS; base < nitems;
+       base += gridDim.x * SLOTS) {
     const int idx = base + slot;
     const int i = idx < nitems ? (use_list ? d.act_list[idx] : idx) : -1;
     const int st = i >= 0 ? d.ts[i].step : 0;
@@ -773,7 +793,7 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int cycle, int chunk) {
   const int sub = threadIdx.x & 7;
   if (threadIdx.x == 0) count = 0;
   __syncthreads();
-  const int begin = blockIdx.x * chunk;
+  const int begin = xcd_block() * chunk;
   const int end = min(NE, begin + chunk);
   for (int base = begin; base < end; base += PER_PASS) {
     const int i = base + (threadIdx.x >> 3);
@@ -817,7 +837,7 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
   const int NV = d.NV;
   const double delta = d.scal->delta;
   if (blockIdx.x == 0 && threadIdx.x == 0) d.scal->updates += (unsigned long long)d.scal->n_active;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
+  for (int k = xcd_block() * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
     const int r0 = d.ring_ptr[k], r1 = d.ring_ptr[k + 1];
     int newt = -1;
     for (int r = r0; r < r1; ++r) {
@@ -889,7 +909,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
   const int NV = d.NV, NF = d.NF;
   const double delta = d.scal->delta;
   const double g = P.gamma;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
+  for (int e = xcd_block() * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
     const int a = d.e_a[e], b = d.e_b[e];
     const bool ma = d.node_stamp[a] == cycle, mb = d.node_stamp[b] == cycle;
     if (!ma && !mb) continue;
@@ -1001,7 +1021,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
 template <int M>
 __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P, int cycle) {
   const int NE = d.NE, NV = d.NV, NF = d.NF;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+  for (int i = xcd_block() * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
     const bool act = d.act_stamp[i] == cycle;
     int es[3];
     bool any = false;
