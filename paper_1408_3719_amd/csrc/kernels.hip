@@ -1021,6 +1021,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
 template <int M>
 __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P, int cycle) {
   const int NE = d.NE, NV = d.NV, NF = d.NF;
+  double gmax = 0.0;   // largest relative GCL residual seen by this lane
   for (int i = xcd_block() * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
     const bool act = d.act_stamp[i] == cycle;
     int es[3];
@@ -1070,7 +1071,7 @@ __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P, int cycle) {
     if (!(An > 0.0)) set_err(d, ERR_GEOM);
     const double res = fmax(fmax(fabs(hm[0]), fabs(hm[1])), fabs(hm[2] - (An - A0)));
     const double rel = res / (A0 + An);
-    atomic_max_pos(&d.scal->max_gcl_bits, rel);
+    gmax = fmax(gmax, rel);
     if (!(rel <= P.gcl_tol)) set_err(d, ERR_GCL);
     double qn[4];
 #pragma unroll
@@ -1099,6 +1100,10 @@ __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P, int cycle) {
         d.ntick[nd[k]] = d.ntick_new[nd[k]];
       }
   }
+  // one atomic per wavefront
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) gmax = fmax(gmax, __shfl_xor(gmax, s));
+  if (__lane_id() == 0 && gmax > 0.0) atomic_max_pos(&d.scal->max_gcl_bits, gmax);
 }
 
 // ---------------------------------------------------------------------------
