@@ -17,6 +17,7 @@ usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n-elems N] [--M 2]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import subprocess
@@ -28,10 +29,24 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X, published
 PEAK_HBM_GBS = 8000.0              # MI355X HBM3E, published
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
+
+# HBM bytes per unit of work (element reconstruction, element predictor): the
+# rocprofv3 FETCH_SIZE and WRITE_SIZE of the profiled LTS pass's launches on
+# the 80k vortex mesh at M=2, scaled by what the same counters read for a plain
+# 256 MiB copy (FETCH x2.0, WRITE x1.0), divided by the units those launches
+# processed. Valid only for the kernel source they were taken on (sha256 of
+# kernels.hip); otherwise traffic is reported null.
+MEASURED_TRAFFIC = {
+    "k_reconstruct": {"bytes_per_unit": 1371, "source_sha256":
+                      "70ee28ec58bfb32fb71cebe12fd47cdccecc3c3284938a8ccfda3d323e8d6bb7"},
+    "k_predict": {"bytes_per_unit": 1502, "source_sha256":
+                  "70ee28ec58bfb32fb71cebe12fd47cdccecc3c3284938a8ccfda3d323e8d6bb7"},
+}
 
 
 # ---------------------------------------------------------------------------
-# Algorithmic work per unit (operation counts of the algorithm; see DESIGN.md)
+# Algorithmic work per unit (operation counts of the algorithm)
 # ---------------------------------------------------------------------------
 def recon_flops(M: int) -> int:
     """FP64 operations of one element reconstruction + CFL step, counting
@@ -169,6 +184,17 @@ def main():
         "predict": p1["predictor_evals"] - p0["predictor_evals"],
         "patch": p1["patches"] - p0["patches"],
     }
+    with open(KERNEL_SOURCE, "rb") as f:
+        source_sha = hashlib.sha256(f.read()).hexdigest()
+
+    def traffic(kernel, units_per_launch):
+        m = MEASURED_TRAFFIC.get(kernel)
+        if m is None or m["source_sha256"] != source_sha or a.M != 2:
+            return None
+        return m["bytes_per_unit"] * units_per_launch
+
+    kname = {"recon": "k_reconstruct", "predict": "k_predict", "patch": "k_patch",
+             "sched": "k_sched", "node": "k_node", "update": "k_update"}
     dom = max(kt, key=lambda k: kt[k][0])
     ms, launches = kt[dom]
     avg_s = ms / max(launches, 1) * 1e-3
@@ -177,15 +203,16 @@ def main():
         work = per * units[dom] / max(launches, 1)
         achieved = work / avg_s / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_VECTOR_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / PEAK_FP64_VECTOR_TFLOPS, traffic=None, kernel=f"k_{dom}",
+                    frac=achieved / PEAK_FP64_VECTOR_TFLOPS,
+                    traffic=traffic(kname[dom], units[dom] / max(launches, 1)), kernel=kname[dom],
                     flops_per_unit=per, units_per_launch=units[dom] / max(launches, 1),
-                    avg_launch_us=avg_s * 1e6)
+                    launches=launches, avg_launch_us=avg_s * 1e6)
     else:
         per = patch_bytes(a.M)
         work = per * units.get(dom, 0) / max(launches, 1)
         achieved = work / avg_s / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=achieved / PEAK_HBM_GBS, traffic=None, kernel=f"k_{dom}",
+                    frac=achieved / PEAK_HBM_GBS, traffic=None, kernel=kname.get(dom, dom),
                     bytes_per_unit=per, avg_launch_us=avg_s * 1e6)
     total_ms = sum(v[0] for v in kt.values())
 
@@ -225,6 +252,8 @@ def main():
         "lts_time_to_solution_speedup": t_gts / t_lts,
         "gts_over_lts_updates": gts_updates / max(lts_updates, 1),
         "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
+        "kernel_launches": {k: v[1] for k, v in kt.items()},
+        "work_units": units,
         "kernel_share": {k: round(v[0] / total_ms, 3) for k, v in kt.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
