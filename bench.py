@@ -12,7 +12,12 @@ time-to-solution ratio, a per-kernel breakdown from HIP events recorded on
 the solver's stream, the roofline of the dominant kernel, and the CPU oracle
 timed on a bounded sample.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n-elems N] [--M 2]
+Other workloads (not the headline line): --workload explosion (EP1 on the unit
+disk, 8:1 radial grading, 400k triangles, M=2, 4 levels) or --workload sod
+(RP1 shock tube, 2k triangles, M=1, one level = GTS).
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload vortex]
+                       [--n-elems N] [--M M] [--levels L]
 """
 from __future__ import annotations
 
@@ -119,9 +124,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n-elems", type=int, default=80_000)
-    ap.add_argument("--M", type=int, default=2)
-    ap.add_argument("--levels", type=int, default=3)
+    ap.add_argument("--workload", choices=["vortex", "explosion", "sod"], default="vortex")
+    ap.add_argument("--n-elems", type=int, default=None)
+    ap.add_argument("--M", type=int, default=None)
+    ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=5000)
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -137,11 +143,25 @@ def main():
     import torch
 
     from paper_1408_3719_amd import Config, Solver
-    from workloads import vortex_case
+    from workloads import explosion_case, sod_case, vortex_case
 
-    mesh, Q0 = vortex_case(a.n_elems, seed=1)
+    # workload defaults: mesh size, order, levels, target time
+    dflt = {"vortex": (80_000, 2, 3, 1.0), "explosion": (400_000, 2, 4, 0.25),
+            "sod": (2_000, 1, 1, 0.2)}[a.workload]
+    a.n_elems = a.n_elems or dflt[0]
+    a.M = a.M or dflt[1]
+    a.levels = a.levels or dflt[2]
+    if a.workload == "vortex":
+        mesh, Q0 = vortex_case(a.n_elems, seed=1)
+        desc = "isentropic vortex, {}-triangle 4:1 graded mesh"
+    elif a.workload == "explosion":
+        mesh, Q0 = explosion_case(a.n_elems, seed=7)
+        desc = "EP1 explosion, {}-triangle 8:1 radially graded disk"
+    else:
+        mesh, Q0 = sod_case(a.n_elems, seed=1408)
+        desc = "RP1 shock tube, {}-triangle strip"
     cfg = Config(M=a.M, levels=a.levels)
-    t_end = 1.0
+    t_end = dflt[3]
     s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, cfg)
     sync = torch.cuda.synchronize
 
@@ -189,7 +209,7 @@ def main():
 
     def traffic(kernel, units_per_launch):
         m = MEASURED_TRAFFIC.get(kernel)
-        if m is None or m["source_sha256"] != source_sha or a.M != 2:
+        if m is None or m["source_sha256"] != source_sha or a.M != 2 or a.workload != "vortex":
             return None
         return m["bytes_per_unit"] * units_per_launch
 
@@ -207,6 +227,10 @@ def main():
                     traffic=traffic(kname[dom], units[dom] / max(launches, 1)), kernel=kname[dom],
                     flops_per_unit=per, units_per_launch=units[dom] / max(launches, 1),
                     launches=launches, avg_launch_us=avg_s * 1e6)
+    elif dom != "patch":
+        # launch- or latency-bound case (small meshes): no algorithmic roofline
+        roof = dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
+                    kernel=kname.get(dom, dom), avg_launch_us=avg_s * 1e6)
     else:
         per = patch_bytes(a.M)
         work = per * units.get(dom, 0) / max(launches, 1)
@@ -226,7 +250,7 @@ def main():
 
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(a.cpu_elems, a.M, a.levels, a.cpu_steps)
+        cpu = cpu_baseline(a.cpu_elems, a.M, a.levels, a.cpu_steps) if a.workload == "vortex" else None
 
     line = {
         "metric": "element-updates/s at 1e-10 rel err vs FP64 oracle, LTS vs GTS",
@@ -242,8 +266,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"isentropic vortex, {mesh.n_elems}-triangle 4:1 graded mesh, M={a.M}, "
-                        f"LTS {a.levels} levels, Lagrangian mesh motion",
+            "workload": desc.format(mesh.n_elems) + f", M={a.M}, LTS {a.levels} levels, "
+                        "Lagrangian mesh motion",
             "n_elems": mesh.n_elems, "M": a.M, "levels": a.levels,
             "parallelism": "single GPU",
         },
