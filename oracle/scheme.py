@@ -64,6 +64,7 @@ class Config:
     weno_lambda: float = 1e5
     gcl_tol: float = 1e-12
     weno_shared: bool = True
+    flux: str = "rusanov"             # "rusanov" (eq. eqn.rusanov), "osher" (eq. eqn.osher) or "hll"
 
     @property
     def npic(self):
@@ -288,6 +289,104 @@ def rusanov_flux(ql, qr, N, gamma):
     return 0.5 * (ft(ql) + ft(qr)) - 0.5 * smax[..., None] * (qr - ql)
 
 
+def _ale_flux_dot(q, N, gamma):
+    """F~(q) . N = f N_x + g N_y + q N_t (eq. PDEdiv3D) for an unnormalised N."""
+    return (euler.flux_f(q, gamma) * N[..., 0:1] + euler.flux_g(q, gamma) * N[..., 1:2]
+            + q * N[..., 2:3])
+
+
+def ale_jacobian(q, N, gamma):
+    """d(F~(q) . N)/dq = A_x N_x + A_y N_y + N_t I, i.e. |N_xy| times the ALE
+    Jacobian of eq. A_n^V along n = N_xy/|N_xy| with normal mesh speed
+    -N_t/|N_xy|. A_x, A_y are the Jacobians of the Euler fluxes f and g written
+    out from their definitions (eq. eulerTerms). Shape (..., 4, 4)."""
+    rho, u, v, p = euler.primitives(q, gamma)
+    gm = gamma - 1.0
+    q2 = u * u + v * v
+    H = (q[..., 3] + p) / rho
+    z, o = np.zeros_like(u), np.ones_like(u)
+    Ax = np.stack([
+        np.stack([z, o, z, z], -1),
+        np.stack([0.5 * gm * q2 - u * u, (3.0 - gamma) * u, -gm * v, gm * o], -1),
+        np.stack([-u * v, v, u, z], -1),
+        np.stack([u * (0.5 * gm * q2 - H), H - gm * u * u, -gm * u * v, gamma * u], -1)], -2)
+    Ay = np.stack([
+        np.stack([z, z, o, z], -1),
+        np.stack([-u * v, v, u, z], -1),
+        np.stack([0.5 * gm * q2 - v * v, -gm * u, (3.0 - gamma) * v, gm * o], -1),
+        np.stack([v * (0.5 * gm * q2 - H), -gm * u * v, H - gm * v * v, gamma * v], -1)], -2)
+    return (Ax * N[..., 0, None, None] + Ay * N[..., 1, None, None]
+            + N[..., 2, None, None] * np.eye(4))
+
+
+def ale_wave_speeds(q, N, gamma):
+    """The three distinct eigenvalues of ale_jacobian: u.N_xy + N_t -/+ c |N_xy|
+    and u.N_xy + N_t (a double one), shape (..., 3)."""
+    rho, u, v, p = euler.primitives(q, gamma)
+    un = u * N[..., 0] + v * N[..., 1] + N[..., 2]
+    c = np.sqrt(gamma * p / rho) * np.sqrt(N[..., 0] ** 2 + N[..., 1] ** 2)
+    return np.stack([un - c, un, un + c], -1)
+
+
+def abs_matrix(A, lam):
+    """|A| = R |Lambda| R^-1 (Sec. 2.4, after eq. eqn.path) for a diagonalizable A
+    whose distinct eigenvalues are lam (..., 3), written without eigenvectors by
+    Sylvester's formula: |A| = sum_k |lam_k| prod_{j != k} (A - lam_j I) / (lam_k - lam_j).
+    Where the three coincide (N_xy = 0), A = lam I and |A| = |lam| I."""
+    I = np.eye(4)
+    out = np.zeros_like(A)
+    spread = lam[..., 2] - lam[..., 0]
+    ok = spread > 1e-300
+    for k in range(3):
+        term = np.broadcast_to(I, A.shape).copy()
+        for j in range(3):
+            if j != k:
+                d = np.where(ok, lam[..., k] - lam[..., j], 1.0)
+                term = term @ ((A - lam[..., j, None, None] * I) / d[..., None, None])
+        out += np.abs(lam[..., k])[..., None, None] * term
+    return np.where(ok[..., None, None], out, np.abs(lam[..., 1])[..., None, None] * I)
+
+
+OSHER_POINTS = 3   # Gauss-Legendre points on the path (reading: the paper cites Gaussian quadrature)
+
+
+def osher_flux(ql, qr, N, gamma, npts=OSHER_POINTS):
+    """Osher-type ALE flux (eq. eqn.osher) with the straight-line path of eq.
+    eqn.path, Psi(s) = ql + s (qr - ql), the path integral of |A| by Gauss-Legendre
+    quadrature in s."""
+    s, w = tb.gauss_legendre01(npts)
+    dq = qr - ql
+    D = np.zeros_like(dq)
+    for k in range(npts):
+        psi = ql + s[k] * dq
+        A = ale_jacobian(psi, N, gamma)
+        D += w[k] * np.einsum("...ij,...j->...i", abs_matrix(A, ale_wave_speeds(psi, N, gamma)), dq)
+    return 0.5 * (_ale_flux_dot(ql, N, gamma) + _ale_flux_dot(qr, N, gamma)) - 0.5 * D
+
+
+def hll_flux(ql, qr, N, gamma):
+    """HLL ALE flux (not in the paper; an alternative dissipation): signal speeds
+    of the ALE system along N, u.N_xy + N_t -/+ c |N_xy|, bounded over both
+    states; upwind flux when both speeds have one sign."""
+    nxy = np.sqrt(N[..., 0] ** 2 + N[..., 1] ** 2)
+
+    def speeds(q):
+        rho, u, v, p = euler.primitives(q, gamma)
+        un = u * N[..., 0] + v * N[..., 1] + N[..., 2]
+        c = np.sqrt(gamma * p / rho) * nxy
+        return un - c, un + c
+
+    l1, r1 = speeds(ql)
+    l2, r2 = speeds(qr)
+    sl, sr = np.minimum(l1, l2), np.maximum(r1, r2)
+    fl, fr = _ale_flux_dot(ql, N, gamma), _ale_flux_dot(qr, N, gamma)
+    den = np.where(sr > sl, sr - sl, 1.0)
+    fh = (sr[..., None] * fl - sl[..., None] * fr + (sl * sr)[..., None] * (qr - ql)) / den[..., None]
+    return np.where((sl >= 0)[..., None], fl, np.where((sr <= 0)[..., None], fr, fh))
+
+
+FLUXES = {"rusanov": rusanov_flux, "osher": osher_flux, "hll": hll_flux}
+
 BC_TRANSMISSIVE = 1
 BC_SLIP = 2
 
@@ -340,7 +439,7 @@ def patch_batch(M, cfg: Config, P, ticks, nL, sL, trL, nR, sR, trR, hasR, bc=Non
                 qrr = np.einsum("eq,eqv->ev", lR, trR[:, nG - 1 - g])
                 qr = np.where(hasR[:, None], qrr, qr)
             wgt = wc[g] * wc[h]
-            G += wgt * rusanov_flux(ql, qr, N, cfg.gamma)
+            G += wgt * FLUXES[cfg.flux](ql, qr, N, cfg.gamma)
             Nint += wgt * N
     return G, Nint
 
