@@ -47,6 +47,14 @@ enum {
   ADER_E_ORDER = -8     /* call out of sequence                                       */
 };
 
+/* Numerical fluxes (ader_config.flux).
+ *  RUSANOV: eq. eqn.rusanov with the largest |eigenvalue| of eq. A_n^V.
+ *  OSHER:   eq. eqn.osher on the straight-line path of eq. eqn.path, the path
+ *           integral of |A| = R |Lambda| R^-1 by 3-point Gauss-Legendre in s.
+ *  HLL:     two-wave HLL flux with the ALE signal speeds u.N + N_t -/+ c |N_xy|
+ *           bounded over both states (not in the paper). */
+enum { ADER_FLUX_RUSANOV = 0, ADER_FLUX_OSHER = 1, ADER_FLUX_HLL = 2 };
+
 /* Boundary tags of ader_upload_mesh. */
 enum { ADER_BC_TRANSMISSIVE = 1, ADER_BC_SLIP = 2 };
 
@@ -55,7 +63,7 @@ typedef struct ader_ctx ader_ctx;
 /* Scheme parameters (paper Sec. 2.2 after eq. Sigma, eq. eqn.timestep). */
 typedef struct {
   int32_t M;             /* polynomial degree 1..3; order of accuracy M+1              */
-  int32_t flux;          /* 0 = Rusanov ALE flux (eq. eqn.rusanov); others rejected    */
+  int32_t flux;          /* ADER_FLUX_*: numerical flux on the space-time patches       */
   double gamma;          /* ratio of specific heats (eq. eqn.eos)                      */
   double cfl;            /* CFL number of eq. eqn.timestep, (0, 0.5]                   */
   int32_t lts_levels;    /* L in 1..8: dyadic levels used by ader_step_lts             */

@@ -434,7 +434,7 @@ int ader_create(const ader_config* cfg, void* hip_stream, ader_ctx** out) {
   if (!cfg || !out) return ADER_E_ARG;
   *out = nullptr;
   if (cfg->M < 1 || cfg->M > 3) return ADER_E_ARG;
-  if (cfg->flux != 0) return ADER_E_ARG;
+  if (cfg->flux < ADER_FLUX_RUSANOV || cfg->flux > ADER_FLUX_HLL) return ADER_E_ARG;
   if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return ADER_E_ARG;
   if (!(cfg->gamma > 1.0)) return ADER_E_ARG;
   if (cfg->lts_levels < 1 || cfg->lts_levels > 8) return ADER_E_ARG;
@@ -451,6 +451,7 @@ int ader_create(const ader_config* cfg, void* hip_stream, ader_ctx** out) {
   c->prm.gcl_tol = 1e-12;
   c->prm.npic = cfg->n_picard > 0 ? cfg->n_picard : cfg->M + 1;
   c->prm.lagrangian = cfg->mesh_velocity == 0;
+  c->prm.flux = cfg->flux;
   try {
     aw::build_tables(cfg->M, c->tab);
   } catch (const std::exception& e) {

@@ -35,12 +35,14 @@ struct Tables {
   double gchi[MAXG], gw[MAXG];      // Gauss-Legendre on [0,1]
   double rqw[MAXRQ];                // triangle rule, exact to degree M (barycentric)
   double rqb[MAXRQ][3];
+  double osh_s[3], osh_w[3];        // Gauss-Legendre on [0,1] for the Osher path integral
 };
 
 struct Params {
   double gamma, cfl, eps, lambda, gcl_tol;
   int npic;
   int lagrangian;
+  int flux;         // ADER_FLUX_*
 };
 
 // Device-resident scalars of the running simulation.

@@ -28,6 +28,7 @@
 
 #include <cfloat>
 
+#include "aderweno.h"
 #include "common.h"
 
 namespace aw {
@@ -68,20 +69,109 @@ __device__ inline double pressure(const double q[4], double g) {
   return (g - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
 }
 
-// Space-time flux F~(q) . N = f N_x + g N_y + q N_t (eq. PDEdiv3D) and the
-// largest |eigenvalue| of the ALE Jacobian along N (eq. A_n^V); nxy = |N_xy|.
-__device__ inline double stflux_speed(const double q[4], const double N[3], double nxy, double g,
-                                      double out[4]) {
+// Space-time flux F~(q) . N = f N_x + g N_y + q N_t (eq. PDEdiv3D) through an
+// unnormalised space-time normal N, nxy = |N_xy|; also the ALE normal speed
+// un = u . N_xy + N_t and the scaled sound speed cn = c |N_xy|, so that the
+// eigenvalues of the ALE Jacobian along N (eq. A_n^V) are un - cn, un, un + cn.
+__device__ inline void stflux(const double q[4], const double N[3], double nxy, double g,
+                              double out[4], double& un, double& cn) {
   const double ir = 1.0 / q[0];
   const double u = q[1] * ir, v = q[2] * ir;
   const double p = (g - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
   const double uxy = u * N[0] + v * N[1];
-  const double un = uxy + N[2];
+  un = uxy + N[2];
   out[0] = q[0] * un;
   out[1] = q[1] * un + p * N[0];
   out[2] = q[2] * un + p * N[1];
   out[3] = q[3] * un + p * uxy;
-  return fabs(un) + sqrt(g * p * ir) * nxy;
+  cn = sqrt(g * p * ir) * nxy;
+}
+
+// Osher-type dissipation of eq. eqn.osher: sum_s w_s |A(Psi(s))| dq along the
+// straight path Psi(s) = ql + s dq of eq. eqn.path, with |A| = R |Lambda| R^-1
+// applied as wave strengths alpha = R^-1 dq followed by sum_k |lambda_k| alpha_k r_k.
+// r_k, R^-1 are the eigenvectors of the Euler flux Jacobian along the unit normal
+// n = N_xy / |N_xy| (acoustic, entropy, shear, acoustic); the ALE eigenvalues are
+// (u.n -/+ c) |N_xy| + N_t and u.n |N_xy| + N_t (entropy and shear).
+__device__ inline void osher_dissipation(const Tables* tb, const double ql[4], const double qr[4],
+                                         const double N[3], double nxy, double g, double D[4]) {
+  double dq[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    dq[v] = qr[v] - ql[v];
+    D[v] = 0.0;
+  }
+  if (!(nxy > 0.0)) {   // no spatial extent: A = N_t I
+#pragma unroll
+    for (int v = 0; v < 4; ++v) D[v] = fabs(N[2]) * dq[v];
+    return;
+  }
+  const double inxy = 1.0 / nxy;
+  const double nx = N[0] * inxy, ny = N[1] * inxy;
+  const double gm = g - 1.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double s = tb->osh_s[k], w = tb->osh_w[k];
+    double ps[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ps[v] = ql[v] + s * dq[v];
+    const double ir = 1.0 / ps[0];
+    const double u = ps[1] * ir, v = ps[2] * ir;
+    const double q2 = u * u + v * v;
+    const double p = gm * (ps[3] - 0.5 * ps[0] * q2);
+    const double c2 = g * p * ir, c = sqrt(c2), ic2 = 1.0 / c2;
+    const double H = (ps[3] + p) * ir;
+    const double un = u * nx + v * ny, ut = v * nx - u * ny;
+    // wave strengths
+    const double X = gm * (0.5 * q2 * dq[0] - u * dq[1] - v * dq[2] + dq[3]);
+    const double Y = c * (un * dq[0] - nx * dq[1] - ny * dq[2]);
+    const double a1 = 0.5 * (X + Y) * ic2, a4 = 0.5 * (X - Y) * ic2;
+    const double a2 = dq[0] - X * ic2;
+    const double a3 = nx * dq[2] - ny * dq[1] - ut * dq[0];
+    const double l1 = fabs((un - c) * nxy + N[2]), l2 = fabs(un * nxy + N[2]);
+    const double l4 = fabs((un + c) * nxy + N[2]);
+    const double b1 = w * l1 * a1, b2 = w * l2 * a2, b3 = w * l2 * a3, b4 = w * l4 * a4;
+    D[0] += b1 + b2 + b4;
+    D[1] += b1 * (u - c * nx) + b2 * u - b3 * ny + b4 * (u + c * nx);
+    D[2] += b1 * (v - c * ny) + b2 * v + b3 * nx + b4 * (v + c * ny);
+    D[3] += b1 * (H - un * c) + b2 * (0.5 * q2) + b3 * ut + b4 * (H + un * c);
+  }
+}
+
+// Numerical flux through the unnormalised space-time normal N of a patch
+// quadrature point: Rusanov (eq. eqn.rusanov), Osher-type (eq. eqn.osher) or HLL.
+__device__ inline void numerical_flux(int flux, const Tables* tb, const double ql[4],
+                                      const double qr[4], const double N[3], double g,
+                                      double out[4]) {
+  const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
+  double fl[4], fr[4], unl, cl, unr, cr;
+  stflux(ql, N, nxy, g, fl, unl, cl);
+  stflux(qr, N, nxy, g, fr, unr, cr);
+  if (flux == ADER_FLUX_HLL) {
+    // signal speeds bounded over both states; upwind when both have one sign
+    const double sl = fmin(unl - cl, unr - cr), sr = fmax(unl + cl, unr + cr);
+    if (sl >= 0.0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[v] = fl[v];
+    } else if (sr <= 0.0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[v] = fr[v];
+    } else {
+      const double id = 1.0 / (sr - sl);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (qr[v] - ql[v])) * id;
+    }
+  } else if (flux == ADER_FLUX_OSHER) {
+    double D[4];
+    osher_dissipation(tb, ql, qr, N, nxy, g, D);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * D[v];
+  } else {
+    // Rusanov: the largest |eigenvalue| of the ALE Jacobian over both states
+    const double smax = fmax(fabs(unl) + cl, fabs(unr) + cr);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * smax * (qr[v] - ql[v]);
+  }
 }
 
 // (a - b) / step for a power-of-two step, exactly
@@ -997,11 +1087,10 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
 #pragma unroll
           for (int v = 0; v < 4; ++v) qr[v] = ql[v];
         }
-        double fl[4], fr[4];
-        const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
-        const double smax = fmax(stflux_speed(ql, N, nxy, g, fl), stflux_speed(qr, N, nxy, g, fr));
+        double fn[4];
+        numerical_flux(P.flux, tb, ql, qr, N, g, fn);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) G[v] += w * (0.5 * (fl[v] + fr[v]) - 0.5 * smax * (qr[v] - ql[v]));
+        for (int v = 0; v < 4; ++v) G[v] += w * fn[v];
 #pragma unroll
         for (int k = 0; k < 3; ++k) Nn[k] += w * N[k];
       }

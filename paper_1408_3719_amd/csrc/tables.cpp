@@ -243,6 +243,7 @@ void build_tables(int M, Tables& T) {
     for (int l = 0; l < nb; ++l) T.psiNodes[m][l] = peval(psi[l], nx[m], ny[m]);
   }
   gauss_legendre01(M + 1, T.gchi, T.gw);
+  gauss_legendre01(3, T.osh_s, T.osh_w);
   const double vx[3] = {0.0, 1.0, 0.0}, vy[3] = {0.0, 0.0, 1.0};
   for (int e = 0; e < 3; ++e)
     for (int g = 0; g <= M; ++g) {

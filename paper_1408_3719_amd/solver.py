@@ -13,6 +13,7 @@ import numpy as np
 from . import _lib
 
 MESH_VELOCITY = {"lagrangian": 0, "eulerian": 1}
+FLUX = {"rusanov": 0, "osher": 1, "hll": 2}
 
 
 @dataclasses.dataclass
@@ -26,9 +27,11 @@ class Config:
     weno_eps: float = 1e-14
     weno_r: float = 8.0
     weno_lambda: float = 1e5
+    flux: str = "rusanov"          # "rusanov", "osher" or "hll"
 
     def to_c(self) -> _lib.AderConfig:
-        return _lib.AderConfig(self.M, 0, self.gamma, self.cfl, self.levels, self.n_picard,
+        return _lib.AderConfig(self.M, FLUX[self.flux], self.gamma, self.cfl, self.levels,
+                               self.n_picard,
                                MESH_VELOCITY[self.mesh_velocity], self.weno_eps, self.weno_r,
                                self.weno_lambda)
 

@@ -33,6 +33,20 @@ def test_invalid_configuration_rejected():
         assert lib.ader_create(ctypes.byref(c), None, ctypes.byref(ctx)) == -1
 
 
+def test_flux_selection():
+    """Rusanov, Osher and HLL are accepted; other flux codes are rejected."""
+    lib = _lib.load()
+    for name in ("rusanov", "osher", "hll"):
+        ctx = ctypes.c_void_p()
+        c = Config(flux=name).to_c()
+        assert lib.ader_create(ctypes.byref(c), None, ctypes.byref(ctx)) == 0
+        lib.ader_destroy(ctx)
+    ctx = ctypes.c_void_p()
+    c = Config().to_c()
+    c.flux = 3
+    assert lib.ader_create(ctypes.byref(c), None, ctypes.byref(ctx)) == -1
+
+
 def test_mesh_errors():
     mesh = strip_mesh(0, 1, 0, 1, 0.2, seed=1)
     tris = mesh.tris.copy()
