@@ -128,6 +128,7 @@ def main():
     ap.add_argument("--n-elems", type=int, default=None)
     ap.add_argument("--M", type=int, default=None)
     ap.add_argument("--levels", type=int, default=None)
+    ap.add_argument("--flux", choices=["rusanov", "osher", "hll"], default="rusanov")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=5000)
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -160,7 +161,7 @@ def main():
     else:
         mesh, Q0 = sod_case(a.n_elems, seed=1408)
         desc = "RP1 shock tube, {}-triangle strip"
-    cfg = Config(M=a.M, levels=a.levels)
+    cfg = Config(M=a.M, levels=a.levels, flux=a.flux)
     t_end = dflt[3]
     s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, cfg)
     sync = torch.cuda.synchronize
@@ -209,7 +210,8 @@ def main():
 
     def traffic(kernel, units_per_launch):
         m = MEASURED_TRAFFIC.get(kernel)
-        if m is None or m["source_sha256"] != source_sha or a.M != 2 or a.workload != "vortex":
+        if (m is None or m["source_sha256"] != source_sha or a.M != 2 or a.workload != "vortex"
+                or a.flux != "rusanov"):
             return None
         return m["bytes_per_unit"] * units_per_launch
 
@@ -267,7 +269,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": desc.format(mesh.n_elems) + f", M={a.M}, LTS {a.levels} levels, "
-                        "Lagrangian mesh motion",
+                        f"{a.flux} flux, Lagrangian mesh motion",
+            "flux": a.flux,
             "n_elems": mesh.n_elems, "M": a.M, "levels": a.levels,
             "parallelism": "single GPU",
         },
