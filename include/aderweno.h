@@ -129,6 +129,15 @@ int ader_step_gts(ader_ctx* ctx, double t_target, int32_t max_steps, ader_stats*
  * stencil; all elements meet again at the end of the macro step. */
 int ader_step_lts(ader_ctx* ctx, double t_target, int32_t max_macro_steps, ader_stats* st);
 
+/* Launch mode of ader_step_gts / ader_step_lts.  on != 0 (the default): each
+ * macro step (levels and predictors, its 2^(L-1) cycles, the unfinished count
+ * and the macro-step end) is one HIP graph, captured on a private stream of
+ * the context at the first step toward a given target time and replayed on
+ * the context's stream; one host synchronisation per macro step. on == 0: the
+ * same kernels are launched one by one.  Results are identical.  While
+ * profiling is on, kernels are always launched one by one. */
+int ader_set_graphs(ader_ctx* ctx, int32_t on);
+
 /* Current state into caller device buffers (any may be NULL):
  * Q_dev [4][n_elems] SoA, node_xy_dev [n_nodes][2], elem_t_dev [n_elems]. */
 int ader_download_state(ader_ctx* ctx, double* Q_dev, double* node_xy_dev, double* elem_t_dev);

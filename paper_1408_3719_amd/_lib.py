@@ -21,7 +21,7 @@ INT_ARRAYS = {"TICK", "STEP", "NTICK", "TOPO_EDGES", "TOPO_STENCILS", "TOPO_SCHE
 EXPORTED = ["ader_create", "ader_upload_mesh", "ader_workspace_size", "ader_bind_workspace",
             "ader_upload_state", "ader_step_gts", "ader_step_lts", "ader_download_state",
             "ader_get_stats", "ader_debug_size", "ader_debug_dump", "ader_debug_inject",
-            "ader_debug_cycles", "ader_debug_macro_begin", "ader_set_profiling",
+            "ader_debug_cycles", "ader_debug_macro_begin", "ader_set_profiling", "ader_set_graphs",
             "ader_kernel_times", "ader_last_error", "ader_destroy"]
 KERNELS = ["sched", "node", "patch", "update", "recon", "predict", "macro", "status"]
 
@@ -77,6 +77,7 @@ def load():
     lib.ader_debug_cycles.argtypes = [P, i32]
     lib.ader_debug_macro_begin.argtypes = [P, dbl, i32]
     lib.ader_set_profiling.argtypes = [P, i32]
+    lib.ader_set_graphs.argtypes = [P, i32]
     lib.ader_kernel_times.argtypes = [P, i32, P, P]
     lib.ader_last_error.argtypes = [P]
     lib.ader_last_error.restype = ctypes.c_char_p

@@ -23,8 +23,14 @@ struct ader_ctx {
   size_t ws_bytes = 0;
   aw::Dev dev{};
   std::string err;
-  int cycle = 0;            // stamp of the last cycle launched (never reused)
   int64_t cycles = 0, macro_steps = 0;
+  // each macro step as one HIP graph (captured on a private stream, replayed on
+  // the caller's), rebuilt when the target time or the ticks per macro step change
+  bool graphs = true;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_t = 0.0;
+  int g_N = 0;
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ADER_K_COUNT];
@@ -148,15 +154,15 @@ void flush_events(ader_ctx* c) {
 }
 
 template <class F>
-int timed(ader_ctx* c, int k, F launch) {
+int timed(ader_ctx* c, int k, hipStream_t st, F launch) {
   hipEvent_t a = nullptr, b = nullptr;
   if (c->prof) {
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return int(hipErrorOutOfMemory);
-    (void)hipEventRecord(a, c->stream);
+    (void)hipEventRecord(a, st);
   }
   int r = launch();
   if (c->prof) {
-    (void)hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, st);
     c->ev[k].push_back({a, b});
   }
   return r;
@@ -177,57 +183,107 @@ int check_err(ader_ctx* c, const aw::Scal& s) {
   return 0;
 }
 
-int run_cycles(ader_ctx* c, int n) {
+// Queue n cycles on stream st: update criterion and list, node motion, patch
+// fluxes, update, reconstruction and time step, predictor.
+int issue_cycles(ader_ctx* c, int n, hipStream_t st) {
   const aw::Dev& d = c->dev;
   const aw::Params& p = c->prm;
   const int M = c->cfg.M;
-  void* s = c->stream;
+  void* s = st;
   for (int k = 0; k < n; ++k) {
-    const int cy = ++c->cycle;
-    LCHK(c, timed(c, ADER_K_SCHED, [&] {
+    LCHK(c, timed(c, ADER_K_SCHED, st, [&] {
       int r = aw::launch_cycle_begin(d, s);
-      return r ? r : aw::launch_sched(d, cy, s);
+      return r ? r : aw::launch_sched(d, s);
     }));
-    LCHK(c, timed(c, ADER_K_NODE, [&] { return aw::launch_node(d, p, M, cy, s); }));
-    LCHK(c, timed(c, ADER_K_PATCH, [&] { return aw::launch_patch(d, p, M, cy, s); }));
-    LCHK(c, timed(c, ADER_K_UPDATE, [&] { return aw::launch_update(d, p, cy, s); }));
-    LCHK(c, timed(c, ADER_K_RECON, [&] { return aw::launch_reconstruct(d, p, M, 1, 1, s); }));
-    LCHK(c, timed(c, ADER_K_PREDICT, [&] { return aw::launch_predict(d, p, M, 1, s); }));
-    c->cycles++;
+    LCHK(c, timed(c, ADER_K_NODE, st, [&] { return aw::launch_node(d, p, M, s); }));
+    LCHK(c, timed(c, ADER_K_PATCH, st, [&] { return aw::launch_patch(d, p, M, s); }));
+    LCHK(c, timed(c, ADER_K_UPDATE, st, [&] { return aw::launch_update(d, p, s); }));
+    LCHK(c, timed(c, ADER_K_RECON, st, [&] { return aw::launch_reconstruct(d, p, M, 1, 1, s); }));
+    LCHK(c, timed(c, ADER_K_PREDICT, st, [&] { return aw::launch_predict(d, p, M, 1, s); }));
   }
   return 0;
 }
 
-int macro_begin(ader_ctx* c, double t_end, int N) {
-  LCHK(c, timed(c, ADER_K_MACRO, [&] { return aw::launch_macro_begin(c->dev, t_end, N, c->stream); }));
-  LCHK(c, timed(c, ADER_K_PREDICT, [&] { return aw::launch_predict(c->dev, c->prm, c->cfg.M, 0, c->stream); }));
+int issue_macro_begin(ader_ctx* c, double t_end, int N, hipStream_t st) {
+  LCHK(c, timed(c, ADER_K_MACRO, st, [&] { return aw::launch_macro_begin(c->dev, t_end, N, st); }));
+  LCHK(c, timed(c, ADER_K_PREDICT, st, [&] { return aw::launch_predict(c->dev, c->prm, c->cfg.M, 0, st); }));
   return 0;
 }
 
-// Macro steps of N ticks until t_target; returns 0 or an error code.
+// One macro step: levels and predictors, N cycles, the count of elements short
+// of tick N, and the macro-step end when that count is zero.
+int issue_macro(ader_ctx* c, double t_end, int N, hipStream_t st) {
+  int r;
+  if ((r = issue_macro_begin(c, t_end, N, st))) return r;
+  if ((r = issue_cycles(c, N, st))) return r;
+  LCHK(c, timed(c, ADER_K_STATUS, st, [&] { return aw::launch_status(c->dev, st); }));
+  LCHK(c, aw::launch_macro_end(c->dev, 1, st));
+  return 0;
+}
+
+int ensure_graph(ader_ctx* c, double t_end, int N) {
+  if (c->gexec && c->g_t == t_end && c->g_N == N) return 0;
+  if (c->gexec) {
+    HIPCHK(c, hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
+  }
+  if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  const int r = issue_macro(c, t_end, N, c->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (r || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return r ? r : hip_fail(c, int(e), "hipStreamEndCapture");
+  }
+  const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->gexec = nullptr;
+    return hip_fail(c, int(ei), "hipGraphInstantiate");
+  }
+  c->g_t = t_end;
+  c->g_N = N;
+  return 0;
+}
+
+// Macro steps of N ticks until t_target; returns 0 or an error code. One host
+// synchronisation per macro step; further cycles only when some element has
+// not reached tick N after N cycles.
 int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
   aw::Scal s;
   int r;
+  if ((r = read_scal(c, s))) return r;
   for (int k = 0; max_macro <= 0 || k < max_macro; ++k) {
-    if ((r = read_scal(c, s))) return r;
     if ((r = check_err(c, s))) return r;
     if (t_target - s.T <= 1e-12 * std::fmax(1.0, std::fabs(t_target))) break;
-    if ((r = macro_begin(c, t_target, N))) return r;
-    if ((r = run_cycles(c, N))) return r;
-    long long last = -1;
-    for (;;) {
-      LCHK(c, timed(c, ADER_K_STATUS, [&] { return aw::launch_status(c->dev, c->stream); }));
-      if ((r = read_scal(c, s))) return r;
-      if ((r = check_err(c, s))) return r;
-      if (!(s.delta > 0.0)) return fail(c, ADER_E_STATE, "time step is not positive");
-      if (s.n_unfinished == 0) break;
-      if ((long long)s.updates == last) return fail(c, ADER_E_DEADLOCK, "no element satisfies the update criterion");
-      last = (long long)s.updates;
-      if ((r = run_cycles(c, 1))) return r;
+    if (c->graphs && !c->prof) {
+      if ((r = ensure_graph(c, t_target, N))) return r;
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    } else if ((r = issue_macro(c, t_target, N, c->stream))) {
+      return r;
     }
-    LCHK(c, aw::launch_macro_end(c->dev, c->stream));
+    c->cycles += N;
+    if ((r = read_scal(c, s))) return r;
+    if ((r = check_err(c, s))) return r;
+    if (!(s.delta > 0.0)) return fail(c, ADER_E_STATE, "time step is not positive");
+    if (s.n_unfinished != 0) {
+      long long last = (long long)s.updates;
+      for (;;) {
+        if ((r = issue_cycles(c, 1, c->stream))) return r;
+        c->cycles++;
+        LCHK(c, timed(c, ADER_K_STATUS, c->stream, [&] { return aw::launch_status(c->dev, c->stream); }));
+        if ((r = read_scal(c, s))) return r;
+        if ((r = check_err(c, s))) return r;
+        if (s.n_unfinished == 0) break;
+        if ((long long)s.updates == last) return fail(c, ADER_E_DEADLOCK, "no element satisfies the update criterion");
+        last = (long long)s.updates;
+      }
+      LCHK(c, aw::launch_macro_end(c->dev, 0, c->stream));
+      if ((r = read_scal(c, s))) return r;
+    }
     c->macro_steps++;
   }
   return 0;
@@ -662,8 +718,9 @@ int ader_debug_inject(ader_ctx* c, int32_t what, const void* host, size_t bytes)
 int ader_debug_cycles(ader_ctx* c, int32_t n) {
   if (!c || n < 0) return ADER_E_ARG;
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
-  int r = run_cycles(c, n);
+  int r = issue_cycles(c, n, c->stream);
   if (r) return r;
+  c->cycles += n;
   aw::Scal s;
   if ((r = read_scal(c, s))) return r;
   return check_err(c, s);
@@ -672,7 +729,7 @@ int ader_debug_cycles(ader_ctx* c, int32_t n) {
 int ader_debug_macro_begin(ader_ctx* c, double t_end, int32_t levels) {
   if (!c || levels < 1 || levels > 8) return ADER_E_ARG;
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
-  int r = macro_begin(c, t_end, 1 << (levels - 1));
+  int r = issue_macro_begin(c, t_end, 1 << (levels - 1), c->stream);
   if (r) return r;
   aw::Scal s;
   if ((r = read_scal(c, s))) return r;
@@ -688,6 +745,12 @@ int ader_set_profiling(ader_ctx* c, int32_t on) {
     c->klaunch[k] = 0;
   }
   c->prof = on != 0;
+  return ADER_OK;
+}
+
+int ader_set_graphs(ader_ctx* c, int32_t on) {
+  if (!c) return ADER_E_ARG;
+  c->graphs = on != 0;
   return ADER_OK;
 }
 
@@ -710,6 +773,8 @@ const char* ader_last_error(const ader_ctx* c) {
 void ader_destroy(ader_ctx* c) {
   if (!c) return;
   if (c->bound) (void)hipStreamSynchronize(c->stream);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   for (int k = 0; k < ADER_K_COUNT; ++k)
     for (auto& p : c->ev[k]) {
       (void)hipEventDestroy(p.first);

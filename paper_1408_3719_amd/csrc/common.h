@@ -54,6 +54,7 @@ struct Scal {
   int n_active;     // active elements of the current cycle
   int n_unfinished; // elements that have not reached tick N
   int err;          // sticky error bits (ERR_*)
+  int cycle;        // stamp of the current cycle (advanced by the cycle's first kernel)
   unsigned long long min_dt_bits;   // min CFL step (positive doubles order as integers)
   unsigned long long max_gcl_bits;  // max relative GCL residual
   unsigned long long updates;
@@ -120,12 +121,12 @@ int launch_reconstruct(const Dev& d, const Params& p, int M, int use_list, int s
 int launch_predict(const Dev& d, const Params& p, int M, int use_list, void* stream);
 int launch_macro_begin(const Dev& d, double t_end, int N, void* stream);
 int launch_cycle_begin(const Dev& d, void* stream);
-int launch_sched(const Dev& d, int cycle, void* stream);
-int launch_node(const Dev& d, const Params& p, int M, int cycle, void* stream);
-int launch_patch(const Dev& d, const Params& p, int M, int cycle, void* stream);
-int launch_update(const Dev& d, const Params& p, int cycle, void* stream);
+int launch_sched(const Dev& d, void* stream);
+int launch_node(const Dev& d, const Params& p, int M, void* stream);
+int launch_patch(const Dev& d, const Params& p, int M, void* stream);
+int launch_update(const Dev& d, const Params& p, void* stream);
 int launch_status(const Dev& d, void* stream);
-int launch_macro_end(const Dev& d, void* stream);
+int launch_macro_end(const Dev& d, int only_if_done, void* stream);
 int launch_download_xy(const Dev& d, double* out, void* stream);
 int launch_download_q(const Dev& d, double* out, void* stream);
 int launch_upload_q(const Dev& d, const double* in, void* stream);

@@ -867,6 +867,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
 __global__ void k_cycle_begin(Dev d) {
   d.scal->n_active = 0;
   d.scal->n_unfinished = 0;
+  d.scal->cycle += 1;
 }
 
 // Each block owns a contiguous chunk of at most SCHED_CHUNK elements; 8 lanes
@@ -874,7 +875,8 @@ __global__ void k_cycle_begin(Dev d) {
 // active elements in LDS and reserves list space with one global atomic.
 constexpr int SCHED_CHUNK = 1024;
 
-__global__ void __launch_bounds__(TPB) k_sched(Dev d, int cycle, int chunk) {
+__global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
+  const int cycle = d.scal->cycle;
   constexpr int PER_PASS = TPB / 8;
   __shared__ int local[SCHED_CHUNK];
   __shared__ int count, gbase;
@@ -922,7 +924,8 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int cycle, int chunk) {
 // Node solver and node motion
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ tb, Params P, int cycle) {
+__global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ tb, Params P) {
+  const int cycle = d.scal->cycle;
   constexpr int T = M + 1, VV = Sz<M>::VV;
   const int NV = d.NV;
   const double delta = d.scal->delta;
@@ -994,7 +997,8 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
 // Space-time patch fluxes: one lane per swept edge
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__ tb, Params P, int cycle) {
+__global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__ tb, Params P) {
+  const int cycle = d.scal->cycle;
   constexpr int T = M + 1, nG = M + 1, TS = Sz<M>::TS;
   const int NV = d.NV, NF = d.NF;
   const double delta = d.scal->delta;
@@ -1108,7 +1112,8 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
 // Memory variables and conservative update
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ void __launch_bounds__(TPB) k_update(Dev d, Params P, int cycle) {
+__global__ void __launch_bounds__(TPB) k_update(Dev d, Params P) {
+  const int cycle = d.scal->cycle;
   const int NE = d.NE, NV = d.NV, NF = d.NF;
   double gmax = 0.0;   // largest relative GCL residual seen by this lane
   for (int i = xcd_block() * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
@@ -1242,7 +1247,11 @@ __global__ void __launch_bounds__(TPB) k_levels(Dev d) {
 }
 
 // All elements met at tick N: advance the common time and restart the ticks.
-__global__ void __launch_bounds__(TPB) k_macro_end(Dev d) {
+// Ends the macro step: common time advanced, ticks reset. With only_if_done,
+// it does nothing unless every element has reached the end of the macro step
+// (the host then runs further cycles and ends the step itself).
+__global__ void __launch_bounds__(TPB) k_macro_end(Dev d, int only_if_done) {
+  if (only_if_done && d.scal->n_unfinished != 0) return;
   const int n = max(d.NE, d.NV);
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid == 0) {
@@ -1408,27 +1417,27 @@ int launch_cycle_begin(const Dev& d, void* s) {
   return 0;
 }
 
-int launch_sched(const Dev& d, int cycle, void* s) {
+int launch_sched(const Dev& d, void* s) {
   // chunks of at most SCHED_CHUNK elements, at least ~1024 blocks when possible
   int chunk = (d.NE + 1023) / 1024;
   chunk = chunk < TPB / 8 ? TPB / 8 : (chunk > SCHED_CHUNK ? SCHED_CHUNK : chunk);
   const int blocks = (d.NE + chunk - 1) / chunk;
-  AW_LAUNCH_G(k_sched, blocks, s, d, cycle, chunk);
+  AW_LAUNCH_G(k_sched, blocks, s, d, chunk);
   return 0;
 }
 
-int launch_node(const Dev& d, const Params& p, int M, int cycle, void* s) {
-  AW_DISPATCH(M, AW_LAUNCH(k_node<MM>, d.NV, s, d, d.tab, p, cycle));
+int launch_node(const Dev& d, const Params& p, int M, void* s) {
+  AW_DISPATCH(M, AW_LAUNCH(k_node<MM>, d.NV, s, d, d.tab, p));
   return 0;
 }
 
-int launch_patch(const Dev& d, const Params& p, int M, int cycle, void* s) {
-  AW_DISPATCH(M, AW_LAUNCH(k_patch<MM>, d.NF, s, d, d.tab, p, cycle));
+int launch_patch(const Dev& d, const Params& p, int M, void* s) {
+  AW_DISPATCH(M, AW_LAUNCH(k_patch<MM>, d.NF, s, d, d.tab, p));
   return 0;
 }
 
-int launch_update(const Dev& d, const Params& p, int cycle, void* s) {
-  AW_DISPATCH(d.M, AW_LAUNCH(k_update<MM>, d.NE, s, d, p, cycle));
+int launch_update(const Dev& d, const Params& p, void* s) {
+  AW_DISPATCH(d.M, AW_LAUNCH(k_update<MM>, d.NE, s, d, p));
   return 0;
 }
 
@@ -1438,8 +1447,8 @@ int launch_status(const Dev& d, void* s) {
   return 0;
 }
 
-int launch_macro_end(const Dev& d, void* s) {
-  AW_LAUNCH(k_macro_end, d.NE > d.NV ? d.NE : d.NV, s, d);
+int launch_macro_end(const Dev& d, int only_if_done, void* s) {
+  AW_LAUNCH(k_macro_end, d.NE > d.NV ? d.NE : d.NV, s, d, only_if_done);
   return 0;
 }
 

@@ -174,6 +174,10 @@ class Solver(_Base):
         _check(self.lib, self.ctx, self.lib.ader_debug_inject(self.ctx, _lib.DBG[what],
                                                               a.ctypes.data, nbytes))
 
+    def set_graphs(self, on: bool):
+        """Each macro step as one captured HIP graph (default) or kernel by kernel."""
+        _check(self.lib, self.ctx, self.lib.ader_set_graphs(self.ctx, 1 if on else 0))
+
     def set_profiling(self, on: bool):
         _check(self.lib, self.ctx, self.lib.ader_set_profiling(self.ctx, 1 if on else 0))
 
