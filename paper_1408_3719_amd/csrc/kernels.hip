@@ -48,7 +48,8 @@ struct Sz {
   static constexpr int TS = trace_stride(M);
   static constexpr int WS = wnod_stride(M);
   static constexpr int VV = rec_off_vv(M);
-  static constexpr int G = nb <= 4 ? 4 : (nb <= 8 ? 8 : 16);   // predictor lanes per element
+  // predictor: one lane per spatial node, as many elements per wavefront as fit
+  static constexpr int EPW = 64 / nb;
 };
 
 constexpr int XE = rec_off_xe(), QO = rec_off_q(), AO = rec_off_a(), AVG = rec_off_avg();
@@ -547,14 +548,17 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Space-time Galerkin predictor: G lanes per element, lane m = spatial node m
+// Space-time Galerkin predictor: nb lanes per element, lane m = spatial node m;
+// floor(64/nb) elements per wavefront (an element never straddles two), the
+// remaining lanes of a wavefront are spare
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict__ tb, Params P,
                                                  int use_list) {
   using S = Sz<M>;
-  constexpr int nb = S::nb, T = S::nt, nG = S::nG, G = S::G, RS = S::RS, TS = S::TS, WS = S::WS;
-  constexpr int SLOTS = TPB / G;
+  constexpr int nb = S::nb, T = S::nt, nG = S::nG, RS = S::RS, TS = S::TS, WS = S::WS;
+  constexpr int G = nb, EPW = S::EPW, WPB = TPB / 64;
+  constexpr int SLOTS = EPW * WPB;       // elements per block
   // exchanged fields per node: q(4), f1..f3, g1..g3 (f0 = q1 and g0 = q2 are
   // not repeated), x, y; the per-element stride is padded by 16 bytes so that
   // the broadcast reads of the elements of one wavefront fall in distinct banks
@@ -562,18 +566,20 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
   constexpr int LSTR = NF * G + 2;
   constexpr int NPT = 1 + 3 * nG;        // element mean + edge Gauss points
   constexpr int PPL = (NPT + G - 1) / G; // points per lane
-  static_assert(64 % G == 0 && TPB % 64 == 0, "an element's lanes must share a wavefront");
-  __shared__ double lds[SLOTS * LSTR];
+  static_assert(TPB % 64 == 0, "whole wavefronts");
+  __shared__ double lds[(SLOTS + WPB) * LSTR];   // one extra slot per wavefront for its spare lanes
   __shared__ double c0[16][TPB];         // per lane: fixed parts of slice t = 0
   const int NE = d.NE;
   const int nitems = use_list ? d.scal->n_active : NE;
   const double delta = d.scal->delta;
   const double g = P.gamma;
-  const int slot = threadIdx.x / G;
-  const int m = threadIdx.x % G;
+  const int wv = threadIdx.x / 64, lw = threadIdx.x % 64;
+  const bool spare = lw >= EPW * G;
+  const int slot = spare ? SLOTS + wv : wv * EPW + lw / G;
+  const int m = spare ? lw - EPW * G : lw % G;   // < G either way
   double* const my = lds + slot * LSTR;
-  const bool node = m < nb;
-  const int mm = node ? m : 0;
+  const bool node = !spare;
+  const int mm = m;
   // this lane's rows of the spatial derivative matrices
   double Dx[nb], De[nb];
 #pragma unroll
@@ -591,7 +597,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
   for (int base = xcd_block((nitems + SLOTS - 1) / SLOTS) * SLOTS; base < nitems;
        base += gridDim.x * SLOTS) {
     const int idx = base + slot;
-    const int i = idx < nitems ? (use_list ? d.act_list[idx] : idx) : -1;
+    const int i = !spare && idx < nitems ? (use_list ? d.act_list[idx] : idx) : -1;
     const int st = i >= 0 ? d.ts[i].step : 0;
     const bool live = st > 0;           // uniform across the G lanes of the element
     const bool act = live && node;
@@ -1400,7 +1406,9 @@ int launch_reconstruct(const Dev& d, const Params& p, int M, int use_list, int s
 }
 
 int launch_predict(const Dev& d, const Params& p, int M, int use_list, void* s) {
-  AW_DISPATCH(M, AW_LAUNCH(k_predict<MM>, long(Sz<MM>::G) * d.NE, s, d, d.tab, p, use_list));
+  AW_DISPATCH(M, AW_LAUNCH(k_predict<MM>, long(TPB) * ((d.NE + Sz<MM>::EPW * (TPB / 64) - 1) /
+                                                     (Sz<MM>::EPW * (TPB / 64))),
+                           s, d, d.tab, p, use_list));
   return 0;
 }
 
