@@ -80,8 +80,9 @@ typedef struct {
   int64_t macro_steps;     /* dyadic macro steps completed                             */
   int64_t cfl_overshoots;  /* element steps longer than their CFL bound (level capped) */
   double max_gcl_residual; /* max |closure of the space-time volume| / (|T|+|T'|)      */
-  double t;                /* common time of all elements (they meet at macro steps)   */
-  double delta;            /* tick length of the last macro step                       */
+  double t;                /* common time of all elements (they meet at macro steps);
+                              with several instances the earliest instance time        */
+  double delta;            /* tick length of the last macro step (of instance 0)       */
   int64_t predictor_evals; /* element predictors computed                              */
   int64_t patches;         /* space-time patches integrated                            */
   int64_t node_moves;      /* node motions                                             */
@@ -107,6 +108,17 @@ int ader_upload_mesh(ader_ctx* ctx, int32_t n_nodes, const double* node_xy,
 /* Device bytes needed for state, topology and scratch of this mesh. */
 int ader_workspace_size(const ader_ctx* ctx, size_t* bytes);
 
+/* Batch of independent simulations (optional; default one instance): the
+ * mesh of ader_upload_mesh is n_instances meshes concatenated, instance k
+ * owning elements [elem_first[k], elem_first[k+1]) (elem_first has
+ * n_instances+1 entries, elem_first[0] = 0, elem_first[n_instances] =
+ * n_elems).  Instances share no node (else ADER_E_MESH).  Each keeps its own
+ * time and its own macro-step tick length (the smallest CFL step of its own
+ * elements); all step through the same macro-step structure in the same
+ * kernel launches, and each stops at t_target.  Call after ader_upload_mesh,
+ * before ader_workspace_size. */
+int ader_set_instances(ader_ctx* ctx, int32_t n_instances, const int32_t* elem_first);
+
 /* Hand the library a caller-owned device buffer of at least
  * ader_workspace_size bytes (256-byte aligned).  It must outlive the context.
  * Copies the topology and tables to it (synchronises the stream). */
@@ -128,6 +140,9 @@ int ader_step_gts(ader_ctx* ctx, double t_target, int32_t max_steps, ader_stats*
  * under the update criterion of eq. eqn.WENOupdate over its scheduling
  * stencil; all elements meet again at the end of the macro step. */
 int ader_step_lts(ader_ctx* ctx, double t_target, int32_t max_macro_steps, ader_stats* st);
+
+/* Current time of the first n instances into host memory (synchronises). */
+int ader_instance_times(ader_ctx* ctx, int32_t n, double* T_host);
 
 /* Launch mode of ader_step_gts / ader_step_lts.  on != 0 (the default): each
  * macro step (levels and predictors, its 2^(L-1) cycles, the unfinished count

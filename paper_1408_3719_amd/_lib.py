@@ -22,6 +22,7 @@ EXPORTED = ["ader_create", "ader_upload_mesh", "ader_workspace_size", "ader_bind
             "ader_upload_state", "ader_step_gts", "ader_step_lts", "ader_download_state",
             "ader_get_stats", "ader_debug_size", "ader_debug_dump", "ader_debug_inject",
             "ader_debug_cycles", "ader_debug_macro_begin", "ader_set_profiling", "ader_set_graphs",
+            "ader_set_instances", "ader_instance_times",
             "ader_kernel_times", "ader_last_error", "ader_destroy"]
 KERNELS = ["sched", "node", "patch", "update", "recon", "predict", "macro", "status"]
 
@@ -78,6 +79,8 @@ def load():
     lib.ader_debug_macro_begin.argtypes = [P, dbl, i32]
     lib.ader_set_profiling.argtypes = [P, i32]
     lib.ader_set_graphs.argtypes = [P, i32]
+    lib.ader_set_instances.argtypes = [P, i32, P]
+    lib.ader_instance_times.argtypes = [P, i32, P]
     lib.ader_kernel_times.argtypes = [P, i32, P, P]
     lib.ader_last_error.argtypes = [P]
     lib.ader_last_error.restype = ctypes.c_char_p

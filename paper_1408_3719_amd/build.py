@@ -35,7 +35,7 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(BUILD, src + ".o")
         # no contraction: the stencil ranking must match an independent
         # implementation bit for bit
-        _run(["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall",
+        _run(["g++", "-std=c++17", "-O2", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall",
               "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"), *inc,
               "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
@@ -47,7 +47,7 @@ def build(verbose: bool = True) -> str:
         objs.append(obj)
     tmp = OUT + ".tmp"
     _run([os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}", "-shared", "-fPIC",
-          "-o", tmp, *objs, f"-L{ROCM}/lib", "-lamdhip64"], verbose)
+          "-pthread", "-o", tmp, *objs, f"-L{ROCM}/lib", "-lamdhip64"], verbose)
     os.replace(tmp, OUT)
     return OUT
 

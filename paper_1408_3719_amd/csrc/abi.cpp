@@ -24,6 +24,8 @@ struct ader_ctx {
   aw::Dev dev{};
   std::string err;
   int64_t cycles = 0, macro_steps = 0;
+  // batch: element ranges [inst_first[k], inst_first[k+1]) of the instances
+  std::vector<int> inst_first, e_inst, v_inst;
   // each macro step as one HIP graph (captured on a private stream, replayed on
   // the caller's), rebuilt when the target time or the ticks per macro step change
   bool graphs = true;
@@ -83,10 +85,16 @@ size_t carve(ader_ctx* c, char* base) {
   size_t o_scal = L.take(sizeof(aw::Scal));
   size_t o_tab = L.take(sizeof(aw::Tables));
   size_t o_ts = L.take(NE * sizeof(aw::TickStep));
+  const size_t K = c->inst_first.size() - 1;
+  size_t o_inst = L.take(K * sizeof(aw::Inst));
   d.NE = t.NE;
   d.NV = t.NV;
   d.NF = t.NF;
   d.M = M;
+  d.K = int(K);
+  d.inst = base ? (aw::Inst*)(base + o_inst) : nullptr;
+  d.e_inst = pi(NE);
+  d.v_inst = pi(NV);
   d.scal = base ? (aw::Scal*)(base + o_scal) : nullptr;
   d.tab = base ? (const aw::Tables*)(base + o_tab) : nullptr;
   d.ts = base ? (aw::TickStep*)(base + o_ts) : nullptr;
@@ -180,6 +188,7 @@ int check_err(ader_ctx* c, const aw::Scal& s) {
   if (s.err & aw::ERR_GCL) return fail(c, ADER_E_GCL, "space-time control volume not closed (GCL residual above tolerance)");
   if (s.err & aw::ERR_STATE) return fail(c, ADER_E_STATE, "non-physical state (rho <= 0, p <= 0 or NaN)");
   if (s.err & aw::ERR_PRED) return fail(c, ADER_E_STATE, "a predictor was read outside its time slab");
+  if (s.err & aw::ERR_DT) return fail(c, ADER_E_STATE, "time step is not positive");
   return 0;
 }
 
@@ -204,20 +213,26 @@ int issue_cycles(ader_ctx* c, int n, hipStream_t st) {
   return 0;
 }
 
+// Open instances (short of t_end), their tick lengths and levels, predictors.
 int issue_macro_begin(ader_ctx* c, double t_end, int N, hipStream_t st) {
-  LCHK(c, timed(c, ADER_K_MACRO, st, [&] { return aw::launch_macro_begin(c->dev, t_end, N, st); }));
+  LCHK(c, timed(c, ADER_K_MACRO, st, [&] {
+    int r = aw::launch_open(c->dev, t_end, st);
+    return r ? r : aw::launch_macro_begin(c->dev, t_end, N, st);
+  }));
   LCHK(c, timed(c, ADER_K_PREDICT, st, [&] { return aw::launch_predict(c->dev, c->prm, c->cfg.M, 0, st); }));
   return 0;
 }
 
 // One macro step: levels and predictors, N cycles, the count of elements short
-// of tick N, and the macro-step end when that count is zero.
+// of tick N, the macro-step end when that count is zero, and the count of
+// instances still short of t_end.
 int issue_macro(ader_ctx* c, double t_end, int N, hipStream_t st) {
   int r;
   if ((r = issue_macro_begin(c, t_end, N, st))) return r;
   if ((r = issue_cycles(c, N, st))) return r;
   LCHK(c, timed(c, ADER_K_STATUS, st, [&] { return aw::launch_status(c->dev, st); }));
   LCHK(c, aw::launch_macro_end(c->dev, 1, st));
+  LCHK(c, aw::launch_open(c->dev, t_end, st));
   return 0;
 }
 
@@ -255,10 +270,11 @@ int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
   if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
   aw::Scal s;
   int r;
+  LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
   if ((r = read_scal(c, s))) return r;
   for (int k = 0; max_macro <= 0 || k < max_macro; ++k) {
     if ((r = check_err(c, s))) return r;
-    if (t_target - s.T <= 1e-12 * std::fmax(1.0, std::fabs(t_target))) break;
+    if (s.n_open == 0) break;      // every instance has reached t_target
     if (c->graphs && !c->prof) {
       if ((r = ensure_graph(c, t_target, N))) return r;
       HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
@@ -268,7 +284,6 @@ int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
     c->cycles += N;
     if ((r = read_scal(c, s))) return r;
     if ((r = check_err(c, s))) return r;
-    if (!(s.delta > 0.0)) return fail(c, ADER_E_STATE, "time step is not positive");
     if (s.n_unfinished != 0) {
       long long last = (long long)s.updates;
       for (;;) {
@@ -282,6 +297,7 @@ int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
         last = (long long)s.updates;
       }
       LCHK(c, aw::launch_macro_end(c->dev, 0, c->stream));
+      LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
       if ((r = read_scal(c, s))) return r;
     }
     c->macro_steps++;
@@ -289,7 +305,17 @@ int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
   return 0;
 }
 
-void fill_stats(ader_ctx* c, const aw::Scal& s, ader_stats* st) {
+int read_insts(ader_ctx* c, std::vector<aw::Inst>& in) {
+  in.resize(c->dev.K);
+  HIPCHK(c, hipMemcpyAsync(in.data(), c->dev.inst, in.size() * sizeof(aw::Inst), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+// t: the earliest instance time (the common time of all elements when there
+// is one instance); delta: the tick length of instance 0.
+void fill_stats(ader_ctx* c, const aw::Scal& s, const std::vector<aw::Inst>& in, ader_stats* st) {
   st->element_updates = s.updates;
   st->cycles = c->cycles;
   st->macro_steps = c->macro_steps;
@@ -298,8 +324,10 @@ void fill_stats(ader_ctx* c, const aw::Scal& s, ader_stats* st) {
   double g;
   std::memcpy(&g, &b, sizeof(g));
   st->max_gcl_residual = g;
-  st->t = s.T;
-  st->delta = s.delta;
+  double tmin = in[0].T;
+  for (const auto& x : in) tmin = std::fmin(tmin, x.T);
+  st->t = tmin;
+  st->delta = in[0].delta;
   st->predictor_evals = (int64_t)s.n_pred;
   st->patches = (int64_t)s.n_patch;
   st->node_moves = (int64_t)s.n_node;
@@ -531,6 +559,36 @@ int ader_upload_mesh(ader_ctx* c, int32_t n_nodes, const double* node_xy, int32_
     return fail(c, ADER_E_MESH, e.what());
   }
   c->has_mesh = true;
+  // one instance until ader_set_instances says otherwise
+  c->inst_first = {0, n_elems};
+  c->e_inst.assign(n_elems, 0);
+  c->v_inst.assign(n_nodes, 0);
+  return ADER_OK;
+}
+
+int ader_set_instances(ader_ctx* c, int32_t n_instances, const int32_t* elem_first) {
+  if (!c || n_instances < 1 || !elem_first) return ADER_E_ARG;
+  if (!c->has_mesh) return fail(c, ADER_E_ORDER, "no mesh uploaded");
+  if (c->bound) return fail(c, ADER_E_ORDER, "mesh already bound to a workspace");
+  const aw::Topology& t = c->topo;
+  if (elem_first[0] != 0 || elem_first[n_instances] != t.NE)
+    return fail(c, ADER_E_ARG, "instance ranges must start at 0 and end at n_elems");
+  for (int k = 0; k < n_instances; ++k)
+    if (elem_first[k + 1] <= elem_first[k]) return fail(c, ADER_E_ARG, "empty or decreasing instance range");
+  std::vector<int> ei(t.NE), vi(t.NV, -1);
+  for (int k = 0; k < n_instances; ++k)
+    for (int i = elem_first[k]; i < elem_first[k + 1]; ++i) {
+      ei[i] = k;
+      for (int j = 0; j < 3; ++j) {
+        int& v = vi[t.tri[3 * i + j]];
+        if (v >= 0 && v != k) return fail(c, ADER_E_MESH, "instances share a node");
+        v = k;
+      }
+    }
+  for (int& v : vi) v = v < 0 ? 0 : v;
+  c->inst_first.assign(elem_first, elem_first + n_instances + 1);
+  c->e_inst = std::move(ei);
+  c->v_inst = std::move(vi);
   return ADER_OK;
 }
 
@@ -562,6 +620,10 @@ int ader_bind_workspace(ader_ctx* c, void* dev_ptr, size_t bytes) {
   std::vector<double> wn = to_soa(t.wall_n, NV, 2);
   int r;
   if ((r = h2d(c, d.tab, &c->tab, sizeof(aw::Tables)))) return r;
+  if ((r = h2d(c, d.e_inst, c->e_inst.data(), NE * sizeof(int)))) return r;
+  if ((r = h2d(c, d.v_inst, c->v_inst.data(), NV * sizeof(int)))) return r;
+  std::vector<aw::Inst> in0(d.K);
+  if ((r = h2d(c, d.inst, in0.data(), in0.size() * sizeof(aw::Inst)))) return r;
   if ((r = h2d(c, d.tri, tri.data(), tri.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.elem_edges, ee.data(), ee.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.neigh, nb.data(), nb.size() * sizeof(int)))) return r;
@@ -596,9 +658,11 @@ int ader_upload_state(ader_ctx* c, const double* Q_dev, double t0) {
   int r;
   if ((r = h2d(c, d.X, xy.data(), xy.size() * sizeof(double)))) return r;
   aw::Scal s{};
-  s.T = t0;
   s.N = 1;
   if ((r = h2d(c, d.scal, &s, sizeof(s)))) return r;
+  std::vector<aw::Inst> in(d.K);
+  for (auto& x : in) x.T = t0;
+  if ((r = h2d(c, d.inst, in.data(), in.size() * sizeof(aw::Inst)))) return r;
   c->cycles = 0;
   c->macro_steps = 0;
   LCHK(c, aw::launch_init_geometry(d, c->stream));
@@ -641,9 +705,10 @@ int ader_get_stats(ader_ctx* c, ader_stats* st) {
   if (!c || !st) return ADER_E_ARG;
   if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
   aw::Scal s;
+  std::vector<aw::Inst> in;
   int r = read_scal(c, s);
-  if (r) return r;
-  fill_stats(c, s, st);
+  if (r || (r = read_insts(c, in))) return r;
+  fill_stats(c, s, in, st);
   return ADER_OK;
 }
 
@@ -675,9 +740,10 @@ int ader_debug_dump(ader_ctx* c, int32_t what, void* host, size_t bytes) {
   if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
   if (what == ADER_DBG_SCAL) {
     aw::Scal s;
+    std::vector<aw::Inst> in;
     int r = read_scal(c, s);
-    if (r) return r;
-    double v[4] = {s.T, s.delta, double(s.N), s.t_end};
+    if (r || (r = read_insts(c, in))) return r;
+    double v[4] = {in[0].T, in[0].delta, double(s.N), s.t_end};
     std::memcpy(host, v, sizeof(v));
     return ADER_OK;
   }
@@ -695,15 +761,17 @@ int ader_debug_inject(ader_ctx* c, int32_t what, const void* host, size_t bytes)
   if (a.bytes == 0 || bytes != a.bytes) return fail(c, ADER_E_ARG, "size mismatch");
   if (what == ADER_DBG_SCAL) {
     aw::Scal s;
+    std::vector<aw::Inst> in;
     int r = read_scal(c, s);
-    if (r) return r;
+    if (r || (r = read_insts(c, in))) return r;
     double v[4];
     std::memcpy(v, host, sizeof(v));
-    s.T = v[0];
-    s.delta = v[1];
+    in[0].T = v[0];
+    in[0].delta = v[1];
     s.N = int(v[2]);
     s.t_end = v[3];
     if ((r = h2d(c, c->dev.scal, &s, sizeof(s)))) return r;
+    if ((r = h2d(c, c->dev.inst, in.data(), sizeof(aw::Inst)))) return r;
   } else if (!a.dev) {
     int r = packed_io(c, what, nullptr, host, bytes);
     if (r) return r;
@@ -745,6 +813,16 @@ int ader_set_profiling(ader_ctx* c, int32_t on) {
     c->klaunch[k] = 0;
   }
   c->prof = on != 0;
+  return ADER_OK;
+}
+
+int ader_instance_times(ader_ctx* c, int32_t n, double* T_host) {
+  if (!c || n < 0 || (n > 0 && !T_host)) return ADER_E_ARG;
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  std::vector<aw::Inst> in;
+  int r = read_insts(c, in);
+  if (r) return r;
+  for (int k = 0; k < n && k < int(in.size()); ++k) T_host[k] = in[k].T;
   return ADER_OK;
 }
 

@@ -45,17 +45,26 @@ struct Params {
   int flux;         // ADER_FLUX_*
 };
 
+// One simulation of a batch: independent meshes are concatenated (no shared
+// node), each with its own time and tick length; an unbatched run is one
+// instance. All instances step through the same macro-step structure.
+struct Inst {
+  double T;                        // common time at the start of the macro step
+  double delta;                    // tick length of the macro step (0 while closed)
+  unsigned long long min_dt_bits;  // min CFL step over its elements (as ordered bits)
+  int open;                        // 1 while short of the target time
+  int pad;
+};
+
 // Device-resident scalars of the running simulation.
 struct Scal {
-  double T;         // common time at the start of the macro step
-  double delta;     // tick length
   double t_end;     // target time of the current call
   int N;            // ticks per macro step 2^(L-1)
+  int n_open;       // instances short of the target time
   int n_active;     // active elements of the current cycle
   int n_unfinished; // elements that have not reached tick N
   int err;          // sticky error bits (ERR_*)
   int cycle;        // stamp of the current cycle (advanced by the cycle's first kernel)
-  unsigned long long min_dt_bits;   // min CFL step (positive doubles order as integers)
   unsigned long long max_gcl_bits;  // max relative GCL residual
   unsigned long long updates;
   unsigned long long overshoots;
@@ -64,7 +73,7 @@ struct Scal {
   unsigned long long n_node;    // node moves
 };
 
-enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8 };
+enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8, ERR_DT = 16 };
 
 // Per-element storage.  Data that other elements gather (vertices, average,
 // area, the predictor's time-node averages and vertex velocities) sits in one
@@ -90,8 +99,10 @@ struct TickStep {   // tick in the macro step and step length in ticks (0: finis
 
 // Pointers into the caller's workspace.
 struct Dev {
-  int NE, NV, NF, M;
+  int NE, NV, NF, M, K;
   Scal* scal;
+  Inst* inst;                        // [K]
+  const int *e_inst, *v_inst;        // instance of each element [NE] and node [NV]
   const Tables* tab;
   // elements
   double* rec;        // [NE][rec_stride]
@@ -127,6 +138,7 @@ int launch_patch(const Dev& d, const Params& p, int M, void* stream);
 int launch_update(const Dev& d, const Params& p, void* stream);
 int launch_status(const Dev& d, void* stream);
 int launch_macro_end(const Dev& d, int only_if_done, void* stream);
+int launch_open(const Dev& d, double t_end, void* stream);
 int launch_download_xy(const Dev& d, double* out, void* stream);
 int launch_download_q(const Dev& d, double* out, void* stream);
 int launch_upload_q(const Dev& d, const double* in, void* stream);

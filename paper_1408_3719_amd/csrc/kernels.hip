@@ -56,6 +56,14 @@ constexpr int XE = rec_off_xe(), QO = rec_off_q(), AO = rec_off_a(), AVG = rec_o
 
 __device__ inline void set_err(const Dev& d, int bits) { atomicOr(&d.scal->err, bits); }
 
+// Tick length of the instance of element i / node k (one instance: no gather).
+__device__ inline double elem_delta(const Dev& d, int i) {
+  return d.K == 1 ? d.inst[0].delta : d.inst[d.e_inst[i]].delta;
+}
+__device__ inline double node_delta(const Dev& d, int k) {
+  return d.K == 1 ? d.inst[0].delta : d.inst[d.v_inst[k]].delta;
+}
+
 // count the calling lanes of the wavefront with one atomic
 __device__ inline void wave_count(unsigned long long* ctr) {
   unsigned long long m = __ballot(1);
@@ -354,12 +362,12 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
   constexpr int nb = S::nb, ne = S::ne, nu = S::nu, WS = S::WS;
   const int NE = d.NE;
   const int nitems = use_list ? d.scal->n_active : NE;
-  const double delta = d.scal->delta;
   const int sl = threadIdx.x & 7;
   const int ngroups = (gridDim.x * blockDim.x) >> 3;
   const int nwork = int((8L * nitems + blockDim.x - 1) / blockDim.x);
   for (int idx = (xcd_block(nwork) * blockDim.x + threadIdx.x) >> 3; idx < nitems; idx += ngroups) {
     const int i = use_list ? d.act_list[idx] : idx;
+    const double delta = elem_delta(d, i);   // stencil elements share the instance
     const int nt = d.ts[i].tick;
     const double* ri = rec<M>(d, i);
     double Xi[6], Qi[4];
@@ -571,7 +579,6 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
   __shared__ double c0[16][TPB];         // per lane: fixed parts of slice t = 0
   const int NE = d.NE;
   const int nitems = use_list ? d.scal->n_active : NE;
-  const double delta = d.scal->delta;
   const double g = P.gamma;
   const int wv = threadIdx.x / 64, lw = threadIdx.x % 64;
   const bool spare = lw >= EPW * G;
@@ -602,7 +609,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
     const bool live = st > 0;           // uniform across the G lanes of the element
     const bool act = live && node;
     if (live && m == 0) wave_count(&d.scal->n_pred);
-    const double dt = live ? double(st) * delta : 1.0;
+    const double dt = live ? double(st) * elem_delta(d, i) : 1.0;
     const double idt = 1.0 / dt;
     double q[T][4], x[T][2];
     if (act) {
@@ -934,7 +941,6 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
   const int cycle = d.scal->cycle;
   constexpr int T = M + 1, VV = Sz<M>::VV;
   const int NV = d.NV;
-  const double delta = d.scal->delta;
   if (blockIdx.x == 0 && threadIdx.x == 0) d.scal->updates += (unsigned long long)d.scal->n_active;
   for (int k = xcd_block() * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
     const int r0 = d.ring_ptr[k], r1 = d.ring_ptr[k + 1];
@@ -990,7 +996,7 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
       Vx -= vn * nx;
       Vy -= vn * ny;
     }
-    const double dtk = double(newt - nk) * delta;
+    const double dtk = double(newt - nk) * node_delta(d, k);
     d.Xnew[k] = d.X[k] + dtk * Vx;
     d.Xnew[NV + k] = d.X[NV + k] + dtk * Vy;
     d.ntick_new[k] = newt;
@@ -1007,12 +1013,12 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
   const int cycle = d.scal->cycle;
   constexpr int T = M + 1, nG = M + 1, TS = Sz<M>::TS;
   const int NV = d.NV, NF = d.NF;
-  const double delta = d.scal->delta;
   const double g = P.gamma;
   for (int e = xcd_block() * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
     const int a = d.e_a[e], b = d.e_b[e];
     const bool ma = d.node_stamp[a] == cycle, mb = d.node_stamp[b] == cycle;
     if (!ma && !mb) continue;
+    const double delta = node_delta(d, a);
     double P1[3], P2[3], P3[3], P4[3];
     const double n1 = d.ntick[a], n2 = d.ntick[b];
     const double n3 = mb ? d.ntick_new[b] : n2, n4 = ma ? d.ntick_new[a] : n1;
@@ -1209,64 +1215,113 @@ __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P) {
 // ---------------------------------------------------------------------------
 // Macro-step boundary
 // ---------------------------------------------------------------------------
-__global__ void k_reset_min(Dev d) { d.scal->min_dt_bits = ~0ull; }
+__global__ void __launch_bounds__(TPB) k_reset_min(Dev d) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.K; k += gridDim.x * blockDim.x)
+    d.inst[k].min_dt_bits = ~0ull;
+}
 
+// Smallest CFL step per instance. Instances own contiguous element ranges, so
+// a wavefront spans one instance except at range ends: one atomic per
+// wavefront then, one per lane otherwise.
 __global__ void __launch_bounds__(TPB) k_min_dt(Dev d) {
-  __shared__ double red[TPB];
-  double m = DBL_MAX;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x)
-    m = fmin(m, d.dtcfl[i]);
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = TPB / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
+  for (int base = blockIdx.x * blockDim.x; base < d.NE; base += gridDim.x * blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool in = i < d.NE;
+    const int k = in ? d.e_inst[i] : -1;
+    double m = in ? d.dtcfl[i] : DBL_MAX;
+    const int k0 = __shfl(k, 0), klast = __shfl(k, 63);
+    if (k0 == klast) {
+#pragma unroll
+      for (int s = 1; s < 64; s <<= 1) m = fmin(m, __shfl_xor(m, s));
+      if (__lane_id() == 0 && k0 >= 0 && m > 0.0 && m < DBL_MAX)
+        atomicMin(&d.inst[k0].min_dt_bits, (unsigned long long)__double_as_longlong(m));
+    } else if (in && m > 0.0 && m < DBL_MAX) {
+      atomicMin(&d.inst[k].min_dt_bits, (unsigned long long)__double_as_longlong(m));
+    }
   }
-  if (threadIdx.x == 0 && red[0] > 0.0 && red[0] < DBL_MAX)
-    atomicMin(&d.scal->min_dt_bits, (unsigned long long)__double_as_longlong(red[0]));
 }
 
-__global__ void k_macro_setup(Dev d, double t_end, int N) {
-  Scal* s = d.scal;
-  const double dmin = __longlong_as_double((long long)s->min_dt_bits);
-  const double rest = (t_end - s->T) / double(N);
-  s->delta = fmin(dmin, rest);
-  s->N = N;
-  s->t_end = t_end;
+// Tick length of the macro step per open instance: the smallest CFL step,
+// clamped so that N ticks do not pass the target time; 0 for closed ones.
+__global__ void __launch_bounds__(TPB) k_macro_setup(Dev d, double t_end, int N) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.scal->N = N;
+    d.scal->t_end = t_end;
+  }
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.K; k += gridDim.x * blockDim.x) {
+    Inst* in = d.inst + k;
+    if (!in->open) {
+      in->delta = 0.0;
+      continue;
+    }
+    const double dmin = __longlong_as_double((long long)in->min_dt_bits);
+    const double rest = (t_end - in->T) / double(N);
+    in->delta = fmin(dmin, rest);
+    if (!(in->delta > 0.0)) set_err(d, ERR_DT);
+  }
 }
 
+// Levels at the macro-step start; elements of closed instances sit at tick N
+// with no step, i.e. finished.
 __global__ void __launch_bounds__(TPB) k_levels(Dev d) {
   const int N = d.scal->N;
-  const double delta = d.scal->delta;
   const int n = max(d.NE, d.NV);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     if (i < d.NE) {
-      int over;
+      const double delta = d.inst[d.e_inst[i]].delta;
       TickStep me;
-      me.tick = 0;
-      me.step = level_step(d.dtcfl[i], delta, N, 0, &over);
+      if (delta > 0.0) {
+        int over;
+        me.tick = 0;
+        me.step = level_step(d.dtcfl[i], delta, N, 0, &over);
+        if (over) atomicAdd(&d.scal->overshoots, 1ull);
+      } else {
+        me.tick = N;
+        me.step = 0;
+      }
       d.ts[i] = me;
-      if (over) atomicAdd(&d.scal->overshoots, 1ull);
     }
     if (i < d.NV) d.ntick[i] = 0;
   }
 }
 
-// All elements met at tick N: advance the common time and restart the ticks.
-// Ends the macro step: common time advanced, ticks reset. With only_if_done,
-// it does nothing unless every element has reached the end of the macro step
-// (the host then runs further cycles and ends the step itself).
+// Ends the macro step: each instance's time advanced, ticks reset. With
+// only_if_done, it does nothing unless every element has reached the end of
+// the macro step (the host then runs further cycles and ends the step itself).
 __global__ void __launch_bounds__(TPB) k_macro_end(Dev d, int only_if_done) {
   if (only_if_done && d.scal->n_unfinished != 0) return;
-  const int n = max(d.NE, d.NV);
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid == 0) {
-    Scal* s = d.scal;
-    s->T = s->T + double(s->N) * s->delta;
-  }
-  for (int i = gid; i < n; i += gridDim.x * blockDim.x) {
+  const int N = d.scal->N;
+  const int n = max(max(d.NE, d.NV), d.K);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (i < d.K) {
+      Inst* in = d.inst + i;
+      in->T = in->T + double(N) * in->delta;
+    }
     if (i < d.NE) d.ts[i].tick = 0;
     if (i < d.NV) d.ntick[i] = 0;
+  }
+}
+
+// Which instances are short of t_end (the same test the host applies to a
+// single time), and how many.
+__global__ void __launch_bounds__(TPB) k_open(Dev d, double t_end) {
+  const double tol = 1e-12 * fmax(1.0, fabs(t_end));
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.K; k += gridDim.x * blockDim.x)
+    d.inst[k].open = !(t_end - d.inst[k].T <= tol);
+}
+
+__global__ void __launch_bounds__(TPB) k_count_open(Dev d) {
+  __shared__ int part[TPB / 64];
+  int c = 0;
+  for (int k = threadIdx.x; k < d.K; k += blockDim.x) c += d.inst[k].open;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) c += __shfl_xor(c, s);
+  if (__lane_id() == 0) part[threadIdx.x / 64] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < TPB / 64; ++w) t += part[w];
+    d.scal->n_open = t;
   }
 }
 
@@ -1354,9 +1409,10 @@ __global__ void __launch_bounds__(TPB) k_download_xy(Dev d, double* out) {
 }
 
 __global__ void __launch_bounds__(TPB) k_elem_times(Dev d, double* out) {
-  const double T = d.scal->T, delta = d.scal->delta;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x)
-    out[i] = T + double(d.ts[i].tick) * delta;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x) {
+    const Inst in = d.inst[d.e_inst[i]];
+    out[i] = in.T + double(d.ts[i].tick) * in.delta;
+  }
 }
 
 int grid_for(long n) {
@@ -1413,9 +1469,9 @@ int launch_predict(const Dev& d, const Params& p, int M, int use_list, void* s) 
 }
 
 int launch_macro_begin(const Dev& d, double t_end, int N, void* s) {
-  AW_LAUNCH1(k_reset_min, s, d);
+  AW_LAUNCH(k_reset_min, d.K, s, d);
   AW_LAUNCH(k_min_dt, d.NE, s, d);
-  AW_LAUNCH1(k_macro_setup, s, d, t_end, N);
+  AW_LAUNCH(k_macro_setup, d.K, s, d, t_end, N);
   AW_LAUNCH(k_levels, d.NE > d.NV ? d.NE : d.NV, s, d);
   return 0;
 }
@@ -1456,7 +1512,15 @@ int launch_status(const Dev& d, void* s) {
 }
 
 int launch_macro_end(const Dev& d, int only_if_done, void* s) {
-  AW_LAUNCH(k_macro_end, d.NE > d.NV ? d.NE : d.NV, s, d, only_if_done);
+  long n = d.NE > d.NV ? d.NE : d.NV;
+  if (d.K > n) n = d.K;
+  AW_LAUNCH(k_macro_end, n, s, d, only_if_done);
+  return 0;
+}
+
+int launch_open(const Dev& d, double t_end, void* s) {
+  AW_LAUNCH(k_open, d.K, s, d, t_end);
+  AW_LAUNCH_G(k_count_open, 1, s, d);
   return 0;
 }
 

@@ -24,13 +24,35 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host.h"
 
 namespace aw {
+
+// Runs fn(begin, end) over [0, n) split into contiguous chunks on up to 16
+// host threads (the work items are independent).
+template <class F>
+void parallel_for(int n, F fn) {
+  int nt = int(std::thread::hardware_concurrency());
+  nt = nt < 1 ? 1 : (nt > 16 ? 16 : nt);
+  if (n < 4096) nt = 1;
+  if (nt == 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int chunk = (n + nt - 1) / nt;
+  for (int w = 0; w < nt; ++w) {
+    const int b = w * chunk, e = std::min(n, b + chunk);
+    if (b < e) th.emplace_back([=, &fn] { fn(b, e); });
+  }
+  for (auto& x : th) x.join();
+}
 
 void build_topology(int M, int NV, const double* xy, int NE, const int* tri_in, int NB,
                     const int* bedge, Topology& t) {
@@ -144,116 +166,136 @@ void build_topology(int M, int NV, const double* xy, int NE, const int* tri_in, 
     return dx * dx + dy * dy;
   };
   std::vector<std::vector<int>> vadj(NE);
-  for (int i = 0; i < NE; ++i) {
-    std::vector<int>& v = vadj[i];
-    for (int k = 0; k < 3; ++k) {
-      int nd = tri[3 * i + k];
-      for (int r = t.ring_ptr[nd]; r < t.ring_ptr[nd + 1]; ++r) v.push_back(t.ring_ent[r] >> 2);
+  parallel_for(NE, [&](int i0, int i1) {
+    for (int i = i0; i < i1; ++i) {
+      std::vector<int>& v = vadj[i];
+      for (int k = 0; k < 3; ++k) {
+        int nd = tri[3 * i + k];
+        for (int r = t.ring_ptr[nd]; r < t.ring_ptr[nd + 1]; ++r) v.push_back(t.ring_ent[r] >> 2);
+      }
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
     }
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-  }
-  // ---- stencils -------------------------------------------------------------------------
+  });
+  // ---- stencils (independent per element; each worker has its own marks) ------------------
   t.sten.assign(size_t(NE) * NSTEN * ne, -1);
-  std::vector<int> mark(NE, -1), dist(NE, 0);
-  std::vector<int> layer, next, cand, adm;
-  for (int i = 0; i < NE; ++i) {
-    int* st = &t.sten[size_t(i) * NSTEN * ne];
-    // central
-    {
-      int cnt = 0;
-      st[cnt++] = i;
-      mark[i] = 2 * i;
+  std::vector<std::string> errors;
+  std::mutex err_mu;
+  parallel_for(NE, [&](int i0, int i1) {
+    std::vector<int> mark(NE, -1);
+    std::vector<int> layer, next, cand, adm, ord;
+    for (int i = i0; i < i1; ++i) {
+      int* st = &t.sten[size_t(i) * NSTEN * ne];
+      // central
+      {
+        int cnt = 0;
+        st[cnt++] = i;
+        mark[i] = 2 * i;
+        layer.assign(1, i);
+        while (cnt < ne && !layer.empty()) {
+          next.clear();
+          for (int j : layer)
+            for (int k = 0; k < 3; ++k) {
+              int m = t.neigh[3 * j + k];
+              if (m >= 0 && mark[m] != 2 * i) {
+                mark[m] = 2 * i;
+                next.push_back(m);
+              }
+            }
+          ord = next;
+          std::sort(ord.begin(), ord.end(), [&](int x, int y) {
+            double dx = d2of(i, x), dy = d2of(i, y);
+            return dx < dy || (dx == dy && x < y);
+          });
+          for (int m : ord)
+            if (cnt < ne) st[cnt++] = m;
+          layer = next;
+        }
+        if (cnt < ne) {
+          std::lock_guard<std::mutex> g(err_mu);
+          errors.push_back("mesh too small: central stencil of element " + std::to_string(i) +
+                           " cannot be filled");
+          return;
+        }
+      }
+      // candidate pool: vertex-adjacency distance 1..M+4
+      cand.clear();
+      mark[i] = 2 * i + 1;
       layer.assign(1, i);
-      while (cnt < ne && !layer.empty()) {
+      for (int depth = 1; depth <= M + 4; ++depth) {
         next.clear();
         for (int j : layer)
-          for (int k = 0; k < 3; ++k) {
-            int m = t.neigh[3 * j + k];
-            if (m >= 0 && mark[m] != 2 * i) {
-              mark[m] = 2 * i;
+          for (int m : vadj[j])
+            if (mark[m] != 2 * i + 1) {
+              mark[m] = 2 * i + 1;
               next.push_back(m);
+              cand.push_back(m);
             }
-          }
-        std::vector<int> ord = next;
-        std::sort(ord.begin(), ord.end(), [&](int x, int y) {
-          double dx = d2of(i, x), dy = d2of(i, y);
-          return dx < dy || (dx == dy && x < y);
-        });
-        for (int m : ord)
-          if (cnt < ne) st[cnt++] = m;
-        layer = next;
+        layer.swap(next);
       }
-      if (cnt < ne)
-        throw std::runtime_error("mesh too small: central stencil of element " + std::to_string(i) +
-                                 " cannot be filled");
-    }
-    // candidate pool: vertex-adjacency distance 1..M+4
-    cand.clear();
-    mark[i] = 2 * i + 1;
-    layer.assign(1, i);
-    for (int depth = 1; depth <= M + 4; ++depth) {
-      next.clear();
-      for (int j : layer)
-        for (int m : vadj[j])
-          if (mark[m] != 2 * i + 1) {
-            mark[m] = 2 * i + 1;
-            next.push_back(m);
-            cand.push_back(m);
+      for (int k = 0; k < 3; ++k) {
+        const double* P = xy + 2 * tri[3 * i + k];
+        const double* Q1 = xy + 2 * tri[3 * i + (k + 1) % 3];
+        const double* Q2 = xy + 2 * tri[3 * i + (k + 2) % 3];
+        double e1x = Q1[0] - P[0], e1y = Q1[1] - P[1];
+        double e2x = Q2[0] - P[0], e2y = Q2[1] - P[1];
+        for (int sgn = 0; sgn < 2; ++sgn) {
+          adm.clear();
+          for (int j : cand) {
+            double dx = bx[j] - P[0], dy = by[j] - P[1];
+            double c1 = dx * e2y - dy * e2x;
+            double c2 = e1x * dy - e1y * dx;
+            bool in = sgn == 0 ? (c1 > 0.0 && c2 > 0.0) : (c1 < 0.0 && c2 < 0.0);
+            if (in) adm.push_back(j);
           }
-      layer.swap(next);
-    }
-    const double* X0 = xy + 2 * tri[3 * i];
-    for (int k = 0; k < 3; ++k) {
-      const double* P = xy + 2 * tri[3 * i + k];
-      const double* Q1 = xy + 2 * tri[3 * i + (k + 1) % 3];
-      const double* Q2 = xy + 2 * tri[3 * i + (k + 2) % 3];
-      double e1x = Q1[0] - P[0], e1y = Q1[1] - P[1];
-      double e2x = Q2[0] - P[0], e2y = Q2[1] - P[1];
-      for (int sgn = 0; sgn < 2; ++sgn) {
-        adm.clear();
-        for (int j : cand) {
-          double dx = bx[j] - P[0], dy = by[j] - P[1];
-          double c1 = dx * e2y - dy * e2x;
-          double c2 = e1x * dy - e1y * dx;
-          bool in = sgn == 0 ? (c1 > 0.0 && c2 > 0.0) : (c1 < 0.0 && c2 < 0.0);
-          if (in) adm.push_back(j);
+          if (int(adm.size()) < ne - 1) continue;
+          std::sort(adm.begin(), adm.end(), [&](int x, int y) {
+            double dx = d2of(i, x), dy = d2of(i, y);
+            return dx < dy || (dx == dy && x < y);
+          });
+          int s = sgn == 0 ? 1 + k : 4 + k;
+          st[s * ne] = i;
+          for (int c = 0; c < ne - 1; ++c) st[s * ne + 1 + c] = adm[c];
         }
-        if (int(adm.size()) < ne - 1) continue;
-        std::sort(adm.begin(), adm.end(), [&](int x, int y) {
-          double dx = d2of(i, x), dy = d2of(i, y);
-          return dx < dy || (dx == dy && x < y);
-        });
-        int s = sgn == 0 ? 1 + k : 4 + k;
-        st[s * ne] = i;
-        for (int c = 0; c < ne - 1; ++c) st[s * ne + 1 + c] = adm[c];
       }
     }
-    (void)X0;
+  });
+  if (!errors.empty()) {
+    std::sort(errors.begin(), errors.end());
+    throw std::runtime_error(errors.front());
   }
-  // ---- scheduling stencils ---------------------------------------------------------------
+  // ---- scheduling stencils: symmetric closure of (stencils + vertex ring) ------------------
+  std::vector<std::vector<int>> U(NE);
+  parallel_for(NE, [&](int i0, int i1) {
+    for (int i = i0; i < i1; ++i) {
+      std::vector<int>& u = U[i];
+      u = vadj[i];
+      const int* st = &t.sten[size_t(i) * NSTEN * ne];
+      for (int s = 0; s < NSTEN; ++s)
+        if (st[s * ne] >= 0)
+          for (int c = 0; c < ne; ++c) u.push_back(st[s * ne + c]);
+      u.push_back(i);
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+    }
+  });
   std::vector<std::vector<int>> S(NE);
-  for (int i = 0; i < NE; ++i) {
-    std::vector<int> U = vadj[i];
-    const int* st = &t.sten[size_t(i) * NSTEN * ne];
-    for (int s = 0; s < NSTEN; ++s)
-      if (st[s * ne] >= 0)
-        for (int c = 0; c < ne; ++c) U.push_back(st[s * ne + c]);
-    U.push_back(i);
-    std::sort(U.begin(), U.end());
-    U.erase(std::unique(U.begin(), U.end()), U.end());
-    for (int j : U) {
+  for (int i = 0; i < NE; ++i)
+    for (int j : U[i]) {
       S[i].push_back(j);
       S[j].push_back(i);
     }
-  }
   t.sched_ptr.assign(NE + 1, 0);
   t.sched_idx.clear();
+  parallel_for(NE, [&](int i0, int i1) {
+    for (int i = i0; i < i1; ++i) {
+      std::vector<int>& v = S[i];
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+  });
   for (int i = 0; i < NE; ++i) {
-    std::vector<int>& v = S[i];
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-    t.sched_idx.insert(t.sched_idx.end(), v.begin(), v.end());
+    t.sched_idx.insert(t.sched_idx.end(), S[i].begin(), S[i].end());
     t.sched_ptr[i + 1] = int(t.sched_idx.size());
   }
 }

@@ -113,13 +113,19 @@ class Solver(_Base):
     transmissive, 2 = slip wall.  Q0 (NE,4) conserved initial averages.
     """
 
-    def __init__(self, nodes, tris, bedges, Q0, cfg: Config, t0: float = 0.0, device="cuda:0"):
+    def __init__(self, nodes, tris, bedges, Q0, cfg: Config, t0: float = 0.0, device="cuda:0",
+                 instance_first=None):
         import torch   # loaded before the library so both share one HIP runtime
         self.torch = torch
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         self.stream = torch.cuda.current_stream(self.device)
         super().__init__(nodes, tris, bedges, cfg, stream=self.stream.cuda_stream)
+        self.n_instances = 1
+        if instance_first is not None:
+            f = np.ascontiguousarray(instance_first, np.int32)
+            self.n_instances = f.size - 1
+            _check(self.lib, self.ctx, self.lib.ader_set_instances(self.ctx, self.n_instances, f.ctypes.data))
         n = ctypes.c_size_t()
         _check(self.lib, self.ctx, self.lib.ader_workspace_size(self.ctx, ctypes.byref(n)))
         self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
@@ -173,6 +179,12 @@ class Solver(_Base):
             raise ValueError(f"{what}: {a.nbytes} bytes given, {nbytes} expected")
         _check(self.lib, self.ctx, self.lib.ader_debug_inject(self.ctx, _lib.DBG[what],
                                                               a.ctypes.data, nbytes))
+
+    def instance_times(self):
+        """Current time of every instance of a batch."""
+        T = np.empty(self.n_instances, np.float64)
+        _check(self.lib, self.ctx, self.lib.ader_instance_times(self.ctx, self.n_instances, T.ctypes.data))
+        return T
 
     def set_graphs(self, on: bool):
         """Each macro step as one captured HIP graph (default) or kernel by kernel."""

@@ -47,6 +47,24 @@ def test_flux_selection():
     assert lib.ader_create(ctypes.byref(c), None, ctypes.byref(ctx)) == -1
 
 
+def test_instance_ranges_validated():
+    """ader_set_instances: contiguous element ranges over disjoint meshes only."""
+    from workloads import concat_instances, sod_case, vortex_case
+    nodes, tris, bedges, _, first = concat_instances([sod_case(300, seed=2), vortex_case(400, seed=3)])
+    host = HostTopology(nodes, tris, bedges, Config(M=2))
+    lib = host.lib
+    f = np.ascontiguousarray(first, np.int32)
+    assert lib.ader_set_instances(host.ctx, 2, f.ctypes.data) == 0
+    bad = f.copy()
+    bad[1] = bad[1] + 5                  # splits a mesh: the two ranges share nodes
+    assert lib.ader_set_instances(host.ctx, 2, bad.ctypes.data) == -2
+    bad = f.copy()
+    bad[2] -= 1                          # does not end at n_elems
+    assert lib.ader_set_instances(host.ctx, 2, bad.ctypes.data) == -1
+    one = np.array([0, tris.shape[0]], np.int32)
+    assert lib.ader_set_instances(host.ctx, 1, one.ctypes.data) == 0
+
+
 def test_mesh_errors():
     mesh = strip_mesh(0, 1, 0, 1, 0.2, seed=1)
     tris = mesh.tris.copy()
@@ -64,6 +82,20 @@ def both(request):
     host = HostTopology(mesh.nodes, mesh.tris, mesh.bedges, Config(M=M))
     ora = build_topology(mesh.nodes, mesh.tris, M, mesh.bedges)
     return M, mesh, host, ora
+
+
+def test_threaded_topology_matches_oracle():
+    """Above 4096 elements the host builds stencils on several threads: the
+    result is still the oracle's, bit for bit (two disjoint instances)."""
+    from workloads import concat_instances, vortex_case
+    nodes, tris, bedges, _, _ = concat_instances([vortex_case(3000, seed=4), vortex_case(2500, seed=6)])
+    host = HostTopology(nodes, tris, bedges, Config(M=2))
+    ora = build_topology(nodes, tris, 2, bedges)
+    assert tris.shape[0] > 4096
+    assert np.array_equal(host.dump("TOPO_STENCILS"), ora.stencils)
+    ptr, idx = host.dump("TOPO_SCHED_PTR"), host.dump("TOPO_SCHED_IDX")
+    for i in range(tris.shape[0]):
+        assert np.array_equal(idx[ptr[i]:ptr[i + 1]], ora.sched[i]), i
 
 
 def test_edges_match_oracle(both):

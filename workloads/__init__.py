@@ -11,8 +11,10 @@ Workloads (shapes follow the paper's test section):
 """
 from .mesh import Mesh, strip_mesh, square_graded_mesh, disk_graded_mesh
 from .ic import (cell_average, sod_primitive, vortex_primitive, explosion_primitive,
-                 prim_to_cons, sod_case, vortex_case, explosion_case, batched_cases)
+                 prim_to_cons, sod_case, vortex_case, explosion_case, batched_cases,
+                 concat_instances)
 
 __all__ = ["Mesh", "strip_mesh", "square_graded_mesh", "disk_graded_mesh",
            "cell_average", "sod_primitive", "vortex_primitive", "explosion_primitive",
-           "prim_to_cons", "sod_case", "vortex_case", "explosion_case", "batched_cases"]
+           "prim_to_cons", "sod_case", "vortex_case", "explosion_case", "batched_cases",
+           "concat_instances"]

@@ -129,3 +129,23 @@ def batched_cases(n_instances: int = 256, seed: int = 256, n_min: int = 1000,
                 x, y, (rl, 0, 0, pl), (rr, 0, 0, pr)), gamma)
         out.append((mesh, q))
     return out
+
+
+def concat_instances(cases):
+    """Concatenate independent (mesh, Q) instances into one disjoint mesh.
+    Returns nodes, tris, bedges, Q and elem_first: instance k owns elements
+    elem_first[k]:elem_first[k+1] and the nodes of those elements."""
+    nodes, tris, bedges, qs, first = [], [], [], [], [0]
+    off = 0
+    for mesh, q in cases:
+        nodes.append(mesh.nodes)
+        tris.append(mesh.tris + off)
+        b = mesh.bedges.copy()
+        b[:, :2] += off
+        bedges.append(b)
+        qs.append(q)
+        off += mesh.nodes.shape[0]
+        first.append(first[-1] + mesh.tris.shape[0])
+    return (np.concatenate(nodes), np.concatenate(tris).astype(np.int32),
+            np.concatenate(bedges).astype(np.int32), np.concatenate(qs),
+            np.array(first, np.int32))
