@@ -213,12 +213,10 @@ int issue_cycles(ader_ctx* c, int n, hipStream_t st) {
   return 0;
 }
 
-// Open instances (short of t_end), their tick lengths and levels, predictors.
+// Tick lengths and levels of the open instances (flagged by launch_open for
+// t_end beforehand), predictors.
 int issue_macro_begin(ader_ctx* c, double t_end, int N, hipStream_t st) {
-  LCHK(c, timed(c, ADER_K_MACRO, st, [&] {
-    int r = aw::launch_open(c->dev, t_end, st);
-    return r ? r : aw::launch_macro_begin(c->dev, t_end, N, st);
-  }));
+  LCHK(c, timed(c, ADER_K_MACRO, st, [&] { return aw::launch_macro_begin(c->dev, t_end, N, st); }));
   LCHK(c, timed(c, ADER_K_PREDICT, st, [&] { return aw::launch_predict(c->dev, c->prm, c->cfg.M, 0, st); }));
   return 0;
 }
@@ -797,6 +795,7 @@ int ader_debug_cycles(ader_ctx* c, int32_t n) {
 int ader_debug_macro_begin(ader_ctx* c, double t_end, int32_t levels) {
   if (!c || levels < 1 || levels > 8) return ADER_E_ARG;
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  LCHK(c, aw::launch_open(c->dev, t_end, c->stream));
   int r = issue_macro_begin(c, t_end, 1 << (levels - 1), c->stream);
   if (r) return r;
   aw::Scal s;

@@ -910,10 +910,19 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
         unf = true;
         fut = me.tick + me.step;
         const int r1 = d.sched_ptr[i + 1];
-        for (int r = d.sched_ptr[i] + sub; r < r1; r += 8) {
-          const TickStep o = d.ts[d.sched_idx[r]];
-          mx = max(mx, o.tick);
-          mn = min(mn, o.tick + o.step);
+        // four entries per lane in flight before any is used
+        for (int r = d.sched_ptr[i] + sub; r < r1; r += 32) {
+          int jx[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) jx[u] = r + 8 * u < r1 ? d.sched_idx[r + 8 * u] : -1;
+          TickStep o[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) o[u] = jx[u] >= 0 ? d.ts[jx[u]] : TickStep{0, 1 << 29};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            mx = max(mx, o[u].tick);
+            mn = min(mn, o[u].tick + o[u].step);
+          }
         }
       }
     }
