@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--M", type=int, default=None)
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--flux", choices=["rusanov", "osher", "hll"], default="rusanov")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: pick launch settings with the library's autotuner before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=5000)
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -243,6 +245,7 @@ def main():
     t_end = dflt[3]
     s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, cfg)
     sync = torch.cuda.synchronize
+    tune = s.autotune(2) if a.autotune else None      # state restored: not part of the run
 
     # ---- LTS: warm-up then the timed macro steps --------------------------------
     s.step_lts(t_end, a.warmup)
@@ -356,6 +359,7 @@ def main():
         "lts": {"updates": lts_updates, "seconds": t_lts, "physical_interval": [T_a, T_b]},
         "lts_time_to_solution_speedup": t_gts / t_lts,
         "gts_over_lts_updates": gts_updates / max(lts_updates, 1),
+        "autotune": tune,
         "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "work_units": units,

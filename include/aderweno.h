@@ -144,6 +144,28 @@ int ader_step_lts(ader_ctx* ctx, double t_target, int32_t max_macro_steps, ader_
 /* Current time of the first n instances into host memory (synchronises). */
 int ader_instance_times(ader_ctx* ctx, int32_t n, double* T_host);
 
+/* Launch choices that leave every result bit-identical: elements per
+ * workgroup of the scheduler (0: built-in rule) and workgroups per CU of the
+ * reconstruction and predictor launches over the active list (0: one grid
+ * covering every element). */
+typedef struct {
+  int32_t sched_chunk;        /* 0 or 32..1024 */
+  int32_t list_wg_per_cu;     /* 0 or 1..64    */
+  double ms_per_macro_step;   /* ader_autotune: time of the chosen setting     */
+} ader_tune;
+
+/* Set the launch choices explicitly. */
+int ader_set_tune(ader_ctx* ctx, const ader_tune* tune);
+
+/* Autotuner: from a snapshot of the current device state, times
+ * `trial_macro_steps` LTS macro steps (levels of the configuration, no target
+ * time) for each candidate setting, one coordinate at a time (scheduler chunk
+ * in {rule, 64, 128, 256, 512, 1024}, then workgroups per CU in {all, 4, 8,
+ * 16, 32}), keeps the fastest, and restores the state, so the simulation does
+ * not advance.  Allocates a device copy of the workspace for the duration
+ * (hipMalloc).  The choice is written to *chosen when not null. */
+int ader_autotune(ader_ctx* ctx, int32_t trial_macro_steps, ader_tune* chosen);
+
 /* Launch mode of ader_step_gts / ader_step_lts.  on != 0 (the default): each
  * macro step (levels and predictors, its 2^(L-1) cycles, the unfinished count
  * and the macro-step end) is one HIP graph, captured on a private stream of

@@ -22,7 +22,7 @@ EXPORTED = ["ader_create", "ader_upload_mesh", "ader_workspace_size", "ader_bind
             "ader_upload_state", "ader_step_gts", "ader_step_lts", "ader_download_state",
             "ader_get_stats", "ader_debug_size", "ader_debug_dump", "ader_debug_inject",
             "ader_debug_cycles", "ader_debug_macro_begin", "ader_set_profiling", "ader_set_graphs",
-            "ader_set_instances", "ader_instance_times",
+            "ader_set_instances", "ader_instance_times", "ader_set_tune", "ader_autotune",
             "ader_kernel_times", "ader_last_error", "ader_destroy"]
 KERNELS = ["sched", "node", "patch", "update", "recon", "predict", "macro", "status"]
 
@@ -33,6 +33,11 @@ class AderConfig(ctypes.Structure):
                 ("n_picard", ctypes.c_int32), ("mesh_velocity", ctypes.c_int32),
                 ("weno_eps", ctypes.c_double), ("weno_r", ctypes.c_double),
                 ("weno_lambda", ctypes.c_double)]
+
+
+class AderTune(ctypes.Structure):
+    _fields_ = [("sched_chunk", ctypes.c_int32), ("list_wg_per_cu", ctypes.c_int32),
+                ("ms_per_macro_step", ctypes.c_double)]
 
 
 class AderStats(ctypes.Structure):
@@ -80,6 +85,8 @@ def load():
     lib.ader_set_profiling.argtypes = [P, i32]
     lib.ader_set_graphs.argtypes = [P, i32]
     lib.ader_set_instances.argtypes = [P, i32, P]
+    lib.ader_set_tune.argtypes = [P, ctypes.POINTER(AderTune)]
+    lib.ader_autotune.argtypes = [P, i32, ctypes.POINTER(AderTune)]
     lib.ader_instance_times.argtypes = [P, i32, P]
     lib.ader_kernel_times.argtypes = [P, i32, P, P]
     lib.ader_last_error.argtypes = [P]

@@ -607,8 +607,14 @@ int ader_bind_workspace(ader_ctx* c, void* dev_ptr, size_t bytes) {
   size_t need = carve(c, nullptr);
   if (bytes < need) return fail(c, ADER_E_ARG, "workspace too small");
   c->ws = (char*)dev_ptr;
-  c->ws_bytes = bytes;
+  c->ws_bytes = need;
   carve(c, c->ws);
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      c->dev.n_cu = ncu;
+  }
   const aw::Topology& t = c->topo;
   aw::Dev& d = c->dev;
   const size_t NE = t.NE, NV = t.NV, NF = t.NF;
@@ -823,6 +829,108 @@ int ader_instance_times(ader_ctx* c, int32_t n, double* T_host) {
   if (r) return r;
   for (int k = 0; k < n && k < int(in.size()); ++k) T_host[k] = in[k].T;
   return ADER_OK;
+}
+
+int ader_set_tune(ader_ctx* c, const ader_tune* t) {
+  if (!c || !t) return ADER_E_ARG;
+  if (t->sched_chunk != 0 && (t->sched_chunk < 32 || t->sched_chunk > 1024)) return ADER_E_ARG;
+  if (t->list_wg_per_cu < 0 || t->list_wg_per_cu > 64) return ADER_E_ARG;
+  c->dev.sched_chunk = t->sched_chunk;
+  c->dev.list_wg_per_cu = t->list_wg_per_cu;
+  if (c->gexec) {
+    HIPCHK(c, hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
+  }
+  return ADER_OK;
+}
+
+int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
+  if (!c || trials < 1) return ADER_E_ARG;
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  const bool prof = c->prof;
+  const int64_t cycles = c->cycles, macro = c->macro_steps;
+  void* snap = nullptr;
+  HIPCHK(c, hipMalloc(&snap, c->ws_bytes));
+  c->prof = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int r = 0;
+  auto cleanup = [&] {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(snap);
+    c->prof = prof;
+    c->cycles = cycles;
+    c->macro_steps = macro;
+  };
+  auto restore = [&]() -> int {
+    HIPCHK(c, hipMemcpyAsync(c->ws, snap, c->ws_bytes, hipMemcpyDeviceToDevice, c->stream));
+    return 0;
+  };
+  // time `trials` macro steps of the current setting from the snapshot
+  auto trial = [&](double& ms) -> int {
+    int rr;
+    if ((rr = restore())) return rr;
+    const double far = 1e300;
+    const int N = 1 << (c->cfg.lts_levels - 1);
+    LCHK(c, aw::launch_open(c->dev, far, c->stream));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int k = 0; k < trials; ++k)
+      if ((rr = issue_macro(c, far, N, c->stream))) return rr;
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&f, e0, e1));
+    ms = double(f) / trials;
+    return 0;
+  };
+  do {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      r = fail(c, ADER_E_HIP, "hipEventCreate");
+      break;
+    }
+    hipError_t he = hipMemcpyAsync(snap, c->ws, c->ws_bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (he != hipSuccess) {
+      r = hip_fail(c, int(he), "snapshot copy");
+      break;
+    }
+    const int chunks[] = {0, 64, 128, 256, 512, 1024};
+    const int wgs[] = {0, 4, 8, 16, 32};
+    double best = 1e300, ms = 0.0;
+    int bc = c->dev.sched_chunk, bw = c->dev.list_wg_per_cu;
+    for (int ch : chunks) {
+      c->dev.sched_chunk = ch;
+      c->dev.list_wg_per_cu = bw;
+      if ((r = trial(ms))) break;
+      if (ms < best) best = ms, bc = ch;
+    }
+    if (r) break;
+    for (int w : wgs) {
+      c->dev.sched_chunk = bc;
+      c->dev.list_wg_per_cu = w;
+      if ((r = trial(ms))) break;
+      if (ms < best) best = ms, bw = w;
+    }
+    if (r) break;
+    c->dev.sched_chunk = bc;
+    c->dev.list_wg_per_cu = bw;
+    if ((r = restore())) break;
+    if ((he = hipStreamSynchronize(c->stream)) != hipSuccess) {
+      r = hip_fail(c, int(he), "hipStreamSynchronize");
+      break;
+    }
+    if (c->gexec) {
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+    if (chosen) {
+      chosen->sched_chunk = bc;
+      chosen->list_wg_per_cu = bw;
+      chosen->ms_per_macro_step = best;
+    }
+  } while (false);
+  (void)hipStreamSynchronize(c->stream);
+  cleanup();
+  return r;
 }
 
 int ader_set_graphs(ader_ctx* c, int32_t on) {

@@ -100,6 +100,10 @@ struct TickStep {   // tick in the macro step and step length in ticks (0: finis
 // Pointers into the caller's workspace.
 struct Dev {
   int NE, NV, NF, M, K;
+  // launch choices (host side; 0 = built-in default): elements per scheduler
+  // workgroup, and workgroups per CU of the list-driven reconstruction and
+  // predictor launches (0: one workgroup per slice of the whole element range)
+  int sched_chunk, list_wg_per_cu, n_cu;
   Scal* scal;
   Inst* inst;                        // [K]
   const int *e_inst, *v_inst;        // instance of each element [NE] and node [NV]

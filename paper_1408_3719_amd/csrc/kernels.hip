@@ -1464,16 +1464,33 @@ int launch_init_geometry(const Dev& d, void* s) {
   return 0;
 }
 
+// Workgroups of a list-driven launch: enough for every element, or (when
+// tuned) a persistent grid of list_wg_per_cu workgroups per CU striding over
+// the active list.
+static int list_grid(const Dev& d, long blocks_for_all, int use_list) {
+  long b = blocks_for_all;
+  if (use_list && d.list_wg_per_cu > 0) {
+    const long cap = long(d.list_wg_per_cu) * (d.n_cu > 0 ? d.n_cu : 256);
+    if (b > cap) b = cap;
+  }
+  if (b < 1) b = 1;
+  if (b > 16384) b = 16384;
+  return int(b);
+}
+
 int launch_reconstruct(const Dev& d, const Params& p, int M, int use_list, int set_level, void* s) {
   // 8 lanes per element
-  AW_DISPATCH(M, AW_LAUNCH(k_reconstruct<MM>, 8L * d.NE, s, d, d.tab, p, use_list, set_level));
+  const int g = list_grid(d, (8L * d.NE + TPB - 1) / TPB, use_list);
+  AW_DISPATCH(M, AW_LAUNCH_G(k_reconstruct<MM>, g, s, d, d.tab, p, use_list, set_level));
   return 0;
 }
 
 int launch_predict(const Dev& d, const Params& p, int M, int use_list, void* s) {
-  AW_DISPATCH(M, AW_LAUNCH(k_predict<MM>, long(TPB) * ((d.NE + Sz<MM>::EPW * (TPB / 64) - 1) /
-                                                     (Sz<MM>::EPW * (TPB / 64))),
-                           s, d, d.tab, p, use_list));
+  AW_DISPATCH(M, {
+    constexpr int per_block = Sz<MM>::EPW * (TPB / 64);
+    const int g = list_grid(d, (long(d.NE) + per_block - 1) / per_block, use_list);
+    AW_LAUNCH_G(k_predict<MM>, g, s, d, d.tab, p, use_list);
+  });
   return 0;
 }
 
@@ -1491,8 +1508,9 @@ int launch_cycle_begin(const Dev& d, void* s) {
 }
 
 int launch_sched(const Dev& d, void* s) {
-  // chunks of at most SCHED_CHUNK elements, at least ~1024 blocks when possible
-  int chunk = (d.NE + 1023) / 1024;
+  // chunks of at most SCHED_CHUNK elements, at least ~1024 blocks when possible,
+  // unless a chunk size was chosen
+  int chunk = d.sched_chunk > 0 ? d.sched_chunk : (d.NE + 1023) / 1024;
   chunk = chunk < TPB / 8 ? TPB / 8 : (chunk > SCHED_CHUNK ? SCHED_CHUNK : chunk);
   const int blocks = (d.NE + chunk - 1) / chunk;
   AW_LAUNCH_G(k_sched, blocks, s, d, chunk);

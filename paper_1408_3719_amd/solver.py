@@ -180,6 +180,17 @@ class Solver(_Base):
         _check(self.lib, self.ctx, self.lib.ader_debug_inject(self.ctx, _lib.DBG[what],
                                                               a.ctypes.data, nbytes))
 
+    def autotune(self, trial_macro_steps: int = 2):
+        """Time candidate launch settings on the current state (restored afterwards)
+        and keep the fastest; returns the choice."""
+        t = _lib.AderTune()
+        _check(self.lib, self.ctx, self.lib.ader_autotune(self.ctx, trial_macro_steps, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in _lib.AderTune._fields_}
+
+    def set_tune(self, sched_chunk: int = 0, list_wg_per_cu: int = 0):
+        t = _lib.AderTune(sched_chunk, list_wg_per_cu, 0.0)
+        _check(self.lib, self.ctx, self.lib.ader_set_tune(self.ctx, ctypes.byref(t)))
+
     def instance_times(self):
         """Current time of every instance of a batch."""
         T = np.empty(self.n_instances, np.float64)

@@ -46,3 +46,33 @@ def test_graph_replays_equal_eager_launches(name, levels):
     assert sg["t"] == se["t"] and abs(sg["t"] - t1) <= 1e-12 * t1
     for f in COUNTERS:
         assert sg[f] == se[f], f
+
+
+def test_autotune_keeps_state_and_results():
+    """The autotuner restores the state it tuned on, and the tuned launch
+    settings give bit-identical results (they only change work grouping)."""
+    make, M = CASES["explosion_M2"]
+    mesh, Q0 = make()
+    a = _gpu_solver(mesh, Q0, M, 3)
+    b = _gpu_solver(mesh, Q0, M, 3)
+    a.step_lts(10.0, 1)
+    b.step_lts(10.0, 1)
+    before = a.stats()
+    Qa0, Xa0, _ = a.download()
+    choice = a.autotune(2)
+    print("tuned", choice, flush=True)
+    assert choice["ms_per_macro_step"] > 0.0
+    after = a.stats()
+    Qa1, Xa1, _ = a.download()
+    assert np.array_equal(Qa0, Qa1) and np.array_equal(Xa0, Xa1)
+    for f in COUNTERS + ("t",):
+        assert before[f] == after[f], f
+    sa, sb = a.step_lts(10.0, 3), b.step_lts(10.0, 3)
+    assert _same(a, b)
+    for f in COUNTERS + ("t",):
+        assert sa[f] == sb[f], f
+    # explicit extreme settings as well
+    b.set_tune(sched_chunk=32, list_wg_per_cu=1)
+    a.set_tune(sched_chunk=1024, list_wg_per_cu=64)
+    a.step_lts(10.0, 2), b.step_lts(10.0, 2)
+    assert _same(a, b)
