@@ -38,15 +38,15 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
 
 # HBM bytes per unit of work (element reconstruction, element predictor): the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE of the profiled LTS pass's launches on
-# the 80k vortex mesh at M=2, scaled by what the same counters read for a plain
+# the 80k vortex mesh at M=2 (autotuned launch settings), scaled by what the same counters read for a plain
 # 256 MiB copy (FETCH x2.0, WRITE x1.0), divided by the units those launches
 # processed. Valid only for the kernel source they were taken on (sha256 of
 # kernels.hip); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    "k_reconstruct": {"bytes_per_unit": 1371, "source_sha256":
-                      "70ee28ec58bfb32fb71cebe12fd47cdccecc3c3284938a8ccfda3d323e8d6bb7"},
+    "k_reconstruct": {"bytes_per_unit": 1037, "source_sha256":
+                      "61f79d1a2868ade060bb32bc231d5ea0309e270f648fada81c7e2894885db462"},
     "k_predict": {"bytes_per_unit": 1502, "source_sha256":
-                  "70ee28ec58bfb32fb71cebe12fd47cdccecc3c3284938a8ccfda3d323e8d6bb7"},
+                  "61f79d1a2868ade060bb32bc231d5ea0309e270f648fada81c7e2894885db462"},
 }
 
 
