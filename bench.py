@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -40,13 +41,14 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
 # rocprofv3 FETCH_SIZE and WRITE_SIZE of the profiled LTS pass's launches on
 # the 80k vortex mesh at M=2 (autotuned launch settings), scaled by what the same counters read for a plain
 # 256 MiB copy (FETCH x2.0, WRITE x1.0), divided by the units those launches
-# processed. Valid only for the kernel source they were taken on (sha256 of
-# kernels.hip); otherwise traffic is reported null.
+# processed. Valid only for the kernel code they were taken on (sha256 of
+# kernels.hip with comments and whitespace removed); otherwise traffic is
+# reported null.
 MEASURED_TRAFFIC = {
     "k_reconstruct": {"bytes_per_unit": 1037, "source_sha256":
-                      "61f79d1a2868ade060bb32bc231d5ea0309e270f648fada81c7e2894885db462"},
+                      "758c10009d6d53aa85c095400e09bb7389f88c5cd4c676a14b73e68be18498cd"},
     "k_predict": {"bytes_per_unit": 1502, "source_sha256":
-                  "61f79d1a2868ade060bb32bc231d5ea0309e270f648fada81c7e2894885db462"},
+                  "758c10009d6d53aa85c095400e09bb7389f88c5cd4c676a14b73e68be18498cd"},
 }
 
 
@@ -286,8 +288,9 @@ def main():
         "predict": p1["predictor_evals"] - p0["predictor_evals"],
         "patch": p1["patches"] - p0["patches"],
     }
-    with open(KERNEL_SOURCE, "rb") as f:
-        source_sha = hashlib.sha256(f.read()).hexdigest()
+    with open(KERNEL_SOURCE) as f:
+        code = re.sub(r"//[^\n]*", " ", re.sub(r"/\*.*?\*/", " ", f.read(), flags=re.S))
+    source_sha = hashlib.sha256(" ".join(code.split()).encode()).hexdigest()
 
     def traffic(kernel, units_per_launch):
         m = MEASURED_TRAFFIC.get(kernel)

@@ -7,7 +7,9 @@
 //   k_node        node solver NS_cs (eqs. eqnNScs, eqn.NScs.weights, eqn.dtau,
 //                 NodesVel) and node motion (eq. eqn.newVertex)
 //   k_patch       flux through every space-time patch swept by a moved edge
-//                 (eqs. eqn.spacetimenodes, G_ij, eqn.rusanov, A_n^V, eqn.STint)
+//                 (eqs. eqn.spacetimenodes, G_ij, eqn.STint) with the Rusanov
+//                 (eqs. eqn.rusanov, A_n^V), Osher-type (eqs. eqn.osher,
+//                 eqn.path) or HLL flux
 //   k_update      memory variables (eq. eqn.Qm2 and the geometric memory) and
 //                 the one-step update (eq. PDEfinal) with the GCL check (eqn.gcl)
 //   k_reconstruct virtual projection of the stencils (eqs. eqn.virtGeom,
@@ -16,14 +18,21 @@
 //   k_predict     space-time Galerkin predictor of the PDE and of the mesh ODE
 //                 (eqs. timeTransf .. newVertPos)
 // Every write target has a single writer per kernel: no atomics on state.
+// A macro step adds the per-instance tick lengths and levels (k_min_dt,
+// k_macro_setup, k_levels) and its end (k_macro_end); instances of a batch
+// (independent meshes) keep their own time and tick length (Inst).
 //
 // Lane mappings (64-wide wavefronts):
 //   k_reconstruct: 8 lanes per element, lane s solves stencil s (s < 7), lane 7
-//                  computes the CFL step; the WENO sum is a 3-step butterfly.
-//   k_predict:     G lanes per element (G >= nb), lane m owns spatial node m for
-//                  all time nodes; spatial derivatives read the other nodes of the
-//                  same time slice from LDS.
+//                  computes the CFL step; the WENO sum is a 3-step butterfly;
+//                  the rows of a stencil are software-pipelined.
+//   k_predict:     nb lanes per element, floor(64/nb) elements per wavefront,
+//                  lane m owns spatial node m for all time nodes; spatial
+//                  derivatives read the other nodes of the same time slice
+//                  from LDS, ordered within the wavefront.
+//   k_sched:       8 lanes per element over its scheduling stencil.
 //   others:        one lane per node, edge or element.
+// Blocks are renumbered so that each XCD works on a contiguous index range.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -606,7 +615,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
     const int idx = base + slot;
     const int i = !spare && idx < nitems ? (use_list ? d.act_list[idx] : idx) : -1;
     const int st = i >= 0 ? d.ts[i].step : 0;
-    const bool live = st > 0;           // uniform across the G lanes of the element
+    const bool live = st > 0;           // uniform across the lanes of the element
     const bool act = live && node;
     if (live && m == 0) wave_count(&d.scal->n_pred);
     const double dt = live ? double(st) * elem_delta(d, i) : 1.0;
