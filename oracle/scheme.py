@@ -38,6 +38,13 @@ design notes of the repository):
       Rusanov speed taken pointwise with the unnormalised normal.
   R9  memory variables are inflow-positive: Q^M_L -= G, Q^M_R += G, and
       |T'| Q' = |T| Q + Q^M; H^M tracks the space-time normal the same way.
+  R11 Osher-type flux: 3 Gauss-Legendre points on the straight path; |A| by
+      Sylvester's formula over the three distinct ALE wave speeds.
+  R19 free local time steps (levels = 0, the paper's own LTS with each element
+      at its CFL step, eq. eqn.timestep): the interval to the target time is one
+      macro step of 2^30 ticks and an element steps floor(dt_CFL / delta) ticks
+      (no power of two, no alignment), at most to the end of the interval; the
+      update criterion eq. eqn.WENOupdate is then exact integer arithmetic.
 """
 from __future__ import annotations
 
@@ -56,7 +63,7 @@ class Config:
     M: int = 2
     gamma: float = 1.4
     cfl: float = 0.5
-    levels: int = 1                   # L; 1 = global time stepping
+    levels: int = 1                   # L; 1 = global time stepping; 0 = free steps (FREE_TICKS)
     n_picard: int = 0                 # 0 -> M+1
     mesh_velocity: object = "lagrangian"   # "lagrangian" (V=v), "eulerian" (V=0) or callable V(x,y,t)
     weno_eps: float = 1e-14
@@ -390,6 +397,12 @@ FLUXES = {"rusanov": rusanov_flux, "osher": osher_flux, "hll": hll_flux}
 BC_TRANSMISSIVE = 1
 BC_SLIP = 2
 
+# Free local time steps (paper-literal LTS, eq. eqn.timestep per element): one
+# macro step covers the whole interval in 2^30 ticks, and each element steps
+# floor(dt_CFL / delta) ticks, so the update criterion stays integer arithmetic
+# while every step is within 2^-30 of the interval below its CFL step.
+FREE_TICKS = 1 << 30
+
 
 def mirror_state(q, N):
     """Slip-wall ghost state: normal momentum reflected about the face normal."""
@@ -499,7 +512,7 @@ class Solver:
                         QM=np.zeros((NE, 4)), HM=np.zeros((NE, 3)), wnod=np.zeros((NE, nb, 4)),
                         avg=np.zeros((NE, M + 1, 4)), trace=np.zeros((NE, 3, nG, M + 1, 4)),
                         vvel=np.zeros((NE, 3, M + 1, 2)), X=X, nk=np.zeros(NV, np.int64))
-        self.st.N = 1 << (cfg.levels - 1)
+        self.st.N = FREE_TICKS if cfg.levels == 0 else 1 << (cfg.levels - 1)
         self.wall_n, self.wall_pin = wall_constraints(self.topo, X)
         # pre-processing (Sec. 2.6): first reconstruction without projection and first CFL step
         allel = np.arange(NE)
@@ -553,9 +566,21 @@ class Solver:
 
     def _level_step(self, elems):
         """Dyadic step in ticks (R2): largest power of two p <= N with p*delta <= dt_CFL,
-        limited by the alignment of the current tick; at least 1 (overshoot counted)."""
+        limited by the alignment of the current tick; at least 1 (overshoot counted).
+        Free steps (levels = 0, R19): floor(dt_CFL / delta) ticks, at most the ticks
+        left to the end of the interval."""
         st = self.st
         out = np.zeros(elems.size, np.int64)
+        if self.cfg.levels == 0:
+            for t, i in enumerate(elems):
+                left = st.N - int(st.n[i])
+                q = st.dtcfl[i] / st.delta
+                p = left if q >= left else int(np.floor(q))
+                if p < 1:
+                    st.cfl_overshoots += 1
+                    p = 1
+                out[t] = p
+            return out
         for t, i in enumerate(elems):
             p = st.N
             while p > 1 and p * st.delta > st.dtcfl[i]:
@@ -582,8 +607,12 @@ class Solver:
     # -- macro-step boundary -----------------------------------------------------
     def macro_begin(self, t_end):
         st = self.st
-        delta = float(st.dtcfl.min())
-        delta = min(delta, (t_end - st.T) / st.N)
+        if self.cfg.levels == 0:
+            # free steps: one macro step spans the whole interval in FREE_TICKS ticks
+            delta = (t_end - st.T) / st.N
+        else:
+            delta = float(st.dtcfl.min())
+            delta = min(delta, (t_end - st.T) / st.N)
         st.delta = delta
         allel = np.arange(self.topo.n_elems)
         st.n[:] = 0

@@ -69,18 +69,18 @@ def _swirl(x, y, t):
             -0.2 + 0.2 * np.cos(0.8 * x + 0.5 * t) * np.sin(0.6 * y))
 
 
-@pytest.mark.parametrize("M", [1, 2])
-def test_free_stream_on_deforming_mesh_lts(graded, M):
+@pytest.mark.parametrize("M,levels", [(1, 3), (2, 3), (2, 0)])
+def test_free_stream_on_deforming_mesh_lts(graded, M, levels):
     """A constant state stays constant on a mesh deformed by a prescribed
-    velocity, with hanging nodes in time (3 levels): the discrete GCL
-    (eq. eqn.gcl) holds to round-off."""
+    velocity, with hanging nodes in time (3 levels, or free steps): the discrete
+    GCL (eq. eqn.gcl) holds to round-off."""
     Q = np.array([1.2, 0.3, -0.1, 2.7])
     Q0 = np.tile(Q, (graded.n_elems, 1))
-    cfg = Config(M=M, levels=3, mesh_velocity=_swirl)
+    cfg = Config(M=M, levels=levels, mesh_velocity=_swirl)
     s = Solver(graded.nodes, graded.tris, Q0, cfg)
-    s.macro_begin(10.0)
-    assert len(np.unique(s.st.s)) >= 2                    # several levels in use
-    s.run(10.0, max_macro_steps=2)
+    s.macro_begin(10.0 if levels else 0.05)
+    assert len(np.unique(s.st.s)) >= 2                    # several step sizes in use
+    s.run(10.0 if levels else 0.05, max_macro_steps=2)
     st = s.st
     assert st.updates < st.cycles * graded.n_elems       # genuinely local steps
     assert np.abs(st.Q - Q).max() < 1e-13
@@ -88,13 +88,14 @@ def test_free_stream_on_deforming_mesh_lts(graded, M):
     assert np.abs(st.X - graded.nodes).max() > 1e-3      # the mesh really moved
 
 
-def test_conservation_and_gcl_every_cycle():
+@pytest.mark.parametrize("levels,t_end", [(3, 1.0), (0, 0.03)])
+def test_conservation_and_gcl_every_cycle(levels, t_end):
     """sum(|T|Q + Q^M) + boundary outflow is constant at every cycle (memory
     variables keep the scheme conservative, Sec. 2.5)."""
     mesh, Q0 = vortex_case(1200, seed=4)
-    s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=2, levels=3))
+    s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=2, levels=levels))
     c0 = s.conserved_total()
-    s.macro_begin(1.0)
+    s.macro_begin(t_end)
     ncyc = 0
     while (s.st.n < s.st.N).any():
         s.cycle()
@@ -188,3 +189,26 @@ def test_vortex_convergence_order():
         hs.append(np.sqrt(s.st.A.mean()))
     order = np.log(errs[0] / errs[1]) / np.log(hs[0] / hs[1])
     assert order > 2.3, (errs, order)
+
+
+def test_free_steps_respect_cfl_and_save_updates():
+    """Free local steps (levels = 0): every element's step stays within its own
+    CFL bound (eq. eqn.timestep) and the run reaches the target time exactly;
+    on a graded mesh it needs fewer element updates than dyadic levels, which
+    need fewer than global time stepping."""
+    mesh, Q0 = vortex_case(900, seed=5)
+    upd = {}
+    for L in (0, 3, 1):
+        s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=2, levels=L))
+        if L == 0:
+            s.macro_begin(0.1)
+            while (s.st.n < s.st.N).any():
+                live = s.st.n < s.st.N
+                assert (s.st.s[live] * s.st.delta <= s.st.dtcfl[live]).all()
+                s.cycle()
+            s.st.T = s.st.T + s.st.N * s.st.delta
+            assert s.st.T == 0.1
+        else:
+            s.run(0.1)
+        upd[L] = s.st.updates
+    assert upd[0] < upd[3] < upd[1], upd
