@@ -66,7 +66,8 @@ typedef struct {
   int32_t flux;          /* ADER_FLUX_*: numerical flux on the space-time patches       */
   double gamma;          /* ratio of specific heats (eq. eqn.eos)                      */
   double cfl;            /* CFL number of eq. eqn.timestep, (0, 0.5]                   */
-  int32_t lts_levels;    /* L in 1..8: dyadic levels used by ader_step_lts             */
+  int32_t lts_levels;    /* L in 1..8: dyadic levels used by ader_step_lts;
+                            0: free local steps (see ader_step_lts)                    */
   int32_t n_picard;      /* Picard sweeps of the predictor; 0 -> M+1                   */
   int32_t mesh_velocity; /* 0 = Lagrangian (V = v), 1 = Eulerian (V = 0)               */
   double weno_eps;       /* epsilon of the WENO weights (paper: 1e-14)                 */
@@ -77,7 +78,7 @@ typedef struct {
 typedef struct {
   int64_t element_updates; /* sum over cycles of the active-set size                   */
   int64_t cycles;          /* cycles run (a cycle = one pass of the update criterion)  */
-  int64_t macro_steps;     /* dyadic macro steps completed                             */
+  int64_t macro_steps;     /* macro steps completed (free steps: one per target time)  */
   int64_t cfl_overshoots;  /* element steps longer than their CFL bound (level capped) */
   double max_gcl_residual; /* max |closure of the space-time volume| / (|T|+|T'|)      */
   double t;                /* common time of all elements (they meet at macro steps);
@@ -138,7 +139,14 @@ int ader_step_gts(ader_ctx* ctx, double t_target, int32_t max_steps, ader_stats*
  * (<= 0: no limit).  A macro step has 2^(L-1) ticks of length delta = the
  * smallest CFL step at its start; each element steps 2^(L-1-level) ticks
  * under the update criterion of eq. eqn.WENOupdate over its scheduling
- * stencil; all elements meet again at the end of the macro step. */
+ * stencil; all elements meet again at the end of the macro step.
+ * lts_levels == 0 (free local steps, Sec. 2.3 with each element at its own CFL
+ * step of eq. eqn.timestep): the whole interval to t_target is one macro step
+ * of 2^30 ticks of length (t_target - t) / 2^30; an element steps
+ * floor(dt_CFL / delta) ticks, at most to the end of the interval (at least
+ * one: counted as a CFL overshoot, so t_target - t must stay well below 2^30
+ * CFL steps).  Cycles run in batches of 16 with a host check after each;
+ * `cycles` counts the launched ones.  Results match the oracle's reading. */
 int ader_step_lts(ader_ctx* ctx, double t_target, int32_t max_macro_steps, ader_stats* st);
 
 /* Current time of the first n instances into host memory (synchronises). */
@@ -158,10 +166,10 @@ typedef struct {
 int ader_set_tune(ader_ctx* ctx, const ader_tune* tune);
 
 /* Autotuner: from a snapshot of the current device state, times
- * `trial_macro_steps` LTS macro steps (levels of the configuration, no target
- * time) for each candidate setting, one coordinate at a time (scheduler chunk
- * in {rule, 64, 128, 256, 512, 1024}, then workgroups per CU in {all, 4, 8,
- * 16, 32}), keeps the fastest, and restores the state, so the simulation does
+ * `trial_macro_steps` LTS macro steps (levels of the configuration, 3 under
+ * free steps; no target time) for each candidate setting, one coordinate at a
+ * time (scheduler chunk in {rule, 64, 128, 256, 512, 1024}, then workgroups
+ * per CU in {all, 4, 8, 16, 32}), keeps the fastest, and restores the state, so the simulation does
  * not advance.  Allocates a device copy of the workspace for the duration
  * (hipMalloc).  The choice is written to *chosen when not null. */
 int ader_autotune(ader_ctx* ctx, int32_t trial_macro_steps, ader_tune* chosen);
@@ -211,7 +219,8 @@ int ader_debug_dump(ader_ctx* ctx, int32_t what, void* host, size_t bytes);
 int ader_debug_inject(ader_ctx* ctx, int32_t what, const void* host, size_t bytes);
 
 /* Test hook: run `n` cycles of the current macro step (no macro boundary
- * handling), or begin a macro step (levels and predictors) toward t_end. */
+ * handling), or begin a macro step (levels and predictors) toward t_end with
+ * `levels` dyadic levels (0: free steps, 2^30 ticks). */
 int ader_debug_cycles(ader_ctx* ctx, int32_t n);
 int ader_debug_macro_begin(ader_ctx* ctx, double t_end, int32_t levels);
 

@@ -33,6 +33,7 @@ struct ader_ctx {
   hipGraphExec_t gexec = nullptr;
   double g_t = 0.0;
   int g_N = 0;
+  hipGraphExec_t gcyc = nullptr;    // FREE_BATCH cycles and the status count
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ADER_K_COUNT];
@@ -234,30 +235,64 @@ int issue_macro(ader_ctx* c, double t_end, int N, hipStream_t st) {
   return 0;
 }
 
-int ensure_graph(ader_ctx* c, double t_end, int N) {
-  if (c->gexec && c->g_t == t_end && c->g_N == N) return 0;
-  if (c->gexec) {
-    HIPCHK(c, hipGraphExecDestroy(c->gexec));
-    c->gexec = nullptr;
+// Cycles per host check of the free-step run.
+constexpr int FREE_BATCH = 16;
+
+// n cycles, then the count of elements short of tick N.
+int issue_cycle_batch(ader_ctx* c, int n, hipStream_t st) {
+  int r;
+  if ((r = issue_cycles(c, n, st))) return r;
+  LCHK(c, timed(c, ADER_K_STATUS, st, [&] { return aw::launch_status(c->dev, st); }));
+  return 0;
+}
+
+// Capture what `issue` queues into one executable graph.
+template <class F>
+int capture(ader_ctx* c, hipGraphExec_t* out, F issue) {
+  if (*out) {
+    HIPCHK(c, hipGraphExecDestroy(*out));
+    *out = nullptr;
   }
   if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-  const int r = issue_macro(c, t_end, N, c->cap);
+  const int r = issue(c->cap);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (r || e != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
     return r ? r : hip_fail(c, int(e), "hipStreamEndCapture");
   }
-  const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) {
-    c->gexec = nullptr;
+    *out = nullptr;
     return hip_fail(c, int(ei), "hipGraphInstantiate");
   }
+  return 0;
+}
+
+// Drop the captured graphs (launch settings or the step mode changed).
+void drop_graphs(ader_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->gcyc) (void)hipGraphExecDestroy(c->gcyc);
+  c->gexec = nullptr;
+  c->gcyc = nullptr;
+}
+
+int ensure_graph(ader_ctx* c, double t_end, int N) {
+  if (c->gexec && c->g_t == t_end && c->g_N == N) return 0;
+  int r = capture(c, &c->gexec, [&](hipStream_t s) { return issue_macro(c, t_end, N, s); });
+  if (r) return r;
   c->g_t = t_end;
   c->g_N = N;
   return 0;
+}
+
+// The step mode the kernels see: free steps change how levels are chosen and
+// how tick lengths are set. Captured graphs hold the mode they were made with.
+void set_free(ader_ctx* c, bool free_steps) {
+  if (c->dev.free_steps != int(free_steps)) drop_graphs(c);
+  c->dev.free_steps = free_steps;
 }
 
 // Macro steps of N ticks until t_target; returns 0 or an error code. One host
@@ -266,6 +301,7 @@ int ensure_graph(ader_ctx* c, double t_end, int N) {
 int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
+  set_free(c, false);
   aw::Scal s;
   int r;
   LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
@@ -298,6 +334,48 @@ int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
       LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
       if ((r = read_scal(c, s))) return r;
     }
+    c->macro_steps++;
+  }
+  return 0;
+}
+
+// Free local steps: the interval to t_target is one macro step of FREE_TICKS
+// ticks, run in batches of FREE_BATCH cycles with a status read after each
+// until every element has reached the end of the interval.
+int run_free(ader_ctx* c, double t_target, int max_macro) {
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
+  set_free(c, true);
+  const int N = aw::FREE_TICKS;
+  const bool graph = c->graphs && !c->prof;
+  aw::Scal s;
+  int r;
+  LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
+  if ((r = read_scal(c, s))) return r;
+  for (int k = 0; max_macro <= 0 || k < max_macro; ++k) {
+    if ((r = check_err(c, s))) return r;
+    if (s.n_open == 0) break;
+    if ((r = issue_macro_begin(c, t_target, N, c->stream))) return r;
+    long long last = -1;
+    for (;;) {
+      if (graph) {
+        if (!c->gcyc &&
+            (r = capture(c, &c->gcyc, [&](hipStream_t st) { return issue_cycle_batch(c, FREE_BATCH, st); })))
+          return r;
+        HIPCHK(c, hipGraphLaunch(c->gcyc, c->stream));
+      } else if ((r = issue_cycle_batch(c, FREE_BATCH, c->stream))) {
+        return r;
+      }
+      c->cycles += FREE_BATCH;
+      if ((r = read_scal(c, s))) return r;
+      if ((r = check_err(c, s))) return r;
+      if (s.n_unfinished == 0) break;
+      if ((long long)s.updates == last) return fail(c, ADER_E_DEADLOCK, "no element satisfies the update criterion");
+      last = (long long)s.updates;
+    }
+    LCHK(c, aw::launch_macro_end(c->dev, 0, c->stream));
+    LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
+    if ((r = read_scal(c, s))) return r;
     c->macro_steps++;
   }
   return 0;
@@ -519,7 +597,7 @@ int ader_create(const ader_config* cfg, void* hip_stream, ader_ctx** out) {
   if (cfg->flux < ADER_FLUX_RUSANOV || cfg->flux > ADER_FLUX_HLL) return ADER_E_ARG;
   if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return ADER_E_ARG;
   if (!(cfg->gamma > 1.0)) return ADER_E_ARG;
-  if (cfg->lts_levels < 1 || cfg->lts_levels > 8) return ADER_E_ARG;
+  if (cfg->lts_levels < 0 || cfg->lts_levels > 8) return ADER_E_ARG;
   if (cfg->weno_r != 8.0) return ADER_E_ARG;
   if (cfg->mesh_velocity != 0 && cfg->mesh_velocity != 1) return ADER_E_ARG;
   ader_ctx* c = new (std::nothrow) ader_ctx();
@@ -689,7 +767,8 @@ int ader_step_gts(ader_ctx* c, double t_target, int32_t max_steps, ader_stats* s
 
 int ader_step_lts(ader_ctx* c, double t_target, int32_t max_macro_steps, ader_stats* st) {
   if (!c) return ADER_E_ARG;
-  int r = run_macro(c, t_target, max_macro_steps, 1 << (c->cfg.lts_levels - 1));
+  int r = c->cfg.lts_levels == 0 ? run_free(c, t_target, max_macro_steps)
+                                 : run_macro(c, t_target, max_macro_steps, 1 << (c->cfg.lts_levels - 1));
   if (r) return r;
   return st ? ader_get_stats(c, st) : ADER_OK;
 }
@@ -799,10 +878,11 @@ int ader_debug_cycles(ader_ctx* c, int32_t n) {
 }
 
 int ader_debug_macro_begin(ader_ctx* c, double t_end, int32_t levels) {
-  if (!c || levels < 1 || levels > 8) return ADER_E_ARG;
+  if (!c || levels < 0 || levels > 8) return ADER_E_ARG;
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  set_free(c, levels == 0);
   LCHK(c, aw::launch_open(c->dev, t_end, c->stream));
-  int r = issue_macro_begin(c, t_end, 1 << (levels - 1), c->stream);
+  int r = issue_macro_begin(c, t_end, levels == 0 ? aw::FREE_TICKS : 1 << (levels - 1), c->stream);
   if (r) return r;
   aw::Scal s;
   if ((r = read_scal(c, s))) return r;
@@ -837,10 +917,8 @@ int ader_set_tune(ader_ctx* c, const ader_tune* t) {
   if (t->list_wg_per_cu < 0 || t->list_wg_per_cu > 64) return ADER_E_ARG;
   c->dev.sched_chunk = t->sched_chunk;
   c->dev.list_wg_per_cu = t->list_wg_per_cu;
-  if (c->gexec) {
-    HIPCHK(c, hipGraphExecDestroy(c->gexec));
-    c->gexec = nullptr;
-  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graphs(c);
   return ADER_OK;
 }
 
@@ -849,6 +927,7 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   const bool prof = c->prof;
   const int64_t cycles = c->cycles, macro = c->macro_steps;
+  set_free(c, false);
   void* snap = nullptr;
   HIPCHK(c, hipMalloc(&snap, c->ws_bytes));
   c->prof = false;
@@ -871,7 +950,8 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
     int rr;
     if ((rr = restore())) return rr;
     const double far = 1e300;
-    const int N = 1 << (c->cfg.lts_levels - 1);
+    // free steps are tuned on 3 dyadic levels: the settings only group work
+    const int N = c->cfg.lts_levels > 0 ? 1 << (c->cfg.lts_levels - 1) : 4;
     LCHK(c, aw::launch_open(c->dev, far, c->stream));
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int k = 0; k < trials; ++k)
@@ -918,10 +998,7 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
       r = hip_fail(c, int(he), "hipStreamSynchronize");
       break;
     }
-    if (c->gexec) {
-      (void)hipGraphExecDestroy(c->gexec);
-      c->gexec = nullptr;
-    }
+    drop_graphs(c);
     if (chosen) {
       chosen->sched_chunk = bc;
       chosen->list_wg_per_cu = bw;
@@ -958,7 +1035,7 @@ const char* ader_last_error(const ader_ctx* c) {
 void ader_destroy(ader_ctx* c) {
   if (!c) return;
   if (c->bound) (void)hipStreamSynchronize(c->stream);
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  drop_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   for (int k = 0; k < ADER_K_COUNT; ++k)
     for (auto& p : c->ev[k]) {

@@ -75,6 +75,10 @@ struct Scal {
 
 enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8, ERR_DT = 16 };
 
+// Free local time steps: the interval to the target time is one macro step of
+// FREE_TICKS ticks; every element steps floor(dt_CFL / delta) ticks.
+constexpr int FREE_TICKS = 1 << 30;
+
 // Per-element storage.  Data that other elements gather (vertices, average,
 // area, the predictor's time-node averages and vertex velocities) sits in one
 // contiguous record per element, so a neighbour costs a few cache lines
@@ -104,6 +108,7 @@ struct Dev {
   // workgroup, and workgroups per CU of the list-driven reconstruction and
   // predictor launches (0: one workgroup per slice of the whole element range)
   int sched_chunk, list_wg_per_cu, n_cu;
+  int free_steps;   // 1: free local steps (one macro step of FREE_TICKS to the target)
   Scal* scal;
   Inst* inst;                        // [K]
   const int *e_inst, *v_inst;        // instance of each element [NE] and node [NV]

@@ -192,9 +192,10 @@ __device__ inline void numerical_flux(int flux, const Tables* tb, const double q
   }
 }
 
-// (a - b) / step for a power-of-two step, exactly
+// (a - b) / step: exact for the power-of-two steps of dyadic levels, a
+// correctly rounded division for free steps
 __device__ inline double tick_ratio(double a_minus_b, int step) {
-  return ldexp(a_minus_b, -__builtin_ctz(step));
+  return (step & (step - 1)) == 0 ? ldexp(a_minus_b, -__builtin_ctz(step)) : a_minus_b / double(step);
 }
 
 template <int M>
@@ -315,7 +316,19 @@ __device__ inline double cfl_ratio(const double X[6], const double Q[4], double 
   return dd / lam;
 }
 
-__device__ inline int level_step(double dtcfl, double delta, int N, int tick, int* over) {
+// Step in ticks from tick `tick` of a macro step of N ticks of length delta.
+// Dyadic levels: the largest power of two p <= N with p*delta <= dt_CFL,
+// limited by the alignment of the current tick. Free steps: floor(dt_CFL /
+// delta) ticks, at most the ticks left. At least one tick (overshoot flagged).
+__device__ inline int level_step(double dtcfl, double delta, int N, int tick, int free_steps,
+                                 int* over) {
+  if (free_steps) {
+    const int left = N - tick;
+    const double q = dtcfl / delta;
+    const int p = q >= double(left) ? left : int(floor(q));
+    *over = p < 1;
+    return p < 1 ? 1 : p;
+  }
   int p = N;
   while (p > 1 && double(p) * delta > dtcfl) p >>= 1;
   *over = double(p) * delta > dtcfl;
@@ -556,7 +569,7 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
           d.ts[i].step = 0;
         } else {
           int over;
-          d.ts[i].step = level_step(dt, delta, N, nt, &over);
+          d.ts[i].step = level_step(dt, delta, N, nt, d.free_steps, &over);
           if (over) atomicAdd(&d.scal->overshoots, 1ull);
         }
       }
@@ -911,7 +924,7 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
   const int end = min(NE, begin + chunk);
   for (int base = begin; base < end; base += PER_PASS) {
     const int i = base + (threadIdx.x >> 3);
-    int fut = 0, mx = 0, mn = 1 << 30;
+    int fut = 0, mx = 0, mn = FREE_TICKS;   // no tick count exceeds FREE_TICKS
     bool unf = false;
     if (i < end) {
       const TickStep me = d.ts[i];
@@ -926,7 +939,7 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
           for (int u = 0; u < 4; ++u) jx[u] = r + 8 * u < r1 ? d.sched_idx[r + 8 * u] : -1;
           TickStep o[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) o[u] = jx[u] >= 0 ? d.ts[jx[u]] : TickStep{0, 1 << 29};
+          for (int u = 0; u < 4; ++u) o[u] = jx[u] >= 0 ? d.ts[jx[u]] : TickStep{0, FREE_TICKS};
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             mx = max(mx, o[u].tick);
@@ -1274,7 +1287,7 @@ __global__ void __launch_bounds__(TPB) k_macro_setup(Dev d, double t_end, int N)
     }
     const double dmin = __longlong_as_double((long long)in->min_dt_bits);
     const double rest = (t_end - in->T) / double(N);
-    in->delta = fmin(dmin, rest);
+    in->delta = d.free_steps ? rest : fmin(dmin, rest);
     if (!(in->delta > 0.0)) set_err(d, ERR_DT);
   }
 }
@@ -1291,7 +1304,7 @@ __global__ void __launch_bounds__(TPB) k_levels(Dev d) {
       if (delta > 0.0) {
         int over;
         me.tick = 0;
-        me.step = level_step(d.dtcfl[i], delta, N, 0, &over);
+        me.step = level_step(d.dtcfl[i], delta, N, 0, d.free_steps, &over);
         if (over) atomicAdd(&d.scal->overshoots, 1ull);
       } else {
         me.tick = N;

@@ -30,7 +30,8 @@ def _cases():
     return cases
 
 
-@pytest.mark.parametrize("levels,t_target,max_steps", [(3, 10.0, 3), (3, 0.02, 0), (1, 0.003, 0)])
+@pytest.mark.parametrize("levels,t_target,max_steps", [(3, 10.0, 3), (3, 0.02, 0), (1, 0.003, 0),
+                                                      (0, 0.02, 0)])
 def test_batch_matches_each_instance_alone(levels, t_target, max_steps):
     from paper_1408_3719_amd import Config, Solver
     cases = _cases()
@@ -38,7 +39,7 @@ def test_batch_matches_each_instance_alone(levels, t_target, max_steps):
     print(f"batch of {len(cases)} instances, {tris.shape[0]} triangles, L={levels}", flush=True)
     cfg = Config(M=2, levels=levels)
     g = Solver(nodes, tris, bedges, Q0, cfg, instance_first=first)
-    st = g.step_lts(t_target, max_steps) if levels > 1 else g.step_gts(t_target, max_steps)
+    st = g.step_lts(t_target, max_steps) if levels != 1 else g.step_gts(t_target, max_steps)
     Q, X, t = g.download()
     T = g.instance_times()
     node_off = np.cumsum([0] + [m.nodes.shape[0] for m, _ in cases])
@@ -56,7 +57,7 @@ def test_batch_matches_each_instance_alone(levels, t_target, max_steps):
         assert np.allclose(t[e0:e1], o.st.T, rtol=1e-13)
         # the same instance alone on the GPU: identical bits
         a = Solver(mesh.nodes, mesh.tris, mesh.bedges, q0, cfg)
-        sa = a.step_lts(t_target, max_steps) if levels > 1 else a.step_gts(t_target, max_steps)
+        sa = a.step_lts(t_target, max_steps) if levels != 1 else a.step_gts(t_target, max_steps)
         Qa, Xa, _ = a.download()
         assert np.array_equal(Qa, Q[e0:e1]) and np.array_equal(Xa, X[v0:v1]), k
         assert sa["t"] == T[k]

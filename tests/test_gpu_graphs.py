@@ -76,3 +76,20 @@ def test_autotune_keeps_state_and_results():
     a.set_tune(sched_chunk=1024, list_wg_per_cu=64)
     a.step_lts(10.0, 2), b.step_lts(10.0, 2)
     assert _same(a, b)
+
+
+@pytest.mark.parametrize("name", ["vortex_M2", "explosion_M2"])
+def test_free_steps_graph_equals_eager(name):
+    """Free local steps: batches of cycles replayed from one captured graph,
+    over three successive target times, against launches one by one."""
+    make, M = CASES[name]
+    mesh, Q0 = make()
+    g = _gpu_solver(mesh, Q0, M, 0)
+    e = _gpu_solver(mesh, Q0, M, 0)
+    e.set_graphs(False)
+    for k, t in enumerate((0.004, 0.01, 0.02)):
+        sg, se = g.step_lts(t), e.step_lts(t)
+        assert _same(g, e), k
+        for f in COUNTERS + ("t", "cfl_overshoots"):
+            assert sg[f] == se[f], (k, f)
+        assert sg["t"] == t and sg["macro_steps"] == k + 1

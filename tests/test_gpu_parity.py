@@ -200,3 +200,58 @@ def test_osher_single_cycles_parity():
         scale = np.abs(o.st.A[:, None] * o.st.Q).max()
         assert np.abs(g.dump("QM").T - o.st.QM).max() < TOL * scale, c
         assert (rel_groups(g.dump("Q").T, o.st.Q) < TOL).all(), c
+
+
+FREE_CASES = [("sod_M2", 0.01), ("vortex_M2", 0.1), ("vortex_M3", 0.05), ("explosion_M2", 0.01)]
+
+
+@pytest.mark.parametrize("name,t_end", FREE_CASES)
+def test_free_steps_end_to_end_parity(name, t_end):
+    """Free local steps (levels = 0): one macro step of 2^30 ticks to t_end,
+    every element at floor(dt_CFL / delta) ticks; ticks, update counts and the
+    final time exact, states to the parity tolerance."""
+    make, M = CASES[name]
+    mesh, Q0 = make()
+    g = _gpu_solver(mesh, Q0, M, 0)
+    o = _oracle(mesh, Q0, M, 0)
+    stg = g.step_lts(t_end)
+    o.run(t_end)
+    Q, X, t = g.download()
+    print(f"{name} updates {stg['element_updates']} oracle cycles {o.st.cycles} "
+          f"launched {stg['cycles']}", flush=True)
+    assert stg["macro_steps"] == o.st.macro_steps == 1
+    assert stg["element_updates"] == o.st.updates
+    assert stg["cfl_overshoots"] == o.st.cfl_overshoots == 0
+    assert stg["cycles"] == 16 * -(-o.st.cycles // 16)      # launched in batches of 16
+    assert stg["t"] == o.st.T == t_end
+    assert (rel_groups(Q, o.st.Q) < TOL).all(), rel_groups(Q, o.st.Q)
+    assert np.abs(X - o.st.X).max() < TOL * _span(mesh)
+    assert (t == t_end).all()
+    assert stg["max_gcl_residual"] < 1e-13
+
+
+@pytest.mark.parametrize("name,t_end", [("vortex_M2", 0.1), ("explosion_M2", 0.01)])
+def test_free_steps_single_cycles_parity(name, t_end):
+    """Cycle by cycle through a free-step interval: ticks and steps (not powers
+    of two, no alignment) bit-exact, states and node motion to tolerance."""
+    make, M = CASES[name]
+    mesh, Q0 = make()
+    g = _gpu_solver(mesh, Q0, M, 0)
+    o = _oracle(mesh, Q0, M, 0)
+    g.debug_macro_begin(t_end, 0)
+    o.macro_begin(t_end)
+    assert g.dump("SCAL")[1] == o.st.delta
+    assert np.array_equal(g.dump("STEP"), o.st.s)
+    assert (o.st.s & (o.st.s - 1) != 0).any()               # genuinely free steps
+    span = _span(mesh)
+    for c in range(6):
+        o.cycle()
+        g.debug_cycles(1)
+        assert np.array_equal(g.dump("TICK"), o.st.n), c
+        assert np.array_equal(g.dump("STEP"), o.st.s), c
+        assert np.array_equal(g.dump("NTICK"), o.st.nk), c
+        assert (rel_groups(g.dump("Q").T, o.st.Q) < TOL).all(), c
+        assert np.abs(g.dump("X").T - o.st.X).max() < TOL * span, c
+        live = o.st.s > 0
+        tr = np.moveaxis(g.dump("TRACE"), -1, 0)
+        assert rel(tr[live], o.st.trace[live]) < TOL, c
