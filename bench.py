@@ -7,8 +7,8 @@ the fluid, WENO M=2, LTS with 3 levels, FP64.  One step = one LTS macro step
 (4 ticks: every element reaches the common time again).  value = element
 updates / wall time of the timed macro steps (state resident in HBM).
 
-Also reported: GTS on the same mesh over the same physical interval, the
-time-to-solution ratio, a per-kernel breakdown from HIP events recorded on
+Also reported: GTS and free local steps (every element at its own CFL step)
+on the same mesh over the same physical interval, the time-to-solution ratios, a per-kernel breakdown from HIP events recorded on
 the solver's stream, the roofline of the dominant kernel, and the CPU oracle
 timed on a bounded sample.
 
@@ -37,18 +37,19 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X, published
 PEAK_HBM_GBS = 8000.0              # MI355X HBM3E, published
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
 
-# HBM bytes per unit of work (element reconstruction, element predictor): the
-# rocprofv3 FETCH_SIZE and WRITE_SIZE of the profiled LTS pass's launches on
-# the 80k vortex mesh at M=2 (autotuned launch settings), scaled by what the same counters read for a plain
-# 256 MiB copy (FETCH x2.0, WRITE x1.0), divided by the units those launches
-# processed. Valid only for the kernel code they were taken on (sha256 of
-# kernels.hip with comments and whitespace removed); otherwise traffic is
-# reported null.
+# HBM bytes per unit of work (element reconstruction, element predictor) for
+# each persistent-grid setting of the list-driven kernels (workgroups per CU;
+# 0 = one grid over all elements): the rocprofv3 FETCH_SIZE and WRITE_SIZE of
+# the profiled LTS pass's launches on the 80k vortex mesh at M=2, scaled by
+# what the same counters read for a plain 256 MiB copy, divided by the units
+# those launches processed. Valid only for the kernel code they were taken on
+# (sha256 of kernels.hip with comments and whitespace removed); otherwise
+# traffic is reported null.
+TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
-    "k_reconstruct": {"bytes_per_unit": 1037, "source_sha256":
-                      "758c10009d6d53aa85c095400e09bb7389f88c5cd4c676a14b73e68be18498cd"},
-    "k_predict": {"bytes_per_unit": 1502, "source_sha256":
-                  "758c10009d6d53aa85c095400e09bb7389f88c5cd4c676a14b73e68be18498cd"},
+    "source_sha256": "4f29b36165920c3f41233d343353e082f9b07f08edd769c6f0388d6bc83b999b",
+    "k_reconstruct": {0: 1153, 4: 1116, 8: 1119, 16: 1079, 32: 1109},
+    "k_predict": {0: 1502, 4: 1502, 8: 1502, 16: 1502, 32: 1501},
 }
 
 
@@ -208,9 +209,13 @@ def main():
     ap.add_argument("--flux", choices=["rusanov", "osher", "hll"], default="rusanov")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: pick launch settings with the library's autotuner before timing")
+    ap.add_argument("--free", type=int, default=1,
+                    help="1: also run free local steps (levels = 0) over the timed interval")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=5000)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--traffic-sweep", action="store_true",
+                    help="repeat the profiled pass for every workgroups-per-CU setting (counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     a = ap.parse_args()
@@ -274,6 +279,29 @@ def main():
     g1 = s.stats()
     gts_updates = g1["element_updates"] - g0["element_updates"]
 
+    # ---- free local steps over the same interval (each element at its CFL step) --
+    free = None
+    if a.free:
+        f = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
+                   Config(M=a.M, levels=0, flux=a.flux))
+        if tune:
+            f.set_tune(sched_chunk=tune["sched_chunk"], list_wg_per_cu=tune["list_wg_per_cu"])
+        f.step_lts(T_a)
+        f0 = f.stats()
+        sync()
+        t0 = time.perf_counter()
+        f.step_lts(T_b)
+        sync()
+        t_free = time.perf_counter() - t0
+        f1 = f.stats()
+        fu = f1["element_updates"] - f0["element_updates"]
+        free = {"value": fu / t_free, "updates": fu, "seconds": t_free,
+                "cycles_launched": f1["cycles"] - f0["cycles"],
+                "cfl_overshoots": f1["cfl_overshoots"] - f0["cfl_overshoots"],
+                "updates_over_lts": fu / max(lts_updates, 1),
+                "time_over_lts": t_free / t_lts}
+        del f
+
     # ---- profiled LTS pass: per-kernel times from HIP events ----------------------
     s.upload_state(Q0, 0.0)
     s.step_lts(t_end, a.warmup)
@@ -293,11 +321,11 @@ def main():
     source_sha = hashlib.sha256(" ".join(code.split()).encode()).hexdigest()
 
     def traffic(kernel, units_per_launch):
-        m = MEASURED_TRAFFIC.get(kernel)
-        if (m is None or m["source_sha256"] != source_sha or a.M != 2 or a.workload != "vortex"
-                or a.flux != "rusanov"):
+        per = MEASURED_TRAFFIC.get(kernel, {}).get(tune["list_wg_per_cu"] if tune else 0)
+        if (per is None or MEASURED_TRAFFIC["source_sha256"] != source_sha or a.M != 2
+                or a.workload != "vortex" or a.flux != "rusanov"):
             return None
-        return m["bytes_per_unit"] * units_per_launch
+        return per * units_per_launch
 
     kname = {"recon": "k_reconstruct", "predict": "k_predict", "patch": "k_patch",
              "sched": "k_sched", "node": "k_node", "update": "k_update"}
@@ -325,6 +353,27 @@ def main():
                     frac=achieved / PEAK_HBM_GBS, traffic=None, kernel=kname.get(dom, dom),
                     bytes_per_unit=per, avg_launch_us=avg_s * 1e6)
     total_ms = sum(v[0] for v in kt.values())
+
+    if a.traffic_sweep:
+        # the profiled pass again for every persistent-grid setting of the
+        # list-driven kernels, in this order, one JSON line each (counter runs)
+        chunk = tune["sched_chunk"] if tune else 0
+        for w in TRAFFIC_SWEEP:
+            s.set_tune(sched_chunk=chunk, list_wg_per_cu=w)
+            s.upload_state(Q0, 0.0)
+            s.step_lts(t_end, a.warmup)
+            q0 = s.stats()
+            s.set_profiling(True)
+            s.step_lts(t_end, a.steps)
+            kq = s.kernel_times()
+            s.set_profiling(False)
+            q1 = s.stats()
+            print(json.dumps({"traffic_sweep": w, "launches": {k: kq[k][1] for k in ("recon", "predict")},
+                              "units": {"recon": q1["element_updates"] - q0["element_updates"],
+                                        "predict": q1["predictor_evals"] - q0["predictor_evals"]}}),
+                  flush=True)
+        if tune:
+            s.set_tune(sched_chunk=tune["sched_chunk"], list_wg_per_cu=tune["list_wg_per_cu"])
 
     if a.calib_copy_mib:
         n = a.calib_copy_mib * (1 << 20) // 8
@@ -362,6 +411,7 @@ def main():
         "lts": {"updates": lts_updates, "seconds": t_lts, "physical_interval": [T_a, T_b]},
         "lts_time_to_solution_speedup": t_gts / t_lts,
         "gts_over_lts_updates": gts_updates / max(lts_updates, 1),
+        "free_steps": free,
         "autotune": tune,
         "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
