@@ -13,7 +13,9 @@ solutions (constant state, entropy wave, rigid translation), node-solver
 translation, closed space-time volumes (GCL), free stream on a deforming
 mesh with local time steps, conservation at every cycle, deadlock freedom,
 LTS with one level against a separate GTS driver, the Sod problem against an
-exact Riemann solver and the design order on the smooth vortex.
+exact Riemann solver and the design order on the smooth vortex; the
+reverse-mode step against the NumPy step, central differences of it and the
+conservation identity of its adjoint.
 
 Parity unpinned (definitions the paper leaves to its references; they are
 checked only by the invariants above and by agreement with the GPU path):
@@ -26,4 +28,6 @@ Layout
   euler.py     Euler fluxes and the ideal-gas equation of state (eulerTerms, eqn.eos)
   scheme.py    reconstruction, predictor, node solver, space-time patch fluxes,
                update, local time step, the LTS cycle driver and a separate GTS driver
+  adjoint.py   one global step on a fixed mesh with dt held fixed, in PyTorch CPU
+               FP64 ops, differentiated by torch.autograd (reverse-mode oracle)
 """

@@ -1,0 +1,257 @@
+"""Reverse mode of one global time step on a fixed mesh (oracle, test
+infrastructure; never used by the product).
+
+The step is the scheme of Sec. 2 with one level (global time stepping) and the
+mesh held fixed (Eulerian mode, V = 0 in eq. ODEmesh): WENO reconstruction
+(eqs. intConsRec .. eqn.weno), space-time predictor (eq. CGfinal), Rusanov
+fluxes over the space-time faces (eqs. eqn.rusanov, eqn.STint) and the
+one-step update (eq. PDEfinal), for a given time step dt that is held fixed
+(the CFL step of eq. eqn.timestep is not differentiated).  It is written here
+a second time with PyTorch CPU operations in FP64, following the NumPy oracle
+step for step, so that torch.autograd yields the exact vector-Jacobian
+product of the step map Q^n -> Q^{n+1}.
+
+Everything that depends only on the fixed geometry (least-squares matrices of
+the stencils, the metric of the reference maps, space-time normals, areas) is
+computed once with the NumPy oracle's own tables and helpers; only the
+dependence on the state runs through torch.
+
+The forward map is pinned to the NumPy oracle's step and its derivative to
+central differences of that step (tests/test_oracle_adjoint.py).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import tables as tb
+from .scheme import BC_SLIP, Config, affine_inverse, affine_map, tri_area
+from .topology import build_topology
+
+_F64 = torch.float64
+
+
+def _t(a):
+    return torch.as_tensor(np.asarray(a, np.float64), dtype=_F64)
+
+
+def primitives(Q, gamma):
+    """rho, u, v, p of eq. eqn.eos (same formula as the NumPy oracle)."""
+    rho = Q[..., 0]
+    u = Q[..., 1] / rho
+    v = Q[..., 2] / rho
+    p = (gamma - 1.0) * (Q[..., 3] - 0.5 * rho * (u * u + v * v))
+    return rho, u, v, p
+
+
+def flux_fg(Q, gamma):
+    """Euler fluxes f and g of eq. eulerTerms."""
+    rho, u, v, p = primitives(Q, gamma)
+    E = Q[..., 3]
+    f = torch.stack([rho * u, rho * u * u + p, rho * u * v, u * (E + p)], dim=-1)
+    g = torch.stack([rho * v, rho * u * v, rho * v * v + p, v * (E + p)], dim=-1)
+    return f, g
+
+
+def rusanov(ql, qr, N, gamma):
+    """Rusanov flux of eq. eqn.rusanov through an unnormalised space-time
+    normal N; the larger signal speed is taken from the left state on ties and
+    |x| has derivative sign(x) (0 at 0), fixing one subgradient."""
+    nxy = torch.sqrt(N[..., 0] ** 2 + N[..., 1] ** 2)
+
+    def ft(q):
+        f, g = flux_fg(q, gamma)
+        return f * N[..., 0:1] + g * N[..., 1:2] + q * N[..., 2:3]
+
+    def speed(q):
+        rho, u, v, p = primitives(q, gamma)
+        return torch.abs(u * N[..., 0] + v * N[..., 1] + N[..., 2]) + torch.sqrt(gamma * p / rho) * nxy
+
+    sl, sr = speed(ql), speed(qr)
+    smax = torch.where(sl >= sr, sl, sr)
+    return 0.5 * (ft(ql) + ft(qr)) - 0.5 * smax[..., None] * (qr - ql)
+
+
+def mirror(q, N):
+    """Slip-wall ghost state: normal momentum reflected (linear in q)."""
+    nxy = torch.sqrt(N[..., 0] ** 2 + N[..., 1] ** 2)
+    nx, ny = N[..., 0] / nxy, N[..., 1] / nxy
+    mn = q[..., 1] * nx + q[..., 2] * ny
+    return torch.stack([q[..., 0], q[..., 1] - 2.0 * mn * nx, q[..., 2] - 2.0 * mn * ny, q[..., 3]],
+                       dim=-1)
+
+
+class EulerianStep:
+    """One global time step of length dt on a fixed mesh, as a torch function
+    of the cell averages Q (NE, 4)."""
+
+    def __init__(self, nodes, tris, cfg: Config, bedges=None, topo=None):
+        if cfg.flux != "rusanov":
+            raise ValueError("the reverse-mode oracle covers the Rusanov flux")
+        self.cfg = cfg
+        M = cfg.M
+        self.M = M
+        self.topo = topo if topo is not None else build_topology(nodes, tris, M, bedges)
+        topo = self.topo
+        X = np.asarray(nodes, float)
+        Xe = X[topo.tris]                                    # (NE,3,2)
+        NE = topo.n_elems
+        self.NE = NE
+        self.area = tri_area(Xe)
+
+        # -- reconstruction: constant least-squares maps per stencil (eq. intConsRec)
+        sz = tb.sizes(M)
+        nb = sz["nb"]
+        u, v, w = tb.duffy_rule(tb.recon_quad_n(M))
+        wmean = w / w.sum()
+        sten = topo.stencils
+        valid = sten[:, :, 0] >= 0
+        ss = np.where(sten >= 0, sten, np.arange(NE)[:, None, None])
+        self.sten_idx = torch.as_tensor(ss, dtype=torch.long)      # (NE,7,ne)
+        self.valid = torch.as_tensor(valid)
+        ne = ss.shape[2]
+        Pm = np.zeros((NE, 7, nb - 1, ne - 1))   # rest = Pm @ br
+        acol = np.zeros((NE, 7, ne - 1))         # A[1:, 0]
+        cvec = np.ones((NE, 7, nb))              # constraint row c
+        for s in range(7):
+            idx = np.nonzero(valid[:, s])[0]
+            if idx.size == 0:
+                continue
+            Xst = Xe[ss[idx, s]]
+            xq = affine_map(Xst, u, v)
+            Xii = Xe[idx][:, None]
+            xi, eta = affine_inverse(np.broadcast_to(Xii, Xst.shape), xq)
+            A = np.einsum("njpl,p->njl", tb.eval_psi(M, xi, eta), wmean)
+            c = A[:, 0, :]
+            Ar = A[:, 1:, 1:] - A[:, 1:, :1] * (c[:, None, 1:] / c[:, None, :1])
+            Qf, Rf = np.linalg.qr(Ar)
+            Pm[idx, s] = np.linalg.solve(Rf, np.transpose(Qf, (0, 2, 1)))
+            acol[idx, s] = A[:, 1:, 0]
+            cvec[idx, s] = c
+        self.Pm, self.acol, self.cvec = _t(Pm), _t(acol), _t(cvec)
+        self.Sig = _t(tb.sigma_matrix(M))
+        self.lam = _t(np.where(np.arange(7) == 0, cfg.weno_lambda, 1.0))
+        nxy = tb.nodal_xy(M)
+        self.psi_nodes = _t(tb.eval_psi(M, nxy[:, 0], nxy[:, 1]))
+
+        # -- predictor: constant metric of the fixed reference maps (eq. CGfinal, V = 0)
+        nt = tb.nodal_tables(M)
+        _, tm = tb.time_matrices(M)
+        self.At, self.Bt, self.Dt = tm["At"], tm["Bt"], tm["Dt"]
+        self.Dxi, self.Deta = _t(nt["Dxi"]), _t(nt["Deta"])
+        self.edge_tab = _t(nt["edge"])
+        x0 = affine_map(Xe, nxy[:, 0], nxy[:, 1])                 # (NE,nb,2)
+        x = np.repeat(x0[:, :, None, :], M + 1, axis=2).copy()
+        x[:, :, 1:, :] = self.Bt[None, None, :, None] * x[:, :, 0:1, :]   # the motion ODE with V = 0
+        self.x = x
+        Dxi, Deta = nt["Dxi"], nt["Deta"]
+        x_xi = np.einsum("km,nmtc->nktc", Dxi, x)
+        x_eta = np.einsum("km,nmtc->nktc", Deta, x)
+        det = x_xi[..., 0] * x_eta[..., 1] - x_eta[..., 0] * x_xi[..., 1]
+        self.metric = dict(xi_x=x_eta[..., 1] / det, xi_y=-x_eta[..., 0] / det,
+                           eta_x=-x_xi[..., 1] / det, eta_y=x_xi[..., 0] / det)
+        self.x_tau = np.einsum("pq,nmqc->nmpc", self.Dt, x)
+
+        # -- patches: fixed edges, corners (x, y, t) old a, old b, new b, new a
+        en = topo.edge_nodes
+        self.L = torch.as_tensor(topo.edge_elems[:, 0], dtype=torch.long)
+        R = topo.edge_elems[:, 1]
+        self.hasR = torch.as_tensor(R >= 0)
+        self.Rs = torch.as_tensor(np.where(R >= 0, R, topo.edge_elems[:, 0]), dtype=torch.long)
+        self.el = torch.as_tensor(topo.edge_local[:, 0], dtype=torch.long)
+        self.ers = torch.as_tensor(np.where(R >= 0, topo.edge_local[:, 1], topo.edge_local[:, 0]),
+                                   dtype=torch.long)
+        self.slip = torch.as_tensor(topo.bc_tag == BC_SLIP)
+        self.Xa, self.Xb = X[en[:, 0]], X[en[:, 1]]
+
+    # ------------------------------------------------------------------
+    def reconstruct(self, Q):
+        """wnod (NE, nb, 4) of eq. eqn.weno from the averages Q (NE, 4)."""
+        cfg = self.cfg
+        Qs = Q[self.sten_idx]                                 # (NE,7,ne,4)
+        Qi = Q[:, None, :]                                    # (NE,1,4)
+        c0 = self.cvec[..., 0]                                # (NE,7)
+        br = Qs[:, :, 1:, :] - self.acol[..., None] * (Qi[:, :, None, :] / c0[..., None, None])
+        rest = torch.einsum("nskj,nsjv->nskv", self.Pm, br)   # (NE,7,nb-1,4)
+        w0 = (Qi - torch.einsum("nsk,nskv->nsv", self.cvec[..., 1:], rest)) / c0[..., None]
+        ws = torch.cat([w0[:, :, None, :], rest], dim=2)      # (NE,7,nb,4)
+        sigma = torch.einsum("nslv,lm,nsmv->nsv", ws, self.Sig, ws)
+        if cfg.weno_shared:
+            sigma = sigma.sum(dim=2, keepdim=True).expand(-1, -1, 4)
+        wt = self.lam[None, :, None] / (sigma + cfg.weno_eps) ** cfg.weno_r
+        wt = torch.where(self.valid[:, :, None], wt, torch.zeros((), dtype=_F64))
+        omega = wt / wt.sum(dim=1, keepdim=True)
+        what = torch.einsum("nsv,nslv->nlv", omega, ws)
+        return torch.einsum("ml,nlv->nmv", self.psi_nodes, what)
+
+    def predict(self, wnod, dt):
+        """Edge traces (NE, 3, nG, M+1, 4) of the space-time predictor with the
+        tau = 0 data fixed (eq. CGfinal), M+1 (or n_picard) Picard sweeps."""
+        M, cfg = self.M, self.cfg
+        T = M + 1
+        met = {k: _t(v)[..., None] for k, v in self.metric.items()}
+        xt = _t(self.x_tau[..., 0] / dt)
+        yt = _t(self.x_tau[..., 1] / dt)
+        xi_t = -(met["xi_x"][..., 0] * xt + met["xi_y"][..., 0] * yt)[..., None]
+        eta_t = -(met["eta_x"][..., 0] * xt + met["eta_y"][..., 0] * yt)[..., None]
+        At, Bt = _t(self.At), _t(self.Bt)
+        q = wnod[:, :, None, :].expand(-1, -1, T, -1)
+        for _ in range(cfg.npic):
+            f, g = flux_fg(q, cfg.gamma)
+            d = lambda D, a: torch.einsum("km,nmtv->nktv", D, a)   # noqa: E731
+            P = -(d(self.Dxi, q) * xi_t + d(self.Deta, q) * eta_t
+                  + d(self.Dxi, f) * met["xi_x"] + d(self.Deta, f) * met["eta_x"]
+                  + d(self.Dxi, g) * met["xi_y"] + d(self.Deta, g) * met["eta_y"])
+            upper = (Bt[None, None, :, None] * q[:, :, 0:1, :]
+                     + dt * torch.einsum("qr,nmrv->nmqv", At, P))
+            q = torch.cat([q[:, :, 0:1, :], upper], dim=2)
+        return torch.einsum("egm,nmtv->negtv", self.edge_tab, q)
+
+    def fluxes(self, trace, dt):
+        """Edge fluxes G (NF, 4), outward from L, over the space-time faces of
+        the fixed edges (eq. eqn.STint with (M+1)^2 Gauss points)."""
+        M, cfg = self.M, self.cfg
+        nG = M + 1
+        chi, wc = tb.gauss_legendre01(nG)
+        z = np.zeros(self.Xa.shape[0])
+        P1 = np.column_stack([self.Xa, z])
+        P2 = np.column_stack([self.Xb, z])
+        P3 = np.column_stack([self.Xb, z + dt])
+        P4 = np.column_stack([self.Xa, z + dt])
+        trL = trace[self.L, self.el]                          # (NF,nG,T,4)
+        trR = trace[self.Rs, self.ers]
+        G = torch.zeros((self.Xa.shape[0], 4), dtype=_F64)
+        for g in range(nG):
+            for h in range(nG):
+                c, t = chi[g], chi[h]
+                dchi = (1 - t) * (P2 - P1) + t * (P3 - P4)
+                dtau = (1 - c) * (P4 - P1) + c * (P3 - P2)
+                N = _t(np.cross(dchi, dtau))
+                tk = (1 - c) * (1 - t) * 0.0 + c * (1 - t) * 0.0 + c * t * 1.0 + (1 - c) * t * 1.0
+                lt = _t(tb.lagrange_time(M, np.array([tk]))[0])
+                ql = torch.einsum("q,eqv->ev", lt, trL[:, g])
+                qrr = torch.einsum("q,eqv->ev", lt, trR[:, nG - 1 - g])
+                qr = torch.where(self.slip[:, None], mirror(ql, N), ql)
+                qr = torch.where(self.hasR[:, None], qrr, qr)
+                G = G + (wc[g] * wc[h]) * rusanov(ql, qr, N, cfg.gamma)
+        return G
+
+    def __call__(self, Q, dt):
+        """Q^{n+1} from Q^n (torch (NE, 4)) for the fixed step dt."""
+        trace = self.predict(self.reconstruct(Q), dt)
+        G = self.fluxes(trace, dt)
+        flux = torch.zeros_like(Q).index_add(0, self.L, G)
+        flux = flux.index_add(0, self.Rs[self.hasR], -G[self.hasR])
+        A = _t(self.area)[:, None]
+        return (A * Q - flux) / A
+
+    def vjp(self, Q, dt, Qbar_next):
+        """(dQ^{n+1}/dQ^n)^T Qbar_next, NumPy in and out."""
+        q = _t(Q).requires_grad_(True)
+        out = self(q, dt)
+        (g,) = torch.autograd.grad(out, q, _t(Qbar_next))
+        return g.detach().numpy()
+
+    def step(self, Q, dt):
+        with torch.no_grad():
+            return self(_t(Q), dt).numpy()
