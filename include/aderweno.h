@@ -183,6 +183,32 @@ int ader_autotune(ader_ctx* ctx, int32_t trial_macro_steps, ader_tune* chosen);
  * profiling is on, kernels are always launched one by one. */
 int ader_set_graphs(ader_ctx* ctx, int32_t on);
 
+/* ---- Adjoint of one global time step (reverse mode) ----------------------
+ * The step map Q^n -> Q^{n+1} of global time stepping of length dt from the
+ * current state, on a fixed mesh (mesh_velocity = 1: the mesh ODE of eq.
+ * ODEmesh with V = 0, so |T'| = |T|) with the Rusanov flux: WENO
+ * reconstruction with the neighbours' real averages (eqs. intConsRec ..
+ * eqn.weno), space-time predictor (eq. CGfinal), fluxes over the space-time
+ * faces of the edges with (M+1)^2 Gauss points (eqs. eqn.rusanov,
+ * eqn.STint) and the update of eq. PDEfinal.  ader_adjoint_gts_step writes
+ * Qbar = (dQ^{n+1}/dQ^n)^T Qbar_next with dt held fixed (the dependence of
+ * the CFL step of eq. eqn.timestep on the state is not differentiated);
+ * subgradients: the larger Rusanov signal speed is taken from the left state
+ * on ties, d|x|/dx = 0 at 0.  It does not change the simulation state.
+ *   Qbar_next_dev, Qbar_dev: device [4][n_elems] SoA (same layout as Q),
+ *     not overlapping;
+ *   work_dev: caller device memory of at least ader_adjoint_workspace_size
+ *     bytes, 256-byte aligned, used as scratch by the call only.
+ * Preconditions: a single instance, state uploaded, every element at one
+ * common time (after ader_upload_state or a completed stepping call; not
+ * after the test hooks) -> else ADER_E_ARG / ADER_E_ORDER.  Queued on the
+ * context's stream; no synchronisation.  The step that
+ * ader_step_gts(ctx, t + dt, 1, ...) takes from the same state is the one
+ * differentiated when dt is at most the smallest CFL step. */
+int ader_adjoint_workspace_size(const ader_ctx* ctx, size_t* bytes);
+int ader_adjoint_gts_step(ader_ctx* ctx, double dt, const double* Qbar_next_dev, double* Qbar_dev,
+                          void* work_dev, size_t work_bytes);
+
 /* Current state into caller device buffers (any may be NULL):
  * Q_dev [4][n_elems] SoA, node_xy_dev [n_nodes][2], elem_t_dev [n_elems]. */
 int ader_download_state(ader_ctx* ctx, double* Q_dev, double* node_xy_dev, double* elem_t_dev);
@@ -238,6 +264,7 @@ enum {
   ADER_K_PREDICT,     /* space-time predictor                                   */
   ADER_K_MACRO,       /* macro-step boundary: min CFL step, levels              */
   ADER_K_STATUS,      /* unfinished-element count                               */
+  ADER_K_ADJOINT,     /* ader_adjoint_gts_step (all its kernels)                */
   ADER_K_COUNT
 };
 int ader_set_profiling(ader_ctx* ctx, int32_t on);

@@ -23,8 +23,9 @@ EXPORTED = ["ader_create", "ader_upload_mesh", "ader_workspace_size", "ader_bind
             "ader_get_stats", "ader_debug_size", "ader_debug_dump", "ader_debug_inject",
             "ader_debug_cycles", "ader_debug_macro_begin", "ader_set_profiling", "ader_set_graphs",
             "ader_set_instances", "ader_instance_times", "ader_set_tune", "ader_autotune",
-            "ader_kernel_times", "ader_last_error", "ader_destroy"]
-KERNELS = ["sched", "node", "patch", "update", "recon", "predict", "macro", "status"]
+            "ader_kernel_times", "ader_adjoint_workspace_size", "ader_adjoint_gts_step",
+            "ader_last_error", "ader_destroy"]
+KERNELS = ["sched", "node", "patch", "update", "recon", "predict", "macro", "status", "adjoint"]
 
 
 class AderConfig(ctypes.Structure):
@@ -89,6 +90,8 @@ def load():
     lib.ader_autotune.argtypes = [P, i32, ctypes.POINTER(AderTune)]
     lib.ader_instance_times.argtypes = [P, i32, P]
     lib.ader_kernel_times.argtypes = [P, i32, P, P]
+    lib.ader_adjoint_workspace_size.argtypes = [P, P]
+    lib.ader_adjoint_gts_step.argtypes = [P, dbl, P, P, P, ctypes.c_size_t]
     lib.ader_last_error.argtypes = [P]
     lib.ader_last_error.restype = ctypes.c_char_p
     lib.ader_destroy.argtypes = [P]

@@ -17,6 +17,7 @@ struct ader_ctx {
   aw::Params prm{};
   hipStream_t stream = nullptr;
   bool has_mesh = false, bound = false, has_state = false;
+  bool synced = false;   // every element at one common time (no macro step in progress)
   aw::Topology topo;
   aw::Tables tab{};
   char* ws = nullptr;
@@ -301,6 +302,7 @@ void set_free(ader_ctx* c, bool free_steps) {
 int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
+  c->synced = false;
   set_free(c, false);
   aw::Scal s;
   int r;
@@ -336,6 +338,7 @@ int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
     }
     c->macro_steps++;
   }
+  c->synced = true;
   return 0;
 }
 
@@ -345,6 +348,7 @@ int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
 int run_free(ader_ctx* c, double t_target, int max_macro) {
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
+  c->synced = false;
   set_free(c, true);
   const int N = aw::FREE_TICKS;
   const bool graph = c->graphs && !c->prof;
@@ -378,6 +382,7 @@ int run_free(ader_ctx* c, double t_target, int max_macro) {
     if ((r = read_scal(c, s))) return r;
     c->macro_steps++;
   }
+  c->synced = true;
   return 0;
 }
 
@@ -755,6 +760,7 @@ int ader_upload_state(ader_ctx* c, const double* Q_dev, double t0) {
   if ((r = read_scal(c, back))) return r;
   if (back.err) return fail(c, ADER_E_STATE, "initial state has rho <= 0 or p <= 0");
   c->has_state = true;
+  c->synced = true;
   return ADER_OK;
 }
 
@@ -863,12 +869,14 @@ int ader_debug_inject(ader_ctx* c, int32_t what, const void* host, size_t bytes)
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->has_state = true;
+  c->synced = false;
   return ADER_OK;
 }
 
 int ader_debug_cycles(ader_ctx* c, int32_t n) {
   if (!c || n < 0) return ADER_E_ARG;
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  c->synced = false;
   int r = issue_cycles(c, n, c->stream);
   if (r) return r;
   c->cycles += n;
@@ -881,6 +889,7 @@ int ader_debug_macro_begin(ader_ctx* c, double t_end, int32_t levels) {
   if (!c || levels < 0 || levels > 8) return ADER_E_ARG;
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   set_free(c, levels == 0);
+  c->synced = false;
   LCHK(c, aw::launch_open(c->dev, t_end, c->stream));
   int r = issue_macro_begin(c, t_end, levels == 0 ? aw::FREE_TICKS : 1 << (levels - 1), c->stream);
   if (r) return r;
@@ -1008,6 +1017,35 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
   (void)hipStreamSynchronize(c->stream);
   cleanup();
   return r;
+}
+
+int ader_adjoint_workspace_size(const ader_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return ADER_E_ARG;
+  if (!c->has_mesh) return ADER_E_ORDER;
+  *bytes = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->prm.npic);
+  return ADER_OK;
+}
+
+int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Qbar_next_dev, double* Qbar_dev,
+                          void* work_dev, size_t work_bytes) {
+  if (!c || !Qbar_next_dev || !Qbar_dev || !work_dev) return ADER_E_ARG;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, ADER_E_ARG, "dt must be positive and finite");
+  if (c->cfg.mesh_velocity != 1) return fail(c, ADER_E_ARG, "the adjoint needs a fixed mesh (mesh_velocity = 1)");
+  if (c->cfg.flux != ADER_FLUX_RUSANOV) return fail(c, ADER_E_ARG, "the adjoint covers the Rusanov flux");
+  if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the adjoint runs on a single instance");
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  if (!c->synced) return fail(c, ADER_E_ORDER, "elements are not at a common time (macro step in progress)");
+  const size_t need = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->prm.npic);
+  if (work_bytes < need) return fail(c, ADER_E_ARG, "adjoint workspace too small");
+  if ((reinterpret_cast<uintptr_t>(work_dev) & 255) != 0)
+    return fail(c, ADER_E_ARG, "adjoint workspace must be 256-byte aligned");
+  aw::AdjWork w{};
+  w.qbar_next = Qbar_next_dev;
+  w.qbar = Qbar_dev;
+  aw::adjoint_carve(c->cfg.M, c->topo.NE, c->prm.npic, static_cast<char*>(work_dev), w);
+  LCHK(c, timed(c, ADER_K_ADJOINT, c->stream,
+                [&] { return aw::launch_adjoint_gts(c->dev, c->prm, c->cfg.M, w, dt, c->stream); }));
+  return ADER_OK;
 }
 
 int ader_set_graphs(ader_ctx* c, int32_t on) {

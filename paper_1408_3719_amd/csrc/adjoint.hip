@@ -1,0 +1,786 @@
+// Reverse mode (adjoint) of one global time step on a fixed mesh (gfx950).
+//
+// The step map Q^n -> Q^{n+1} of global time stepping with the mesh held fixed
+// (mesh velocity V = 0, eq. ODEmesh) and a given time step dt:
+//   WENO reconstruction with real neighbour data (eqs. intConsRec .. eqn.weno)
+//   -> space-time predictor (eq. CGfinal; the metric of the fixed affine map,
+//   no time derivative of the mesh) -> edge traces -> Rusanov fluxes over the
+//   space-time faces of the fixed edges ((M+1)^2 Gauss points, eqs.
+//   eqn.rusanov, eqn.STint) -> one-step update (eq. PDEfinal, |T'| = |T|).
+// Given qbar_next = dL/dQ^{n+1} the kernels return qbar = dL/dQ^n, with dt
+// held fixed (the CFL step of eq. eqn.timestep is not differentiated):
+//   k_adj_init        qbar = qbar_next (the identity part of the update)
+//   k_adj_recon<fwd>  reconstruction from the current averages (8 lanes per
+//                     element, lane s solves stencil s by Givens rotations)
+//   k_adj_pred_fwd    predictor sweeps, each iterate kept, edge traces
+//   k_adj_patch       adjoint of the fluxes: per edge, the flux adjoint
+//                     -qbar_L/|T_L| + qbar_R/|T_R| pulled back through the
+//                     Rusanov flux at every Gauss point onto the two elements'
+//                     trace adjoints (each (element, edge) slot has one writer)
+//   k_adj_pred_rev    the sweeps in reverse: trace adjoint -> adjoint of the
+//                     reconstruction's nodal values
+//   k_adj_recon<rev>  WENO weights and least squares in reverse; the stencil
+//                     rows are rebuilt and their adjoints added to qbar of the
+//                     stencil elements with atomics
+// Subgradients: the larger Rusanov signal speed is taken from the left state
+// on ties, and |x| has derivative sign(x), 0 at 0.
+// The least-squares adjoint uses A R^-1 = Q of the QR factorisation: the
+// adjoint of the right-hand side is A R^-1 R^-T wbar, so the rotations need
+// not be kept.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace aw {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int XE = rec_off_xe(), QO = rec_off_q(), AO = rec_off_a();
+
+template <int M>
+struct AZ {
+  static constexpr int nb = (M + 1) * (M + 2) / 2;
+  static constexpr int T = M + 1;
+  static constexpr int nG = M + 1;
+  static constexpr int ne = 2 * nb;
+  static constexpr int nu = nb - 1;
+  static constexpr int RS = rec_stride(M);
+  static constexpr int TS = trace_stride(M);
+  static constexpr int WS = wnod_stride(M);
+  static constexpr int QS = nb * T * 4;   // nodal space-time values of one element
+};
+
+// Euler fluxes f, g (eq. eulerTerms) with p from eq. eqn.eos.
+__device__ inline void euler_fg(const double q[4], double gam, double f[4], double g[4]) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r, E = q[3];
+  const double p = (gam - 1.0) * (E - 0.5 * r * (u * u + v * v));
+  f[0] = r * u;
+  f[1] = r * u * u + p;
+  f[2] = r * u * v;
+  f[3] = u * (E + p);
+  g[0] = r * v;
+  g[1] = r * u * v;
+  g[2] = r * v * v + p;
+  g[3] = v * (E + p);
+}
+
+// Adjoint of the primitive variables (rho, u, v, p, E written as rb, ub, vb,
+// pb, Eb) pulled back to the conserved ones: qb += d(rho, u, v, p, E)/dq ^T (.).
+__device__ inline void prim_pullback(const double q[4], double gam, double rb, double ub, double vb,
+                                     double pb, double Eb, double qb[4]) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  const double gm = gam - 1.0;
+  Eb += gm * pb;
+  rb += -gm * 0.5 * (u * u + v * v) * pb;
+  ub += -gm * r * u * pb;
+  vb += -gm * r * v * pb;
+  qb[0] += rb - (ub * u + vb * v) / r;
+  qb[1] += ub / r;
+  qb[2] += vb / r;
+  qb[3] += Eb;
+}
+
+// qb += J_f(q)^T fb + J_g(q)^T gb
+__device__ inline void euler_fg_vjp(const double q[4], double gam, const double fb[4],
+                                    const double gb[4], double qb[4]) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r, E = q[3];
+  const double p = (gam - 1.0) * (E - 0.5 * r * (u * u + v * v));
+  const double H = E + p;
+  double rb = 0.0, ub = 0.0, vb = 0.0, pb = 0.0, Eb = 0.0;
+  rb += fb[0] * u;            ub += fb[0] * r;
+  rb += fb[1] * u * u;        ub += fb[1] * 2.0 * r * u;   pb += fb[1];
+  rb += fb[2] * u * v;        ub += fb[2] * r * v;         vb += fb[2] * r * u;
+  ub += fb[3] * H;            Eb += fb[3] * u;             pb += fb[3] * u;
+  rb += gb[0] * v;            vb += gb[0] * r;
+  rb += gb[1] * u * v;        ub += gb[1] * r * v;         vb += gb[1] * r * u;
+  rb += gb[2] * v * v;        vb += gb[2] * 2.0 * r * v;   pb += gb[2];
+  vb += gb[3] * H;            Eb += gb[3] * v;             pb += gb[3] * v;
+  prim_pullback(q, gam, rb, ub, vb, pb, Eb, qb);
+}
+
+// ALE signal speed |u.N_xy + N_t| + c |N_xy| (eq. eqn.rusanov)
+__device__ inline double signal_speed(const double q[4], const double N[3], double nxy, double gam) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  const double p = (gam - 1.0) * (q[3] - 0.5 * r * (u * u + v * v));
+  return fabs(u * N[0] + v * N[1] + N[2]) + sqrt(gam * p / r) * nxy;
+}
+
+// qb += sb * d(signal speed)/dq
+__device__ inline void signal_speed_vjp(const double q[4], const double N[3], double nxy, double gam,
+                                        double sb, double qb[4]) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  const double p = (gam - 1.0) * (q[3] - 0.5 * r * (u * u + v * v));
+  const double un = u * N[0] + v * N[1] + N[2];
+  const double sg = (un > 0.0) ? 1.0 : (un < 0.0 ? -1.0 : 0.0);
+  const double c = sqrt(gam * p / r);
+  const double cb = sb * nxy;
+  prim_pullback(q, gam, -cb * c / (2.0 * r), sb * sg * N[0], sb * sg * N[1], cb * gam / (2.0 * c * r),
+                0.0, qb);
+}
+
+// Adjoint of the Rusanov flux 0.5 (F(ql) + F(qr)) . N - 0.5 smax (qr - ql).
+__device__ inline void rusanov_vjp(const double ql[4], const double qr[4], const double N[3],
+                                   double gam, const double Gb[4], double qlb[4], double qrb[4]) {
+  const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
+  const double sl = signal_speed(ql, N, nxy, gam), sr = signal_speed(qr, N, nxy, gam);
+  const bool left = sl >= sr;
+  const double smax = left ? sl : sr;
+  double fb[4], gb[4], sbar = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    fb[v] = 0.5 * N[0] * Gb[v];
+    gb[v] = 0.5 * N[1] * Gb[v];
+    qlb[v] += 0.5 * N[2] * Gb[v] + 0.5 * smax * Gb[v];
+    qrb[v] += 0.5 * N[2] * Gb[v] - 0.5 * smax * Gb[v];
+    sbar -= 0.5 * Gb[v] * (qr[v] - ql[v]);
+  }
+  euler_fg_vjp(ql, gam, fb, gb, qlb);
+  euler_fg_vjp(qr, gam, fb, gb, qrb);
+  if (left)
+    signal_speed_vjp(ql, N, nxy, gam, sbar, qlb);
+  else
+    signal_speed_vjp(qr, N, nxy, gam, sbar, qrb);
+}
+
+// Lagrange basis in time, l_q(tau)
+template <int M>
+__device__ inline void time_basis(const Tables* tb, double tau, double l[M + 1]) {
+#pragma unroll
+  for (int q = 0; q <= M; ++q) {
+    double s = tb->lag[q][M];
+#pragma unroll
+    for (int k = M - 1; k >= 0; --k) s = s * tau + tb->lag[q][k];
+    l[q] = s;
+  }
+}
+
+__device__ inline double group8_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+
+// Row of the least-squares system for stencil element j seen from element i:
+// the means of psi_1 .. psi_nu over T_j mapped into the reference frame of T_i
+// (vertices Xi, inverse edge matrix through e1, e2, idet).
+template <int M>
+__device__ inline void ls_row(const Tables* tb, const double* Xj, const double Xi[6], double e1x,
+                              double e1y, double e2x, double e2y, double idet,
+                              double a[AZ<M>::nu]) {
+  constexpr int nb = AZ<M>::nb, nu = AZ<M>::nu;
+  double rx[3], ry[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double dx = Xj[2 * k] - Xi[0], dy = Xj[2 * k + 1] - Xi[1];
+    rx[k] = (dx * e2y - dy * e2x) * idet;
+    ry[k] = (e1x * dy - e1y * dx) * idet;
+  }
+  double mm[nb];
+#pragma unroll
+  for (int k = 0; k < nb; ++k) mm[k] = 0.0;
+  for (int r = 0; r < tb->nrq; ++r) {
+    const double px = tb->rqb[r][0] * rx[0] + tb->rqb[r][1] * rx[1] + tb->rqb[r][2] * rx[2];
+    const double py = tb->rqb[r][0] * ry[0] + tb->rqb[r][1] * ry[1] + tb->rqb[r][2] * ry[2];
+    const double w = tb->rqw[r];
+    double xp[M + 1], yp[M + 1];
+    xp[0] = 1.0;
+    yp[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= M; ++k) {
+      xp[k] = xp[k - 1] * px;
+      yp[k] = yp[k - 1] * py;
+    }
+    int k = 0;
+#pragma unroll
+    for (int dg = 0; dg <= M; ++dg)
+#pragma unroll
+      for (int b = 0; b <= dg; ++b) {
+        mm[k] += w * xp[dg - b] * yp[b];
+        ++k;
+      }
+  }
+#pragma unroll
+  for (int l = 0; l < nu; ++l) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < nb; ++k) s += tb->psiC[l + 1][k] * mm[k];
+    a[l] = s;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_adj_init(Dev d, AdjWork w) {
+  const size_t n = size_t(4) * d.NE;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x)
+    w.qbar[k] = w.qbar_next[k];
+}
+
+// Reconstruction (REV = false: write the nodal values) or its adjoint (REV =
+// true: read their adjoint, add to qbar). 8 lanes per element.
+template <int M, bool REV>
+__global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restrict__ tb, Params P,
+                                                   AdjWork w) {
+  using S = AZ<M>;
+  constexpr int nb = S::nb, ne = S::ne, nu = S::nu, WS = S::WS;
+  const int NE = d.NE;
+  const int sl = threadIdx.x & 7;
+  const int ngroups = (gridDim.x * blockDim.x) >> 3;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < NE; i += ngroups) {
+    const double* ri = d.rec + size_t(i) * S::RS;
+    double Xi[6], Qi[4];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Xi[c] = ri[XE + c];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Qi[v] = ri[QO + v];
+    const double e1x = Xi[2] - Xi[0], e1y = Xi[3] - Xi[1];
+    const double e2x = Xi[4] - Xi[0], e2y = Xi[5] - Xi[1];
+    const double idet = 1.0 / (e1x * e2y - e2x * e1y);
+    const int* sidx = d.sten + size_t(sl * ne) * NE + i;    // row c at sidx[c * NE]
+    const bool valid = sl < NSTEN && sidx[0] >= 0;
+    double R[nu][nu], ws[nu][4];
+    double om = 0.0, sig = 0.0;
+#pragma unroll
+    for (int a = 0; a < nu; ++a) {
+#pragma unroll
+      for (int b = 0; b < nu; ++b) R[a][b] = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ws[a][v] = 0.0;
+    }
+    if (valid) {
+      double z[nu][4];
+#pragma unroll
+      for (int a = 0; a < nu; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) z[a][v] = 0.0;
+#pragma unroll 1
+      for (int c = 1; c < ne; ++c) {
+        const double* rj = d.rec + size_t(sidx[c * NE]) * S::RS;
+        double a[nu], b[4];
+        ls_row<M>(tb, rj + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) b[v] = rj[QO + v] - Qi[v];
+#pragma unroll
+        for (int k = 0; k < nu; ++k) {
+          const double rkk = R[k][k], ak = a[k];
+          const double h2 = rkk * rkk + ak * ak;
+          if (h2 == 0.0) continue;
+          const double rh = rsqrt(h2);
+          const double cs = rkk * rh, sn = ak * rh;
+          R[k][k] = h2 * rh;
+#pragma unroll
+          for (int c2 = k + 1; c2 < nu; ++c2) {
+            const double t = cs * R[k][c2] + sn * a[c2];
+            a[c2] = cs * a[c2] - sn * R[k][c2];
+            R[k][c2] = t;
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double t = cs * z[k][v] + sn * b[v];
+            b[v] = cs * b[v] - sn * z[k][v];
+            z[k][v] = t;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = nu - 1; k >= 0; --k) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double t = z[k][v];
+#pragma unroll
+          for (int c2 = k + 1; c2 < nu; ++c2) t -= R[k][c2] * ws[c2][v];
+          ws[k][v] = t / R[k][k];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int l = 0; l < nu; ++l) {
+          double t = 0.0;
+#pragma unroll
+          for (int m = 0; m < nu; ++m) t += tb->Sigma[l + 1][m + 1] * ws[m][v];
+          sig += ws[l][v] * t;
+        }
+      const double x = sig + P.eps;
+      const double x2 = x * x, x4 = x2 * x2;
+      om = (sl == 0 ? P.lambda : 1.0) / (x4 * x4);
+    }
+    // combined reconstruction W = sum_s om_s w_s / sum_s om_s
+    const double Ssum = group8_sum(om);
+    double W[nu][4];
+#pragma unroll
+    for (int l = 0; l < nu; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[l][v] = group8_sum(om * ws[l][v]) / Ssum;
+    if (!REV) {
+      double* wo = w.wnod + size_t(i) * WS;
+#pragma unroll
+      for (int m = 0; m < nb; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (((m * 4 + v) & 7) != sl) continue;
+          double t = tb->psiNodes[m][0] * Qi[v];
+#pragma unroll
+          for (int l = 0; l < nu; ++l) t += tb->psiNodes[m][l + 1] * W[l][v];
+          wo[m * 4 + v] = t;
+        }
+      continue;
+    }
+    // adjoint of the nodal values -> adjoint of (Q_i, W)
+    const double* wbi = w.wbar + size_t(i) * WS;
+    double Wb[nu][4], q0b[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      q0b[v] = 0.0;
+#pragma unroll
+      for (int l = 0; l < nu; ++l) Wb[l][v] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < nb; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double b = wbi[m * 4 + v];
+        q0b[v] += tb->psiNodes[m][0] * b;
+#pragma unroll
+        for (int l = 0; l < nu; ++l) Wb[l][v] += tb->psiNodes[m][l + 1] * b;
+      }
+    if (sl == 7) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) atomicAdd(&w.qbar[size_t(v) * NE + i], q0b[v]);
+    }
+    if (!valid) continue;
+    // weights: om_s = lambda_s / (sigma_s + eps)^8, W = sum om_s w_s / sum om_s
+    double omb = 0.0;
+#pragma unroll
+    for (int l = 0; l < nu; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) omb += Wb[l][v] * (ws[l][v] - W[l][v]);
+    omb /= Ssum;
+    const double sigb = omb * (-8.0) * om / (sig + P.eps);
+    double u[nu][4];   // wbar_s, then R^-T wbar_s, then R^-1 R^-T wbar_s
+#pragma unroll
+    for (int l = 0; l < nu; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t = 0.0;
+#pragma unroll
+        for (int m = 0; m < nu; ++m) t += (tb->Sigma[l + 1][m + 1] + tb->Sigma[m + 1][l + 1]) * ws[m][v];
+        u[l][v] = (om / Ssum) * Wb[l][v] + sigb * t;
+      }
+#pragma unroll
+    for (int k = 0; k < nu; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t = u[k][v];
+#pragma unroll
+        for (int c2 = 0; c2 < k; ++c2) t -= R[c2][k] * u[c2][v];
+        u[k][v] = t / R[k][k];
+      }
+#pragma unroll
+    for (int k = nu - 1; k >= 0; --k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t = u[k][v];
+#pragma unroll
+        for (int c2 = k + 1; c2 < nu; ++c2) t -= R[k][c2] * u[c2][v];
+        u[k][v] = t / R[k][k];
+      }
+    // right-hand sides b_c = Q_j - Q_i: their adjoints are a_c . u
+    double sumb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int c = 1; c < ne; ++c) {
+      const int j = sidx[c * NE];
+      const double* rj = d.rec + size_t(j) * S::RS;
+      double a[nu];
+      ls_row<M>(tb, rj + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < nu; ++l) t += a[l] * u[l][v];
+        atomicAdd(&w.qbar[size_t(v) * NE + j], t);
+        sumb[v] += t;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) atomicAdd(&w.qbar[size_t(v) * NE + i], -sumb[v]);
+  }
+}
+
+// Metric of the fixed affine map of element i: xi_x, xi_y, eta_x, eta_y.
+__device__ inline void affine_metric(const double X[6], double m[4]) {
+  const double e1x = X[2] - X[0], e1y = X[3] - X[1], e2x = X[4] - X[0], e2y = X[5] - X[1];
+  const double det = e1x * e2y - e2x * e1y;
+  m[0] = e2y / det;
+  m[1] = -e2x / det;
+  m[2] = -e1y / det;
+  m[3] = e1x / det;
+}
+
+// Predictor sweeps from the reconstruction, each iterate kept; edge traces.
+// One lane per element; nodal data element-minor in the sweep store.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_adj_pred_fwd(Dev d, const Tables* __restrict__ tb, Params P,
+                                                      AdjWork w, double dt) {
+  using S = AZ<M>;
+  constexpr int nb = S::nb, T = S::T, nG = S::nG, QS = S::QS;
+  const int NE = d.NE;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    const double* ri = d.rec + size_t(i) * S::RS;
+    double X[6], mt[4];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) X[c] = ri[XE + c];
+    affine_metric(X, mt);
+    double q[nb][T][4];
+    const double* wn = w.wnod + size_t(i) * S::WS;
+#pragma unroll
+    for (int m = 0; m < nb; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double x = wn[m * 4 + v];
+#pragma unroll
+        for (int t = 0; t < T; ++t) q[m][t][v] = x;
+      }
+#pragma unroll 1
+    for (int k = 0; k < P.npic; ++k) {
+      double* st = w.sweeps + size_t(k) * QS * NE + i;
+#pragma unroll
+      for (int m = 0; m < nb; ++m)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) st[size_t((m * T + t) * 4 + v) * NE] = q[m][t][v];
+      double qn[nb][M][4];
+#pragma unroll
+      for (int m = 0; m < nb; ++m)
+#pragma unroll
+        for (int r = 0; r < M; ++r)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) qn[m][r][v] = tb->Bt[r] * q[m][0][v];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        double f[nb][4], g[nb][4];
+#pragma unroll
+        for (int m = 0; m < nb; ++m) euler_fg(q[m][t], P.gamma, f[m], g[m]);
+#pragma unroll
+        for (int kk = 0; kk < nb; ++kk)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < nb; ++m)
+              s += (mt[0] * tb->Dxi[kk][m] + mt[2] * tb->Deta[kk][m]) * f[m][v] +
+                   (mt[1] * tb->Dxi[kk][m] + mt[3] * tb->Deta[kk][m]) * g[m][v];
+#pragma unroll
+            for (int r = 0; r < M; ++r) qn[kk][r][v] += dt * tb->At[r][t] * (-s);
+          }
+      }
+#pragma unroll
+      for (int m = 0; m < nb; ++m)
+#pragma unroll
+        for (int r = 0; r < M; ++r)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) q[m][r + 1][v] = qn[m][r][v];
+    }
+    double* tr = w.trace + size_t(i) * S::TS;
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+      for (int g = 0; g < nG; ++g)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < nb; ++m) s += tb->edge[e][g][m] * q[m][t][v];
+            tr[((e * nG + g) * T + t) * 4 + v] = s;
+          }
+  }
+}
+
+// Adjoint of the fluxes through the space-time faces of the fixed edges.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_adj_patch(Dev d, const Tables* __restrict__ tb, Params P,
+                                                   AdjWork w, double dt) {
+  using S = AZ<M>;
+  constexpr int T = S::T, nG = S::nG, TS = S::TS;
+  const int NE = d.NE, NV = d.NV, NF = d.NF;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
+    const int a = d.e_a[e], b = d.e_b[e];
+    const int L = d.e_L[e], el = d.e_el[e], R = d.e_R[e], er = d.e_er[e], bc = d.e_bc[e];
+    const double P1[3] = {d.X[a], d.X[NV + a], 0.0};
+    const double P2[3] = {d.X[b], d.X[NV + b], 0.0};
+    const double P3[3] = {d.X[b], d.X[NV + b], dt};
+    const double P4[3] = {d.X[a], d.X[NV + a], dt};
+    // flux adjoint: Q_L' = Q_L - G / |T_L|, Q_R' = Q_R + G / |T_R|
+    double Gb[4];
+    const double AL = d.rec[size_t(L) * S::RS + AO];
+    const double AR = R >= 0 ? d.rec[size_t(R) * S::RS + AO] : 1.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Gb[v] = -w.qbar_next[size_t(v) * NE + L] / AL;
+      if (R >= 0) Gb[v] += w.qbar_next[size_t(v) * NE + R] / AR;
+    }
+    const double* trL = w.trace + size_t(L) * TS + el * nG * T * 4;
+    const double* trR = R >= 0 ? w.trace + size_t(R) * TS + er * nG * T * 4 : trL;
+    double bL[nG][T][4], bR[nG][T][4];
+#pragma unroll
+    for (int g = 0; g < nG; ++g)
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          bL[g][t][v] = 0.0;
+          bR[g][t][v] = 0.0;
+        }
+#pragma unroll
+    for (int gq = 0; gq < nG; ++gq) {
+      const double c = tb->gchi[gq];
+#pragma unroll
+      for (int h = 0; h < nG; ++h) {
+        const double tt = tb->gchi[h];
+        const double wgt = tb->gw[gq] * tb->gw[h];
+        double dchi[3], dtau[3], N[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          dchi[k] = (1.0 - tt) * (P2[k] - P1[k]) + tt * (P3[k] - P4[k]);
+          dtau[k] = (1.0 - c) * (P4[k] - P1[k]) + c * (P3[k] - P2[k]);
+        }
+        N[0] = dchi[1] * dtau[2] - dchi[2] * dtau[1];
+        N[1] = dchi[2] * dtau[0] - dchi[0] * dtau[2];
+        N[2] = dchi[0] * dtau[1] - dchi[1] * dtau[0];
+        // corner ticks 0, 0, 1, 1 of a one-tick step: tau at the point
+        const double tk = c * tt + (1.0 - c) * tt;
+        double l[T];
+        time_basis<M>(tb, tk, l);
+        double ql[4], qr[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double s = 0.0, s2 = 0.0;
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            s += l[t] * trL[(gq * T + t) * 4 + v];
+            s2 += l[t] * trR[((nG - 1 - gq) * T + t) * 4 + v];
+          }
+          ql[v] = s;
+          qr[v] = s2;
+        }
+        double nx = 0.0, ny = 0.0;
+        if (R < 0 && bc == 2) {
+          const double inxy = 1.0 / sqrt(N[0] * N[0] + N[1] * N[1]);
+          nx = N[0] * inxy;
+          ny = N[1] * inxy;
+          const double mn = ql[1] * nx + ql[2] * ny;
+          qr[0] = ql[0];
+          qr[1] = ql[1] - 2.0 * mn * nx;
+          qr[2] = ql[2] - 2.0 * mn * ny;
+          qr[3] = ql[3];
+        } else if (R < 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) qr[v] = ql[v];
+        }
+        double Gw[4], qlb[4] = {0, 0, 0, 0}, qrb[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Gw[v] = wgt * Gb[v];
+        rusanov_vjp(ql, qr, N, P.gamma, Gw, qlb, qrb);
+        if (R >= 0) {
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bR[nG - 1 - gq][t][v] += l[t] * qrb[v];
+        } else if (bc == 2) {
+          // the mirror map is a symmetric reflection of the momentum
+          const double mb = qrb[1] * nx + qrb[2] * ny;
+          qlb[0] += qrb[0];
+          qlb[1] += qrb[1] - 2.0 * mb * nx;
+          qlb[2] += qrb[2] - 2.0 * mb * ny;
+          qlb[3] += qrb[3];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) qlb[v] += qrb[v];
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bL[gq][t][v] += l[t] * qlb[v];
+      }
+    }
+    double* oL = w.tbar + size_t(L) * TS + el * nG * T * 4;
+#pragma unroll
+    for (int g = 0; g < nG; ++g)
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) oL[(g * T + t) * 4 + v] = bL[g][t][v];
+    if (R >= 0) {
+      double* oR = w.tbar + size_t(R) * TS + er * nG * T * 4;
+#pragma unroll
+      for (int g = 0; g < nG; ++g)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) oR[(g * T + t) * 4 + v] = bR[g][t][v];
+    }
+  }
+}
+
+// Predictor sweeps in reverse: trace adjoint -> adjoint of the reconstruction.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_adj_pred_rev(Dev d, const Tables* __restrict__ tb, Params P,
+                                                      AdjWork w, double dt) {
+  using S = AZ<M>;
+  constexpr int nb = S::nb, T = S::T, nG = S::nG, QS = S::QS;
+  const int NE = d.NE;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    const double* ri = d.rec + size_t(i) * S::RS;
+    double X[6], mt[4];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) X[c] = ri[XE + c];
+    affine_metric(X, mt);
+    double qb[nb][T][4];
+    const double* tb_i = w.tbar + size_t(i) * S::TS;
+#pragma unroll
+    for (int m = 0; m < nb; ++m)
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double s = 0.0;
+#pragma unroll
+          for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int g = 0; g < nG; ++g) s += tb->edge[e][g][m] * tb_i[((e * nG + g) * T + t) * 4 + v];
+          qb[m][t][v] = s;
+        }
+#pragma unroll 1
+    for (int k = P.npic - 1; k >= 0; --k) {
+      const double* st = w.sweeps + size_t(k) * QS * NE + i;
+      // q_new[m][r+1] = Bt[r] q[m][0] + dt sum_t At[r][t] P[m][t];  q_new[m][0] = q[m][0]
+      double nb0[nb][4];
+#pragma unroll
+      for (int m = 0; m < nb; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double s = qb[m][0][v];
+#pragma unroll
+          for (int r = 0; r < M; ++r) s += tb->Bt[r] * qb[m][r + 1][v];
+          nb0[m][v] = s;
+        }
+      double nq[nb][T][4];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        // Pbar at time node t for every spatial node
+        double Pb[nb][4];
+#pragma unroll
+        for (int m = 0; m < nb; ++m)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < M; ++r) s += tb->At[r][t] * qb[m][r + 1][v];
+            Pb[m][v] = dt * s;
+          }
+        // P[kk] = -sum_m (xi_x Dxi + eta_x Deta)[kk][m] f[m] + (xi_y Dxi + eta_y Deta)[kk][m] g[m]
+#pragma unroll
+        for (int m = 0; m < nb; ++m) {
+          double fb[4], gb[4], q[4], acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double sf = 0.0, sg = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < nb; ++kk) {
+              sf += (mt[0] * tb->Dxi[kk][m] + mt[2] * tb->Deta[kk][m]) * Pb[kk][v];
+              sg += (mt[1] * tb->Dxi[kk][m] + mt[3] * tb->Deta[kk][m]) * Pb[kk][v];
+            }
+            fb[v] = -sf;
+            gb[v] = -sg;
+            q[v] = st[size_t((m * T + t) * 4 + v) * NE];
+          }
+          euler_fg_vjp(q, P.gamma, fb, gb, acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) nq[m][t][v] = acc[v] + (t == 0 ? nb0[m][v] : 0.0);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < nb; ++m)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) qb[m][t][v] = nq[m][t][v];
+    }
+    // the first iterate repeats the reconstruction at every time node
+    double* wb = w.wbar + size_t(i) * S::WS;
+#pragma unroll
+    for (int m = 0; m < nb; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) s += qb[m][t][v];
+        wb[m * 4 + v] = s;
+      }
+  }
+}
+
+int grid_for(long n) {
+  long b = (n + TPB - 1) / TPB;
+  if (b < 1) b = 1;
+  if (b > 16384) b = 16384;
+  return int(b);
+}
+
+#define AD_LAUNCH(kern, n, stream, ...)                                                      \
+  do {                                                                                       \
+    hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(TPB), 0, (hipStream_t)(stream),         \
+                       __VA_ARGS__);                                                         \
+    hipError_t _e = hipGetLastError();                                                       \
+    if (_e != hipSuccess) return int(_e);                                                    \
+  } while (0)
+
+template <int M>
+int adjoint_gts(const Dev& d, const Params& p, const AdjWork& w, double dt, void* s) {
+  AD_LAUNCH(k_adj_init, 4L * d.NE, s, d, w);
+  AD_LAUNCH((k_adj_recon<M, false>), 8L * d.NE, s, d, d.tab, p, w);
+  AD_LAUNCH(k_adj_pred_fwd<M>, d.NE, s, d, d.tab, p, w, dt);
+  AD_LAUNCH(k_adj_patch<M>, d.NF, s, d, d.tab, p, w, dt);
+  AD_LAUNCH(k_adj_pred_rev<M>, d.NE, s, d, d.tab, p, w, dt);
+  AD_LAUNCH((k_adj_recon<M, true>), 8L * d.NE, s, d, d.tab, p, w);
+  return 0;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
+
+size_t adjoint_work_bytes(int M, int NE, int npic) {
+  const size_t nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, D = sizeof(double);
+  const size_t ws = align256(NE * size_t(wnod_stride(M)) * D);
+  const size_t ts = align256(NE * size_t(trace_stride(M)) * D);
+  const size_t sw = align256(size_t(npic) * nb * T * 4 * NE * D);
+  return 2 * ws + 2 * ts + sw;
+}
+
+void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w) {
+  const size_t nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, D = sizeof(double);
+  const size_t ws = align256(NE * size_t(wnod_stride(M)) * D);
+  const size_t ts = align256(NE * size_t(trace_stride(M)) * D);
+  w.wnod = (double*)base;
+  w.wbar = (double*)(base + ws);
+  w.trace = (double*)(base + 2 * ws);
+  w.tbar = (double*)(base + 2 * ws + ts);
+  w.sweeps = (double*)(base + 2 * ws + 2 * ts);
+  (void)nb;
+  (void)T;
+}
+
+int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt, void* s) {
+  switch (M) {
+    case 1: return adjoint_gts<1>(d, p, w, dt, s);
+    case 2: return adjoint_gts<2>(d, p, w, dt, s);
+    case 3: return adjoint_gts<3>(d, p, w, dt, s);
+    default: return int(hipErrorInvalidValue);
+  }
+}
+
+}  // namespace aw

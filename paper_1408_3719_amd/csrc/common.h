@@ -1,5 +1,6 @@
 // Shared host/device definitions of the aderweno library.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 
 namespace aw {
@@ -132,6 +133,27 @@ struct Dev {
   double *G, *Nint;   // [4][NF], [3][NF]
   int* edge_stamp;
 };
+
+// Buffers of the reverse-mode step (adjoint.hip), carved from the caller's
+// adjoint workspace; nodal space-time data are element-minor ([slot][NE]).
+struct AdjWork {
+  const double* qbar_next;   // [4][NE] adjoint of the averages after the step
+  double* qbar;              // [4][NE] adjoint of the averages before the step
+  double* wnod;              // [NE][wnod_stride] reconstruction at the step start
+  double* trace;             // [NE][trace_stride] predictor edge traces
+  double* tbar;              // [NE][trace_stride] their adjoints
+  double* wbar;              // [NE][wnod_stride] adjoint of the reconstruction
+  double* sweeps;            // [npic][nb*(M+1)*4][NE] predictor iterate before each sweep
+};
+
+// Bytes of the adjoint workspace (each buffer 256-byte aligned).
+size_t adjoint_work_bytes(int M, int NE, int npic);
+// Carve the buffers from base (qbar_next, qbar left to the caller).
+void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w);
+// The reverse-mode step: qbar = (dQ^{n+1}/dQ^n)^T qbar_next for one global
+// step of length dt on a fixed mesh (adjoint.hip).
+int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,
+                       void* stream);
 
 // Kernel launchers (kernels.hip).  All launch on `stream`, return a
 // hipError_t as int.

@@ -144,6 +144,29 @@ class Solver(_Base):
     def _stats(self, st):
         return {f: getattr(st, f) for f, _ in _lib.AderStats._fields_}
 
+    def adjoint_gts_step(self, dt, qbar_next):
+        """(dQ^{n+1}/dQ^n)^T qbar_next for one global step of length dt from the
+        current state on a fixed mesh (dt held fixed).  qbar_next: (NE, 4)
+        array or a device tensor [4][NE]; returns a device tensor [4][NE]."""
+        torch = self.torch
+        qn = qbar_next
+        if not torch.is_tensor(qn):
+            qn = torch.as_tensor(np.ascontiguousarray(np.asarray(qn, np.float64).T), device=self.device)
+        qn = qn.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(qn.shape) != (4, self.NE):
+            raise ValueError(f"qbar_next must be [4][{self.NE}] on the device or ({self.NE}, 4)")
+        out = torch.empty_like(qn)
+        if getattr(self, "_adj_ws", None) is None:
+            n = ctypes.c_size_t()
+            _check(self.lib, self.ctx, self.lib.ader_adjoint_workspace_size(self.ctx, ctypes.byref(n)))
+            self._adj_ws = (torch.empty(n.value + 256, dtype=torch.uint8, device=self.device), n.value)
+        buf, n = self._adj_ws
+        aligned = (buf.data_ptr() + 255) // 256 * 256
+        _check(self.lib, self.ctx, self.lib.ader_adjoint_gts_step(
+            self.ctx, dt, ctypes.c_void_p(qn.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(aligned), n))
+        return out
+
     def step_gts(self, t_target, max_steps=0):
         st = _lib.AderStats()
         _check(self.lib, self.ctx, self.lib.ader_step_gts(self.ctx, t_target, max_steps, ctypes.byref(st)))
