@@ -13,8 +13,10 @@ the solver's stream, the roofline of the dominant kernel, and the CPU oracle
 timed on a bounded sample.
 
 Other workloads (not the headline line): --workload explosion (EP1 on the unit
-disk, 8:1 radial grading, 400k triangles, M=2, 4 levels) or --workload sod
-(RP1 shock tube, 2k triangles, M=1, one level = GTS).
+disk, 8:1 radial grading, 400k triangles, M=2, 4 levels), --workload sod
+(RP1 shock tube, 2k triangles, M=1, one level = GTS), --workload batched
+(256 independent instances in the same launches) or --workload adjoint
+(adjoint/forward time of one global step on a fixed 50k-triangle mesh).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload vortex]
                        [--n-elems N] [--M M] [--levels L]
@@ -122,6 +124,72 @@ print(json.dumps(dict(updates=s.st.updates, seconds=dt, n_elems=mesh.n_elems)))
                        f"{r['seconds']:.1f} s, one host thread)")
 
 
+def bench_adjoint(a):
+    """Adjoint of one global time step on a fixed mesh: EP1 explosion on a
+    50k-triangle 8:1 graded disk, M=2, Rusanov flux, dt = the smallest CFL
+    step held fixed. Forward = ader_step_gts of one step (pre-step
+    reconstruction included), adjoint = ader_adjoint_gts_step from the same
+    state; both timed over K calls with the state resident in HBM."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3719_amd import Config, Solver
+    from workloads import explosion_case
+
+    n = a.n_elems or 50_000
+    M = a.M or 2
+    mesh, Q0 = explosion_case(n, seed=7)
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=1, mesh_velocity="eulerian"))
+    dt = float(s.dump("DTCFL").min())
+    sync = torch.cuda.synchronize
+    # forward: K single steps of length dt from the initial state
+    for _ in range(a.warmup):
+        s.upload_state(Q0, 0.0)
+        s.step_gts(dt, 1)
+    t_f = 0.0
+    for _ in range(a.steps):
+        s.upload_state(Q0, 0.0)
+        sync()
+        t0 = time.perf_counter()
+        s.step_gts(dt, 1)
+        sync()
+        t_f += time.perf_counter() - t0
+    # adjoint from the same state
+    s.upload_state(Q0, 0.0)
+    rng = np.random.default_rng(0)
+    qb = torch.tensor(rng.standard_normal((4, mesh.n_elems)), device="cuda")
+    for _ in range(a.warmup):
+        s.adjoint_gts_step(dt, qb)
+    sync()
+    s.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        out = s.adjoint_gts_step(dt, qb)
+    sync()
+    t_a = time.perf_counter() - t0
+    kt = s.kernel_times()
+    s.set_profiling(False)
+    assert torch.isfinite(out).all()
+    ms_f, ms_a = t_f / a.steps * 1e3, t_a / a.steps * 1e3
+    line = {
+        "metric": "adjoint/forward time of one global step",
+        "value": ms_a / ms_f,
+        "unit": "ratio",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_a,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"EP1 explosion, {mesh.n_elems}-triangle 8:1 radially graded disk, "
+                               f"M={M}, fixed mesh, one global step of the smallest CFL step, Rusanov",
+                   "n_elems": mesh.n_elems, "M": M, "parallelism": "single GPU"},
+        "forward_ms_per_step": ms_f,
+        "adjoint_ms_per_step": ms_a,
+        "adjoint_elements_per_s": mesh.n_elems / (ms_a * 1e-3),
+        "adjoint_hip_event_ms": kt["adjoint"][0] / max(kt["adjoint"][1], 1),
+    }
+    print(json.dumps(line))
+
+
 def bench_batched(a):
     """Uneven batch of independent Riemann and explosion instances (log-uniform
     1k-50k triangles, random left/right density and pressure), M=2, LTS 3
@@ -201,7 +269,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["vortex", "explosion", "sod", "batched"], default="vortex")
+    ap.add_argument("--workload", choices=["vortex", "explosion", "sod", "batched", "adjoint"],
+                    default="vortex")
     ap.add_argument("--instances", type=int, default=256, help="batched workload: instances")
     ap.add_argument("--n-elems", type=int, default=None)
     ap.add_argument("--M", type=int, default=None)
@@ -226,6 +295,8 @@ def main():
 
     if a.workload == "batched":
         return bench_batched(a)
+    if a.workload == "adjoint":
+        return bench_adjoint(a)
 
     import numpy as np
     import torch

@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
       }
     if (sl == 7) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) atomicAdd(&w.qbar[size_t(v) * NE + i], q0b[v]);
+      for (int v = 0; v < 4; ++v) unsafeAtomicAdd(&w.qbar[size_t(v) * NE + i], q0b[v]);
     }
     if (!valid) continue;
     // weights: om_s = lambda_s / (sigma_s + eps)^8, W = sum om_s w_s / sum om_s
@@ -398,12 +398,12 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         double t = 0.0;
 #pragma unroll
         for (int l = 0; l < nu; ++l) t += a[l] * u[l][v];
-        atomicAdd(&w.qbar[size_t(v) * NE + j], t);
+        unsafeAtomicAdd(&w.qbar[size_t(v) * NE + j], t);
         sumb[v] += t;
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) atomicAdd(&w.qbar[size_t(v) * NE + i], -sumb[v]);
+    for (int v = 0; v < 4; ++v) unsafeAtomicAdd(&w.qbar[size_t(v) * NE + i], -sumb[v]);
   }
 }
 

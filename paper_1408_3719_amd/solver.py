@@ -135,9 +135,15 @@ class Solver(_Base):
         self.upload_state(Q0, t0)
 
     def upload_state(self, Q0, t0=0.0):
+        """Q0: (NE, 4) array, or a device tensor [4][NE] (used in place)."""
         torch = self.torch
-        q = torch.as_tensor(np.ascontiguousarray(np.asarray(Q0, np.float64).T), device=self.device)
-        q = q.contiguous()
+        if torch.is_tensor(Q0) and Q0.is_cuda:
+            q = Q0.to(dtype=torch.float64).contiguous()
+            if tuple(q.shape) != (4, self.NE):
+                raise ValueError(f"a device state must be [4][{self.NE}]")
+        else:
+            q = torch.as_tensor(np.ascontiguousarray(np.asarray(Q0, np.float64).T), device=self.device)
+            q = q.contiguous()
         _check(self.lib, self.ctx, self.lib.ader_upload_state(self.ctx, ctypes.c_void_p(q.data_ptr()), t0))
         self.stream.synchronize()
 
@@ -182,6 +188,13 @@ class Solver(_Base):
         st = _lib.AderStats()
         _check(self.lib, self.ctx, self.lib.ader_get_stats(self.ctx, ctypes.byref(st)))
         return self._stats(st)
+
+    def download_q(self):
+        """The cell averages as a device tensor [4][NE]."""
+        Q = self.torch.empty((4, self.NE), dtype=self.torch.float64, device=self.device)
+        _check(self.lib, self.ctx, self.lib.ader_download_state(
+            self.ctx, ctypes.c_void_p(Q.data_ptr()), None, None))
+        return Q
 
     def download(self):
         """(Q (NE,4), node positions (NV,2), element times (NE,)) as numpy."""

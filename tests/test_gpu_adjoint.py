@@ -147,3 +147,38 @@ def test_adjoint_full_size_against_gpu_differences_and_conservation():
         exp = np.zeros((NE, 4))
         exp[:, var] = A
         assert np.abs(out[far] - exp[far]).max() <= 1e-12 * A.max(), var
+
+
+@pytest.mark.parametrize("every", [2, 10])
+def test_trajectory_gradient_matches_oracle(every):
+    """Gradient of a weighted sum of Q^5 with respect to Q^0 through five
+    steps (torch.autograd.Function over the library's steps and adjoints,
+    checkpoints every `every` steps) against autograd through five oracle
+    steps."""
+    import torch
+
+    from paper_1408_3719_amd.trajectory import gts_trajectory
+    mesh, Q0 = _case("vortex", 2)
+    cfg = OConfig(M=2, levels=1, mesh_velocity="eulerian")
+    o = GTSSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+    dt = 0.4 * float(o.dtcfl.min())
+    st = EulerianStep(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+    rng = np.random.default_rng(7)
+    W = rng.standard_normal(Q0.shape)
+    q = torch.tensor(Q0, dtype=torch.float64, requires_grad=True)
+    x = q
+    for _ in range(5):
+        x = st(x, dt)
+    (x * torch.tensor(W)).sum().backward()
+    ref_q5, ref_g = x.detach().numpy(), q.grad.numpy()
+
+    g = _solver(mesh, Q0, 2)
+    q0 = torch.tensor(Q0.T.copy(), dtype=torch.float64, device="cuda", requires_grad=True)
+    q5 = gts_trajectory(g, q0, dt, 5, every=every)
+    (q5 * torch.tensor(W.T.copy(), device="cuda")).sum().backward()
+    got_q5 = q5.detach().cpu().numpy().T
+    got_g = q0.grad.cpu().numpy().T
+    assert np.abs(got_q5 - ref_q5).max() <= TOL * np.abs(ref_q5).max()
+    for v in range(4):
+        err = np.abs(got_g[:, v] - ref_g[:, v]).max() / np.abs(ref_g[:, v]).max()
+        assert err < TOL, (v, err)
