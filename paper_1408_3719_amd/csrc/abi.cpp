@@ -114,6 +114,8 @@ size_t carve(ader_ctx* c, char* base) {
   d.sten = pi(size_t(aw::NSTEN) * ne * NE);
   d.sched_ptr = pi(NE + 1);
   d.sched_idx = pi(t.sched_idx.size());
+  d.tsten_ptr = pi(NE + 1);
+  d.tsten_idx = pi(t.tsten_idx.size());
   d.X = pd(2 * NV);
   d.Xnew = pd(2 * NV);
   d.ntick = pi(NV);
@@ -717,6 +719,8 @@ int ader_bind_workspace(ader_ctx* c, void* dev_ptr, size_t bytes) {
   if ((r = h2d(c, d.sten, st.data(), st.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.sched_ptr, t.sched_ptr.data(), t.sched_ptr.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.sched_idx, t.sched_idx.data(), t.sched_idx.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.tsten_ptr, t.tsten_ptr.data(), t.tsten_ptr.size() * sizeof(int)))) return r;
+  if ((r = h2d(c, d.tsten_idx, t.tsten_idx.data(), t.tsten_idx.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.ring_ptr, t.ring_ptr.data(), t.ring_ptr.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.ring_ent, t.ring_ent.data(), t.ring_ent.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.wall_n, wn.data(), wn.size() * sizeof(double)))) return r;

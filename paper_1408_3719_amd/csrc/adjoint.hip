@@ -9,7 +9,6 @@
 //   eqn.rusanov, eqn.STint) -> one-step update (eq. PDEfinal, |T'| = |T|).
 // Given qbar_next = dL/dQ^{n+1} the kernels return qbar = dL/dQ^n, with dt
 // held fixed (the CFL step of eq. eqn.timestep is not differentiated):
-//   k_adj_init        qbar = qbar_next (the identity part of the update)
 //   k_adj_recon<fwd>  reconstruction from the current averages (8 lanes per
 //                     element, lane s solves stencil s by Givens rotations)
 //   k_adj_pred_fwd    predictor sweeps, each iterate kept, edge traces
@@ -19,9 +18,12 @@
 //                     trace adjoints (each (element, edge) slot has one writer)
 //   k_adj_pred_rev    the sweeps in reverse: trace adjoint -> adjoint of the
 //                     reconstruction's nodal values
-//   k_adj_recon<rev>  WENO weights and least squares in reverse; the stencil
-//                     rows are rebuilt and their adjoints added to qbar of the
-//                     stencil elements with atomics
+//   k_adj_recon<rev>  WENO weights and least squares in reverse from the data
+//                     the forward pass kept; each stencil row's adjoint goes to
+//                     a slot of its own
+//   k_adj_gather      qbar_j = qbar_next_j (the identity part of the update) +
+//                     the slots of every stencil row that names element j, in a
+//                     fixed order (no atomics: each average is named by ~80 rows)
 // Subgradients: the larger Rusanov signal speed is taken from the left state
 // on ties, and |x| has derivative sign(x), 0 at 0.
 // The least-squares adjoint uses A R^-1 = Q of the QR factorisation: the
@@ -49,6 +51,10 @@ struct AZ {
   static constexpr int TS = trace_stride(M);
   static constexpr int WS = wnod_stride(M);
   static constexpr int QS = nb * T * 4;   // nodal space-time values of one element
+  // kept per stencil lane by the forward reconstruction: R (upper triangle),
+  // solution, weight and indicator, rows
+  static constexpr int L_R = 0, L_W = nu * (nu + 1) / 2, L_OM = L_W + 4 * nu, L_SIG = L_OM + 1,
+                       L_ROW = L_SIG + 1, LB = L_ROW + (ne - 1) * nu;
 };
 
 // Euler fluxes f, g (eq. eulerTerms) with p from eq. eqn.eos.
@@ -210,10 +216,43 @@ __device__ inline void ls_row(const Tables* tb, const double* Xj, const double X
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_adj_init(Dev d, AdjWork w) {
-  const size_t n = size_t(4) * d.NE;
-  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x)
-    w.qbar[k] = w.qbar_next[k];
+// qbar_j = qbar_next_j + own terms of j (row 0, 8 lanes) + rows naming j.
+// 8 lanes per element: lane s takes own slot s and every 8th naming row, two
+// rows in flight; a butterfly sums the lanes (a fixed order: deterministic).
+template <int M>
+__global__ void __launch_bounds__(TPB) k_adj_gather(Dev d, AdjWork w) {
+  const int NE = d.NE;
+  const int sl = threadIdx.x & 7;
+  const int ngroups = (gridDim.x * blockDim.x) >> 3;
+  for (int j = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; j < NE; j += ngroups) {
+    const double* own = w.rowbar + (size_t(j) * AZ<M>::ne * 8 + sl) * 4;
+    double acc[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = own[v];
+    const int k1 = d.tsten_ptr[j + 1];
+    int k = d.tsten_ptr[j] + sl;
+    for (; k + 8 < k1; k += 16) {
+      const double* r0 = w.rowbar + size_t(d.tsten_idx[k]) * 4;
+      const double* r1 = w.rowbar + size_t(d.tsten_idx[k + 8]) * 4;
+      double a0[4], a1[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        a0[v] = r0[v];
+        a1[v] = r1[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] += a0[v] + a1[v];
+    }
+    if (k < k1) {
+      const double* r0 = w.rowbar + size_t(d.tsten_idx[k]) * 4;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] += r0[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = group8_sum(acc[v]);
+    const double mine = sl == 0 ? acc[0] : sl == 1 ? acc[1] : sl == 2 ? acc[2] : acc[3];
+    if (sl < 4) w.qbar[size_t(sl) * NE + j] = w.qbar_next[size_t(sl) * NE + j] + mine;
+  }
 }
 
 // Reconstruction (REV = false: write the nodal values) or its adjoint (REV =
@@ -238,6 +277,9 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
     const double idet = 1.0 / (e1x * e2y - e2x * e1y);
     const int* sidx = d.sten + size_t(sl * ne) * NE + i;    // row c at sidx[c * NE]
     const bool valid = sl < NSTEN && sidx[0] >= 0;
+    // kept data of this lane: slot k at lq[k * 8 * NE]
+    double* lq = w.lsq + size_t(i) * 8 + sl;
+    const size_t LS = size_t(8) * NE;
     double R[nu][nu], ws[nu][4];
     double om = 0.0, sig = 0.0;
 #pragma unroll
@@ -247,7 +289,19 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll
       for (int v = 0; v < 4; ++v) ws[a][v] = 0.0;
     }
-    if (valid) {
+    if (REV && valid) {
+      int k = S::L_R;
+#pragma unroll
+      for (int a = 0; a < nu; ++a)
+#pragma unroll
+        for (int b = a; b < nu; ++b) R[a][b] = lq[(k++) * LS];
+#pragma unroll
+      for (int a = 0; a < nu; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ws[a][v] = lq[(S::L_W + a * 4 + v) * LS];
+      om = lq[S::L_OM * LS];
+      sig = lq[S::L_SIG * LS];
+    } else if (valid) {
       double z[nu][4];
 #pragma unroll
       for (int a = 0; a < nu; ++a)
@@ -258,6 +312,8 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         const double* rj = d.rec + size_t(sidx[c * NE]) * S::RS;
         double a[nu], b[4];
         ls_row<M>(tb, rj + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
+#pragma unroll
+        for (int l = 0; l < nu; ++l) lq[(S::L_ROW + (c - 1) * nu + l) * LS] = a[l];
 #pragma unroll
         for (int v = 0; v < 4; ++v) b[v] = rj[QO + v] - Qi[v];
 #pragma unroll
@@ -304,6 +360,17 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
       const double x = sig + P.eps;
       const double x2 = x * x, x4 = x2 * x2;
       om = (sl == 0 ? P.lambda : 1.0) / (x4 * x4);
+      int k = S::L_R;
+#pragma unroll
+      for (int a = 0; a < nu; ++a)
+#pragma unroll
+        for (int b = a; b < nu; ++b) lq[(k++) * LS] = R[a][b];
+#pragma unroll
+      for (int a = 0; a < nu; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lq[(S::L_W + a * 4 + v) * LS] = ws[a][v];
+      lq[S::L_OM * LS] = om;
+      lq[S::L_SIG * LS] = sig;
     }
     // combined reconstruction W = sum_s om_s w_s / sum_s om_s
     const double Ssum = group8_sum(om);
@@ -344,11 +411,15 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll
         for (int l = 0; l < nu; ++l) Wb[l][v] += tb->psiNodes[m][l + 1] * b;
       }
-    if (sl == 7) {
+    // row c of this lane's stencil: slot ((i * ne + c) * 8 + sl); row 0 holds
+    // the element's own terms
+    double* rb = w.rowbar + (size_t(i) * ne * 8 + sl) * 4;
+    constexpr int RB = 32;
+    if (!valid) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) unsafeAtomicAdd(&w.qbar[size_t(v) * NE + i], q0b[v]);
+      for (int v = 0; v < 4; ++v) rb[v] = sl == 7 ? q0b[v] : 0.0;
+      continue;
     }
-    if (!valid) continue;
     // weights: om_s = lambda_s / (sigma_s + eps)^8, W = sum om_s w_s / sum om_s
     double omb = 0.0;
 #pragma unroll
@@ -390,20 +461,20 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll 1
     for (int c = 1; c < ne; ++c) {
       const int j = sidx[c * NE];
-      const double* rj = d.rec + size_t(j) * S::RS;
       double a[nu];
-      ls_row<M>(tb, rj + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
+#pragma unroll
+      for (int l = 0; l < nu; ++l) a[l] = lq[(S::L_ROW + (c - 1) * nu + l) * LS];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double t = 0.0;
 #pragma unroll
         for (int l = 0; l < nu; ++l) t += a[l] * u[l][v];
-        unsafeAtomicAdd(&w.qbar[size_t(v) * NE + j], t);
+        rb[c * RB + v] = t;
         sumb[v] += t;
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) unsafeAtomicAdd(&w.qbar[size_t(v) * NE + i], -sumb[v]);
+    for (int v = 0; v < 4; ++v) rb[v] = -sumb[v];
   }
 }
 
@@ -740,38 +811,54 @@ int grid_for(long n) {
 
 template <int M>
 int adjoint_gts(const Dev& d, const Params& p, const AdjWork& w, double dt, void* s) {
-  AD_LAUNCH(k_adj_init, 4L * d.NE, s, d, w);
   AD_LAUNCH((k_adj_recon<M, false>), 8L * d.NE, s, d, d.tab, p, w);
   AD_LAUNCH(k_adj_pred_fwd<M>, d.NE, s, d, d.tab, p, w, dt);
   AD_LAUNCH(k_adj_patch<M>, d.NF, s, d, d.tab, p, w, dt);
   AD_LAUNCH(k_adj_pred_rev<M>, d.NE, s, d, d.tab, p, w, dt);
   AD_LAUNCH((k_adj_recon<M, true>), 8L * d.NE, s, d, d.tab, p, w);
+  AD_LAUNCH(k_adj_gather<M>, 8L * d.NE, s, d, w);
   return 0;
 }
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+int lsq_slots(int M) {
+  switch (M) {
+    case 1: return AZ<1>::LB;
+    case 2: return AZ<2>::LB;
+    default: return AZ<3>::LB;
+  }
+}
+
+// Buffer sizes in bytes: nodal values, traces, sweeps, kept least-squares data.
+void adjoint_sizes(int M, int NE, int npic, size_t& ws, size_t& ts, size_t& sw, size_t& lq,
+                   size_t& rb) {
+  const size_t nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, D = sizeof(double);
+  ws = align256(NE * size_t(wnod_stride(M)) * D);
+  ts = align256(NE * size_t(trace_stride(M)) * D);
+  sw = align256(size_t(npic) * nb * T * 4 * NE * D);
+  lq = align256(size_t(lsq_slots(M)) * 8 * NE * D);
+  rb = align256(size_t(2 * nb) * NE * 32 * D);
+}
+
 }  // namespace
 
 size_t adjoint_work_bytes(int M, int NE, int npic) {
-  const size_t nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, D = sizeof(double);
-  const size_t ws = align256(NE * size_t(wnod_stride(M)) * D);
-  const size_t ts = align256(NE * size_t(trace_stride(M)) * D);
-  const size_t sw = align256(size_t(npic) * nb * T * 4 * NE * D);
-  return 2 * ws + 2 * ts + sw;
+  size_t ws, ts, sw, lq, rb;
+  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb);
+  return 2 * ws + 2 * ts + sw + lq + rb;
 }
 
 void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w) {
-  const size_t nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, D = sizeof(double);
-  const size_t ws = align256(NE * size_t(wnod_stride(M)) * D);
-  const size_t ts = align256(NE * size_t(trace_stride(M)) * D);
+  size_t ws, ts, sw, lq, rb;
+  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb);
   w.wnod = (double*)base;
   w.wbar = (double*)(base + ws);
   w.trace = (double*)(base + 2 * ws);
   w.tbar = (double*)(base + 2 * ws + ts);
   w.sweeps = (double*)(base + 2 * ws + 2 * ts);
-  (void)nb;
-  (void)T;
+  w.lsq = (double*)(base + 2 * ws + 2 * ts + sw);
+  w.rowbar = (double*)(base + 2 * ws + 2 * ts + sw + lq);
 }
 
 int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt, void* s) {

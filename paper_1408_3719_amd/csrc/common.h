@@ -122,6 +122,7 @@ struct Dev {
   double *dtcfl, *QM, *HM;   // SoA: [NE], [4][NE], [3][NE]
   int *act_stamp, *act_list;
   const int *tri, *elem_edges, *neigh, *sten, *sched_ptr, *sched_idx;   // SoA [k][NE]
+  const int *tsten_ptr, *tsten_idx;   // stencil rows naming each element (adjoint gather)
   // nodes
   double *X, *Xnew;   // [2][NV]
   int *ntick, *ntick_new, *node_stamp;
@@ -144,6 +145,10 @@ struct AdjWork {
   double* tbar;              // [NE][trace_stride] their adjoints
   double* wbar;              // [NE][wnod_stride] adjoint of the reconstruction
   double* sweeps;            // [npic][nb*(M+1)*4][NE] predictor iterate before each sweep
+  double* lsq;               // [slot][NE][8] per stencil lane: R factor, solution, weight,
+                             // indicator and least-squares rows of the forward pass
+  double* rowbar;            // [NE][ne][8][4] adjoint of each stencil row's right-hand side
+                             // (row 0: the element's own terms), summed by the gather
 };
 
 // Bytes of the adjoint workspace (each buffer 256-byte aligned).

@@ -22,6 +22,9 @@ struct Topology {
   std::vector<int> ring_ptr, ring_ent;    // node -> (element*4 + local vertex), by element
   std::vector<int> sten;                  // [NE][7][ne], -1 rows: dropped
   std::vector<int> sched_ptr, sched_idx;  // symmetric scheduling stencils (sorted)
+  // for each element j, the stencil rows (c >= 1) that name it, as slots
+  // ((i * ne + c) * 8 + s) of row c of stencil s of element i, ascending
+  std::vector<int> tsten_ptr, tsten_idx;
   std::vector<double> wall_n;             // [NV][2] slip-wall unit normal or 0
   std::vector<int> wall_pin;              // [NV]
 };

@@ -298,6 +298,24 @@ void build_topology(int M, int NV, const double* xy, int NE, const int* tri_in, 
     t.sched_idx.insert(t.sched_idx.end(), S[i].begin(), S[i].end());
     t.sched_ptr[i + 1] = int(t.sched_idx.size());
   }
+  // transposed stencil rows (counting sort by the element named)
+  t.tsten_ptr.assign(NE + 1, 0);
+  for (int i = 0; i < NE; ++i)
+    for (int s = 0; s < NSTEN; ++s) {
+      const int* st = &t.sten[(size_t(i) * NSTEN + s) * ne];
+      if (st[0] < 0) continue;
+      for (int c = 1; c < ne; ++c) t.tsten_ptr[st[c] + 1]++;
+    }
+  for (int j = 0; j < NE; ++j) t.tsten_ptr[j + 1] += t.tsten_ptr[j];
+  t.tsten_idx.assign(t.tsten_ptr[NE], 0);
+  std::vector<int> fill(t.tsten_ptr.begin(), t.tsten_ptr.end() - 1);
+  for (int i = 0; i < NE; ++i)
+    for (int c = 1; c < ne; ++c)
+      for (int s = 0; s < NSTEN; ++s) {
+        const int* st = &t.sten[(size_t(i) * NSTEN + s) * ne];
+        if (st[0] < 0) continue;
+        t.tsten_idx[fill[st[c]]++] = (i * ne + c) * 8 + s;
+      }
 }
 
 }  // namespace aw
