@@ -101,7 +101,9 @@ int ader_create(const ader_config* cfg, void* hip_stream, ader_ctx** out);
  * the symmetric scheduling stencils (eqs. stencil, eqn.WENOstencil and the
  * discussion after eqn.WENOupdate).  No device call.  ADER_E_MESH on a
  * clockwise or degenerate triangle, a non-manifold edge, a boundary list
- * that does not match the mesh, or a mesh too small for the central stencil. */
+ * that does not match the mesh, or a mesh too small for the central stencil.
+ * ADER_E_ARG on an empty mesh or n_elems * n_e * 8 >= 2^31 (32-bit indices of
+ * the stencil rows: 13.4 M triangles at M = 3, 22 M at M = 2). */
 int ader_upload_mesh(ader_ctx* ctx, int32_t n_nodes, const double* node_xy,
                      int32_t n_elems, const int32_t* tri,
                      int32_t n_bedges, const int32_t* bedge);
@@ -229,13 +231,16 @@ int ader_get_stats(ader_ctx* ctx, ader_stats* st);
  *   TOPO_EDGES [NF][6] int32: a, b, L, R, local edge in L, in R (-1)
  *   TOPO_STENCILS [NE][7][n_e] int32 (-1 rows: dropped sector stencil)
  *   TOPO_SCHED_PTR [NE+1] int32, TOPO_SCHED_IDX [nnz] int32
+ *   TOPO_TSTEN_PTR [NE+1] int32, TOPO_TSTEN_IDX [nnz] int32: for each element j
+ *     the stencil rows that name it, as (i * n_e + c) * 8 + s (row c >= 1 of
+ *     stencil s of element i), ascending (the adjoint's gather lists)
  *   TAB_* host tables: see ader_debug_size. */
 enum {
   ADER_DBG_Q = 0, ADER_DBG_A, ADER_DBG_XE, ADER_DBG_TICK, ADER_DBG_STEP, ADER_DBG_DTCFL,
   ADER_DBG_QM, ADER_DBG_HM, ADER_DBG_WNOD, ADER_DBG_AVG, ADER_DBG_TRACE, ADER_DBG_VVEL,
   ADER_DBG_X, ADER_DBG_NTICK, ADER_DBG_SCAL,
   ADER_DBG_TOPO_EDGES = 32, ADER_DBG_TOPO_STENCILS, ADER_DBG_TOPO_SCHED_PTR,
-  ADER_DBG_TOPO_SCHED_IDX,
+  ADER_DBG_TOPO_SCHED_IDX, ADER_DBG_TOPO_TSTEN_PTR, ADER_DBG_TOPO_TSTEN_IDX,
   ADER_DBG_TAB_DXI = 48, ADER_DBG_TAB_DETA, ADER_DBG_TAB_AMEAN, ADER_DBG_TAB_EDGE,
   ADER_DBG_TAB_AT, ADER_DBG_TAB_BT, ADER_DBG_TAB_DT, ADER_DBG_TAB_PSIC, ADER_DBG_TAB_SIGMA,
   ADER_DBG_TAB_GAUSS

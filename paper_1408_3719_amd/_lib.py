@@ -13,10 +13,11 @@ E_NAMES = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_STATE", -4: "E_GEOM", -5: 
 DBG = dict(Q=0, A=1, XE=2, TICK=3, STEP=4, DTCFL=5, QM=6, HM=7, WNOD=8, AVG=9, TRACE=10,
            VVEL=11, X=12, NTICK=13, SCAL=14,
            TOPO_EDGES=32, TOPO_STENCILS=33, TOPO_SCHED_PTR=34, TOPO_SCHED_IDX=35,
+           TOPO_TSTEN_PTR=36, TOPO_TSTEN_IDX=37,
            TAB_DXI=48, TAB_DETA=49, TAB_AMEAN=50, TAB_EDGE=51, TAB_AT=52, TAB_BT=53, TAB_DT=54,
            TAB_PSIC=55, TAB_SIGMA=56, TAB_GAUSS=57)
 INT_ARRAYS = {"TICK", "STEP", "NTICK", "TOPO_EDGES", "TOPO_STENCILS", "TOPO_SCHED_PTR",
-              "TOPO_SCHED_IDX"}
+              "TOPO_SCHED_IDX", "TOPO_TSTEN_PTR", "TOPO_TSTEN_IDX"}
 
 EXPORTED = ["ader_create", "ader_upload_mesh", "ader_workspace_size", "ader_bind_workspace",
             "ader_upload_state", "ader_step_gts", "ader_step_lts", "ader_download_state",

@@ -449,6 +449,8 @@ Arr lookup(ader_ctx* c, int what) {
     case ADER_DBG_TOPO_STENCILS: a.host = t.sten.data(); a.bytes = t.sten.size() * I; break;
     case ADER_DBG_TOPO_SCHED_PTR: a.host = t.sched_ptr.data(); a.bytes = t.sched_ptr.size() * I; break;
     case ADER_DBG_TOPO_SCHED_IDX: a.host = t.sched_idx.data(); a.bytes = t.sched_idx.size() * I; break;
+    case ADER_DBG_TOPO_TSTEN_PTR: a.host = t.tsten_ptr.data(); a.bytes = t.tsten_ptr.size() * I; break;
+    case ADER_DBG_TOPO_TSTEN_IDX: a.host = t.tsten_idx.data(); a.bytes = t.tsten_idx.size() * I; break;
     case ADER_DBG_TAB_DXI: a.bytes = nb * nb * D; break;
     case ADER_DBG_TAB_DETA: a.bytes = nb * nb * D; break;
     case ADER_DBG_TAB_AMEAN: a.bytes = nb * D; break;
@@ -635,6 +637,12 @@ int ader_upload_mesh(ader_ctx* c, int32_t n_nodes, const double* node_xy, int32_
   if (n_nodes <= 0 || n_elems <= 0 || n_bedges < 0 || !node_xy || !tri || (n_bedges > 0 && !bedge))
     return fail(c, ADER_E_ARG, "invalid mesh arguments");
   if (c->bound) return fail(c, ADER_E_ORDER, "mesh already bound to a workspace");
+  {
+    // 32-bit indices of stencil rows ((element * ne + row) * 8 + lane)
+    const long long ne = (long long)(c->cfg.M + 1) * (c->cfg.M + 2);
+    if ((long long)n_elems * ne * 8 >= (1LL << 31))
+      return fail(c, ADER_E_ARG, "mesh too large: n_elems * (M+1)(M+2) * 8 must stay below 2^31");
+  }
   try {
     aw::build_topology(c->cfg.M, n_nodes, node_xy, n_elems, tri, n_bedges, bedge, c->topo);
   } catch (const std::exception& e) {

@@ -159,3 +159,42 @@ def test_modal_basis_gives_same_indicator(M):
         vals = P_ora @ f
         ch = np.linalg.lstsq(P_host, vals, rcond=None)[0]
         assert abs(ch @ S @ ch - f @ tb.sigma_matrix(M) @ f) < 1e-10 * (1 + abs(f @ tb.sigma_matrix(M) @ f))
+
+
+def test_degenerate_meshes_rejected():
+    """Two triangles cannot fill a central stencil of n_e elements (the method
+    needs them, eq. stencil): E_MESH, as the oracle refuses them; no element
+    at all is an argument error."""
+    nodes = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+    tris = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    be = np.array([[0, 1, 1], [1, 2, 1], [2, 3, 1], [3, 0, 1]], np.int32)
+    for M in (1, 2, 3):
+        with pytest.raises(_lib.AderError, match="E_MESH"):
+            HostTopology(nodes, tris, be, Config(M=M))
+        with pytest.raises(ValueError, match="too small"):
+            build_topology(nodes, tris, M, be)
+    with pytest.raises(_lib.AderError, match="E_ARG"):
+        HostTopology(np.zeros((0, 2)), np.zeros((0, 3), np.int32), None, Config(M=1))
+
+
+def test_transposed_stencil_rows():
+    """The adjoint's gather lists: every row c >= 1 of every kept stencil
+    appears exactly once, under the element it names, in ascending order."""
+    mesh = square_graded_mesh(0.3, seed=3)
+    for M in (1, 2):
+        host = HostTopology(mesh.nodes, mesh.tris, mesh.bedges, Config(M=M))
+        sten = host.dump("TOPO_STENCILS")             # (NE, 7, ne)
+        NE, _, ne = sten.shape
+        expect = {}
+        for i in range(NE):
+            for s in range(7):
+                if sten[i, s, 0] < 0:
+                    continue
+                for c in range(1, ne):
+                    expect.setdefault(int(sten[i, s, c]), []).append((i * ne + c) * 8 + s)
+        ptr = host.dump("TOPO_TSTEN_PTR")
+        idx = host.dump("TOPO_TSTEN_IDX")
+        assert ptr[0] == 0 and ptr[-1] == idx.size
+        for j in range(NE):
+            got = idx[ptr[j]:ptr[j + 1]].tolist()
+            assert got == sorted(expect.get(j, [])), j
