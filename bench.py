@@ -16,7 +16,7 @@ Other workloads (not the headline line): --workload explosion (EP1 on the unit
 disk, 8:1 radial grading, 400k triangles, M=2, 4 levels), --workload sod
 (RP1 shock tube, 2k triangles, M=1, one level = GTS), --workload batched
 (256 independent instances in the same launches) or --workload adjoint
-(adjoint/forward time of one global step on a fixed 50k-triangle mesh).
+(gradient through 100 global steps on a fixed 50k-triangle mesh, against the run).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload vortex]
                        [--n-elems N] [--M M] [--levels L]
@@ -125,67 +125,100 @@ print(json.dumps(dict(updates=s.st.updates, seconds=dt, n_elems=mesh.n_elems)))
 
 
 def bench_adjoint(a):
-    """Adjoint of one global time step on a fixed mesh: EP1 explosion on a
-    50k-triangle 8:1 graded disk, M=2, Rusanov flux, dt = the smallest CFL
-    step held fixed. Forward = ader_step_gts of one step (pre-step
-    reconstruction included), adjoint = ader_adjoint_gts_step from the same
-    state; both timed over K calls with the state resident in HBM."""
+    """Gradient through a run of global steps on a fixed mesh: EP1 explosion on
+    a 50k-triangle 8:1 graded disk, M=2, Rusanov flux, 100 steps of a fixed dt
+    (half the smallest initial CFL step), checkpoints every 10 steps, J = total
+    energy inside r < 0.3 at the final time, gradient with respect to the
+    initial averages. value = backward time (the adjoint steps and the
+    recomputation inside the checkpoint segments) / forward time of the run.
+    Also per step: ader_adjoint_gts_step against one ader_step_gts from the
+    same state. States resident in HBM throughout."""
     import numpy as np
     import torch
 
     from paper_1408_3719_amd import Config, Solver
+    from paper_1408_3719_amd.trajectory import gts_trajectory
     from workloads import explosion_case
 
     n = a.n_elems or 50_000
     M = a.M or 2
+    n_steps, every = 100, 10
     mesh, Q0 = explosion_case(n, seed=7)
+    NE = mesh.n_elems
     s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=1, mesh_velocity="eulerian"))
-    dt = float(s.dump("DTCFL").min())
+    dt = 0.5 * float(s.dump("DTCFL").min())
+    p = mesh.nodes[mesh.tris]
+    A = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+               - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    c = p.mean(axis=1)
+    W = np.zeros((4, NE))
+    inner = np.hypot(c[:, 0], c[:, 1]) < 0.3
+    W[3, inner] = A[inner]
+    Wd = torch.tensor(W, device="cuda")
     sync = torch.cuda.synchronize
-    # forward: K single steps of length dt from the initial state
-    for _ in range(a.warmup):
-        s.upload_state(Q0, 0.0)
-        s.step_gts(dt, 1)
-    t_f = 0.0
-    for _ in range(a.steps):
+
+    def run(every):
+        t_f = t_b = 0.0
+        for k in range(a.warmup + a.steps):
+            q0 = torch.tensor(Q0.T.copy(), device="cuda", requires_grad=True)
+            sync()
+            t0 = time.perf_counter()
+            Jv = (gts_trajectory(s, q0, dt, n_steps, every=every) * Wd).sum()
+            sync()
+            t1 = time.perf_counter()
+            Jv.backward()
+            sync()
+            t2 = time.perf_counter()
+            if k >= a.warmup:
+                t_f += t1 - t0
+                t_b += t2 - t1
+        assert torch.isfinite(q0.grad).all()
+        return t_f, t_b, q0.grad
+
+    t_f, t_b, g10 = run(every)
+    t_f1, t_b1, g1 = run(1)
+    # the checkpoint spacing changes only rounding (recomputed steps restart
+    # from a checkpoint's time)
+    assert float((g10 - g1).abs().max()) <= 1e-10 * float(g1.abs().max())
+    # one step each, from the same state
+    s.upload_state(Q0, 0.0)
+    qb = torch.tensor(np.random.default_rng(0).standard_normal((4, NE)), device="cuda")
+    for _ in range(3):
+        s.adjoint_gts_step(dt, qb)
+    sync()
+    K = 20
+    t0 = time.perf_counter()
+    for _ in range(K):
+        s.adjoint_gts_step(dt, qb)
+    sync()
+    ms_adj = (time.perf_counter() - t0) / K * 1e3
+    ms_fwd = 0.0
+    for _ in range(K):
         s.upload_state(Q0, 0.0)
         sync()
         t0 = time.perf_counter()
         s.step_gts(dt, 1)
         sync()
-        t_f += time.perf_counter() - t0
-    # adjoint from the same state
-    s.upload_state(Q0, 0.0)
-    rng = np.random.default_rng(0)
-    qb = torch.tensor(rng.standard_normal((4, mesh.n_elems)), device="cuda")
-    for _ in range(a.warmup):
-        s.adjoint_gts_step(dt, qb)
-    sync()
-    s.set_profiling(True)
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        out = s.adjoint_gts_step(dt, qb)
-    sync()
-    t_a = time.perf_counter() - t0
-    kt = s.kernel_times()
-    s.set_profiling(False)
-    assert torch.isfinite(out).all()
-    ms_f, ms_a = t_f / a.steps * 1e3, t_a / a.steps * 1e3
+        ms_fwd += (time.perf_counter() - t0) / K * 1e3
     line = {
-        "metric": "adjoint/forward time of one global step",
-        "value": ms_a / ms_f,
+        "metric": "adjoint/forward time (gradient of J through 100 global steps)",
+        "value": t_b / t_f,
         "unit": "ratio",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms_a,
+        "ms_per_step": t_b / a.steps * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"EP1 explosion, {mesh.n_elems}-triangle 8:1 radially graded disk, "
-                               f"M={M}, fixed mesh, one global step of the smallest CFL step, Rusanov",
-                   "n_elems": mesh.n_elems, "M": M, "parallelism": "single GPU"},
-        "forward_ms_per_step": ms_f,
-        "adjoint_ms_per_step": ms_a,
-        "adjoint_elements_per_s": mesh.n_elems / (ms_a * 1e-3),
-        "adjoint_hip_event_ms": kt["adjoint"][0] / max(kt["adjoint"][1], 1),
+        "config": {"workload": f"EP1 explosion, {NE}-triangle 8:1 radially graded disk, M={M}, fixed mesh, "
+                               f"{n_steps} global steps of dt = half the smallest CFL step, checkpoints every "
+                               f"{every}, J = energy in r < 0.3, Rusanov",
+                   "n_elems": NE, "M": M, "n_steps": n_steps, "checkpoint_every": every,
+                   "parallelism": "single GPU"},
+        "forward_s_per_run": t_f / a.steps,
+        "gradient_s_per_run": t_b / a.steps,
+        "per_step": {"forward_ms": ms_fwd, "adjoint_ms": ms_adj, "ratio": ms_adj / ms_fwd},
+        "all_states_kept": {"forward_s_per_run": t_f1 / a.steps, "gradient_s_per_run": t_b1 / a.steps,
+                            "ratio": t_b1 / t_f1},
+        "note": "steps are timed one host call each; ms_per_step is the gradient time of one run",
     }
     print(json.dumps(line))
 

@@ -197,19 +197,23 @@ int ader_set_graphs(ader_ctx* ctx, int32_t on);
  * the CFL step of eq. eqn.timestep on the state is not differentiated);
  * subgradients: the larger Rusanov signal speed is taken from the left state
  * on ties, d|x|/dx = 0 at 0.  It does not change the simulation state.
+ *   Q_dev: device [4][n_elems] SoA averages Q^n to differentiate at, or NULL
+ *     for the context's current averages (then every element must be at one
+ *     common time);
  *   Qbar_next_dev, Qbar_dev: device [4][n_elems] SoA (same layout as Q),
  *     not overlapping;
  *   work_dev: caller device memory of at least ader_adjoint_workspace_size
  *     bytes, 256-byte aligned, used as scratch by the call only.
- * Preconditions: a single instance, state uploaded, every element at one
- * common time (after ader_upload_state or a completed stepping call; not
- * after the test hooks) -> else ADER_E_ARG / ADER_E_ORDER.  Queued on the
+ * Preconditions: a single instance, state uploaded (the fixed geometry), and
+ * with Q_dev == NULL every element at one common time (after
+ * ader_upload_state or a completed stepping call; not after the test hooks)
+ * -> else ADER_E_ARG / ADER_E_ORDER.  Queued on the
  * context's stream; no synchronisation.  The step that
  * ader_step_gts(ctx, t + dt, 1, ...) takes from the same state is the one
  * differentiated when dt is at most the smallest CFL step. */
 int ader_adjoint_workspace_size(const ader_ctx* ctx, size_t* bytes);
-int ader_adjoint_gts_step(ader_ctx* ctx, double dt, const double* Qbar_next_dev, double* Qbar_dev,
-                          void* work_dev, size_t work_bytes);
+int ader_adjoint_gts_step(ader_ctx* ctx, double dt, const double* Q_dev, const double* Qbar_next_dev,
+                          double* Qbar_dev, void* work_dev, size_t work_bytes);
 
 /* Current state into caller device buffers (any may be NULL):
  * Q_dev [4][n_elems] SoA, node_xy_dev [n_nodes][2], elem_t_dev [n_elems]. */

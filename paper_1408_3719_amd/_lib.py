@@ -92,7 +92,7 @@ def load():
     lib.ader_instance_times.argtypes = [P, i32, P]
     lib.ader_kernel_times.argtypes = [P, i32, P, P]
     lib.ader_adjoint_workspace_size.argtypes = [P, P]
-    lib.ader_adjoint_gts_step.argtypes = [P, dbl, P, P, P, ctypes.c_size_t]
+    lib.ader_adjoint_gts_step.argtypes = [P, dbl, P, P, P, P, ctypes.c_size_t]
     lib.ader_last_error.argtypes = [P]
     lib.ader_last_error.restype = ctypes.c_char_p
     lib.ader_destroy.argtypes = [P]

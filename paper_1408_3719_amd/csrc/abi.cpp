@@ -1038,15 +1038,16 @@ int ader_adjoint_workspace_size(const ader_ctx* c, size_t* bytes) {
   return ADER_OK;
 }
 
-int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Qbar_next_dev, double* Qbar_dev,
-                          void* work_dev, size_t work_bytes) {
+int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Q_dev, const double* Qbar_next_dev,
+                          double* Qbar_dev, void* work_dev, size_t work_bytes) {
   if (!c || !Qbar_next_dev || !Qbar_dev || !work_dev) return ADER_E_ARG;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, ADER_E_ARG, "dt must be positive and finite");
   if (c->cfg.mesh_velocity != 1) return fail(c, ADER_E_ARG, "the adjoint needs a fixed mesh (mesh_velocity = 1)");
   if (c->cfg.flux != ADER_FLUX_RUSANOV) return fail(c, ADER_E_ARG, "the adjoint covers the Rusanov flux");
   if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the adjoint runs on a single instance");
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
-  if (!c->synced) return fail(c, ADER_E_ORDER, "elements are not at a common time (macro step in progress)");
+  if (!Q_dev && !c->synced)
+    return fail(c, ADER_E_ORDER, "elements are not at a common time (macro step in progress)");
   const size_t need = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->prm.npic);
   if (work_bytes < need) return fail(c, ADER_E_ARG, "adjoint workspace too small");
   if ((reinterpret_cast<uintptr_t>(work_dev) & 255) != 0)
@@ -1055,8 +1056,10 @@ int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Qbar_next_dev, d
   w.qbar_next = Qbar_next_dev;
   w.qbar = Qbar_dev;
   aw::adjoint_carve(c->cfg.M, c->topo.NE, c->prm.npic, static_cast<char*>(work_dev), w);
-  LCHK(c, timed(c, ADER_K_ADJOINT, c->stream,
-                [&] { return aw::launch_adjoint_gts(c->dev, c->prm, c->cfg.M, w, dt, c->stream); }));
+  w.q = Q_dev ? Q_dev : w.qcopy;
+  LCHK(c, timed(c, ADER_K_ADJOINT, c->stream, [&] {
+    return aw::launch_adjoint_gts(c->dev, c->prm, c->cfg.M, w, dt, Q_dev == nullptr, c->stream);
+  }));
   return ADER_OK;
 }
 

@@ -216,6 +216,16 @@ __device__ inline void ls_row(const Tables* tb, const double* Xj, const double X
   }
 }
 
+// The context's averages as [4][NE].
+template <int M>
+__global__ void __launch_bounds__(TPB) k_adj_state(Dev d, AdjWork w) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x) {
+    const double* r = d.rec + size_t(i) * AZ<M>::RS;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) w.qcopy[size_t(v) * d.NE + i] = r[QO + v];
+  }
+}
+
 // qbar_j = qbar_next_j + own terms of j (row 0, 8 lanes) + rows naming j.
 // 8 lanes per element: lane s takes own slot s and every 8th naming row, two
 // rows in flight; a butterfly sums the lanes (a fixed order: deterministic).
@@ -271,7 +281,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll
     for (int c = 0; c < 6; ++c) Xi[c] = ri[XE + c];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Qi[v] = ri[QO + v];
+    for (int v = 0; v < 4; ++v) Qi[v] = w.q[size_t(v) * NE + i];
     const double e1x = Xi[2] - Xi[0], e1y = Xi[3] - Xi[1];
     const double e2x = Xi[4] - Xi[0], e2y = Xi[5] - Xi[1];
     const double idet = 1.0 / (e1x * e2y - e2x * e1y);
@@ -315,7 +325,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll
         for (int l = 0; l < nu; ++l) lq[(S::L_ROW + (c - 1) * nu + l) * LS] = a[l];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) b[v] = rj[QO + v] - Qi[v];
+        for (int v = 0; v < 4; ++v) b[v] = w.q[size_t(v) * NE + sidx[c * NE]] - Qi[v];
 #pragma unroll
         for (int k = 0; k < nu; ++k) {
           const double rkk = R[k][k], ak = a[k];
@@ -810,7 +820,8 @@ int grid_for(long n) {
   } while (0)
 
 template <int M>
-int adjoint_gts(const Dev& d, const Params& p, const AdjWork& w, double dt, void* s) {
+int adjoint_gts(const Dev& d, const Params& p, const AdjWork& w, double dt, bool from_ctx, void* s) {
+  if (from_ctx) AD_LAUNCH(k_adj_state<M>, d.NE, s, d, w);
   AD_LAUNCH((k_adj_recon<M, false>), 8L * d.NE, s, d, d.tab, p, w);
   AD_LAUNCH(k_adj_pred_fwd<M>, d.NE, s, d, d.tab, p, w, dt);
   AD_LAUNCH(k_adj_patch<M>, d.NF, s, d, d.tab, p, w, dt);
@@ -832,26 +843,27 @@ int lsq_slots(int M) {
 
 // Buffer sizes in bytes: nodal values, traces, sweeps, kept least-squares data.
 void adjoint_sizes(int M, int NE, int npic, size_t& ws, size_t& ts, size_t& sw, size_t& lq,
-                   size_t& rb) {
+                   size_t& rb, size_t& qc) {
   const size_t nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, D = sizeof(double);
   ws = align256(NE * size_t(wnod_stride(M)) * D);
   ts = align256(NE * size_t(trace_stride(M)) * D);
   sw = align256(size_t(npic) * nb * T * 4 * NE * D);
   lq = align256(size_t(lsq_slots(M)) * 8 * NE * D);
   rb = align256(size_t(2 * nb) * NE * 32 * D);
+  qc = align256(size_t(4) * NE * D);
 }
 
 }  // namespace
 
 size_t adjoint_work_bytes(int M, int NE, int npic) {
-  size_t ws, ts, sw, lq, rb;
-  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb);
-  return 2 * ws + 2 * ts + sw + lq + rb;
+  size_t ws, ts, sw, lq, rb, qc;
+  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb, qc);
+  return 2 * ws + 2 * ts + sw + lq + rb + qc;
 }
 
 void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w) {
-  size_t ws, ts, sw, lq, rb;
-  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb);
+  size_t ws, ts, sw, lq, rb, qc;
+  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb, qc);
   w.wnod = (double*)base;
   w.wbar = (double*)(base + ws);
   w.trace = (double*)(base + 2 * ws);
@@ -859,13 +871,15 @@ void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w) {
   w.sweeps = (double*)(base + 2 * ws + 2 * ts);
   w.lsq = (double*)(base + 2 * ws + 2 * ts + sw);
   w.rowbar = (double*)(base + 2 * ws + 2 * ts + sw + lq);
+  w.qcopy = (double*)(base + 2 * ws + 2 * ts + sw + lq + rb);
 }
 
-int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt, void* s) {
+int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,
+                       bool state_from_context, void* s) {
   switch (M) {
-    case 1: return adjoint_gts<1>(d, p, w, dt, s);
-    case 2: return adjoint_gts<2>(d, p, w, dt, s);
-    case 3: return adjoint_gts<3>(d, p, w, dt, s);
+    case 1: return adjoint_gts<1>(d, p, w, dt, state_from_context, s);
+    case 2: return adjoint_gts<2>(d, p, w, dt, state_from_context, s);
+    case 3: return adjoint_gts<3>(d, p, w, dt, state_from_context, s);
     default: return int(hipErrorInvalidValue);
   }
 }

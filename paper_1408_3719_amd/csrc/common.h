@@ -138,6 +138,8 @@ struct Dev {
 // Buffers of the reverse-mode step (adjoint.hip), carved from the caller's
 // adjoint workspace; nodal space-time data are element-minor ([slot][NE]).
 struct AdjWork {
+  const double* q;           // [4][NE] averages at the step start (the caller's, or a copy)
+  double* qcopy;             // [4][NE] copy of the context's averages
   const double* qbar_next;   // [4][NE] adjoint of the averages after the step
   double* qbar;              // [4][NE] adjoint of the averages before the step
   double* wnod;              // [NE][wnod_stride] reconstruction at the step start
@@ -158,7 +160,7 @@ void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w);
 // The reverse-mode step: qbar = (dQ^{n+1}/dQ^n)^T qbar_next for one global
 // step of length dt on a fixed mesh (adjoint.hip).
 int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,
-                       void* stream);
+                       bool state_from_context, void* stream);
 
 // Kernel launchers (kernels.hip).  All launch on `stream`, return a
 // hipError_t as int.

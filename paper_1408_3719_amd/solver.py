@@ -150,17 +150,23 @@ class Solver(_Base):
     def _stats(self, st):
         return {f: getattr(st, f) for f, _ in _lib.AderStats._fields_}
 
-    def adjoint_gts_step(self, dt, qbar_next):
-        """(dQ^{n+1}/dQ^n)^T qbar_next for one global step of length dt from the
-        current state on a fixed mesh (dt held fixed).  qbar_next: (NE, 4)
-        array or a device tensor [4][NE]; returns a device tensor [4][NE]."""
+    def _dev4(self, a, what):
         torch = self.torch
-        qn = qbar_next
-        if not torch.is_tensor(qn):
-            qn = torch.as_tensor(np.ascontiguousarray(np.asarray(qn, np.float64).T), device=self.device)
-        qn = qn.to(device=self.device, dtype=torch.float64).contiguous()
-        if tuple(qn.shape) != (4, self.NE):
-            raise ValueError(f"qbar_next must be [4][{self.NE}] on the device or ({self.NE}, 4)")
+        if not torch.is_tensor(a):
+            a = torch.as_tensor(np.ascontiguousarray(np.asarray(a, np.float64).T), device=self.device)
+        a = a.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(a.shape) != (4, self.NE):
+            raise ValueError(f"{what} must be [4][{self.NE}] on the device or ({self.NE}, 4)")
+        return a
+
+    def adjoint_gts_step(self, dt, qbar_next, q=None):
+        """(dQ^{n+1}/dQ^n)^T qbar_next for one global step of length dt on a
+        fixed mesh (dt held fixed), at the averages q (default: the current
+        state).  qbar_next, q: (NE, 4) arrays or device tensors [4][NE];
+        returns a device tensor [4][NE]."""
+        torch = self.torch
+        qn = self._dev4(qbar_next, "qbar_next")
+        qs = self._dev4(q, "q") if q is not None else None
         out = torch.empty_like(qn)
         if getattr(self, "_adj_ws", None) is None:
             n = ctypes.c_size_t()
@@ -169,7 +175,8 @@ class Solver(_Base):
         buf, n = self._adj_ws
         aligned = (buf.data_ptr() + 255) // 256 * 256
         _check(self.lib, self.ctx, self.lib.ader_adjoint_gts_step(
-            self.ctx, dt, ctypes.c_void_p(qn.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            self.ctx, dt, ctypes.c_void_p(qs.data_ptr()) if qs is not None else None,
+            ctypes.c_void_p(qn.data_ptr()), ctypes.c_void_p(out.data_ptr()),
             ctypes.c_void_p(aligned), n))
         return out
 
