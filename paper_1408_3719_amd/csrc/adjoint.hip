@@ -547,11 +547,15 @@ __global__ void __launch_bounds__(TPB) k_adj_pred_fwd(Dev d, const Tables* __res
         for (int kk = 0; kk < nb; ++kk)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            double s = 0.0;
+            double fx = 0.0, fe = 0.0, gx = 0.0, ge = 0.0;
 #pragma unroll
-            for (int m = 0; m < nb; ++m)
-              s += (mt[0] * tb->Dxi[kk][m] + mt[2] * tb->Deta[kk][m]) * f[m][v] +
-                   (mt[1] * tb->Dxi[kk][m] + mt[3] * tb->Deta[kk][m]) * g[m][v];
+            for (int m = 0; m < nb; ++m) {
+              fx += tb->Dxi[kk][m] * f[m][v];
+              fe += tb->Deta[kk][m] * f[m][v];
+              gx += tb->Dxi[kk][m] * g[m][v];
+              ge += tb->Deta[kk][m] * g[m][v];
+            }
+            const double s = mt[0] * fx + mt[2] * fe + mt[1] * gx + mt[3] * ge;
 #pragma unroll
             for (int r = 0; r < M; ++r) qn[kk][r][v] += dt * tb->At[r][t] * (-s);
           }
@@ -768,14 +772,14 @@ __global__ void __launch_bounds__(TPB) k_adj_pred_rev(Dev d, const Tables* __res
           double fb[4], gb[4], q[4], acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            double sf = 0.0, sg = 0.0;
+            double ax = 0.0, ae = 0.0;
 #pragma unroll
             for (int kk = 0; kk < nb; ++kk) {
-              sf += (mt[0] * tb->Dxi[kk][m] + mt[2] * tb->Deta[kk][m]) * Pb[kk][v];
-              sg += (mt[1] * tb->Dxi[kk][m] + mt[3] * tb->Deta[kk][m]) * Pb[kk][v];
+              ax += tb->Dxi[kk][m] * Pb[kk][v];
+              ae += tb->Deta[kk][m] * Pb[kk][v];
             }
-            fb[v] = -sf;
-            gb[v] = -sg;
+            fb[v] = -(mt[0] * ax + mt[2] * ae);
+            gb[v] = -(mt[1] * ax + mt[3] * ae);
             q[v] = st[size_t((m * T + t) * 4 + v) * NE];
           }
           euler_fg_vjp(q, P.gamma, fb, gb, acc);
