@@ -315,7 +315,7 @@ def main():
                     help="1: also run free local steps (levels = 0) over the timed interval")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=5000)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--traffic-sweep", action="store_true",
                     help="repeat the profiled pass for every workgroups-per-CU setting (counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
