@@ -108,6 +108,7 @@ size_t carve(ader_ctx* c, char* base) {
   d.HM = pd(3 * NE);
   d.act_stamp = pi(NE);
   d.act_list = pi(NE);
+  d.live_list = pi(NE);
   d.tri = pi(3 * NE);
   d.elem_edges = pi(3 * NE);
   d.neigh = pi(3 * NE);

@@ -62,10 +62,14 @@ struct Scal {
   double t_end;     // target time of the current call
   int N;            // ticks per macro step 2^(L-1)
   int n_open;       // instances short of the target time
-  int n_active;     // active elements of the current cycle
+  // n_active and n_live share one 8-byte word (little-endian, n_active low):
+  // one 64-bit atomic reserves space in both lists
+  alignas(8) int n_active;  // active elements of the current cycle
+  int n_live;       // active elements that stay short of tick N (they need a new predictor)
   int n_unfinished; // elements that have not reached tick N
   int err;          // sticky error bits (ERR_*)
   int cycle;        // stamp of the current cycle (advanced by the cycle's first kernel)
+  int pad;
   unsigned long long max_gcl_bits;  // max relative GCL residual
   unsigned long long updates;
   unsigned long long overshoots;
@@ -73,6 +77,10 @@ struct Scal {
   unsigned long long n_patch;   // space-time patches integrated
   unsigned long long n_node;    // node moves
 };
+
+static_assert(offsetof(Scal, n_live) == offsetof(Scal, n_active) + sizeof(int) &&
+                  offsetof(Scal, n_active) % 8 == 0,
+              "n_active and n_live must form one aligned 8-byte word");
 
 enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8, ERR_DT = 16 };
 
@@ -121,6 +129,7 @@ struct Dev {
   TickStep* ts;       // [NE]
   double *dtcfl, *QM, *HM;   // SoA: [NE], [4][NE], [3][NE]
   int *act_stamp, *act_list;
+  int* live_list;     // the active elements that stay short of tick N after the update
   const int *tri, *elem_edges, *neigh, *sten, *sched_ptr, *sched_idx;   // SoA [k][NE]
   const int *tsten_ptr, *tsten_idx;   // stencil rows naming each element (adjoint gather)
   // nodes

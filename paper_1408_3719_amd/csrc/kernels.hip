@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
   __shared__ double lds[(SLOTS + WPB) * LSTR];   // one extra slot per wavefront for its spare lanes
   __shared__ double c0[16][TPB];         // per lane: fixed parts of slice t = 0
   const int NE = d.NE;
-  const int nitems = use_list ? d.scal->n_active : NE;
+  const int nitems = use_list ? d.scal->n_live : NE;
   const double g = P.gamma;
   const int wv = threadIdx.x / 64, lw = threadIdx.x % 64;
   const bool spare = lw >= EPW * G;
@@ -626,7 +626,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
   for (int base = xcd_block((nitems + SLOTS - 1) / SLOTS) * SLOTS; base < nitems;
        base += gridDim.x * SLOTS) {
     const int idx = base + slot;
-    const int i = !spare && idx < nitems ? (use_list ? d.act_list[idx] : idx) : -1;
+    const int i = !spare && idx < nitems ? (use_list ? d.live_list[idx] : idx) : -1;
     const int st = i >= 0 ? d.ts[i].step : 0;
     const bool live = st > 0;           // uniform across the lanes of the element
     const bool act = live && node;
@@ -901,24 +901,31 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
 // ---------------------------------------------------------------------------
 __global__ void k_cycle_begin(Dev d) {
   d.scal->n_active = 0;
+  d.scal->n_live = 0;
   d.scal->n_unfinished = 0;
   d.scal->cycle += 1;
 }
 
 // Each block owns a contiguous chunk of at most SCHED_CHUNK elements; 8 lanes
 // per element share the scan of its scheduling stencil; the block gathers its
-// active elements in LDS and reserves list space with one global atomic.
+// active elements in LDS and reserves list space with one global atomic. A
+// second list keeps the active elements that stay short of tick N: only they
+// need a predictor after their update (an element reaching tick N gets its
+// next one at the macro-step start, and no stage reads it before).
 constexpr int SCHED_CHUNK = 1024;
 
 __global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
   const int cycle = d.scal->cycle;
   constexpr int PER_PASS = TPB / 8;
-  __shared__ int local[SCHED_CHUNK];
-  __shared__ int count, gbase;
+  __shared__ int local[SCHED_CHUNK], local_live[SCHED_CHUNK];
+  __shared__ int count, gbase, count_live, gbase_live;
   const int NE = d.NE;
   const int N = d.scal->N;
   const int sub = threadIdx.x & 7;
-  if (threadIdx.x == 0) count = 0;
+  if (threadIdx.x == 0) {
+    count = 0;
+    count_live = 0;
+  }
   __syncthreads();
   const int begin = xcd_block() * chunk;
   const int end = min(NE, begin + chunk);
@@ -953,15 +960,39 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
       mx = max(mx, __shfl_xor(mx, s));
       mn = min(mn, __shfl_xor(mn, s));
     }
-    if (unf && sub == 0 && mx <= fut && fut <= mn) {
-      local[atomicAdd(&count, 1)] = i;
+    // append to both block lists with one LDS atomic per wavefront and list
+    const bool isact = unf && sub == 0 && mx <= fut && fut <= mn;
+    const bool islive = isact && fut < N;
+    const unsigned long long ba = __ballot(isact), bl = __ballot(islive);
+    const int lane = __lane_id();
+    int pa = 0, pl = 0;
+    if (lane == 0) {
+      pa = ba ? atomicAdd(&count, __popcll(ba)) : 0;
+      pl = bl ? atomicAdd(&count_live, __popcll(bl)) : 0;
+    }
+    pa = __shfl(pa, 0);
+    pl = __shfl(pl, 0);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (isact) {
+      local[pa + __popcll(ba & below)] = i;
       d.act_stamp[i] = cycle;
+    }
+    if (islive) local_live[pl + __popcll(bl & below)] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    gbase = gbase_live = 0;
+    if (count) {
+      const unsigned long long both = (unsigned long long)count | ((unsigned long long)count_live << 32);
+      const unsigned long long old =
+          atomicAdd(reinterpret_cast<unsigned long long*>(&d.scal->n_active), both);
+      gbase = int(old & 0xffffffffull);
+      gbase_live = int(old >> 32);
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) gbase = count ? atomicAdd(&d.scal->n_active, count) : 0;
-  __syncthreads();
   for (int k = threadIdx.x; k < count; k += TPB) d.act_list[gbase + k] = local[k];
+  for (int k = threadIdx.x; k < count_live; k += TPB) d.live_list[gbase_live + k] = local_live[k];
 }
 
 // ---------------------------------------------------------------------------
