@@ -460,6 +460,26 @@ def patch_batch(M, cfg: Config, P, ticks, nL, sL, trL, nR, sR, trR, hasR, bc=Non
 # ---------------------------------------------------------------------------
 # Solver state
 # ---------------------------------------------------------------------------
+def level_step(dtcfl, delta, N, n, free):
+    """Step in ticks of an element at tick n of a macro step of N ticks of
+    length delta, and whether it overshoots its CFL step.
+    Dyadic (R2): the largest power of two p <= N with p*delta <= dt_CFL,
+    limited by the alignment of tick n.  Free (R19): floor(dt_CFL / delta),
+    at most the ticks left.  At least one tick."""
+    if free:
+        left = N - n
+        q = dtcfl / delta
+        p = left if q >= left else int(np.floor(q))
+        return (1, True) if p < 1 else (p, False)
+    p = N
+    while p > 1 and p * delta > dtcfl:
+        p //= 2
+    over = p * delta > dtcfl
+    if n > 0:
+        p = min(p, n & (-n))
+    return p, over
+
+
 @dataclasses.dataclass
 class State:
     Q: np.ndarray
@@ -565,31 +585,13 @@ class Solver:
         st.dtcfl[elems] = self.cfg.cfl * ratio.min(axis=1)
 
     def _level_step(self, elems):
-        """Dyadic step in ticks (R2): largest power of two p <= N with p*delta <= dt_CFL,
-        limited by the alignment of the current tick; at least 1 (overshoot counted).
-        Free steps (levels = 0, R19): floor(dt_CFL / delta) ticks, at most the ticks
-        left to the end of the interval."""
+        """Steps in ticks of the given elements (R2, R19), at least 1 (an
+        overshoot of the CFL step is counted)."""
         st = self.st
         out = np.zeros(elems.size, np.int64)
-        if self.cfg.levels == 0:
-            for t, i in enumerate(elems):
-                left = st.N - int(st.n[i])
-                q = st.dtcfl[i] / st.delta
-                p = left if q >= left else int(np.floor(q))
-                if p < 1:
-                    st.cfl_overshoots += 1
-                    p = 1
-                out[t] = p
-            return out
         for t, i in enumerate(elems):
-            p = st.N
-            while p > 1 and p * st.delta > st.dtcfl[i]:
-                p //= 2
-            if p * st.delta > st.dtcfl[i]:
-                st.cfl_overshoots += 1
-            n = int(st.n[i])
-            if n > 0:
-                p = min(p, n & (-n))
+            p, over = level_step(st.dtcfl[i], st.delta, st.N, int(st.n[i]), self.cfg.levels == 0)
+            st.cfl_overshoots += over
             out[t] = p
         return out
 
@@ -751,6 +753,16 @@ class Solver:
 # ---------------------------------------------------------------------------
 # Global time stepping driver (separate code path, used to check LTS with L = 1)
 # ---------------------------------------------------------------------------
+def cfl_time_steps(Xe, Q, neigh, gamma, cfl):
+    """Local CFL time step of eq. eqn.timestep with every element at one time:
+    cfl * min over the element and its face neighbours of d / (|v| + c), with
+    d the diameter of the inscribed circle, 4|T| / perimeter."""
+    d = 4.0 * tri_area(Xe) / tri_perimeter(Xe)
+    r = d / euler.max_signal(Q, gamma)
+    rn = np.where(neigh >= 0, r[np.maximum(neigh, 0)], np.inf)
+    return cfl * np.minimum(r, rn.min(axis=1))
+
+
 class GTSSolver:
     """All elements advance together with dt = min CFL step: predictor on all,
     node motion on all nodes over [0,1], one patch per edge, direct update."""
@@ -772,10 +784,7 @@ class GTSSolver:
         valid = sten[:, :, 0] >= 0
         ss = np.where(sten >= 0, sten, np.arange(topo.n_elems)[:, None, None])
         self.wnod, _, _, _ = reconstruct_batch(cfg.M, cfg, Xe, self.Q, Xe[ss], self.Q[ss], valid)
-        d = 4.0 * tri_area(Xe) / tri_perimeter(Xe)
-        r = d / euler.max_signal(self.Q, cfg.gamma)
-        rn = np.where(topo.neigh >= 0, r[np.maximum(topo.neigh, 0)], np.inf)
-        self.dtcfl = cfg.cfl * np.minimum(r, rn.min(axis=1))
+        self.dtcfl = cfl_time_steps(Xe, self.Q, topo.neigh, cfg.gamma, cfg.cfl)
 
     def step(self, t_end):
         topo, cfg, M = self.topo, self.cfg, self.cfg.M

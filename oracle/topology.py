@@ -107,6 +107,76 @@ def _central(i, neigh, bc, ne):
     return out
 
 
+def _vertex_reach(tris, NV, M):
+    """Vertex adjacency of the elements and the candidate pools within M+4
+    vertex layers (sparse, sorted indices)."""
+    NE = tris.shape[0]
+    rows = np.repeat(np.arange(NE), 3)
+    en = sp.csr_matrix((np.ones(3 * NE), (rows, tris.ravel())), shape=(NE, NV))
+    adj = (en @ en.T).tocsr()
+    adj.data[:] = 1.0
+    reach = adj.copy()
+    for _ in range(M + 3):
+        reach = (reach @ adj).tocsr()
+        reach.data[:] = 1.0
+    reach.sort_indices()
+    return adj, reach
+
+
+def _element_stencils(i, nodes, tris, neigh, bc, reach, ne):
+    """The 7 stencils of element i (eqs. stencil, eqn.WENOstencil): central
+    (face-neighbour layers), then for each vertex the primary and the reverse
+    sector; a sector without ne - 1 candidates stays -1."""
+    out = -np.ones((7, ne), np.int64)
+    out[0] = _central(i, neigh, bc, ne)
+    cand = reach.indices[reach.indptr[i]:reach.indptr[i + 1]]
+    cand = cand[cand != i]
+    dxc = bc[cand, 0] - bc[i, 0]
+    dyc = bc[cand, 1] - bc[i, 1]
+    d2 = dxc * dxc + dyc * dyc
+    X = nodes[tris[i]]
+    for k in range(3):
+        P = X[k]
+        e1 = X[(k + 1) % 3] - P
+        e2 = X[(k + 2) % 3] - P
+        dx = bc[cand, 0] - P[0]
+        dy = bc[cand, 1] - P[1]
+        c1 = dx * e2[1] - dy * e2[0]        # cross(d, e2)
+        c2 = e1[0] * dy - e1[1] * dx        # cross(e1, d)
+        for s, mask in ((1 + k, (c1 > 0) & (c2 > 0)), (4 + k, (c1 < 0) & (c2 < 0))):
+            idx = np.nonzero(mask)[0]
+            if idx.size < ne - 1:
+                continue
+            order = np.lexsort((cand[idx], d2[idx]))[: ne - 1]
+            out[s, 0] = i
+            out[s, 1:] = cand[idx][order]
+    return out
+
+
+def face_neighbours(tris: np.ndarray) -> np.ndarray:
+    """(NE, 3) element across local edge k, -1 on the boundary."""
+    tris = np.asarray(tris, np.int64)
+    edge_nodes, edge_elems, edge_local, _ = build_edges(tris)
+    neigh = -np.ones((tris.shape[0], 3), np.int64)
+    inner = edge_elems[:, 1] >= 0
+    L, R = edge_elems[inner, 0], edge_elems[inner, 1]
+    neigh[L, edge_local[inner, 0]] = R
+    neigh[R, edge_local[inner, 1]] = L
+    return neigh
+
+
+def stencils_of(nodes: np.ndarray, tris: np.ndarray, M: int, elems) -> np.ndarray:
+    """The 7 stencils of the given elements only (same construction as
+    build_topology), for sampled checks on meshes too large to process whole."""
+    nodes = np.asarray(nodes, float)
+    tris = np.asarray(tris, np.int64)
+    ne = sizes(M)["ne"]
+    neigh = face_neighbours(tris)
+    bc = barycentres(nodes, tris)
+    _, reach = _vertex_reach(tris, nodes.shape[0], M)
+    return np.stack([_element_stencils(int(i), nodes, tris, neigh, bc, reach, ne) for i in elems])
+
+
 def build_topology(nodes: np.ndarray, tris: np.ndarray, M: int, bedges=None) -> Topology:
     nodes = np.asarray(nodes, float)
     tris = np.asarray(tris, np.int64)
@@ -134,42 +204,10 @@ def build_topology(nodes: np.ndarray, tris: np.ndarray, M: int, bedges=None) -> 
         for k in range(3):
             ring[int(tris[i, k])].append((i, k))
     bc = barycentres(nodes, tris)
-
-    # vertex adjacency and candidate pools within M+4 vertex layers
-    rows = np.repeat(np.arange(NE), 3)
-    en = sp.csr_matrix((np.ones(3 * NE), (rows, tris.ravel())), shape=(NE, NV))
-    adj = (en @ en.T).tocsr()
-    adj.data[:] = 1.0
-    reach = adj.copy()
-    for _ in range(M + 3):
-        reach = (reach @ adj).tocsr()
-        reach.data[:] = 1.0
-    reach.sort_indices()
-
+    adj, reach = _vertex_reach(tris, NV, M)
     stencils = -np.ones((NE, 7, ne), np.int64)
     for i in range(NE):
-        stencils[i, 0] = _central(i, neigh, bc, ne)
-        cand = reach.indices[reach.indptr[i]:reach.indptr[i + 1]]
-        cand = cand[cand != i]
-        dxc = bc[cand, 0] - bc[i, 0]
-        dyc = bc[cand, 1] - bc[i, 1]
-        d2 = dxc * dxc + dyc * dyc
-        X = nodes[tris[i]]
-        for k in range(3):
-            P = X[k]
-            e1 = X[(k + 1) % 3] - P
-            e2 = X[(k + 2) % 3] - P
-            dx = bc[cand, 0] - P[0]
-            dy = bc[cand, 1] - P[1]
-            c1 = dx * e2[1] - dy * e2[0]        # cross(d, e2)
-            c2 = e1[0] * dy - e1[1] * dx        # cross(e1, d)
-            for s, mask in ((1 + k, (c1 > 0) & (c2 > 0)), (4 + k, (c1 < 0) & (c2 < 0))):
-                idx = np.nonzero(mask)[0]
-                if idx.size < ne - 1:
-                    continue
-                order = np.lexsort((cand[idx], d2[idx]))[: ne - 1]
-                stencils[i, s, 0] = i
-                stencils[i, s, 1:] = cand[idx][order]
+        stencils[i] = _element_stencils(i, nodes, tris, neigh, bc, reach, ne)
 
     # scheduling stencil: symmetric closure of stencils + vertex ring
     U = [set() for _ in range(NE)]

@@ -50,3 +50,59 @@ def test_explosion_four_levels_parity():
     assert (rel_groups(Q, o.st.Q) < TOL).all()
     assert np.abs(X - o.st.X).max() < TOL * _span(mesh)
     assert o.st.updates < 2 * 8 * mesh.n_elems         # fewer updates than GTS at the finest step
+
+
+def test_explosion_full_size_sampled_parity_and_conservation():
+    """The explosion workload at its full size (400k triangles, M=2, 4 levels):
+    the pre-processing reconstruction and the macro-step start (predictor)
+    element by element on a seeded sample of 2,000 elements, each computed by
+    the oracle from its own stencil; CFL steps and levels on every element.
+    Then two macro steps (16 cycles): mass, momentum and energy conserved to
+    round-off (no wave reaches the boundary yet, and the uniform boundary
+    pressure sums to zero force over the closed polygon), the GCL held, and
+    fewer element updates than global steps at the finest step."""
+    from oracle.scheme import Config as OConfig
+    from oracle.scheme import cfl_time_steps, level_step, predictor_batch, reconstruct_batch
+    from oracle.topology import face_neighbours, stencils_of
+    mesh, Q0 = explosion_case(400_000, seed=7)
+    NE = mesh.n_elems
+    print(f"explosion mesh {NE} triangles", flush=True)
+    cfg = OConfig(M=2, levels=4)
+    g = _gpu_solver(mesh, Q0, 2, 4)
+    rng = np.random.default_rng(400)
+    sample = np.sort(rng.choice(NE, 2000, replace=False))
+    Xe = mesh.nodes[mesh.tris]
+    sten = stencils_of(mesh.nodes, mesh.tris, 2, sample)
+    valid = sten[:, :, 0] >= 0
+    ss = np.where(sten >= 0, sten, sample[:, None, None])
+    wnod_o, _, _, _ = reconstruct_batch(2, cfg, Xe[sample], Q0[sample], Xe[ss], Q0[ss], valid)
+    assert rel(np.transpose(g.dump("WNOD"), (2, 0, 1))[sample], wnod_o) < TOL
+    dt_o = cfl_time_steps(Xe, Q0, face_neighbours(mesh.tris), cfg.gamma, cfg.cfl)
+    assert rel(g.dump("DTCFL"), dt_o) < TOL
+    print("pre-processing checked", flush=True)
+    g.debug_macro_begin(1.0, 4)
+    delta = float(dt_o.min())
+    assert abs(g.dump("SCAL")[1] - delta) <= 1e-14 * delta
+    steps_o = np.array([level_step(dt_o[i], delta, 8, 0, False)[0] for i in range(NE)])
+    assert np.array_equal(g.dump("STEP"), steps_o)
+    assert len(np.unique(steps_o)) == 4                 # all four levels in use
+    pr = predictor_batch(2, cfg, wnod_o, Xe[sample], steps_o[sample] * delta, np.zeros(sample.size))
+    assert rel(np.moveaxis(g.dump("TRACE"), -1, 0)[sample], pr["trace"]) < TOL
+    assert rel(np.moveaxis(g.dump("VVEL"), -1, 0)[sample], pr["vvel"]) < TOL
+    print("macro begin checked", flush=True)
+    g.upload_state(Q0, 0.0)
+    st = g.step_lts(1.0, 2)
+    Q, X, _ = g.download()
+    p = X[mesh.tris]
+    A1 = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    A0 = 0.5 * ((Xe[:, 1, 0] - Xe[:, 0, 0]) * (Xe[:, 2, 1] - Xe[:, 0, 1])
+                - (Xe[:, 2, 0] - Xe[:, 0, 0]) * (Xe[:, 1, 1] - Xe[:, 0, 1]))
+    c0 = (A0[:, None] * Q0).sum(axis=0)
+    c1 = (A1[:, None] * Q).sum(axis=0)
+    scale = (A0[:, None] * np.abs(Q0)).sum(axis=0).max()
+    print(f"two macro steps: t={st['t']:.3e} updates={st['element_updates']} drift={np.abs(c1 - c0) / scale}",
+          flush=True)
+    assert np.abs(c1 - c0).max() <= 1e-13 * scale
+    assert st["max_gcl_residual"] < 1e-12
+    assert st["element_updates"] < 2 * 8 * NE

@@ -212,3 +212,14 @@ def test_free_steps_respect_cfl_and_save_updates():
             s.run(0.1)
         upd[L] = s.st.updates
     assert upd[0] < upd[3] < upd[1], upd
+
+
+def test_sampled_stencils_equal_the_full_construction(graded):
+    """stencils_of (for sampled checks on large meshes) builds the same rows as
+    build_topology, element by element."""
+    from oracle.topology import build_topology, face_neighbours, stencils_of
+    for M in (1, 2):
+        topo = build_topology(graded.nodes, graded.tris, M, graded.bedges)
+        elems = np.arange(0, graded.n_elems, 7)
+        assert np.array_equal(stencils_of(graded.nodes, graded.tris, M, elems), topo.stencils[elems])
+        assert np.array_equal(face_neighbours(graded.tris), topo.neigh)
