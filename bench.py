@@ -322,7 +322,7 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for {a.gpus}); "
               "the multi-GPU layout is a design note, not an implementation.", file=sys.stderr)
         sys.exit(2)
 
