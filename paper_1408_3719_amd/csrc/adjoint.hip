@@ -52,9 +52,9 @@ struct AZ {
   static constexpr int WS = wnod_stride(M);
   static constexpr int QS = nb * T * 4;   // nodal space-time values of one element
   // kept per stencil lane by the forward reconstruction: R (upper triangle),
-  // solution, weight and indicator, rows
+  // solution, weight and indicator (the rows are rebuilt in reverse)
   static constexpr int L_R = 0, L_W = nu * (nu + 1) / 2, L_OM = L_W + 4 * nu, L_SIG = L_OM + 1,
-                       L_ROW = L_SIG + 1, LB = L_ROW + (ne - 1) * nu;
+                       LB = L_SIG + 1;
 };
 
 // Euler fluxes f, g (eq. eulerTerms) with p from eq. eqn.eos.
@@ -323,8 +323,6 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         double a[nu], b[4];
         ls_row<M>(tb, rj + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
-        for (int l = 0; l < nu; ++l) lq[(S::L_ROW + (c - 1) * nu + l) * LS] = a[l];
-#pragma unroll
         for (int v = 0; v < 4; ++v) b[v] = w.q[size_t(v) * NE + sidx[c * NE]] - Qi[v];
 #pragma unroll
         for (int k = 0; k < nu; ++k) {
@@ -472,8 +470,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
     for (int c = 1; c < ne; ++c) {
       const int j = sidx[c * NE];
       double a[nu];
-#pragma unroll
-      for (int l = 0; l < nu; ++l) a[l] = lq[(S::L_ROW + (c - 1) * nu + l) * LS];
+      ls_row<M>(tb, d.rec + size_t(j) * S::RS + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double t = 0.0;
