@@ -255,3 +255,23 @@ def test_free_steps_single_cycles_parity(name, t_end):
         live = o.st.s > 0
         tr = np.moveaxis(g.dump("TRACE"), -1, 0)
         assert rel(tr[live], o.st.trace[live]) < TOL, c
+
+
+@pytest.mark.parametrize("levels", [1, 3, 0])
+def test_target_time_already_reached_is_a_no_op(levels):
+    """A target at or before the current time takes no step and leaves the
+    state bit for bit; stepping on afterwards works as from a fresh start."""
+    make, M = CASES["vortex_M2"]
+    mesh, Q0 = make()
+    g = _gpu_solver(mesh, Q0, M, levels)
+    step = g.step_gts if levels == 1 else g.step_lts
+    first = step(0.02)
+    Qa, Xa, ta = g.download()
+    for t in (0.02, 0.01, 0.0, -1.0):
+        st = step(t)
+        Qb, Xb, tb = g.download()
+        assert np.array_equal(Qa, Qb) and np.array_equal(Xa, Xb) and np.array_equal(ta, tb), t
+        for f in ("element_updates", "cycles", "macro_steps"):
+            assert st[f] == first[f], (t, f)
+    st = step(0.03)
+    assert abs(st["t"] - 0.03) <= 1e-13 and st["element_updates"] > first["element_updates"]
