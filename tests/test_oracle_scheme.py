@@ -223,3 +223,46 @@ def test_sampled_stencils_equal_the_full_construction(graded):
         elems = np.arange(0, graded.n_elems, 7)
         assert np.array_equal(stencils_of(graded.nodes, graded.tris, M, elems), topo.stencils[elems])
         assert np.array_equal(face_neighbours(graded.tris), topo.neigh)
+
+
+def test_level_rule_against_its_definition():
+    """Dyadic steps (eq. eqn.timestep with levels): the step p is a power of two
+    dividing the current tick, p * delta <= dt_CFL unless p = 1 (then flagged),
+    and 2p would break the CFL bound, the macro step or the alignment. Free
+    steps: p = floor(dt_CFL / delta) within the ticks left."""
+    from oracle.scheme import level_step
+    rng = np.random.default_rng(9)
+    N = 16
+    for _ in range(2000):
+        delta = rng.uniform(0.1, 1.0)
+        dt = delta * np.exp(rng.uniform(np.log(0.3), np.log(40.0)))
+        n = int(rng.integers(0, N))
+        p, over = level_step(dt, delta, N, n, False)
+        assert p >= 1 and p & (p - 1) == 0 and p <= N and (n == 0 or n % p == 0)
+        assert over == (p * delta > dt)
+        if not over:
+            assert 2 * p > N or 2 * p * delta > dt or (n > 0 and n % (2 * p) != 0)
+        q, over = level_step(dt, delta, N, n, True)
+        assert q == max(1, min(N - n, int(np.floor(dt / delta))))
+        assert over == (dt < delta)
+
+
+def test_cfl_steps_closed_form():
+    """eq. eqn.timestep on a uniform state over congruent right isosceles
+    triangles of leg h: the inscribed-circle diameter is 2h / (2 + sqrt 2)."""
+    from oracle.scheme import cfl_time_steps
+    from oracle.topology import face_neighbours
+    n, h = 6, 0.2
+    xs = np.arange(n + 1) * h
+    nodes = np.array([(x, y) for y in xs for x in xs])
+    tris = []
+    for j in range(n):
+        for i in range(n):
+            a, b, c, d = j * (n + 1) + i, j * (n + 1) + i + 1, (j + 1) * (n + 1) + i + 1, (j + 1) * (n + 1) + i
+            tris += [(a, b, c), (a, c, d)]
+    tris = np.array(tris)
+    rho, u, v, p, g = 1.3, 0.4, -0.2, 2.1, 1.4
+    Q = np.tile([rho, rho * u, rho * v, p / (g - 1) + 0.5 * rho * (u * u + v * v)], (tris.shape[0], 1))
+    dt = cfl_time_steps(nodes[tris], Q, face_neighbours(tris), g, 0.5)
+    expect = 0.5 * (2 * h / (2 + np.sqrt(2))) / (np.hypot(u, v) + np.sqrt(g * p / rho))
+    assert np.abs(dt - expect).max() <= 1e-15 * expect
