@@ -188,15 +188,16 @@ int ader_set_graphs(ader_ctx* ctx, int32_t on);
 /* ---- Adjoint of one global time step (reverse mode) ----------------------
  * The step map Q^n -> Q^{n+1} of global time stepping of length dt from the
  * current state, on a fixed mesh (mesh_velocity = 1: the mesh ODE of eq.
- * ODEmesh with V = 0, so |T'| = |T|) with the Rusanov flux: WENO
+ * ODEmesh with V = 0, so |T'| = |T|) with the Rusanov or HLL flux: WENO
  * reconstruction with the neighbours' real averages (eqs. intConsRec ..
  * eqn.weno), space-time predictor (eq. CGfinal), fluxes over the space-time
  * faces of the edges with (M+1)^2 Gauss points (eqs. eqn.rusanov,
  * eqn.STint) and the update of eq. PDEfinal.  ader_adjoint_gts_step writes
  * Qbar = (dQ^{n+1}/dQ^n)^T Qbar_next with dt held fixed (the dependence of
  * the CFL step of eq. eqn.timestep on the state is not differentiated);
- * subgradients: the larger Rusanov signal speed is taken from the left state
- * on ties, d|x|/dx = 0 at 0.  It does not change the simulation state.
+ * subgradients: the larger Rusanov signal speed, and the bounding HLL speeds,
+ * are taken from the left state on ties, d|x|/dx = 0 at 0.  ADER_E_ARG with
+ * the Osher flux.  It does not change the simulation state.
  *   Q_dev: device [4][n_elems] SoA averages Q^n to differentiate at, or NULL
  *     for the context's current averages (then every element must be at one
  *     common time);

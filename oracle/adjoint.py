@@ -4,8 +4,8 @@ infrastructure; never used by the product).
 The step is the scheme of Sec. 2 with one level (global time stepping) and the
 mesh held fixed (Eulerian mode, V = 0 in eq. ODEmesh): WENO reconstruction
 (eqs. intConsRec .. eqn.weno), space-time predictor (eq. CGfinal), Rusanov
-fluxes over the space-time faces (eqs. eqn.rusanov, eqn.STint) and the
-one-step update (eq. PDEfinal), for a given time step dt that is held fixed
+(eq. eqn.rusanov) or HLL fluxes over the space-time faces (eq. eqn.STint) and
+the one-step update (eq. PDEfinal), for a given time step dt that is held fixed
 (the CFL step of eq. eqn.timestep is not differentiated).  It is written here
 a second time with PyTorch CPU operations in FP64, following the NumPy oracle
 step for step, so that torch.autograd yields the exact vector-Jacobian
@@ -72,6 +72,36 @@ def rusanov(ql, qr, N, gamma):
     return 0.5 * (ft(ql) + ft(qr)) - 0.5 * smax[..., None] * (qr - ql)
 
 
+def hll(ql, qr, N, gamma):
+    """HLL flux through an unnormalised space-time normal N (same formula as
+    the NumPy oracle): signal speeds u.N_xy + N_t -/+ c|N_xy| bounded over both
+    states, the left state's speed taken on ties; upwind when both speeds have
+    one sign."""
+    nxy = torch.sqrt(N[..., 0] ** 2 + N[..., 1] ** 2)
+
+    def ft(q):
+        f, g = flux_fg(q, gamma)
+        return f * N[..., 0:1] + g * N[..., 1:2] + q * N[..., 2:3]
+
+    def speeds(q):
+        rho, u, v, p = primitives(q, gamma)
+        un = u * N[..., 0] + v * N[..., 1] + N[..., 2]
+        c = torch.sqrt(gamma * p / rho) * nxy
+        return un - c, un + c
+
+    l1, r1 = speeds(ql)
+    l2, r2 = speeds(qr)
+    sl = torch.where(l1 <= l2, l1, l2)
+    sr = torch.where(r1 >= r2, r1, r2)
+    fl, fr = ft(ql), ft(qr)
+    den = torch.where(sr > sl, sr - sl, torch.ones_like(sr))
+    fh = (sr[..., None] * fl - sl[..., None] * fr + (sl * sr)[..., None] * (qr - ql)) / den[..., None]
+    return torch.where((sl >= 0)[..., None], fl, torch.where((sr <= 0)[..., None], fr, fh))
+
+
+FLUX_FUNCTIONS = {"rusanov": rusanov, "hll": hll}
+
+
 def mirror(q, N):
     """Slip-wall ghost state: normal momentum reflected (linear in q)."""
     nxy = torch.sqrt(N[..., 0] ** 2 + N[..., 1] ** 2)
@@ -86,8 +116,8 @@ class EulerianStep:
     of the cell averages Q (NE, 4)."""
 
     def __init__(self, nodes, tris, cfg: Config, bedges=None, topo=None):
-        if cfg.flux != "rusanov":
-            raise ValueError("the reverse-mode oracle covers the Rusanov flux")
+        if cfg.flux not in FLUX_FUNCTIONS:
+            raise ValueError("the reverse-mode oracle covers the Rusanov and HLL fluxes")
         self.cfg = cfg
         M = cfg.M
         self.M = M
@@ -233,7 +263,7 @@ class EulerianStep:
                 qrr = torch.einsum("q,eqv->ev", lt, trR[:, nG - 1 - g])
                 qr = torch.where(self.slip[:, None], mirror(ql, N), ql)
                 qr = torch.where(self.hasR[:, None], qrr, qr)
-                G = G + (wc[g] * wc[h]) * rusanov(ql, qr, N, cfg.gamma)
+                G = G + (wc[g] * wc[h]) * FLUX_FUNCTIONS[cfg.flux](ql, qr, N, cfg.gamma)
         return G
 
     def __call__(self, Q, dt):

@@ -1044,7 +1044,7 @@ int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Q_dev, const dou
   if (!c || !Qbar_next_dev || !Qbar_dev || !work_dev) return ADER_E_ARG;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, ADER_E_ARG, "dt must be positive and finite");
   if (c->cfg.mesh_velocity != 1) return fail(c, ADER_E_ARG, "the adjoint needs a fixed mesh (mesh_velocity = 1)");
-  if (c->cfg.flux != ADER_FLUX_RUSANOV) return fail(c, ADER_E_ARG, "the adjoint covers the Rusanov flux");
+  if (c->cfg.flux == ADER_FLUX_OSHER) return fail(c, ADER_E_ARG, "the adjoint covers the Rusanov and HLL fluxes");
   if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the adjoint runs on a single instance");
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (!Q_dev && !c->synced)

@@ -4,9 +4,10 @@
 // (mesh velocity V = 0, eq. ODEmesh) and a given time step dt:
 //   WENO reconstruction with real neighbour data (eqs. intConsRec .. eqn.weno)
 //   -> space-time predictor (eq. CGfinal; the metric of the fixed affine map,
-//   no time derivative of the mesh) -> edge traces -> Rusanov fluxes over the
-//   space-time faces of the fixed edges ((M+1)^2 Gauss points, eqs.
-//   eqn.rusanov, eqn.STint) -> one-step update (eq. PDEfinal, |T'| = |T|).
+//   no time derivative of the mesh) -> edge traces -> Rusanov (eq.
+//   eqn.rusanov) or HLL fluxes over the space-time faces of the fixed edges
+//   ((M+1)^2 Gauss points, eq. eqn.STint) -> one-step update (eq. PDEfinal,
+//   |T'| = |T|).
 // Given qbar_next = dL/dQ^{n+1} the kernels return qbar = dL/dQ^n, with dt
 // held fixed (the CFL step of eq. eqn.timestep is not differentiated):
 //   k_adj_recon<fwd>  reconstruction from the current averages (8 lanes per
@@ -24,13 +25,14 @@
 //   k_adj_gather      qbar_j = qbar_next_j (the identity part of the update) +
 //                     the slots of every stencil row that names element j, in a
 //                     fixed order (no atomics: each average is named by ~80 rows)
-// Subgradients: the larger Rusanov signal speed is taken from the left state
-// on ties, and |x| has derivative sign(x), 0 at 0.
+// Subgradients: the larger Rusanov signal speed and the bounding HLL speeds are
+// taken from the left state on ties, and |x| has derivative sign(x), 0 at 0.
 // The least-squares adjoint uses A R^-1 = Q of the QR factorisation: the
 // adjoint of the right-hand side is A R^-1 R^-T wbar, so the rotations need
 // not be kept.
 #include <hip/hip_runtime.h>
 
+#include "aderweno.h"
 #include "common.h"
 
 namespace aw {
@@ -147,6 +149,91 @@ __device__ inline void rusanov_vjp(const double ql[4], const double qr[4], const
     signal_speed_vjp(ql, N, nxy, gam, sbar, qlb);
   else
     signal_speed_vjp(qr, N, nxy, gam, sbar, qrb);
+}
+
+// ALE signal speeds u.N_xy + N_t -/+ c|N_xy|
+__device__ inline void hll_speeds(const double q[4], const double N[3], double nxy, double gam,
+                                  double& lo, double& hi) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  const double p = (gam - 1.0) * (q[3] - 0.5 * r * (u * u + v * v));
+  const double un = u * N[0] + v * N[1] + N[2];
+  const double c = sqrt(gam * p / r) * nxy;
+  lo = un - c;
+  hi = un + c;
+}
+
+// qb += sb * d(u.N_xy + N_t + sgn * c|N_xy|)/dq
+__device__ inline void hll_speed_vjp(const double q[4], const double N[3], double nxy, double gam,
+                                     double sgn, double sb, double qb[4]) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  const double p = (gam - 1.0) * (q[3] - 0.5 * r * (u * u + v * v));
+  const double c = sqrt(gam * p / r);
+  const double cb = sgn * sb * nxy;
+  prim_pullback(q, gam, -cb * c / (2.0 * r), sb * N[0], sb * N[1], cb * gam / (2.0 * c * r), 0.0, qb);
+}
+
+// qb += J_ft(q)^T gb with ft = f N_x + g N_y + q N_t
+__device__ inline void ft_vjp(const double q[4], const double N[3], double gam, const double gb[4],
+                              double qb[4]) {
+  double fb[4], gg[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    fb[v] = N[0] * gb[v];
+    gg[v] = N[1] * gb[v];
+    qb[v] += N[2] * gb[v];
+  }
+  euler_fg_vjp(q, gam, fb, gg, qb);
+}
+
+// Adjoint of the HLL flux: speeds bounded over both states (the left state's
+// speed on ties), upwind when both have one sign, else
+// (sr F(ql) - sl F(qr) + sl sr (qr - ql)) / (sr - sl).
+__device__ inline void hll_vjp(const double ql[4], const double qr[4], const double N[3], double gam,
+                               const double Gb[4], double qlb[4], double qrb[4]) {
+  const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
+  double l1, r1, l2, r2;
+  hll_speeds(ql, N, nxy, gam, l1, r1);
+  hll_speeds(qr, N, nxy, gam, l2, r2);
+  const bool left_lo = l1 <= l2, left_hi = r1 >= r2;
+  const double sl = left_lo ? l1 : l2, sr = left_hi ? r1 : r2;
+  if (sl >= 0.0) {
+    ft_vjp(ql, N, gam, Gb, qlb);
+    return;
+  }
+  if (sr <= 0.0) {
+    ft_vjp(qr, N, gam, Gb, qrb);
+    return;
+  }
+  double fl[4], fr[4], f[4], g[4];
+  euler_fg(ql, gam, f, g);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) fl[v] = f[v] * N[0] + g[v] * N[1] + ql[v] * N[2];
+  euler_fg(qr, gam, f, g);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) fr[v] = f[v] * N[0] + g[v] * N[1] + qr[v] * N[2];
+  const double id = 1.0 / (sr - sl);
+  double flb[4], frb[4], slb = 0.0, srb = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double d = qr[v] - ql[v];
+    const double F = (sr * fl[v] - sl * fr[v] + sl * sr * d) * id;
+    flb[v] = sr * id * Gb[v];
+    frb[v] = -sl * id * Gb[v];
+    qrb[v] += sl * sr * id * Gb[v];
+    qlb[v] -= sl * sr * id * Gb[v];
+    srb += Gb[v] * (fl[v] + sl * d - F) * id;
+    slb += Gb[v] * (-fr[v] + sr * d + F) * id;
+  }
+  ft_vjp(ql, N, gam, flb, qlb);
+  ft_vjp(qr, N, gam, frb, qrb);
+  if (left_lo)
+    hll_speed_vjp(ql, N, nxy, gam, -1.0, slb, qlb);
+  else
+    hll_speed_vjp(qr, N, nxy, gam, -1.0, slb, qrb);
+  if (left_hi)
+    hll_speed_vjp(ql, N, nxy, gam, 1.0, srb, qlb);
+  else
+    hll_speed_vjp(qr, N, nxy, gam, 1.0, srb, qrb);
 }
 
 // Lagrange basis in time, l_q(tau)
@@ -665,7 +752,10 @@ __global__ void __launch_bounds__(TPB) k_adj_patch(Dev d, const Tables* __restri
         double Gw[4], qlb[4] = {0, 0, 0, 0}, qrb[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int v = 0; v < 4; ++v) Gw[v] = wgt * Gb[v];
-        rusanov_vjp(ql, qr, N, P.gamma, Gw, qlb, qrb);
+        if (P.flux == ADER_FLUX_HLL)
+          hll_vjp(ql, qr, N, P.gamma, Gw, qlb, qrb);
+        else
+          rusanov_vjp(ql, qr, N, P.gamma, Gw, qlb, qrb);
         if (R >= 0) {
 #pragma unroll
           for (int t = 0; t < T; ++t)

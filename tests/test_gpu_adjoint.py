@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(__file__))
-from test_oracle_adjoint import CASES, _case  # noqa: E402
+from test_oracle_adjoint import CASES, HLL_CASES, _case  # noqa: E402
 
 from oracle.adjoint import EulerianStep  # noqa: E402
 from oracle.scheme import Config as OConfig  # noqa: E402
@@ -22,23 +22,24 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
-def _solver(mesh, Q0, M):
+def _solver(mesh, Q0, M, flux="rusanov"):
     from paper_1408_3719_amd import Config, Solver
-    return Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=1, mesh_velocity="eulerian"))
+    return Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
+                  Config(M=M, levels=1, mesh_velocity="eulerian", flux=flux))
 
 
-@pytest.mark.parametrize("name,M", CASES)
-def test_adjoint_matches_reverse_mode_oracle(name, M):
+@pytest.mark.parametrize("name,M,flux", [c + ("rusanov",) for c in CASES] + [c + ("hll",) for c in HLL_CASES])
+def test_adjoint_matches_reverse_mode_oracle(name, M, flux):
     mesh, Q0 = _case(name, M)
-    print(f"adjoint {name} M={M} {mesh.n_elems} triangles", flush=True)
-    cfg = OConfig(M=M, levels=1, mesh_velocity="eulerian")
+    print(f"adjoint {name} M={M} {flux} {mesh.n_elems} triangles", flush=True)
+    cfg = OConfig(M=M, levels=1, mesh_velocity="eulerian", flux=flux)
     o = GTSSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
     dt = 0.5 * float(o.dtcfl.min())
     st = EulerianStep(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
     rng = np.random.default_rng(1)
     qb = rng.standard_normal(Q0.shape)
     ref = st.vjp(Q0, dt, qb)
-    g = _solver(mesh, Q0, M)
+    g = _solver(mesh, Q0, M, flux)
     Qa, Xa, _ = g.download()
     out = g.adjoint_gts_step(dt, qb).cpu().numpy().T
     for v in range(4):
@@ -84,7 +85,7 @@ def test_adjoint_rejects_unsupported_modes():
     with pytest.raises(AderError):
         lag.adjoint_gts_step(1e-3, np.zeros_like(Q0))
     osh = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
-                 Config(M=2, levels=1, mesh_velocity="eulerian", flux="osher"))
+                 Config(M=2, levels=1, mesh_velocity="eulerian", flux="osher"))   # not covered
     with pytest.raises(AderError):
         osh.adjoint_gts_step(1e-3, np.zeros_like(Q0))
     e = _solver(mesh, Q0, 2)

@@ -21,9 +21,9 @@ def _case(name, M):
     return mesh, Q0 * (1.0 + 1e-3 * rng.standard_normal(Q0.shape))
 
 
-def _setup(name, M):
+def _setup(name, M, flux="rusanov"):
     mesh, Q0 = _case(name, M)
-    cfg = Config(M=M, levels=1, mesh_velocity="eulerian")
+    cfg = Config(M=M, levels=1, mesh_velocity="eulerian", flux=flux)
     o = GTSSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
     dt = 0.5 * float(o.dtcfl.min())
     st = EulerianStep(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
@@ -31,6 +31,7 @@ def _setup(name, M):
 
 
 CASES = [("vortex", 1), ("vortex", 2), ("vortex", 3), ("sod", 1), ("sod", 2), ("explosion", 2)]
+HLL_CASES = [("vortex", 2), ("sod", 2), ("explosion", 2)]
 
 
 @pytest.mark.parametrize("name,M", CASES)
@@ -90,3 +91,25 @@ def test_adjoint_of_conserved_totals_is_the_area(name, M):
         # and the boundary does act on the rest (the pin is not vacuous)
         if var in (1, 2):
             assert np.abs(g[reach] - exp[reach]).max() > 1e-8 * st.area.max()
+
+
+@pytest.mark.parametrize("name,M", HLL_CASES)
+def test_hll_forward_and_vjp(name, M):
+    """The same two pins with the HLL flux."""
+    mesh, Q0, cfg, o, dt, st = _setup(name, M, flux="hll")
+    o.step(dt)
+    assert np.abs(st.step(Q0, dt) - o.Q).max() <= 1e-14 * np.abs(o.Q).max()
+    rng = np.random.default_rng(0)
+    qb = rng.standard_normal(Q0.shape)
+    g = st.vjp(Q0, dt, qb)
+
+    def F(Q):
+        s = GTSSolver(mesh.nodes, mesh.tris, Q, cfg, bedges=mesh.bedges, topo=o.topo)
+        s.step(dt)
+        return s.Q
+
+    h = 1e-8
+    v = rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=0)
+    fd = ((F(Q0 + h * v) - F(Q0 - h * v)) * qb).sum() / (2 * h)
+    ad = (g * v).sum()
+    assert abs(fd - ad) <= 1e-6 * np.abs(g * v).sum(), (fd, ad)
