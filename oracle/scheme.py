@@ -500,6 +500,8 @@ class State:
     delta: float = 0.0
     N: int = 1
     updates: int = 0
+    node_moves: int = 0
+    patches: int = 0
     cycles: int = 0
     macro_steps: int = 0
     cfl_overshoots: int = 0
@@ -723,6 +725,8 @@ class Solver:
             st.s[going] = self._level_step(going)
             self._predict(going)
         st.updates += int(act.size)
+        st.node_moves += int(moved.size)
+        st.patches += int(swept.size)
         st.cycles += 1
         st.active_sizes.append(int(act.size))
         return act

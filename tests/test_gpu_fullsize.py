@@ -47,6 +47,7 @@ def test_explosion_four_levels_parity():
     o.run(1.0, max_macro_steps=2)
     Q, X, _ = g.download()
     assert st["element_updates"] == o.st.updates
+    assert st["node_moves"] == o.st.node_moves and st["patches"] == o.st.patches
     assert (rel_groups(Q, o.st.Q) < TOL).all()
     assert np.abs(X - o.st.X).max() < TOL * _span(mesh)
     assert o.st.updates < 2 * 8 * mesh.n_elems         # fewer updates than GTS at the finest step

@@ -132,6 +132,7 @@ def test_end_to_end_parity(name, levels, steps):
     Q, X, t = g.download()
     assert stg["macro_steps"] == steps
     assert stg["element_updates"] == o.st.updates
+    assert stg["node_moves"] == o.st.node_moves and stg["patches"] == o.st.patches
     assert abs(stg["t"] - o.st.T) <= 1e-13 * o.st.T
     assert (rel_groups(Q, o.st.Q) < TOL).all(), rel_groups(Q, o.st.Q)
     assert np.abs(X - o.st.X).max() < TOL * _span(mesh)
@@ -221,6 +222,7 @@ def test_free_steps_end_to_end_parity(name, t_end):
           f"launched {stg['cycles']}", flush=True)
     assert stg["macro_steps"] == o.st.macro_steps == 1
     assert stg["element_updates"] == o.st.updates
+    assert stg["node_moves"] == o.st.node_moves and stg["patches"] == o.st.patches
     assert stg["cfl_overshoots"] == o.st.cfl_overshoots == 0
     assert stg["cycles"] == 16 * -(-o.st.cycles // 16)      # launched in batches of 16
     assert stg["t"] == o.st.T == t_end
