@@ -49,9 +49,9 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
 # traffic is reported null.
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
-    "source_sha256": "859025c29dfd0b38ff9a94a03fbd353e11640e62e5e46fbe070250c5746e60f4",
-    "k_reconstruct": {0: 1154, 4: 1112, 8: 1117, 16: 1075, 32: 1107},
-    "k_predict": {0: 1503, 4: 1504, 8: 1505, 16: 1503, 32: 1502},
+    "source_sha256": "4815fd071c714618621de20379dc6e45963519d7157e0bed89e82490b1146ba1",
+    "k_reconstruct": {0: 1152, 4: 1111, 8: 1119, 16: 1077, 32: 1109},
+    "k_predict": {0: 1501, 4: 1501, 8: 1501, 16: 1500, 32: 1499},
 }
 
 

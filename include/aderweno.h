@@ -55,7 +55,10 @@ enum {
  *           bounded over both states (not in the paper). */
 enum { ADER_FLUX_RUSANOV = 0, ADER_FLUX_OSHER = 1, ADER_FLUX_HLL = 2 };
 
-/* Boundary tags of ader_upload_mesh. */
+/* Boundary tags of ader_upload_mesh.  A transmissive edge takes as outer
+ * state the inner element's predicted cell mean at each flux point's time
+ * (a ghost copy of the element); a slip wall takes the mirror image of the
+ * inner state, and its nodes slide along the wall. */
 enum { ADER_BC_TRANSMISSIVE = 1, ADER_BC_SLIP = 2 };
 
 typedef struct ader_ctx ader_ctx;

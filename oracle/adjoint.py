@@ -170,6 +170,7 @@ class EulerianStep:
         self.At, self.Bt, self.Dt = tm["At"], tm["Bt"], tm["Dt"]
         self.Dxi, self.Deta = _t(nt["Dxi"]), _t(nt["Deta"])
         self.edge_tab = _t(nt["edge"])
+        self.amean = _t(nt["amean"])
         x0 = affine_map(Xe, nxy[:, 0], nxy[:, 1])                 # (NE,nb,2)
         x = np.repeat(x0[:, :, None, :], M + 1, axis=2).copy()
         x[:, :, 1:, :] = self.Bt[None, None, :, None] * x[:, :, 0:1, :]   # the motion ODE with V = 0
@@ -215,8 +216,9 @@ class EulerianStep:
         return torch.einsum("ml,nlv->nmv", self.psi_nodes, what)
 
     def predict(self, wnod, dt):
-        """Edge traces (NE, 3, nG, M+1, 4) of the space-time predictor with the
-        tau = 0 data fixed (eq. CGfinal), M+1 (or n_picard) Picard sweeps."""
+        """Edge traces (NE, 3, nG, M+1, 4) and cell means at the time nodes
+        (NE, M+1, 4) of the space-time predictor with the tau = 0 data fixed
+        (eq. CGfinal), M+1 (or n_picard) Picard sweeps."""
         M, cfg = self.M, self.cfg
         T = M + 1
         met = {k: _t(v)[..., None] for k, v in self.metric.items()}
@@ -235,11 +237,13 @@ class EulerianStep:
             upper = (Bt[None, None, :, None] * q[:, :, 0:1, :]
                      + dt * torch.einsum("qr,nmrv->nmqv", At, P))
             q = torch.cat([q[:, :, 0:1, :], upper], dim=2)
-        return torch.einsum("egm,nmtv->negtv", self.edge_tab, q)
+        return (torch.einsum("egm,nmtv->negtv", self.edge_tab, q),
+                torch.einsum("m,nmtv->ntv", self.amean, q))
 
-    def fluxes(self, trace, dt):
+    def fluxes(self, trace, avg, dt):
         """Edge fluxes G (NF, 4), outward from L, over the space-time faces of
-        the fixed edges (eq. eqn.STint with (M+1)^2 Gauss points)."""
+        the fixed edges (eq. eqn.STint with (M+1)^2 Gauss points); transmissive
+        edges take the inner element's predicted mean as outer state (R10)."""
         M, cfg = self.M, self.cfg
         nG = M + 1
         chi, wc = tb.gauss_legendre01(nG)
@@ -250,6 +254,7 @@ class EulerianStep:
         P4 = np.column_stack([self.Xa, z + dt])
         trL = trace[self.L, self.el]                          # (NF,nG,T,4)
         trR = trace[self.Rs, self.ers]
+        avL = avg[self.L]                                     # (NF,T,4)
         G = torch.zeros((self.Xa.shape[0], 4), dtype=_F64)
         for g in range(nG):
             for h in range(nG):
@@ -261,15 +266,16 @@ class EulerianStep:
                 lt = _t(tb.lagrange_time(M, np.array([tk]))[0])
                 ql = torch.einsum("q,eqv->ev", lt, trL[:, g])
                 qrr = torch.einsum("q,eqv->ev", lt, trR[:, nG - 1 - g])
-                qr = torch.where(self.slip[:, None], mirror(ql, N), ql)
+                qr = torch.where(self.slip[:, None], mirror(ql, N),
+                                 torch.einsum("q,eqv->ev", lt, avL))
                 qr = torch.where(self.hasR[:, None], qrr, qr)
                 G = G + (wc[g] * wc[h]) * FLUX_FUNCTIONS[cfg.flux](ql, qr, N, cfg.gamma)
         return G
 
     def __call__(self, Q, dt):
         """Q^{n+1} from Q^n (torch (NE, 4)) for the fixed step dt."""
-        trace = self.predict(self.reconstruct(Q), dt)
-        G = self.fluxes(trace, dt)
+        trace, avg = self.predict(self.reconstruct(Q), dt)
+        G = self.fluxes(trace, avg, dt)
         flux = torch.zeros_like(Q).index_add(0, self.L, G)
         flux = flux.index_add(0, self.Rs[self.hasR], -G[self.hasR])
         A = _t(self.area)[:, None]

@@ -30,9 +30,11 @@ design notes of the repository):
       the others in the least-squares sense (unweighted).  The nonlinear weight
       omega_s of eq. weno is one scalar per stencil, shared by the four
       conserved variables, computed from the indicator summed over them.
-  R10 boundaries: transmissive edges take the outer state equal to the inner
-      one; slip walls mirror the normal momentum and their nodes slide along
-      the (straight) wall.
+  R10 boundaries: a transmissive edge takes as outer state the inner element's
+      predicted cell mean at the flux point's time (a ghost copy of the
+      element; the inner trace as outer state would leave the face without
+      dissipation); slip walls mirror the normal momentum and their nodes slide
+      along the (straight) wall.
   R8  lateral patch states: each element's predictor at the reference edge
       point chi and at the patch time rescaled to the element's time slab;
       Rusanov speed taken pointwise with the unnormalised normal.
@@ -415,7 +417,7 @@ def mirror_state(q, N):
     return out
 
 
-def patch_batch(M, cfg: Config, P, ticks, nL, sL, trL, nR, sR, trR, hasR, bc=None):
+def patch_batch(M, cfg: Config, P, ticks, nL, sL, trL, nR, sR, trR, hasR, bc=None, avgL=None):
     """Flux and normal integral over bilinear space-time patches.
 
     P (E,4,3): corners (x, y, t) in the order old a, old b, new b, new a (eq.
@@ -423,8 +425,10 @@ def patch_batch(M, cfg: Config, P, ticks, nL, sL, trL, nR, sR, trR, hasR, bc=Non
     nL, sL (E,): left element tick and step; trL (E,nG,M+1,4) its edge trace
     (chi running from a to b).  nR, sR, trR likewise for the right element,
     whose trace is read in reverse chi order; hasR (E,) False on boundary edges.
-    bc (E,) boundary tag: transmissive edges take the outer state equal to the
-    inner one, slip walls its mirror image.
+    bc (E,) boundary tag: a transmissive edge takes as outer state the inner
+    element's predicted cell mean at the point's time (avgL (E,M+1,4), its
+    means at the time nodes; R10), a slip wall the mirror image of the inner
+    trace.
     Returns G (E,4) (outward from L) and Nint (E,3).
     """
     nG = M + 1
@@ -444,8 +448,14 @@ def patch_batch(M, cfg: Config, P, ticks, nL, sL, trL, nR, sR, trR, hasR, bc=Non
             lL = tb.lagrange_time(M, (tk - nL) / sL)
             ql = np.einsum("eq,eqv->ev", lL, trL[:, g])
             qr = ql.copy()
-            if bc is not None and (bc == BC_SLIP).any():
-                qr = np.where((bc == BC_SLIP)[:, None], mirror_state(ql, N), qr)
+            slip = np.zeros(E, bool) if bc is None else (bc == BC_SLIP)
+            if slip.any():
+                qr = np.where(slip[:, None], mirror_state(ql, N), qr)
+            open_ = ~hasR & ~slip
+            if open_.any():
+                if avgL is None:
+                    raise ValueError("transmissive edges need the inner element's predicted means")
+                qr = np.where(open_[:, None], np.einsum("eq,eqv->ev", lL, avgL), qr)
             if hasR.any():
                 sRs = np.where(hasR, sR, 1)
                 lR = tb.lagrange_time(M, (tk - nR) / sRs)
@@ -689,7 +699,7 @@ class Solver:
                 raise AssertionError("patch neighbour without a valid predictor")
             G, Nint = patch_batch(M, cfg, P, ticks, st.n[L], st.s[L], st.trace[L, el],
                                   st.n[Rs], st.s[Rs], st.trace[Rs, ers], hasR,
-                                  topo.bc_tag[swept])
+                                  topo.bc_tag[swept], st.avg[L])
             # memory variables (eq. eqn.Qm2 and the geometric memory H^M), R9
             np.subtract.at(st.QM, L, G)
             np.subtract.at(st.HM, L, Nint)
@@ -818,7 +828,7 @@ class GTSSolver:
         zero = np.zeros(a.size, np.int64)
         one = np.ones(a.size, np.int64)
         G, _ = patch_batch(M, cfg, P, ticks, zero, one, pr["trace"][L, el],
-                           zero, one, pr["trace"][Rs, ers], hasR, topo.bc_tag)
+                           zero, one, pr["trace"][Rs, ers], hasR, topo.bc_tag, pr["avg"][L])
         flux = np.zeros((topo.n_elems, 4))
         np.add.at(flux, L, G)
         np.subtract.at(flux, R[hasR], G[hasR])

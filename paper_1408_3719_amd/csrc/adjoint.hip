@@ -12,11 +12,14 @@
 // held fixed (the CFL step of eq. eqn.timestep is not differentiated):
 //   k_adj_recon<fwd>  reconstruction from the current averages (8 lanes per
 //                     element, lane s solves stencil s by Givens rotations)
-//   k_adj_pred_fwd    predictor sweeps, each iterate kept, edge traces
+//   k_adj_pred_fwd    predictor sweeps, each iterate kept, edge traces and
+//                     cell means at the time nodes
 //   k_adj_patch       adjoint of the fluxes: per edge, the flux adjoint
 //                     -qbar_L/|T_L| + qbar_R/|T_R| pulled back through the
 //                     Rusanov flux at every Gauss point onto the two elements'
-//                     trace adjoints (each (element, edge) slot has one writer)
+//                     trace adjoints, and on transmissive edges onto the inner
+//                     element's mean adjoint (each (element, edge) slot has
+//                     one writer)
 //   k_adj_pred_rev    the sweeps in reverse: trace adjoint -> adjoint of the
 //                     reconstruction's nodal values
 //   k_adj_recon<rev>  WENO weights and least squares in reverse from the data
@@ -651,6 +654,16 @@ __global__ void __launch_bounds__(TPB) k_adj_pred_fwd(Dev d, const Tables* __res
 #pragma unroll
           for (int v = 0; v < 4; ++v) q[m][r + 1][v] = qn[m][r][v];
     }
+    double* av = w.avg + size_t(i) * T * 4;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < nb; ++m) s += tb->amean[m] * q[m][t][v];
+        av[t * 4 + v] = s;
+      }
     double* tr = w.trace + size_t(i) * S::TS;
 #pragma unroll
     for (int e = 0; e < 3; ++e)
@@ -693,16 +706,21 @@ __global__ void __launch_bounds__(TPB) k_adj_patch(Dev d, const Tables* __restri
     }
     const double* trL = w.trace + size_t(L) * TS + el * nG * T * 4;
     const double* trR = R >= 0 ? w.trace + size_t(R) * TS + er * nG * T * 4 : trL;
-    double bL[nG][T][4], bR[nG][T][4];
+    const bool open_edge = R < 0 && bc != 2;
+    const double* avL = w.avg + size_t(L) * T * 4;
+    double bL[nG][T][4], bR[nG][T][4], bA[T][4];
 #pragma unroll
-    for (int g = 0; g < nG; ++g)
+    for (int t = 0; t < T; ++t) {
 #pragma unroll
-      for (int t = 0; t < T; ++t)
+      for (int g = 0; g < nG; ++g)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           bL[g][t][v] = 0.0;
           bR[g][t][v] = 0.0;
         }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bA[t][v] = 0.0;
+    }
 #pragma unroll
     for (int gq = 0; gq < nG; ++gq) {
       const double c = tb->gchi[gq];
@@ -745,9 +763,15 @@ __global__ void __launch_bounds__(TPB) k_adj_patch(Dev d, const Tables* __restri
           qr[1] = ql[1] - 2.0 * mn * nx;
           qr[2] = ql[2] - 2.0 * mn * ny;
           qr[3] = ql[3];
-        } else if (R < 0) {
+        } else if (open_edge) {
+          // transmissive: the inner element's predicted mean at this time
 #pragma unroll
-          for (int v = 0; v < 4; ++v) qr[v] = ql[v];
+          for (int v = 0; v < 4; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < T; ++t) s += l[t] * avL[t * 4 + v];
+            qr[v] = s;
+          }
         }
         double Gw[4], qlb[4] = {0, 0, 0, 0}, qrb[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -770,7 +794,9 @@ __global__ void __launch_bounds__(TPB) k_adj_patch(Dev d, const Tables* __restri
           qlb[3] += qrb[3];
         } else {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) qlb[v] += qrb[v];
+          for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bA[t][v] += l[t] * qrb[v];
         }
 #pragma unroll
         for (int t = 0; t < T; ++t)
@@ -785,7 +811,16 @@ __global__ void __launch_bounds__(TPB) k_adj_patch(Dev d, const Tables* __restri
       for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) oL[(g * T + t) * 4 + v] = bL[g][t][v];
+    // mean adjoints: this edge is the only writer of its two (element, edge) slots
+    double* aL = w.abar + (size_t(L) * 3 + el) * T * 4;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) aL[t * 4 + v] = bA[t][v];
     if (R >= 0) {
+      double* aR = w.abar + (size_t(R) * 3 + er) * T * 4;
+#pragma unroll
+      for (int c = 0; c < T * 4; ++c) aR[c] = 0.0;
       double* oR = w.tbar + size_t(R) * TS + er * nG * T * 4;
 #pragma unroll
       for (int g = 0; g < nG; ++g)
@@ -823,7 +858,8 @@ __global__ void __launch_bounds__(TPB) k_adj_pred_rev(Dev d, const Tables* __res
           for (int e = 0; e < 3; ++e)
 #pragma unroll
             for (int g = 0; g < nG; ++g) s += tb->edge[e][g][m] * tb_i[((e * nG + g) * T + t) * 4 + v];
-          qb[m][t][v] = s;
+          const double* ab = w.abar + size_t(i) * 3 * T * 4 + t * 4 + v;
+          qb[m][t][v] = s + tb->amean[m] * (ab[0] + ab[T * 4] + ab[2 * T * 4]);
         }
 #pragma unroll 1
     for (int k = P.npic - 1; k >= 0; --k) {
@@ -934,7 +970,7 @@ int lsq_slots(int M) {
 
 // Buffer sizes in bytes: nodal values, traces, sweeps, kept least-squares data.
 void adjoint_sizes(int M, int NE, int npic, size_t& ws, size_t& ts, size_t& sw, size_t& lq,
-                   size_t& rb, size_t& qc) {
+                   size_t& rb, size_t& qc, size_t& mb) {
   const size_t nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, D = sizeof(double);
   ws = align256(NE * size_t(wnod_stride(M)) * D);
   ts = align256(NE * size_t(trace_stride(M)) * D);
@@ -942,19 +978,20 @@ void adjoint_sizes(int M, int NE, int npic, size_t& ws, size_t& ts, size_t& sw, 
   lq = align256(size_t(lsq_slots(M)) * 8 * NE * D);
   rb = align256(size_t(2 * nb) * NE * 32 * D);
   qc = align256(size_t(4) * NE * D);
+  mb = align256(size_t(4) * T * 4 * NE * D);   // means and their per-edge adjoints
 }
 
 }  // namespace
 
 size_t adjoint_work_bytes(int M, int NE, int npic) {
-  size_t ws, ts, sw, lq, rb, qc;
-  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb, qc);
-  return 2 * ws + 2 * ts + sw + lq + rb + qc;
+  size_t ws, ts, sw, lq, rb, qc, mb;
+  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb, qc, mb);
+  return 2 * ws + 2 * ts + sw + lq + rb + qc + mb;
 }
 
 void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w) {
-  size_t ws, ts, sw, lq, rb, qc;
-  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb, qc);
+  size_t ws, ts, sw, lq, rb, qc, mb;
+  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb, qc, mb);
   w.wnod = (double*)base;
   w.wbar = (double*)(base + ws);
   w.trace = (double*)(base + 2 * ws);
@@ -963,6 +1000,8 @@ void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w) {
   w.lsq = (double*)(base + 2 * ws + 2 * ts + sw);
   w.rowbar = (double*)(base + 2 * ws + 2 * ts + sw + lq);
   w.qcopy = (double*)(base + 2 * ws + 2 * ts + sw + lq + rb);
+  w.avg = (double*)(base + 2 * ws + 2 * ts + sw + lq + rb + qc);
+  w.abar = w.avg + size_t(NE) * (M + 1) * 4;
 }
 
 int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,

@@ -159,6 +159,8 @@ struct AdjWork {
   double* lsq;               // [slot][NE][8] per stencil lane: R factor, solution, weight,
                              // indicator and least-squares rows of the forward pass
   double* rowbar;            // [NE][ne][8][4] adjoint of each stencil row's right-hand side
+  double* avg;               // [NE][M+1][4] predictor cell means at the time nodes
+  double* abar;              // [NE][3][M+1][4] their adjoints, one slot per (element, edge)
                              // (row 0: the element's own terms), summed by the gather
 };
 

@@ -1162,8 +1162,17 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
           qr[2] = ql[2] - 2.0 * mn * ny;
           qr[3] = ql[3];
         } else {
+          // transmissive: the inner element's predicted cell mean at this
+          // time (a ghost copy of the element; the inner trace as outer state
+          // leaves the face without dissipation and lets boundary modes grow)
+          const double* rl = rec<M>(d, L);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) qr[v] = ql[v];
+          for (int v = 0; v < 4; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < T; ++t) s += lL[t] * rl[AVG + t * 4 + v];
+            qr[v] = s;
+          }
         }
         double fn[4];
         numerical_flux(P.flux, tb, ql, qr, N, g, fn);

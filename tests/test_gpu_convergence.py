@@ -1,18 +1,24 @@
-"""The method on the GPU path at full resolution: the isentropic vortex (paper
-Sec. 3.1, strength 5, background velocity (1, 1)) run with LTS (3 levels) to
-t = 1 on 5k/20k/80k-triangle graded meshes. The error of the cell averages
-against the exact averages over the moved triangles, within radius 3 of the
-vortex centre, falls at close to the design order M+1 (the paper reports L2
-orders 2.8 for M=2 and 3.8 for M=3 with periodic boundaries). Over the whole
-square the transmissive boundaries, which the vortex's tail still touches
-(velocity perturbation ~4e-4 at the edges), set an error floor near 1e-4."""
+"""The method on the GPU path at full resolution.
+
+The isentropic vortex (paper Sec. 3.1, strength 5, background velocity (1, 1))
+run with LTS (3 levels) to t = 1: on the workload's 5k/20k/80k-triangle graded
+meshes of [0,10]^2, the error of the cell averages against the exact averages
+over the moved triangles, within radius 3 of the vortex centre, falls at close
+to the design order M+1; on a square twice as wide, where the vortex's tail is
+below round-off at the boundary, the paper's continuous L2 error of the
+reconstructed density over the whole domain does too (the paper reports orders
+2.1, 2.8 and 3.8 for M = 1, 2, 3 with periodic boundaries).
+
+Transmissive boundaries: a uniform flow carrying 1e-10 noise stays at the
+noise level through t = 2 (with the inner trace as outer state, a boundary mode
+grew from such noise to O(1) within t = 2)."""
 import math
 from types import SimpleNamespace
 
 import numpy as np
 import pytest
 
-from workloads import cell_average, vortex_case, vortex_primitive
+from workloads import cell_average, square_graded_mesh, vortex_case, vortex_primitive
 
 pytestmark = pytest.mark.gpu
 
@@ -46,3 +52,54 @@ def test_vortex_design_order(M, min_order):
               for k in range(2)]
     print(f"M={M} orders {orders}", flush=True)
     assert orders[-1] > min_order, (res, orders)
+
+
+def _l2_whole(M, h_fine):
+    """Continuous L2 norm of rho - w_h over the moved domain at t = 1 (the
+    paper's error measure), vortex centred in [-5,15]^2."""
+    from oracle import tables as tb
+    from oracle.scheme import affine_map
+    from paper_1408_3719_amd import Config, Solver
+    mesh = square_graded_mesh(h_fine, 1, lo=-5.0, hi=15.0, name="vortex")
+    Q0 = cell_average(mesh, vortex_primitive, 1.4)
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=3))
+    st = s.step_lts(1.0)
+    assert abs(st["t"] - 1.0) < 1e-12 and st["max_gcl_residual"] < 1e-12
+    _, X, _ = s.download()
+    wn = np.transpose(s.dump("WNOD"), (2, 0, 1))          # (NE, nb, 4) nodal values
+    xi, eta, w = tb.duffy_rule(M + 3)
+    p = X[mesh.tris]
+    x = affine_map(p, xi, eta)
+    ex = vortex_primitive(x[..., 0] - 1.0, x[..., 1] - 1.0)[..., 0]
+    wh = np.einsum("qm,em->eq", tb.eval_phi(M, xi, eta), wn[:, :, 0])
+    A = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+               - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    err = math.sqrt(float(((((wh - ex) ** 2) * w[None, :]).sum(axis=1) * 2 * A).sum()))
+    print(f"M={M} n={mesh.n_elems} whole-domain L2(rho) {err:.4e}", flush=True)
+    return err, math.sqrt(A.mean())
+
+
+@pytest.mark.parametrize("M,min_order", [(1, 1.6), (2, 2.6), (3, 3.3)])
+def test_vortex_design_order_whole_domain(M, min_order):
+    res = [_l2_whole(M, h) for h in (0.09274, 0.04637, 0.02318)]   # ~10k, 39k, 155k
+    orders = [math.log(res[k][0] / res[k + 1][0]) / math.log(res[k][1] / res[k + 1][1])
+              for k in range(2)]
+    print(f"M={M} whole-domain orders {orders}", flush=True)
+    assert min(orders) > min_order, (res, orders)
+
+
+@pytest.mark.parametrize("levels,velocity,t_end,bound", [
+    (1, "lagrangian", 2.0, 1e-9), (3, "lagrangian", 2.0, 1e-9), (1, "eulerian", 1.0, 1e-7)])
+def test_transmissive_boundaries_do_not_amplify_noise(levels, velocity, t_end, bound):
+    from paper_1408_3719_amd import Config, Solver
+    mesh = square_graded_mesh(0.02318, 1, name="uniform")            # ~75k triangles
+    rng = np.random.default_rng(3)
+    Q0 = np.tile([1.0, 1.0, 1.0, 1.0 / 0.4 + 1.0], (mesh.n_elems, 1))
+    Q0[:, 0] += 1e-10 * rng.standard_normal(mesh.n_elems)
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
+               Config(M=2, levels=levels, mesh_velocity=velocity))
+    st = s.step_lts(t_end) if levels > 1 else s.step_gts(t_end, 1_000_000)
+    assert abs(st["t"] - t_end) < 1e-12
+    dev = np.abs(s.download()[0][:, 0] - 1.0).max()
+    print(f"L={levels} {velocity} t={t_end}: max |rho - 1| = {dev:.3e}", flush=True)
+    assert dev < bound

@@ -166,7 +166,8 @@ def _patch(P, ticks, trL, trR=None, M=1):
     zero = np.zeros(E, np.int64)
     hasR = np.zeros(E, bool) if trR is None else np.ones(E, bool)
     trR = trL if trR is None else trR
-    return patch_batch(M, Config(M=M), P, ticks, zero, one * 4, trL, zero, one * 4, trR, hasR)
+    return patch_batch(M, Config(M=M), P, ticks, zero, one * 4, trL, zero, one * 4, trR, hasR,
+                       avgL=trL[:, 0])    # constant traces: the means equal them
 
 
 def _const_trace(Q, M, E=1):
