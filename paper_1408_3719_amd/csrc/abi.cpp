@@ -1035,7 +1035,7 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
 int ader_adjoint_workspace_size(const ader_ctx* c, size_t* bytes) {
   if (!c || !bytes) return ADER_E_ARG;
   if (!c->has_mesh) return ADER_E_ORDER;
-  *bytes = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->prm.npic);
+  *bytes = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->topo.NF, c->prm.npic);
   return ADER_OK;
 }
 
@@ -1049,14 +1049,14 @@ int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Q_dev, const dou
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (!Q_dev && !c->synced)
     return fail(c, ADER_E_ORDER, "elements are not at a common time (macro step in progress)");
-  const size_t need = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->prm.npic);
+  const size_t need = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->topo.NF, c->prm.npic);
   if (work_bytes < need) return fail(c, ADER_E_ARG, "adjoint workspace too small");
   if ((reinterpret_cast<uintptr_t>(work_dev) & 255) != 0)
     return fail(c, ADER_E_ARG, "adjoint workspace must be 256-byte aligned");
   aw::AdjWork w{};
   w.qbar_next = Qbar_next_dev;
   w.qbar = Qbar_dev;
-  aw::adjoint_carve(c->cfg.M, c->topo.NE, c->prm.npic, static_cast<char*>(work_dev), w);
+  aw::adjoint_carve(c->cfg.M, c->topo.NE, c->topo.NF, c->prm.npic, static_cast<char*>(work_dev), w);
   w.q = Q_dev ? Q_dev : w.qcopy;
   LCHK(c, timed(c, ADER_K_ADJOINT, c->stream, [&] {
     return aw::launch_adjoint_gts(c->dev, c->prm, c->cfg.M, w, dt, Q_dev == nullptr, c->stream);

@@ -17,9 +17,9 @@
 //   k_adj_patch       adjoint of the fluxes: per edge, the flux adjoint
 //                     -qbar_L/|T_L| + qbar_R/|T_R| pulled back through the
 //                     Rusanov flux at every Gauss point onto the two elements'
-//                     trace adjoints, and on transmissive edges onto the inner
-//                     element's mean adjoint (each (element, edge) slot has
-//                     one writer)
+//                     trace adjoints (each (element, edge) slot has one
+//                     writer), and on a transmissive edge onto the inner
+//                     element's mean adjoint in the edge's own slot
 //   k_adj_pred_rev    the sweeps in reverse: trace adjoint -> adjoint of the
 //                     reconstruction's nodal values
 //   k_adj_recon<rev>  WENO weights and least squares in reverse from the data
@@ -811,16 +811,15 @@ __global__ void __launch_bounds__(TPB) k_adj_patch(Dev d, const Tables* __restri
       for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) oL[(g * T + t) * 4 + v] = bL[g][t][v];
-    // mean adjoints: this edge is the only writer of its two (element, edge) slots
-    double* aL = w.abar + (size_t(L) * 3 + el) * T * 4;
+    if (open_edge) {
+      // adjoint of the inner element's means, in this edge's own slot
+      double* aL = w.abar + size_t(e) * T * 4;
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+      for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) aL[t * 4 + v] = bA[t][v];
+        for (int v = 0; v < 4; ++v) aL[t * 4 + v] = bA[t][v];
+    }
     if (R >= 0) {
-      double* aR = w.abar + (size_t(R) * 3 + er) * T * 4;
-#pragma unroll
-      for (int c = 0; c < T * 4; ++c) aR[c] = 0.0;
       double* oR = w.tbar + size_t(R) * TS + er * nG * T * 4;
 #pragma unroll
       for (int g = 0; g < nG; ++g)
@@ -845,6 +844,23 @@ __global__ void __launch_bounds__(TPB) k_adj_pred_rev(Dev d, const Tables* __res
 #pragma unroll
     for (int c = 0; c < 6; ++c) X[c] = ri[XE + c];
     affine_metric(X, mt);
+    // adjoint of the means, from the element's transmissive edges (if any)
+    double ab[T][4];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ab[t][v] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int e = d.elem_edges[k * NE + i];
+      if (d.e_R[e] < 0 && d.e_bc[e] != 2) {
+        const double* a = w.abar + size_t(e) * T * 4;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ab[t][v] += a[t * 4 + v];
+      }
+    }
     double qb[nb][T][4];
     const double* tb_i = w.tbar + size_t(i) * S::TS;
 #pragma unroll
@@ -858,8 +874,7 @@ __global__ void __launch_bounds__(TPB) k_adj_pred_rev(Dev d, const Tables* __res
           for (int e = 0; e < 3; ++e)
 #pragma unroll
             for (int g = 0; g < nG; ++g) s += tb->edge[e][g][m] * tb_i[((e * nG + g) * T + t) * 4 + v];
-          const double* ab = w.abar + size_t(i) * 3 * T * 4 + t * 4 + v;
-          qb[m][t][v] = s + tb->amean[m] * (ab[0] + ab[T * 4] + ab[2 * T * 4]);
+          qb[m][t][v] = s + tb->amean[m] * ab[t][v];
         }
 #pragma unroll 1
     for (int k = P.npic - 1; k >= 0; --k) {
@@ -969,7 +984,7 @@ int lsq_slots(int M) {
 }
 
 // Buffer sizes in bytes: nodal values, traces, sweeps, kept least-squares data.
-void adjoint_sizes(int M, int NE, int npic, size_t& ws, size_t& ts, size_t& sw, size_t& lq,
+void adjoint_sizes(int M, int NE, int NF, int npic, size_t& ws, size_t& ts, size_t& sw, size_t& lq,
                    size_t& rb, size_t& qc, size_t& mb) {
   const size_t nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, D = sizeof(double);
   ws = align256(NE * size_t(wnod_stride(M)) * D);
@@ -978,20 +993,20 @@ void adjoint_sizes(int M, int NE, int npic, size_t& ws, size_t& ts, size_t& sw, 
   lq = align256(size_t(lsq_slots(M)) * 8 * NE * D);
   rb = align256(size_t(2 * nb) * NE * 32 * D);
   qc = align256(size_t(4) * NE * D);
-  mb = align256(size_t(4) * T * 4 * NE * D);   // means and their per-edge adjoints
+  mb = align256(size_t(T) * 4 * (NE + NF) * D);   // means, and their adjoints per edge
 }
 
 }  // namespace
 
-size_t adjoint_work_bytes(int M, int NE, int npic) {
+size_t adjoint_work_bytes(int M, int NE, int NF, int npic) {
   size_t ws, ts, sw, lq, rb, qc, mb;
-  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb, qc, mb);
+  adjoint_sizes(M, NE, NF, npic, ws, ts, sw, lq, rb, qc, mb);
   return 2 * ws + 2 * ts + sw + lq + rb + qc + mb;
 }
 
-void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w) {
+void adjoint_carve(int M, int NE, int NF, int npic, char* base, AdjWork& w) {
   size_t ws, ts, sw, lq, rb, qc, mb;
-  adjoint_sizes(M, NE, npic, ws, ts, sw, lq, rb, qc, mb);
+  adjoint_sizes(M, NE, NF, npic, ws, ts, sw, lq, rb, qc, mb);
   w.wnod = (double*)base;
   w.wbar = (double*)(base + ws);
   w.trace = (double*)(base + 2 * ws);
@@ -1001,7 +1016,7 @@ void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w) {
   w.rowbar = (double*)(base + 2 * ws + 2 * ts + sw + lq);
   w.qcopy = (double*)(base + 2 * ws + 2 * ts + sw + lq + rb);
   w.avg = (double*)(base + 2 * ws + 2 * ts + sw + lq + rb + qc);
-  w.abar = w.avg + size_t(NE) * (M + 1) * 4;
+  w.abar = w.avg + size_t(NE) * (M + 1) * 4;   // [NF][M+1][4]
 }
 
 int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,

@@ -160,14 +160,14 @@ struct AdjWork {
                              // indicator and least-squares rows of the forward pass
   double* rowbar;            // [NE][ne][8][4] adjoint of each stencil row's right-hand side
   double* avg;               // [NE][M+1][4] predictor cell means at the time nodes
-  double* abar;              // [NE][3][M+1][4] their adjoints, one slot per (element, edge)
+  double* abar;              // [NF][M+1][4] their adjoints, a slot per transmissive edge
                              // (row 0: the element's own terms), summed by the gather
 };
 
 // Bytes of the adjoint workspace (each buffer 256-byte aligned).
-size_t adjoint_work_bytes(int M, int NE, int npic);
+size_t adjoint_work_bytes(int M, int NE, int NF, int npic);
 // Carve the buffers from base (qbar_next, qbar left to the caller).
-void adjoint_carve(int M, int NE, int npic, char* base, AdjWork& w);
+void adjoint_carve(int M, int NE, int NF, int npic, char* base, AdjWork& w);
 // The reverse-mode step: qbar = (dQ^{n+1}/dQ^n)^T qbar_next for one global
 // step of length dt on a fixed mesh (adjoint.hip).
 int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,
