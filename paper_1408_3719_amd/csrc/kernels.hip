@@ -374,6 +374,54 @@ __device__ inline double group8_sum(double v) {
   return v;
 }
 
+// Means of the monomials x^a y^b (a + b <= M) over a triangle with vertices
+// (x[k], y[k]), by a rule exact to degree M with its points written out: the
+// centroid (M=1), the edge midpoints (M=2), and the vertices, edge midpoints
+// and centroid with weights 3/60, 8/60, 27/60 (M=3).
+template <int M>
+__device__ inline void monomial_means(const double x[3], const double y[3], double mm[]) {
+  constexpr int nb = (M + 1) * (M + 2) / 2;
+#pragma unroll
+  for (int k = 0; k < nb; ++k) mm[k] = 0.0;
+  auto point = [&](double w, double px, double py) {
+    double xp[M + 1], yp[M + 1];
+    xp[0] = 1.0;
+    yp[0] = 1.0;
+#pragma unroll
+    for (int a = 1; a <= M; ++a) {
+      xp[a] = xp[a - 1] * px;
+      yp[a] = yp[a - 1] * py;
+    }
+    int k = 0;
+#pragma unroll
+    for (int dg = 0; dg <= M; ++dg)
+#pragma unroll
+      for (int b = 0; b <= dg; ++b) {
+        mm[k] += w * xp[dg - b] * yp[b];
+        ++k;
+      }
+  };
+  constexpr double third = 1.0 / 3.0;
+  if constexpr (M == 1) {
+    point(1.0, (x[0] + x[1] + x[2]) * third, (y[0] + y[1] + y[2]) * third);
+  } else if constexpr (M == 2) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = k == 2 ? 0 : k + 1;
+      point(third, 0.5 * (x[k] + x[k1]), 0.5 * (y[k] + y[k1]));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) point(3.0 / 60.0, x[k], y[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = k == 2 ? 0 : k + 1;
+      point(8.0 / 60.0, 0.5 * (x[k] + x[k1]), 0.5 * (y[k] + y[k1]));
+    }
+    point(27.0 / 60.0, (x[0] + x[1] + x[2]) * third, (y[0] + y[1] + y[2]) * third);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Reconstruction + local time step: 8 lanes per element
 // ---------------------------------------------------------------------------
@@ -443,29 +491,7 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
         }
         // means of the monomials over the virtual element (rule exact to degree M)
         double mm[nb];
-#pragma unroll
-        for (int k = 0; k < nb; ++k) mm[k] = 0.0;
-        for (int r = 0; r < tb->nrq; ++r) {
-          const double px = tb->rqb[r][0] * rx[0] + tb->rqb[r][1] * rx[1] + tb->rqb[r][2] * rx[2];
-          const double py = tb->rqb[r][0] * ry[0] + tb->rqb[r][1] * ry[1] + tb->rqb[r][2] * ry[2];
-          const double w = tb->rqw[r];
-          double xp[M + 1], yp[M + 1];
-          xp[0] = 1.0;
-          yp[0] = 1.0;
-#pragma unroll
-          for (int a = 1; a <= M; ++a) {
-            xp[a] = xp[a - 1] * px;
-            yp[a] = yp[a - 1] * py;
-          }
-          int k = 0;
-#pragma unroll
-          for (int dg = 0; dg <= M; ++dg)
-#pragma unroll
-            for (int b = 0; b <= dg; ++b) {
-              mm[k] += w * xp[dg - b] * yp[b];
-              ++k;
-            }
-        }
+        monomial_means<M>(rx, ry, mm);
         double a[nu], b[4];
 #pragma unroll
         for (int l = 0; l < nu; ++l) {
