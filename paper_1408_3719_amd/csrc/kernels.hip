@@ -374,6 +374,25 @@ __device__ inline double group8_sum(double v) {
   return v;
 }
 
+// Means of the monomials x^a y^b over the reference triangle (0,0), (1,0),
+// (0,1): 2 a! b! / (a + b + 2)!, in the order of increasing degree, then b.
+template <int M>
+struct RefMeans {
+  static constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+  struct Arr {
+    double v[(M + 1) * (M + 2) / 2];
+    constexpr double operator[](int k) const { return v[k]; }
+  };
+  static constexpr Arr make() {
+    Arr r{};
+    int k = 0;
+    for (int d = 0; d <= M; ++d)
+      for (int b = 0; b <= d; ++b) r.v[k++] = 2.0 * fact(d - b) * fact(b) / fact(d + 2);
+    return r;
+  }
+  static constexpr Arr m = make();
+};
+
 // Means of the monomials x^a y^b (a + b <= M) over a triangle with vertices
 // (x[k], y[k]), by a rule exact to degree M with its points written out: the
 // centroid (M=1), the edge midpoints (M=2), and the vertices, edge midpoints
@@ -489,17 +508,14 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
           rx[k] = (dx * e2y - dy * e2x) * idet;
           ry[k] = (e1x * dy - e1y * dx) * idet;
         }
-        // means of the monomials over the virtual element (rule exact to degree M)
+        // means of the monomials over the virtual element (rule exact to degree
+        // M); the row is taken in the monomials shifted by their means on the
+        // reference triangle, which span the same space as psi_1 .. psi_nu
         double mm[nb];
         monomial_means<M>(rx, ry, mm);
         double a[nu], b[4];
 #pragma unroll
-        for (int l = 0; l < nu; ++l) {
-          double s2 = 0.0;
-#pragma unroll
-          for (int k = 0; k < nb; ++k) s2 += tb->psiC[l + 1][k] * mm[k];
-          a[l] = s2;
-        }
+        for (int l = 0; l < nu; ++l) a[l] = mm[l + 1] - RefMeans<M>::m[l + 1];
 #pragma unroll
         for (int v = 0; v < 4; ++v) b[v] = Qv[v] - Qi[v];
         // Givens rotations fold the row into the triangular factor
@@ -525,7 +541,7 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
           }
         }
       }
-      double w[nu][4];
+      double u[nu][4];
 #pragma unroll
       for (int k = nu - 1; k >= 0; --k) {
         const double rinv = 1.0 / R[k][k];
@@ -533,10 +549,21 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
         for (int v = 0; v < 4; ++v) {
           double t = z[k][v];
 #pragma unroll
-          for (int c2 = k + 1; c2 < nu; ++c2) t -= R[k][c2] * w[c2][v];
-          w[k][v] = t * rinv;
+          for (int c2 = k + 1; c2 < nu; ++c2) t -= R[k][c2] * u[c2][v];
+          u[k][v] = t * rinv;
         }
       }
+      // coefficients of psi_1 .. psi_nu
+      double w[nu][4];
+#pragma unroll
+      for (int l = 0; l < nu; ++l)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double t = 0.0;
+#pragma unroll
+          for (int k = 0; k < nu; ++k) t += tb->monoToPsi[l][k] * u[k][v];
+          w[l][v] = t;
+        }
       double sigma = 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
