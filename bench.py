@@ -49,9 +49,9 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
 # traffic is reported null.
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
-    "source_sha256": "eb1d1717b9b15b8565706c9229653001d61cb65cc64cc024f801e19947707fbe",
-    "k_reconstruct": {0: 1278, 4: 1236, 8: 1229, 16: 1181, 32: 1233},
-    "k_predict": {0: 1501, 4: 1501, 8: 1501, 16: 1503, 32: 1500},
+    "source_sha256": "42a53d3b5d9bd17ed4a082303675b832d26808cbc23254a3b2438d16e1f52552",
+    "k_reconstruct": {0: 1150, 4: 1109, 8: 1115, 16: 1075, 32: 1105},
+    "k_predict": {0: 1502, 4: 1503, 8: 1500, 16: 1501, 32: 1500},
 }
 
 

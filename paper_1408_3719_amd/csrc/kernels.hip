@@ -198,24 +198,65 @@ __device__ inline double tick_ratio(double a_minus_b, int step) {
   return (step & (step - 1)) == 0 ? ldexp(a_minus_b, -__builtin_ctz(step)) : a_minus_b / double(step);
 }
 
+// Monomial coefficients of the Lagrange polynomials l_q on the time nodes
+// q/M (q = 0..M) and of their integrals from 0, evaluated at compile time so
+// that they enter the kernels as constants (the same polynomials as the host
+// tables, built as products of the linear factors (tau - j/M) / ((q - j)/M)).
 template <int M>
-__device__ inline void time_basis(const Tables* tb, double tau, double l[M + 1]) {
+struct TimePoly {
+  static constexpr int T = M + 1;
+  struct Coef {
+    double lag[T][T];
+    double lint[T][T + 1];
+  };
+  static constexpr Coef make() {
+    Coef c{};
+    for (int q = 0; q < T; ++q) {
+      double p[T] = {};
+      p[0] = 1.0;
+      int deg = 0;
+      for (int j = 0; j < T; ++j) {
+        if (j == q) continue;
+        const double tj = double(j) / M, den = double(q - j) / M;
+        double np[T] = {};
+        for (int k = 0; k <= deg; ++k) {
+          np[k + 1] += p[k] / den;
+          np[k] -= p[k] * tj / den;
+        }
+        ++deg;
+        for (int k = 0; k < T; ++k) p[k] = np[k];
+      }
+      c.lint[q][0] = 0.0;
+      for (int k = 0; k < T; ++k) {
+        c.lag[q][k] = p[k];
+        c.lint[q][k + 1] = p[k] / (k + 1);
+      }
+    }
+    return c;
+  }
+  static constexpr Coef c = make();
+};
+
+template <int M>
+__device__ inline void time_basis(double tau, double l[M + 1]) {
+  constexpr auto& C = TimePoly<M>::c;
 #pragma unroll
   for (int q = 0; q <= M; ++q) {
-    double s = tb->lag[q][M];
+    double s = C.lag[q][M];
 #pragma unroll
-    for (int k = M - 1; k >= 0; --k) s = s * tau + tb->lag[q][k];
+    for (int k = M - 1; k >= 0; --k) s = s * tau + C.lag[q][k];
     l[q] = s;
   }
 }
 
 template <int M>
-__device__ inline void time_antideriv(const Tables* tb, double tau, double L[M + 1]) {
+__device__ inline void time_antideriv(double tau, double L[M + 1]) {
+  constexpr auto& C = TimePoly<M>::c;
 #pragma unroll
   for (int q = 0; q <= M; ++q) {
-    double s = tb->Lint[q][M + 1];
+    double s = C.lint[q][M + 1];
 #pragma unroll
-    for (int k = M; k >= 0; --k) s = s * tau + tb->Lint[q][k];
+    for (int k = M; k >= 0; --k) s = s * tau + C.lint[q][k];
     L[q] = s;
   }
 }
@@ -268,8 +309,8 @@ __device__ inline bool place_nbr(const Tables* tb, const NbrRaw<M>& r, TickStep 
   const double tau = tick_ratio(double(nt - tsj.tick), tsj.step);
   const double dtj = double(tsj.step) * delta;
   double L[T], l[T];
-  time_antideriv<M>(tb, tau, L);
-  time_basis<M>(tb, tau, l);
+  time_antideriv<M>(tau, L);
+  time_basis<M>(tau, l);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -1083,8 +1124,8 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
       const double tau0 = tick_ratio(double(nk - tsj.tick), tsj.step);
       const double tau1 = tick_ratio(double(newt - tsj.tick), tsj.step);
       double L0[T], L1[T];
-      time_antideriv<M>(tb, tau0, L0);
-      time_antideriv<M>(tb, tau1, L1);
+      time_antideriv<M>(tau0, L0);
+      time_antideriv<M>(tau1, L1);
       const double* rj = rec<M>(d, j);
       double vx = 0.0, vy = 0.0;
 #pragma unroll
@@ -1186,7 +1227,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
         N[2] = dchi[0] * dtau[1] - dchi[1] * dtau[0];
         const double tk = (1.0 - c) * (1.0 - tt) * n1 + c * (1.0 - tt) * n2 + c * tt * n3 + (1.0 - c) * tt * n4;
         double lL[T];
-        time_basis<M>(tb, tick_ratio(tk - tL.tick, tL.step), lL);
+        time_basis<M>(tick_ratio(tk - tL.tick, tL.step), lL);
         double ql[4], qr[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -1197,7 +1238,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
         }
         if (R >= 0) {
           double lR[T];
-          time_basis<M>(tb, tick_ratio(tk - tR.tick, tR.step), lR);
+          time_basis<M>(tick_ratio(tk - tR.tick, tR.step), lR);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             double s = 0.0;
