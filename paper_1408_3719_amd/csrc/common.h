@@ -37,10 +37,6 @@ struct Tables {
   double rqw[MAXRQ];                // triangle rule, exact to degree M (barycentric)
   double rqb[MAXRQ][3];
   double osh_s[3], osh_w[3];        // Gauss-Legendre on [0,1] for the Osher path integral
-  // Least squares in the shifted monomials mono_k - mean_ref(mono_k), k >= 1:
-  // psi_l = sum_{k>=1} psiC[l][k] (mono_k - mean_ref(mono_k)) for l >= 1, so a
-  // solution u in those monomials gives w_l = sum_k monoToPsi[l-1][k-1] u_k.
-  double monoToPsi[MAXNB - 1][MAXNB - 1];
 };
 
 struct Params {

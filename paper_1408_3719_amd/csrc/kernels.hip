@@ -434,6 +434,59 @@ struct RefMeans {
   static constexpr Arr m = make();
 };
 
+// The reconstruction's basis: the monomials x^a y^b (1 <= a + b <= M, by
+// degree, then b) minus their means on the reference triangle. For it, at
+// compile time: the oscillation-indicator matrix (sum over all derivatives of
+// orders 1..M of the integral of their products over the reference triangle,
+// eq. eqn.sigma) and the values at the nodal lattice (i/M, j/M), i + j <= M,
+// ordered by j then i. Integrals of x^p y^q over the triangle: p! q! / (p+q+2)!.
+template <int M>
+struct MonoBasis {
+  static constexpr int nb = (M + 1) * (M + 2) / 2, nu = nb - 1;
+  struct Coef {
+    double sig[nu][nu];
+    double node[nb][nu];
+  };
+  static constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+  static constexpr double falling(int n, int k) { return k == 0 ? 1.0 : n * falling(n - 1, k - 1); }
+  static constexpr double ipow(double x, int n) { return n == 0 ? 1.0 : x * ipow(x, n - 1); }
+  static constexpr Coef make() {
+    Coef c{};
+    int ea[nb] = {}, eb[nb] = {};
+    int k = 0;
+    for (int d = 0; d <= M; ++d)
+      for (int b = 0; b <= d; ++b) {
+        ea[k] = d - b;
+        eb[k] = b;
+        ++k;
+      }
+    for (int l = 1; l < nb; ++l)
+      for (int m = 1; m < nb; ++m) {
+        double s = 0.0;
+        for (int ord = 1; ord <= M; ++ord)
+          for (int be = 0; be <= ord; ++be) {
+            const int al = ord - be;
+            if (ea[l] < al || eb[l] < be || ea[m] < al || eb[m] < be) continue;
+            const int p = ea[l] + ea[m] - 2 * al, q = eb[l] + eb[m] - 2 * be;
+            s += falling(ea[l], al) * falling(eb[l], be) * falling(ea[m], al) * falling(eb[m], be) *
+                 fact(p) * fact(q) / fact(p + q + 2);
+          }
+        c.sig[l - 1][m - 1] = s;
+      }
+    int n = 0;
+    for (int j = 0; j <= M; ++j)
+      for (int i = 0; i + j <= M; ++i) {
+        const double x = double(i) / M, y = double(j) / M;
+        for (int l = 1; l < nb; ++l)
+          c.node[n][l - 1] = ipow(x, ea[l]) * ipow(y, eb[l]) -
+                             2.0 * fact(ea[l]) * fact(eb[l]) / fact(ea[l] + eb[l] + 2);
+        ++n;
+      }
+    return c;
+  }
+  static constexpr Coef c = make();
+};
+
 // Means of the monomials x^a y^b (a + b <= M) over a triangle with vertices
 // (x[k], y[k]), by a rule exact to degree M with its points written out: the
 // centroid (M=1), the edge midpoints (M=2), and the vertices, edge midpoints
@@ -594,17 +647,9 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
           u[k][v] = t * rinv;
         }
       }
-      // coefficients of psi_1 .. psi_nu
-      double w[nu][4];
-#pragma unroll
-      for (int l = 0; l < nu; ++l)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          double t = 0.0;
-#pragma unroll
-          for (int k = 0; k < nu; ++k) t += tb->monoToPsi[l][k] * u[k][v];
-          w[l][v] = t;
-        }
+      // oscillation indicator (eq. eqn.sigma), summed over the variables;
+      // it depends only on the polynomial, so it is taken in the shifted
+      // monomials with their own (constant) indicator matrix
       double sigma = 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
@@ -612,8 +657,8 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
         for (int l = 0; l < nu; ++l) {
           double t = 0.0;
 #pragma unroll
-          for (int m = 0; m < nu; ++m) t += tb->Sigma[l + 1][m + 1] * w[m][v];
-          sigma += w[l][v] * t;
+          for (int m = 0; m < nu; ++m) t += MonoBasis<M>::c.sig[l][m] * u[m][v];
+          sigma += u[l][v] * t;
         }
       const double x = sigma + P.eps;
       const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
@@ -621,7 +666,7 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
 #pragma unroll
       for (int l = 0; l < nu; ++l)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) W[l][v] = om * w[l][v];
+        for (int v = 0; v < 4; ++v) W[l][v] = om * u[l][v];
     }
     double dt = 0.0;
     if (sl == 7) {
@@ -650,9 +695,9 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (((m * 4 + v) & 7) != sl) continue;
-        double t = tb->psiNodes[m][0] * Qi[v];
+        double t = Qi[v];
 #pragma unroll
-        for (int l = 0; l < nu; ++l) t += tb->psiNodes[m][l + 1] * (W[l][v] * iw);
+        for (int l = 0; l < nu; ++l) t += MonoBasis<M>::c.node[m][l] * (W[l][v] * iw);
         wo[m * 4 + v] = t;
       }
     if (sl == 7) {

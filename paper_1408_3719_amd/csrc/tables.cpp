@@ -204,16 +204,6 @@ void build_tables(int M, Tables& T) {
     }
   for (int l = 0; l < nb; ++l)
     for (int k = 0; k < nb; ++k) T.psiC[l][k] = psi[l].c[T.monoA[k]][T.monoB[k]];
-  {
-    // u = C^T w with C[l][k] = psiC[l+1][k+1]: monoToPsi = (C^T)^-1
-    const int nu = nb - 1;
-    std::vector<double> Ct(nu * nu);
-    for (int k = 0; k < nu; ++k)
-      for (int l = 0; l < nu; ++l) Ct[k * nu + l] = T.psiC[l + 1][k + 1];
-    std::vector<double> Ci = invert(Ct, nu);
-    for (int l = 0; l < nu; ++l)
-      for (int k = 0; k < nu; ++k) T.monoToPsi[l][k] = Ci[l * nu + k];
-  }
   for (int l = 0; l < nb; ++l)
     for (int m = 0; m < nb; ++m) {
       double s = 0.0;

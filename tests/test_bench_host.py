@@ -20,7 +20,7 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_operation_counts():
-    assert bench.recon_flops(2) == 30737
+    assert bench.recon_flops(2) == 29289
     assert bench.recon_flops(1) < bench.recon_flops(2) < bench.recon_flops(3)
     assert bench.predict_flops(1) < bench.predict_flops(2) < bench.predict_flops(3)
     assert bench.patch_bytes(2) == 760
