@@ -49,9 +49,9 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
 # traffic is reported null.
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
-    "source_sha256": "3f2369ddbb6500071279c1c36e8572b728d19e0c1eece59ae49533da1a2f889f",
-    "k_reconstruct": {0: 1280, 4: 1235, 8: 1235, 16: 1182, 32: 1230},
-    "k_predict": {0: 1501, 4: 1501, 8: 1502, 16: 1500, 32: 1499},
+    "source_sha256": "43cb23c3e120a223f65170a4d84e67413923c6221dbffcdeed2ed7324d6c14c6",
+    "k_reconstruct": {0: 1020, 4: 982, 8: 997, 16: 964, 32: 980},
+    "k_predict": {0: 1497, 4: 1498, 8: 1498, 16: 1498, 32: 1497},
 }
 
 

@@ -408,10 +408,34 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A double from another lane of the same row of 16 lanes, moved by a DPP
+// pattern (no LDS round trip).
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum over the 8 lanes of an aligned group, the same in every lane: pairs,
+// then quads, then the two quads of the group; every step adds two equal
+// partial sums, so all lanes end bit-identical and both forms give the same
+// bits. The DPP form (lane moves inside the VALU, no LDS round trip) needs a
+// few more registers, which at M=2 would take the reconstruction past 256
+// VGPRs (one wave per SIMD instead of two): it is used where that does not
+// matter.
+template <bool DPP>
 __device__ inline double group8_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
+  if constexpr (DPP) {
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);   // row_half_mirror: lane i <-> 7 - i within 8
+  } else {
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+  }
   return v;
 }
 
@@ -687,8 +711,8 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
 #pragma unroll
     for (int l = 0; l < nu; ++l)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) W[l][v] = group8_sum(W[l][v]);
-    const double iw = 1.0 / group8_sum(om);
+      for (int v = 0; v < 4; ++v) W[l][v] = group8_sum<(M == 3)>(W[l][v]);
+    const double iw = 1.0 / group8_sum<(M == 3)>(om);
     double* wo = d.wnod + size_t(i) * WS;
 #pragma unroll
     for (int m = 0; m < nb; ++m)
