@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X, published
 PEAK_HBM_GBS = 8000.0              # MI355X HBM3E, published
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in ("kernels.hip", "basis.h")]
 
 # HBM bytes per unit of work (element reconstruction, element predictor) for
 # each persistent-grid setting of the list-driven kernels (workgroups per CU;
@@ -45,14 +45,24 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1408_3719_amd", "csrc", "kernels.hip")
 # the profiled LTS pass's launches on the 80k vortex mesh at M=2, scaled by
 # what the same counters read for a plain 256 MiB copy, divided by the units
 # those launches processed. Valid only for the kernel code they were taken on
-# (sha256 of kernels.hip with comments and whitespace removed); otherwise
-# traffic is reported null.
+# (sha256 of kernels.hip and basis.h with comments and whitespace removed);
+# otherwise traffic is reported null.
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
-    "source_sha256": "43cb23c3e120a223f65170a4d84e67413923c6221dbffcdeed2ed7324d6c14c6",
-    "k_reconstruct": {0: 1020, 4: 982, 8: 997, 16: 964, 32: 980},
-    "k_predict": {0: 1497, 4: 1498, 8: 1498, 16: 1498, 32: 1497},
+    "source_sha256": "af222f0b42f0bef0bc488d56df19b0b22216c7f92e8bd81106a6dd35823bd528",
+    "k_reconstruct": {0: 1454, 4: 1405, 8: 1386, 16: 1325, 32: 1397},
+    "k_predict": {0: 1499, 4: 1501, 8: 1499, 16: 1499, 32: 1498},
 }
+
+
+def kernel_source_sha() -> str:
+    """sha256 of the step kernels' sources with comments and whitespace removed."""
+    text = ""
+    for path in KERNEL_SOURCES:
+        with open(path) as f:
+            text += f.read() + "\n"
+    code = re.sub(r"//[^\n]*", " ", re.sub(r"/\*.*?\*/", " ", text, flags=re.S))
+    return hashlib.sha256(" ".join(code.split()).encode()).hexdigest()
 
 
 # ---------------------------------------------------------------------------
@@ -422,9 +432,7 @@ def main():
         "predict": p1["predictor_evals"] - p0["predictor_evals"],
         "patch": p1["patches"] - p0["patches"],
     }
-    with open(KERNEL_SOURCE) as f:
-        code = re.sub(r"//[^\n]*", " ", re.sub(r"/\*.*?\*/", " ", f.read(), flags=re.S))
-    source_sha = hashlib.sha256(" ".join(code.split()).encode()).hexdigest()
+    source_sha = kernel_source_sha()
 
     def traffic(kernel, units_per_launch):
         per = MEASURED_TRAFFIC.get(kernel, {}).get(tune["list_wg_per_cu"] if tune else 0)

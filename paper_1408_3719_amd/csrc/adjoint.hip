@@ -36,6 +36,7 @@
 #include <hip/hip_runtime.h>
 
 #include "aderweno.h"
+#include "basis.h"
 #include "common.h"
 
 namespace aw {
@@ -239,18 +240,6 @@ __device__ inline void hll_vjp(const double ql[4], const double qr[4], const dou
     hll_speed_vjp(qr, N, nxy, gam, 1.0, srb, qrb);
 }
 
-// Lagrange basis in time, l_q(tau)
-template <int M>
-__device__ inline void time_basis(const Tables* tb, double tau, double l[M + 1]) {
-#pragma unroll
-  for (int q = 0; q <= M; ++q) {
-    double s = tb->lag[q][M];
-#pragma unroll
-    for (int k = M - 1; k >= 0; --k) s = s * tau + tb->lag[q][k];
-    l[q] = s;
-  }
-}
-
 __device__ inline double group8_sum(double v) {
   v += __shfl_xor(v, 1);
   v += __shfl_xor(v, 2);
@@ -259,12 +248,12 @@ __device__ inline double group8_sum(double v) {
 }
 
 // Row of the least-squares system for stencil element j seen from element i:
-// the means of psi_1 .. psi_nu over T_j mapped into the reference frame of T_i
-// (vertices Xi, inverse edge matrix through e1, e2, idet).
+// the means over T_j, mapped into the reference frame of T_i (vertices Xi,
+// inverse edge matrix through e1, e2, idet), of the monomials shifted by their
+// reference means, the basis the forward reconstruction solves in.
 template <int M>
-__device__ inline void ls_row(const Tables* tb, const double* Xj, const double Xi[6], double e1x,
-                              double e1y, double e2x, double e2y, double idet,
-                              double a[AZ<M>::nu]) {
+__device__ inline void ls_row(const double* Xj, const double Xi[6], double e1x, double e1y,
+                              double e2x, double e2y, double idet, double a[AZ<M>::nu]) {
   constexpr int nb = AZ<M>::nb, nu = AZ<M>::nu;
   double rx[3], ry[3];
 #pragma unroll
@@ -274,36 +263,9 @@ __device__ inline void ls_row(const Tables* tb, const double* Xj, const double X
     ry[k] = (e1x * dy - e1y * dx) * idet;
   }
   double mm[nb];
+  monomial_means<M>(rx, ry, mm);
 #pragma unroll
-  for (int k = 0; k < nb; ++k) mm[k] = 0.0;
-  for (int r = 0; r < tb->nrq; ++r) {
-    const double px = tb->rqb[r][0] * rx[0] + tb->rqb[r][1] * rx[1] + tb->rqb[r][2] * rx[2];
-    const double py = tb->rqb[r][0] * ry[0] + tb->rqb[r][1] * ry[1] + tb->rqb[r][2] * ry[2];
-    const double w = tb->rqw[r];
-    double xp[M + 1], yp[M + 1];
-    xp[0] = 1.0;
-    yp[0] = 1.0;
-#pragma unroll
-    for (int k = 1; k <= M; ++k) {
-      xp[k] = xp[k - 1] * px;
-      yp[k] = yp[k - 1] * py;
-    }
-    int k = 0;
-#pragma unroll
-    for (int dg = 0; dg <= M; ++dg)
-#pragma unroll
-      for (int b = 0; b <= dg; ++b) {
-        mm[k] += w * xp[dg - b] * yp[b];
-        ++k;
-      }
-  }
-#pragma unroll
-  for (int l = 0; l < nu; ++l) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < nb; ++k) s += tb->psiC[l + 1][k] * mm[k];
-    a[l] = s;
-  }
+  for (int l = 0; l < nu; ++l) a[l] = mm[l + 1] - RefMeans<M>::m[l + 1];
 }
 
 // The context's averages as [4][NE].
@@ -411,7 +373,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
       for (int c = 1; c < ne; ++c) {
         const double* rj = d.rec + size_t(sidx[c * NE]) * S::RS;
         double a[nu], b[4];
-        ls_row<M>(tb, rj + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
+        ls_row<M>(rj + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
         for (int v = 0; v < 4; ++v) b[v] = w.q[size_t(v) * NE + sidx[c * NE]] - Qi[v];
 #pragma unroll
@@ -452,7 +414,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         for (int l = 0; l < nu; ++l) {
           double t = 0.0;
 #pragma unroll
-          for (int m = 0; m < nu; ++m) t += tb->Sigma[l + 1][m + 1] * ws[m][v];
+          for (int m = 0; m < nu; ++m) t += MonoBasis<M>::c.sig[l][m] * ws[m][v];
           sig += ws[l][v] * t;
         }
       const double x = sig + P.eps;
@@ -484,9 +446,9 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           if (((m * 4 + v) & 7) != sl) continue;
-          double t = tb->psiNodes[m][0] * Qi[v];
+          double t = Qi[v];
 #pragma unroll
-          for (int l = 0; l < nu; ++l) t += tb->psiNodes[m][l + 1] * W[l][v];
+          for (int l = 0; l < nu; ++l) t += MonoBasis<M>::c.node[m][l] * W[l][v];
           wo[m * 4 + v] = t;
         }
       continue;
@@ -505,9 +467,9 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double b = wbi[m * 4 + v];
-        q0b[v] += tb->psiNodes[m][0] * b;
+        q0b[v] += b;
 #pragma unroll
-        for (int l = 0; l < nu; ++l) Wb[l][v] += tb->psiNodes[m][l + 1] * b;
+        for (int l = 0; l < nu; ++l) Wb[l][v] += MonoBasis<M>::c.node[m][l] * b;
       }
     // row c of this lane's stencil: slot ((i * ne + c) * 8 + sl); row 0 holds
     // the element's own terms
@@ -533,7 +495,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
       for (int v = 0; v < 4; ++v) {
         double t = 0.0;
 #pragma unroll
-        for (int m = 0; m < nu; ++m) t += (tb->Sigma[l + 1][m + 1] + tb->Sigma[m + 1][l + 1]) * ws[m][v];
+        for (int m = 0; m < nu; ++m) t += (MonoBasis<M>::c.sig[l][m] + MonoBasis<M>::c.sig[m][l]) * ws[m][v];
         u[l][v] = (om / Ssum) * Wb[l][v] + sigb * t;
       }
 #pragma unroll
@@ -560,7 +522,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
     for (int c = 1; c < ne; ++c) {
       const int j = sidx[c * NE];
       double a[nu];
-      ls_row<M>(tb, d.rec + size_t(j) * S::RS + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
+      ls_row<M>(d.rec + size_t(j) * S::RS + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double t = 0.0;
@@ -740,7 +702,7 @@ __global__ void __launch_bounds__(TPB) k_adj_patch(Dev d, const Tables* __restri
         // corner ticks 0, 0, 1, 1 of a one-tick step: tau at the point
         const double tk = c * tt + (1.0 - c) * tt;
         double l[T];
-        time_basis<M>(tb, tk, l);
+        time_basis<M>(tk, l);
         double ql[4], qr[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
