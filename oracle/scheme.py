@@ -648,6 +648,28 @@ class Solver:
                 act.append(i)
         return np.array(act, np.int64)
 
+    def move_nodes(self, moved, newtick):
+        """Node solver NS_cs (eqs. eqn.dtau, NodesVel, eqnNScs, eqn.NScs.weights,
+        eqn.newVertex): each moved node k goes from its tick to newtick[k] with
+        the mass-weighted time average of its ring elements' predicted vertex
+        velocities; masses rho_j |T_j| from the element-stored state (R5).
+        Returns the new node positions (the others unchanged)."""
+        st, topo, M = self.st, self.topo, self.cfg.M
+        Xnew = st.X.copy()
+        for k in moved:
+            ring = topo.ring[k]
+            j = np.array([r[0] for r in ring])
+            lv = np.array([r[1] for r in ring])
+            if (st.s[j] <= 0).any():
+                raise AssertionError("node ring element without a valid predictor")
+            tau0 = (st.nk[k] - st.n[j]) / st.s[j]
+            tau1 = (newtick[k] - st.n[j]) / st.s[j]
+            mu = st.Q[j, 0] * st.A[j]
+            V = node_velocity(M, st.vvel[j, lv], tau0, tau1, mu)
+            V = wall_project(V, self.wall_n[k], self.wall_pin[k])
+            Xnew[k] = st.X[k] + (newtick[k] - st.nk[k]) * st.delta * V
+        return Xnew
+
     def cycle(self):
         st, topo, cfg, M = self.st, self.topo, self.cfg, self.cfg.M
         act = self.active_set()
@@ -663,20 +685,7 @@ class Solver:
                         raise AssertionError("co-active elements sharing a node disagree on its time")
                     newtick[k] = fut[i]
         moved = np.nonzero(newtick != st.nk)[0]
-        # node motion (eqs. eqn.dtau, NodesVel, eqnNScs, eqn.newVertex)
-        Xnew = st.X.copy()
-        for k in moved:
-            ring = topo.ring[k]
-            j = np.array([r[0] for r in ring])
-            lv = np.array([r[1] for r in ring])
-            if (st.s[j] <= 0).any():
-                raise AssertionError("node ring element without a valid predictor")
-            tau0 = (st.nk[k] - st.n[j]) / st.s[j]
-            tau1 = (newtick[k] - st.n[j]) / st.s[j]
-            mu = st.Q[j, 0] * st.A[j]
-            V = node_velocity(M, st.vvel[j, lv], tau0, tau1, mu)
-            V = wall_project(V, self.wall_n[k], self.wall_pin[k])
-            Xnew[k] = st.X[k] + (newtick[k] - st.nk[k]) * st.delta * V
+        Xnew = self.move_nodes(moved, newtick)
         # swept patches
         en = topo.edge_nodes
         is_moved = newtick != st.nk

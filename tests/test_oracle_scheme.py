@@ -167,9 +167,13 @@ def test_sod_against_exact_solution():
     assert s2.st.max_gcl < 1e-13
 
 
-@pytest.mark.slow
-def test_vortex_convergence_order():
-    """Smooth isentropic vortex (paper Sec. 3.1): L2(rho) order close to M+1."""
+@pytest.mark.parametrize("M,bar", [(1, 1.6), (2, 2.3),
+                                   pytest.param(3, 3.0, marks=pytest.mark.slow)])
+def test_vortex_convergence_order(M, bar):
+    """Smooth isentropic vortex (paper Sec. 3.1), Lagrangian mesh, 3 levels:
+    the L2 error of the reconstructed density against the exact solution falls
+    with order close to M + 1 from ~1k to ~4k triangles (design order; M = 1
+    and 2 run by default in ~45 s, M = 3 takes ~100 s and runs with RUN_SLOW=1)."""
     from oracle import tables as tb
     from oracle.scheme import affine_map
     from workloads import vortex_primitive
@@ -177,18 +181,18 @@ def test_vortex_convergence_order():
     hs = []
     for n in (1000, 4000):
         mesh, Q0 = vortex_case(n, seed=1)
-        s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=2, levels=3))
+        s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=M, levels=3))
         s.run(0.2)
-        xi, eta, w = tb.duffy_rule(4)
+        xi, eta, w = tb.duffy_rule(M + 2)
         x = affine_map(s.st.Xe, xi, eta)
         ex = vortex_primitive(x[..., 0] - 0.2, x[..., 1] - 0.2)[..., 0]
-        psi_nodes = tb.eval_phi(2, xi, eta)          # nodal reconstruction
+        psi_nodes = tb.eval_phi(M, xi, eta)          # nodal reconstruction
         wh = np.einsum("qm,em->eq", psi_nodes, s.st.wnod[..., 0])
         e2 = (((wh - ex) ** 2) * w[None, :]).sum(axis=1) * 2 * s.st.A
         errs.append(np.sqrt(e2.sum()))
         hs.append(np.sqrt(s.st.A.mean()))
     order = np.log(errs[0] / errs[1]) / np.log(hs[0] / hs[1])
-    assert order > 2.3, (errs, order)
+    assert order > bar, (errs, order)
 
 
 def test_free_steps_respect_cfl_and_save_updates():
