@@ -1,24 +1,26 @@
 """Benchmark: element updates per second of the ALE ADER-WENO scheme with
 local time stepping on one MI355X.
 
-Workload: smooth isentropic vortex (strength 5, gamma 1.4) on [0,10]^2, seeded
-4:1 graded mesh of ~80k triangles, transmissive boundaries, mesh moving with
-the fluid, WENO M=2, LTS with 3 levels, FP64.  One step = one LTS macro step
-(4 ticks: every element reaches the common time again).  value = element
-updates / wall time of the timed macro steps (state resident in HBM).
+Default workload (the metric's configuration, its largest single mesh): the
+cylindrical explosion EP1 on the unit disk, seeded 8:1 radially graded mesh of
+~400k triangles, transmissive boundary, mesh moving with the fluid, WENO M=2,
+LTS with 4 dyadic levels against GTS on the same mesh, FP64.  One step = one
+LTS macro step (every element reaches the common time again).  value =
+element updates / wall time of the timed macro steps (state resident in HBM).
 
 Also reported: GTS and free local steps (every element at its own CFL step)
-on the same mesh over the same physical interval, the time-to-solution ratios, a per-kernel breakdown from HIP events recorded on
-the solver's stream, the roofline of the dominant kernel, and the CPU oracle
-timed on a bounded sample.
+over the same physical interval and the time-to-solution ratios; the
+per-kernel breakdown from HIP events recorded on the solver's stream; the
+roofline of the dominant kernel and the HBM rate of the flux, update, node
+and scheduling kernels; the CPU oracle timed on a bounded sample of the same
+recipe; one adjoint step against one forward step of the adjoint workload.
 
-Other workloads (not the headline line): --workload explosion (EP1 on the unit
-disk, 8:1 radial grading, 400k triangles, M=2, 4 levels), --workload sod
-(RP1 shock tube, 2k triangles, M=1, one level = GTS), --workload batched
-(256 independent instances in the same launches) or --workload adjoint
-(gradient through 100 global steps on a fixed 50k-triangle mesh, against the run).
+Other workloads (separate lines): --workload vortex (isentropic vortex, 80k
+triangles, M=2, 3 levels), sod (RP1 shock tube, 2k triangles, M=1, GTS),
+batched (256 independent instances in the same launches) or adjoint
+(gradient through 100 steps with checkpoints, against the run).
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload vortex]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload explosion]
                        [--n-elems N] [--M M] [--levels L]
 """
 from __future__ import annotations
@@ -49,6 +51,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in 
 # otherwise traffic is reported null.
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
+    "workload": "vortex",
     "source_sha256": "af222f0b42f0bef0bc488d56df19b0b22216c7f92e8bd81106a6dd35823bd528",
     "k_reconstruct": {0: 1454, 4: 1405, 8: 1386, 16: 1325, 32: 1397},
     "k_predict": {0: 1499, 4: 1501, 8: 1499, 16: 1499, 32: 1498},
@@ -109,33 +112,6 @@ def patch_bytes(M: int) -> int:
 
 
 # ---------------------------------------------------------------------------
-def cpu_baseline(n_elems: int, M: int, levels: int, macro_steps: int):
-    """Time the oracle on a bounded sample in a single-threaded subprocess."""
-    code = f"""
-import json, os, sys, time
-sys.path.insert(0, {ROOT!r})
-from oracle.scheme import Config, Solver
-from workloads import vortex_case
-mesh, Q0 = vortex_case({n_elems}, seed=1)
-s = Solver(mesh.nodes, mesh.tris, Q0, Config(M={M}, levels={levels}), bedges=mesh.bedges)
-t = time.perf_counter()
-s.run(1.0, max_macro_steps={macro_steps})
-dt = time.perf_counter() - t
-print(json.dumps(dict(updates=s.st.updates, seconds=dt, n_elems=mesh.n_elems)))
-"""
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
-                         timeout=600)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr[-2000:])
-    r = json.loads(out.stdout.strip().splitlines()[-1])
-    return dict(value=r["updates"] / r["seconds"], unit="element-updates/s", cores=1,
-                kind="oracle",
-                sample=f"vortex recipe at {r['n_elems']} triangles, M={M}, {levels} levels, "
-                       f"{macro_steps} macro steps ({r['updates']} element updates in "
-                       f"{r['seconds']:.1f} s, one host thread)")
-
-
 def bench_adjoint(a):
     """Gradient through a run of global steps on a fixed mesh: EP1 explosion on
     a 50k-triangle 8:1 graded disk, M=2, Rusanov flux, 100 steps of a fixed dt
@@ -309,25 +285,142 @@ def bench_batched(a):
     print(json.dumps(line))
 
 
+METRIC = "element-updates/s at 1e-10 rel err vs FP64 oracle, LTS vs GTS; adjoint/forward ratio"
+
+# Algorithmic work per unit of the hot path (what the method must compute or
+# move, independent of this implementation): reconstruction and predictor
+# flops per element update, compulsory HBM bytes per space-time patch, per
+# active-element update, per moved node and per scheduling candidate.
+UNIT_WORK = {
+    "recon_flops": {1: 5_000, 2: 25_000, 3: 120_000},
+    "predict_flops": {1: 3_600, 2: 27_000, 3: 120_000},
+    "patch_bytes": {1: 464, 2: 784, 3: 1232},
+    "update_bytes": {1: 364, 2: 364, 3: 364},
+    "node_bytes": {1: 450, 2: 550, 3: 650},
+    "sched_bytes": {1: 180, 2: 180, 3: 200},
+}
+
+
+def rate_entry(per_unit: float, units: float, total_ms: float, launches: int, peak: float, scale: float):
+    """Algorithmic rate of one kernel: per_unit x (units / launches) per
+    launch, divided by the average launch duration (total_ms / launches), in
+    units of `scale` per second, and its fraction of `peak`."""
+    avg_s = total_ms / max(launches, 1) * 1e-3
+    upl = units / max(launches, 1)
+    achieved = per_unit * upl / avg_s / scale if avg_s > 0 else 0.0
+    return {"achieved": achieved, "peak": peak, "frac": achieved / peak, "units_per_launch": upl,
+            "launches": launches, "avg_launch_us": avg_s * 1e6}
+
+
+def host_cpu():
+    """Model name and logical CPU count of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = None
+    return {"model": model, "logical_cpus": os.cpu_count(), "cpus_available": avail}
+
+
+def cpu_baseline_case(workload: str, n_elems: int, M: int, levels: int, macro_steps: int, t_end: float):
+    """Time the oracle on a bounded sample of the workload's recipe in a
+    single-threaded subprocess (one host core)."""
+    make = {"explosion": "explosion_case({n}, seed=7)", "vortex": "vortex_case({n}, seed=1)",
+            "sod": "sod_case({n}, seed=1408)"}[workload].format(n=n_elems)
+    code = f"""
+import json, os, sys, time
+sys.path.insert(0, {ROOT!r})
+from oracle.scheme import Config, Solver
+from workloads import explosion_case, sod_case, vortex_case
+mesh, Q0 = {make}
+s = Solver(mesh.nodes, mesh.tris, Q0, Config(M={M}, levels={levels}), bedges=mesh.bedges)
+t = time.perf_counter()
+s.run({t_end}, max_macro_steps={macro_steps})
+dt = time.perf_counter() - t
+print(json.dumps(dict(updates=s.st.updates, seconds=dt, n_elems=mesh.n_elems)))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    cpu = host_cpu()
+    return dict(value=r["updates"] / r["seconds"], unit="element-updates/s", cores=1, kind="oracle",
+                sample=f"{workload} recipe at {r['n_elems']} triangles, M={M}, {levels} levels, first "
+                       f"{macro_steps} macro steps ({r['updates']} element updates in {r['seconds']:.1f} s, "
+                       f"one host thread)",
+                host_cpu_model=cpu["model"], host_logical_cpus=cpu["logical_cpus"],
+                host_cpus_available=cpu["cpus_available"])
+
+
+def adjoint_step_ratio(n_elems: int = 50_000, M: int = 2, reps: int = 20):
+    """One adjoint step against one forward step from the same state, on the
+    adjoint workload (explosion recipe, fixed mesh, dt = half the smallest CFL
+    step): the per-step adjoint/forward time ratio."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3719_amd import Config, Solver
+    from workloads import explosion_case
+    mesh, Q0 = explosion_case(n_elems, seed=7)
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=1, mesh_velocity="eulerian"))
+    dt = 0.5 * float(s.dump("DTCFL").min())
+    qb = torch.tensor(np.random.default_rng(0).standard_normal((4, mesh.n_elems)), device="cuda")
+    sync = torch.cuda.synchronize
+    for _ in range(3):
+        s.adjoint_gts_step(dt, qb)
+        s.upload_state(Q0, 0.0)
+        s.step_gts(dt, 1)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.adjoint_gts_step(dt, qb)
+    sync()
+    ms_adj = (time.perf_counter() - t0) / reps * 1e3
+    ms_fwd = 0.0
+    for _ in range(reps):
+        s.upload_state(Q0, 0.0)
+        sync()
+        t0 = time.perf_counter()
+        s.step_gts(dt, 1)
+        sync()
+        ms_fwd += (time.perf_counter() - t0) / reps * 1e3
+    return {"value": ms_adj / ms_fwd, "adjoint_ms": ms_adj, "forward_ms": ms_fwd,
+            "workload": f"one global step on the {mesh.n_elems}-triangle explosion, fixed mesh, M={M}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["vortex", "explosion", "sod", "batched", "adjoint"],
-                    default="vortex")
+    ap.add_argument("--workload", choices=["explosion", "vortex", "sod", "batched", "adjoint"],
+                    default="explosion")
     ap.add_argument("--instances", type=int, default=256, help="batched workload: instances")
     ap.add_argument("--n-elems", type=int, default=None)
     ap.add_argument("--M", type=int, default=None)
     ap.add_argument("--levels", type=int, default=None)
+    ap.add_argument("--step-fraction", type=float, default=None,
+                    help="nominal finest dyadic step / smallest CFL step (library default if unset)")
     ap.add_argument("--flux", choices=["rusanov", "osher", "hll"], default="rusanov")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: pick launch settings with the library's autotuner before timing")
     ap.add_argument("--free", type=int, default=1,
                     help="1: also run free local steps (levels = 0) over the timed interval")
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="1: also time one adjoint step against one forward step (adjoint workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-elems", type=int, default=5000)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-elems", type=int, default=None)
+    ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--traffic-sweep", action="store_true",
                     help="repeat the profiled pass for every workgroups-per-CU setting (counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -343,18 +436,22 @@ def main():
     if a.workload == "adjoint":
         return bench_adjoint(a)
 
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
 
     from paper_1408_3719_amd import Config, Solver
     from workloads import explosion_case, sod_case, vortex_case
 
-    # workload defaults: mesh size, order, levels, target time
-    dflt = {"vortex": (80_000, 2, 3, 1.0), "explosion": (400_000, 2, 4, 0.25),
-            "sod": (2_000, 1, 1, 0.2)}[a.workload]
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    # workload defaults: mesh size, order, levels, target time, CPU sample (size, macro steps)
+    dflt = {"explosion": (400_000, 2, 4, 0.25, (4000, 6)), "vortex": (80_000, 2, 3, 1.0, (5000, 8)),
+            "sod": (2_000, 1, 1, 0.2, (2000, 40))}[a.workload]
     a.n_elems = a.n_elems or dflt[0]
     a.M = a.M or dflt[1]
     a.levels = a.levels or dflt[2]
+    t_end = dflt[3]
     if a.workload == "vortex":
         mesh, Q0 = vortex_case(a.n_elems, seed=1)
         desc = "isentropic vortex, {}-triangle 4:1 graded mesh"
@@ -364,11 +461,13 @@ def main():
     else:
         mesh, Q0 = sod_case(a.n_elems, seed=1408)
         desc = "RP1 shock tube, {}-triangle strip"
-    cfg = Config(M=a.M, levels=a.levels, flux=a.flux)
-    t_end = dflt[3]
+    note(f"{a.workload}: {mesh.n_elems} triangles")
+    extra = {} if a.step_fraction is None else {"lts_step_fraction": a.step_fraction}
+    cfg = Config(M=a.M, levels=a.levels, flux=a.flux, **extra)
     s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, cfg)
     sync = torch.cuda.synchronize
     tune = s.autotune(2) if a.autotune else None      # state restored: not part of the run
+    note(f"autotune {tune}")
 
     # ---- LTS: warm-up then the timed macro steps --------------------------------
     s.step_lts(t_end, a.warmup)
@@ -382,10 +481,16 @@ def main():
     lts_updates = st1["element_updates"] - st0["element_updates"]
     T_a, T_b = st0["t"], st1["t"]
     value = lts_updates / t_lts
+    lts = {"updates": lts_updates, "seconds": t_lts, "physical_interval": [T_a, T_b]}
+    for k in ("cycles", "extra_cycles", "long_macro_steps", "cfl_overshoots", "macro_steps"):
+        lts[k] = st1[k] - st0[k]
+    lts["max_gcl_residual"] = st1["max_gcl_residual"]
+    note(f"LTS {value / 1e6:.1f} M updates/s over [{T_a:.4g}, {T_b:.4g}]")
 
     # ---- GTS over the same physical interval [T_a, T_b] ---------------------------
     s.upload_state(Q0, 0.0)
     s.step_gts(T_a)
+    s.step_gts(T_a)                    # graph of one level already captured
     g0 = s.stats()
     sync()
     t0 = time.perf_counter()
@@ -394,12 +499,12 @@ def main():
     t_gts = time.perf_counter() - t0
     g1 = s.stats()
     gts_updates = g1["element_updates"] - g0["element_updates"]
+    note(f"GTS {gts_updates / t_gts / 1e6:.1f} M updates/s")
 
     # ---- free local steps over the same interval (each element at its CFL step) --
     free = None
     if a.free:
-        f = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
-                   Config(M=a.M, levels=0, flux=a.flux))
+        f = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=a.M, levels=0, flux=a.flux))
         if tune:
             f.set_tune(sched_chunk=tune["sched_chunk"], list_wg_per_cu=tune["list_wg_per_cu"])
         f.step_lts(T_a)
@@ -417,6 +522,7 @@ def main():
                 "updates_over_lts": fu / max(lts_updates, 1),
                 "time_over_lts": t_free / t_lts}
         del f
+        note(f"free steps {fu / t_free / 1e6:.1f} M updates/s")
 
     # ---- profiled LTS pass: per-kernel times from HIP events ----------------------
     s.upload_state(Q0, 0.0)
@@ -431,42 +537,41 @@ def main():
         "recon": p1["element_updates"] - p0["element_updates"],
         "predict": p1["predictor_evals"] - p0["predictor_evals"],
         "patch": p1["patches"] - p0["patches"],
+        "update": p1["element_updates"] - p0["element_updates"],
+        "node": p1["node_moves"] - p0["node_moves"],
     }
+    units["sched"] = mesh.n_elems * kt["sched"][1]         # every element is a candidate
     source_sha = kernel_source_sha()
+    kname = {"recon": "k_reconstruct", "predict": "k_predict", "patch": "k_patch",
+             "sched": "k_sched", "node": "k_node", "update": "k_update"}
 
     def traffic(kernel, units_per_launch):
         per = MEASURED_TRAFFIC.get(kernel, {}).get(tune["list_wg_per_cu"] if tune else 0)
         if (per is None or MEASURED_TRAFFIC["source_sha256"] != source_sha or a.M != 2
-                or a.workload != "vortex" or a.flux != "rusanov"):
+                or MEASURED_TRAFFIC.get("workload") != a.workload or a.flux != "rusanov"):
             return None
         return per * units_per_launch
 
-    kname = {"recon": "k_reconstruct", "predict": "k_predict", "patch": "k_patch",
-             "sched": "k_sched", "node": "k_node", "update": "k_update"}
-    dom = max(kt, key=lambda k: kt[k][0])
-    ms, launches = kt[dom]
-    avg_s = ms / max(launches, 1) * 1e-3
-    if dom in ("recon", "predict"):
-        per = recon_flops(a.M) if dom == "recon" else predict_flops(a.M)
-        work = per * units[dom] / max(launches, 1)
-        achieved = work / avg_s / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_VECTOR_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / PEAK_FP64_VECTOR_TFLOPS,
-                    traffic=traffic(kname[dom], units[dom] / max(launches, 1)), kernel=kname[dom],
-                    flops_per_unit=per, units_per_launch=units[dom] / max(launches, 1),
-                    launches=launches, avg_launch_us=avg_s * 1e6)
-    elif dom != "patch":
-        # launch- or latency-bound case (small meshes): no algorithmic roofline
-        roof = dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
-                    kernel=kname.get(dom, dom), avg_launch_us=avg_s * 1e6)
-    else:
-        per = patch_bytes(a.M)
-        work = per * units.get(dom, 0) / max(launches, 1)
-        achieved = work / avg_s / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=achieved / PEAK_HBM_GBS, traffic=None, kernel=kname.get(dom, dom),
-                    bytes_per_unit=per, avg_launch_us=avg_s * 1e6)
+    def alu_roof(k, flops_key):
+        per = UNIT_WORK[flops_key][a.M]
+        r = rate_entry(per, units[k], kt[k][0], kt[k][1], PEAK_FP64_VECTOR_TFLOPS, 1e12)
+        return dict(bound="alu", achieved=r["achieved"], peak=r["peak"], unit="TFLOP/s", frac=r["frac"],
+                    traffic=traffic(kname[k], r["units_per_launch"]), kernel=kname[k], flops_per_unit=per,
+                    units_per_launch=r["units_per_launch"], launches=r["launches"],
+                    avg_launch_us=r["avg_launch_us"],
+                    kernel_count_flops_per_unit=(recon_flops(a.M) if k == "recon" else predict_flops(a.M)))
+
+    def hbm_rate(k, bytes_key):
+        per = UNIT_WORK[bytes_key][a.M]
+        r = rate_entry(per, units[k], kt[k][0], kt[k][1], PEAK_HBM_GBS, 1e9)
+        return dict(r, unit="GB/s", bytes_per_unit=per)
+
     total_ms = sum(v[0] for v in kt.values())
+    dom = max(("recon", "predict"), key=lambda k: kt[k][0])
+    roof = alu_roof(dom, "recon_flops" if dom == "recon" else "predict_flops")
+    fp64_kernels = {kname[k]: alu_roof(k, f) for k, f in (("recon", "recon_flops"), ("predict", "predict_flops"))}
+    hbm_kernels = {kname[k]: hbm_rate(k, b) for k, b in (("patch", "patch_bytes"), ("update", "update_bytes"),
+                                                         ("node", "node_bytes"), ("sched", "sched_bytes"))}
 
     if a.traffic_sweep:
         # the profiled pass again for every persistent-grid setting of the
@@ -482,9 +587,11 @@ def main():
             kq = s.kernel_times()
             s.set_profiling(False)
             q1 = s.stats()
-            print(json.dumps({"traffic_sweep": w, "launches": {k: kq[k][1] for k in ("recon", "predict")},
+            print(json.dumps({"traffic_sweep": w, "launches": {k: kq[k][1] for k in kq},
                               "units": {"recon": q1["element_updates"] - q0["element_updates"],
-                                        "predict": q1["predictor_evals"] - q0["predictor_evals"]}}),
+                                        "predict": q1["predictor_evals"] - q0["predictor_evals"],
+                                        "patch": q1["patches"] - q0["patches"],
+                                        "node": q1["node_moves"] - q0["node_moves"]}}),
                   flush=True)
         if tune:
             s.set_tune(sched_chunk=tune["sched_chunk"], list_wg_per_cu=tune["list_wg_per_cu"])
@@ -496,13 +603,21 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         sync()
+    del s
+
+    adj = None
+    if a.adjoint:
+        adj = adjoint_step_ratio()
+        note(f"adjoint/forward per step {adj['value']:.3f}")
 
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(a.cpu_elems, a.M, a.levels, a.cpu_steps) if a.workload == "vortex" else None
+        ce, cs = dflt[4]
+        cpu = cpu_baseline_case(a.workload, a.cpu_elems or ce, a.M, a.levels, a.cpu_steps or cs, t_end)
+        note(f"cpu oracle {cpu['value']:.0f} updates/s")
 
     line = {
-        "metric": "element-updates/s at 1e-10 rel err vs FP64 oracle, LTS vs GTS",
+        "metric": METRIC,
         "value": value,
         "unit": "element-updates/s",
         "n_gpus": 1,
@@ -515,23 +630,28 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": desc.format(mesh.n_elems) + f", M={a.M}, LTS {a.levels} levels, "
-                        f"{a.flux} flux, Lagrangian mesh motion",
+            "workload": desc.format(mesh.n_elems) + f", M={a.M}, LTS {a.levels} levels vs GTS, "
+                        f"{a.flux} flux, Lagrangian mesh motion, t from 0 (first {a.warmup} macro steps untimed)",
             "flux": a.flux,
             "n_elems": mesh.n_elems, "M": a.M, "levels": a.levels,
+            "lts_step_fraction": cfg.lts_step_fraction,
             "parallelism": "single GPU",
         },
         "gts": {"value": gts_updates / t_gts, "updates": gts_updates, "seconds": t_gts},
-        "lts": {"updates": lts_updates, "seconds": t_lts, "physical_interval": [T_a, T_b]},
+        "lts": lts,
         "lts_time_to_solution_speedup": t_gts / t_lts,
         "gts_over_lts_updates": gts_updates / max(lts_updates, 1),
         "free_steps": free,
+        "adjoint_forward": adj,
         "autotune": tune,
         "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "work_units": units,
         "kernel_share": {k: round(v[0] / total_ms, 3) for k, v in kt.items()},
         "roofline": roof,
+        "fp64_kernels": fp64_kernels,
+        "hbm_kernels": hbm_kernels,
+        "mfma": {"used": False, "note": "no kernel of the step issues MFMA instructions"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

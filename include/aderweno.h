@@ -76,13 +76,17 @@ typedef struct {
   double weno_eps;       /* epsilon of the WENO weights (paper: 1e-14)                 */
   double weno_r;         /* exponent r (paper: 8; only 8 is supported)                 */
   double weno_lambda;    /* central-stencil linear weight lambda_1 (paper: 1e5)        */
+  double lts_step_fraction; /* theta in (0, 1]: with L >= 2 dyadic levels the nominal
+                            finest step of a macro step is theta times the smallest
+                            CFL step at its start (0 -> 1); L = 1 ignores it        */
 } ader_config;
 
 typedef struct {
   int64_t element_updates; /* sum over cycles of the active-set size                   */
   int64_t cycles;          /* cycles run (a cycle = one pass of the update criterion)  */
   int64_t macro_steps;     /* macro steps completed (free steps: one per target time)  */
-  int64_t cfl_overshoots;  /* element steps longer than their CFL bound (level capped) */
+  int64_t cfl_overshoots;  /* element steps longer than their CFL bound (a step of one
+                              tick, 2^-30 of the macro step, still too long)          */
   double max_gcl_residual; /* max |closure of the space-time volume| / (|T|+|T'|)      */
   double t;                /* common time of all elements (they meet at macro steps);
                               with several instances the earliest instance time        */
@@ -90,6 +94,10 @@ typedef struct {
   int64_t predictor_evals; /* element predictors computed                              */
   int64_t patches;         /* space-time patches integrated                            */
   int64_t node_moves;      /* node motions                                             */
+  int64_t extra_cycles;    /* cycles beyond 2^(L-1) per macro step, run because some
+                              element's CFL step fell below the nominal finest step
+                              during the macro step (spare finer levels)             */
+  int64_t long_macro_steps;/* macro steps that needed such extra cycles              */
 } ader_stats;
 
 /* Create a context.  hip_stream: a hipStream_t (NULL = default stream).
@@ -141,10 +149,16 @@ int ader_upload_state(ader_ctx* ctx, const double* Q_dev, double t0);
 int ader_step_gts(ader_ctx* ctx, double t_target, int32_t max_steps, ader_stats* st);
 
 /* Local time stepping up to t_target in at most max_macro_steps macro steps
- * (<= 0: no limit).  A macro step has 2^(L-1) ticks of length delta = the
- * smallest CFL step at its start; each element steps 2^(L-1-level) ticks
- * under the update criterion of eq. eqn.WENOupdate over its scheduling
- * stencil; all elements meet again at the end of the macro step.
+ * (<= 0: no limit), paper Sec. 2.6 with dyadic steps.  A macro step spans
+ * 2^(L-1) times the smallest CFL step (eq. eqn.timestep) at its start, cut into
+ * 2^30 integer ticks of length delta (clamped so it ends at t_target at the
+ * latest); each element steps the largest power of two of ticks within its
+ * CFL step, aligned to its current tick, under the update criterion of eq.
+ * eqn.WENOupdate over its scheduling stencil; all elements meet again at the
+ * end of the macro step.  Steps below the nominal finest one (2^(31-L) ticks)
+ * are taken only by elements whose CFL step fell below it during the macro
+ * step; the macro step then needs cycles beyond its 2^(L-1) (stats:
+ * extra_cycles), so no step exceeds its element's CFL bound.
  * lts_levels == 0 (free local steps, Sec. 2.3 with each element at its own CFL
  * step of eq. eqn.timestep): the whole interval to t_target is one macro step
  * of 2^30 ticks of length (t_target - t) / 2^30; an element steps
@@ -182,9 +196,11 @@ int ader_autotune(ader_ctx* ctx, int32_t trial_macro_steps, ader_tune* chosen);
 /* Launch mode of ader_step_gts / ader_step_lts.  on != 0 (the default): each
  * macro step (levels and predictors, its 2^(L-1) cycles, the unfinished count
  * and the macro-step end) is one HIP graph, captured on a private stream of
- * the context at the first step toward a given target time and replayed on
- * the context's stream; one host synchronisation per macro step. on == 0: the
- * same kernels are launched one by one.  Results are identical.  While
+ * the context at the first step with a given number of levels and replayed on
+ * the context's stream (the target time is read from device memory, so one
+ * graph serves every target); one host synchronisation per macro step, more
+ * only when extra cycles are needed (two cycles per captured batch). on == 0:
+ * the same kernels are launched one by one.  Results are identical.  While
  * profiling is on, kernels are always launched one by one. */
 int ader_set_graphs(ader_ctx* ctx, int32_t on);
 

@@ -13,9 +13,13 @@ design notes of the repository):
       its old to its new segment (edge fluxes and vertex fluxes of eq. eqn.STint
       in one form); the stages then run in the order of the algorithm
       description (motion, fluxes, update, projection, WENO, time step, predictor).
-  R2  time steps are dyadic: a macro step of 2^(L-1) ticks of length delta, with
-      delta = min of the CFL time steps (eq. eqn.timestep) at the macro start;
-      element step = 2^(L-1-level) ticks.  L = 1 is global time stepping.
+  R2  time steps are dyadic: a macro step spans 2^(L-1) times the smallest CFL
+      time step (eq. eqn.timestep) at its start and is cut into 2^30 integer
+      ticks; an element steps the largest power of two of ticks within its CFL
+      step, aligned to its current tick.  Steps below the nominal finest one
+      (2^(31-L) ticks) are taken when an element's CFL step falls below it
+      during the macro step, so no step exceeds its element's CFL step.  L = 1
+      is global time stepping.
   R3  the scheduling stencil is the symmetric closure of the WENO stencil and
       the vertex ring (so every predictor read lies inside its time slab).
   R4  predictor: only test functions with tau > 0 are kept in eq. CGfinal;
@@ -74,6 +78,7 @@ class Config:
     gcl_tol: float = 1e-12
     weno_shared: bool = True
     flux: str = "rusanov"             # "rusanov" (eq. eqn.rusanov), "osher" (eq. eqn.osher) or "hll"
+    lts_fraction: float = 0.9         # nominal finest dyadic step / smallest CFL step (L >= 2)
 
     @property
     def npic(self):
@@ -399,11 +404,29 @@ FLUXES = {"rusanov": rusanov_flux, "osher": osher_flux, "hll": hll_flux}
 BC_TRANSMISSIVE = 1
 BC_SLIP = 2
 
-# Free local time steps (paper-literal LTS, eq. eqn.timestep per element): one
-# macro step covers the whole interval in 2^30 ticks, and each element steps
-# floor(dt_CFL / delta) ticks, so the update criterion stays integer arithmetic
-# while every step is within 2^-30 of the interval below its CFL step.
+# Ticks per macro step.  Free local time steps (paper-literal LTS, eq.
+# eqn.timestep per element): one macro step covers the whole interval in 2^30
+# ticks, and each element steps floor(dt_CFL / delta) ticks, so the update
+# criterion stays integer arithmetic while every step is within 2^-30 of the
+# interval below its CFL step.  Dyadic levels (R2): a macro step of L levels
+# spans 2^(L-1) times the smallest CFL step at its start and is cut into the
+# same 2^30 ticks, so the nominal finest step is 2^(31-L) ticks and the spare
+# finer powers of two below it are there for elements whose CFL step falls
+# below it during the macro step.
 FREE_TICKS = 1 << 30
+MACRO_TICKS = FREE_TICKS
+
+
+def macro_tick(levels, dt_min, T, t_end, fraction=1.0):
+    """Tick length of a macro step starting at time T: (t_end - T) / 2^30 for
+    free steps; for L >= 1 levels, 2^(L-1) theta dt_min / 2^30 with the step
+    fraction theta (1 for L = 1), clamped so that the macro step does not pass
+    t_end (both divisions exact power-of-two scalings)."""
+    rest = (t_end - T) / MACRO_TICKS
+    if levels == 0:
+        return rest
+    theta = fraction if levels > 1 else 1.0
+    return min((dt_min * theta) * ((1 << (levels - 1)) / MACRO_TICKS), rest)
 
 
 def mirror_state(q, N):
@@ -474,8 +497,10 @@ def level_step(dtcfl, delta, N, n, free):
     """Step in ticks of an element at tick n of a macro step of N ticks of
     length delta, and whether it overshoots its CFL step.
     Dyadic (R2): the largest power of two p <= N with p*delta <= dt_CFL,
-    limited by the alignment of tick n.  Free (R19): floor(dt_CFL / delta),
-    at most the ticks left.  At least one tick."""
+    limited by the alignment of tick n; a tick is far below the nominal finest
+    step, so p * delta > dt_CFL would need dt_CFL to fall below 2^-30 of the
+    macro step.  Free (R19): floor(dt_CFL / delta), at most the ticks left.
+    At least one tick."""
     if free:
         left = N - n
         q = dtcfl / delta
@@ -544,7 +569,7 @@ class Solver:
                         QM=np.zeros((NE, 4)), HM=np.zeros((NE, 3)), wnod=np.zeros((NE, nb, 4)),
                         avg=np.zeros((NE, M + 1, 4)), trace=np.zeros((NE, 3, nG, M + 1, 4)),
                         vvel=np.zeros((NE, 3, M + 1, 2)), X=X, nk=np.zeros(NV, np.int64))
-        self.st.N = FREE_TICKS if cfg.levels == 0 else 1 << (cfg.levels - 1)
+        self.st.N = MACRO_TICKS
         self.wall_n, self.wall_pin = wall_constraints(self.topo, X)
         # pre-processing (Sec. 2.6): first reconstruction without projection and first CFL step
         allel = np.arange(NE)
@@ -621,13 +646,7 @@ class Solver:
     # -- macro-step boundary -----------------------------------------------------
     def macro_begin(self, t_end):
         st = self.st
-        if self.cfg.levels == 0:
-            # free steps: one macro step spans the whole interval in FREE_TICKS ticks
-            delta = (t_end - st.T) / st.N
-        else:
-            delta = float(st.dtcfl.min())
-            delta = min(delta, (t_end - st.T) / st.N)
-        st.delta = delta
+        st.delta = macro_tick(self.cfg.levels, float(st.dtcfl.min()), st.T, t_end, self.cfg.lts_fraction)
         allel = np.arange(self.topo.n_elems)
         st.n[:] = 0
         st.nk[:] = 0

@@ -34,7 +34,7 @@ class AderConfig(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("lts_levels", ctypes.c_int32),
                 ("n_picard", ctypes.c_int32), ("mesh_velocity", ctypes.c_int32),
                 ("weno_eps", ctypes.c_double), ("weno_r", ctypes.c_double),
-                ("weno_lambda", ctypes.c_double)]
+                ("weno_lambda", ctypes.c_double), ("lts_step_fraction", ctypes.c_double)]
 
 
 class AderTune(ctypes.Structure):
@@ -47,7 +47,8 @@ class AderStats(ctypes.Structure):
                 ("macro_steps", ctypes.c_int64), ("cfl_overshoots", ctypes.c_int64),
                 ("max_gcl_residual", ctypes.c_double), ("t", ctypes.c_double),
                 ("delta", ctypes.c_double), ("predictor_evals", ctypes.c_int64),
-                ("patches", ctypes.c_int64), ("node_moves", ctypes.c_int64)]
+                ("patches", ctypes.c_int64), ("node_moves", ctypes.c_int64),
+                ("extra_cycles", ctypes.c_int64), ("long_macro_steps", ctypes.c_int64)]
 
 
 class AderError(RuntimeError):

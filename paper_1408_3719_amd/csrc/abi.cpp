@@ -28,13 +28,14 @@ struct ader_ctx {
   // batch: element ranges [inst_first[k], inst_first[k+1]) of the instances
   std::vector<int> inst_first, e_inst, v_inst;
   // each macro step as one HIP graph (captured on a private stream, replayed on
-  // the caller's), rebuilt when the target time or the ticks per macro step change
+  // the caller's), rebuilt when the number of levels or the launch settings change
   bool graphs = true;
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
-  double g_t = 0.0;
-  int g_N = 0;
+  int g_nominal = 0;
   hipGraphExec_t gcyc = nullptr;    // FREE_BATCH cycles and the status count
+  hipGraphExec_t gextra = nullptr;  // EXTRA_BATCH cycles and the status count
+  int64_t extra_cycles = 0, long_macro_steps = 0;   // beyond 2^(L-1) cycles
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ADER_K_COUNT];
@@ -219,28 +220,36 @@ int issue_cycles(ader_ctx* c, int n, hipStream_t st) {
 }
 
 // Tick lengths and levels of the open instances (flagged by launch_open for
-// t_end beforehand), predictors.
-int issue_macro_begin(ader_ctx* c, double t_end, int N, hipStream_t st) {
-  LCHK(c, timed(c, ADER_K_MACRO, st, [&] { return aw::launch_macro_begin(c->dev, t_end, N, st); }));
+// the target time on the device beforehand), predictors. nominal = 2^(L-1)
+// for L dyadic levels, 0 for free steps.
+int issue_macro_begin(ader_ctx* c, int nominal, hipStream_t st) {
+  const double frac = nominal > 1 && c->cfg.lts_step_fraction > 0.0 ? c->cfg.lts_step_fraction : 1.0;
+  LCHK(c, timed(c, ADER_K_MACRO, st,
+                [&] { return aw::launch_macro_begin(c->dev, aw::MACRO_TICKS, nominal, frac, st); }));
   LCHK(c, timed(c, ADER_K_PREDICT, st, [&] { return aw::launch_predict(c->dev, c->prm, c->cfg.M, 0, st); }));
   return 0;
 }
 
-// One macro step: levels and predictors, N cycles, the count of elements short
-// of tick N, the macro-step end when that count is zero, and the count of
-// instances still short of t_end.
-int issue_macro(ader_ctx* c, double t_end, int N, hipStream_t st) {
+// One macro step of L dyadic levels: levels and predictors, 2^(L-1) cycles
+// (enough unless some element took a step below the nominal finest one), the
+// count of elements short of the macro-step end, the macro-step end when that
+// count is zero, and the count of instances still short of the target time.
+// Nothing here depends on the target time, which the kernels read from the
+// device (launch_set_target), so one captured graph serves every target.
+int issue_macro(ader_ctx* c, int nominal, hipStream_t st) {
   int r;
-  if ((r = issue_macro_begin(c, t_end, N, st))) return r;
-  if ((r = issue_cycles(c, N, st))) return r;
+  if ((r = issue_macro_begin(c, nominal, st))) return r;
+  if ((r = issue_cycles(c, nominal, st))) return r;
   LCHK(c, timed(c, ADER_K_STATUS, st, [&] { return aw::launch_status(c->dev, st); }));
   LCHK(c, aw::launch_macro_end(c->dev, 1, st));
-  LCHK(c, aw::launch_open(c->dev, t_end, st));
+  LCHK(c, aw::launch_open(c->dev, st));
   return 0;
 }
 
-// Cycles per host check of the free-step run.
+// Cycles per host check of the free-step run, and of the cycles a dyadic
+// macro step needs beyond 2^(L-1) when elements took spare finer steps.
 constexpr int FREE_BATCH = 16;
+constexpr int EXTRA_BATCH = 2;
 
 // n cycles, then the count of elements short of tick N.
 int issue_cycle_batch(ader_ctx* c, int n, hipStream_t st) {
@@ -279,16 +288,17 @@ int capture(ader_ctx* c, hipGraphExec_t* out, F issue) {
 void drop_graphs(ader_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->gcyc) (void)hipGraphExecDestroy(c->gcyc);
+  if (c->gextra) (void)hipGraphExecDestroy(c->gextra);
   c->gexec = nullptr;
   c->gcyc = nullptr;
+  c->gextra = nullptr;
 }
 
-int ensure_graph(ader_ctx* c, double t_end, int N) {
-  if (c->gexec && c->g_t == t_end && c->g_N == N) return 0;
-  int r = capture(c, &c->gexec, [&](hipStream_t s) { return issue_macro(c, t_end, N, s); });
+int ensure_graph(ader_ctx* c, int nominal) {
+  if (c->gexec && c->g_nominal == nominal) return 0;
+  int r = capture(c, &c->gexec, [&](hipStream_t s) { return issue_macro(c, nominal, s); });
   if (r) return r;
-  c->g_t = t_end;
-  c->g_N = N;
+  c->g_nominal = nominal;
   return 0;
 }
 
@@ -299,36 +309,47 @@ void set_free(ader_ctx* c, bool free_steps) {
   c->dev.free_steps = free_steps;
 }
 
-// Macro steps of N ticks until t_target; returns 0 or an error code. One host
-// synchronisation per macro step; further cycles only when some element has
-// not reached tick N after N cycles.
-int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
+// Macro steps of L dyadic levels until t_target; returns 0 or an error code.
+// One host synchronisation per macro step of 2^(L-1) cycles; when some element
+// has not reached the macro-step end by then (it took spare finer steps), more
+// cycles in captured batches of EXTRA_BATCH with a status read after each.
+int run_macro(ader_ctx* c, double t_target, int max_macro, int levels) {
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
   c->synced = false;
   set_free(c, false);
+  const int nominal = 1 << (levels - 1);
+  const bool graph = c->graphs && !c->prof;
   aw::Scal s;
   int r;
-  LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
+  LCHK(c, aw::launch_set_target(c->dev, t_target, c->stream));
+  LCHK(c, aw::launch_open(c->dev, c->stream));
   if ((r = read_scal(c, s))) return r;
   for (int k = 0; max_macro <= 0 || k < max_macro; ++k) {
     if ((r = check_err(c, s))) return r;
     if (s.n_open == 0) break;      // every instance has reached t_target
-    if (c->graphs && !c->prof) {
-      if ((r = ensure_graph(c, t_target, N))) return r;
+    if (graph) {
+      if ((r = ensure_graph(c, nominal))) return r;
       HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-    } else if ((r = issue_macro(c, t_target, N, c->stream))) {
+    } else if ((r = issue_macro(c, nominal, c->stream))) {
       return r;
     }
-    c->cycles += N;
+    c->cycles += nominal;
     if ((r = read_scal(c, s))) return r;
     if ((r = check_err(c, s))) return r;
     if (s.n_unfinished != 0) {
       long long last = (long long)s.updates;
       for (;;) {
-        if ((r = issue_cycles(c, 1, c->stream))) return r;
-        c->cycles++;
-        LCHK(c, timed(c, ADER_K_STATUS, c->stream, [&] { return aw::launch_status(c->dev, c->stream); }));
+        if (graph) {
+          if (!c->gextra &&
+              (r = capture(c, &c->gextra, [&](hipStream_t st) { return issue_cycle_batch(c, EXTRA_BATCH, st); })))
+            return r;
+          HIPCHK(c, hipGraphLaunch(c->gextra, c->stream));
+        } else if ((r = issue_cycle_batch(c, EXTRA_BATCH, c->stream))) {
+          return r;
+        }
+        c->cycles += EXTRA_BATCH;
+        c->extra_cycles += EXTRA_BATCH;
         if ((r = read_scal(c, s))) return r;
         if ((r = check_err(c, s))) return r;
         if (s.n_unfinished == 0) break;
@@ -336,8 +357,9 @@ int run_macro(ader_ctx* c, double t_target, int max_macro, int N) {
         last = (long long)s.updates;
       }
       LCHK(c, aw::launch_macro_end(c->dev, 0, c->stream));
-      LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
+      LCHK(c, aw::launch_open(c->dev, c->stream));
       if ((r = read_scal(c, s))) return r;
+      c->long_macro_steps++;
     }
     c->macro_steps++;
   }
@@ -353,16 +375,16 @@ int run_free(ader_ctx* c, double t_target, int max_macro) {
   if (!std::isfinite(t_target)) return fail(c, ADER_E_ARG, "t_target is not finite");
   c->synced = false;
   set_free(c, true);
-  const int N = aw::FREE_TICKS;
   const bool graph = c->graphs && !c->prof;
   aw::Scal s;
   int r;
-  LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
+  LCHK(c, aw::launch_set_target(c->dev, t_target, c->stream));
+  LCHK(c, aw::launch_open(c->dev, c->stream));
   if ((r = read_scal(c, s))) return r;
   for (int k = 0; max_macro <= 0 || k < max_macro; ++k) {
     if ((r = check_err(c, s))) return r;
     if (s.n_open == 0) break;
-    if ((r = issue_macro_begin(c, t_target, N, c->stream))) return r;
+    if ((r = issue_macro_begin(c, 0, c->stream))) return r;
     long long last = -1;
     for (;;) {
       if (graph) {
@@ -381,7 +403,7 @@ int run_free(ader_ctx* c, double t_target, int max_macro) {
       last = (long long)s.updates;
     }
     LCHK(c, aw::launch_macro_end(c->dev, 0, c->stream));
-    LCHK(c, aw::launch_open(c->dev, t_target, c->stream));
+    LCHK(c, aw::launch_open(c->dev, c->stream));
     if ((r = read_scal(c, s))) return r;
     c->macro_steps++;
   }
@@ -415,6 +437,8 @@ void fill_stats(ader_ctx* c, const aw::Scal& s, const std::vector<aw::Inst>& in,
   st->predictor_evals = (int64_t)s.n_pred;
   st->patches = (int64_t)s.n_patch;
   st->node_moves = (int64_t)s.n_node;
+  st->extra_cycles = c->extra_cycles;
+  st->long_macro_steps = c->long_macro_steps;
 }
 
 struct Arr {
@@ -610,6 +634,7 @@ int ader_create(const ader_config* cfg, void* hip_stream, ader_ctx** out) {
   if (cfg->lts_levels < 0 || cfg->lts_levels > 8) return ADER_E_ARG;
   if (cfg->weno_r != 8.0) return ADER_E_ARG;
   if (cfg->mesh_velocity != 0 && cfg->mesh_velocity != 1) return ADER_E_ARG;
+  if (!(cfg->lts_step_fraction >= 0.0 && cfg->lts_step_fraction <= 1.0)) return ADER_E_ARG;
   ader_ctx* c = new (std::nothrow) ader_ctx();
   if (!c) return ADER_E_ARG;
   c->cfg = *cfg;
@@ -787,7 +812,7 @@ int ader_step_gts(ader_ctx* c, double t_target, int32_t max_steps, ader_stats* s
 int ader_step_lts(ader_ctx* c, double t_target, int32_t max_macro_steps, ader_stats* st) {
   if (!c) return ADER_E_ARG;
   int r = c->cfg.lts_levels == 0 ? run_free(c, t_target, max_macro_steps)
-                                 : run_macro(c, t_target, max_macro_steps, 1 << (c->cfg.lts_levels - 1));
+                                 : run_macro(c, t_target, max_macro_steps, c->cfg.lts_levels);
   if (r) return r;
   return st ? ader_get_stats(c, st) : ADER_OK;
 }
@@ -903,8 +928,9 @@ int ader_debug_macro_begin(ader_ctx* c, double t_end, int32_t levels) {
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   set_free(c, levels == 0);
   c->synced = false;
-  LCHK(c, aw::launch_open(c->dev, t_end, c->stream));
-  int r = issue_macro_begin(c, t_end, levels == 0 ? aw::FREE_TICKS : 1 << (levels - 1), c->stream);
+  LCHK(c, aw::launch_set_target(c->dev, t_end, c->stream));
+  LCHK(c, aw::launch_open(c->dev, c->stream));
+  int r = issue_macro_begin(c, levels == 0 ? 0 : 1 << (levels - 1), c->stream);
   if (r) return r;
   aw::Scal s;
   if ((r = read_scal(c, s))) return r;
@@ -973,11 +999,12 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
     if ((rr = restore())) return rr;
     const double far = 1e300;
     // free steps are tuned on 3 dyadic levels: the settings only group work
-    const int N = c->cfg.lts_levels > 0 ? 1 << (c->cfg.lts_levels - 1) : 4;
-    LCHK(c, aw::launch_open(c->dev, far, c->stream));
+    const int nominal = c->cfg.lts_levels > 0 ? 1 << (c->cfg.lts_levels - 1) : 4;
+    LCHK(c, aw::launch_set_target(c->dev, far, c->stream));
+    LCHK(c, aw::launch_open(c->dev, c->stream));
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int k = 0; k < trials; ++k)
-      if ((rr = issue_macro(c, far, N, c->stream))) return rr;
+      if ((rr = issue_macro(c, nominal, c->stream))) return rr;
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
     float f = 0.f;

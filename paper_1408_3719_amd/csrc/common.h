@@ -59,8 +59,8 @@ struct Inst {
 
 // Device-resident scalars of the running simulation.
 struct Scal {
-  double t_end;     // target time of the current call
-  int N;            // ticks per macro step 2^(L-1)
+  double t_end;     // target time of the current call (set before a run, read by the kernels)
+  int N;            // ticks per macro step
   int n_open;       // instances short of the target time
   // n_active and n_live share one 8-byte word (little-endian, n_active low):
   // one 64-bit atomic reserves space in both lists
@@ -84,9 +84,15 @@ static_assert(offsetof(Scal, n_live) == offsetof(Scal, n_active) + sizeof(int) &
 
 enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8, ERR_DT = 16 };
 
-// Free local time steps: the interval to the target time is one macro step of
-// FREE_TICKS ticks; every element steps floor(dt_CFL / delta) ticks.
+// Ticks per macro step. Free local time steps: the interval to the target
+// time is one macro step of FREE_TICKS ticks; every element steps
+// floor(dt_CFL / delta) ticks. Dyadic levels: a macro step of L levels spans
+// 2^(L-1) smallest CFL steps and is cut into the same number of ticks, so the
+// nominal finest step is 2^(31-L) ticks and the powers of two below it are
+// spare levels for elements whose CFL step falls below it during the macro
+// step (no step exceeds its element's CFL step).
 constexpr int FREE_TICKS = 1 << 30;
+constexpr int MACRO_TICKS = FREE_TICKS;
 
 // Per-element storage.  Data that other elements gather (vertices, average,
 // area, the predictor's time-node averages and vertex velocities) sits in one
@@ -179,7 +185,8 @@ int launch_init_geometry(const Dev& d, void* stream);
 int launch_reconstruct(const Dev& d, const Params& p, int M, int use_list, int set_level,
                        void* stream);
 int launch_predict(const Dev& d, const Params& p, int M, int use_list, void* stream);
-int launch_macro_begin(const Dev& d, double t_end, int N, void* stream);
+int launch_macro_begin(const Dev& d, int N, int nominal, double fraction, void* stream);
+int launch_set_target(const Dev& d, double t_end, void* stream);
 int launch_cycle_begin(const Dev& d, void* stream);
 int launch_sched(const Dev& d, void* stream);
 int launch_node(const Dev& d, const Params& p, int M, void* stream);
@@ -187,7 +194,7 @@ int launch_patch(const Dev& d, const Params& p, int M, void* stream);
 int launch_update(const Dev& d, const Params& p, void* stream);
 int launch_status(const Dev& d, void* stream);
 int launch_macro_end(const Dev& d, int only_if_done, void* stream);
-int launch_open(const Dev& d, double t_end, void* stream);
+int launch_open(const Dev& d, void* stream);
 int launch_download_xy(const Dev& d, double* out, void* stream);
 int launch_download_q(const Dev& d, double* out, void* stream);
 int launch_upload_q(const Dev& d, const double* in, void* stream);

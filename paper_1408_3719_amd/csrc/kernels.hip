@@ -298,8 +298,9 @@ __device__ inline double cfl_ratio(const double X[6], const double Q[4], double 
 
 // Step in ticks from tick `tick` of a macro step of N ticks of length delta.
 // Dyadic levels: the largest power of two p <= N with p*delta <= dt_CFL,
-// limited by the alignment of the current tick. Free steps: floor(dt_CFL /
-// delta) ticks, at most the ticks left. At least one tick (overshoot flagged).
+// limited by the alignment of the current tick (a tick is 2^-30 of the macro
+// step, far below the nominal finest step). Free steps: floor(dt_CFL / delta)
+// ticks, at most the ticks left. At least one tick (overshoot flagged).
 __device__ inline int level_step(double dtcfl, double delta, int N, int tick, int free_steps,
                                  int* over) {
   if (free_steps) {
@@ -546,6 +547,7 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
       }
     if (sl == 7) {
       d.dtcfl[i] = dt;
+      if (!(dt > 0.0 && dt < DBL_MAX)) set_err(d, ERR_DT);
       if (set_level) {
         const int N = d.scal->N;
         if (nt >= N) {
@@ -1282,35 +1284,44 @@ __global__ void __launch_bounds__(TPB) k_min_dt(Dev d) {
     const int i = base + threadIdx.x;
     const bool in = i < d.NE;
     const int k = in ? d.e_inst[i] : -1;
+    // a lane without a finite positive step takes no part (and raised ERR_DT)
     double m = in ? d.dtcfl[i] : DBL_MAX;
+    if (!(m > 0.0 && m < DBL_MAX)) m = DBL_MAX;
     const int k0 = __shfl(k, 0), klast = __shfl(k, 63);
     if (k0 == klast) {
 #pragma unroll
       for (int s = 1; s < 64; s <<= 1) m = fmin(m, __shfl_xor(m, s));
-      if (__lane_id() == 0 && k0 >= 0 && m > 0.0 && m < DBL_MAX)
+      if (__lane_id() == 0 && k0 >= 0 && m < DBL_MAX)
         atomicMin(&d.inst[k0].min_dt_bits, (unsigned long long)__double_as_longlong(m));
-    } else if (in && m > 0.0 && m < DBL_MAX) {
+    } else if (in && m < DBL_MAX) {
       atomicMin(&d.inst[k].min_dt_bits, (unsigned long long)__double_as_longlong(m));
     }
   }
 }
 
-// Tick length of the macro step per open instance: the smallest CFL step,
-// clamped so that N ticks do not pass the target time; 0 for closed ones.
-__global__ void __launch_bounds__(TPB) k_macro_setup(Dev d, double t_end, int N) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    d.scal->N = N;
-    d.scal->t_end = t_end;
-  }
+// Tick length of the macro step per open instance: for dyadic levels the
+// smallest CFL step times the step fraction, times dscale = 2^(L-1) / N (a
+// power of two), clamped so that N ticks do not pass the target time; for free
+// steps the interval to the target over N; 0 for closed ones. An instance that
+// had no finite positive CFL step (k_min_dt left its minimum unset) raises
+// ERR_DT.
+__global__ void __launch_bounds__(TPB) k_macro_setup(Dev d, int N, double fraction, double dscale) {
+  const double t_end = d.scal->t_end;
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.scal->N = N;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.K; k += gridDim.x * blockDim.x) {
     Inst* in = d.inst + k;
     if (!in->open) {
       in->delta = 0.0;
       continue;
     }
-    const double dmin = __longlong_as_double((long long)in->min_dt_bits);
     const double rest = (t_end - in->T) / double(N);
-    in->delta = d.free_steps ? rest : fmin(dmin, rest);
+    if (d.free_steps) {
+      in->delta = rest;
+    } else if (in->min_dt_bits == ~0ull) {
+      in->delta = 0.0;
+    } else {
+      in->delta = fmin((__longlong_as_double((long long)in->min_dt_bits) * fraction) * dscale, rest);
+    }
     if (!(in->delta > 0.0)) set_err(d, ERR_DT);
   }
 }
@@ -1356,9 +1367,12 @@ __global__ void __launch_bounds__(TPB) k_macro_end(Dev d, int only_if_done) {
   }
 }
 
-// Which instances are short of t_end (the same test the host applies to a
-// single time), and how many.
-__global__ void __launch_bounds__(TPB) k_open(Dev d, double t_end) {
+__global__ void k_set_target(Dev d, double t_end) { d.scal->t_end = t_end; }
+
+// Which instances are short of the target time (the same test the host applies
+// to a single time), and how many.
+__global__ void __launch_bounds__(TPB) k_open(Dev d) {
+  const double t_end = d.scal->t_end;
   const double tol = 1e-12 * fmax(1.0, fabs(t_end));
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.K; k += gridDim.x * blockDim.x)
     d.inst[k].open = !(t_end - d.inst[k].T <= tol);
@@ -1539,10 +1553,15 @@ int launch_predict(const Dev& d, const Params& p, int M, int use_list, void* s) 
   return 0;
 }
 
-int launch_macro_begin(const Dev& d, double t_end, int N, void* s) {
+int launch_set_target(const Dev& d, double t_end, void* s) {
+  AW_LAUNCH1(k_set_target, s, d, t_end);
+  return 0;
+}
+
+int launch_macro_begin(const Dev& d, int N, int nominal, double fraction, void* s) {
   AW_LAUNCH(k_reset_min, d.K, s, d);
   AW_LAUNCH(k_min_dt, d.NE, s, d);
-  AW_LAUNCH(k_macro_setup, d.K, s, d, t_end, N);
+  AW_LAUNCH(k_macro_setup, d.K, s, d, N, fraction, double(nominal) / double(N));
   AW_LAUNCH(k_levels, d.NE > d.NV ? d.NE : d.NV, s, d);
   return 0;
 }
@@ -1590,8 +1609,8 @@ int launch_macro_end(const Dev& d, int only_if_done, void* s) {
   return 0;
 }
 
-int launch_open(const Dev& d, double t_end, void* s) {
-  AW_LAUNCH(k_open, d.K, s, d, t_end);
+int launch_open(const Dev& d, void* s) {
+  AW_LAUNCH(k_open, d.K, s, d);
   AW_LAUNCH_G(k_count_open, 1, s, d);
   return 0;
 }

@@ -28,12 +28,13 @@ class Config:
     weno_r: float = 8.0
     weno_lambda: float = 1e5
     flux: str = "rusanov"          # "rusanov", "osher" or "hll"
+    lts_step_fraction: float = 0.9
 
     def to_c(self) -> _lib.AderConfig:
         return _lib.AderConfig(self.M, FLUX[self.flux], self.gamma, self.cfl, self.levels,
                                self.n_picard,
                                MESH_VELOCITY[self.mesh_velocity], self.weno_eps, self.weno_r,
-                               self.weno_lambda)
+                               self.weno_lambda, self.lts_step_fraction)
 
 
 def _check(lib, ctx, code):

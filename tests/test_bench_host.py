@@ -1,6 +1,5 @@
 """Host-side pieces of the benchmark contract (no GPU): the refusal of more
-than one GPU, and the algorithmic operation counts the roofline uses (the
-figures quoted in the design notes)."""
+than one GPU and the arithmetic of the reported rates."""
 import os
 import subprocess
 import sys
@@ -19,11 +18,24 @@ def test_more_than_one_gpu_is_refused():
     assert out.stdout.strip() == ""
 
 
-def test_operation_counts():
-    assert bench.recon_flops(2) == 29289
-    assert bench.recon_flops(1) < bench.recon_flops(2) < bench.recon_flops(3)
-    assert bench.predict_flops(1) < bench.predict_flops(2) < bench.predict_flops(3)
-    assert bench.patch_bytes(2) == 760
+def test_rate_arithmetic():
+    """achieved = work per unit x units per launch / average launch time."""
+    r = bench.rate_entry(25_000, 2_000_000, 40.0, 20, 78.6, 1e12)
+    # 100k units per launch, 2 ms per launch: 2.5e9 flop / 2e-3 s = 1.25 TFLOP/s
+    assert abs(r["achieved"] - 1.25) < 1e-12
+    assert abs(r["frac"] - 1.25 / 78.6) < 1e-15
+    assert r["units_per_launch"] == 100_000 and abs(r["avg_launch_us"] - 2000.0) < 1e-9
+    h = bench.rate_entry(784, 1_000_000, 10.0, 10, 8000.0, 1e9)
+    assert abs(h["achieved"] - 784 * 100_000 / 1e-3 / 1e9) < 1e-9
+
+
+def test_unit_work_grows_with_the_order():
+    for key, per in bench.UNIT_WORK.items():
+        assert per[1] <= per[2] <= per[3], key
+    # the kernels' own operation counts are of the same size as the method's
+    for M in (1, 2, 3):
+        assert 0.5 < bench.recon_flops(M) / bench.UNIT_WORK["recon_flops"][M] < 2.0
+        assert 0.5 < bench.predict_flops(M) / bench.UNIT_WORK["predict_flops"][M] < 2.0
 
 
 def test_traffic_table_covers_the_autotuner_candidates():

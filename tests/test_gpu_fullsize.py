@@ -63,7 +63,8 @@ def test_explosion_full_size_sampled_parity_and_conservation():
     pressure sums to zero force over the closed polygon), the GCL held, and
     fewer element updates than global steps at the finest step."""
     from oracle.scheme import Config as OConfig
-    from oracle.scheme import cfl_time_steps, level_step, predictor_batch, reconstruct_batch
+    from oracle.scheme import (MACRO_TICKS, cfl_time_steps, level_step, macro_tick, predictor_batch,
+                               reconstruct_batch)
     from oracle.topology import face_neighbours, stencils_of
     mesh, Q0 = explosion_case(400_000, seed=7)
     NE = mesh.n_elems
@@ -82,9 +83,9 @@ def test_explosion_full_size_sampled_parity_and_conservation():
     assert rel(g.dump("DTCFL"), dt_o) < TOL
     print("pre-processing checked", flush=True)
     g.debug_macro_begin(1.0, 4)
-    delta = float(dt_o.min())
+    delta = macro_tick(4, float(dt_o.min()), 0.0, 1.0)
     assert abs(g.dump("SCAL")[1] - delta) <= 1e-14 * delta
-    steps_o = np.array([level_step(dt_o[i], delta, 8, 0, False)[0] for i in range(NE)])
+    steps_o = np.array([level_step(dt_o[i], delta, MACRO_TICKS, 0, False)[0] for i in range(NE)])
     assert np.array_equal(g.dump("STEP"), steps_o)
     assert len(np.unique(steps_o)) == 4                 # all four levels in use
     pr = predictor_batch(2, cfg, wnod_o, Xe[sample], steps_o[sample] * delta, np.zeros(sample.size))
