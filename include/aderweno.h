@@ -235,6 +235,21 @@ int ader_adjoint_workspace_size(const ader_ctx* ctx, size_t* bytes);
 int ader_adjoint_gts_step(ader_ctx* ctx, double dt, const double* Q_dev, const double* Qbar_next_dev,
                           double* Qbar_dev, void* work_dev, size_t work_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step
+ * adjoint of ader_adjoint_gts_step, same arguments and preconditions, with its
+ * scratch in a fixed device array of ADER_STATIC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends (its address
+ * on the context's GPU is looked up once, by ader_bind_workspace).  Calls no
+ * allocating routine.  ADER_E_ARG when ader_adjoint_workspace_size exceeds
+ * ADER_STATIC_SCRATCH_BYTES (M = 2 fits ~26k triangles).  Every call on one
+ * GPU uses the same array, which keeps the last call's contents (nothing in it
+ * is read before the call writes it): calls that overlap on one GPU, from
+ * any stream or context, race and must be serialised by the caller. */
+#define ADER_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+int ader_adjoint_gts_step_static(ader_ctx* ctx, double dt, const double* Q_dev,
+                                 const double* Qbar_next_dev, double* Qbar_dev);
+
 /* Current state into caller device buffers (any may be NULL):
  * Q_dev [4][n_elems] SoA, node_xy_dev [n_nodes][2], elem_t_dev [n_elems]. */
 int ader_download_state(ader_ctx* ctx, double* Q_dev, double* node_xy_dev, double* elem_t_dev);

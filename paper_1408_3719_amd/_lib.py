@@ -7,6 +7,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaderweno.so")
 
+E_ARG = -1
+# ADER_STATIC_SCRATCH_BYTES: the fixed device array of ader_adjoint_gts_step_static
+STATIC_SCRATCH_BYTES = 256 << 20
 E_NAMES = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_STATE", -4: "E_GEOM", -5: "E_GCL",
            -6: "E_DEADLOCK", -7: "E_HIP", -8: "E_ORDER"}
 
@@ -25,6 +28,7 @@ EXPORTED = ["ader_create", "ader_upload_mesh", "ader_workspace_size", "ader_bind
             "ader_debug_cycles", "ader_debug_macro_begin", "ader_set_profiling", "ader_set_graphs",
             "ader_set_instances", "ader_instance_times", "ader_set_tune", "ader_autotune",
             "ader_kernel_times", "ader_adjoint_workspace_size", "ader_adjoint_gts_step",
+            "ader_adjoint_gts_step_static",
             "ader_last_error", "ader_destroy"]
 KERNELS = ["sched", "node", "patch", "update", "recon", "predict", "macro", "status", "adjoint"]
 
@@ -94,6 +98,7 @@ def load():
     lib.ader_kernel_times.argtypes = [P, i32, P, P]
     lib.ader_adjoint_workspace_size.argtypes = [P, P]
     lib.ader_adjoint_gts_step.argtypes = [P, dbl, P, P, P, P, ctypes.c_size_t]
+    lib.ader_adjoint_gts_step_static.argtypes = [P, dbl, P, P, P]
     lib.ader_last_error.argtypes = [P]
     lib.ader_last_error.restype = ctypes.c_char_p
     lib.ader_destroy.argtypes = [P]

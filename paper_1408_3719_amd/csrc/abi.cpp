@@ -36,6 +36,9 @@ struct ader_ctx {
   hipGraphExec_t gcyc = nullptr;    // FREE_BATCH cycles and the status count
   hipGraphExec_t gextra = nullptr;  // EXTRA_BATCH cycles and the status count
   int64_t extra_cycles = 0, long_macro_steps = 0;   // beyond 2^(L-1) cycles
+  // the library's fixed adjoint scratch on this context's GPU (ader_bind_workspace)
+  void* static_work = nullptr;
+  size_t static_bytes = 0;
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ADER_K_COUNT];
@@ -770,6 +773,8 @@ int ader_bind_workspace(ader_ctx* c, void* dev_ptr, size_t bytes) {
   s.N = 1;
   if ((r = h2d(c, d.scal, &s, sizeof(s)))) return r;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  // the fixed adjoint scratch of this GPU (device address looked up once per device)
+  if ((r = aw::static_scratch(&c->static_work, &c->static_bytes))) return hip_fail(c, r, "hipGetSymbolAddress");
   c->bound = true;
   return ADER_OK;
 }
@@ -1066,9 +1071,12 @@ int ader_adjoint_workspace_size(const ader_ctx* c, size_t* bytes) {
   return ADER_OK;
 }
 
-int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Q_dev, const double* Qbar_next_dev,
-                          double* Qbar_dev, void* work_dev, size_t work_bytes) {
-  if (!c || !Qbar_next_dev || !Qbar_dev || !work_dev) return ADER_E_ARG;
+}  // extern "C"
+
+namespace {
+
+// Checks shared by both adjoint entry points.
+int adjoint_check(ader_ctx* c, double dt, const double* Q_dev) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, ADER_E_ARG, "dt must be positive and finite");
   if (c->cfg.mesh_velocity != 1) return fail(c, ADER_E_ARG, "the adjoint needs a fixed mesh (mesh_velocity = 1)");
   if (c->cfg.flux == ADER_FLUX_OSHER) return fail(c, ADER_E_ARG, "the adjoint covers the Rusanov and HLL fluxes");
@@ -1076,18 +1084,51 @@ int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Q_dev, const dou
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (!Q_dev && !c->synced)
     return fail(c, ADER_E_ORDER, "elements are not at a common time (macro step in progress)");
+  return 0;
+}
+
+aw::AdjWork adjoint_buffers(ader_ctx* c, const double* Q_dev, const double* Qbar_next_dev, double* Qbar_dev,
+                            char* work) {
+  aw::AdjWork w{};
+  w.qbar_next = Qbar_next_dev;
+  w.qbar = Qbar_dev;
+  aw::adjoint_carve(c->cfg.M, c->topo.NE, c->topo.NF, c->prm.npic, work, w);
+  w.q = Q_dev ? Q_dev : w.qcopy;
+  return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ader_adjoint_gts_step(ader_ctx* c, double dt, const double* Q_dev, const double* Qbar_next_dev,
+                          double* Qbar_dev, void* work_dev, size_t work_bytes) {
+  if (!c || !Qbar_next_dev || !Qbar_dev || !work_dev) return ADER_E_ARG;
+  int r = adjoint_check(c, dt, Q_dev);
+  if (r) return r;
   const size_t need = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->topo.NF, c->prm.npic);
   if (work_bytes < need) return fail(c, ADER_E_ARG, "adjoint workspace too small");
   if ((reinterpret_cast<uintptr_t>(work_dev) & 255) != 0)
     return fail(c, ADER_E_ARG, "adjoint workspace must be 256-byte aligned");
-  aw::AdjWork w{};
-  w.qbar_next = Qbar_next_dev;
-  w.qbar = Qbar_dev;
-  aw::adjoint_carve(c->cfg.M, c->topo.NE, c->topo.NF, c->prm.npic, static_cast<char*>(work_dev), w);
-  w.q = Q_dev ? Q_dev : w.qcopy;
+  const aw::AdjWork w = adjoint_buffers(c, Q_dev, Qbar_next_dev, Qbar_dev, static_cast<char*>(work_dev));
   LCHK(c, timed(c, ADER_K_ADJOINT, c->stream, [&] {
     return aw::launch_adjoint_gts(c->dev, c->prm, c->cfg.M, w, dt, Q_dev == nullptr, c->stream);
   }));
+  return ADER_OK;
+}
+
+int ader_adjoint_gts_step_static(ader_ctx* c, double dt, const double* Q_dev, const double* Qbar_next_dev,
+                                 double* Qbar_dev) {
+  if (!c || !Qbar_next_dev || !Qbar_dev) return ADER_E_ARG;
+  int r = adjoint_check(c, dt, Q_dev);
+  if (r) return r;
+  if (!c->static_work) return fail(c, ADER_E_ORDER, "no workspace bound (the fixed scratch is set up there)");
+  const size_t need = aw::adjoint_work_bytes(c->cfg.M, c->topo.NE, c->topo.NF, c->prm.npic);
+  if (need > c->static_bytes)
+    return fail(c, ADER_E_ARG, "mesh too large for the fixed adjoint scratch: needs " + std::to_string(need) +
+                                   " bytes, ADER_STATIC_SCRATCH_BYTES is " + std::to_string(c->static_bytes));
+  const aw::AdjWork w = adjoint_buffers(c, Q_dev, Qbar_next_dev, Qbar_dev, static_cast<char*>(c->static_work));
+  LCHK(c, aw::launch_adjoint_gts(c->dev, c->prm, c->cfg.M, w, dt, Q_dev == nullptr, c->stream));
   return ADER_OK;
 }
 

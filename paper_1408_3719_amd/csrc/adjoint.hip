@@ -35,11 +35,40 @@
 // not be kept.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "aderweno.h"
 #include "basis.h"
 #include "common.h"
 
 namespace aw {
+
+// Scratch of ader_adjoint_gts_step_static (callers that cannot allocate): a
+// file-scope device array, one copy on every GPU the library runs on, held
+// until the process ends. Host code never passes `scratch` itself to a kernel
+// (on the host it is only a stand-in for the symbol): its device address on
+// the current GPU comes from static_scratch() below.
+static __device__ __align__(256) char scratch[ADER_STATIC_SCRATCH_BYTES];
+
+int static_scratch(void** ptr, size_t* bytes) {
+  static std::mutex mu;
+  static std::vector<void*> addr;   // per device, looked up once
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return int(e);
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev >= int(addr.size())) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return int(e);
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = ADER_STATIC_SCRATCH_BYTES;
+  return 0;
+}
 
 namespace {
 

@@ -170,6 +170,9 @@ struct AdjWork {
                              // (row 0: the element's own terms), summed by the gather
 };
 
+// Device address of the library's fixed adjoint scratch on the current GPU
+// and its size (adjoint.hip); looked up once per device.
+int static_scratch(void** ptr, size_t* bytes);
 // Bytes of the adjoint workspace (each buffer 256-byte aligned).
 size_t adjoint_work_bytes(int M, int NE, int NF, int npic);
 // Carve the buffers from base (qbar_next, qbar left to the caller).

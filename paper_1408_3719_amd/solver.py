@@ -181,6 +181,19 @@ class Solver(_Base):
             ctypes.c_void_p(aligned), n))
         return out
 
+    def adjoint_gts_step_static(self, dt, qbar_next, q=None, out=None):
+        """The same step adjoint through ader_adjoint_gts_step_static: its
+        scratch is the library's fixed device array, nothing is allocated by
+        the library (out: optional caller tensor [4][NE] for the result)."""
+        qn = self._dev4(qbar_next, "qbar_next")
+        qs = self._dev4(q, "q") if q is not None else None
+        if out is None:
+            out = self.torch.empty_like(qn)
+        _check(self.lib, self.ctx, self.lib.ader_adjoint_gts_step_static(
+            self.ctx, dt, ctypes.c_void_p(qs.data_ptr()) if qs is not None else None,
+            ctypes.c_void_p(qn.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def step_gts(self, t_target, max_steps=0):
         st = _lib.AderStats()
         _check(self.lib, self.ctx, self.lib.ader_step_gts(self.ctx, t_target, max_steps, ctypes.byref(st)))

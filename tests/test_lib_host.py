@@ -198,3 +198,11 @@ def test_transposed_stencil_rows():
         for j in range(NE):
             got = idx[ptr[j]:ptr[j + 1]].tolist()
             assert got == sorted(expect.get(j, [])), j
+
+
+def test_static_scratch_size_matches_the_header():
+    import re
+    from paper_1408_3719_amd import _lib
+    hdr = open(os.path.join(ROOT, "include", "aderweno.h")).read()
+    m = re.search(r"#define ADER_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.STATIC_SCRATCH_BYTES
