@@ -78,7 +78,9 @@ typedef struct {
   double weno_lambda;    /* central-stencil linear weight lambda_1 (paper: 1e5)        */
   double lts_step_fraction; /* theta in (0, 1]: with L >= 2 dyadic levels the nominal
                             finest step of a macro step is theta times the smallest
-                            CFL step at its start (0 -> 1); L = 1 ignores it        */
+                            CFL step at its start (0 -> the default 0.95, which
+                            leaves room for the CFL step's usual decrease within a
+                            macro step); L = 1 ignores it                          */
 } ader_config;
 
 typedef struct {
@@ -98,6 +100,8 @@ typedef struct {
                               element's CFL step fell below the nominal finest step
                               during the macro step (spare finer levels)             */
   int64_t long_macro_steps;/* macro steps that needed such extra cycles              */
+  int64_t replay_overrides;/* under schedule replay: replayed steps that differ from
+                              the level rule's own choice                            */
 } ader_stats;
 
 /* Create a context.  hip_stream: a hipStream_t (NULL = default stream).
@@ -139,7 +143,8 @@ int ader_set_instances(ader_ctx* ctx, int32_t n_instances, const int32_t* elem_f
 int ader_bind_workspace(ader_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Initial cell averages, device [4][n_elems] SoA (rho, rho u, rho v, rho E),
- * at time t0, on the mesh of ader_upload_mesh.  Runs the pre-processing of
+ * at time t0, on the mesh of ader_upload_mesh (node positions are reset to
+ * that mesh: a state of a Lagrangian run on a moved mesh cannot be restored).  Runs the pre-processing of
  * the paper (Sec. 2.6): first reconstruction without projection and first
  * CFL time step of every element.  ADER_E_STATE on rho <= 0 or p <= 0. */
 int ader_upload_state(ader_ctx* ctx, const double* Q_dev, double t0);
@@ -192,6 +197,22 @@ int ader_set_tune(ader_ctx* ctx, const ader_tune* tune);
  * not advance.  Allocates a device copy of the workspace for the duration
  * (hipMalloc).  The choice is written to *chosen when not null. */
 int ader_autotune(ader_ctx* ctx, int32_t trial_macro_steps, ader_tune* chosen);
+
+/* Schedule replay for parity tests (Sec. 2.6: which step each element takes).
+ * step_ptr: host [n_elems + 1], step_ptr[0] = 0, non-decreasing, step_ptr[n_elems]
+ * = n_steps; steps: host [n_steps]; element i takes, in order, the steps (in
+ * ticks) steps[step_ptr[i] .. step_ptr[i+1]) at its step decisions (at each
+ * macro-step start and after each update that leaves it short of the
+ * macro-step end) instead of the level rule's, e.g. the steps another
+ * implementation took, so that a decision taken in floating point on both
+ * sides (a CFL step at a level boundary, a free step's floor) cannot flip.
+ * The library copies the tables into device memory it allocates (hipMalloc)
+ * and owns; positions restart at zero here and at ader_upload_state.
+ * stats.replay_overrides counts replayed steps that differ from the rule's.
+ * A missing entry or a step that would leave the macro step fails the next
+ * stepping call with ADER_E_ARG.  step_ptr == NULL switches replay off.
+ * Synchronises the stream. */
+int ader_set_schedule_replay(ader_ctx* ctx, const int32_t* step_ptr, const int32_t* steps, int64_t n_steps);
 
 /* Launch mode of ader_step_gts / ader_step_lts.  on != 0 (the default): each
  * macro step (levels and predictors, its 2^(L-1) cycles, the unfinished count

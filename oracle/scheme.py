@@ -13,13 +13,13 @@ design notes of the repository):
       its old to its new segment (edge fluxes and vertex fluxes of eq. eqn.STint
       in one form); the stages then run in the order of the algorithm
       description (motion, fluxes, update, projection, WENO, time step, predictor).
-  R2  time steps are dyadic: a macro step spans 2^(L-1) times the smallest CFL
-      time step (eq. eqn.timestep) at its start and is cut into 2^30 integer
-      ticks; an element steps the largest power of two of ticks within its CFL
-      step, aligned to its current tick.  Steps below the nominal finest one
-      (2^(31-L) ticks) are taken when an element's CFL step falls below it
-      during the macro step, so no step exceeds its element's CFL step.  L = 1
-      is global time stepping.
+  R2  time steps are dyadic: a macro step spans 2^(L-1) nominal finest steps of
+      theta (0.95) times the smallest CFL time step (eq. eqn.timestep) at its
+      start and is cut into 2^30 integer ticks; an element steps the largest
+      power of two of ticks within its CFL step, aligned to its current tick.
+      Steps below the nominal finest one (2^(31-L) ticks) are taken when an
+      element's CFL step falls below it during the macro step, so no step
+      exceeds its element's CFL step.  L = 1 is global time stepping (theta 1).
   R3  the scheduling stencil is the symmetric closure of the WENO stencil and
       the vertex ring (so every predictor read lies inside its time slab).
   R4  predictor: only test functions with tau > 0 are kept in eq. CGfinal;
@@ -78,7 +78,7 @@ class Config:
     gcl_tol: float = 1e-12
     weno_shared: bool = True
     flux: str = "rusanov"             # "rusanov" (eq. eqn.rusanov), "osher" (eq. eqn.osher) or "hll"
-    lts_fraction: float = 0.9         # nominal finest dyadic step / smallest CFL step (L >= 2)
+    lts_fraction: float = 0.95        # nominal finest dyadic step / smallest CFL step (L >= 2)
 
     @property
     def npic(self):
@@ -571,6 +571,11 @@ class Solver:
                         vvel=np.zeros((NE, 3, M + 1, 2)), X=X, nk=np.zeros(NV, np.int64))
         self.st.N = MACRO_TICKS
         self.wall_n, self.wall_pin = wall_constraints(self.topo, X)
+        # schedule record and override (parity tooling): step_log[i] lists the
+        # steps element i took, in order; step_hook(i, k, p) may replace the
+        # k-th step p that the level rule chose for element i
+        self.step_log = [[] for _ in range(NE)]
+        self.step_hook = None
         # pre-processing (Sec. 2.6): first reconstruction without projection and first CFL step
         allel = np.arange(NE)
         self._reconstruct(allel)
@@ -628,7 +633,14 @@ class Solver:
         out = np.zeros(elems.size, np.int64)
         for t, i in enumerate(elems):
             p, over = level_step(st.dtcfl[i], st.delta, st.N, int(st.n[i]), self.cfg.levels == 0)
+            if self.step_hook is not None:
+                q = int(self.step_hook(int(i), len(self.step_log[i]), p))
+                if q != p:
+                    if not 1 <= q <= st.N - st.n[i]:
+                        raise ValueError("a forced step must stay within the macro step")
+                    p, over = q, q * st.delta > st.dtcfl[i]
             st.cfl_overshoots += over
+            self.step_log[i].append(p)
             out[t] = p
         return out
 

@@ -28,7 +28,7 @@ EXPORTED = ["ader_create", "ader_upload_mesh", "ader_workspace_size", "ader_bind
             "ader_debug_cycles", "ader_debug_macro_begin", "ader_set_profiling", "ader_set_graphs",
             "ader_set_instances", "ader_instance_times", "ader_set_tune", "ader_autotune",
             "ader_kernel_times", "ader_adjoint_workspace_size", "ader_adjoint_gts_step",
-            "ader_adjoint_gts_step_static",
+            "ader_adjoint_gts_step_static", "ader_set_schedule_replay",
             "ader_last_error", "ader_destroy"]
 KERNELS = ["sched", "node", "patch", "update", "recon", "predict", "macro", "status", "adjoint"]
 
@@ -52,7 +52,8 @@ class AderStats(ctypes.Structure):
                 ("max_gcl_residual", ctypes.c_double), ("t", ctypes.c_double),
                 ("delta", ctypes.c_double), ("predictor_evals", ctypes.c_int64),
                 ("patches", ctypes.c_int64), ("node_moves", ctypes.c_int64),
-                ("extra_cycles", ctypes.c_int64), ("long_macro_steps", ctypes.c_int64)]
+                ("extra_cycles", ctypes.c_int64), ("long_macro_steps", ctypes.c_int64),
+                ("replay_overrides", ctypes.c_int64)]
 
 
 class AderError(RuntimeError):
@@ -99,6 +100,7 @@ def load():
     lib.ader_adjoint_workspace_size.argtypes = [P, P]
     lib.ader_adjoint_gts_step.argtypes = [P, dbl, P, P, P, P, ctypes.c_size_t]
     lib.ader_adjoint_gts_step_static.argtypes = [P, dbl, P, P, P]
+    lib.ader_set_schedule_replay.argtypes = [P, P, P, ctypes.c_int64]
     lib.ader_last_error.argtypes = [P]
     lib.ader_last_error.restype = ctypes.c_char_p
     lib.ader_destroy.argtypes = [P]

@@ -36,6 +36,8 @@ struct ader_ctx {
   hipGraphExec_t gcyc = nullptr;    // FREE_BATCH cycles and the status count
   hipGraphExec_t gextra = nullptr;  // EXTRA_BATCH cycles and the status count
   int64_t extra_cycles = 0, long_macro_steps = 0;   // beyond 2^(L-1) cycles
+  // schedule replay tables (device memory owned by the context)
+  int* replay_buf = nullptr;
   // the library's fixed adjoint scratch on this context's GPU (ader_bind_workspace)
   void* static_work = nullptr;
   size_t static_bytes = 0;
@@ -108,8 +110,7 @@ size_t carve(ader_ctx* c, char* base) {
   d.trace = pd(NE * aw::trace_stride(M));
   d.wnod = pd(NE * aw::wnod_stride(M));
   d.dtcfl = pd(NE);
-  d.QM = pd(4 * NE);
-  d.HM = pd(3 * NE);
+  d.mem = pd(NE * 3 * aw::MEM_W);
   d.act_stamp = pi(NE);
   d.act_list = pi(NE);
   d.live_list = pi(NE);
@@ -137,9 +138,6 @@ size_t carve(ader_ctx* c, char* base) {
   d.e_el = pi(NF);
   d.e_er = pi(NF);
   d.e_bc = pi(NF);
-  d.G = pd(4 * NF);
-  d.Nint = pd(3 * NF);
-  d.edge_stamp = pi(NF);
   return L.total;
 }
 
@@ -198,6 +196,8 @@ int check_err(ader_ctx* c, const aw::Scal& s) {
   if (s.err & aw::ERR_STATE) return fail(c, ADER_E_STATE, "non-physical state (rho <= 0, p <= 0 or NaN)");
   if (s.err & aw::ERR_PRED) return fail(c, ADER_E_STATE, "a predictor was read outside its time slab");
   if (s.err & aw::ERR_DT) return fail(c, ADER_E_STATE, "time step is not positive");
+  if (s.err & aw::ERR_REPLAY)
+    return fail(c, ADER_E_ARG, "schedule replay: an element ran out of recorded steps or a step leaves its macro step");
   return 0;
 }
 
@@ -226,7 +226,7 @@ int issue_cycles(ader_ctx* c, int n, hipStream_t st) {
 // the target time on the device beforehand), predictors. nominal = 2^(L-1)
 // for L dyadic levels, 0 for free steps.
 int issue_macro_begin(ader_ctx* c, int nominal, hipStream_t st) {
-  const double frac = nominal > 1 && c->cfg.lts_step_fraction > 0.0 ? c->cfg.lts_step_fraction : 1.0;
+  const double frac = nominal <= 1 ? 1.0 : c->cfg.lts_step_fraction > 0.0 ? c->cfg.lts_step_fraction : 0.95;
   LCHK(c, timed(c, ADER_K_MACRO, st,
                 [&] { return aw::launch_macro_begin(c->dev, aw::MACRO_TICKS, nominal, frac, st); }));
   LCHK(c, timed(c, ADER_K_PREDICT, st, [&] { return aw::launch_predict(c->dev, c->prm, c->cfg.M, 0, st); }));
@@ -442,6 +442,7 @@ void fill_stats(ader_ctx* c, const aw::Scal& s, const std::vector<aw::Inst>& in,
   st->node_moves = (int64_t)s.n_node;
   st->extra_cycles = c->extra_cycles;
   st->long_macro_steps = c->long_macro_steps;
+  st->replay_overrides = (int64_t)s.replay_overrides;
 }
 
 struct Arr {
@@ -464,8 +465,8 @@ Arr lookup(ader_ctx* c, int what) {
     case ADER_DBG_TICK: a.bytes = NE * I; break;
     case ADER_DBG_STEP: a.bytes = NE * I; break;
     case ADER_DBG_DTCFL: a.dev = d.dtcfl; a.bytes = NE * D; break;
-    case ADER_DBG_QM: a.dev = d.QM; a.bytes = 4 * NE * D; break;
-    case ADER_DBG_HM: a.dev = d.HM; a.bytes = 3 * NE * D; break;
+    case ADER_DBG_QM: a.bytes = 4 * NE * D; break;
+    case ADER_DBG_HM: a.bytes = 3 * NE * D; break;
     case ADER_DBG_WNOD: a.bytes = nb * 4 * NE * D; break;
     case ADER_DBG_AVG: a.bytes = nt * 4 * NE * D; break;
     case ADER_DBG_TRACE: a.bytes = 3 * nG * nt * 4 * NE * D; break;
@@ -760,6 +761,7 @@ int ader_bind_workspace(ader_ctx* c, void* dev_ptr, size_t bytes) {
   if ((r = h2d(c, d.tsten_idx, t.tsten_idx.data(), t.tsten_idx.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.ring_ptr, t.ring_ptr.data(), t.ring_ptr.size() * sizeof(int)))) return r;
   if ((r = h2d(c, d.ring_ent, t.ring_ent.data(), t.ring_ent.size() * sizeof(int)))) return r;
+
   if ((r = h2d(c, d.wall_n, wn.data(), wn.size() * sizeof(double)))) return r;
   if ((r = h2d(c, d.wall_pin, t.wall_pin.data(), NV * sizeof(int)))) return r;
   if ((r = h2d(c, d.e_a, t.e_a.data(), NF * sizeof(int)))) return r;
@@ -795,6 +797,8 @@ int ader_upload_state(ader_ctx* c, const double* Q_dev, double t0) {
   if ((r = h2d(c, d.inst, in.data(), in.size() * sizeof(aw::Inst)))) return r;
   c->cycles = 0;
   c->macro_steps = 0;
+  c->extra_cycles = 0;
+  c->long_macro_steps = 0;
   LCHK(c, aw::launch_init_geometry(d, c->stream));
   LCHK(c, aw::launch_upload_q(d, Q_dev, c->stream));
   LCHK(c, aw::launch_check_state(d, c->prm.gamma, c->stream));
@@ -879,6 +883,19 @@ int ader_debug_dump(ader_ctx* c, int32_t what, void* host, size_t bytes) {
     std::memcpy(host, v, sizeof(v));
     return ADER_OK;
   }
+  if (what == ADER_DBG_QM || what == ADER_DBG_HM) {
+    // memory variables: the sum of the element's three edge slots
+    const size_t NE = c->topo.NE, W = aw::MEM_W;
+    std::vector<double> m(NE * 3 * W);
+    HIPCHK(c, hipMemcpyAsync(m.data(), c->dev.mem, m.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int nf = what == ADER_DBG_QM ? 4 : 3, f0 = what == ADER_DBG_QM ? 0 : 4;
+    double* out = static_cast<double*>(host);
+    for (int f = 0; f < nf; ++f)
+      for (size_t i = 0; i < NE; ++i)
+        out[f * NE + i] = (m[(i * 3 + 0) * W + f0 + f] + m[(i * 3 + 1) * W + f0 + f]) + m[(i * 3 + 2) * W + f0 + f];
+    return ADER_OK;
+  }
   if (!a.dev) return packed_io(c, what, host, nullptr, bytes);
   HIPCHK(c, hipMemcpyAsync(host, a.dev, bytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -889,6 +906,8 @@ int ader_debug_inject(ader_ctx* c, int32_t what, const void* host, size_t bytes)
   if (!c || !host) return ADER_E_ARG;
   if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
   if (what >= ADER_DBG_TOPO_EDGES) return fail(c, ADER_E_ARG, "topology and tables are read-only");
+  if (what == ADER_DBG_QM || what == ADER_DBG_HM)
+    return fail(c, ADER_E_ARG, "memory variables are kept per element edge and cannot be injected");
   Arr a = lookup(c, what);
   if (a.bytes == 0 || bytes != a.bytes) return fail(c, ADER_E_ARG, "size mismatch");
   if (what == ADER_DBG_SCAL) {
@@ -1132,6 +1151,40 @@ int ader_adjoint_gts_step_static(ader_ctx* c, double dt, const double* Q_dev, co
   return ADER_OK;
 }
 
+int ader_set_schedule_replay(ader_ctx* c, const int32_t* step_ptr, const int32_t* steps, int64_t n_steps) {
+  if (!c) return ADER_E_ARG;
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  const size_t NE = c->topo.NE;
+  if (step_ptr) {
+    if (n_steps < 0 || n_steps > INT32_MAX || (n_steps > 0 && !steps))
+      return fail(c, ADER_E_ARG, "schedule replay: bad step count");
+    if (step_ptr[0] != 0 || int64_t(step_ptr[NE]) != n_steps)
+      return fail(c, ADER_E_ARG, "schedule replay: step_ptr must run from 0 to n_steps");
+    for (size_t i = 0; i < NE; ++i)
+      if (step_ptr[i + 1] < step_ptr[i]) return fail(c, ADER_E_ARG, "schedule replay: step_ptr decreases");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->replay_buf) {
+    HIPCHK(c, hipFree(c->replay_buf));
+    c->replay_buf = nullptr;
+  }
+  c->dev.replay_ptr = c->dev.replay_steps = nullptr;
+  c->dev.replay_pos = nullptr;
+  drop_graphs(c);              // graphs hold the launch arguments they were captured with
+  if (!step_ptr) return ADER_OK;
+  const size_t words = (NE + 1) + size_t(n_steps) + NE;
+  HIPCHK(c, hipMalloc(&c->replay_buf, words * sizeof(int)));
+  std::vector<int> host(words, 0);
+  std::memcpy(host.data(), step_ptr, (NE + 1) * sizeof(int));
+  if (n_steps) std::memcpy(host.data() + NE + 1, steps, size_t(n_steps) * sizeof(int));
+  HIPCHK(c, hipMemcpyAsync(c->replay_buf, host.data(), words * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->dev.replay_ptr = c->replay_buf;
+  c->dev.replay_steps = c->replay_buf + NE + 1;
+  c->dev.replay_pos = c->replay_buf + NE + 1 + n_steps;
+  return ADER_OK;
+}
+
 int ader_set_graphs(ader_ctx* c, int32_t on) {
   if (!c) return ADER_E_ARG;
   c->graphs = on != 0;
@@ -1157,6 +1210,7 @@ const char* ader_last_error(const ader_ctx* c) {
 void ader_destroy(ader_ctx* c) {
   if (!c) return;
   if (c->bound) (void)hipStreamSynchronize(c->stream);
+  if (c->replay_buf) (void)hipFree(c->replay_buf);
   drop_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   for (int k = 0; k < ADER_K_COUNT; ++k)

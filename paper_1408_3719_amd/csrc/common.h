@@ -76,13 +76,14 @@ struct Scal {
   unsigned long long n_pred;    // predictor evaluations
   unsigned long long n_patch;   // space-time patches integrated
   unsigned long long n_node;    // node moves
+  unsigned long long replay_overrides;   // replayed steps that differ from the level rule's
 };
 
 static_assert(offsetof(Scal, n_live) == offsetof(Scal, n_active) + sizeof(int) &&
                   offsetof(Scal, n_active) % 8 == 0,
               "n_active and n_live must form one aligned 8-byte word");
 
-enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8, ERR_DT = 16 };
+enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8, ERR_DT = 16, ERR_REPLAY = 32 };
 
 // Ticks per macro step. Free local time steps: the interval to the target
 // time is one macro step of FREE_TICKS ticks; every element steps
@@ -112,6 +113,8 @@ constexpr int rec_stride(int M) { return round16(11 + 10 * (M + 1)); }
 constexpr int trace_stride(int M) { return round16(3 * (M + 1) * (M + 1) * 4); }
 constexpr int wnod_stride(int M) { return (M + 1) * (M + 2) / 2 * 4; }
 
+constexpr int MEM_W = 8;   // doubles per memory-variable slot (G, N, one pad)
+
 struct TickStep {   // tick in the macro step and step length in ticks (0: finished)
   int tick, step;
 };
@@ -133,7 +136,11 @@ struct Dev {
   double* trace;      // [NE][trace_stride]
   double* wnod;       // [NE][wnod_stride]
   TickStep* ts;       // [NE]
-  double *dtcfl, *QM, *HM;   // SoA: [NE], [4][NE], [3][NE]
+  double* dtcfl;      // [NE]
+  // memory variables per (element, local edge), accumulated by the swept
+  // patches of that edge since the element's last update: flux (4) and
+  // space-time normal integral (3), MEM_W doubles per slot, [NE][3][MEM_W]
+  double* mem;
   int *act_stamp, *act_list;
   int* live_list;     // the active elements that stay short of tick N after the update
   const int *tri, *elem_edges, *neigh, *sten, *sched_ptr, *sched_idx;   // SoA [k][NE]
@@ -146,8 +153,10 @@ struct Dev {
   const int* wall_pin;              // node held fixed (two walls meet)
   // edges
   const int *e_a, *e_b, *e_L, *e_R, *e_el, *e_er, *e_bc;
-  double *G, *Nint;   // [4][NF], [3][NF]
-  int* edge_stamp;
+  // schedule replay (null when off): element i takes, in order, the steps
+  // replay_steps[replay_ptr[i] .. replay_ptr[i+1]); replay_pos[i] counts them
+  const int *replay_ptr, *replay_steps;
+  int* replay_pos;
 };
 
 // Buffers of the reverse-mode step (adjoint.hip), carved from the caller's

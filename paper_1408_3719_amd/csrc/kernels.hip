@@ -320,6 +320,31 @@ __device__ inline int level_step(double dtcfl, double delta, int N, int tick, in
   return p;
 }
 
+// The step an element takes: the level rule's choice `own`, or under schedule
+// replay the next recorded step of the element (counted when it differs from
+// `own`; a missing or out-of-range entry raises ERR_REPLAY and keeps `own`).
+// *over is set for the step taken.
+__device__ inline int take_step(const Dev& d, int i, int own, int tick, int N, double dtcfl, double delta,
+                                int* over) {
+  if (!d.replay_steps) return own;
+  const int pos = d.replay_ptr[i] + d.replay_pos[i];
+  if (pos >= d.replay_ptr[i + 1]) {
+    set_err(d, ERR_REPLAY);
+    return own;
+  }
+  d.replay_pos[i] += 1;
+  const int p = d.replay_steps[pos];
+  if (p < 1 || p > N - tick) {
+    set_err(d, ERR_REPLAY);
+    return own;
+  }
+  if (p != own) {
+    atomicAdd(&d.scal->replay_overrides, 1ull);
+    *over = double(p) * delta > dtcfl;
+  }
+  return p;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // This renumbering gives every XCD a contiguous range of logical blocks, so
 // that with Hilbert-ordered elements, nodes and edges the neighbours that a
@@ -554,7 +579,8 @@ __global__ void __launch_bounds__(TPB) k_reconstruct(Dev d, const Tables* __rest
           d.ts[i].step = 0;
         } else {
           int over;
-          d.ts[i].step = level_step(dt, delta, N, nt, d.free_steps, &over);
+          const int own = level_step(dt, delta, N, nt, d.free_steps, &over);
+          d.ts[i].step = take_step(d, i, own, nt, N, dt, delta, &over);
           if (over) atomicAdd(&d.scal->overshoots, 1ull);
         }
       }
@@ -1053,7 +1079,10 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Space-time patch fluxes: one lane per swept edge
+// Space-time patch fluxes: one lane per edge; an edge with a moved node
+// sweeps a patch, whose flux and normal integral go to the memory-variable
+// slots of the edge in its two elements (each slot has one writer per cycle:
+// its edge)
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__ tb, Params P) {
@@ -1091,6 +1120,17 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
     }
     const double* trL = d.trace + size_t(L) * TS + el * nG * T * 4;
     const double* trR = R >= 0 ? d.trace + size_t(R) * TS + er * nG * T * 4 : trL;
+    // the two memory-variable slots this edge adds to, read now so that the
+    // loads overlap the flux integration
+    double* sl = d.mem + (size_t(L) * 3 + el) * MEM_W;
+    double* sr = d.mem + (size_t(R >= 0 ? R : L) * 3 + (R >= 0 ? er : el)) * MEM_W;
+    double mL[7], mR[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) mL[c] = sl[c];
+    if (R >= 0) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) mR[c] = sr[c];
+    }
     double G[4] = {0, 0, 0, 0}, Nn[3] = {0, 0, 0};
 #pragma unroll 1
     for (int gq = 0; gq < nG; ++gq) {
@@ -1167,11 +1207,17 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
         for (int k = 0; k < 3; ++k) Nn[k] += w * N[k];
       }
     }
+    // inflow-positive memory variables: the flux leaves L and enters R
 #pragma unroll
-    for (int v = 0; v < 4; ++v) d.G[v * NF + e] = G[v];
+    for (int v = 0; v < 4; ++v) sl[v] = mL[v] - G[v];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) d.Nint[k * NF + e] = Nn[k];
-    d.edge_stamp[e] = cycle;
+    for (int k = 0; k < 3; ++k) sl[4 + k] = mL[4 + k] - Nn[k];
+    if (R >= 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sr[v] = mR[v] + G[v];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sr[4 + k] = mR[4 + k] + Nn[k];
+    }
     wave_count(&d.scal->n_patch);
   }
 }
@@ -1182,41 +1228,21 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
 template <int M>
 __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P) {
   const int cycle = d.scal->cycle;
-  const int NE = d.NE, NV = d.NV, NF = d.NF;
+  const int NE = d.NE, NV = d.NV;
+  const int na = d.scal->n_active;
+  const int nwork = (na + TPB - 1) / TPB;
   double gmax = 0.0;   // largest relative GCL residual seen by this lane
-  for (int i = xcd_block() * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
-    const bool act = d.act_stamp[i] == cycle;
-    int es[3];
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      es[k] = d.elem_edges[k * NE + i];
-      if (d.edge_stamp[es[k]] != cycle) es[k] = -1;
-      any |= es[k] >= 0;
-    }
-    if (!any && !act) continue;
+  for (int idx = xcd_block(nwork) * blockDim.x + threadIdx.x; idx < na; idx += gridDim.x * blockDim.x) {
+    const int i = d.act_list[idx];
+    // memory variables: the three edge slots, consumed and cleared
+    double* ms = d.mem + size_t(i) * 3 * MEM_W;
     double qm[4], hm[3];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) qm[v] = d.QM[v * NE + i];
+    for (int v = 0; v < 4; ++v) qm[v] = (ms[v] + ms[MEM_W + v]) + ms[2 * MEM_W + v];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) hm[c] = d.HM[c * NE + i];
+    for (int c = 0; c < 3; ++c) hm[c] = (ms[4 + c] + ms[MEM_W + 4 + c]) + ms[2 * MEM_W + 4 + c];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int e = es[k];
-      if (e < 0) continue;
-      const double sg = d.e_L[e] == i ? -1.0 : 1.0;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) qm[v] += sg * d.G[v * NF + e];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) hm[c] += sg * d.Nint[c * NF + e];
-    }
-    if (!act) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) d.QM[v * NE + i] = qm[v];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) d.HM[c * NE + i] = hm[c];
-      continue;
-    }
+    for (int c = 0; c < 3 * MEM_W; ++c) ms[c] = 0.0;
     double X[6];
     int nd[3];
     bool mv[3];
@@ -1241,12 +1267,7 @@ __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P) {
     const double pn = pressure(qn, P.gamma);
     if (!(qn[0] > 0.0) || !(pn > 0.0)) set_err(d, ERR_STATE);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      r[QO + v] = qn[v];
-      d.QM[v * NE + i] = 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) d.HM[c * NE + i] = 0.0;
+    for (int v = 0; v < 4; ++v) r[QO + v] = qn[v];
 #pragma unroll
     for (int c = 0; c < 6; ++c) r[XE + c] = X[c];
     r[AO] = An;
@@ -1338,7 +1359,8 @@ __global__ void __launch_bounds__(TPB) k_levels(Dev d) {
       if (delta > 0.0) {
         int over;
         me.tick = 0;
-        me.step = level_step(d.dtcfl[i], delta, N, 0, d.free_steps, &over);
+        const int own = level_step(d.dtcfl[i], delta, N, 0, d.free_steps, &over);
+        me.step = take_step(d, i, own, 0, N, d.dtcfl[i], delta, &over);
         if (over) atomicAdd(&d.scal->overshoots, 1ull);
       } else {
         me.tick = N;
@@ -1428,15 +1450,13 @@ __global__ void __launch_bounds__(TPB) k_init_geometry(Dev d) {
       d.ts[i] = TickStep{0, 0};
       d.act_stamp[i] = -1;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) d.QM[v * NE + i] = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) d.HM[c * NE + i] = 0.0;
+      for (int c = 0; c < 3 * MEM_W; ++c) d.mem[size_t(i) * 3 * MEM_W + c] = 0.0;
+      if (d.replay_pos) d.replay_pos[i] = 0;
     }
     if (i < NV) {
       d.ntick[i] = 0;
       d.node_stamp[i] = -1;
     }
-    if (i < NF) d.edge_stamp[i] = -1;
   }
 }
 
@@ -1581,6 +1601,9 @@ int launch_sched(const Dev& d, void* s) {
   return 0;
 }
 
+// The update kernel runs over the cycle's active list, whose length only the
+// device knows: a grid sized for every element (or the persistent grid of the
+// launch settings), blocks beyond the list exit at once.
 int launch_node(const Dev& d, const Params& p, int M, void* s) {
   AW_DISPATCH(M, AW_LAUNCH(k_node<MM>, d.NV, s, d, d.tab, p));
   return 0;
@@ -1592,7 +1615,8 @@ int launch_patch(const Dev& d, const Params& p, int M, void* s) {
 }
 
 int launch_update(const Dev& d, const Params& p, void* s) {
-  AW_DISPATCH(d.M, AW_LAUNCH(k_update<MM>, d.NE, s, d, p));
+  const int g = list_grid(d, (long(d.NE) + TPB - 1) / TPB, 1);
+  AW_DISPATCH(d.M, AW_LAUNCH_G(k_update<MM>, g, s, d, p));
   return 0;
 }
 

@@ -28,7 +28,7 @@ class Config:
     weno_r: float = 8.0
     weno_lambda: float = 1e5
     flux: str = "rusanov"          # "rusanov", "osher" or "hll"
-    lts_step_fraction: float = 0.9
+    lts_step_fraction: float = 0.95
 
     def to_c(self) -> _lib.AderConfig:
         return _lib.AderConfig(self.M, FLUX[self.flux], self.gamma, self.cfl, self.levels,
@@ -193,6 +193,21 @@ class Solver(_Base):
             self.ctx, dt, ctypes.c_void_p(qs.data_ptr()) if qs is not None else None,
             ctypes.c_void_p(qn.data_ptr()), ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def set_schedule_replay(self, step_log):
+        """Replay recorded steps: step_log[i] lists the steps (in ticks)
+        element i takes, in order (None: the level rule again)."""
+        if step_log is None:
+            _check(self.lib, self.ctx, self.lib.ader_set_schedule_replay(self.ctx, None, None, 0))
+            return
+        if len(step_log) != self.NE:
+            raise ValueError("one step list per element")
+        ptr = np.zeros(self.NE + 1, np.int32)
+        ptr[1:] = np.cumsum([len(x) for x in step_log])
+        steps = np.ascontiguousarray(np.concatenate([np.asarray(x, np.int64) for x in step_log]).astype(np.int32)) \
+            if ptr[-1] else np.zeros(1, np.int32)
+        _check(self.lib, self.ctx, self.lib.ader_set_schedule_replay(
+            self.ctx, ptr.ctypes.data, steps.ctypes.data, int(ptr[-1])))
 
     def step_gts(self, t_target, max_steps=0):
         st = _lib.AderStats()

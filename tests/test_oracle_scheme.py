@@ -287,3 +287,46 @@ def test_transmissive_boundary_does_not_amplify_noise():
     for _ in range(150):
         s.step(1e9)
     assert np.abs(s.Q[:, 0] - 1.0).max() < 1e-6
+
+
+def test_tick_length_of_a_macro_step():
+    """A macro step of L levels is cut into 2^30 ticks: its nominal finest step
+    (2^(31-L) ticks) is theta times the smallest CFL step, the macro step
+    2^(L-1) of them, clamped at the target time; one level ignores theta;
+    free steps cut the interval to the target."""
+    from oracle.scheme import MACRO_TICKS, macro_tick
+    assert MACRO_TICKS == 2 ** 30
+    for L in range(2, 9):
+        d = macro_tick(L, 0.37, 1.0, 1e9, 0.95)
+        assert d * 2 ** (31 - L) == 0.95 * 0.37            # exact power-of-two scaling
+        assert d * MACRO_TICKS == 2 ** (L - 1) * 0.95 * 0.37
+        short = macro_tick(L, 0.37, 1.0, 1.01, 0.95)
+        assert short * MACRO_TICKS == 1.01 - 1.0                # clamped at the target
+    assert macro_tick(1, 0.37, 0.0, 1e9, 0.95) * MACRO_TICKS == 0.37
+    assert macro_tick(0, 0.37, 0.5, 2.5, 0.95) * MACRO_TICKS == 2.0
+
+
+def test_dyadic_steps_never_exceed_the_cfl_step():
+    """eq. eqn.timestep holds for every step under dyadic levels: on the
+    explosion, where the CFL steps fall fast inside a macro step, elements take
+    the spare finer levels below the nominal finest step (the macro step then
+    runs extra cycles) and none steps past its CFL bound."""
+    from workloads import explosion_case
+    mesh, Q0 = explosion_case(1500, seed=7)
+    s = Solver(mesh.nodes, mesh.tris, Q0, Config(M=2, levels=4), bedges=mesh.bedges)
+    sub = 0
+    cycles = []
+    for _ in range(2):
+        s.macro_begin(1.0)
+        finest = s.st.N >> 3
+        c = 0
+        while (s.st.n < s.st.N).any():
+            live = s.st.n < s.st.N
+            assert (s.st.s[live] * s.st.delta <= s.st.dtcfl[live]).all()
+            sub += int((s.st.s[live] < finest).sum())
+            s.cycle()
+            c += 1
+        cycles.append(c)
+        s.st.T = s.st.T + s.st.N * s.st.delta
+    assert s.st.cfl_overshoots == 0
+    assert sub > 0 and max(cycles) > 8, (sub, cycles)
