@@ -1,5 +1,6 @@
-"""Reverse mode of one global time step on a fixed mesh (oracle, test
-infrastructure; never used by the product).
+"""Reverse mode of one global time step (oracle, test infrastructure; never
+used by the product): EulerianStep on a fixed mesh, LagrangianStep with the
+mesh moving with the fluid (node positions differentiated as well).
 
 The step is the scheme of Sec. 2 with one level (global time stepping) and the
 mesh held fixed (Eulerian mode, V = 0 in eq. ODEmesh): WENO reconstruction
@@ -17,7 +18,8 @@ computed once with the NumPy oracle's own tables and helpers; only the
 dependence on the state runs through torch.
 
 The forward map is pinned to the NumPy oracle's step and its derivative to
-central differences of that step (tests/test_oracle_adjoint.py).
+central differences of that step (tests/test_oracle_adjoint.py); the
+Lagrangian step also to the translation invariance of the scheme.
 """
 from __future__ import annotations
 
@@ -291,3 +293,236 @@ class EulerianStep:
     def step(self, Q, dt):
         with torch.no_grad():
             return self(_t(Q), dt).numpy()
+
+
+# ---------------------------------------------------------------------------
+# Lagrangian global step: state and node positions both differentiated
+# ---------------------------------------------------------------------------
+def _tri_area_t(X):
+    return 0.5 * ((X[..., 1, 0] - X[..., 0, 0]) * (X[..., 2, 1] - X[..., 0, 1])
+                  - (X[..., 2, 0] - X[..., 0, 0]) * (X[..., 1, 1] - X[..., 0, 1]))
+
+
+def _affine_map_t(X, xi, eta):
+    """x(xi, eta) of eq. xietaTransf for triangles X (..., 3, 2) at constant
+    reference points (P,) -> (..., P, 2)."""
+    return (X[..., 0, None, :] + (X[..., 1, None, :] - X[..., 0, None, :]) * xi[:, None]
+            + (X[..., 2, None, :] - X[..., 0, None, :]) * eta[:, None])
+
+
+def _affine_inverse_t(X, x):
+    """Reference coordinates of points x (..., P, 2) in triangles X (..., 3, 2)."""
+    e1 = X[..., 1, :] - X[..., 0, :]
+    e2 = X[..., 2, :] - X[..., 0, :]
+    det = e1[..., 0] * e2[..., 1] - e2[..., 0] * e1[..., 1]
+    d = x - X[..., 0, None, :]
+    xi = (d[..., 0] * e2[..., 1, None] - d[..., 1] * e2[..., 0, None]) / det[..., None]
+    eta = (e1[..., 0, None] * d[..., 1] - e1[..., 1, None] * d[..., 0]) / det[..., None]
+    return xi, eta
+
+
+class LagrangianStep:
+    """One global time step of length dt with the mesh moving with the fluid
+    (Lagrangian mode, V = v in eq. ODEmesh), as a torch function of the cell
+    averages Q (NE, 4) and the node positions X (NV, 2): the reconstruction on
+    the current geometry (eqs. intConsRec .. eqn.weno), the predictor of the
+    PDE and the mesh ODE (eqs. CGfinal, VCG, newVertPos), the node solver
+    (eqs. eqnNScs, eqn.NScs.weights, NodesVel, eqn.newVertex over [0, 1]), the
+    fluxes over the bilinear space-time patches of the moving edges (eqs.
+    eqn.spacetimenodes, G_ij, eqn.STint) and the update with the new areas
+    (eq. PDEfinal). Every geometric quantity is computed from X inside the
+    graph, so torch.autograd gives the vector-Jacobian product with respect to
+    both Q and X (dt held fixed)."""
+
+    def __init__(self, nodes, tris, cfg: Config, bedges=None, topo=None):
+        if cfg.flux not in FLUX_FUNCTIONS:
+            raise ValueError("the reverse-mode oracle covers the Rusanov and HLL fluxes")
+        if cfg.mesh_velocity != "lagrangian":
+            raise ValueError("LagrangianStep moves the mesh with the fluid")
+        from .scheme import wall_constraints
+        self.cfg = cfg
+        M = cfg.M
+        self.M = M
+        self.topo = topo if topo is not None else build_topology(nodes, tris, M, bedges)
+        topo = self.topo
+        self.NE, self.NV = topo.n_elems, topo.n_nodes
+        self.tris = torch.as_tensor(topo.tris, dtype=torch.long)
+        sten = topo.stencils
+        self.valid = sten[:, :, 0] >= 0
+        self.sten = sten
+        # reference-element tables (constants)
+        u, v, w = tb.duffy_rule(tb.recon_quad_n(M))
+        self.qu, self.qv, self.qw = _t(u), _t(v), _t(w / w.sum())
+        self.mons = tb.monomials(M)
+        self.psiC = _t(tb.psi_coeffs(M))                      # (nb, n_mono)
+        self.Sig = _t(tb.sigma_matrix(M))
+        self.lam = _t(np.where(np.arange(7) == 0, cfg.weno_lambda, 1.0))
+        nxy = tb.nodal_xy(M)
+        self.nod_xi, self.nod_eta = _t(nxy[:, 0]), _t(nxy[:, 1])
+        self.psi_nodes = _t(tb.eval_psi(M, nxy[:, 0], nxy[:, 1]))
+        nt = tb.nodal_tables(M)
+        _, tm = tb.time_matrices(M)
+        self.At, self.Bt, self.Dt = _t(tm["At"]), _t(tm["Bt"]), _t(tm["Dt"])
+        self.Dxi, self.Deta = _t(nt["Dxi"]), _t(nt["Deta"])
+        self.edge_tab = _t(nt["edge"])
+        self.amean = _t(nt["amean"])
+        self.vtx = torch.as_tensor(tb.vertex_node_index(M), dtype=torch.long)
+        self.Iq = _t(tb.lagrange_time_integral(M, 0.0, 1.0))  # time averages over [0, 1]
+        # node rings and slip walls
+        ring = [(k, j, lv) for k in range(self.NV) for (j, lv) in topo.ring[k]]
+        self.r_node = torch.as_tensor([r[0] for r in ring], dtype=torch.long)
+        self.r_elem = torch.as_tensor([r[1] for r in ring], dtype=torch.long)
+        self.r_lv = torch.as_tensor([r[2] for r in ring], dtype=torch.long)
+        wn, pin = wall_constraints(topo, np.asarray(nodes, float))
+        self.wall_n = _t(wn)
+        self.wall_free = _t((~pin).astype(float))
+        # edges
+        en = topo.edge_nodes
+        self.ea = torch.as_tensor(en[:, 0], dtype=torch.long)
+        self.eb = torch.as_tensor(en[:, 1], dtype=torch.long)
+        self.L = torch.as_tensor(topo.edge_elems[:, 0], dtype=torch.long)
+        R = topo.edge_elems[:, 1]
+        self.hasR = torch.as_tensor(R >= 0)
+        self.Rs = torch.as_tensor(np.where(R >= 0, R, topo.edge_elems[:, 0]), dtype=torch.long)
+        self.el = torch.as_tensor(topo.edge_local[:, 0], dtype=torch.long)
+        self.ers = torch.as_tensor(np.where(R >= 0, topo.edge_local[:, 1], topo.edge_local[:, 0]),
+                                   dtype=torch.long)
+        self.slip = torch.as_tensor(topo.bc_tag == BC_SLIP)
+
+    def _psi(self, xi, eta):
+        mono = torch.stack([xi ** a * eta ** b for (a, b) in self.mons], dim=-1)
+        return mono @ self.psiC.T
+
+    def reconstruct(self, Q, Xe):
+        """wnod (NE, nb, 4) on the current geometry Xe (NE, 3, 2)."""
+        cfg, NE = self.cfg, self.NE
+        nb = self.psiC.shape[0]
+        ws_all = torch.zeros((NE, 7, nb, 4), dtype=_F64)
+        sig_all = torch.zeros((NE, 7, 4), dtype=_F64)
+        for s in range(7):
+            idx_np = np.nonzero(self.valid[:, s])[0]
+            if idx_np.size == 0:
+                continue
+            idx = torch.as_tensor(idx_np, dtype=torch.long)
+            js = torch.as_tensor(self.sten[idx_np, s], dtype=torch.long)        # (n, ne)
+            Xst = Xe[js]                                                          # (n, ne, 3, 2)
+            xq = _affine_map_t(Xst, self.qu, self.qv)                             # (n, ne, P, 2)
+            Xii = Xe[idx][:, None].expand_as(Xst)
+            xi, eta = _affine_inverse_t(Xii, xq)
+            A = torch.einsum("njpl,p->njl", self._psi(xi, eta), self.qw)         # (n, ne, nb)
+            c = A[:, 0, :]
+            Qi = Q[idx]
+            b = Q[js]                                                             # (n, ne, 4)
+            Ar = A[:, 1:, 1:] - A[:, 1:, :1] * (c[:, None, 1:] / c[:, None, :1])
+            br = b[:, 1:, :] - A[:, 1:, :1] * (Qi[:, None, :] / c[:, None, :1])
+            Qf, Rf = torch.linalg.qr(Ar)
+            rest = torch.linalg.solve_triangular(Rf, Qf.transpose(1, 2) @ br, upper=True)
+            w0 = (Qi - torch.einsum("nk,nkv->nv", c[:, 1:], rest)) / c[:, :1]
+            ws = torch.cat([w0[:, None, :], rest], dim=1)                         # (n, nb, 4)
+            sig = torch.einsum("nlv,lm,nmv->nv", ws, self.Sig, ws)
+            ws_all = ws_all.index_put((idx, torch.full_like(idx, s)), ws)
+            sig_all = sig_all.index_put((idx, torch.full_like(idx, s)), sig)
+        valid = torch.as_tensor(self.valid)
+        if cfg.weno_shared:
+            sig_all = sig_all.sum(dim=2, keepdim=True).expand(-1, -1, 4)
+        wt = self.lam[None, :, None] / (sig_all + cfg.weno_eps) ** cfg.weno_r
+        wt = torch.where(valid[:, :, None], wt, torch.zeros((), dtype=_F64))
+        omega = wt / wt.sum(dim=1, keepdim=True)
+        what = torch.einsum("nsv,nslv->nlv", omega, ws_all)
+        return torch.einsum("ml,nlv->nmv", self.psi_nodes, what)
+
+    def predict(self, wnod, Xe, dt):
+        """Space-time predictor with the mesh moving at the fluid velocity:
+        traces (NE, 3, nG, T, 4), means (NE, T, 4), vertex velocities (NE, 3, T, 2)."""
+        M, cfg = self.M, self.cfg
+        T = M + 1
+        q = wnod[:, :, None, :].expand(-1, -1, T, -1)
+        x0 = _affine_map_t(Xe, self.nod_xi, self.nod_eta)                        # (NE, nb, 2)
+        x = x0[:, :, None, :].expand(-1, -1, T, -1)
+        d = lambda D, a: torch.einsum("km,nmtv->nktv", D, a)   # noqa: E731
+        for _ in range(cfg.npic):
+            V = q[..., 1:3] / q[..., 0:1]
+            xu = self.Bt[None, None, :, None] * x[:, :, 0:1, :] + dt * torch.einsum("qr,nmrc->nmqc", self.At, V)
+            x = torch.cat([x[:, :, 0:1, :], xu], dim=2)
+            x_xi, x_eta = d(self.Dxi, x), d(self.Deta, x)
+            x_tau = torch.einsum("pq,nmqc->nmpc", self.Dt, x)
+            det = x_xi[..., 0] * x_eta[..., 1] - x_eta[..., 0] * x_xi[..., 1]
+            xi_x, xi_y = x_eta[..., 1] / det, -x_eta[..., 0] / det
+            eta_x, eta_y = -x_xi[..., 1] / det, x_xi[..., 0] / det
+            xt, yt = x_tau[..., 0] / dt, x_tau[..., 1] / dt
+            xi_t = -(xi_x * xt + xi_y * yt)
+            eta_t = -(eta_x * xt + eta_y * yt)
+            f, g = flux_fg(q, cfg.gamma)
+            P = -(d(self.Dxi, q) * xi_t[..., None] + d(self.Deta, q) * eta_t[..., None]
+                  + d(self.Dxi, f) * xi_x[..., None] + d(self.Deta, f) * eta_x[..., None]
+                  + d(self.Dxi, g) * xi_y[..., None] + d(self.Deta, g) * eta_y[..., None])
+            qu = self.Bt[None, None, :, None] * q[:, :, 0:1, :] + dt * torch.einsum("qr,nmrv->nmqv", self.At, P)
+            q = torch.cat([q[:, :, 0:1, :], qu], dim=2)
+        V = q[..., 1:3] / q[..., 0:1]
+        return (torch.einsum("egm,nmtv->negtv", self.edge_tab, q),
+                torch.einsum("m,nmtv->ntv", self.amean, q), V[:, self.vtx])
+
+    def move_nodes(self, X, Q, A, vvel, dt):
+        """New node positions: mass-weighted (rho |T|) mean over each node's ring
+        of the vertex velocities averaged over [0, 1]; slip-wall nodes slide."""
+        vbar = torch.einsum("q,rqc->rc", self.Iq, vvel[self.r_elem, self.r_lv])
+        mu = (Q[:, 0] * A)[self.r_elem]
+        num = torch.zeros((self.NV, 2), dtype=_F64).index_add(0, self.r_node, mu[:, None] * vbar)
+        den = torch.zeros(self.NV, dtype=_F64).index_add(0, self.r_node, mu)
+        V = num / den[:, None]
+        V = (V - (V * self.wall_n).sum(dim=1, keepdim=True) * self.wall_n) * self.wall_free[:, None]
+        return X + dt * V
+
+    def fluxes(self, X, Xn, trace, avg, dt):
+        M, cfg = self.M, self.cfg
+        nG = M + 1
+        chi, wc = tb.gauss_legendre01(nG)
+        NF = self.ea.shape[0]
+        z = torch.zeros((NF, 1), dtype=_F64)
+        P1 = torch.cat([X[self.ea], z], 1)
+        P2 = torch.cat([X[self.eb], z], 1)
+        P3 = torch.cat([Xn[self.eb], z + dt], 1)
+        P4 = torch.cat([Xn[self.ea], z + dt], 1)
+        trL = trace[self.L, self.el]
+        trR = trace[self.Rs, self.ers]
+        avL = avg[self.L]
+        G = torch.zeros((NF, 4), dtype=_F64)
+        for g in range(nG):
+            for h in range(nG):
+                c, t = float(chi[g]), float(chi[h])
+                dchi = (1 - t) * (P2 - P1) + t * (P3 - P4)
+                dtau = (1 - c) * (P4 - P1) + c * (P3 - P2)
+                N = torch.linalg.cross(dchi, dtau, dim=-1)
+                lt = _t(tb.lagrange_time(M, np.array([t]))[0])
+                ql = torch.einsum("q,eqv->ev", lt, trL[:, g])
+                qrr = torch.einsum("q,eqv->ev", lt, trR[:, nG - 1 - g])
+                qr = torch.where(self.slip[:, None], mirror(ql, N), torch.einsum("q,eqv->ev", lt, avL))
+                qr = torch.where(self.hasR[:, None], qrr, qr)
+                G = G + (wc[g] * wc[h]) * FLUX_FUNCTIONS[cfg.flux](ql, qr, N, cfg.gamma)
+        return G
+
+    def __call__(self, Q, X, dt):
+        """(Q^{n+1}, X^{n+1}) from (Q^n, X^n) for the fixed step dt."""
+        Xe = X[self.tris]
+        A = _tri_area_t(Xe)
+        trace, avg, vvel = self.predict(self.reconstruct(Q, Xe), Xe, dt)
+        Xn = self.move_nodes(X, Q, A, vvel, dt)
+        G = self.fluxes(X, Xn, trace, avg, dt)
+        flux = torch.zeros_like(Q).index_add(0, self.L, G)
+        flux = flux.index_add(0, self.Rs[self.hasR], -G[self.hasR])
+        An = _tri_area_t(Xn[self.tris])
+        return (A[:, None] * Q - flux) / An[:, None], Xn
+
+    def vjp(self, Q, X, dt, Qbar_next, Xbar_next):
+        """Adjoints (Qbar, Xbar) of (Q^n, X^n) for (Qbar_next, Xbar_next) of
+        (Q^{n+1}, X^{n+1}); NumPy in and out."""
+        q = _t(Q).requires_grad_(True)
+        x = _t(X).requires_grad_(True)
+        qn, xn = self(q, x, dt)
+        gq, gx = torch.autograd.grad((qn, xn), (q, x), (_t(Qbar_next), _t(Xbar_next)))
+        return gq.detach().numpy(), gx.detach().numpy()
+
+    def step(self, Q, X, dt):
+        with torch.no_grad():
+            qn, xn = self(_t(Q), _t(X), dt)
+        return qn.numpy(), xn.numpy()

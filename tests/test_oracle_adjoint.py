@@ -1,5 +1,5 @@
 """Pins of the reverse-mode oracle (oracle/adjoint.py): one global time step on
-a fixed mesh with dt held fixed.  The torch forward map must equal the NumPy
+a fixed mesh, and one with the mesh moving with the fluid, with dt held fixed.  The torch forward map must equal the NumPy
 oracle's step, its vector-Jacobian product must match central differences of
 the NumPy oracle's step, and the adjoint of the conserved totals must be the
 element areas wherever the boundary flux cannot reach (conservation of the
@@ -113,3 +113,77 @@ def test_hll_forward_and_vjp(name, M):
     fd = ((F(Q0 + h * v) - F(Q0 - h * v)) * qb).sum() / (2 * h)
     ad = (g * v).sum()
     assert abs(fd - ad) <= 1e-6 * np.abs(g * v).sum(), (fd, ad)
+
+
+# ---------------------------------------------------------------------------
+# Lagrangian step: (Q, X) -> (Q', X'), the mesh moving with the fluid
+# ---------------------------------------------------------------------------
+def _setup_lagrangian(name, M, flux="rusanov"):
+    from oracle.adjoint import LagrangianStep
+    mesh, Q0 = _case(name, M)
+    cfg = Config(M=M, levels=1, mesh_velocity="lagrangian", flux=flux)
+    o = GTSSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+    dt = 0.5 * float(o.dtcfl.min())
+    st = LagrangianStep(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+    return mesh, Q0, cfg, o, dt, st
+
+
+LAGR_CASES = [("vortex", 1), ("vortex", 2), ("vortex", 3), ("sod", 2), ("explosion", 2)]
+
+
+@pytest.mark.parametrize("name,M", LAGR_CASES)
+def test_lagrangian_forward_equals_numpy_step(name, M):
+    """The torch Lagrangian step (reconstruction on the moving geometry,
+    predictor with the mesh ODE, node solver, moving patches, new areas)
+    equals the NumPy oracle's global step: averages and node positions."""
+    mesh, Q0, cfg, o, dt, st = _setup_lagrangian(name, M)
+    Q1, X1 = st.step(Q0, mesh.nodes, dt)
+    o.step(dt)
+    assert o.T == dt
+    assert np.abs(Q1 - o.Q).max() <= 1e-14 * np.abs(o.Q).max()
+    assert np.abs(X1 - o.X).max() <= 1e-14 * np.abs(o.X).max()
+    assert np.abs(X1 - mesh.nodes).max() > 1e-6 * np.ptp(mesh.nodes)       # the mesh moved
+
+
+@pytest.mark.parametrize("name,M", [("vortex", 1), ("vortex", 2), ("explosion", 2)])
+def test_lagrangian_vjp_matches_central_differences(name, M):
+    """<(Qbar, Xbar), (F(Q+hv, X+hy) - F(Q-hv, X-hy)) / 2h> of the NumPy step
+    (topology held) against the vector-Jacobian product, with directions in
+    both the averages and the node positions, and in each alone."""
+    mesh, Q0, cfg, o, dt, st = _setup_lagrangian(name, M)
+    rng = np.random.default_rng(1)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    gq, gx = st.vjp(Q0, mesh.nodes, dt, qb, xb)
+
+    def F(Q, X):
+        s = GTSSolver(X, mesh.tris, Q, cfg, bedges=mesh.bedges, topo=o.topo)
+        s.step(dt)
+        return s.Q, s.X
+
+    h = 1e-8
+    hx = h * np.ptp(mesh.nodes) * 1e-1
+    for k, (wq, wx) in enumerate(((1, 1), (1, 0), (0, 1))):
+        v = wq * rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=0)
+        y = wx * rng.standard_normal(mesh.nodes.shape) * hx / h
+        Qp, Xp = F(Q0 + h * v, mesh.nodes + h * y)
+        Qm, Xm = F(Q0 - h * v, mesh.nodes - h * y)
+        fd = (((Qp - Qm) * qb).sum() + ((Xp - Xm) * xb).sum()) / (2 * h)
+        ad = (gq * v).sum() + (gx * y).sum()
+        scale = np.abs(gq * v).sum() + np.abs(gx * y).sum()
+        assert abs(fd - ad) <= 1e-6 * scale, (k, fd, ad)
+
+
+@pytest.mark.parametrize("name,M", [("vortex", 2), ("explosion", 2)])
+def test_lagrangian_adjoint_of_a_translation(name, M):
+    """Moving every node by the same vector c leaves the averages unchanged and
+    moves every new node by c (translation invariance of the scheme), so for
+    any (Qbar, Xbar) the node-position adjoints sum to the sum of Xbar."""
+    mesh, Q0, cfg, o, dt, st = _setup_lagrangian(name, M)
+    rng = np.random.default_rng(2)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    _, gx = st.vjp(Q0, mesh.nodes, dt, qb, xb)
+    scale = np.abs(gx).sum(axis=0)
+    assert np.abs(gx.sum(axis=0) - xb.sum(axis=0)).max() <= 1e-12 * scale.max()
+    assert np.abs(gx - xb).max() > 1e-3 * np.abs(xb).max()        # the geometry does act
