@@ -41,20 +41,25 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X, published
 PEAK_HBM_GBS = 8000.0              # MI355X HBM3E, published
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in ("kernels.hip", "basis.h")]
 
-# HBM bytes per unit of work (element reconstruction, element predictor) for
-# each persistent-grid setting of the list-driven kernels (workgroups per CU;
-# 0 = one grid over all elements): the rocprofv3 FETCH_SIZE and WRITE_SIZE of
-# the profiled LTS pass's launches on the 80k vortex mesh at M=2, scaled by
-# what the same counters read for a plain 256 MiB copy, divided by the units
-# those launches processed. Valid only for the kernel code they were taken on
+# HBM bytes per unit of work of the step kernels for each persistent-grid
+# setting of the list-driven kernels (workgroups per CU; 0 = one grid over all
+# elements): the rocprofv3 FETCH_SIZE and WRITE_SIZE of the profiled LTS pass's
+# launches on the 400k explosion mesh at M=2 (4 levels), scaled by what the
+# same counters read for a plain 256 MiB copy, divided by the units those
+# launches processed (element updates; patches; moved nodes; for the scheduler
+# the elements of the mesh). Valid only for the kernel code they were taken on
 # (sha256 of kernels.hip and basis.h with comments and whitespace removed);
 # otherwise traffic is reported null.
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
-    "workload": "vortex",
-    "source_sha256": "af222f0b42f0bef0bc488d56df19b0b22216c7f92e8bd81106a6dd35823bd528",
-    "k_reconstruct": {0: 1454, 4: 1405, 8: 1386, 16: 1325, 32: 1397},
-    "k_predict": {0: 1499, 4: 1501, 8: 1499, 16: 1499, 32: 1498},
+    "workload": "explosion",
+    "source_sha256": "246c43c9813b7607fe8a8b66dfb586c4c1aea03f4754e86c52e692fd4e9f8ec3",
+    "k_reconstruct": {0: 1581, 4: 1617, 8: 1595, 16: 1586, 32: 1582},
+    "k_predict": {0: 1499, 4: 1499, 8: 1499, 16: 1499, 32: 1499},
+    "k_patch": {w: 1046 for w in TRAFFIC_SWEEP},
+    "k_update": {w: 728 for w in TRAFFIC_SWEEP},
+    "k_node": {w: 1776 for w in TRAFFIC_SWEEP},
+    "k_sched": {w: 89 for w in TRAFFIC_SWEEP},
 }
 
 
@@ -564,7 +569,7 @@ def main():
     def hbm_rate(k, bytes_key):
         per = UNIT_WORK[bytes_key][a.M]
         r = rate_entry(per, units[k], kt[k][0], kt[k][1], PEAK_HBM_GBS, 1e9)
-        return dict(r, unit="GB/s", bytes_per_unit=per)
+        return dict(r, unit="GB/s", bytes_per_unit=per, traffic=traffic(kname[k], r["units_per_launch"]))
 
     total_ms = sum(v[0] for v in kt.values())
     dom = max(("recon", "predict"), key=lambda k: kt[k][0])
