@@ -271,6 +271,40 @@ int ader_adjoint_gts_step(ader_ctx* ctx, double dt, const double* Q_dev, const d
 int ader_adjoint_gts_step_static(ader_ctx* ctx, double dt, const double* Q_dev,
                                  const double* Qbar_next_dev, double* Qbar_dev);
 
+/* ---- Adjoint of one global step on the moving (Lagrangian) mesh ----------
+ * The step map (Q^n, X^n) -> (Q^{n+1}, X^{n+1}) of global time stepping of
+ * length dt with the mesh moving with the fluid (mesh_velocity = 0, V = v in
+ * eq. ODEmesh) and the Rusanov flux: reconstruction on the current geometry
+ * (eqs. intConsRec .. eqn.weno), predictor of the PDE and the mesh ODE (eqs.
+ * CGfinal, VCG, newVertPos), node solver with mass weights rho |T| and the
+ * velocities averaged over the step (eqs. eqnNScs, eqn.NScs.weights,
+ * NodesVel, eqn.newVertex), fluxes over the bilinear space-time patches of
+ * the moving edges (eqs. eqn.spacetimenodes, G_ij, eqn.STint) and the update
+ * with the new areas (eq. PDEfinal).  Writes Qbar = (dQ^{n+1}/dQ^n)^T Qbar_next
+ * + (dX^{n+1}/dQ^n)^T Xbar_next and Xbar likewise with respect to X^n, dt held
+ * fixed; subgradients as for ader_adjoint_gts_step.  Optionally also the
+ * forward result.  It does not change the simulation state.
+ *   Q_dev: device [4][n_elems] SoA averages Q^n, or NULL for the context's;
+ *   X_dev: device [n_nodes][2] node positions X^n, or NULL for the context's
+ *     (NULL for either: every element must be at one common time);
+ *   Qbar_next_dev, Qbar_dev: device [4][n_elems] SoA;
+ *   Xbar_next_dev, Xbar_dev: device [n_nodes][2];
+ *   Q_next_dev ([4][n_elems]), X_next_dev ([n_nodes][2]): device buffers for
+ *     (Q^{n+1}, X^{n+1}), or NULL;
+ *   work_dev: caller device memory of at least
+ *     ader_adjoint_lagrangian_workspace_size bytes, 256-byte aligned, scratch
+ *     of the call only.  No output may overlap an input.
+ * ADER_E_ARG for another mesh velocity or flux, slip-wall edges, a batch of
+ * instances, a workspace too small; ADER_E_ORDER before a state upload.
+ * Queued on the context's stream; no synchronisation.  With dt at most the
+ * smallest CFL step, the step that ader_step_gts(ctx, t + dt, 1, ...) takes
+ * from the same state is the one differentiated. */
+int ader_adjoint_lagrangian_workspace_size(const ader_ctx* ctx, size_t* bytes);
+int ader_adjoint_lagrangian_step(ader_ctx* ctx, double dt, const double* Q_dev, const double* X_dev,
+                                 const double* Qbar_next_dev, const double* Xbar_next_dev, double* Qbar_dev,
+                                 double* Xbar_dev, double* Q_next_dev, double* X_next_dev, void* work_dev,
+                                 size_t work_bytes);
+
 /* Current state into caller device buffers (any may be NULL):
  * Q_dev [4][n_elems] SoA, node_xy_dev [n_nodes][2], elem_t_dev [n_elems]. */
 int ader_download_state(ader_ctx* ctx, double* Q_dev, double* node_xy_dev, double* elem_t_dev);

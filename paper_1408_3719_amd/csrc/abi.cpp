@@ -1151,6 +1151,49 @@ int ader_adjoint_gts_step_static(ader_ctx* c, double dt, const double* Q_dev, co
   return ADER_OK;
 }
 
+int ader_adjoint_lagrangian_workspace_size(const ader_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return ADER_E_ARG;
+  if (!c->has_mesh) return ADER_E_ORDER;
+  *bytes = aw::lagadj_work_bytes(c->cfg.M, c->topo.NE, c->topo.NV, c->topo.NF, c->prm.npic);
+  return ADER_OK;
+}
+
+int ader_adjoint_lagrangian_step(ader_ctx* c, double dt, const double* Q_dev, const double* X_dev,
+                                 const double* Qbar_next_dev, const double* Xbar_next_dev, double* Qbar_dev,
+                                 double* Xbar_dev, double* Q_next_dev, double* X_next_dev, void* work_dev,
+                                 size_t work_bytes) {
+  if (!c || !Qbar_next_dev || !Xbar_next_dev || !Qbar_dev || !Xbar_dev || !work_dev) return ADER_E_ARG;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, ADER_E_ARG, "dt must be positive and finite");
+  if (c->cfg.mesh_velocity != 0)
+    return fail(c, ADER_E_ARG, "the moving-mesh adjoint needs the Lagrangian mesh (mesh_velocity = 0)");
+  if (c->cfg.flux != ADER_FLUX_RUSANOV) return fail(c, ADER_E_ARG, "the moving-mesh adjoint covers the Rusanov flux");
+  if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the adjoint runs on a single instance");
+  for (int e = 0; e < c->topo.NF; ++e)
+    if (c->topo.e_bc[e] == 2) return fail(c, ADER_E_ARG, "the moving-mesh adjoint does not cover slip walls");
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  if ((!Q_dev || !X_dev) && !c->synced)
+    return fail(c, ADER_E_ORDER, "elements are not at a common time (macro step in progress)");
+  const size_t need = aw::lagadj_work_bytes(c->cfg.M, c->topo.NE, c->topo.NV, c->topo.NF, c->prm.npic);
+  if (work_bytes < need) return fail(c, ADER_E_ARG, "adjoint workspace too small");
+  if ((reinterpret_cast<uintptr_t>(work_dev) & 255) != 0)
+    return fail(c, ADER_E_ARG, "adjoint workspace must be 256-byte aligned");
+  aw::LagWork w{};
+  aw::lagadj_carve(c->cfg.M, c->topo.NE, c->topo.NV, c->topo.NF, c->prm.npic, static_cast<char*>(work_dev), w);
+  w.a.q = Q_dev;
+  w.a.qbar_next = Qbar_next_dev;
+  w.a.qbar = Qbar_dev;
+  w.x = X_dev;
+  w.xbar_next = Xbar_next_dev;
+  w.xbar = Xbar_dev;
+  w.qnext = Q_next_dev;
+  w.xnext = X_next_dev;
+  LCHK(c, timed(c, ADER_K_ADJOINT, c->stream, [&] {
+    return aw::launch_adjoint_lagrangian(c->dev, c->prm, c->cfg.M, w, dt, Q_dev == nullptr, X_dev == nullptr,
+                                         c->stream);
+  }));
+  return ADER_OK;
+}
+
 int ader_set_schedule_replay(ader_ctx* c, const int32_t* step_ptr, const int32_t* steps, int64_t n_steps) {
   if (!c) return ADER_E_ARG;
   if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");

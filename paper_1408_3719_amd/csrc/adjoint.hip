@@ -41,6 +41,7 @@
 #include "aderweno.h"
 #include "basis.h"
 #include "common.h"
+#include "lagadj.h"
 
 namespace aw {
 
@@ -310,45 +311,75 @@ __global__ void __launch_bounds__(TPB) k_adj_state(Dev d, AdjWork w) {
 // qbar_j = qbar_next_j + own terms of j (row 0, 8 lanes) + rows naming j.
 // 8 lanes per element: lane s takes own slot s and every 8th naming row, two
 // rows in flight; a butterfly sums the lanes (a fixed order: deterministic).
-template <int M>
+// GEO: the same for the vertex adjoints of the rows, added to xeb_j.
+template <int M, bool GEO = false>
 __global__ void __launch_bounds__(TPB) k_adj_gather(Dev d, AdjWork w) {
+  constexpr int NA = GEO ? 10 : 4;
   const int NE = d.NE;
   const int sl = threadIdx.x & 7;
   const int ngroups = (gridDim.x * blockDim.x) >> 3;
   for (int j = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; j < NE; j += ngroups) {
-    const double* own = w.rowbar + (size_t(j) * AZ<M>::ne * 8 + sl) * 4;
-    double acc[4];
+    double acc[NA];
+    auto add = [&](size_t slot) {
+      const double* r = w.rowbar + slot * 4;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = own[v];
+      for (int v = 0; v < 4; ++v) acc[v] += r[v];
+      if (GEO) {
+        const double* x = w.xrow + slot * 6;
+#pragma unroll
+        for (int k = 0; k < NA - 4; ++k) acc[4 + k] += x[k];
+      }
+    };
+#pragma unroll
+    for (int v = 0; v < NA; ++v) acc[v] = 0.0;
+    add(size_t(j) * AZ<M>::ne * 8 + sl);
     const int k1 = d.tsten_ptr[j + 1];
     int k = d.tsten_ptr[j] + sl;
     for (; k + 8 < k1; k += 16) {
-      const double* r0 = w.rowbar + size_t(d.tsten_idx[k]) * 4;
-      const double* r1 = w.rowbar + size_t(d.tsten_idx[k + 8]) * 4;
-      double a0[4], a1[4];
+      const size_t s0 = size_t(d.tsten_idx[k]), s1 = size_t(d.tsten_idx[k + 8]);
+      double a0[NA], a1[NA];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        a0[v] = r0[v];
-        a1[v] = r1[v];
+        a0[v] = w.rowbar[s0 * 4 + v];
+        a1[v] = w.rowbar[s1 * 4 + v];
+      }
+      if (GEO) {
+#pragma unroll
+        for (int v = 4; v < NA; ++v) {
+          a0[v] = w.xrow[s0 * 6 + v - 4];
+          a1[v] = w.xrow[s1 * 6 + v - 4];
+        }
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] += a0[v] + a1[v];
+      for (int v = 0; v < NA; ++v) acc[v] += a0[v] + a1[v];
     }
-    if (k < k1) {
-      const double* r0 = w.rowbar + size_t(d.tsten_idx[k]) * 4;
+    if (k < k1) add(size_t(d.tsten_idx[k]));
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] += r0[v];
-    }
+    for (int v = 0; v < NA; ++v) acc[v] = group8_sum(acc[v]);
+    double mine = acc[0];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = group8_sum(acc[v]);
-    const double mine = sl == 0 ? acc[0] : sl == 1 ? acc[1] : sl == 2 ? acc[2] : acc[3];
+    for (int v = 1; v < NA; ++v)
+      if (sl == v) mine = acc[v];
     if (sl < 4) w.qbar[size_t(sl) * NE + j] = w.qbar_next[size_t(sl) * NE + j] + mine;
+    if (GEO) {
+      // lanes 0..5 hold the vertex sums in acc[4 + lane]
+      double xm = acc[4];
+#pragma unroll
+      for (int v = 1; v < 6; ++v)
+        if (sl == v) xm = acc[4 + v];
+      if (sl < 6) w.xeb[size_t(j) * 6 + sl] += xm;
+    }
   }
 }
 
 // Reconstruction (REV = false: write the nodal values) or its adjoint (REV =
-// true: read their adjoint, add to qbar). 8 lanes per element.
-template <int M, bool REV>
+// true: read their adjoint, add to qbar). 8 lanes per element. GEO: the rows
+// depend on vertices that are differentiated too (a moving mesh): with w = the
+// least-squares solution, z = (A^T A)^-1 wbar and the residual r_c = b_c - a_c w,
+// the adjoint of row a_c is sum over the variables of r_c z - (a_c . z) w, pulled
+// back to the vertices of the stencil element (its slot) and of element i
+// (row 0 of the lane).
+template <int M, bool REV, bool GEO = false>
 __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restrict__ tb, Params P,
                                                    AdjWork w) {
   using S = AZ<M>;
@@ -356,11 +387,13 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
   const int NE = d.NE;
   const int sl = threadIdx.x & 7;
   const int ngroups = (gridDim.x * blockDim.x) >> 3;
+  const double* gbase = w.geo ? w.geo : d.rec + XE;
+  const size_t gs = w.geo ? size_t(w.geo_stride) : size_t(S::RS);
   for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < NE; i += ngroups) {
-    const double* ri = d.rec + size_t(i) * S::RS;
+    const double* ri = gbase + size_t(i) * gs;
     double Xi[6], Qi[4];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Xi[c] = ri[XE + c];
+    for (int c = 0; c < 6; ++c) Xi[c] = ri[c];
 #pragma unroll
     for (int v = 0; v < 4; ++v) Qi[v] = w.q[size_t(v) * NE + i];
     const double e1x = Xi[2] - Xi[0], e1y = Xi[3] - Xi[1];
@@ -400,9 +433,9 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         for (int v = 0; v < 4; ++v) z[a][v] = 0.0;
 #pragma unroll 1
       for (int c = 1; c < ne; ++c) {
-        const double* rj = d.rec + size_t(sidx[c * NE]) * S::RS;
+        const double* rj = gbase + size_t(sidx[c * NE]) * gs;
         double a[nu], b[4];
-        ls_row<M>(rj + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
+        ls_row<M>(rj, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
         for (int v = 0; v < 4; ++v) b[v] = w.q[size_t(v) * NE + sidx[c * NE]] - Qi[v];
 #pragma unroll
@@ -507,6 +540,11 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
     if (!valid) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) rb[v] = sl == 7 ? q0b[v] : 0.0;
+      if (GEO) {
+        double* xo = w.xrow + (size_t(i) * ne * 8 + sl) * 6;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) xo[c] = 0.0;
+      }
       continue;
     }
     // weights: om_s = lambda_s / (sigma_s + eps)^8, W = sum om_s w_s / sum om_s
@@ -547,11 +585,13 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
       }
     // right-hand sides b_c = Q_j - Q_i: their adjoints are a_c . u
     double sumb[4] = {0.0, 0.0, 0.0, 0.0};
+    double Xib[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int c = 1; c < ne; ++c) {
       const int j = sidx[c * NE];
-      double a[nu];
-      ls_row<M>(d.rec + size_t(j) * S::RS + XE, Xi, e1x, e1y, e2x, e2y, idet, a);
+      const double* Xj = gbase + size_t(j) * gs;
+      double a[nu], bb[4];
+      ls_row<M>(Xj, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double t = 0.0;
@@ -559,10 +599,35 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         for (int l = 0; l < nu; ++l) t += a[l] * u[l][v];
         rb[c * RB + v] = t;
         sumb[v] += t;
+        bb[v] = t;
+      }
+      if (GEO) {
+        double ab[nu], xj[6], Xjb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l < nu; ++l) ab[l] = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double r = w.q[size_t(v) * NE + j] - Qi[v];
+#pragma unroll
+          for (int l = 0; l < nu; ++l) r -= a[l] * ws[l][v];
+#pragma unroll
+          for (int l = 0; l < nu; ++l) ab[l] += r * u[l][v] - bb[v] * ws[l][v];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) xj[k] = Xj[k];
+        lag::ls_row_geom_vjp<M>(xj, Xi, ab, Xjb, Xib);
+        double* xo = w.xrow + ((size_t(i) * ne + c) * 8 + sl) * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) xo[k] = Xjb[k];
       }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) rb[v] = -sumb[v];
+    if (GEO) {
+      double* xo = w.xrow + (size_t(i) * ne * 8 + sl) * 6;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) xo[k] = Xib[k];
+    }
   }
 }
 
@@ -937,6 +1002,362 @@ __global__ void __launch_bounds__(TPB) k_adj_pred_rev(Dev d, const Tables* __res
   }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of one global step with the mesh moving with the fluid (V = v in eq.
+// ODEmesh): (Q^n, X^n) -> (Q^{n+1}, X^{n+1}) for a fixed dt. Forward:
+// reconstruction on the current geometry, the predictor of the PDE and the
+// mesh ODE (eqs. CGfinal, VCG, newVertPos), the node solver (eqs. eqnNScs,
+// eqn.NScs.weights, NodesVel, eqn.newVertex over the whole step), the fluxes
+// over the bilinear space-time patches of the moving edges (eqs.
+// eqn.spacetimenodes, G_ij, eqn.STint) and the update with the new areas (eq.
+// PDEfinal). Reverse, each sum in a fixed order (no atomics): patch adjoints
+// per edge; update adjoints per element; node solver adjoints per node, into
+// (element, vertex) slots; predictor in reverse per element; reconstruction
+// in reverse with row slots; gathers per element and per node.
+// ---------------------------------------------------------------------------
+
+// The edges of node k, each once: those of the ring elements j at local edges
+// lv (node = a) and lv + 2 (node = b) of which j is the left element.
+template <class F>
+__device__ inline void node_edges(const Dev& d, int k, F f) {
+  const int NE = d.NE;
+  for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+    const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+    const int ea = d.elem_edges[lv * NE + j], eb = d.elem_edges[((lv + 2) % 3) * NE + j];
+    if (d.e_L[ea] == j) f(ea, 0);
+    if (d.e_L[eb] == j) f(eb, 1);
+  }
+}
+
+// Positions (from the caller or the context) and averages, vertices, areas.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_geom(Dev d, LagWork w, int x_from_ctx, int q_from_ctx) {
+  const int NE = d.NE, NV = d.NV;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV && x_from_ctx; k += gridDim.x * blockDim.x) {
+    w.xcopy[2 * k] = d.X[k];
+    w.xcopy[2 * k + 1] = d.X[NV + k];
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    if (q_from_ctx) {
+      const double* r = d.rec + size_t(i) * AZ<M>::RS;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) w.a.qcopy[size_t(v) * NE + i] = r[QO + v];
+    }
+    const double* X = x_from_ctx ? nullptr : w.x;
+    double xe[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int n = d.tri[c * NE + i];
+      xe[2 * c] = X ? X[2 * n] : d.X[n];
+      xe[2 * c + 1] = X ? X[2 * n + 1] : d.X[NV + n];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w.xe[size_t(i) * 6 + c] = xe[c];
+    w.area[i] = lag::area3(xe);
+  }
+}
+
+// Predictor with the mesh ODE, every iterate kept; traces, means, vertex velocities.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __restrict__ tb, Params P,
+                                                      LagWork w, double dt) {
+  using S = AZ<M>;
+  const int NE = d.NE;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    double xe[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) xe[c] = w.xe[size_t(i) * 6 + c];
+    lag::pred_fwd<M>(*tb, P.gamma, P.npic, w.a.wnod + size_t(i) * S::WS, xe, dt, w.keep + i, size_t(NE),
+                     w.a.trace + size_t(i) * S::TS, w.a.avg + size_t(i) * S::T * 4,
+                     w.vvel + size_t(i) * 6 * S::T);
+  }
+}
+
+// Node solver: mass-weighted ring mean of the time-averaged vertex velocities,
+// slip walls slide and pinned nodes stay; new positions.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_node_fwd(Dev d, const Tables* __restrict__ tb, LagWork w,
+                                                      double dt) {
+  constexpr int T = M + 1;
+  const int NE = d.NE, NV = d.NV;
+  double I[T];
+  lag::tint01<M>(*tb, I);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
+    double num[2] = {0.0, 0.0}, den = 0.0;
+    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      const double* vv = w.vvel + (size_t(j) * 3 + lv) * T * 2;
+      double vb[2] = {0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        vb[0] += I[q] * vv[2 * q];
+        vb[1] += I[q] * vv[2 * q + 1];
+      }
+      const double mu = w.a.q[j] * w.area[j];
+      num[0] += mu * vb[0];
+      num[1] += mu * vb[1];
+      den += mu;
+    }
+    const double Vx = num[0] / den, Vy = num[1] / den;
+    w.vraw[2 * k] = Vx;
+    w.vraw[2 * k + 1] = Vy;
+    w.den[k] = den;
+    double Wx = Vx, Wy = Vy;
+    if (d.wall_pin[k]) {
+      Wx = Wy = 0.0;
+    } else {
+      const double nx = d.wall_n[k], ny = d.wall_n[NV + k];
+      const double vn = Vx * nx + Vy * ny;
+      Wx -= vn * nx;
+      Wy -= vn * ny;
+    }
+    const double* x = w.x + 2 * size_t(k);
+    w.xn[2 * k] = x[0] + dt * Wx;
+    w.xn[2 * k + 1] = x[1] + dt * Wy;
+  }
+  (void)NE;
+}
+
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_area_new(Dev d, LagWork w) {
+  const int NE = d.NE;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    double xe[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int n = d.tri[c * NE + i];
+      xe[2 * c] = w.xn[2 * n];
+      xe[2 * c + 1] = w.xn[2 * n + 1];
+    }
+    w.an[i] = lag::area3(xe);
+  }
+}
+
+// Per edge: the patch flux (into the two (element, edge) slots, inflow
+// positive) and its adjoint for Gbar = -Qbar'_L / |T_L'| + Qbar'_R / |T_R'|
+// onto the traces, the inner element's means (transmissive edge) and the
+// four corners.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_patch(Dev d, const Tables* __restrict__ tb, Params P, LagWork w,
+                                                   double dt) {
+  using S = AZ<M>;
+  constexpr int T = S::T, nG = S::nG, TS = S::TS, NT = nG * T * 4;
+  const int NE = d.NE, NF = d.NF;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
+    const int a = d.e_a[e], b = d.e_b[e];
+    const int L = d.e_L[e], el = d.e_el[e], R = d.e_R[e], er = d.e_er[e];
+    const bool hasR = R >= 0;
+    const double xa[2] = {w.x[2 * a], w.x[2 * a + 1]}, xb[2] = {w.x[2 * b], w.x[2 * b + 1]};
+    const double xan[2] = {w.xn[2 * a], w.xn[2 * a + 1]}, xbn[2] = {w.xn[2 * b], w.xn[2 * b + 1]};
+    const double* trL = w.a.trace + size_t(L) * TS + el * NT;
+    const double* trR = hasR ? w.a.trace + size_t(R) * TS + er * NT : trL;
+    const double* avL = w.a.avg + size_t(L) * T * 4;
+    double G[4];
+    lag::patch_flux<M>(*tb, P.gamma, xa, xb, xan, xbn, dt, trL, trR, avL, hasR, G);
+    double Gb[4];
+    const double anL = w.an[L], anR = hasR ? w.an[R] : 1.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      w.gslot[(size_t(L) * 3 + el) * 4 + v] = -G[v];
+      Gb[v] = -w.a.qbar_next[size_t(v) * NE + L] / anL;
+      if (hasR) {
+        w.gslot[(size_t(R) * 3 + er) * 4 + v] = G[v];
+        Gb[v] += w.a.qbar_next[size_t(v) * NE + R] / anR;
+      }
+    }
+    double bL[NT], bR[NT], bA[T * 4];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) bL[k] = bR[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < T * 4; ++k) bA[k] = 0.0;
+    double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    lag::patch_flux_vjp<M>(*tb, P.gamma, xa, xb, xan, xbn, dt, trL, trR, avL, hasR, Gb, bL, bR, bA, c, c + 2,
+                           c + 4, c + 6);
+    double* oL = w.a.tbar + size_t(L) * TS + el * NT;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) oL[k] = bL[k];
+    if (hasR) {
+      double* oR = w.a.tbar + size_t(R) * TS + er * NT;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) oR[k] = bR[k];
+    } else {
+      double* aL = w.a.abar + size_t(e) * T * 4;
+#pragma unroll
+      for (int k = 0; k < T * 4; ++k) aL[k] = bA[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w.xs[size_t(e) * 8 + k] = c[k];
+  }
+}
+
+// Per element: the update Q' = (|T| Q + sum of inflows) / |T'| and the
+// adjoints of its direct inputs: Q (qdir), |T| and |T'| pulled back to the
+// old (xeb) and new (xnbe) vertices.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_update_rev(Dev d, LagWork w) {
+  const int NE = d.NE;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    const double A = w.area[i], An = w.an[i];
+    double qn[4], q[4], qb[4], Ab = 0.0, Anb = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double* g = w.gslot + size_t(i) * 12 + v;
+      q[v] = w.a.q[size_t(v) * NE + i];
+      qn[v] = (A * q[v] + ((g[0] + g[4]) + g[8])) / An;
+      qb[v] = w.a.qbar_next[size_t(v) * NE + i];
+      Ab += qb[v] * q[v] / An;
+      Anb -= qb[v] * qn[v] / An;
+      w.qdir[size_t(v) * NE + i] = (A / An) * qb[v];
+      if (w.qnext) w.qnext[size_t(v) * NE + i] = qn[v];
+    }
+    double xe[6], xne[6], g0[6] = {0, 0, 0, 0, 0, 0}, g1[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int n = d.tri[c * NE + i];
+      xe[2 * c] = w.xe[size_t(i) * 6 + 2 * c];
+      xe[2 * c + 1] = w.xe[size_t(i) * 6 + 2 * c + 1];
+      xne[2 * c] = w.xn[2 * n];
+      xne[2 * c + 1] = w.xn[2 * n + 1];
+    }
+    lag::area3_grad(xe, Ab, g0);
+    lag::area3_grad(xne, Anb, g1);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      w.a.xeb[size_t(i) * 6 + c] = g0[c];
+      w.xnbe[size_t(i) * 6 + c] = g1[c];
+    }
+  }
+}
+
+// Per node: adjoint of the new position (the caller's, the new areas, the
+// patch corners at the step end) -> that of the old position (direct part) and
+// of the ring's vertex velocities and masses, into (element, vertex) slots.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_node_rev(Dev d, const Tables* __restrict__ tb, LagWork w,
+                                                      double dt) {
+  constexpr int T = M + 1;
+  const int NV = d.NV;
+  double I[T];
+  lag::tint01<M>(*tb, I);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
+    double xb[2] = {w.xbar_next[2 * k], w.xbar_next[2 * k + 1]};
+    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      xb[0] += w.xnbe[size_t(j) * 6 + 2 * lv];
+      xb[1] += w.xnbe[size_t(j) * 6 + 2 * lv + 1];
+    }
+    node_edges(d, k, [&](int e, int isb) {
+      xb[0] += w.xs[size_t(e) * 8 + 4 + 2 * isb];
+      xb[1] += w.xs[size_t(e) * 8 + 5 + 2 * isb];
+    });
+    w.xbar[2 * k] = xb[0];
+    w.xbar[2 * k + 1] = xb[1];
+    if (w.xnext) {
+      w.xnext[2 * k] = w.xn[2 * k];
+      w.xnext[2 * k + 1] = w.xn[2 * k + 1];
+    }
+    // x' = x + dt P V, P the (symmetric) wall constraint
+    double Vb[2] = {dt * xb[0], dt * xb[1]};
+    if (d.wall_pin[k]) {
+      Vb[0] = Vb[1] = 0.0;
+    } else {
+      const double nx = d.wall_n[k], ny = d.wall_n[NV + k];
+      const double vn = Vb[0] * nx + Vb[1] * ny;
+      Vb[0] -= vn * nx;
+      Vb[1] -= vn * ny;
+    }
+    // V = num / den
+    const double den = w.den[k];
+    const double numb[2] = {Vb[0] / den, Vb[1] / den};
+    const double denb = -(numb[0] * w.vraw[2 * k] + numb[1] * w.vraw[2 * k + 1]);
+    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      const double* vv = w.vvel + (size_t(j) * 3 + lv) * T * 2;
+      double vb[2] = {0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        vb[0] += I[q] * vv[2 * q];
+        vb[1] += I[q] * vv[2 * q + 1];
+      }
+      const double mu = w.a.q[j] * w.area[j];
+      double* o = w.nslot + (size_t(j) * 3 + lv) * 3;
+      o[0] = mu * numb[0];
+      o[1] = mu * numb[1];
+      o[2] = numb[0] * vb[0] + numb[1] * vb[1] + denb;
+    }
+  }
+}
+
+// Predictor in reverse per element: adjoints of the traces, of the means
+// (transmissive edges) and of the vertex velocities -> the reconstruction's
+// nodal values and the element's vertices; the ring masses rho |T|.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __restrict__ tb, Params P,
+                                                      LagWork w, double dt) {
+  using S = AZ<M>;
+  constexpr int T = S::T;
+  const int NE = d.NE;
+  double I[T];
+  lag::tint01<M>(*tb, I);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    double ab[T * 4];
+#pragma unroll
+    for (int k = 0; k < T * 4; ++k) ab[k] = 0.0;
+#pragma unroll
+    for (int le = 0; le < 3; ++le) {
+      const int e = d.elem_edges[le * NE + i];
+      if (d.e_R[e] < 0) {
+        const double* a = w.a.abar + size_t(e) * T * 4;
+#pragma unroll
+        for (int k = 0; k < T * 4; ++k) ab[k] += a[k];
+      }
+    }
+    double vvb[3 * T * 2], mub = 0.0;
+#pragma unroll
+    for (int lv = 0; lv < 3; ++lv) {
+      const double* o = w.nslot + (size_t(i) * 3 + lv) * 3;
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        vvb[(lv * T + q) * 2] = I[q] * o[0];
+        vvb[(lv * T + q) * 2 + 1] = I[q] * o[1];
+      }
+      mub += o[2];
+    }
+    double xe[6], xb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) xe[c] = w.xe[size_t(i) * 6 + c];
+    lag::pred_rev<M>(*tb, P.gamma, P.npic, xe, dt, w.keep + i, size_t(NE), w.a.tbar + size_t(i) * S::TS, ab, vvb,
+                     w.a.wbar + size_t(i) * S::WS, xb);
+    // mu = rho |T|
+    const double A = w.area[i];
+    w.qdir[i] += mub * A;
+    lag::area3_grad(xe, mub * w.a.q[i], xb);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w.a.xeb[size_t(i) * 6 + c] += xb[c];
+  }
+}
+
+// Per node: the old position's adjoint = direct part + ring elements' vertex
+// adjoints + the patch corners at the step start.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lag_node_gather(Dev d, LagWork w) {
+  const int NV = d.NV;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
+    double xb[2] = {w.xbar[2 * k], w.xbar[2 * k + 1]};
+    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      xb[0] += w.a.xeb[size_t(j) * 6 + 2 * lv];
+      xb[1] += w.a.xeb[size_t(j) * 6 + 2 * lv + 1];
+    }
+    node_edges(d, k, [&](int e, int isb) {
+      xb[0] += w.xs[size_t(e) * 8 + 2 * isb];
+      xb[1] += w.xs[size_t(e) * 8 + 1 + 2 * isb];
+    });
+    w.xbar[2 * k] = xb[0];
+    w.xbar[2 * k + 1] = xb[1];
+  }
+}
+
 int grid_for(long n) {
   long b = (n + TPB - 1) / TPB;
   if (b < 1) b = 1;
@@ -961,6 +1382,27 @@ int adjoint_gts(const Dev& d, const Params& p, const AdjWork& w, double dt, bool
   AD_LAUNCH(k_adj_pred_rev<M>, d.NE, s, d, d.tab, p, w, dt);
   AD_LAUNCH((k_adj_recon<M, true>), 8L * d.NE, s, d, d.tab, p, w);
   AD_LAUNCH(k_adj_gather<M>, 8L * d.NE, s, d, w);
+  return 0;
+}
+
+template <int M>
+int adjoint_lagrangian(const Dev& d, const Params& p, LagWork w, double dt, bool qctx, bool xctx, void* s) {
+  if (qctx) w.a.q = w.a.qcopy;
+  if (xctx) w.x = w.xcopy;
+  AD_LAUNCH(k_lag_geom<M>, d.NE > d.NV ? d.NE : d.NV, s, d, w, int(xctx), int(qctx));
+  AD_LAUNCH((k_adj_recon<M, false, true>), 8L * d.NE, s, d, d.tab, p, w.a);
+  AD_LAUNCH(k_lag_pred_fwd<M>, d.NE, s, d, d.tab, p, w, dt);
+  AD_LAUNCH(k_lag_node_fwd<M>, d.NV, s, d, d.tab, w, dt);
+  AD_LAUNCH(k_lag_area_new<M>, d.NE, s, d, w);
+  AD_LAUNCH(k_lag_patch<M>, d.NF, s, d, d.tab, p, w, dt);
+  AD_LAUNCH(k_lag_update_rev<M>, d.NE, s, d, w);
+  AD_LAUNCH(k_lag_node_rev<M>, d.NV, s, d, d.tab, w, dt);
+  AD_LAUNCH(k_lag_pred_rev<M>, d.NE, s, d, d.tab, p, w, dt);
+  AD_LAUNCH((k_adj_recon<M, true, true>), 8L * d.NE, s, d, d.tab, p, w.a);
+  AdjWork g = w.a;
+  g.qbar_next = w.qdir;
+  AD_LAUNCH((k_adj_gather<M, true>), 8L * d.NE, s, d, g);
+  AD_LAUNCH(k_lag_node_gather<M>, d.NV, s, d, w);
   return 0;
 }
 
@@ -1008,6 +1450,97 @@ void adjoint_carve(int M, int NE, int NF, int npic, char* base, AdjWork& w) {
   w.qcopy = (double*)(base + 2 * ws + 2 * ts + sw + lq + rb);
   w.avg = (double*)(base + 2 * ws + 2 * ts + sw + lq + rb + qc);
   w.abar = w.avg + size_t(NE) * (M + 1) * 4;   // [NF][M+1][4]
+}
+
+namespace {
+// Buffers of the moving-mesh adjoint, in carve order (bytes, 256-aligned each).
+struct LagPlan {
+  size_t off[32];
+  size_t total = 0;
+  int n = 0;
+  void add(size_t bytes) {
+    off[n++] = total;
+    total += align256(bytes);
+  }
+};
+
+LagPlan lag_plan(int M, int NE, int NV, int NF, int npic) {
+  const size_t D = sizeof(double), nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, ne = 2 * nb;
+  LagPlan p;
+  p.add(4 * size_t(NE) * D);                       // 0 qcopy
+  p.add(2 * size_t(NV) * D);                       // 1 xcopy
+  p.add(6 * size_t(NE) * D);                       // 2 xe
+  p.add(size_t(NE) * D);                           // 3 area
+  p.add(size_t(NE) * D);                           // 4 an
+  p.add(2 * size_t(NV) * D);                       // 5 xn
+  p.add(2 * size_t(NV) * D);                       // 6 vraw
+  p.add(size_t(NV) * D);                           // 7 den
+  p.add(size_t(NE) * wnod_stride(M) * D);          // 8 wnod
+  p.add(size_t(NE) * wnod_stride(M) * D);          // 9 wbar
+  p.add(size_t(npic + 1) * nb * T * 4 * NE * D);   // 10 keep
+  p.add(size_t(NE) * trace_stride(M) * D);         // 11 trace
+  p.add(size_t(NE) * trace_stride(M) * D);         // 12 tbar
+  p.add(size_t(NE) * T * 4 * D);                   // 13 avg
+  p.add(size_t(NF) * T * 4 * D);                   // 14 abar
+  p.add(size_t(NE) * 3 * T * 2 * D);               // 15 vvel
+  p.add(size_t(NE) * 12 * D);                      // 16 gslot
+  p.add(size_t(NF) * 8 * D);                       // 17 xs
+  p.add(size_t(NE) * 6 * D);                       // 18 xeb
+  p.add(size_t(NE) * 6 * D);                       // 19 xnbe
+  p.add(size_t(NE) * 9 * D);                       // 20 nslot
+  p.add(4 * size_t(NE) * D);                       // 21 qdir
+  p.add(size_t(lsq_slots(M)) * 8 * NE * D);        // 22 lsq
+  p.add(ne * NE * 32 * D);                         // 23 rowbar
+  p.add(ne * NE * 48 * D);                         // 24 xrow
+  return p;
+}
+}  // namespace
+
+size_t lagadj_work_bytes(int M, int NE, int NV, int NF, int npic) {
+  return lag_plan(M, NE, NV, NF, npic).total;
+}
+
+void lagadj_carve(int M, int NE, int NV, int NF, int npic, char* base, LagWork& w) {
+  const LagPlan p = lag_plan(M, NE, NV, NF, npic);
+  auto at = [&](int k) { return reinterpret_cast<double*>(base + p.off[k]); };
+  w.a.qcopy = at(0);
+  w.xcopy = at(1);
+  w.xe = at(2);
+  w.area = at(3);
+  w.an = at(4);
+  w.xn = at(5);
+  w.vraw = at(6);
+  w.den = at(7);
+  w.a.wnod = at(8);
+  w.a.wbar = at(9);
+  w.keep = at(10);
+  w.a.sweeps = nullptr;
+  w.a.trace = at(11);
+  w.a.tbar = at(12);
+  w.a.avg = at(13);
+  w.a.abar = at(14);
+  w.vvel = at(15);
+  w.gslot = at(16);
+  w.xs = at(17);
+  w.a.xeb = at(18);
+  w.xnbe = at(19);
+  w.nslot = at(20);
+  w.qdir = at(21);
+  w.a.lsq = at(22);
+  w.a.rowbar = at(23);
+  w.a.xrow = at(24);
+  w.a.geo = w.xe;
+  w.a.geo_stride = 6;
+}
+
+int launch_adjoint_lagrangian(const Dev& d, const Params& p, int M, const LagWork& w, double dt,
+                              bool q_from_context, bool x_from_context, void* s) {
+  switch (M) {
+    case 1: return adjoint_lagrangian<1>(d, p, w, dt, q_from_context, x_from_context, s);
+    case 2: return adjoint_lagrangian<2>(d, p, w, dt, q_from_context, x_from_context, s);
+    case 3: return adjoint_lagrangian<3>(d, p, w, dt, q_from_context, x_from_context, s);
+    default: return int(hipErrorInvalidValue);
+  }
 }
 
 int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,

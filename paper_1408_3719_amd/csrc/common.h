@@ -177,6 +177,40 @@ struct AdjWork {
   double* avg;               // [NE][M+1][4] predictor cell means at the time nodes
   double* abar;              // [NF][M+1][4] their adjoints, a slot per transmissive edge
                              // (row 0: the element's own terms), summed by the gather
+  // element vertices the least squares is built on: [NE][geo_stride] from
+  // geo, or the context's records when geo is null
+  const double* geo;
+  int geo_stride;
+  double* xrow;              // [NE][ne][8][6] adjoint of the stencil element's vertices per
+                             // row (row 0: the element's own vertices), or null
+  double* xeb;               // [NE][6] adjoint of the element's vertices (gather adds rows)
+};
+
+// Scratch and arguments of the adjoint of a global step with the mesh moving
+// with the fluid (adjoint.hip). a.q / a.qbar_next / a.qbar are the averages,
+// their adjoint after and before the step; the least squares runs on xe.
+struct LagWork {
+  AdjWork a;
+  const double* x;           // [NV][2] node positions at the step start
+  const double* xbar_next;   // [NV][2] adjoint of the positions after the step
+  double* xbar;              // [NV][2] adjoint of the positions before the step
+  double* qnext;             // [4][NE] averages after the step, or null
+  double* xnext;             // [NV][2] positions after the step, or null
+  double* xcopy;             // [NV][2] copy of the context's positions
+  double* xe;                // [NE][6] element vertices
+  double* area;              // [NE] areas at the step start
+  double* an;                // [NE] areas after the step
+  double* xn;                // [NV][2] positions after the step
+  double* vraw;              // [NV][2] ring-mean velocity before the wall constraint
+  double* den;               // [NV] ring mass
+  double* keep;              // [npic+1][nb*(M+1)*4][NE] predictor iterates
+  double* vvel;              // [NE][3][M+1][2] predicted vertex velocities
+  double* gslot;             // [NE][3][4] inflow-positive patch flux per (element, edge)
+  double* xs;                // [NF][8] adjoint of the patch corners (a, b old; a, b new)
+  double* xnbe;              // [NE][6] adjoint of the element's new vertices (area)
+  double* nslot;             // [NE][3][3] per (element, vertex): adjoint of the time-averaged
+                             // vertex velocity (2) and of the ring mass (1)
+  double* qdir;              // [4][NE] adjoint of the averages not through the reconstruction
 };
 
 // Device address of the library's fixed adjoint scratch on the current GPU
@@ -184,6 +218,10 @@ struct AdjWork {
 int static_scratch(void** ptr, size_t* bytes);
 // Bytes of the adjoint workspace (each buffer 256-byte aligned).
 size_t adjoint_work_bytes(int M, int NE, int NF, int npic);
+size_t lagadj_work_bytes(int M, int NE, int NV, int NF, int npic);
+void lagadj_carve(int M, int NE, int NV, int NF, int npic, char* base, LagWork& w);
+int launch_adjoint_lagrangian(const Dev& d, const Params& p, int M, const LagWork& w, double dt,
+                              bool q_from_context, bool x_from_context, void* stream);
 // Carve the buffers from base (qbar_next, qbar left to the caller).
 void adjoint_carve(int M, int NE, int NF, int npic, char* base, AdjWork& w);
 // The reverse-mode step: qbar = (dQ^{n+1}/dQ^n)^T qbar_next for one global

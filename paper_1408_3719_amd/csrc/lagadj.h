@@ -1,0 +1,738 @@
+// Per-element and per-edge pieces of the adjoint of one global time step with
+// the mesh moving with the fluid (Lagrangian mode): the space-time predictor of
+// the PDE and the mesh ODE, the Rusanov flux over a bilinear space-time patch,
+// and the geometry part of a least-squares row of the reconstruction, each
+// with its vector-Jacobian product. Written for host and device so that the
+// products can be checked against central differences on the CPU.
+#pragma once
+
+#include <cmath>
+
+#include "common.h"
+
+#if defined(__HIPCC__)
+#define AWHD __host__ __device__
+#else
+#define AWHD
+#endif
+
+namespace aw {
+namespace lag {
+
+template <int M>
+struct Dim {
+  static constexpr int nb = (M + 1) * (M + 2) / 2, T = M + 1, nG = M + 1, nu = nb - 1;
+  static constexpr int QS = nb * T * 4;     // one predictor iterate
+};
+
+// Lattice point m of the nodal set (i/M, j/M), ordered by j then i.
+template <int M>
+AWHD inline void lattice(int m, double& xi, double& eta) {
+  int jj = 0, ii = m;
+  while (ii > M - jj) {
+    ii -= M + 1 - jj;
+    ++jj;
+  }
+  xi = double(ii) / M;
+  eta = double(jj) / M;
+}
+
+// Lagrange time basis l_q(tau) from the host tables' monomial coefficients.
+template <int M>
+AWHD inline void tbasis(const Tables& tb, double tau, double l[M + 1]) {
+  for (int q = 0; q <= M; ++q) {
+    double s = tb.lag[q][M];
+    for (int k = M - 1; k >= 0; --k) s = s * tau + tb.lag[q][k];
+    l[q] = s;
+  }
+}
+
+// int_0^1 l_q
+template <int M>
+AWHD inline void tint01(const Tables& tb, double I[M + 1]) {
+  for (int q = 0; q <= M; ++q) {
+    double s = 0.0;
+    for (int k = 0; k <= M + 1; ++k) s += tb.Lint[q][k];
+    I[q] = s;
+  }
+}
+
+AWHD inline void euler_f_g(const double q[4], double gam, double f[4], double g[4]) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r, E = q[3];
+  const double p = (gam - 1.0) * (E - 0.5 * r * (u * u + v * v));
+  f[0] = r * u;
+  f[1] = r * u * u + p;
+  f[2] = r * u * v;
+  f[3] = u * (E + p);
+  g[0] = r * v;
+  g[1] = r * u * v;
+  g[2] = r * v * v + p;
+  g[3] = v * (E + p);
+}
+
+// qb += J_f(q)^T fb + J_g(q)^T gb
+AWHD inline void euler_f_g_vjp(const double q[4], double gam, const double fb[4], const double gb[4],
+                               double qb[4]) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r, E = q[3];
+  const double gm = gam - 1.0;
+  const double p = gm * (E - 0.5 * r * (u * u + v * v));
+  const double H = E + p;
+  double rb = 0.0, ub = 0.0, vb = 0.0, pb = 0.0, Eb = 0.0;
+  rb += fb[0] * u;       ub += fb[0] * r;
+  rb += fb[1] * u * u;   ub += fb[1] * 2.0 * r * u;   pb += fb[1];
+  rb += fb[2] * u * v;   ub += fb[2] * r * v;         vb += fb[2] * r * u;
+  ub += fb[3] * H;       Eb += fb[3] * u;             pb += fb[3] * u;
+  rb += gb[0] * v;       vb += gb[0] * r;
+  rb += gb[1] * u * v;   ub += gb[1] * r * v;         vb += gb[1] * r * u;
+  rb += gb[2] * v * v;   vb += gb[2] * 2.0 * r * v;   pb += gb[2];
+  vb += gb[3] * H;       Eb += gb[3] * v;             pb += gb[3] * v;
+  // p = gm (E - (q1^2 + q2^2) / (2 q0)), u = q1 / q0, v = q2 / q0, r = q0
+  Eb += gm * pb;
+  rb += -gm * 0.5 * (u * u + v * v) * pb;
+  ub += -gm * r * u * pb;
+  vb += -gm * r * v * pb;
+  qb[0] += rb - (ub * u + vb * v) / r;
+  qb[1] += ub / r;
+  qb[2] += vb / r;
+  qb[3] += Eb;
+}
+
+// ------------------------------------------------------------------------
+// Predictor with the mesh ODE (eqs. CGfinal, VCG, newVertPos; V = v)
+// ------------------------------------------------------------------------
+// keep: the iterate before each of the npic sweeps and the final one,
+// keep[(k * QS + (m * T + t) * 4 + v) * ks], k = 0..npic.
+template <int M>
+AWHD inline void pred_fwd(const Tables& tb, double gam, int npic, const double* wnod, const double Xe[6],
+                          double dt, double* keep, size_t ks, double* trace, double* avg, double* vvel) {
+  using D = Dim<M>;
+  constexpr int nb = D::nb, T = D::T, nG = D::nG, QS = D::QS;
+  double q[nb][T][4], x0[nb][2];
+  for (int m = 0; m < nb; ++m) {
+    double xi, eta;
+    lattice<M>(m, xi, eta);
+    x0[m][0] = Xe[0] + (Xe[2] - Xe[0]) * xi + (Xe[4] - Xe[0]) * eta;
+    x0[m][1] = Xe[1] + (Xe[3] - Xe[1]) * xi + (Xe[5] - Xe[1]) * eta;
+    for (int t = 0; t < T; ++t)
+      for (int v = 0; v < 4; ++v) q[m][t][v] = wnod[m * 4 + v];
+  }
+  for (int k = 0; k < npic; ++k) {
+    for (int m = 0; m < nb; ++m)
+      for (int t = 0; t < T; ++t)
+        for (int v = 0; v < 4; ++v) keep[(size_t(k) * QS + (m * T + t) * 4 + v) * ks] = q[m][t][v];
+    // mesh ODE: x at the time nodes from x0 and V = v(q)
+    double x[nb][T][2];
+    for (int m = 0; m < nb; ++m) {
+      double V[T][2];
+      for (int s = 0; s < T; ++s) {
+        V[s][0] = q[m][s][1] / q[m][s][0];
+        V[s][1] = q[m][s][2] / q[m][s][0];
+      }
+      x[m][0][0] = x0[m][0];
+      x[m][0][1] = x0[m][1];
+      for (int t = 0; t < M; ++t)
+        for (int c = 0; c < 2; ++c) {
+          double s = tb.Bt[t] * x0[m][c];
+          for (int r = 0; r < T; ++r) s += dt * tb.At[t][r] * V[r][c];
+          x[m][t + 1][c] = s;
+        }
+    }
+    double P[nb][T][4];
+    for (int t = 0; t < T; ++t) {
+      double f[nb][4], g[nb][4];
+      for (int m = 0; m < nb; ++m) euler_f_g(q[m][t], gam, f[m], g[m]);
+      for (int kk = 0; kk < nb; ++kk) {
+        double xx = 0, xe = 0, yx = 0, ye = 0;
+        for (int m = 0; m < nb; ++m) {
+          xx += tb.Dxi[kk][m] * x[m][t][0];
+          xe += tb.Deta[kk][m] * x[m][t][0];
+          yx += tb.Dxi[kk][m] * x[m][t][1];
+          ye += tb.Deta[kk][m] * x[m][t][1];
+        }
+        double xtau = 0, ytau = 0;
+        for (int s = 0; s < T; ++s) {
+          xtau += tb.Dt[t][s] * x[kk][s][0];
+          ytau += tb.Dt[t][s] * x[kk][s][1];
+        }
+        const double det = xx * ye - xe * yx;
+        const double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
+        const double xt = xtau / dt, yt = ytau / dt;
+        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
+        for (int v = 0; v < 4; ++v) {
+          double dqx = 0, dqe = 0, dfx = 0, dfe = 0, dgx = 0, dge = 0;
+          for (int m = 0; m < nb; ++m) {
+            dqx += tb.Dxi[kk][m] * q[m][t][v];
+            dqe += tb.Deta[kk][m] * q[m][t][v];
+            dfx += tb.Dxi[kk][m] * f[m][v];
+            dfe += tb.Deta[kk][m] * f[m][v];
+            dgx += tb.Dxi[kk][m] * g[m][v];
+            dge += tb.Deta[kk][m] * g[m][v];
+          }
+          P[kk][t][v] = -(dqx * xi_t + dqe * eta_t + dfx * xi_x + dfe * eta_x + dgx * xi_y + dge * eta_y);
+        }
+      }
+    }
+    for (int m = 0; m < nb; ++m)
+      for (int t = 0; t < M; ++t)
+        for (int v = 0; v < 4; ++v) {
+          double s = tb.Bt[t] * q[m][0][v];
+          for (int r = 0; r < T; ++r) s += dt * tb.At[t][r] * P[m][r][v];
+          q[m][t + 1][v] = s;
+        }
+  }
+  for (int m = 0; m < nb; ++m)
+    for (int t = 0; t < T; ++t)
+      for (int v = 0; v < 4; ++v) keep[(size_t(npic) * QS + (m * T + t) * 4 + v) * ks] = q[m][t][v];
+  for (int e = 0; e < 3; ++e)
+    for (int gq = 0; gq < nG; ++gq)
+      for (int t = 0; t < T; ++t)
+        for (int v = 0; v < 4; ++v) {
+          double s = 0.0;
+          for (int m = 0; m < nb; ++m) s += tb.edge[e][gq][m] * q[m][t][v];
+          trace[((e * nG + gq) * T + t) * 4 + v] = s;
+        }
+  for (int t = 0; t < T; ++t)
+    for (int v = 0; v < 4; ++v) {
+      double s = 0.0;
+      for (int m = 0; m < nb; ++m) s += tb.amean[m] * q[m][t][v];
+      avg[t * 4 + v] = s;
+    }
+  for (int k = 0; k < 3; ++k)
+    for (int t = 0; t < T; ++t) {
+      const double* qq = q[tb.vtx[k]][t];
+      vvel[(k * T + t) * 2 + 0] = qq[1] / qq[0];
+      vvel[(k * T + t) * 2 + 1] = qq[2] / qq[0];
+    }
+}
+
+// Reverse of pred_fwd: from the adjoints of the traces, cell means and vertex
+// velocities to those of the nodal reconstruction (wnodb, overwritten) and of
+// the element vertices (Xeb, added to).
+template <int M>
+AWHD inline void pred_rev(const Tables& tb, double gam, int npic, const double Xe[6], double dt,
+                          const double* keep, size_t ks, const double* traceb, const double* avgb,
+                          const double* vvelb, double* wnodb, double Xeb[6]) {
+  using D = Dim<M>;
+  constexpr int nb = D::nb, T = D::T, nG = D::nG, QS = D::QS;
+  double qb[nb][T][4], x0[nb][2], x0b[nb][2];
+  for (int m = 0; m < nb; ++m) {
+    double xi, eta;
+    lattice<M>(m, xi, eta);
+    x0[m][0] = Xe[0] + (Xe[2] - Xe[0]) * xi + (Xe[4] - Xe[0]) * eta;
+    x0[m][1] = Xe[1] + (Xe[3] - Xe[1]) * xi + (Xe[5] - Xe[1]) * eta;
+    x0b[m][0] = x0b[m][1] = 0.0;
+    for (int t = 0; t < T; ++t)
+      for (int v = 0; v < 4; ++v) {
+        double s = tb.amean[m] * avgb[t * 4 + v];
+        for (int e = 0; e < 3; ++e)
+          for (int gq = 0; gq < nG; ++gq) s += tb.edge[e][gq][m] * traceb[((e * nG + gq) * T + t) * 4 + v];
+        qb[m][t][v] = s;
+      }
+  }
+  for (int k = 0; k < 3; ++k)
+    for (int t = 0; t < T; ++t) {
+      const int m = tb.vtx[k];
+      double qq[4];
+      for (int v = 0; v < 4; ++v) qq[v] = keep[(size_t(npic) * QS + (m * T + t) * 4 + v) * ks];
+      const double vxb = vvelb[(k * T + t) * 2 + 0], vyb = vvelb[(k * T + t) * 2 + 1];
+      qb[m][t][0] -= (vxb * qq[1] + vyb * qq[2]) / (qq[0] * qq[0]);
+      qb[m][t][1] += vxb / qq[0];
+      qb[m][t][2] += vyb / qq[0];
+    }
+  for (int k = npic - 1; k >= 0; --k) {
+    double q[nb][T][4];
+    for (int m = 0; m < nb; ++m)
+      for (int t = 0; t < T; ++t)
+        for (int v = 0; v < 4; ++v) q[m][t][v] = keep[(size_t(k) * QS + (m * T + t) * 4 + v) * ks];
+    // the sweep's mesh positions, recomputed
+    double x[nb][T][2];
+    for (int m = 0; m < nb; ++m) {
+      x[m][0][0] = x0[m][0];
+      x[m][0][1] = x0[m][1];
+      for (int t = 0; t < M; ++t)
+        for (int c = 0; c < 2; ++c) {
+          double s = tb.Bt[t] * x0[m][c];
+          for (int r = 0; r < T; ++r) s += dt * tb.At[t][r] * q[m][r][1 + c] / q[m][r][0];
+          x[m][t + 1][c] = s;
+        }
+    }
+    // q_out[m][0] = q[m][0]; q_out[m][t+1] = Bt[t] q[m][0] + dt sum_r At[t][r] P[m][r]
+    double qi[nb][T][4], Pb[nb][T][4];
+    for (int m = 0; m < nb; ++m)
+      for (int v = 0; v < 4; ++v) {
+        double s = qb[m][0][v];
+        for (int t = 0; t < M; ++t) s += tb.Bt[t] * qb[m][t + 1][v];
+        qi[m][0][v] = s;
+        for (int t = 1; t < T; ++t) qi[m][t][v] = 0.0;
+        for (int r = 0; r < T; ++r) {
+          double p = 0.0;
+          for (int t = 0; t < M; ++t) p += tb.At[t][r] * qb[m][t + 1][v];
+          Pb[m][r][v] = dt * p;
+        }
+      }
+    double xb[nb][T][2];
+    for (int m = 0; m < nb; ++m)
+      for (int t = 0; t < T; ++t) xb[m][t][0] = xb[m][t][1] = 0.0;
+    for (int t = 0; t < T; ++t) {
+      double f[nb][4], g[nb][4], fb[nb][4], gb[nb][4];
+      for (int m = 0; m < nb; ++m) {
+        euler_f_g(q[m][t], gam, f[m], g[m]);
+        for (int v = 0; v < 4; ++v) fb[m][v] = gb[m][v] = 0.0;
+      }
+      for (int kk = 0; kk < nb; ++kk) {
+        double xx = 0, xe = 0, yx = 0, ye = 0;
+        for (int m = 0; m < nb; ++m) {
+          xx += tb.Dxi[kk][m] * x[m][t][0];
+          xe += tb.Deta[kk][m] * x[m][t][0];
+          yx += tb.Dxi[kk][m] * x[m][t][1];
+          ye += tb.Deta[kk][m] * x[m][t][1];
+        }
+        double xtau = 0, ytau = 0;
+        for (int s = 0; s < T; ++s) {
+          xtau += tb.Dt[t][s] * x[kk][s][0];
+          ytau += tb.Dt[t][s] * x[kk][s][1];
+        }
+        const double det = xx * ye - xe * yx;
+        const double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
+        const double xt = xtau / dt, yt = ytau / dt;
+        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
+        double xitb = 0, etatb = 0, xixb = 0, xiyb = 0, etaxb = 0, etayb = 0;
+        for (int v = 0; v < 4; ++v) {
+          double dqx = 0, dqe = 0, dfx = 0, dfe = 0, dgx = 0, dge = 0;
+          for (int m = 0; m < nb; ++m) {
+            dqx += tb.Dxi[kk][m] * q[m][t][v];
+            dqe += tb.Deta[kk][m] * q[m][t][v];
+            dfx += tb.Dxi[kk][m] * f[m][v];
+            dfe += tb.Deta[kk][m] * f[m][v];
+            dgx += tb.Dxi[kk][m] * g[m][v];
+            dge += tb.Deta[kk][m] * g[m][v];
+          }
+          const double pb = Pb[kk][t][v];
+          xitb -= pb * dqx;
+          etatb -= pb * dqe;
+          xixb -= pb * dfx;
+          etaxb -= pb * dfe;
+          xiyb -= pb * dgx;
+          etayb -= pb * dge;
+          for (int m = 0; m < nb; ++m) {
+            qi[m][t][v] -= pb * (tb.Dxi[kk][m] * xi_t + tb.Deta[kk][m] * eta_t);
+            fb[m][v] -= pb * (tb.Dxi[kk][m] * xi_x + tb.Deta[kk][m] * eta_x);
+            gb[m][v] -= pb * (tb.Dxi[kk][m] * xi_y + tb.Deta[kk][m] * eta_y);
+          }
+        }
+        // xi_t = -(xi_x xt + xi_y yt), eta_t = -(eta_x xt + eta_y yt)
+        xixb -= xitb * xt;
+        xiyb -= xitb * yt;
+        etaxb -= etatb * xt;
+        etayb -= etatb * yt;
+        const double xtb = -(xitb * xi_x + etatb * eta_x), ytb = -(xitb * xi_y + etatb * eta_y);
+        // metric from the spatial derivatives
+        const double detb = -(xixb * xi_x + xiyb * xi_y + etaxb * eta_x + etayb * eta_y) / det;
+        const double xxb = etayb / det + detb * ye;
+        const double yeb = xixb / det + detb * xx;
+        const double xeb = -xiyb / det - detb * yx;
+        const double yxb = -etaxb / det - detb * xe;
+        for (int m = 0; m < nb; ++m) {
+          xb[m][t][0] += tb.Dxi[kk][m] * xxb + tb.Deta[kk][m] * xeb;
+          xb[m][t][1] += tb.Dxi[kk][m] * yxb + tb.Deta[kk][m] * yeb;
+        }
+        for (int s = 0; s < T; ++s) {
+          xb[kk][s][0] += tb.Dt[t][s] * xtb / dt;
+          xb[kk][s][1] += tb.Dt[t][s] * ytb / dt;
+        }
+      }
+      for (int m = 0; m < nb; ++m) euler_f_g_vjp(q[m][t], gam, fb[m], gb[m], qi[m][t]);
+    }
+    // x[m][0] = x0[m]; x[m][t+1] = Bt[t] x0[m] + dt sum_r At[t][r] V[m][r], V = (q1, q2) / q0
+    for (int m = 0; m < nb; ++m) {
+      for (int c = 0; c < 2; ++c) {
+        double s = xb[m][0][c];
+        for (int t = 0; t < M; ++t) s += tb.Bt[t] * xb[m][t + 1][c];
+        x0b[m][c] += s;
+      }
+      for (int r = 0; r < T; ++r) {
+        double vb[2];
+        for (int c = 0; c < 2; ++c) {
+          double s = 0.0;
+          for (int t = 0; t < M; ++t) s += tb.At[t][r] * xb[m][t + 1][c];
+          vb[c] = dt * s;
+        }
+        const double* qq = q[m][r];
+        qi[m][r][0] -= (vb[0] * qq[1] + vb[1] * qq[2]) / (qq[0] * qq[0]);
+        qi[m][r][1] += vb[0] / qq[0];
+        qi[m][r][2] += vb[1] / qq[0];
+      }
+    }
+    for (int m = 0; m < nb; ++m)
+      for (int t = 0; t < T; ++t)
+        for (int v = 0; v < 4; ++v) qb[m][t][v] = qi[m][t][v];
+  }
+  for (int m = 0; m < nb; ++m) {
+    for (int v = 0; v < 4; ++v) {
+      double s = 0.0;
+      for (int t = 0; t < T; ++t) s += qb[m][t][v];
+      wnodb[m * 4 + v] = s;
+    }
+    double xi, eta;
+    lattice<M>(m, xi, eta);
+    for (int c = 0; c < 2; ++c) {
+      Xeb[0 + c] += (1.0 - xi - eta) * x0b[m][c];
+      Xeb[2 + c] += xi * x0b[m][c];
+      Xeb[4 + c] += eta * x0b[m][c];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// Rusanov flux through an unnormalised space-time normal and its product
+// ------------------------------------------------------------------------
+AWHD inline double rus_speed(const double q[4], const double N[3], double gam, double* un_out, double* c_out) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  const double p = (gam - 1.0) * (q[3] - 0.5 * r * (u * u + v * v));
+  const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
+  const double un = u * N[0] + v * N[1] + N[2];
+  const double c = sqrt(gam * p / r);
+  *un_out = un;
+  *c_out = c;
+  return fabs(un) + c * nxy;
+}
+
+AWHD inline void rusanov_flux(const double ql[4], const double qr[4], const double N[3], double gam, double F[4]) {
+  double fl[4], gl[4], fr[4], gr[4], un, c;
+  euler_f_g(ql, gam, fl, gl);
+  euler_f_g(qr, gam, fr, gr);
+  const double sl = rus_speed(ql, N, gam, &un, &c), sr = rus_speed(qr, N, gam, &un, &c);
+  const double s = sl >= sr ? sl : sr;
+  for (int v = 0; v < 4; ++v)
+    F[v] = 0.5 * ((fl[v] + fr[v]) * N[0] + (gl[v] + gr[v]) * N[1] + (ql[v] + qr[v]) * N[2]) -
+           0.5 * s * (qr[v] - ql[v]);
+}
+
+// qlb, qrb, Nb += the product of Fb with the Rusanov flux's Jacobian (the
+// larger signal speed taken from the left state on ties, d|x|/dx = 0 at 0).
+AWHD inline void rusanov_flux_vjp(const double ql[4], const double qr[4], const double N[3], double gam,
+                                  const double Fb[4], double qlb[4], double qrb[4], double Nb[3]) {
+  double fl[4], gl[4], fr[4], gr[4], unl, cl, unr, cr;
+  euler_f_g(ql, gam, fl, gl);
+  euler_f_g(qr, gam, fr, gr);
+  const double sl = rus_speed(ql, N, gam, &unl, &cl), sr = rus_speed(qr, N, gam, &unr, &cr);
+  const bool left = sl >= sr;
+  const double s = left ? sl : sr;
+  double fb[4], gb[4], sb = 0.0;
+  for (int v = 0; v < 4; ++v) {
+    fb[v] = 0.5 * N[0] * Fb[v];
+    gb[v] = 0.5 * N[1] * Fb[v];
+    qlb[v] += 0.5 * N[2] * Fb[v] + 0.5 * s * Fb[v];
+    qrb[v] += 0.5 * N[2] * Fb[v] - 0.5 * s * Fb[v];
+    sb -= 0.5 * Fb[v] * (qr[v] - ql[v]);
+    Nb[0] += 0.5 * Fb[v] * (fl[v] + fr[v]);
+    Nb[1] += 0.5 * Fb[v] * (gl[v] + gr[v]);
+    Nb[2] += 0.5 * Fb[v] * (ql[v] + qr[v]);
+  }
+  euler_f_g_vjp(ql, gam, fb, gb, qlb);
+  euler_f_g_vjp(qr, gam, fb, gb, qrb);
+  // s = |u N0 + v N1 + N2| + c |N_xy| of the state that gives the maximum
+  const double* q = left ? ql : qr;
+  double* qsb = left ? qlb : qrb;
+  const double un = left ? unl : unr, c = left ? cl : cr;
+  const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
+  const double sg = un > 0.0 ? 1.0 : (un < 0.0 ? -1.0 : 0.0);
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  Nb[0] += sb * (sg * u + c * N[0] / nxy);
+  Nb[1] += sb * (sg * v + c * N[1] / nxy);
+  Nb[2] += sb * sg;
+  // through u, v and c = sqrt(gam p / r)
+  const double gm = gam - 1.0;
+  const double ub = sb * sg * N[0], vb = sb * sg * N[1];
+  const double cb = sb * nxy;
+  const double p = gm * (q[3] - 0.5 * r * (u * u + v * v));
+  double rb = -cb * c / (2.0 * r), pb = cb * gam / (2.0 * c * r);
+  double ubb = ub - gm * r * u * pb, vbb = vb - gm * r * v * pb;
+  rb += -gm * 0.5 * (u * u + v * v) * pb;
+  (void)p;
+  qsb[0] += rb - (ubb * u + vbb * v) / r;
+  qsb[1] += ubb / r;
+  qsb[2] += vbb / r;
+  qsb[3] += gm * pb;
+}
+
+// ------------------------------------------------------------------------
+// One edge's bilinear space-time patch over a global step (eqs.
+// eqn.spacetimenodes, G_ij, eqn.STint): old nodes a, b at time 0, new nodes at
+// dt; trL (nG, T, 4) the left element's trace along the edge, trR the right
+// one's (read in reverse), or on a transmissive edge (hasR false) the left
+// element's predicted cell means avL (T, 4) as outer state.
+// ------------------------------------------------------------------------
+template <int M>
+AWHD inline void patch_corners(const double xa[2], const double xb[2], const double xan[2], const double xbn[2],
+                               double dt, double P[4][3]) {
+  P[0][0] = xa[0];  P[0][1] = xa[1];  P[0][2] = 0.0;
+  P[1][0] = xb[0];  P[1][1] = xb[1];  P[1][2] = 0.0;
+  P[2][0] = xbn[0]; P[2][1] = xbn[1]; P[2][2] = dt;
+  P[3][0] = xan[0]; P[3][1] = xan[1]; P[3][2] = dt;
+}
+
+template <int M>
+AWHD inline void patch_point(const Tables& tb, int gq, int h, const double P[4][3], double N[3], double lt[M + 1],
+                             double dchi[3], double dtau[3]) {
+  const double c = tb.gchi[gq], t = tb.gchi[h];
+  for (int k = 0; k < 3; ++k) {
+    dchi[k] = (1.0 - t) * (P[1][k] - P[0][k]) + t * (P[2][k] - P[3][k]);
+    dtau[k] = (1.0 - c) * (P[3][k] - P[0][k]) + c * (P[2][k] - P[1][k]);
+  }
+  N[0] = dchi[1] * dtau[2] - dchi[2] * dtau[1];
+  N[1] = dchi[2] * dtau[0] - dchi[0] * dtau[2];
+  N[2] = dchi[0] * dtau[1] - dchi[1] * dtau[0];
+  tbasis<M>(tb, t, lt);
+}
+
+template <int M>
+AWHD inline void patch_states(const double* trL, const double* trR, const double* avL, bool hasR, int gq,
+                              const double lt[M + 1], double ql[4], double qr[4]) {
+  constexpr int T = M + 1, nG = M + 1;
+  for (int v = 0; v < 4; ++v) {
+    double a = 0.0, b = 0.0;
+    for (int s = 0; s < T; ++s) {
+      a += lt[s] * trL[(gq * T + s) * 4 + v];
+      b += lt[s] * (hasR ? trR[((nG - 1 - gq) * T + s) * 4 + v] : avL[s * 4 + v]);
+    }
+    ql[v] = a;
+    qr[v] = b;
+  }
+}
+
+template <int M>
+AWHD inline void patch_flux(const Tables& tb, double gam, const double xa[2], const double xb[2], const double xan[2],
+                            const double xbn[2], double dt, const double* trL, const double* trR, const double* avL,
+                            bool hasR, double G[4]) {
+  constexpr int nG = M + 1;
+  double P[4][3];
+  patch_corners<M>(xa, xb, xan, xbn, dt, P);
+  for (int v = 0; v < 4; ++v) G[v] = 0.0;
+  for (int gq = 0; gq < nG; ++gq)
+    for (int h = 0; h < nG; ++h) {
+      double N[3], lt[M + 1], dc[3], dtau[3], ql[4], qr[4], F[4];
+      patch_point<M>(tb, gq, h, P, N, lt, dc, dtau);
+      patch_states<M>(trL, trR, avL, hasR, gq, lt, ql, qr);
+      rusanov_flux(ql, qr, N, gam, F);
+      const double w = tb.gw[gq] * tb.gw[h];
+      for (int v = 0; v < 4; ++v) G[v] += w * F[v];
+    }
+}
+
+// Products of Gb with patch_flux: trLb, trRb (or avLb) and the four corner
+// nodes' adjoints (xab, xbb, xanb, xbnb: x, y) are added to.
+template <int M>
+AWHD inline void patch_flux_vjp(const Tables& tb, double gam, const double xa[2], const double xb[2],
+                                const double xan[2], const double xbn[2], double dt, const double* trL,
+                                const double* trR, const double* avL, bool hasR, const double Gb[4], double* trLb,
+                                double* trRb, double* avLb, double xab[2], double xbb[2], double xanb[2],
+                                double xbnb[2]) {
+  constexpr int T = M + 1, nG = M + 1;
+  double P[4][3], Pb[4][3] = {};
+  patch_corners<M>(xa, xb, xan, xbn, dt, P);
+  for (int gq = 0; gq < nG; ++gq)
+    for (int h = 0; h < nG; ++h) {
+      double N[3], lt[M + 1], dc[3], dtau[3], ql[4], qr[4];
+      patch_point<M>(tb, gq, h, P, N, lt, dc, dtau);
+      patch_states<M>(trL, trR, avL, hasR, gq, lt, ql, qr);
+      const double w = tb.gw[gq] * tb.gw[h];
+      double Fb[4], qlb[4] = {}, qrb[4] = {}, Nb[3] = {};
+      for (int v = 0; v < 4; ++v) Fb[v] = w * Gb[v];
+      rusanov_flux_vjp(ql, qr, N, gam, Fb, qlb, qrb, Nb);
+      for (int s = 0; s < T; ++s)
+        for (int v = 0; v < 4; ++v) {
+          trLb[(gq * T + s) * 4 + v] += lt[s] * qlb[v];
+          if (hasR)
+            trRb[((nG - 1 - gq) * T + s) * 4 + v] += lt[s] * qrb[v];
+          else
+            avLb[s * 4 + v] += lt[s] * qrb[v];
+        }
+      // N = dchi x dtau
+      double dcb[3], dtb[3];
+      dcb[0] = dtau[1] * Nb[2] - dtau[2] * Nb[1];
+      dcb[1] = dtau[2] * Nb[0] - dtau[0] * Nb[2];
+      dcb[2] = dtau[0] * Nb[1] - dtau[1] * Nb[0];
+      dtb[0] = Nb[1] * dc[2] - Nb[2] * dc[1];
+      dtb[1] = Nb[2] * dc[0] - Nb[0] * dc[2];
+      dtb[2] = Nb[0] * dc[1] - Nb[1] * dc[0];
+      const double c = tb.gchi[gq], t = tb.gchi[h];
+      for (int k = 0; k < 3; ++k) {
+        Pb[1][k] += (1.0 - t) * dcb[k] - c * dtb[k];
+        Pb[0][k] -= (1.0 - t) * dcb[k] + (1.0 - c) * dtb[k];
+        Pb[2][k] += t * dcb[k] + c * dtb[k];
+        Pb[3][k] += -t * dcb[k] + (1.0 - c) * dtb[k];
+      }
+    }
+  for (int c = 0; c < 2; ++c) {
+    xab[c] += Pb[0][c];
+    xbb[c] += Pb[1][c];
+    xbnb[c] += Pb[2][c];
+    xanb[c] += Pb[3][c];
+  }
+}
+
+// Signed area of a triangle and its gradient with respect to the vertices.
+AWHD inline double area3(const double X[6]) {
+  return 0.5 * ((X[2] - X[0]) * (X[5] - X[1]) - (X[4] - X[0]) * (X[3] - X[1]));
+}
+AWHD inline void area3_grad(const double X[6], double s, double Xb[6]) {
+  Xb[0] += s * 0.5 * (X[3] - X[5]);
+  Xb[1] += s * 0.5 * (X[4] - X[2]);
+  Xb[2] += s * 0.5 * (X[5] - X[1]);
+  Xb[3] += s * 0.5 * (X[0] - X[4]);
+  Xb[4] += s * 0.5 * (X[1] - X[3]);
+  Xb[5] += s * 0.5 * (X[2] - X[0]);
+}
+
+// ------------------------------------------------------------------------
+// Geometry of a least-squares row: the means over the triangle Xj of the
+// monomials shifted by their reference means, in the reference frame of the
+// triangle Xi (the rule exact to degree M of the reconstruction: centroid;
+// edge midpoints; vertices, edge midpoints and centroid with 3/60, 8/60, 27/60)
+// ------------------------------------------------------------------------
+template <int M>
+AWHD inline void mono_point(double w, double px, double py, double* mm) {
+  double xp[M + 1], yp[M + 1];
+  xp[0] = yp[0] = 1.0;
+  for (int a = 1; a <= M; ++a) {
+    xp[a] = xp[a - 1] * px;
+    yp[a] = yp[a - 1] * py;
+  }
+  int k = 0;
+  for (int dg = 0; dg <= M; ++dg)
+    for (int b = 0; b <= dg; ++b) mm[k++] += w * xp[dg - b] * yp[b];
+}
+
+template <int M>
+AWHD inline void mono_point_vjp(double w, double px, double py, const double* mmb, double& pxb, double& pyb) {
+  double xp[M + 1], yp[M + 1];
+  xp[0] = yp[0] = 1.0;
+  for (int a = 1; a <= M; ++a) {
+    xp[a] = xp[a - 1] * px;
+    yp[a] = yp[a - 1] * py;
+  }
+  pxb = pyb = 0.0;
+  int k = 0;
+  for (int dg = 0; dg <= M; ++dg)
+    for (int b = 0; b <= dg; ++b) {
+      const int a = dg - b;
+      if (a > 0) pxb += mmb[k] * w * a * xp[a - 1] * yp[b];
+      if (b > 0) pyb += mmb[k] * w * b * xp[a] * yp[b - 1];
+      ++k;
+    }
+}
+
+// The rule's points as barycentric combinations of the three vertices.
+template <int M>
+struct RowRule {
+  static constexpr int NP = M == 1 ? 1 : (M == 2 ? 3 : 7);
+};
+
+template <int M>
+AWHD inline void row_rule_point(int p, double& w, double bc[3]) {
+  const double third = 1.0 / 3.0;
+  bc[0] = bc[1] = bc[2] = 0.0;
+  if (M == 1) {
+    w = 1.0;
+    bc[0] = bc[1] = bc[2] = third;
+  } else if (M == 2) {
+    w = third;
+    bc[p] = 0.5;
+    bc[p == 2 ? 0 : p + 1] = 0.5;
+  } else {
+    if (p < 3) {
+      w = 3.0 / 60.0;
+      bc[p] = 1.0;
+    } else if (p < 6) {
+      w = 8.0 / 60.0;
+      bc[p - 3] = 0.5;
+      bc[p - 3 == 2 ? 0 : p - 2] = 0.5;
+    } else {
+      w = 27.0 / 60.0;
+      bc[0] = bc[1] = bc[2] = third;
+    }
+  }
+}
+
+// Row a (nu values) of neighbour triangle Xj in the frame of Xi, given the
+// shifted monomials' reference means refm (nb values).
+template <int M>
+AWHD inline void ls_row_geom(const double Xj[6], const double Xi[6], const double* refm, double* a) {
+  constexpr int nb = Dim<M>::nb;
+  const double e1x = Xi[2] - Xi[0], e1y = Xi[3] - Xi[1], e2x = Xi[4] - Xi[0], e2y = Xi[5] - Xi[1];
+  const double idet = 1.0 / (e1x * e2y - e2x * e1y);
+  double rx[3], ry[3];
+  for (int k = 0; k < 3; ++k) {
+    const double dx = Xj[2 * k] - Xi[0], dy = Xj[2 * k + 1] - Xi[1];
+    rx[k] = (dx * e2y - dy * e2x) * idet;
+    ry[k] = (e1x * dy - e1y * dx) * idet;
+  }
+  double mm[nb] = {};
+  for (int p = 0; p < RowRule<M>::NP; ++p) {
+    double w, bc[3];
+    row_rule_point<M>(p, w, bc);
+    mono_point<M>(w, bc[0] * rx[0] + bc[1] * rx[1] + bc[2] * rx[2], bc[0] * ry[0] + bc[1] * ry[1] + bc[2] * ry[2],
+                  mm);
+  }
+  for (int l = 0; l + 1 < nb; ++l) a[l] = mm[l + 1] - refm[l + 1];
+}
+
+// Xjb, Xib += the product of ab (nu values) with ls_row_geom's Jacobian.
+template <int M>
+AWHD inline void ls_row_geom_vjp(const double Xj[6], const double Xi[6], const double* ab, double Xjb[6],
+                                 double Xib[6]) {
+  constexpr int nb = Dim<M>::nb;
+  const double e1x = Xi[2] - Xi[0], e1y = Xi[3] - Xi[1], e2x = Xi[4] - Xi[0], e2y = Xi[5] - Xi[1];
+  const double det = e1x * e2y - e2x * e1y;
+  const double idet = 1.0 / det;
+  double rx[3], ry[3], dx[3], dy[3];
+  for (int k = 0; k < 3; ++k) {
+    dx[k] = Xj[2 * k] - Xi[0];
+    dy[k] = Xj[2 * k + 1] - Xi[1];
+    rx[k] = (dx[k] * e2y - dy[k] * e2x) * idet;
+    ry[k] = (e1x * dy[k] - e1y * dx[k]) * idet;
+  }
+  double mmb[nb];
+  mmb[0] = 0.0;
+  for (int l = 0; l + 1 < nb; ++l) mmb[l + 1] = ab[l];
+  double rxb[3] = {}, ryb[3] = {};
+  for (int p = 0; p < RowRule<M>::NP; ++p) {
+    double w, bc[3], pxb, pyb;
+    row_rule_point<M>(p, w, bc);
+    mono_point_vjp<M>(w, bc[0] * rx[0] + bc[1] * rx[1] + bc[2] * rx[2],
+                      bc[0] * ry[0] + bc[1] * ry[1] + bc[2] * ry[2], mmb, pxb, pyb);
+    for (int k = 0; k < 3; ++k) {
+      rxb[k] += bc[k] * pxb;
+      ryb[k] += bc[k] * pyb;
+    }
+  }
+  double e1xb = 0, e1yb = 0, e2xb = 0, e2yb = 0, idetb = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double dxb = (rxb[k] * e2y - ryb[k] * e1y) * idet;
+    const double dyb = (-rxb[k] * e2x + ryb[k] * e1x) * idet;
+    Xjb[2 * k] += dxb;
+    Xjb[2 * k + 1] += dyb;
+    Xib[0] -= dxb;
+    Xib[1] -= dyb;
+    e2yb += rxb[k] * dx[k] * idet;
+    e2xb -= rxb[k] * dy[k] * idet;
+    e1xb += ryb[k] * dy[k] * idet;
+    e1yb -= ryb[k] * dx[k] * idet;
+    idetb += rxb[k] * rx[k] * det + ryb[k] * ry[k] * det;   // d rx / d idet = rx / idet
+  }
+  const double detb = -idetb * idet * idet;
+  e1xb += detb * e2y;
+  e2yb += detb * e1x;
+  e2xb -= detb * e1y;
+  e1yb -= detb * e2x;
+  Xib[2] += e1xb;
+  Xib[3] += e1yb;
+  Xib[0] -= e1xb + e2xb;
+  Xib[1] -= e1yb + e2yb;
+  Xib[4] += e2xb;
+  Xib[5] += e2yb;
+}
+
+}  // namespace lag
+}  // namespace aw

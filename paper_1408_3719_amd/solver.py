@@ -194,6 +194,43 @@ class Solver(_Base):
             ctypes.c_void_p(qn.data_ptr()), ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def _devxy(self, a, what):
+        torch = self.torch
+        if not torch.is_tensor(a):
+            a = torch.as_tensor(np.ascontiguousarray(np.asarray(a, np.float64)), device=self.device)
+        a = a.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(a.shape) != (self.NV, 2):
+            raise ValueError(f"{what} must be ({self.NV}, 2)")
+        return a
+
+    def adjoint_lagrangian_step(self, dt, qbar_next, xbar_next, q=None, x=None):
+        """Adjoint of one global step of length dt on the mesh moving with the
+        fluid (dt held fixed), at averages q and node positions x (default:
+        the current state).  qbar_next, q: (NE, 4) arrays or device tensors
+        [4][NE]; xbar_next, x: (NV, 2).  Returns device tensors (qbar [4][NE],
+        xbar (NV, 2), q_next [4][NE], x_next (NV, 2)): the adjoints at the step
+        start and the step's own result."""
+        torch = self.torch
+        qn = self._dev4(qbar_next, "qbar_next")
+        xn = self._devxy(xbar_next, "xbar_next")
+        qs = self._dev4(q, "q") if q is not None else None
+        xs = self._devxy(x, "x") if x is not None else None
+        qbar, q_next = torch.empty_like(qn), torch.empty_like(qn)
+        xbar, x_next = torch.empty_like(xn), torch.empty_like(xn)
+        if getattr(self, "_lag_ws", None) is None:
+            n = ctypes.c_size_t()
+            _check(self.lib, self.ctx, self.lib.ader_adjoint_lagrangian_workspace_size(self.ctx, ctypes.byref(n)))
+            self._lag_ws = (torch.empty(n.value + 256, dtype=torch.uint8, device=self.device), n.value)
+        buf, n = self._lag_ws
+        aligned = (buf.data_ptr() + 255) // 256 * 256
+
+        def ptr(t):
+            return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        _check(self.lib, self.ctx, self.lib.ader_adjoint_lagrangian_step(
+            self.ctx, dt, ptr(qs), ptr(xs), ptr(qn), ptr(xn), ptr(qbar), ptr(xbar), ptr(q_next), ptr(x_next),
+            ctypes.c_void_p(aligned), n))
+        return qbar, xbar, q_next, x_next
+
     def set_schedule_replay(self, step_log):
         """Replay recorded steps: step_log[i] lists the steps (in ticks)
         element i takes, in order (None: the level rule again)."""

@@ -1,0 +1,153 @@
+"""Adjoint of one global time step on the mesh moving with the fluid through
+the C ABI (ader_adjoint_lagrangian_step), dt held fixed: averages and node
+positions differentiated, element by element and node by node against the
+reverse-mode oracle (torch.autograd through the oracle's Lagrangian step) on
+small meshes, its forward result against the oracle's step and the context's
+own global step; at a larger mesh against central differences of the GPU's own
+forward map and against translation invariance."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from test_oracle_adjoint import _case  # noqa: E402
+
+from oracle.adjoint import LagrangianStep  # noqa: E402
+from oracle.scheme import Config as OConfig  # noqa: E402
+from oracle.scheme import GTSSolver  # noqa: E402
+from workloads import explosion_case  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+# (the explosion at M=3 reaches a non-physical state within the step in the oracle too:
+# unlimited third-order data at the jump)
+CASES = [("vortex", 1), ("vortex", 2), ("vortex", 3), ("explosion", 1), ("explosion", 2)]
+
+
+def _solver(mesh, Q0, M, flux="rusanov", velocity="lagrangian"):
+    from paper_1408_3719_amd import Config, Solver
+    return Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=1, mesh_velocity=velocity, flux=flux))
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("name,M", CASES)
+def test_lagrangian_adjoint_matches_reverse_mode_oracle(name, M):
+    mesh, Q0 = _case(name, M)
+    print(f"lagrangian adjoint {name} M={M} {mesh.n_elems} triangles", flush=True)
+    cfg = OConfig(M=M, levels=1, mesh_velocity="lagrangian")
+    o = GTSSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+    dt = 0.5 * float(o.dtcfl.min())
+    st = LagrangianStep(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+    rng = np.random.default_rng(4)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    ref_q, ref_x = st.vjp(Q0, mesh.nodes, dt, qb, xb)
+    ref_q1, ref_x1 = st.step(Q0, mesh.nodes, dt)
+    g = _solver(mesh, Q0, M)
+    Qa, Xa, _ = g.download()
+    gq, gx, q1, x1 = (t.cpu().numpy() for t in g.adjoint_lagrangian_step(dt, qb, xb))
+    gq, q1 = gq.T, q1.T
+    for v in range(4):
+        assert _rel(gq[:, v], ref_q[:, v]) < TOL, (v, _rel(gq[:, v], ref_q[:, v]))
+    assert _rel(gx, ref_x) < TOL, _rel(gx, ref_x)
+    assert _rel(q1, ref_q1) < 1e-12 and np.abs(x1 - ref_x1).max() < 1e-12 * np.ptp(mesh.nodes)
+    # the simulation state is untouched; the context's own step is the one differentiated
+    Qb, Xb, _ = g.download()
+    assert np.array_equal(Qa, Qb) and np.array_equal(Xa, Xb)
+    g.step_gts(dt, 1)
+    Q1, X1, _ = g.download()
+    assert _rel(Q1, q1) < 1e-12 and np.abs(X1 - x1).max() < 1e-12 * np.ptp(mesh.nodes)
+
+
+def test_lagrangian_adjoint_explicit_state_and_linearity():
+    """The state passed in equals the context's when they agree (bit for bit);
+    the result is linear in (Qbar', Xbar'); a state reached by steps."""
+    mesh, Q0 = _case("vortex", 2)
+    g = _solver(mesh, Q0, 2)
+    g.step_gts(10.0, 2)
+    Q, X, _ = g.download()
+    o = GTSSolver(X, mesh.tris, Q, OConfig(M=2, levels=1, mesh_velocity="lagrangian"), bedges=mesh.bedges)
+    dt = 0.5 * float(o.dtcfl.min())
+    rng = np.random.default_rng(5)
+    qb = rng.standard_normal(Q.shape)
+    xb = rng.standard_normal(X.shape)
+    a = [t.cpu().numpy() for t in g.adjoint_lagrangian_step(dt, qb, xb)]
+    b = [t.cpu().numpy() for t in g.adjoint_lagrangian_step(dt, qb, xb, q=Q, x=X)]
+    for u, w in zip(a, b):
+        assert np.array_equal(u, w)
+    c = [t.cpu().numpy() for t in g.adjoint_lagrangian_step(dt, 2.0 * qb, -3.0 * xb)]
+    d = [t.cpu().numpy() for t in g.adjoint_lagrangian_step(dt, 0.0 * qb, xb)]
+    e = [t.cpu().numpy() for t in g.adjoint_lagrangian_step(dt, qb, 0.0 * xb)]
+    for k in range(2):
+        lin = 2.0 * e[k] - 3.0 * d[k]
+        assert np.abs(c[k] - lin).max() <= 1e-12 * np.abs(lin).max()
+        assert np.abs(a[k] - (d[k] + e[k])).max() <= 1e-12 * np.abs(a[k]).max()
+    # the stencils are fixed on the initial mesh (the context's), not rebuilt on X
+    o0 = GTSSolver(mesh.nodes, mesh.tris, Q0, OConfig(M=2, levels=1, mesh_velocity="lagrangian"),
+                   bedges=mesh.bedges)
+    st = LagrangianStep(X, mesh.tris, OConfig(M=2, levels=1, mesh_velocity="lagrangian"), bedges=mesh.bedges,
+                        topo=o0.topo)
+    rq, rx = st.vjp(Q, X, dt, qb, xb)
+    assert _rel(a[0].T, rq) < TOL and _rel(a[1], rx) < TOL
+
+
+def test_lagrangian_adjoint_central_differences_and_translation():
+    """20k-triangle explosion, M=2: <Qbar, v> + <Xbar, y> against central
+    differences of the forward map the same entry point returns (h = 1e-7
+    relative), in the averages, the positions and both; the position adjoints
+    sum to the sum of Xbar' (translation invariance)."""
+    mesh, Q0 = explosion_case(20000, seed=9)
+    rng = np.random.default_rng(6)
+    Q0 = Q0 * (1.0 + 1e-3 * rng.standard_normal(Q0.shape))
+    print(f"lagrangian adjoint FD: {mesh.n_elems} triangles", flush=True)
+    g = _solver(mesh, Q0, 2)
+    o = GTSSolver(mesh.nodes, mesh.tris, Q0, OConfig(M=2, levels=1, mesh_velocity="lagrangian"),
+                  bedges=mesh.bedges)
+    dt = 0.5 * float(o.dtcfl.min())
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    gq, gx, _, _ = (t.cpu().numpy() for t in g.adjoint_lagrangian_step(dt, qb, xb))
+    gq = gq.T
+    assert np.abs(gx.sum(axis=0) - xb.sum(axis=0)).max() <= 1e-11 * np.abs(gx).sum(axis=0).max()
+
+    def F(Q, X):
+        _, _, q1, x1 = g.adjoint_lagrangian_step(dt, qb, xb, q=Q, x=X)
+        return q1.cpu().numpy().T, x1.cpu().numpy()
+
+    h = 1e-7
+    span = np.ptp(mesh.nodes)
+    for k, (wq, wx) in enumerate(((1, 1), (1, 0), (0, 1))):
+        v = wq * rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=0)
+        y = wx * rng.standard_normal(mesh.nodes.shape) * 1e-3 * span
+        Qp, Xp = F(Q0 + h * v, mesh.nodes + h * y)
+        Qm, Xm = F(Q0 - h * v, mesh.nodes - h * y)
+        fd = (((Qp - Qm) * qb).sum() + ((Xp - Xm) * xb).sum()) / (2 * h)
+        ad = (gq * v).sum() + (gx * y).sum()
+        scale = np.abs(gq * v).sum() + np.abs(gx * y).sum()
+        print(f"direction {k}: fd {fd:.12e} adjoint {ad:.12e} rel {abs(fd - ad) / scale:.2e}", flush=True)
+        assert abs(fd - ad) <= 1e-6 * scale, (k, fd, ad)
+
+
+def test_lagrangian_adjoint_rejects_unsupported_modes():
+    from paper_1408_3719_amd import AderError
+    mesh, Q0 = _case("vortex", 2)
+    qb = np.zeros(Q0.shape)
+    xb = np.zeros(mesh.nodes.shape)
+    for kw in ({"velocity": "eulerian"}, {"flux": "hll"}):
+        g = _solver(mesh, Q0, 2, **kw)
+        with pytest.raises(AderError):
+            g.adjoint_lagrangian_step(1e-4, qb, xb)
+    mesh, Q0 = _case("sod", 2)                 # slip walls
+    g = _solver(mesh, Q0, 2)
+    with pytest.raises(AderError, match="slip"):
+        g.adjoint_lagrangian_step(1e-4, np.zeros(Q0.shape), np.zeros(mesh.nodes.shape))
+    g = _solver(*_case("vortex", 2), 2)
+    with pytest.raises(AderError, match="dt"):
+        g.adjoint_lagrangian_step(-1.0, qb, xb)
