@@ -403,6 +403,45 @@ def adjoint_step_ratio(n_elems: int = 50_000, M: int = 2, reps: int = 20):
             "workload": f"one global step on the {mesh.n_elems}-triangle explosion, fixed mesh, M={M}"}
 
 
+def lagrangian_adjoint_step_ratio(n_elems: int = 50_000, M: int = 2, reps: int = 20):
+    """One adjoint step of the moving-mesh global step (averages and node
+    positions differentiated, ader_adjoint_lagrangian_step) against one forward
+    Lagrangian global step from the same state, explosion recipe, dt = half
+    the smallest CFL step."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3719_amd import Config, Solver
+    from workloads import explosion_case
+    mesh, Q0 = explosion_case(n_elems, seed=7)
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=1, mesh_velocity="lagrangian"))
+    dt = 0.5 * float(s.dump("DTCFL").min())
+    rng = np.random.default_rng(0)
+    qb = torch.tensor(rng.standard_normal((4, mesh.n_elems)), device="cuda")
+    xb = torch.tensor(rng.standard_normal((mesh.n_nodes, 2)), device="cuda")
+    sync = torch.cuda.synchronize
+    for _ in range(3):
+        s.adjoint_lagrangian_step(dt, qb, xb)
+        s.upload_state(Q0, 0.0)
+        s.step_gts(dt, 1)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.adjoint_lagrangian_step(dt, qb, xb)
+    sync()
+    ms_adj = (time.perf_counter() - t0) / reps * 1e3
+    ms_fwd = 0.0
+    for _ in range(reps):
+        s.upload_state(Q0, 0.0)
+        sync()
+        t0 = time.perf_counter()
+        s.step_gts(dt, 1)
+        sync()
+        ms_fwd += (time.perf_counter() - t0) / reps * 1e3
+    return {"value": ms_adj / ms_fwd, "adjoint_ms": ms_adj, "forward_ms": ms_fwd,
+            "workload": f"one global step on the {mesh.n_elems}-triangle explosion, Lagrangian mesh, M={M}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -610,10 +649,12 @@ def main():
         sync()
     del s
 
-    adj = None
+    adj = adj_lag = None
     if a.adjoint:
         adj = adjoint_step_ratio()
         note(f"adjoint/forward per step {adj['value']:.3f}")
+        adj_lag = lagrangian_adjoint_step_ratio()
+        note(f"moving-mesh adjoint/forward per step {adj_lag['value']:.3f}")
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -648,6 +689,7 @@ def main():
         "gts_over_lts_updates": gts_updates / max(lts_updates, 1),
         "free_steps": free,
         "adjoint_forward": adj,
+        "adjoint_lagrangian_forward": adj_lag,
         "autotune": tune,
         "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},

@@ -294,7 +294,9 @@ int ader_adjoint_gts_step_static(ader_ctx* ctx, double dt, const double* Q_dev,
  *   work_dev: caller device memory of at least
  *     ader_adjoint_lagrangian_workspace_size bytes, 256-byte aligned, scratch
  *     of the call only.  No output may overlap an input.
- * ADER_E_ARG for another mesh velocity or flux, slip-wall edges, a batch of
+ * Slip walls: the outer state is the mirrored inner one (its dependence on the
+ * patch normal included) and wall nodes slide or stay pinned as in the
+ * forward step.  ADER_E_ARG for another mesh velocity or flux, a batch of
  * instances, a workspace too small; ADER_E_ORDER before a state upload.
  * Queued on the context's stream; no synchronisation.  With dt at most the
  * smallest CFL step, the step that ader_step_gts(ctx, t + dt, 1, ...) takes

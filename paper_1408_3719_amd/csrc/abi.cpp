@@ -1168,8 +1168,6 @@ int ader_adjoint_lagrangian_step(ader_ctx* c, double dt, const double* Q_dev, co
     return fail(c, ADER_E_ARG, "the moving-mesh adjoint needs the Lagrangian mesh (mesh_velocity = 0)");
   if (c->cfg.flux != ADER_FLUX_RUSANOV) return fail(c, ADER_E_ARG, "the moving-mesh adjoint covers the Rusanov flux");
   if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the adjoint runs on a single instance");
-  for (int e = 0; e < c->topo.NF; ++e)
-    if (c->topo.e_bc[e] == 2) return fail(c, ADER_E_ARG, "the moving-mesh adjoint does not cover slip walls");
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if ((!Q_dev || !X_dev) && !c->synced)
     return fail(c, ADER_E_ORDER, "elements are not at a common time (macro step in progress)");

@@ -1057,19 +1057,201 @@ __global__ void __launch_bounds__(TPB) k_lag_geom(Dev d, LagWork w, int x_from_c
   }
 }
 
-// Predictor with the mesh ODE, every iterate kept; traces, means, vertex velocities.
+// Orders LDS accesses among the lanes of one wavefront (the lanes of an
+// element's predictor always share one, and the LDS serves a wavefront's
+// accesses in issue order, so only the compiler's reordering is fenced).
+__device__ inline void lag_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane layout of the moving-mesh predictor kernels: one lane per spatial node
+// of the nodal basis, floor(64 / nb) elements per wavefront (the spare lanes
+// of a wavefront exchange into a slot of their own); LDS holds NX values per
+// node of each element.
+template <int M>
+struct LP {
+  static constexpr int nb = (M + 1) * (M + 2) / 2, T = M + 1, nG = M + 1, G = nb;
+  static constexpr int EPW = 64 / nb, WPB = TPB / 64, SLOTS = EPW * WPB;
+  static constexpr int NX = 28;
+  static constexpr int LSTR = NX * G + 2;
+  static constexpr int QS = nb * T * 4;
+};
+
+// Predictor with the mesh ODE (eqs. CGfinal, VCG, newVertPos), one lane per
+// spatial node: each node's space-time values and trajectory stay in its
+// lane, the spatial derivatives at a node take the element's other nodes
+// through LDS. Every iterate is kept (element-minor) for the reverse sweeps;
+// traces, means and vertex velocities as in the forward step.
 template <int M>
 __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __restrict__ tb, Params P,
                                                       LagWork w, double dt) {
   using S = AZ<M>;
+  using L = LP<M>;
+  constexpr int nb = L::nb, T = L::T, nG = L::nG, G = L::G, EPW = L::EPW, SLOTS = L::SLOTS, QS = L::QS;
+  constexpr int NPT = 1 + 3 * nG;
+  __shared__ double lds[(SLOTS + L::WPB) * L::LSTR];
   const int NE = d.NE;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
-    double xe[6];
+  const double gam = P.gamma;
+  const int wv = threadIdx.x / 64, lw = threadIdx.x % 64;
+  const bool spare = lw >= EPW * G;
+  const int slot = spare ? SLOTS + wv : wv * EPW + lw / G;
+  const int m = spare ? lw - EPW * G : lw % G;
+  double* const my = lds + slot * L::LSTR;
+  double Dx[nb], De[nb];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) xe[c] = w.xe[size_t(i) * 6 + c];
-    lag::pred_fwd<M>(*tb, P.gamma, P.npic, w.a.wnod + size_t(i) * S::WS, xe, dt, w.keep + i, size_t(NE),
-                     w.a.trace + size_t(i) * S::TS, w.a.avg + size_t(i) * S::T * 4,
-                     w.vvel + size_t(i) * 6 * S::T);
+  for (int k = 0; k < nb; ++k) {
+    Dx[k] = tb->Dxi[m][k];
+    De[k] = tb->Deta[m][k];
+  }
+  double nxi, neta;
+  lag::lattice<M>(m, nxi, neta);
+  for (int base = blockIdx.x * SLOTS; base < NE; base += gridDim.x * SLOTS) {
+    const int i = spare ? -1 : base + slot;
+    const bool live = i >= 0 && i < NE;
+    double q[T][4], x[T][2], x0[2];
+    if (live) {
+      const double* X = w.xe + size_t(i) * 6;
+      x0[0] = X[0] + (X[2] - X[0]) * nxi + (X[4] - X[0]) * neta;
+      x0[1] = X[1] + (X[3] - X[1]) * nxi + (X[5] - X[1]) * neta;
+      const double* wn = w.a.wnod + size_t(i) * S::WS + m * 4;
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q[t][v] = wn[v];
+    } else {
+      // idle lanes: the reference triangle at rest
+      x0[0] = nxi;
+      x0[1] = neta;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        q[t][0] = 1.0;
+        q[t][1] = q[t][2] = 0.0;
+        q[t][3] = 2.5;
+      }
+    }
+#pragma unroll 1
+    for (int k = 0; k < P.npic; ++k) {
+      if (live) {
+        double* kp = w.keep + size_t(k) * QS * NE + i;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) kp[size_t((m * T + t) * 4 + v) * NE] = q[t][v];
+      }
+      // mesh ODE of this node
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        x[0][c] = x0[c];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < T; ++t) s += tb->At[r][t] * q[t][1 + c] / q[t][0];
+          x[r + 1][c] = tb->Bt[r] * x0[c] + dt * s;
+        }
+      }
+      double qn[M][4];
+#pragma unroll
+      for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qn[r][v] = tb->Bt[r] * q[0][v];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        double f[4], g[4];
+        lag::euler_f_g(q[t], gam, f, g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          my[v * G + m] = q[t][v];
+          my[(4 + v) * G + m] = f[v];
+          my[(8 + v) * G + m] = g[v];
+        }
+        my[12 * G + m] = x[t][0];
+        my[13 * G + m] = x[t][1];
+        lag_wave_sync();
+        double xx = 0, xe = 0, yx = 0, ye = 0;
+#pragma unroll
+        for (int kk = 0; kk < nb; ++kk) {
+          xx += Dx[kk] * my[12 * G + kk];
+          xe += De[kk] * my[12 * G + kk];
+          yx += Dx[kk] * my[13 * G + kk];
+          ye += De[kk] * my[13 * G + kk];
+        }
+        double xtau = 0, ytau = 0;
+#pragma unroll
+        for (int r = 0; r < T; ++r) {
+          xtau += tb->Dt[t][r] * x[r][0];
+          ytau += tb->Dt[t][r] * x[r][1];
+        }
+        const double det = xx * ye - xe * yx;
+        const double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
+        const double xt = xtau / dt, yt = ytau / dt;
+        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double dqx = 0, dqe = 0, dfx = 0, dfe = 0, dgx = 0, dge = 0;
+#pragma unroll
+          for (int kk = 0; kk < nb; ++kk) {
+            dqx += Dx[kk] * my[v * G + kk];
+            dqe += De[kk] * my[v * G + kk];
+            dfx += Dx[kk] * my[(4 + v) * G + kk];
+            dfe += De[kk] * my[(4 + v) * G + kk];
+            dgx += Dx[kk] * my[(8 + v) * G + kk];
+            dge += De[kk] * my[(8 + v) * G + kk];
+          }
+          const double Pv = -(dqx * xi_t + dqe * eta_t + dfx * xi_x + dfe * eta_x + dgx * xi_y + dge * eta_y);
+#pragma unroll
+          for (int r = 0; r < M; ++r) qn[r][v] += dt * tb->At[r][t] * Pv;
+        }
+        lag_wave_sync();
+      }
+#pragma unroll
+      for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q[r + 1][v] = qn[r][v];
+    }
+    if (live) {
+      double* kp = w.keep + size_t(P.npic) * QS * NE + i;
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) kp[size_t((m * T + t) * 4 + v) * NE] = q[t][v];
+#pragma unroll
+      for (int kv = 0; kv < 3; ++kv) {
+        if (tb->vtx[kv] != m) continue;
+        double* vv = w.vvel + (size_t(i) * 3 + kv) * T * 2;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          vv[2 * t] = q[t][1] / q[t][0];
+          vv[2 * t + 1] = q[t][2] / q[t][0];
+        }
+      }
+    }
+    // cell means and edge traces, one time slice at a time through LDS; lane m
+    // evaluates points m, m + G, ... (point 0 the mean, 1 + e nG + gq the Gauss
+    // point gq of edge e)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) my[v * G + m] = q[t][v];
+      lag_wave_sync();
+      if (live) {
+        for (int pt = m; pt < NPT; pt += G) {
+          const double* c = pt == 0 ? tb->amean : tb->edge[(pt - 1) / nG][(pt - 1) % nG];
+          double* out = pt == 0 ? w.a.avg + size_t(i) * T * 4 + t * 4
+                                : w.a.trace + size_t(i) * S::TS + ((pt - 1) * T + t) * 4;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < nb; ++kk) s += c[kk] * my[v * G + kk];
+            out[v] = s;
+          }
+        }
+      }
+      lag_wave_sync();
+    }
   }
 }
 
@@ -1134,7 +1316,7 @@ __global__ void __launch_bounds__(TPB) k_lag_area_new(Dev d, LagWork w) {
 }
 
 // Per edge: the patch flux (into the two (element, edge) slots, inflow
-// positive) and its adjoint for Gbar = -Qbar'_L / |T_L'| + Qbar'_R / |T_R'|
+// positive) and, in the same pass, its adjoint for Gbar = -Qbar'_L / |T_L'| + Qbar'_R / |T_R'|
 // onto the traces, the inner element's means (transmissive edge) and the
 // four corners.
 template <int M>
@@ -1147,40 +1329,33 @@ __global__ void __launch_bounds__(TPB) k_lag_patch(Dev d, const Tables* __restri
     const int a = d.e_a[e], b = d.e_b[e];
     const int L = d.e_L[e], el = d.e_el[e], R = d.e_R[e], er = d.e_er[e];
     const bool hasR = R >= 0;
+    const int kind = hasR ? lag::INTERIOR : (d.e_bc[e] == 2 ? lag::SLIP : lag::TRANSMISSIVE);
     const double xa[2] = {w.x[2 * a], w.x[2 * a + 1]}, xb[2] = {w.x[2 * b], w.x[2 * b + 1]};
     const double xan[2] = {w.xn[2 * a], w.xn[2 * a + 1]}, xbn[2] = {w.xn[2 * b], w.xn[2 * b + 1]};
     const double* trL = w.a.trace + size_t(L) * TS + el * NT;
     const double* trR = hasR ? w.a.trace + size_t(R) * TS + er * NT : trL;
     const double* avL = w.a.avg + size_t(L) * T * 4;
-    double G[4];
-    lag::patch_flux<M>(*tb, P.gamma, xa, xb, xan, xbn, dt, trL, trR, avL, hasR, G);
     double Gb[4];
     const double anL = w.an[L], anR = hasR ? w.an[R] : 1.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      w.gslot[(size_t(L) * 3 + el) * 4 + v] = -G[v];
       Gb[v] = -w.a.qbar_next[size_t(v) * NE + L] / anL;
-      if (hasR) {
-        w.gslot[(size_t(R) * 3 + er) * 4 + v] = G[v];
-        Gb[v] += w.a.qbar_next[size_t(v) * NE + R] / anR;
-      }
+      if (hasR) Gb[v] += w.a.qbar_next[size_t(v) * NE + R] / anR;
     }
-    double bL[NT], bR[NT], bA[T * 4];
-#pragma unroll
-    for (int k = 0; k < NT; ++k) bL[k] = bR[k] = 0.0;
+    double G[4] = {0.0, 0.0, 0.0, 0.0}, bA[T * 4];
 #pragma unroll
     for (int k = 0; k < T * 4; ++k) bA[k] = 0.0;
     double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    lag::patch_flux_vjp<M>(*tb, P.gamma, xa, xb, xan, xbn, dt, trL, trR, avL, hasR, Gb, bL, bR, bA, c, c + 2,
-                           c + 4, c + 6);
     double* oL = w.a.tbar + size_t(L) * TS + el * NT;
+    double* oR = hasR ? w.a.tbar + size_t(R) * TS + er * NT : oL;
+    lag::patch_flux_vjp<M>(*tb, P.gamma, xa, xb, xan, xbn, dt, trL, trR, avL, kind, Gb, G, oL, oR, bA, c, c + 2,
+                           c + 4, c + 6);
 #pragma unroll
-    for (int k = 0; k < NT; ++k) oL[k] = bL[k];
-    if (hasR) {
-      double* oR = w.a.tbar + size_t(R) * TS + er * NT;
-#pragma unroll
-      for (int k = 0; k < NT; ++k) oR[k] = bR[k];
-    } else {
+    for (int v = 0; v < 4; ++v) {
+      w.gslot[(size_t(L) * 3 + el) * 4 + v] = -G[v];
+      if (hasR) w.gslot[(size_t(R) * 3 + er) * 4 + v] = G[v];
+    }
+    if (kind == lag::TRANSMISSIVE) {
       double* aL = w.a.abar + size_t(e) * T * 4;
 #pragma unroll
       for (int k = 0; k < T * 4; ++k) aL[k] = bA[k];
@@ -1288,52 +1463,333 @@ __global__ void __launch_bounds__(TPB) k_lag_node_rev(Dev d, const Tables* __res
   }
 }
 
-// Predictor in reverse per element: adjoints of the traces, of the means
-// (transmissive edges) and of the vertex velocities -> the reconstruction's
-// nodal values and the element's vertices; the ring masses rho |T|.
+// Predictor in reverse, one lane per spatial node as in k_lag_pred_fwd: the
+// adjoints of the traces, of the means (transmissive edges) and of the vertex
+// velocities -> those of the reconstruction's nodal values and of the
+// element's vertices; the ring masses rho |T| (qdir, vertices through the
+// area). Per sweep and time node the lanes exchange their forward fields,
+// then the products their node's equation sends to the other nodes (the
+// transposed spatial derivatives).
 template <int M>
 __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __restrict__ tb, Params P,
                                                       LagWork w, double dt) {
   using S = AZ<M>;
-  constexpr int T = S::T;
+  using L = LP<M>;
+  constexpr int nb = L::nb, T = L::T, nG = L::nG, G = L::G, EPW = L::EPW, SLOTS = L::SLOTS, QS = L::QS;
+  __shared__ double lds[(SLOTS + L::WPB) * L::LSTR];
   const int NE = d.NE;
+  const double gam = P.gamma;
+  const int wv = threadIdx.x / 64, lw = threadIdx.x % 64;
+  const bool spare = lw >= EPW * G;
+  const int slot = spare ? SLOTS + wv : wv * EPW + lw / G;
+  const int m = spare ? lw - EPW * G : lw % G;
+  double* const my = lds + slot * L::LSTR;
+  // this node's rows (its derivatives) and columns (its share of the others')
+  double Dx[nb], De[nb], DxT[nb], DeT[nb];
+#pragma unroll
+  for (int k = 0; k < nb; ++k) {
+    Dx[k] = tb->Dxi[m][k];
+    De[k] = tb->Deta[m][k];
+    DxT[k] = tb->Dxi[k][m];
+    DeT[k] = tb->Deta[k][m];
+  }
   double I[T];
   lag::tint01<M>(*tb, I);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
-    double ab[T * 4];
+  double nxi, neta;
+  lag::lattice<M>(m, nxi, neta);
+  for (int base = blockIdx.x * SLOTS; base < NE; base += gridDim.x * SLOTS) {
+    const int i = spare ? -1 : base + slot;
+    const bool live = i >= 0 && i < NE;
+    double x0[2], qb[T][4];
+    if (live) {
+      const double* X = w.xe + size_t(i) * 6;
+      x0[0] = X[0] + (X[2] - X[0]) * nxi + (X[4] - X[0]) * neta;
+      x0[1] = X[1] + (X[3] - X[1]) * nxi + (X[5] - X[1]) * neta;
+      // adjoint of the final iterate at this node: traces, means, vertex velocity
+      double ab[T][4];
 #pragma unroll
-    for (int k = 0; k < T * 4; ++k) ab[k] = 0.0;
+      for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int le = 0; le < 3; ++le) {
-      const int e = d.elem_edges[le * NE + i];
-      if (d.e_R[e] < 0) {
-        const double* a = w.a.abar + size_t(e) * T * 4;
+        for (int v = 0; v < 4; ++v) ab[t][v] = 0.0;
 #pragma unroll
-        for (int k = 0; k < T * 4; ++k) ab[k] += a[k];
+      for (int le = 0; le < 3; ++le) {
+        const int e = d.elem_edges[le * NE + i];
+        if (d.e_R[e] < 0 && d.e_bc[e] != 2) {
+          const double* a = w.a.abar + size_t(e) * T * 4;
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ab[t][v] += a[t * 4 + v];
+        }
+      }
+      const double* tbi = w.a.tbar + size_t(i) * S::TS;
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double s = tb->amean[m] * ab[t][v];
+#pragma unroll
+          for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int gq = 0; gq < nG; ++gq) s += tb->edge[e][gq][m] * tbi[((e * nG + gq) * T + t) * 4 + v];
+          qb[t][v] = s;
+        }
+#pragma unroll
+      for (int kv = 0; kv < 3; ++kv) {
+        if (tb->vtx[kv] != m) continue;
+        const double* o = w.nslot + (size_t(i) * 3 + kv) * 3;
+        const double* kp = w.keep + size_t(P.npic) * QS * NE + i;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const double q0 = kp[size_t((m * T + t) * 4 + 0) * NE];
+          const double q1 = kp[size_t((m * T + t) * 4 + 1) * NE];
+          const double q2 = kp[size_t((m * T + t) * 4 + 2) * NE];
+          const double vxb = I[t] * o[0], vyb = I[t] * o[1];
+          qb[t][0] -= (vxb * q1 + vyb * q2) / (q0 * q0);
+          qb[t][1] += vxb / q0;
+          qb[t][2] += vyb / q0;
+        }
+      }
+    } else {
+      x0[0] = nxi;
+      x0[1] = neta;
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qb[t][v] = 0.0;
+    }
+    double x0b[2] = {0.0, 0.0};
+#pragma unroll 1
+    for (int k = P.npic - 1; k >= 0; --k) {
+      double q[T][4];
+      if (live) {
+        const double* kp = w.keep + size_t(k) * QS * NE + i;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) q[t][v] = kp[size_t((m * T + t) * 4 + v) * NE];
+      } else {
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          q[t][0] = 1.0;
+          q[t][1] = q[t][2] = 0.0;
+          q[t][3] = 2.5;
+        }
+      }
+      // this node's trajectory in the sweep
+      double x[T][2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        x[0][c] = x0[c];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < T; ++t) s += tb->At[r][t] * q[t][1 + c] / q[t][0];
+          x[r + 1][c] = tb->Bt[r] * x0[c] + dt * s;
+        }
+      }
+      // q_out[0] = q[0]; q_out[r+1] = Bt[r] q[0] + dt sum_t At[r][t] P[t]
+      double qi[T][4], Pb[T][4], xb[T][2];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double s = qb[0][v];
+#pragma unroll
+        for (int r = 0; r < M; ++r) s += tb->Bt[r] * qb[r + 1][v];
+        qi[0][v] = s;
+#pragma unroll
+        for (int t = 1; t < T; ++t) qi[t][v] = 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          double p = 0.0;
+#pragma unroll
+          for (int r = 0; r < M; ++r) p += tb->At[r][t] * qb[r + 1][v];
+          Pb[t][v] = dt * p;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) xb[t][0] = xb[t][1] = 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        double f[4], g[4];
+        lag::euler_f_g(q[t], gam, f, g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          my[v * G + m] = q[t][v];
+          my[(4 + v) * G + m] = f[v];
+          my[(8 + v) * G + m] = g[v];
+        }
+        my[12 * G + m] = x[t][0];
+        my[13 * G + m] = x[t][1];
+        lag_wave_sync();
+        double xx = 0, xe = 0, yx = 0, ye = 0;
+#pragma unroll
+        for (int kk = 0; kk < nb; ++kk) {
+          xx += Dx[kk] * my[12 * G + kk];
+          xe += De[kk] * my[12 * G + kk];
+          yx += Dx[kk] * my[13 * G + kk];
+          ye += De[kk] * my[13 * G + kk];
+        }
+        double xtau = 0, ytau = 0;
+#pragma unroll
+        for (int r = 0; r < T; ++r) {
+          xtau += tb->Dt[t][r] * x[r][0];
+          ytau += tb->Dt[t][r] * x[r][1];
+        }
+        const double det = xx * ye - xe * yx;
+        const double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
+        const double xt = xtau / dt, yt = ytau / dt;
+        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
+        double xitb = 0, etatb = 0, xixb = 0, xiyb = 0, etaxb = 0, etayb = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double dqx = 0, dqe = 0, dfx = 0, dfe = 0, dgx = 0, dge = 0;
+#pragma unroll
+          for (int kk = 0; kk < nb; ++kk) {
+            dqx += Dx[kk] * my[v * G + kk];
+            dqe += De[kk] * my[v * G + kk];
+            dfx += Dx[kk] * my[(4 + v) * G + kk];
+            dfe += De[kk] * my[(4 + v) * G + kk];
+            dgx += Dx[kk] * my[(8 + v) * G + kk];
+            dge += De[kk] * my[(8 + v) * G + kk];
+          }
+          const double pb = Pb[t][v];
+          xitb -= pb * dqx;
+          etatb -= pb * dqe;
+          xixb -= pb * dfx;
+          etaxb -= pb * dfe;
+          xiyb -= pb * dgx;
+          etayb -= pb * dge;
+        }
+        // xi_t = -(xi_x xt + xi_y yt), eta_t = -(eta_x xt + eta_y yt)
+        xixb -= xitb * xt;
+        xiyb -= xitb * yt;
+        etaxb -= etatb * xt;
+        etayb -= etatb * yt;
+        const double xtb = -(xitb * xi_x + etatb * eta_x), ytb = -(xitb * xi_y + etatb * eta_y);
+        const double detb = -(xixb * xi_x + xiyb * xi_y + etaxb * eta_x + etayb * eta_y) / det;
+        const double xxb = etayb / det + detb * ye;
+        const double yeb = xixb / det + detb * xx;
+        const double xeb = -xiyb / det - detb * yx;
+        const double yxb = -etaxb / det - detb * xe;
+#pragma unroll
+        for (int r = 0; r < T; ++r) {
+          xb[r][0] += tb->Dt[t][r] * xtb / dt;
+          xb[r][1] += tb->Dt[t][r] * ytb / dt;
+        }
+        lag_wave_sync();
+        // what this node's equation sends to every node: the transposed sums
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double pb = Pb[t][v];
+          my[v * G + m] = pb * xi_t;
+          my[(4 + v) * G + m] = pb * eta_t;
+          my[(8 + v) * G + m] = pb * xi_x;
+          my[(12 + v) * G + m] = pb * eta_x;
+          my[(16 + v) * G + m] = pb * xi_y;
+          my[(20 + v) * G + m] = pb * eta_y;
+        }
+        my[24 * G + m] = xxb;
+        my[25 * G + m] = xeb;
+        my[26 * G + m] = yxb;
+        my[27 * G + m] = yeb;
+        lag_wave_sync();
+        double fb[4], gb[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double sq = 0.0, sf = 0.0, sg = 0.0;
+#pragma unroll
+          for (int kk = 0; kk < nb; ++kk) {
+            sq += DxT[kk] * my[v * G + kk] + DeT[kk] * my[(4 + v) * G + kk];
+            sf += DxT[kk] * my[(8 + v) * G + kk] + DeT[kk] * my[(12 + v) * G + kk];
+            sg += DxT[kk] * my[(16 + v) * G + kk] + DeT[kk] * my[(20 + v) * G + kk];
+          }
+          qi[t][v] -= sq;
+          fb[v] = -sf;
+          gb[v] = -sg;
+        }
+        {
+          double sx = 0.0, sy = 0.0;
+#pragma unroll
+          for (int kk = 0; kk < nb; ++kk) {
+            sx += DxT[kk] * my[24 * G + kk] + DeT[kk] * my[25 * G + kk];
+            sy += DxT[kk] * my[26 * G + kk] + DeT[kk] * my[27 * G + kk];
+          }
+          xb[t][0] += sx;
+          xb[t][1] += sy;
+        }
+        lag::euler_f_g_vjp(q[t], gam, fb, gb, qi[t]);
+        lag_wave_sync();
+      }
+      // mesh ODE of this node in reverse: x[0] = x0, x[r+1] = Bt[r] x0 + dt sum_t At[r][t] V[t]
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double s = xb[0][c];
+#pragma unroll
+        for (int r = 0; r < M; ++r) s += tb->Bt[r] * xb[r + 1][c];
+        x0b[c] += s;
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        double vb[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int r = 0; r < M; ++r) s += tb->At[r][t] * xb[r + 1][c];
+          vb[c] = dt * s;
+        }
+        qi[t][0] -= (vb[0] * q[t][1] + vb[1] * q[t][2]) / (q[t][0] * q[t][0]);
+        qi[t][1] += vb[0] / q[t][0];
+        qi[t][2] += vb[1] / q[t][0];
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qb[t][v] = qi[t][v];
+    }
+    // the first iterate repeats the reconstruction at every time node
+    if (live) {
+      double* wb = w.a.wbar + size_t(i) * S::WS + m * 4;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) s += qb[t][v];
+        wb[v] = s;
       }
     }
-    double vvb[3 * T * 2], mub = 0.0;
+    // x0 = (1 - xi - eta) X0 + xi X1 + eta X2: the element's vertex adjoints,
+    // summed over its nodes by lane 0
+    const double bw[3] = {1.0 - nxi - neta, nxi, neta};
 #pragma unroll
-    for (int lv = 0; lv < 3; ++lv) {
-      const double* o = w.nslot + (size_t(i) * 3 + lv) * 3;
-#pragma unroll
-      for (int q = 0; q < T; ++q) {
-        vvb[(lv * T + q) * 2] = I[q] * o[0];
-        vvb[(lv * T + q) * 2 + 1] = I[q] * o[1];
-      }
-      mub += o[2];
+    for (int c = 0; c < 3; ++c) {
+      my[(2 * c) * G + m] = bw[c] * x0b[0];
+      my[(2 * c + 1) * G + m] = bw[c] * x0b[1];
     }
-    double xe[6], xb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    lag_wave_sync();
+    if (live && m == 0) {
+      double xb6[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) xe[c] = w.xe[size_t(i) * 6 + c];
-    lag::pred_rev<M>(*tb, P.gamma, P.npic, xe, dt, w.keep + i, size_t(NE), w.a.tbar + size_t(i) * S::TS, ab, vvb,
-                     w.a.wbar + size_t(i) * S::WS, xb);
-    // mu = rho |T|
-    const double A = w.area[i];
-    w.qdir[i] += mub * A;
-    lag::area3_grad(xe, mub * w.a.q[i], xb);
+      for (int c = 0; c < 6; ++c) {
+        double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) w.a.xeb[size_t(i) * 6 + c] += xb[c];
+        for (int kk = 0; kk < nb; ++kk) s += my[c * G + kk];
+        xb6[c] = s;
+      }
+      // mu = rho |T| of the ring means
+      double mub = 0.0;
+#pragma unroll
+      for (int kv = 0; kv < 3; ++kv) mub += w.nslot[(size_t(i) * 3 + kv) * 3 + 2];
+      double xe[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) xe[c] = w.xe[size_t(i) * 6 + c];
+      w.qdir[i] += mub * w.area[i];
+      lag::area3_grad(xe, mub * w.a.q[i], xb6);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) w.a.xeb[size_t(i) * 6 + c] += xb6[c];
+    }
+    lag_wave_sync();
   }
 }
 
@@ -1385,19 +1841,28 @@ int adjoint_gts(const Dev& d, const Params& p, const AdjWork& w, double dt, bool
   return 0;
 }
 
+#define AD_LAUNCH_BLOCKS(kern, blocks, stream, ...)                                          \
+  do {                                                                                       \
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(TPB), 0, (hipStream_t)(stream), __VA_ARGS__); \
+    hipError_t _e = hipGetLastError();                                                       \
+    if (_e != hipSuccess) return int(_e);                                                    \
+  } while (0)
+
 template <int M>
 int adjoint_lagrangian(const Dev& d, const Params& p, LagWork w, double dt, bool qctx, bool xctx, void* s) {
+  long pb = (long(d.NE) + LP<M>::SLOTS - 1) / LP<M>::SLOTS;   // predictor blocks: SLOTS elements each
+  if (pb > 16384) pb = 16384;
   if (qctx) w.a.q = w.a.qcopy;
   if (xctx) w.x = w.xcopy;
   AD_LAUNCH(k_lag_geom<M>, d.NE > d.NV ? d.NE : d.NV, s, d, w, int(xctx), int(qctx));
   AD_LAUNCH((k_adj_recon<M, false, true>), 8L * d.NE, s, d, d.tab, p, w.a);
-  AD_LAUNCH(k_lag_pred_fwd<M>, d.NE, s, d, d.tab, p, w, dt);
+  AD_LAUNCH_BLOCKS(k_lag_pred_fwd<M>, pb, s, d, d.tab, p, w, dt);
   AD_LAUNCH(k_lag_node_fwd<M>, d.NV, s, d, d.tab, w, dt);
   AD_LAUNCH(k_lag_area_new<M>, d.NE, s, d, w);
   AD_LAUNCH(k_lag_patch<M>, d.NF, s, d, d.tab, p, w, dt);
   AD_LAUNCH(k_lag_update_rev<M>, d.NE, s, d, w);
   AD_LAUNCH(k_lag_node_rev<M>, d.NV, s, d, d.tab, w, dt);
-  AD_LAUNCH(k_lag_pred_rev<M>, d.NE, s, d, d.tab, p, w, dt);
+  AD_LAUNCH_BLOCKS(k_lag_pred_rev<M>, pb, s, d, d.tab, p, w, dt);
   AD_LAUNCH((k_adj_recon<M, true, true>), 8L * d.NE, s, d, d.tab, p, w.a);
   AdjWork g = w.a;
   g.qbar_next = w.qdir;

@@ -1,9 +1,10 @@
-// Per-element and per-edge pieces of the adjoint of one global time step with
-// the mesh moving with the fluid (Lagrangian mode): the space-time predictor of
-// the PDE and the mesh ODE, the Rusanov flux over a bilinear space-time patch,
-// and the geometry part of a least-squares row of the reconstruction, each
-// with its vector-Jacobian product. Written for host and device so that the
-// products can be checked against central differences on the CPU.
+// Per-edge and per-row pieces of the adjoint of one global time step with the
+// mesh moving with the fluid (Lagrangian mode): the Rusanov flux through an
+// unnormalised space-time normal, the flux over a bilinear space-time patch
+// (interior, transmissive and slip-wall edges) and the geometry part of a
+// least-squares row of the reconstruction, each with its vector-Jacobian
+// product; triangle areas. Written for host and device so that the products
+// can be checked against central differences on the CPU.
 #pragma once
 
 #include <cmath>
@@ -22,7 +23,6 @@ namespace lag {
 template <int M>
 struct Dim {
   static constexpr int nb = (M + 1) * (M + 2) / 2, T = M + 1, nG = M + 1, nu = nb - 1;
-  static constexpr int QS = nb * T * 4;     // one predictor iterate
 };
 
 // Lattice point m of the nodal set (i/M, j/M), ordered by j then i.
@@ -98,292 +98,6 @@ AWHD inline void euler_f_g_vjp(const double q[4], double gam, const double fb[4]
 }
 
 // ------------------------------------------------------------------------
-// Predictor with the mesh ODE (eqs. CGfinal, VCG, newVertPos; V = v)
-// ------------------------------------------------------------------------
-// keep: the iterate before each of the npic sweeps and the final one,
-// keep[(k * QS + (m * T + t) * 4 + v) * ks], k = 0..npic.
-template <int M>
-AWHD inline void pred_fwd(const Tables& tb, double gam, int npic, const double* wnod, const double Xe[6],
-                          double dt, double* keep, size_t ks, double* trace, double* avg, double* vvel) {
-  using D = Dim<M>;
-  constexpr int nb = D::nb, T = D::T, nG = D::nG, QS = D::QS;
-  double q[nb][T][4], x0[nb][2];
-  for (int m = 0; m < nb; ++m) {
-    double xi, eta;
-    lattice<M>(m, xi, eta);
-    x0[m][0] = Xe[0] + (Xe[2] - Xe[0]) * xi + (Xe[4] - Xe[0]) * eta;
-    x0[m][1] = Xe[1] + (Xe[3] - Xe[1]) * xi + (Xe[5] - Xe[1]) * eta;
-    for (int t = 0; t < T; ++t)
-      for (int v = 0; v < 4; ++v) q[m][t][v] = wnod[m * 4 + v];
-  }
-  for (int k = 0; k < npic; ++k) {
-    for (int m = 0; m < nb; ++m)
-      for (int t = 0; t < T; ++t)
-        for (int v = 0; v < 4; ++v) keep[(size_t(k) * QS + (m * T + t) * 4 + v) * ks] = q[m][t][v];
-    // mesh ODE: x at the time nodes from x0 and V = v(q)
-    double x[nb][T][2];
-    for (int m = 0; m < nb; ++m) {
-      double V[T][2];
-      for (int s = 0; s < T; ++s) {
-        V[s][0] = q[m][s][1] / q[m][s][0];
-        V[s][1] = q[m][s][2] / q[m][s][0];
-      }
-      x[m][0][0] = x0[m][0];
-      x[m][0][1] = x0[m][1];
-      for (int t = 0; t < M; ++t)
-        for (int c = 0; c < 2; ++c) {
-          double s = tb.Bt[t] * x0[m][c];
-          for (int r = 0; r < T; ++r) s += dt * tb.At[t][r] * V[r][c];
-          x[m][t + 1][c] = s;
-        }
-    }
-    double P[nb][T][4];
-    for (int t = 0; t < T; ++t) {
-      double f[nb][4], g[nb][4];
-      for (int m = 0; m < nb; ++m) euler_f_g(q[m][t], gam, f[m], g[m]);
-      for (int kk = 0; kk < nb; ++kk) {
-        double xx = 0, xe = 0, yx = 0, ye = 0;
-        for (int m = 0; m < nb; ++m) {
-          xx += tb.Dxi[kk][m] * x[m][t][0];
-          xe += tb.Deta[kk][m] * x[m][t][0];
-          yx += tb.Dxi[kk][m] * x[m][t][1];
-          ye += tb.Deta[kk][m] * x[m][t][1];
-        }
-        double xtau = 0, ytau = 0;
-        for (int s = 0; s < T; ++s) {
-          xtau += tb.Dt[t][s] * x[kk][s][0];
-          ytau += tb.Dt[t][s] * x[kk][s][1];
-        }
-        const double det = xx * ye - xe * yx;
-        const double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
-        const double xt = xtau / dt, yt = ytau / dt;
-        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
-        for (int v = 0; v < 4; ++v) {
-          double dqx = 0, dqe = 0, dfx = 0, dfe = 0, dgx = 0, dge = 0;
-          for (int m = 0; m < nb; ++m) {
-            dqx += tb.Dxi[kk][m] * q[m][t][v];
-            dqe += tb.Deta[kk][m] * q[m][t][v];
-            dfx += tb.Dxi[kk][m] * f[m][v];
-            dfe += tb.Deta[kk][m] * f[m][v];
-            dgx += tb.Dxi[kk][m] * g[m][v];
-            dge += tb.Deta[kk][m] * g[m][v];
-          }
-          P[kk][t][v] = -(dqx * xi_t + dqe * eta_t + dfx * xi_x + dfe * eta_x + dgx * xi_y + dge * eta_y);
-        }
-      }
-    }
-    for (int m = 0; m < nb; ++m)
-      for (int t = 0; t < M; ++t)
-        for (int v = 0; v < 4; ++v) {
-          double s = tb.Bt[t] * q[m][0][v];
-          for (int r = 0; r < T; ++r) s += dt * tb.At[t][r] * P[m][r][v];
-          q[m][t + 1][v] = s;
-        }
-  }
-  for (int m = 0; m < nb; ++m)
-    for (int t = 0; t < T; ++t)
-      for (int v = 0; v < 4; ++v) keep[(size_t(npic) * QS + (m * T + t) * 4 + v) * ks] = q[m][t][v];
-  for (int e = 0; e < 3; ++e)
-    for (int gq = 0; gq < nG; ++gq)
-      for (int t = 0; t < T; ++t)
-        for (int v = 0; v < 4; ++v) {
-          double s = 0.0;
-          for (int m = 0; m < nb; ++m) s += tb.edge[e][gq][m] * q[m][t][v];
-          trace[((e * nG + gq) * T + t) * 4 + v] = s;
-        }
-  for (int t = 0; t < T; ++t)
-    for (int v = 0; v < 4; ++v) {
-      double s = 0.0;
-      for (int m = 0; m < nb; ++m) s += tb.amean[m] * q[m][t][v];
-      avg[t * 4 + v] = s;
-    }
-  for (int k = 0; k < 3; ++k)
-    for (int t = 0; t < T; ++t) {
-      const double* qq = q[tb.vtx[k]][t];
-      vvel[(k * T + t) * 2 + 0] = qq[1] / qq[0];
-      vvel[(k * T + t) * 2 + 1] = qq[2] / qq[0];
-    }
-}
-
-// Reverse of pred_fwd: from the adjoints of the traces, cell means and vertex
-// velocities to those of the nodal reconstruction (wnodb, overwritten) and of
-// the element vertices (Xeb, added to).
-template <int M>
-AWHD inline void pred_rev(const Tables& tb, double gam, int npic, const double Xe[6], double dt,
-                          const double* keep, size_t ks, const double* traceb, const double* avgb,
-                          const double* vvelb, double* wnodb, double Xeb[6]) {
-  using D = Dim<M>;
-  constexpr int nb = D::nb, T = D::T, nG = D::nG, QS = D::QS;
-  double qb[nb][T][4], x0[nb][2], x0b[nb][2];
-  for (int m = 0; m < nb; ++m) {
-    double xi, eta;
-    lattice<M>(m, xi, eta);
-    x0[m][0] = Xe[0] + (Xe[2] - Xe[0]) * xi + (Xe[4] - Xe[0]) * eta;
-    x0[m][1] = Xe[1] + (Xe[3] - Xe[1]) * xi + (Xe[5] - Xe[1]) * eta;
-    x0b[m][0] = x0b[m][1] = 0.0;
-    for (int t = 0; t < T; ++t)
-      for (int v = 0; v < 4; ++v) {
-        double s = tb.amean[m] * avgb[t * 4 + v];
-        for (int e = 0; e < 3; ++e)
-          for (int gq = 0; gq < nG; ++gq) s += tb.edge[e][gq][m] * traceb[((e * nG + gq) * T + t) * 4 + v];
-        qb[m][t][v] = s;
-      }
-  }
-  for (int k = 0; k < 3; ++k)
-    for (int t = 0; t < T; ++t) {
-      const int m = tb.vtx[k];
-      double qq[4];
-      for (int v = 0; v < 4; ++v) qq[v] = keep[(size_t(npic) * QS + (m * T + t) * 4 + v) * ks];
-      const double vxb = vvelb[(k * T + t) * 2 + 0], vyb = vvelb[(k * T + t) * 2 + 1];
-      qb[m][t][0] -= (vxb * qq[1] + vyb * qq[2]) / (qq[0] * qq[0]);
-      qb[m][t][1] += vxb / qq[0];
-      qb[m][t][2] += vyb / qq[0];
-    }
-  for (int k = npic - 1; k >= 0; --k) {
-    double q[nb][T][4];
-    for (int m = 0; m < nb; ++m)
-      for (int t = 0; t < T; ++t)
-        for (int v = 0; v < 4; ++v) q[m][t][v] = keep[(size_t(k) * QS + (m * T + t) * 4 + v) * ks];
-    // the sweep's mesh positions, recomputed
-    double x[nb][T][2];
-    for (int m = 0; m < nb; ++m) {
-      x[m][0][0] = x0[m][0];
-      x[m][0][1] = x0[m][1];
-      for (int t = 0; t < M; ++t)
-        for (int c = 0; c < 2; ++c) {
-          double s = tb.Bt[t] * x0[m][c];
-          for (int r = 0; r < T; ++r) s += dt * tb.At[t][r] * q[m][r][1 + c] / q[m][r][0];
-          x[m][t + 1][c] = s;
-        }
-    }
-    // q_out[m][0] = q[m][0]; q_out[m][t+1] = Bt[t] q[m][0] + dt sum_r At[t][r] P[m][r]
-    double qi[nb][T][4], Pb[nb][T][4];
-    for (int m = 0; m < nb; ++m)
-      for (int v = 0; v < 4; ++v) {
-        double s = qb[m][0][v];
-        for (int t = 0; t < M; ++t) s += tb.Bt[t] * qb[m][t + 1][v];
-        qi[m][0][v] = s;
-        for (int t = 1; t < T; ++t) qi[m][t][v] = 0.0;
-        for (int r = 0; r < T; ++r) {
-          double p = 0.0;
-          for (int t = 0; t < M; ++t) p += tb.At[t][r] * qb[m][t + 1][v];
-          Pb[m][r][v] = dt * p;
-        }
-      }
-    double xb[nb][T][2];
-    for (int m = 0; m < nb; ++m)
-      for (int t = 0; t < T; ++t) xb[m][t][0] = xb[m][t][1] = 0.0;
-    for (int t = 0; t < T; ++t) {
-      double f[nb][4], g[nb][4], fb[nb][4], gb[nb][4];
-      for (int m = 0; m < nb; ++m) {
-        euler_f_g(q[m][t], gam, f[m], g[m]);
-        for (int v = 0; v < 4; ++v) fb[m][v] = gb[m][v] = 0.0;
-      }
-      for (int kk = 0; kk < nb; ++kk) {
-        double xx = 0, xe = 0, yx = 0, ye = 0;
-        for (int m = 0; m < nb; ++m) {
-          xx += tb.Dxi[kk][m] * x[m][t][0];
-          xe += tb.Deta[kk][m] * x[m][t][0];
-          yx += tb.Dxi[kk][m] * x[m][t][1];
-          ye += tb.Deta[kk][m] * x[m][t][1];
-        }
-        double xtau = 0, ytau = 0;
-        for (int s = 0; s < T; ++s) {
-          xtau += tb.Dt[t][s] * x[kk][s][0];
-          ytau += tb.Dt[t][s] * x[kk][s][1];
-        }
-        const double det = xx * ye - xe * yx;
-        const double xi_x = ye / det, xi_y = -xe / det, eta_x = -yx / det, eta_y = xx / det;
-        const double xt = xtau / dt, yt = ytau / dt;
-        const double xi_t = -(xi_x * xt + xi_y * yt), eta_t = -(eta_x * xt + eta_y * yt);
-        double xitb = 0, etatb = 0, xixb = 0, xiyb = 0, etaxb = 0, etayb = 0;
-        for (int v = 0; v < 4; ++v) {
-          double dqx = 0, dqe = 0, dfx = 0, dfe = 0, dgx = 0, dge = 0;
-          for (int m = 0; m < nb; ++m) {
-            dqx += tb.Dxi[kk][m] * q[m][t][v];
-            dqe += tb.Deta[kk][m] * q[m][t][v];
-            dfx += tb.Dxi[kk][m] * f[m][v];
-            dfe += tb.Deta[kk][m] * f[m][v];
-            dgx += tb.Dxi[kk][m] * g[m][v];
-            dge += tb.Deta[kk][m] * g[m][v];
-          }
-          const double pb = Pb[kk][t][v];
-          xitb -= pb * dqx;
-          etatb -= pb * dqe;
-          xixb -= pb * dfx;
-          etaxb -= pb * dfe;
-          xiyb -= pb * dgx;
-          etayb -= pb * dge;
-          for (int m = 0; m < nb; ++m) {
-            qi[m][t][v] -= pb * (tb.Dxi[kk][m] * xi_t + tb.Deta[kk][m] * eta_t);
-            fb[m][v] -= pb * (tb.Dxi[kk][m] * xi_x + tb.Deta[kk][m] * eta_x);
-            gb[m][v] -= pb * (tb.Dxi[kk][m] * xi_y + tb.Deta[kk][m] * eta_y);
-          }
-        }
-        // xi_t = -(xi_x xt + xi_y yt), eta_t = -(eta_x xt + eta_y yt)
-        xixb -= xitb * xt;
-        xiyb -= xitb * yt;
-        etaxb -= etatb * xt;
-        etayb -= etatb * yt;
-        const double xtb = -(xitb * xi_x + etatb * eta_x), ytb = -(xitb * xi_y + etatb * eta_y);
-        // metric from the spatial derivatives
-        const double detb = -(xixb * xi_x + xiyb * xi_y + etaxb * eta_x + etayb * eta_y) / det;
-        const double xxb = etayb / det + detb * ye;
-        const double yeb = xixb / det + detb * xx;
-        const double xeb = -xiyb / det - detb * yx;
-        const double yxb = -etaxb / det - detb * xe;
-        for (int m = 0; m < nb; ++m) {
-          xb[m][t][0] += tb.Dxi[kk][m] * xxb + tb.Deta[kk][m] * xeb;
-          xb[m][t][1] += tb.Dxi[kk][m] * yxb + tb.Deta[kk][m] * yeb;
-        }
-        for (int s = 0; s < T; ++s) {
-          xb[kk][s][0] += tb.Dt[t][s] * xtb / dt;
-          xb[kk][s][1] += tb.Dt[t][s] * ytb / dt;
-        }
-      }
-      for (int m = 0; m < nb; ++m) euler_f_g_vjp(q[m][t], gam, fb[m], gb[m], qi[m][t]);
-    }
-    // x[m][0] = x0[m]; x[m][t+1] = Bt[t] x0[m] + dt sum_r At[t][r] V[m][r], V = (q1, q2) / q0
-    for (int m = 0; m < nb; ++m) {
-      for (int c = 0; c < 2; ++c) {
-        double s = xb[m][0][c];
-        for (int t = 0; t < M; ++t) s += tb.Bt[t] * xb[m][t + 1][c];
-        x0b[m][c] += s;
-      }
-      for (int r = 0; r < T; ++r) {
-        double vb[2];
-        for (int c = 0; c < 2; ++c) {
-          double s = 0.0;
-          for (int t = 0; t < M; ++t) s += tb.At[t][r] * xb[m][t + 1][c];
-          vb[c] = dt * s;
-        }
-        const double* qq = q[m][r];
-        qi[m][r][0] -= (vb[0] * qq[1] + vb[1] * qq[2]) / (qq[0] * qq[0]);
-        qi[m][r][1] += vb[0] / qq[0];
-        qi[m][r][2] += vb[1] / qq[0];
-      }
-    }
-    for (int m = 0; m < nb; ++m)
-      for (int t = 0; t < T; ++t)
-        for (int v = 0; v < 4; ++v) qb[m][t][v] = qi[m][t][v];
-  }
-  for (int m = 0; m < nb; ++m) {
-    for (int v = 0; v < 4; ++v) {
-      double s = 0.0;
-      for (int t = 0; t < T; ++t) s += qb[m][t][v];
-      wnodb[m * 4 + v] = s;
-    }
-    double xi, eta;
-    lattice<M>(m, xi, eta);
-    for (int c = 0; c < 2; ++c) {
-      Xeb[0 + c] += (1.0 - xi - eta) * x0b[m][c];
-      Xeb[2 + c] += xi * x0b[m][c];
-      Xeb[4 + c] += eta * x0b[m][c];
-    }
-  }
-}
-
-// ------------------------------------------------------------------------
 // Rusanov flux through an unnormalised space-time normal and its product
 // ------------------------------------------------------------------------
 AWHD inline double rus_speed(const double q[4], const double N[3], double gam, double* un_out, double* c_out) {
@@ -397,27 +111,22 @@ AWHD inline double rus_speed(const double q[4], const double N[3], double gam, d
   return fabs(un) + c * nxy;
 }
 
-AWHD inline void rusanov_flux(const double ql[4], const double qr[4], const double N[3], double gam, double F[4]) {
-  double fl[4], gl[4], fr[4], gr[4], un, c;
-  euler_f_g(ql, gam, fl, gl);
-  euler_f_g(qr, gam, fr, gr);
-  const double sl = rus_speed(ql, N, gam, &un, &c), sr = rus_speed(qr, N, gam, &un, &c);
-  const double s = sl >= sr ? sl : sr;
-  for (int v = 0; v < 4; ++v)
-    F[v] = 0.5 * ((fl[v] + fr[v]) * N[0] + (gl[v] + gr[v]) * N[1] + (ql[v] + qr[v]) * N[2]) -
-           0.5 * s * (qr[v] - ql[v]);
-}
-
 // qlb, qrb, Nb += the product of Fb with the Rusanov flux's Jacobian (the
-// larger signal speed taken from the left state on ties, d|x|/dx = 0 at 0).
+// larger signal speed taken from the left state on ties, d|x|/dx = 0 at 0);
+// the flux itself into F when F is not null.
 AWHD inline void rusanov_flux_vjp(const double ql[4], const double qr[4], const double N[3], double gam,
-                                  const double Fb[4], double qlb[4], double qrb[4], double Nb[3]) {
+                                  const double Fb[4], double qlb[4], double qrb[4], double Nb[3],
+                                  double* F = nullptr) {
   double fl[4], gl[4], fr[4], gr[4], unl, cl, unr, cr;
   euler_f_g(ql, gam, fl, gl);
   euler_f_g(qr, gam, fr, gr);
   const double sl = rus_speed(ql, N, gam, &unl, &cl), sr = rus_speed(qr, N, gam, &unr, &cr);
   const bool left = sl >= sr;
   const double s = left ? sl : sr;
+  if (F)
+    for (int v = 0; v < 4; ++v)
+      F[v] = 0.5 * ((fl[v] + fr[v]) * N[0] + (gl[v] + gr[v]) * N[1] + (ql[v] + qr[v]) * N[2]) -
+             0.5 * s * (qr[v] - ql[v]);
   double fb[4], gb[4], sb = 0.0;
   for (int v = 0; v < 4; ++v) {
     fb[v] = 0.5 * N[0] * Fb[v];
@@ -459,10 +168,39 @@ AWHD inline void rusanov_flux_vjp(const double ql[4], const double qr[4], const 
 // ------------------------------------------------------------------------
 // One edge's bilinear space-time patch over a global step (eqs.
 // eqn.spacetimenodes, G_ij, eqn.STint): old nodes a, b at time 0, new nodes at
-// dt; trL (nG, T, 4) the left element's trace along the edge, trR the right
-// one's (read in reverse), or on a transmissive edge (hasR false) the left
-// element's predicted cell means avL (T, 4) as outer state.
+// dt; trL (nG, T, 4) the left element's trace along the edge. Outer state by
+// edge kind: INTERIOR the right element's trace trR (read in reverse),
+// TRANSMISSIVE the left element's predicted cell means avL (T, 4), SLIP the
+// inner state with its normal momentum mirrored about the patch normal.
 // ------------------------------------------------------------------------
+enum { INTERIOR = 0, TRANSMISSIVE = 1, SLIP = 2 };
+
+// q with the momentum reflected about the unit normal of N's space part
+AWHD inline void mirror(const double q[4], const double N[3], double out[4]) {
+  const double inxy = 1.0 / sqrt(N[0] * N[0] + N[1] * N[1]);
+  const double nx = N[0] * inxy, ny = N[1] * inxy;
+  const double mn = q[1] * nx + q[2] * ny;
+  out[0] = q[0];
+  out[1] = q[1] - 2.0 * mn * nx;
+  out[2] = q[2] - 2.0 * mn * ny;
+  out[3] = q[3];
+}
+
+// qb, Nb += the product of ob with mirror's Jacobian
+AWHD inline void mirror_vjp(const double q[4], const double N[3], const double ob[4], double qb[4], double Nb[3]) {
+  const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
+  const double nx = N[0] / nxy, ny = N[1] / nxy;
+  const double mn = q[1] * nx + q[2] * ny, mb = ob[1] * nx + ob[2] * ny;
+  qb[0] += ob[0];
+  qb[1] += ob[1] - 2.0 * mb * nx;
+  qb[2] += ob[2] - 2.0 * mb * ny;
+  qb[3] += ob[3];
+  // n = N_xy / |N_xy|: nbar = -2 (mb q_m + mn ob_m), projected off n
+  const double bx = -2.0 * (mb * q[1] + mn * ob[1]), by = -2.0 * (mb * q[2] + mn * ob[2]);
+  const double bn = bx * nx + by * ny;
+  Nb[0] += (bx - bn * nx) / nxy;
+  Nb[1] += (by - bn * ny) / nxy;
+}
 template <int M>
 AWHD inline void patch_corners(const double xa[2], const double xb[2], const double xan[2], const double xbn[2],
                                double dt, double P[4][3]) {
@@ -487,66 +225,52 @@ AWHD inline void patch_point(const Tables& tb, int gq, int h, const double P[4][
 }
 
 template <int M>
-AWHD inline void patch_states(const double* trL, const double* trR, const double* avL, bool hasR, int gq,
-                              const double lt[M + 1], double ql[4], double qr[4]) {
+AWHD inline void patch_states(const double* trL, const double* trR, const double* avL, int kind, int gq,
+                              const double lt[M + 1], const double N[3], double ql[4], double qr[4]) {
   constexpr int T = M + 1, nG = M + 1;
   for (int v = 0; v < 4; ++v) {
     double a = 0.0, b = 0.0;
     for (int s = 0; s < T; ++s) {
       a += lt[s] * trL[(gq * T + s) * 4 + v];
-      b += lt[s] * (hasR ? trR[((nG - 1 - gq) * T + s) * 4 + v] : avL[s * 4 + v]);
+      if (kind == INTERIOR) b += lt[s] * trR[((nG - 1 - gq) * T + s) * 4 + v];
+      if (kind == TRANSMISSIVE) b += lt[s] * avL[s * 4 + v];
     }
     ql[v] = a;
     qr[v] = b;
   }
+  if (kind == SLIP) mirror(ql, N, qr);
 }
 
-template <int M>
-AWHD inline void patch_flux(const Tables& tb, double gam, const double xa[2], const double xb[2], const double xan[2],
-                            const double xbn[2], double dt, const double* trL, const double* trR, const double* avL,
-                            bool hasR, double G[4]) {
-  constexpr int nG = M + 1;
-  double P[4][3];
-  patch_corners<M>(xa, xb, xan, xbn, dt, P);
-  for (int v = 0; v < 4; ++v) G[v] = 0.0;
-  for (int gq = 0; gq < nG; ++gq)
-    for (int h = 0; h < nG; ++h) {
-      double N[3], lt[M + 1], dc[3], dtau[3], ql[4], qr[4], F[4];
-      patch_point<M>(tb, gq, h, P, N, lt, dc, dtau);
-      patch_states<M>(trL, trR, avL, hasR, gq, lt, ql, qr);
-      rusanov_flux(ql, qr, N, gam, F);
-      const double w = tb.gw[gq] * tb.gw[h];
-      for (int v = 0; v < 4; ++v) G[v] += w * F[v];
-    }
-}
-
-// Products of Gb with patch_flux: trLb, trRb (or avLb) and the four corner
-// nodes' adjoints (xab, xbb, xanb, xbnb: x, y) are added to.
+// The flux through the patch, G (added to), and the products of Gb with its
+// Jacobian: the rows of the trace adjoints trLb and (interior) trRb are
+// written, the means' adjoint avLb (transmissive) and the four corner nodes'
+// adjoints (xab, xbb, xanb, xbnb: x, y) are added to.
 template <int M>
 AWHD inline void patch_flux_vjp(const Tables& tb, double gam, const double xa[2], const double xb[2],
                                 const double xan[2], const double xbn[2], double dt, const double* trL,
-                                const double* trR, const double* avL, bool hasR, const double Gb[4], double* trLb,
-                                double* trRb, double* avLb, double xab[2], double xbb[2], double xanb[2],
-                                double xbnb[2]) {
+                                const double* trR, const double* avL, int kind, const double Gb[4], double G[4],
+                                double* trLb, double* trRb, double* avLb, double xab[2], double xbb[2],
+                                double xanb[2], double xbnb[2]) {
   constexpr int T = M + 1, nG = M + 1;
   double P[4][3], Pb[4][3] = {};
   patch_corners<M>(xa, xb, xan, xbn, dt, P);
-  for (int gq = 0; gq < nG; ++gq)
+  for (int gq = 0; gq < nG; ++gq) {
+    double rl[T][4] = {}, rr[T][4] = {};
     for (int h = 0; h < nG; ++h) {
       double N[3], lt[M + 1], dc[3], dtau[3], ql[4], qr[4];
       patch_point<M>(tb, gq, h, P, N, lt, dc, dtau);
-      patch_states<M>(trL, trR, avL, hasR, gq, lt, ql, qr);
+      patch_states<M>(trL, trR, avL, kind, gq, lt, N, ql, qr);
       const double w = tb.gw[gq] * tb.gw[h];
-      double Fb[4], qlb[4] = {}, qrb[4] = {}, Nb[3] = {};
+      double Fb[4], F[4], qlb[4] = {}, qrb[4] = {}, Nb[3] = {};
       for (int v = 0; v < 4; ++v) Fb[v] = w * Gb[v];
-      rusanov_flux_vjp(ql, qr, N, gam, Fb, qlb, qrb, Nb);
+      rusanov_flux_vjp(ql, qr, N, gam, Fb, qlb, qrb, Nb, F);
+      for (int v = 0; v < 4; ++v) G[v] += w * F[v];
+      if (kind == SLIP) mirror_vjp(ql, N, qrb, qlb, Nb);
       for (int s = 0; s < T; ++s)
         for (int v = 0; v < 4; ++v) {
-          trLb[(gq * T + s) * 4 + v] += lt[s] * qlb[v];
-          if (hasR)
-            trRb[((nG - 1 - gq) * T + s) * 4 + v] += lt[s] * qrb[v];
-          else
-            avLb[s * 4 + v] += lt[s] * qrb[v];
+          rl[s][v] += lt[s] * qlb[v];
+          if (kind == INTERIOR) rr[s][v] += lt[s] * qrb[v];
+          if (kind == TRANSMISSIVE) avLb[s * 4 + v] += lt[s] * qrb[v];
         }
       // N = dchi x dtau
       double dcb[3], dtb[3];
@@ -564,6 +288,12 @@ AWHD inline void patch_flux_vjp(const Tables& tb, double gam, const double xa[2]
         Pb[3][k] += -t * dcb[k] + (1.0 - c) * dtb[k];
       }
     }
+    for (int s = 0; s < T; ++s)
+      for (int v = 0; v < 4; ++v) {
+        trLb[(gq * T + s) * 4 + v] = rl[s][v];
+        if (kind == INTERIOR) trRb[((nG - 1 - gq) * T + s) * 4 + v] = rr[s][v];
+      }
+  }
   for (int c = 0; c < 2; ++c) {
     xab[c] += Pb[0][c];
     xbb[c] += Pb[1][c];

@@ -58,37 +58,10 @@ static double check(std::vector<double>& x, const std::vector<double>& an, F L, 
 template <int M>
 static void run(const Tables& tb) {
   using D = Dim<M>;
-  constexpr int nb = D::nb, T = D::T, nG = D::nG, QS = D::QS, nu = D::nu;
+  constexpr int nb = D::nb, T = D::T, nG = D::nG, nu = D::nu;
   const double gam = 1.4, dt = 0.02;
-  const int npic = M + 1;
-  // ---- predictor with the mesh ODE ----------------------------------------
-  {
-    std::vector<double> x(nb * 4 + 6);
-    for (int m = 0; m < nb; ++m) state(&x[m * 4]);
-    triangle(&x[nb * 4], 0.0, 0.0, 0.2);
-    std::vector<double> trb(3 * nG * T * 4), avb(T * 4), vvb(3 * T * 2);
-    for (auto& v : trb) v = uni(-1, 1);
-    for (auto& v : avb) v = uni(-1, 1);
-    for (auto& v : vvb) v = uni(-1, 1);
-    auto L = [&](const std::vector<double>& y) {
-      std::vector<double> keep((npic + 1) * QS), tr(3 * nG * T * 4), av(T * 4), vv(3 * T * 2);
-      pred_fwd<M>(tb, gam, npic, y.data(), y.data() + nb * 4, dt, keep.data(), 1, tr.data(), av.data(),
-                  vv.data());
-      double s = 0.0;
-      for (size_t k = 0; k < tr.size(); ++k) s += trb[k] * tr[k];
-      for (size_t k = 0; k < av.size(); ++k) s += avb[k] * av[k];
-      for (size_t k = 0; k < vv.size(); ++k) s += vvb[k] * vv[k];
-      return s;
-    };
-    std::vector<double> keep((npic + 1) * QS), tr(3 * nG * T * 4), av(T * 4), vv(3 * T * 2);
-    pred_fwd<M>(tb, gam, npic, x.data(), x.data() + nb * 4, dt, keep.data(), 1, tr.data(), av.data(), vv.data());
-    std::vector<double> an(nb * 4 + 6, 0.0);
-    pred_rev<M>(tb, gam, npic, x.data() + nb * 4, dt, keep.data(), 1, trb.data(), avb.data(), vvb.data(),
-                an.data(), an.data() + nb * 4);
-    std::printf("predictor M=%d %.3e\n", M, check(x, an, L, 1e-6));
-  }
   // ---- space-time patch flux ------------------------------------------------
-  for (int hasR = 0; hasR < 2; ++hasR) {
+  for (int kind = 0; kind < 3; ++kind) {
     const int NT = nG * T * 4;
     std::vector<double> x(2 * NT + T * 4 + 8);
     for (int k = 0; k < 2 * nG * T; ++k) state(&x[k * 4]);
@@ -106,16 +79,19 @@ static void run(const Tables& tb) {
     for (auto& v : Gb) v = uni(-1, 1);
     auto L = [&](const std::vector<double>& y) {
       const double* cc = &y[2 * NT + T * 4];
-      double G[4];
-      patch_flux<M>(tb, gam, cc, cc + 2, cc + 4, cc + 6, dt, y.data(), y.data() + NT, y.data() + 2 * NT,
-                    hasR != 0, G);
+      double G[4] = {0, 0, 0, 0}, c8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      std::vector<double> t1(NT), t2(NT), t3(T * 4);
+      patch_flux_vjp<M>(tb, gam, cc, cc + 2, cc + 4, cc + 6, dt, y.data(), y.data() + NT, y.data() + 2 * NT, kind,
+                        Gb, G, t1.data(), t2.data(), t3.data(), c8, c8 + 2, c8 + 4, c8 + 6);
       return Gb[0] * G[0] + Gb[1] * G[1] + Gb[2] * G[2] + Gb[3] * G[3];
     };
     std::vector<double> an(x.size(), 0.0);
     double* ac = &an[2 * NT + T * 4];
-    patch_flux_vjp<M>(tb, gam, c, c + 2, c + 4, c + 6, dt, x.data(), x.data() + NT, x.data() + 2 * NT, hasR != 0,
-                      Gb, an.data(), an.data() + NT, an.data() + 2 * NT, ac, ac + 2, ac + 4, ac + 6);
-    std::printf("patch_%s M=%d %.3e\n", hasR ? "interior" : "transmissive", M, check(x, an, L, 1e-6));
+    double G[4] = {0, 0, 0, 0};
+    patch_flux_vjp<M>(tb, gam, c, c + 2, c + 4, c + 6, dt, x.data(), x.data() + NT, x.data() + 2 * NT, kind, Gb, G,
+                      an.data(), an.data() + NT, an.data() + 2 * NT, ac, ac + 2, ac + 4, ac + 6);
+    const char* name[3] = {"interior", "transmissive", "slip"};
+    std::printf("patch_%s M=%d %.3e\n", name[kind], M, check(x, an, L, 1e-6));
   }
   // ---- least-squares row geometry ------------------------------------------
   {
@@ -189,8 +165,8 @@ int main() {
     double Fb[4];
     for (auto& v : Fb) v = uni(-1, 1);
     auto L = [&](const std::vector<double>& y) {
-      double F[4];
-      rusanov_flux(&y[0], &y[4], &y[8], 1.4, F);
+      double F[4], d1[4], d2[4], d3[3];
+      rusanov_flux_vjp(&y[0], &y[4], &y[8], 1.4, Fb, d1, d2, d3, F);
       return Fb[0] * F[0] + Fb[1] * F[1] + Fb[2] * F[2] + Fb[3] * F[3];
     };
     std::vector<double> an(11, 0.0);
