@@ -118,45 +118,64 @@ def patch_bytes(M: int) -> int:
 
 # ---------------------------------------------------------------------------
 def bench_adjoint(a):
-    """Gradient through a run of global steps on a fixed mesh: EP1 explosion on
-    a 50k-triangle 8:1 graded disk, M=2, Rusanov flux, 100 steps of a fixed dt
-    (half the smallest initial CFL step), checkpoints every 10 steps, J = total
-    energy inside r < 0.3 at the final time, gradient with respect to the
-    initial averages. value = backward time (the adjoint steps and the
-    recomputation inside the checkpoint segments) / forward time of the run.
-    Also per step: ader_adjoint_gts_step against one ader_step_gts from the
-    same state. States resident in HBM throughout."""
+    """Gradient through a run of global steps: EP1 explosion on a 50k-triangle
+    8:1 graded disk, M=2, Rusanov flux, 100 steps of a fixed dt, checkpoints
+    every 10 steps. Default: the mesh moving with the fluid (dt = 0.3 x the
+    smallest initial CFL step), J = energy carried at the final time by the
+    elements that start inside r < 0.3 (their moved areas included), gradient
+    with respect to the initial averages and node positions. With
+    --mesh-velocity eulerian: the fixed mesh (dt = half the smallest CFL step),
+    J = total energy inside r < 0.3, gradient with respect to the initial
+    averages. value = backward time (the adjoint steps and the recomputation
+    inside the checkpoint segments) / forward time of the run. Also per step:
+    the step adjoint against one ader_step_gts from the same state. States
+    resident in HBM throughout."""
     import numpy as np
     import torch
 
     from paper_1408_3719_amd import Config, Solver
-    from paper_1408_3719_amd.trajectory import gts_trajectory
+    from paper_1408_3719_amd.trajectory import gts_trajectory, lagrangian_trajectory
     from workloads import explosion_case
 
     n = a.n_elems or 50_000
     M = a.M or 2
+    lagr = a.mesh_velocity == "lagrangian"
     n_steps, every = 100, 10
     mesh, Q0 = explosion_case(n, seed=7)
     NE = mesh.n_elems
-    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=1, mesh_velocity="eulerian"))
-    dt = 0.5 * float(s.dump("DTCFL").min())
-    p = mesh.nodes[mesh.tris]
-    A = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
-               - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
-    c = p.mean(axis=1)
-    W = np.zeros((4, NE))
-    inner = np.hypot(c[:, 0], c[:, 1]) < 0.3
-    W[3, inner] = A[inner]
-    Wd = torch.tensor(W, device="cuda")
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=1, mesh_velocity=a.mesh_velocity))
+    if lagr:
+        # 0.8 x the smallest of 100 free-running global CFL steps: the mesh
+        # compresses and the CFL step shrinks along the run
+        t = [0.0] + [s.step_gts(1e9, 1)["t"] for _ in range(n_steps)]
+        dt = 0.8 * float(np.diff(t).min())
+    else:
+        dt = 0.5 * float(s.dump("DTCFL").min())
+    c = mesh.nodes[mesh.tris].mean(axis=1)
+    inner_np = np.hypot(c[:, 0], c[:, 1]) < 0.3
+    inner = torch.tensor(np.nonzero(inner_np)[0], device="cuda")
+    tris = torch.tensor(mesh.tris, dtype=torch.long, device="cuda")[inner]
+
+    def area(x):
+        p = x[tris]
+        return 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                      - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    A0 = area(torch.tensor(mesh.nodes, device="cuda"))
     sync = torch.cuda.synchronize
 
     def run(every):
         t_f = t_b = 0.0
         for k in range(a.warmup + a.steps):
             q0 = torch.tensor(Q0.T.copy(), device="cuda", requires_grad=True)
+            x0 = torch.tensor(mesh.nodes, device="cuda", requires_grad=True)
             sync()
             t0 = time.perf_counter()
-            Jv = (gts_trajectory(s, q0, dt, n_steps, every=every) * Wd).sum()
+            if lagr:
+                qn, xn = lagrangian_trajectory(s, q0, x0, dt, n_steps, every=every)
+                Jv = (area(xn) * qn[3][inner]).sum()
+            else:
+                qn = gts_trajectory(s, q0, dt, n_steps, every=every)
+                Jv = (A0 * qn[3][inner]).sum()
             sync()
             t1 = time.perf_counter()
             Jv.backward()
@@ -173,26 +192,10 @@ def bench_adjoint(a):
     # the checkpoint spacing changes only rounding (recomputed steps restart
     # from a checkpoint's time)
     assert float((g10 - g1).abs().max()) <= 1e-10 * float(g1.abs().max())
-    # one step each, from the same state
-    s.upload_state(Q0, 0.0)
-    qb = torch.tensor(np.random.default_rng(0).standard_normal((4, NE)), device="cuda")
-    for _ in range(3):
-        s.adjoint_gts_step(dt, qb)
-    sync()
-    K = 20
-    t0 = time.perf_counter()
-    for _ in range(K):
-        s.adjoint_gts_step(dt, qb)
-    sync()
-    ms_adj = (time.perf_counter() - t0) / K * 1e3
-    ms_fwd = 0.0
-    for _ in range(K):
-        s.upload_state(Q0, 0.0)
-        sync()
-        t0 = time.perf_counter()
-        s.step_gts(dt, 1)
-        sync()
-        ms_fwd += (time.perf_counter() - t0) / K * 1e3
+    per_step = (lagrangian_adjoint_step_ratio if lagr else adjoint_step_ratio)(n_elems=n, M=M)
+    mesh_desc = ("mesh moving with the fluid, J = energy carried by the elements starting in r < 0.3, "
+                 "gradient w.r.t. initial averages and node positions" if lagr else
+                 "fixed mesh, J = energy inside r < 0.3, gradient w.r.t. initial averages")
     line = {
         "metric": "adjoint/forward time (gradient of J through 100 global steps)",
         "value": t_b / t_f,
@@ -201,14 +204,15 @@ def bench_adjoint(a):
         "ms_per_step": t_b / a.steps * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"EP1 explosion, {NE}-triangle 8:1 radially graded disk, M={M}, fixed mesh, "
-                               f"{n_steps} global steps of dt = half the smallest CFL step, checkpoints every "
-                               f"{every}, J = energy in r < 0.3, Rusanov",
+        "config": {"workload": f"EP1 explosion, {NE}-triangle 8:1 radially graded disk, M={M}, {mesh_desc}, "
+                               f"{n_steps} global steps of a fixed dt ({'0.8 x the smallest of 100 free-running CFL steps' if lagr else 'half the smallest initial CFL step'}), "
+                               f"checkpoints every {every}, Rusanov", "dt": dt,
                    "n_elems": NE, "M": M, "n_steps": n_steps, "checkpoint_every": every,
-                   "parallelism": "single GPU"},
+                   "mesh_velocity": a.mesh_velocity, "parallelism": "single GPU"},
         "forward_s_per_run": t_f / a.steps,
         "gradient_s_per_run": t_b / a.steps,
-        "per_step": {"forward_ms": ms_fwd, "adjoint_ms": ms_adj, "ratio": ms_adj / ms_fwd},
+        "per_step": {"forward_ms": per_step["forward_ms"], "adjoint_ms": per_step["adjoint_ms"],
+                     "ratio": per_step["value"]},
         "all_states_kept": {"forward_s_per_run": t_f1 / a.steps, "gradient_s_per_run": t_b1 / a.steps,
                             "ratio": t_b1 / t_f1},
         "note": "steps are timed one host call each; ms_per_step is the gradient time of one run",
@@ -462,6 +466,8 @@ def main():
                     help="1: also run free local steps (levels = 0) over the timed interval")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="1: also time one adjoint step against one forward step (adjoint workload)")
+    ap.add_argument("--mesh-velocity", choices=["lagrangian", "eulerian"], default="lagrangian",
+                    help="adjoint workload: mesh moving with the fluid, or fixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=None)

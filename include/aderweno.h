@@ -19,7 +19,7 @@
  *   - Errors: every int-returning call returns 0 on success or a negative
  *     ADER_E_* code; ader_last_error() then holds a message.  Nothing throws
  *     across the ABI.  After a stepping error the device state is undefined;
- *     restore a saved state with ader_upload_state.
+ *     restore a saved state with ader_upload_state_xy.
  *   - Threads: one context per host thread.
  *   - Call order: ader_create -> ader_upload_mesh -> ader_workspace_size ->
  *     ader_bind_workspace -> ader_upload_state -> ader_step_* ...;
@@ -144,10 +144,18 @@ int ader_bind_workspace(ader_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Initial cell averages, device [4][n_elems] SoA (rho, rho u, rho v, rho E),
  * at time t0, on the mesh of ader_upload_mesh (node positions are reset to
- * that mesh: a state of a Lagrangian run on a moved mesh cannot be restored).  Runs the pre-processing of
- * the paper (Sec. 2.6): first reconstruction without projection and first
- * CFL time step of every element.  ADER_E_STATE on rho <= 0 or p <= 0. */
+ * that mesh).  Runs the pre-processing of the paper (Sec. 2.6): first
+ * reconstruction without projection and first CFL time step of every
+ * element.  ADER_E_STATE on rho <= 0 or p <= 0. */
 int ader_upload_state(ader_ctx* ctx, const double* Q_dev, double t0);
+
+/* The same with the node positions too: node_xy_dev, device [n_nodes][2]
+ * (the layout of ader_download_state), or NULL for the mesh of
+ * ader_upload_mesh.  Restores a state of a Lagrangian run on a moved mesh
+ * (topology, stencils and slip-wall normals stay those of the uploaded mesh,
+ * paper Sec. 2.2: fixed stencils).  ADER_E_GEOM when an element is inverted
+ * or degenerate at those positions. */
+int ader_upload_state_xy(ader_ctx* ctx, const double* Q_dev, const double* node_xy_dev, double t0);
 
 /* Global time stepping up to t_target (at most max_steps steps; <= 0 means
  * no limit): one level, every element updates in every step. */

@@ -782,13 +782,24 @@ int ader_bind_workspace(ader_ctx* c, void* dev_ptr, size_t bytes) {
 }
 
 int ader_upload_state(ader_ctx* c, const double* Q_dev, double t0) {
+  return ader_upload_state_xy(c, Q_dev, nullptr, t0);
+}
+
+int ader_upload_state_xy(ader_ctx* c, const double* Q_dev, const double* node_xy_dev, double t0) {
   if (!c || !Q_dev) return ADER_E_ARG;
   if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
   const aw::Topology& t = c->topo;
   aw::Dev& d = c->dev;
-  std::vector<double> xy = to_soa(t.xy, t.NV, 2);
+  c->has_state = false;
+  c->synced = false;
   int r;
-  if ((r = h2d(c, d.X, xy.data(), xy.size() * sizeof(double)))) return r;
+  std::vector<double> xy;
+  if (node_xy_dev) {
+    LCHK(c, aw::launch_upload_xy(d, node_xy_dev, c->stream));
+  } else {
+    xy = to_soa(t.xy, t.NV, 2);
+    if ((r = h2d(c, d.X, xy.data(), xy.size() * sizeof(double)))) return r;
+  }
   aw::Scal s{};
   s.N = 1;
   if ((r = h2d(c, d.scal, &s, sizeof(s)))) return r;
@@ -800,6 +811,12 @@ int ader_upload_state(ader_ctx* c, const double* Q_dev, double t0) {
   c->extra_cycles = 0;
   c->long_macro_steps = 0;
   LCHK(c, aw::launch_init_geometry(d, c->stream));
+  if (node_xy_dev) {
+    // caller positions: refuse inverted elements before any kernel uses them
+    aw::Scal g;
+    if ((r = read_scal(c, g))) return r;
+    if (g.err & aw::ERR_GEOM) return fail(c, ADER_E_GEOM, "node positions give an inverted or degenerate element");
+  }
   LCHK(c, aw::launch_upload_q(d, Q_dev, c->stream));
   LCHK(c, aw::launch_check_state(d, c->prm.gamma, c->stream));
   LCHK(c, aw::launch_reconstruct(d, c->prm, c->cfg.M, 0, 0, c->stream));

@@ -246,6 +246,7 @@ int launch_status(const Dev& d, void* stream);
 int launch_macro_end(const Dev& d, int only_if_done, void* stream);
 int launch_open(const Dev& d, void* stream);
 int launch_download_xy(const Dev& d, double* out, void* stream);
+int launch_upload_xy(const Dev& d, const double* in, void* stream);
 int launch_download_q(const Dev& d, double* out, void* stream);
 int launch_upload_q(const Dev& d, const double* in, void* stream);
 int launch_elem_times(const Dev& d, double* out, void* stream);

@@ -1447,6 +1447,7 @@ __global__ void __launch_bounds__(TPB) k_init_geometry(Dev d) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) r[XE + c] = X[c];
       r[AO] = tri_area(X);
+      if (!(r[AO] > 0.0)) set_err(d, ERR_GEOM);
       d.ts[i] = TickStep{0, 0};
       d.act_stamp[i] = -1;
 #pragma unroll
@@ -1493,6 +1494,13 @@ __global__ void __launch_bounds__(TPB) k_download_xy(Dev d, double* out) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.NV; k += gridDim.x * blockDim.x) {
     out[2 * k] = d.X[k];
     out[2 * k + 1] = d.X[d.NV + k];
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_upload_xy(Dev d, const double* in) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.NV; k += gridDim.x * blockDim.x) {
+    d.X[k] = in[2 * k];
+    d.X[d.NV + k] = in[2 * k + 1];
   }
 }
 
@@ -1641,6 +1649,11 @@ int launch_open(const Dev& d, void* s) {
 
 int launch_download_xy(const Dev& d, double* out, void* s) {
   AW_LAUNCH(k_download_xy, d.NV, s, d, out);
+  return 0;
+}
+
+int launch_upload_xy(const Dev& d, const double* in, void* s) {
+  AW_LAUNCH(k_upload_xy, d.NV, s, d, in);
   return 0;
 }
 

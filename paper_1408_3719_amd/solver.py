@@ -135,8 +135,9 @@ class Solver(_Base):
         _check(self.lib, self.ctx, self.lib.ader_bind_workspace(self.ctx, ctypes.c_void_p(aligned), n.value))
         self.upload_state(Q0, t0)
 
-    def upload_state(self, Q0, t0=0.0):
-        """Q0: (NE, 4) array, or a device tensor [4][NE] (used in place)."""
+    def upload_state(self, Q0, t0=0.0, X=None):
+        """Q0: (NE, 4) array, or a device tensor [4][NE] (used in place); X:
+        node positions (NV, 2) (array or device tensor), default the mesh's."""
         torch = self.torch
         if torch.is_tensor(Q0) and Q0.is_cuda:
             q = Q0.to(dtype=torch.float64).contiguous()
@@ -145,8 +146,17 @@ class Solver(_Base):
         else:
             q = torch.as_tensor(np.ascontiguousarray(np.asarray(Q0, np.float64).T), device=self.device)
             q = q.contiguous()
-        _check(self.lib, self.ctx, self.lib.ader_upload_state(self.ctx, ctypes.c_void_p(q.data_ptr()), t0))
+        x = self._devxy(X, "X") if X is not None else None
+        _check(self.lib, self.ctx, self.lib.ader_upload_state_xy(
+            self.ctx, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(x.data_ptr()) if x is not None else None, t0))
         self.stream.synchronize()
+
+    def download_x(self):
+        """The node positions as a device tensor (NV, 2)."""
+        X = self.torch.empty((self.NV, 2), dtype=self.torch.float64, device=self.device)
+        _check(self.lib, self.ctx, self.lib.ader_download_state(
+            self.ctx, None, ctypes.c_void_p(X.data_ptr()), None))
+        return X
 
     def _stats(self, st):
         return {f: getattr(st, f) for f, _ in _lib.AderStats._fields_}
