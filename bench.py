@@ -446,6 +446,36 @@ def lagrangian_adjoint_step_ratio(n_elems: int = 50_000, M: int = 2, reps: int =
             "workload": f"one global step on the {mesh.n_elems}-triangle explosion, Lagrangian mesh, M={M}"}
 
 
+def mfma_probe(n_elems: int = 400_000, iters: int = 64, reps: int = 5):
+    """The predictor's derivative contraction (D_xi, D_eta of the M=2 nodal
+    basis on ten fields at six nodes, fed back `iters` times) on the vector
+    ALUs and on the matrix cores (ader_probe_contraction), best of `reps`
+    launches each; useful work 2 x 12 x 6 x 10 = 1,440 flop per element and
+    round (the MFMA variant issues 7 tiles x 2 k-steps x 16x16x4 per ten
+    elements, 2,867 flop per element and round, padding included)."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3719_amd import Config, Solver
+    from workloads import vortex_case
+    mesh, Q0 = vortex_case(400, seed=5)
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=2, levels=1))
+    F = torch.tensor(np.random.default_rng(0).standard_normal((n_elems, 10, 6)), device="cuda")
+    out = {}
+    res = {}
+    for name, mf in (("valu", False), ("mfma", True)):
+        best = None
+        for _ in range(reps):
+            r, ms = s.probe_contraction(F, iters, mf)
+            best = ms if best is None else min(best, ms)
+        res[name] = r
+        useful = 1440.0 * n_elems * iters
+        out[name] = {"ms": best, "useful_tflops": useful / (best * 1e-3) / 1e12}
+    d = float((res["valu"] - res["mfma"]).abs().max() / res["valu"].abs().max())
+    return {"n_elems": n_elems, "rounds": iters, **out, "mfma_over_valu_time": out["mfma"]["ms"] / out["valu"]["ms"],
+            "max_rel_difference": d}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +498,8 @@ def main():
                     help="1: also time one adjoint step against one forward step (adjoint workload)")
     ap.add_argument("--mesh-velocity", choices=["lagrangian", "eulerian"], default="lagrangian",
                     help="adjoint workload: mesh moving with the fluid, or fixed")
+    ap.add_argument("--mfma-probe", type=int, default=1,
+                    help="1: time the predictor's derivative contraction on MFMA against VALU")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=None)
@@ -662,6 +694,10 @@ def main():
         adj_lag = lagrangian_adjoint_step_ratio()
         note(f"moving-mesh adjoint/forward per step {adj_lag['value']:.3f}")
 
+    probe = mfma_probe() if a.mfma_probe else None
+    if probe:
+        note(f"contraction probe: VALU {probe['valu']['ms']:.3f} ms, MFMA {probe['mfma']['ms']:.3f} ms")
+
     cpu = None
     if not a.no_cpu_baseline:
         ce, cs = dflt[4]
@@ -704,7 +740,10 @@ def main():
         "roofline": roof,
         "fp64_kernels": fp64_kernels,
         "hbm_kernels": hbm_kernels,
-        "mfma": {"used": False, "note": "no kernel of the step issues MFMA instructions"},
+        "mfma": {"used": False, "utilisation": 0.0,
+                 "note": "no kernel of the step issues MFMA instructions; the probe times the predictor's "
+                         "derivative contraction on the matrix cores against the vector ALUs",
+                 "probe": probe},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -315,6 +315,21 @@ int ader_adjoint_lagrangian_step(ader_ctx* ctx, double dt, const double* Q_dev, 
                                  double* Xbar_dev, double* Q_next_dev, double* X_next_dev, void* work_dev,
                                  size_t work_bytes);
 
+/* ---- Measurement: the predictor's derivative contraction -----------------
+ * Not a step of the scheme: runs, in one timed launch on the context's
+ * stream, `iters` rounds of the space-time predictor's spatial-derivative
+ * contraction (D_xi and D_eta of eq. CGfinal's nodal basis applied to ten
+ * fields at the six nodes of each of n_elems elements, fed back as
+ * q <- q/2 + (d_xi q + d_eta q)/20) in the lane layout of the step's predictor,
+ * on the vector ALUs (use_mfma = 0) or on the matrix cores (use_mfma = 1,
+ * v_mfma_f64_16x16x4f64 over ten elements per wavefront), so that the two can
+ * be timed and profiled against each other.  F_dev, out_dev: device
+ * [n_elems][10][6] (element, field, node), not overlapping; ms: the launch's
+ * duration (HIP events; synchronises the stream).  Needs M = 2 and a bound
+ * workspace (the tables), else ADER_E_ARG / ADER_E_ORDER. */
+int ader_probe_contraction(ader_ctx* ctx, int32_t use_mfma, int64_t n_elems, int32_t iters, const double* F_dev,
+                           double* out_dev, float* ms);
+
 /* Current state into caller device buffers (any may be NULL):
  * Q_dev [4][n_elems] SoA, node_xy_dev [n_nodes][2], elem_t_dev [n_elems]. */
 int ader_download_state(ader_ctx* ctx, double* Q_dev, double* node_xy_dev, double* elem_t_dev);

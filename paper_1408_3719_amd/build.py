@@ -18,7 +18,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["tables.cpp", "topology.cpp", "abi.cpp"]
-HIP_SOURCES = ["kernels.hip", "adjoint.hip"]
+HIP_SOURCES = ["kernels.hip", "adjoint.hip", "probe.hip"]
 
 
 def _run(cmd, verbose):

@@ -1209,6 +1209,28 @@ int ader_adjoint_lagrangian_step(ader_ctx* c, double dt, const double* Q_dev, co
   return ADER_OK;
 }
 
+int ader_probe_contraction(ader_ctx* c, int32_t use_mfma, int64_t n_elems, int32_t iters, const double* F_dev,
+                           double* out_dev, float* ms) {
+  if (!c || !F_dev || !out_dev || n_elems <= 0 || n_elems > INT32_MAX || iters < 1) return ADER_E_ARG;
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  if (c->cfg.M != 2) return fail(c, ADER_E_ARG, "the contraction probe measures M = 2");
+  hipStream_t s = c->stream;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, s));
+  const int r = aw::probe_contraction(c->dev.tab, use_mfma, long(n_elems), iters, F_dev, out_dev, s, 0);
+  HIPCHK(c, hipEventRecord(e1, s));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float t = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r) return hip_fail(c, r, "probe launch");
+  if (ms) *ms = t;
+  return ADER_OK;
+}
+
 int ader_set_schedule_replay(ader_ctx* c, const int32_t* step_ptr, const int32_t* steps, int64_t n_steps) {
   if (!c) return ADER_E_ARG;
   if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");

@@ -229,6 +229,11 @@ void adjoint_carve(int M, int NE, int NF, int npic, char* base, AdjWork& w);
 int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,
                        bool state_from_context, void* stream);
 
+// The derivative-contraction measurement (probe.hip): one launch, M = 2
+// tables, F and out [n][10][6]; blocks <= 0: one block per 40 elements.
+int probe_contraction(const Tables* tab, int use_mfma, long n, int iters, const double* F, double* out,
+                      void* stream, int blocks);
+
 // Kernel launchers (kernels.hip).  All launch on `stream`, return a
 // hipError_t as int.
 int launch_init_geometry(const Dev& d, void* stream);

@@ -241,6 +241,20 @@ class Solver(_Base):
             ctypes.c_void_p(aligned), n))
         return qbar, xbar, q_next, x_next
 
+    def probe_contraction(self, F, iters: int, use_mfma: bool):
+        """Time `iters` rounds of the predictor's derivative contraction on the
+        fields F (device tensor [n][10][6]) on the vector ALUs or the matrix
+        cores (ader_probe_contraction); returns (out tensor, milliseconds)."""
+        F = F.to(device=self.device, dtype=self.torch.float64).contiguous()
+        if F.dim() != 3 or tuple(F.shape[1:]) != (10, 6):
+            raise ValueError("F must be [n][10][6]")
+        out = self.torch.empty_like(F)
+        ms = ctypes.c_float()
+        _check(self.lib, self.ctx, self.lib.ader_probe_contraction(
+            self.ctx, int(bool(use_mfma)), F.shape[0], iters, ctypes.c_void_p(F.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()), ctypes.byref(ms)))
+        return out, ms.value
+
     def set_schedule_replay(self, step_log):
         """Replay recorded steps: step_log[i] lists the steps (in ticks)
         element i takes, in order (None: the level rule again)."""
