@@ -1079,6 +1079,14 @@ struct LP {
   static constexpr int QS = nb * T * 4;
 };
 
+// Predictor iterate k of element i, time node t, variable v, spatial node m:
+// the nb nodes of an element adjacent, then the elements, so that the lanes of
+// a wavefront (ten elements x six nodes at M = 2) touch one contiguous run.
+template <int M>
+__device__ inline size_t keep_at(int k, int t, int v, int i, int m, int NE) {
+  return ((size_t(k * (M + 1) + t) * 4 + v) * NE + i) * LP<M>::nb + m;
+}
+
 // Predictor with the mesh ODE (eqs. CGfinal, VCG, newVertPos), one lane per
 // spatial node: each node's space-time values and trajectory stay in its
 // lane, the spatial derivatives at a node take the element's other nodes
@@ -1089,7 +1097,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __res
                                                       LagWork w, double dt) {
   using S = AZ<M>;
   using L = LP<M>;
-  constexpr int nb = L::nb, T = L::T, nG = L::nG, G = L::G, EPW = L::EPW, SLOTS = L::SLOTS, QS = L::QS;
+  constexpr int nb = L::nb, T = L::T, nG = L::nG, G = L::G, EPW = L::EPW, SLOTS = L::SLOTS;
   constexpr int NPT = 1 + 3 * nG;
   __shared__ double lds[(SLOTS + L::WPB) * L::LSTR];
   const int NE = d.NE;
@@ -1134,11 +1142,10 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __res
 #pragma unroll 1
     for (int k = 0; k < P.npic; ++k) {
       if (live) {
-        double* kp = w.keep + size_t(k) * QS * NE + i;
 #pragma unroll
         for (int t = 0; t < T; ++t)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) kp[size_t((m * T + t) * 4 + v) * NE] = q[t][v];
+          for (int v = 0; v < 4; ++v) w.keep[keep_at<M>(k, t, v, i, m, NE)] = q[t][v];
       }
       // mesh ODE of this node
 #pragma unroll
@@ -1212,11 +1219,10 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __res
         for (int v = 0; v < 4; ++v) q[r + 1][v] = qn[r][v];
     }
     if (live) {
-      double* kp = w.keep + size_t(P.npic) * QS * NE + i;
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) kp[size_t((m * T + t) * 4 + v) * NE] = q[t][v];
+        for (int v = 0; v < 4; ++v) w.keep[keep_at<M>(P.npic, t, v, i, m, NE)] = q[t][v];
 #pragma unroll
       for (int kv = 0; kv < 3; ++kv) {
         if (tb->vtx[kv] != m) continue;
@@ -1475,7 +1481,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
                                                       LagWork w, double dt) {
   using S = AZ<M>;
   using L = LP<M>;
-  constexpr int nb = L::nb, T = L::T, nG = L::nG, G = L::G, EPW = L::EPW, SLOTS = L::SLOTS, QS = L::QS;
+  constexpr int nb = L::nb, T = L::T, nG = L::nG, G = L::G, EPW = L::EPW, SLOTS = L::SLOTS;
   __shared__ double lds[(SLOTS + L::WPB) * L::LSTR];
   const int NE = d.NE;
   const double gam = P.gamma;
@@ -1500,6 +1506,14 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
   for (int base = blockIdx.x * SLOTS; base < NE; base += gridDim.x * SLOTS) {
     const int i = spare ? -1 : base + slot;
     const bool live = i >= 0 && i < NE;
+    // the element's trace adjoints into LDS, a share per lane, then every lane
+    // reads the ones its node contributes to
+    constexpr int NTB = 3 * nG * T * 4;
+    if (live) {
+      const double* tbi = w.a.tbar + size_t(i) * S::TS;
+      for (int c = m; c < NTB; c += G) my[c] = tbi[c];
+    }
+    lag_wave_sync();
     double x0[2], qb[T][4];
     if (live) {
       const double* X = w.xe + size_t(i) * 6;
@@ -1522,7 +1536,6 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
             for (int v = 0; v < 4; ++v) ab[t][v] += a[t * 4 + v];
         }
       }
-      const double* tbi = w.a.tbar + size_t(i) * S::TS;
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -1531,19 +1544,18 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
 #pragma unroll
           for (int e = 0; e < 3; ++e)
 #pragma unroll
-            for (int gq = 0; gq < nG; ++gq) s += tb->edge[e][gq][m] * tbi[((e * nG + gq) * T + t) * 4 + v];
+            for (int gq = 0; gq < nG; ++gq) s += tb->edge[e][gq][m] * my[((e * nG + gq) * T + t) * 4 + v];
           qb[t][v] = s;
         }
 #pragma unroll
       for (int kv = 0; kv < 3; ++kv) {
         if (tb->vtx[kv] != m) continue;
         const double* o = w.nslot + (size_t(i) * 3 + kv) * 3;
-        const double* kp = w.keep + size_t(P.npic) * QS * NE + i;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-          const double q0 = kp[size_t((m * T + t) * 4 + 0) * NE];
-          const double q1 = kp[size_t((m * T + t) * 4 + 1) * NE];
-          const double q2 = kp[size_t((m * T + t) * 4 + 2) * NE];
+          const double q0 = w.keep[keep_at<M>(P.npic, t, 0, i, m, NE)];
+          const double q1 = w.keep[keep_at<M>(P.npic, t, 1, i, m, NE)];
+          const double q2 = w.keep[keep_at<M>(P.npic, t, 2, i, m, NE)];
           const double vxb = I[t] * o[0], vyb = I[t] * o[1];
           qb[t][0] -= (vxb * q1 + vyb * q2) / (q0 * q0);
           qb[t][1] += vxb / q0;
@@ -1558,16 +1570,16 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
 #pragma unroll
         for (int v = 0; v < 4; ++v) qb[t][v] = 0.0;
     }
+    lag_wave_sync();   // the staged trace adjoints are read before the sweeps reuse the buffer
     double x0b[2] = {0.0, 0.0};
 #pragma unroll 1
     for (int k = P.npic - 1; k >= 0; --k) {
       double q[T][4];
       if (live) {
-        const double* kp = w.keep + size_t(k) * QS * NE + i;
 #pragma unroll
         for (int t = 0; t < T; ++t)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) q[t][v] = kp[size_t((m * T + t) * 4 + v) * NE];
+          for (int v = 0; v < 4; ++v) q[t][v] = w.keep[keep_at<M>(k, t, v, i, m, NE)];
       } else {
 #pragma unroll
         for (int t = 0; t < T; ++t) {

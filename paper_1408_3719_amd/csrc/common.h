@@ -203,7 +203,7 @@ struct LagWork {
   double* xn;                // [NV][2] positions after the step
   double* vraw;              // [NV][2] ring-mean velocity before the wall constraint
   double* den;               // [NV] ring mass
-  double* keep;              // [npic+1][nb*(M+1)*4][NE] predictor iterates
+  double* keep;              // [npic+1][M+1][4][NE][nb] predictor iterates
   double* vvel;              // [NE][3][M+1][2] predicted vertex velocities
   double* gslot;             // [NE][3][4] inflow-positive patch flux per (element, edge)
   double* xs;                // [NF][8] adjoint of the patch corners (a, b old; a, b new)
