@@ -53,12 +53,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in 
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
     "workload": "explosion",
-    "source_sha256": "246c43c9813b7607fe8a8b66dfb586c4c1aea03f4754e86c52e692fd4e9f8ec3",
-    "k_reconstruct": {0: 1581, 4: 1617, 8: 1595, 16: 1586, 32: 1582},
-    "k_predict": {0: 1499, 4: 1499, 8: 1499, 16: 1499, 32: 1499},
+    "source_sha256": "639d3100074d865237df690f93eff5c86c86973fc14bf713a4d16ad9222de5fa",
+    "k_reconstruct": {0: 1728, 4: 1778, 8: 1751, 16: 1736, 32: 1736},
+    "k_predict": {0: 1503, 4: 1504, 8: 1503, 16: 1503, 32: 1503},
     "k_patch": {w: 1046 for w in TRAFFIC_SWEEP},
-    "k_update": {w: 728 for w in TRAFFIC_SWEEP},
-    "k_node": {w: 1776 for w in TRAFFIC_SWEEP},
+    "k_update": {w: 735 for w in TRAFFIC_SWEEP},
+    "k_node": {w: 1778 for w in TRAFFIC_SWEEP},
     "k_sched": {w: 89 for w in TRAFFIC_SWEEP},
 }
 
