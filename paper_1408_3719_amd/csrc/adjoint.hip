@@ -320,15 +320,12 @@ __global__ void __launch_bounds__(TPB) k_adj_gather(Dev d, AdjWork w) {
   const int ngroups = (gridDim.x * blockDim.x) >> 3;
   for (int j = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; j < NE; j += ngroups) {
     double acc[NA];
+    // a row slot holds NA doubles: the right-hand side's adjoint (4), then
+    // with GEO the stencil element's vertex adjoints (6)
     auto add = [&](size_t slot) {
-      const double* r = w.rowbar + slot * 4;
+      const double* r = w.rowbar + slot * NA;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] += r[v];
-      if (GEO) {
-        const double* x = w.xrow + slot * 6;
-#pragma unroll
-        for (int k = 0; k < NA - 4; ++k) acc[4 + k] += x[k];
-      }
+      for (int v = 0; v < NA; ++v) acc[v] += r[v];
     };
 #pragma unroll
     for (int v = 0; v < NA; ++v) acc[v] = 0.0;
@@ -339,16 +336,9 @@ __global__ void __launch_bounds__(TPB) k_adj_gather(Dev d, AdjWork w) {
       const size_t s0 = size_t(d.tsten_idx[k]), s1 = size_t(d.tsten_idx[k + 8]);
       double a0[NA], a1[NA];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        a0[v] = w.rowbar[s0 * 4 + v];
-        a1[v] = w.rowbar[s1 * 4 + v];
-      }
-      if (GEO) {
-#pragma unroll
-        for (int v = 4; v < NA; ++v) {
-          a0[v] = w.xrow[s0 * 6 + v - 4];
-          a1[v] = w.xrow[s1 * 6 + v - 4];
-        }
+      for (int v = 0; v < NA; ++v) {
+        a0[v] = w.rowbar[s0 * NA + v];
+        a1[v] = w.rowbar[s1 * NA + v];
       }
 #pragma unroll
       for (int v = 0; v < NA; ++v) acc[v] += a0[v] + a1[v];
@@ -535,15 +525,15 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
       }
     // row c of this lane's stencil: slot ((i * ne + c) * 8 + sl); row 0 holds
     // the element's own terms
-    double* rb = w.rowbar + (size_t(i) * ne * 8 + sl) * 4;
-    constexpr int RB = 32;
+    constexpr int SW = GEO ? 10 : 4;   // doubles per row slot
+    double* rb = w.rowbar + (size_t(i) * ne * 8 + sl) * SW;
+    constexpr int RB = 8 * SW;
     if (!valid) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) rb[v] = sl == 7 ? q0b[v] : 0.0;
       if (GEO) {
-        double* xo = w.xrow + (size_t(i) * ne * 8 + sl) * 6;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) xo[c] = 0.0;
+        for (int c = 0; c < 6; ++c) rb[4 + c] = 0.0;
       }
       continue;
     }
@@ -616,7 +606,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll
         for (int k = 0; k < 6; ++k) xj[k] = Xj[k];
         lag::ls_row_geom_vjp<M>(xj, Xi, ab, Xjb, Xib);
-        double* xo = w.xrow + ((size_t(i) * ne + c) * 8 + sl) * 6;
+        double* xo = rb + c * RB + 4;
 #pragma unroll
         for (int k = 0; k < 6; ++k) xo[k] = Xjb[k];
       }
@@ -624,7 +614,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
 #pragma unroll
     for (int v = 0; v < 4; ++v) rb[v] = -sumb[v];
     if (GEO) {
-      double* xo = w.xrow + (size_t(i) * ne * 8 + sl) * 6;
+      double* xo = rb + 4;
 #pragma unroll
       for (int k = 0; k < 6; ++k) xo[k] = Xib[k];
     }
@@ -1967,8 +1957,7 @@ LagPlan lag_plan(int M, int NE, int NV, int NF, int npic) {
   p.add(size_t(NE) * 9 * D);                       // 20 nslot
   p.add(4 * size_t(NE) * D);                       // 21 qdir
   p.add(size_t(lsq_slots(M)) * 8 * NE * D);        // 22 lsq
-  p.add(ne * NE * 32 * D);                         // 23 rowbar
-  p.add(ne * NE * 48 * D);                         // 24 xrow
+  p.add(ne * NE * 80 * D);                         // 23 row slots (10 doubles)
   return p;
 }
 }  // namespace
@@ -2005,7 +1994,6 @@ void lagadj_carve(int M, int NE, int NV, int NF, int npic, char* base, LagWork& 
   w.qdir = at(21);
   w.a.lsq = at(22);
   w.a.rowbar = at(23);
-  w.a.xrow = at(24);
   w.a.geo = w.xe;
   w.a.geo_stride = 6;
 }

@@ -174,6 +174,7 @@ struct AdjWork {
   double* lsq;               // [slot][NE][8] per stencil lane: R factor, solution, weight,
                              // indicator and least-squares rows of the forward pass
   double* rowbar;            // [NE][ne][8][4] adjoint of each stencil row's right-hand side
+                             // ([NE][ne][8][10] with the vertex adjoints after it, moving mesh)
   double* avg;               // [NE][M+1][4] predictor cell means at the time nodes
   double* abar;              // [NF][M+1][4] their adjoints, a slot per transmissive edge
                              // (row 0: the element's own terms), summed by the gather
@@ -181,8 +182,6 @@ struct AdjWork {
   // geo, or the context's records when geo is null
   const double* geo;
   int geo_stride;
-  double* xrow;              // [NE][ne][8][6] adjoint of the stencil element's vertices per
-                             // row (row 0: the element's own vertices), or null
   double* xeb;               // [NE][6] adjoint of the element's vertices (gather adds rows)
 };
 
