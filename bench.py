@@ -216,6 +216,7 @@ def bench_adjoint(a):
         "all_states_kept": {"forward_s_per_run": t_f1 / a.steps, "gradient_s_per_run": t_b1 / a.steps,
                             "ratio": t_b1 / t_f1},
         "note": "steps are timed one host call each; ms_per_step is the gradient time of one run",
+        "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline_adjoint(a.mesh_velocity, M=M),
     }
     print(json.dumps(line))
 
@@ -367,6 +368,54 @@ print(json.dumps(dict(updates=s.st.updates, seconds=dt, n_elems=mesh.n_elems)))
                 sample=f"{workload} recipe at {r['n_elems']} triangles, M={M}, {levels} levels, first "
                        f"{macro_steps} macro steps ({r['updates']} element updates in {r['seconds']:.1f} s, "
                        f"one host thread)",
+                host_cpu_model=cpu["model"], host_logical_cpus=cpu["logical_cpus"],
+                host_cpus_available=cpu["cpus_available"])
+
+
+def cpu_baseline_adjoint(mesh_velocity: str, n_elems: int = 5000, M: int = 2, reps: int = 3):
+    """The reverse-mode oracle (torch.autograd through the oracle's global
+    step, CPU, one thread) on a bounded sample of the adjoint workload's
+    recipe: one step's vector-Jacobian product against one forward step, in a
+    single-threaded subprocess."""
+    cls = "LagrangianStep" if mesh_velocity == "lagrangian" else "EulerianStep"
+    code = f"""
+import json, sys, time
+sys.path.insert(0, {ROOT!r})
+import numpy as np, torch
+torch.set_num_threads(1)
+from oracle.adjoint import {cls} as Step
+from oracle.scheme import Config, GTSSolver
+from workloads import explosion_case
+mesh, Q0 = explosion_case({n_elems}, seed=7)
+cfg = Config(M={M}, levels=1, mesh_velocity={mesh_velocity!r})
+o = GTSSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+dt = 0.5 * float(o.dtcfl.min())
+st = Step(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+rng = np.random.default_rng(0)
+qb, xb = rng.standard_normal(Q0.shape), rng.standard_normal(mesh.nodes.shape)
+lag = {mesh_velocity == "lagrangian"}
+t = time.perf_counter()
+for _ in range({reps}):
+    st.vjp(Q0, mesh.nodes, dt, qb, xb) if lag else st.vjp(Q0, dt, qb)
+ta = (time.perf_counter() - t) / {reps}
+t = time.perf_counter()
+for _ in range({reps}):
+    st.step(Q0, mesh.nodes, dt) if lag else st.step(Q0, dt)
+tf = (time.perf_counter() - t) / {reps}
+print(json.dumps(dict(adjoint_s=ta, forward_s=tf, n_elems=mesh.n_elems)))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    cpu = host_cpu()
+    return dict(value=r["adjoint_s"] / r["forward_s"], unit="ratio", cores=1, kind="oracle",
+                adjoint_element_steps_per_s=r["n_elems"] / r["adjoint_s"],
+                forward_element_steps_per_s=r["n_elems"] / r["forward_s"],
+                sample=f"explosion recipe at {r['n_elems']} triangles, M={M}, {mesh_velocity} mesh, one global "
+                       f"step: the oracle's reverse-mode step {r['adjoint_s']:.2f} s against its forward step "
+                       f"{r['forward_s']:.2f} s (mean of {reps}, one host thread)",
                 host_cpu_model=cpu["model"], host_logical_cpus=cpu["logical_cpus"],
                 host_cpus_available=cpu["cpus_available"])
 
