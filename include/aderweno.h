@@ -282,7 +282,7 @@ int ader_adjoint_gts_step_static(ader_ctx* ctx, double dt, const double* Q_dev,
 /* ---- Adjoint of one global step on the moving (Lagrangian) mesh ----------
  * The step map (Q^n, X^n) -> (Q^{n+1}, X^{n+1}) of global time stepping of
  * length dt with the mesh moving with the fluid (mesh_velocity = 0, V = v in
- * eq. ODEmesh) and the Rusanov flux: reconstruction on the current geometry
+ * eq. ODEmesh) and the Rusanov or HLL flux: reconstruction on the current geometry
  * (eqs. intConsRec .. eqn.weno), predictor of the PDE and the mesh ODE (eqs.
  * CGfinal, VCG, newVertPos), node solver with mass weights rho |T| and the
  * velocities averaged over the step (eqs. eqnNScs, eqn.NScs.weights,
@@ -304,7 +304,7 @@ int ader_adjoint_gts_step_static(ader_ctx* ctx, double dt, const double* Q_dev,
  *     of the call only.  No output may overlap an input.
  * Slip walls: the outer state is the mirrored inner one (its dependence on the
  * patch normal included) and wall nodes slide or stay pinned as in the
- * forward step.  ADER_E_ARG for another mesh velocity or flux, a batch of
+ * forward step.  ADER_E_ARG for a fixed mesh, the Osher flux, a batch of
  * instances, a workspace too small; ADER_E_ORDER before a state upload.
  * Queued on the context's stream; no synchronisation.  With dt at most the
  * smallest CFL step, the step that ader_step_gts(ctx, t + dt, 1, ...) takes

@@ -1183,7 +1183,8 @@ int ader_adjoint_lagrangian_step(ader_ctx* c, double dt, const double* Q_dev, co
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, ADER_E_ARG, "dt must be positive and finite");
   if (c->cfg.mesh_velocity != 0)
     return fail(c, ADER_E_ARG, "the moving-mesh adjoint needs the Lagrangian mesh (mesh_velocity = 0)");
-  if (c->cfg.flux != ADER_FLUX_RUSANOV) return fail(c, ADER_E_ARG, "the moving-mesh adjoint covers the Rusanov flux");
+  if (c->cfg.flux == ADER_FLUX_OSHER)
+    return fail(c, ADER_E_ARG, "the moving-mesh adjoint covers the Rusanov and HLL fluxes");
   if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the adjoint runs on a single instance");
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if ((!Q_dev || !X_dev) && !c->synced)

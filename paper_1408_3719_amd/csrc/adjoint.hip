@@ -1345,7 +1345,7 @@ __global__ void __launch_bounds__(TPB) k_lag_patch(Dev d, const Tables* __restri
     double* oL = w.a.tbar + size_t(L) * TS + el * NT;
     double* oR = hasR ? w.a.tbar + size_t(R) * TS + er * NT : oL;
     lag::patch_flux_vjp<M>(*tb, P.gamma, xa, xb, xan, xbn, dt, trL, trR, avL, kind, Gb, G, oL, oR, bA, c, c + 2,
-                           c + 4, c + 6);
+                           c + 4, c + 6, P.flux == ADER_FLUX_HLL);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       w.gslot[(size_t(L) * 3 + el) * 4 + v] = -G[v];

@@ -1,6 +1,6 @@
 // Per-edge and per-row pieces of the adjoint of one global time step with the
-// mesh moving with the fluid (Lagrangian mode): the Rusanov flux through an
-// unnormalised space-time normal, the flux over a bilinear space-time patch
+// mesh moving with the fluid (Lagrangian mode): the Rusanov and HLL fluxes
+// through an unnormalised space-time normal, the flux over a bilinear space-time patch
 // (interior, transmissive and slip-wall edges) and the geometry part of a
 // least-squares row of the reconstruction, each with its vector-Jacobian
 // product; triangle areas. Written for host and device so that the products
@@ -166,6 +166,103 @@ AWHD inline void rusanov_flux_vjp(const double ql[4], const double qr[4], const 
 }
 
 // ------------------------------------------------------------------------
+// HLL flux through an unnormalised space-time normal and its product
+// ------------------------------------------------------------------------
+// F~(q) . N = f N_x + g N_y + q N_t; its product: qb += J^T fb, Nb += (f . fb, g . fb, q . fb)
+AWHD inline void ft_dot(const double q[4], const double N[3], double gam, double out[4]) {
+  double f[4], g[4];
+  euler_f_g(q, gam, f, g);
+  for (int v = 0; v < 4; ++v) out[v] = f[v] * N[0] + g[v] * N[1] + q[v] * N[2];
+}
+
+AWHD inline void ft_dot_vjp(const double q[4], const double N[3], double gam, const double ob[4], double qb[4],
+                            double Nb[3]) {
+  double f[4], g[4], fb[4], gb[4];
+  euler_f_g(q, gam, f, g);
+  for (int v = 0; v < 4; ++v) {
+    fb[v] = N[0] * ob[v];
+    gb[v] = N[1] * ob[v];
+    qb[v] += N[2] * ob[v];
+    Nb[0] += f[v] * ob[v];
+    Nb[1] += g[v] * ob[v];
+    Nb[2] += q[v] * ob[v];
+  }
+  euler_f_g_vjp(q, gam, fb, gb, qb);
+}
+
+// u . N_xy + N_t + sgn c |N_xy| and its product with sb onto q and N
+AWHD inline double hll_speed(const double q[4], const double N[3], double gam, double sgn) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  const double p = (gam - 1.0) * (q[3] - 0.5 * r * (u * u + v * v));
+  return u * N[0] + v * N[1] + N[2] + sgn * sqrt(gam * p / r) * sqrt(N[0] * N[0] + N[1] * N[1]);
+}
+
+AWHD inline void hll_speed_vjp(const double q[4], const double N[3], double gam, double sgn, double sb, double qb[4],
+                               double Nb[3]) {
+  const double r = q[0], u = q[1] / r, v = q[2] / r;
+  const double gm = gam - 1.0;
+  const double p = gm * (q[3] - 0.5 * r * (u * u + v * v));
+  const double c = sqrt(gam * p / r);
+  const double nxy = sqrt(N[0] * N[0] + N[1] * N[1]);
+  Nb[0] += sb * (u + sgn * c * N[0] / nxy);
+  Nb[1] += sb * (v + sgn * c * N[1] / nxy);
+  Nb[2] += sb;
+  // through u, v and c = sqrt(gam p / r)
+  const double cb = sgn * sb * nxy;
+  double rb = -cb * c / (2.0 * r), pb = cb * gam / (2.0 * c * r);
+  const double ub = sb * N[0] - gm * r * u * pb, vb = sb * N[1] - gm * r * v * pb;
+  rb += -gm * 0.5 * (u * u + v * v) * pb;
+  qb[0] += rb - (ub * u + vb * v) / r;
+  qb[1] += ub / r;
+  qb[2] += vb / r;
+  qb[3] += gm * pb;
+}
+
+// qlb, qrb, Nb += the product of Fb with the HLL flux's Jacobian: signal
+// speeds bounded over both states (the left state's speed on ties), upwind
+// when both have one sign, else (sr F(ql) - sl F(qr) + sl sr (qr - ql)) /
+// (sr - sl); the flux itself into F when F is not null.
+AWHD inline void hll_flux_vjp(const double ql[4], const double qr[4], const double N[3], double gam,
+                              const double Fb[4], double qlb[4], double qrb[4], double Nb[3], double* F = nullptr) {
+  const double l1 = hll_speed(ql, N, gam, -1.0), r1 = hll_speed(ql, N, gam, 1.0);
+  const double l2 = hll_speed(qr, N, gam, -1.0), r2 = hll_speed(qr, N, gam, 1.0);
+  const bool left_lo = l1 <= l2, left_hi = r1 >= r2;
+  const double sl = left_lo ? l1 : l2, sr = left_hi ? r1 : r2;
+  double fl[4], fr[4];
+  ft_dot(ql, N, gam, fl);
+  ft_dot(qr, N, gam, fr);
+  if (sl >= 0.0) {
+    if (F)
+      for (int v = 0; v < 4; ++v) F[v] = fl[v];
+    ft_dot_vjp(ql, N, gam, Fb, qlb, Nb);
+    return;
+  }
+  if (sr <= 0.0) {
+    if (F)
+      for (int v = 0; v < 4; ++v) F[v] = fr[v];
+    ft_dot_vjp(qr, N, gam, Fb, qrb, Nb);
+    return;
+  }
+  const double id = 1.0 / (sr - sl);
+  double flb[4], frb[4], slb = 0.0, srb = 0.0;
+  for (int v = 0; v < 4; ++v) {
+    const double d = qr[v] - ql[v];
+    const double Fv = (sr * fl[v] - sl * fr[v] + sl * sr * d) * id;
+    if (F) F[v] = Fv;
+    flb[v] = sr * id * Fb[v];
+    frb[v] = -sl * id * Fb[v];
+    qrb[v] += sl * sr * id * Fb[v];
+    qlb[v] -= sl * sr * id * Fb[v];
+    srb += Fb[v] * (fl[v] + sl * d - Fv) * id;
+    slb += Fb[v] * (-fr[v] + sr * d + Fv) * id;
+  }
+  ft_dot_vjp(ql, N, gam, flb, qlb, Nb);
+  ft_dot_vjp(qr, N, gam, frb, qrb, Nb);
+  hll_speed_vjp(left_lo ? ql : qr, N, gam, -1.0, slb, left_lo ? qlb : qrb, Nb);
+  hll_speed_vjp(left_hi ? ql : qr, N, gam, 1.0, srb, left_hi ? qlb : qrb, Nb);
+}
+
+// ------------------------------------------------------------------------
 // One edge's bilinear space-time patch over a global step (eqs.
 // eqn.spacetimenodes, G_ij, eqn.STint): old nodes a, b at time 0, new nodes at
 // dt; trL (nG, T, 4) the left element's trace along the edge. Outer state by
@@ -241,8 +338,8 @@ AWHD inline void patch_states(const double* trL, const double* trR, const double
   if (kind == SLIP) mirror(ql, N, qr);
 }
 
-// The flux through the patch, G (added to), and the products of Gb with its
-// Jacobian: the rows of the trace adjoints trLb and (interior) trRb are
+// The flux through the patch, G (added to; Rusanov, or HLL when hll), and the
+// products of Gb with its Jacobian: the rows of the trace adjoints trLb and (interior) trRb are
 // written, the means' adjoint avLb (transmissive) and the four corner nodes'
 // adjoints (xab, xbb, xanb, xbnb: x, y) are added to.
 template <int M>
@@ -250,7 +347,7 @@ AWHD inline void patch_flux_vjp(const Tables& tb, double gam, const double xa[2]
                                 const double xan[2], const double xbn[2], double dt, const double* trL,
                                 const double* trR, const double* avL, int kind, const double Gb[4], double G[4],
                                 double* trLb, double* trRb, double* avLb, double xab[2], double xbb[2],
-                                double xanb[2], double xbnb[2]) {
+                                double xanb[2], double xbnb[2], bool hll = false) {
   constexpr int T = M + 1, nG = M + 1;
   double P[4][3], Pb[4][3] = {};
   patch_corners<M>(xa, xb, xan, xbn, dt, P);
@@ -263,7 +360,10 @@ AWHD inline void patch_flux_vjp(const Tables& tb, double gam, const double xa[2]
       const double w = tb.gw[gq] * tb.gw[h];
       double Fb[4], F[4], qlb[4] = {}, qrb[4] = {}, Nb[3] = {};
       for (int v = 0; v < 4; ++v) Fb[v] = w * Gb[v];
-      rusanov_flux_vjp(ql, qr, N, gam, Fb, qlb, qrb, Nb, F);
+      if (hll)
+        hll_flux_vjp(ql, qr, N, gam, Fb, qlb, qrb, Nb, F);
+      else
+        rusanov_flux_vjp(ql, qr, N, gam, Fb, qlb, qrb, Nb, F);
       for (int v = 0; v < 4; ++v) G[v] += w * F[v];
       if (kind == SLIP) mirror_vjp(ql, N, qrb, qlb, Nb);
       for (int s = 0; s < T; ++s)

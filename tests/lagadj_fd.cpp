@@ -61,7 +61,9 @@ static void run(const Tables& tb) {
   constexpr int nb = D::nb, T = D::T, nG = D::nG, nu = D::nu;
   const double gam = 1.4, dt = 0.02;
   // ---- space-time patch flux ------------------------------------------------
-  for (int kind = 0; kind < 3; ++kind) {
+  for (int kh = 0; kh < 6; ++kh) {
+    const int kind = kh % 3;
+    const bool hll = kh >= 3;
     const int NT = nG * T * 4;
     std::vector<double> x(2 * NT + T * 4 + 8);
     for (int k = 0; k < 2 * nG * T; ++k) state(&x[k * 4]);
@@ -82,16 +84,16 @@ static void run(const Tables& tb) {
       double G[4] = {0, 0, 0, 0}, c8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       std::vector<double> t1(NT), t2(NT), t3(T * 4);
       patch_flux_vjp<M>(tb, gam, cc, cc + 2, cc + 4, cc + 6, dt, y.data(), y.data() + NT, y.data() + 2 * NT, kind,
-                        Gb, G, t1.data(), t2.data(), t3.data(), c8, c8 + 2, c8 + 4, c8 + 6);
+                        Gb, G, t1.data(), t2.data(), t3.data(), c8, c8 + 2, c8 + 4, c8 + 6, hll);
       return Gb[0] * G[0] + Gb[1] * G[1] + Gb[2] * G[2] + Gb[3] * G[3];
     };
     std::vector<double> an(x.size(), 0.0);
     double* ac = &an[2 * NT + T * 4];
     double G[4] = {0, 0, 0, 0};
     patch_flux_vjp<M>(tb, gam, c, c + 2, c + 4, c + 6, dt, x.data(), x.data() + NT, x.data() + 2 * NT, kind, Gb, G,
-                      an.data(), an.data() + NT, an.data() + 2 * NT, ac, ac + 2, ac + 4, ac + 6);
+                      an.data(), an.data() + NT, an.data() + 2 * NT, ac, ac + 2, ac + 4, ac + 6, hll);
     const char* name[3] = {"interior", "transmissive", "slip"};
-    std::printf("patch_%s M=%d %.3e\n", name[kind], M, check(x, an, L, 1e-6));
+    std::printf("patch_%s%s M=%d %.3e\n", hll ? "hll_" : "", name[kind], M, check(x, an, L, 1e-6));
   }
   // ---- least-squares row geometry ------------------------------------------
   {
@@ -154,6 +156,28 @@ int main() {
     std::vector<double> an(6, 0.0);
     area3_grad(x.data(), sb, an.data());
     std::printf("area M=0 %.3e\n", check(x, an, [&](const std::vector<double>& y) { return sb * area3(y.data()); }, 1e-6));
+  }
+  for (int rep = 0; rep < 6; ++rep) {
+    // N_t chosen so that the two signal speeds straddle 0, or both are
+    // positive (upwind left), or both negative (upwind right)
+    std::vector<double> x(11);
+    state(&x[0]);
+    state(&x[4]);
+    x[8] = uni(-0.1, 0.1);
+    x[9] = uni(-0.1, 0.1);
+    const double shift = rep < 2 ? 0.0 : (rep < 4 ? 1.0 : -1.0);
+    x[10] = uni(-0.02, 0.02) + shift;
+    double Fb[4];
+    for (auto& v : Fb) v = uni(-1, 1);
+    auto L = [&](const std::vector<double>& y) {
+      double F[4], d1[4], d2[4], d3[3];
+      hll_flux_vjp(&y[0], &y[4], &y[8], 1.4, Fb, d1, d2, d3, F);
+      return Fb[0] * F[0] + Fb[1] * F[1] + Fb[2] * F[2] + Fb[3] * F[3];
+    };
+    std::vector<double> an(11, 0.0);
+    hll_flux_vjp(&x[0], &x[4], &x[8], 1.4, Fb, &an[0], &an[4], &an[8]);
+    const char* nm[3] = {"hll_middle", "hll_upwind_left", "hll_upwind_right"};
+    std::printf("%s M=0 %.3e\n", nm[rep / 2], check(x, an, L, 1e-7));
   }
   for (int rep = 0; rep < 4; ++rep) {
     std::vector<double> x(11);
