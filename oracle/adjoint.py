@@ -395,24 +395,32 @@ class LagrangianStep:
 
     def reconstruct(self, Q, Xe):
         """wnod (NE, nb, 4) on the current geometry Xe (NE, 3, 2)."""
-        cfg, NE = self.cfg, self.NE
+        ss = torch.as_tensor(np.where(self.sten >= 0, self.sten, np.arange(self.NE)[:, None, None]),
+                             dtype=torch.long)
+        return self.recon_core(Xe, Q, Xe[ss], Q[ss], self.valid)
+
+    def recon_core(self, Xi, Qi_all, Xs, Qs, valid_np):
+        """wnod (n, nb, 4) of elements with vertices Xi (n, 3, 2) and averages
+        Qi_all (n, 4), their stencils' elements given as Xs (n, 7, ne, 3, 2)
+        and Qs (n, 7, ne, 4) (row 0 the element itself; real or projected
+        data), valid_np (n, 7) the stencils that exist."""
+        cfg, n_el = self.cfg, Xi.shape[0]
         nb = self.psiC.shape[0]
-        ws_all = torch.zeros((NE, 7, nb, 4), dtype=_F64)
-        sig_all = torch.zeros((NE, 7, 4), dtype=_F64)
+        ws_all = torch.zeros((n_el, 7, nb, 4), dtype=_F64)
+        sig_all = torch.zeros((n_el, 7, 4), dtype=_F64)
         for s in range(7):
-            idx_np = np.nonzero(self.valid[:, s])[0]
+            idx_np = np.nonzero(valid_np[:, s])[0]
             if idx_np.size == 0:
                 continue
             idx = torch.as_tensor(idx_np, dtype=torch.long)
-            js = torch.as_tensor(self.sten[idx_np, s], dtype=torch.long)        # (n, ne)
-            Xst = Xe[js]                                                          # (n, ne, 3, 2)
+            Xst = Xs[idx, s]                                                      # (n, ne, 3, 2)
             xq = _affine_map_t(Xst, self.qu, self.qv)                             # (n, ne, P, 2)
-            Xii = Xe[idx][:, None].expand_as(Xst)
+            Xii = Xi[idx][:, None].expand_as(Xst)
             xi, eta = _affine_inverse_t(Xii, xq)
             A = torch.einsum("njpl,p->njl", self._psi(xi, eta), self.qw)         # (n, ne, nb)
             c = A[:, 0, :]
-            Qi = Q[idx]
-            b = Q[js]                                                             # (n, ne, 4)
+            Qi = Qi_all[idx]
+            b = Qs[idx, s]                                                        # (n, ne, 4)
             Ar = A[:, 1:, 1:] - A[:, 1:, :1] * (c[:, None, 1:] / c[:, None, :1])
             br = b[:, 1:, :] - A[:, 1:, :1] * (Qi[:, None, :] / c[:, None, :1])
             Qf, Rf = torch.linalg.qr(Ar)
@@ -422,7 +430,7 @@ class LagrangianStep:
             sig = torch.einsum("nlv,lm,nmv->nv", ws, self.Sig, ws)
             ws_all = ws_all.index_put((idx, torch.full_like(idx, s)), ws)
             sig_all = sig_all.index_put((idx, torch.full_like(idx, s)), sig)
-        valid = torch.as_tensor(self.valid)
+        valid = torch.as_tensor(valid_np)
         if cfg.weno_shared:
             sig_all = sig_all.sum(dim=2, keepdim=True).expand(-1, -1, 4)
         wt = self.lam[None, :, None] / (sig_all + cfg.weno_eps) ** cfg.weno_r
@@ -433,16 +441,22 @@ class LagrangianStep:
 
     def predict(self, wnod, Xe, dt):
         """Space-time predictor with the mesh moving at the fluid velocity:
-        traces (NE, 3, nG, T, 4), means (NE, T, 4), vertex velocities (NE, 3, T, 2)."""
+        traces (NE, 3, nG, T, 4), means (NE, T, 4), vertex velocities (NE, 3, T, 2).
+        dt: one step for all elements, or one per element."""
         M, cfg = self.M, self.cfg
         T = M + 1
+        if np.ndim(dt):
+            dt = _t(dt)[:, None, None]
+            dt4 = dt[..., None]
+        else:
+            dt4 = dt
         q = wnod[:, :, None, :].expand(-1, -1, T, -1)
         x0 = _affine_map_t(Xe, self.nod_xi, self.nod_eta)                        # (NE, nb, 2)
         x = x0[:, :, None, :].expand(-1, -1, T, -1)
         d = lambda D, a: torch.einsum("km,nmtv->nktv", D, a)   # noqa: E731
         for _ in range(cfg.npic):
             V = q[..., 1:3] / q[..., 0:1]
-            xu = self.Bt[None, None, :, None] * x[:, :, 0:1, :] + dt * torch.einsum("qr,nmrc->nmqc", self.At, V)
+            xu = self.Bt[None, None, :, None] * x[:, :, 0:1, :] + dt4 * torch.einsum("qr,nmrc->nmqc", self.At, V)
             x = torch.cat([x[:, :, 0:1, :], xu], dim=2)
             x_xi, x_eta = d(self.Dxi, x), d(self.Deta, x)
             x_tau = torch.einsum("pq,nmqc->nmpc", self.Dt, x)
@@ -456,7 +470,7 @@ class LagrangianStep:
             P = -(d(self.Dxi, q) * xi_t[..., None] + d(self.Deta, q) * eta_t[..., None]
                   + d(self.Dxi, f) * xi_x[..., None] + d(self.Deta, f) * eta_x[..., None]
                   + d(self.Dxi, g) * xi_y[..., None] + d(self.Deta, g) * eta_y[..., None])
-            qu = self.Bt[None, None, :, None] * q[:, :, 0:1, :] + dt * torch.einsum("qr,nmrv->nmqv", self.At, P)
+            qu = self.Bt[None, None, :, None] * q[:, :, 0:1, :] + dt4 * torch.einsum("qr,nmrv->nmqv", self.At, P)
             q = torch.cat([q[:, :, 0:1, :], qu], dim=2)
         V = q[..., 1:3] / q[..., 0:1]
         return (torch.einsum("egm,nmtv->negtv", self.edge_tab, q),
@@ -526,3 +540,239 @@ class LagrangianStep:
         with torch.no_grad():
             qn, xn = self(_t(Q), _t(X), dt)
         return qn.numpy(), xn.numpy()
+
+
+# ---------------------------------------------------------------------------
+# Dyadic LTS macro step with its schedule frozen (mesh moving with the fluid)
+# ---------------------------------------------------------------------------
+def lts_schedule(solver, t_end, n_macro):
+    """Advance the NumPy LTS oracle `solver` by n_macro macro steps and return
+    what it decided: per macro step the tick length delta and, per element,
+    the steps (in ticks) it took, in order."""
+    out = []
+    for _ in range(n_macro):
+        before = [len(x) for x in solver.step_log]
+        solver.macro_step(t_end)
+        out.append((solver.st.delta, [solver.step_log[i][before[i]:] for i in range(len(before))]))
+    return out
+
+
+class LagrangianLTS:
+    """Macro steps of the local time stepping scheme (Sec. 2.6: dyadic levels,
+    the update criterion over the scheduling stencil, virtual projection of
+    the stencil in space and time, eqs. eqn.virtGeom and eqn.virtCellaverage;
+    the node solver over each node's own interval, eqs. eqn.dtau .. eqn.newVertex;
+    swept space-time patches with corners at different times, eqs.
+    eqn.spacetimenodes and eqn.STint; memory variables, eq. eqn.Qm2) with the
+    mesh moving with the fluid, written with PyTorch CPU operations in FP64
+    after the NumPy oracle's Solver, cycle by cycle, with the schedule held
+    fixed: the tick length of every macro step and every element's sequence of
+    steps are inputs (taken from a run of the NumPy oracle), so the update
+    sets, node and patch sets follow from integer ticks alone and the map
+    (Q, X, wnod) -> (Q', X', wnod') over a macro step is smooth where its
+    fluxes and WENO weights are. The state between macro steps is the
+    averages, the node positions and each element's last reconstruction
+    (nodal values wnod): element vertices and areas then follow from X."""
+
+    def __init__(self, nodes, tris, cfg: Config, bedges=None, topo=None):
+        if cfg.levels < 1:
+            raise ValueError("the frozen-schedule macro step covers dyadic levels (levels >= 1)")
+        self.g = LagrangianStep(nodes, tris, cfg, bedges=bedges, topo=topo)
+        g = self.g
+        self.cfg, self.M, self.topo = cfg, cfg.M, g.topo
+        self.NE, self.NV = g.NE, g.NV
+        self.sten = g.sten
+        self.r_node = g.r_node.numpy()
+        self.r_elem = g.r_elem.numpy()
+        self.r_lv = g.r_lv.numpy()
+
+    # -- pieces of a cycle ------------------------------------------------------
+    def _virtual(self, j, ntarget, Q, Xe, avg, vvel, n, s, delta):
+        """Vertices (..., 3, 2) and average (..., 4) of elements j projected to
+        tick ntarget with their predictors; real data where the ticks agree."""
+        M = self.M
+        same = n[j] == ntarget
+        sj = np.where(same, 1, s[j])
+        tau = np.where(same, 0.0, (ntarget - n[j]) / sj)
+        dtj = sj * delta
+        I = _t(tb.lagrange_time_integral(M, np.zeros_like(tau), tau))
+        lt = _t(tb.lagrange_time(M, tau))
+        jt = torch.as_tensor(j, dtype=torch.long)
+        Xv = Xe[jt] + _t(dtj)[..., None, None] * torch.einsum("...q,...kqc->...kc", I, vvel[jt])
+        Qv = torch.einsum("...q,...qv->...v", lt, avg[jt])
+        sm = torch.as_tensor(same)
+        return (torch.where(sm[..., None, None], Xe[jt], Xv), torch.where(sm[..., None], Q[jt], Qv))
+
+    def _reconstruct(self, act, Q, Xe, avg, vvel, n, s, delta):
+        sten = self.sten[act]
+        valid = sten[:, :, 0] >= 0
+        ss = np.where(sten >= 0, sten, act[:, None, None])
+        nt = np.broadcast_to(n[act][:, None, None], ss.shape)
+        Xs, Qs = self._virtual(ss, nt, Q, Xe, avg, vvel, n, s, delta)
+        ta = torch.as_tensor(act, dtype=torch.long)
+        return self.g.recon_core(Xe[ta], Q[ta], Xs, Qs, valid)
+
+    def _move(self, X, Q, A, vvel, n, s, nk, newtick, moved, delta):
+        """New node positions: each moved node over its own interval [nk, newtick]
+        with the mass-weighted mean of its ring's vertex velocities averaged over
+        that interval of each ring element's predictor."""
+        if moved.size == 0:
+            return X
+        g, M = self.g, self.M
+        sel = np.isin(self.r_node, moved)
+        rk, rj, rl = self.r_node[sel], self.r_elem[sel], self.r_lv[sel]
+        if (s[rj] <= 0).any():
+            raise AssertionError("node ring element without a valid predictor")
+        tau0 = (nk[rk] - n[rj]) / s[rj]
+        tau1 = (newtick[rk] - n[rj]) / s[rj]
+        I = _t(tb.lagrange_time_integral(M, tau0, tau1))
+        rjt, rlt, rkt = (torch.as_tensor(v, dtype=torch.long) for v in (rj, rl, rk))
+        vbar = torch.einsum("rq,rqc->rc", I, vvel[rjt, rlt]) / _t(tau1 - tau0)[:, None]
+        mu = Q[rjt, 0] * A[rjt]
+        num = torch.zeros((self.NV, 2), dtype=_F64).index_add(0, rkt, mu[:, None] * vbar)
+        den = torch.zeros(self.NV, dtype=_F64).index_add(0, rkt, mu)
+        mt = torch.as_tensor(moved, dtype=torch.long)
+        V = num[mt] / den[mt][:, None]
+        wn = g.wall_n[mt]
+        V = (V - (V * wn).sum(dim=1, keepdim=True) * wn) * g.wall_free[mt][:, None]
+        dtk = _t((newtick[moved] - nk[moved]) * delta)
+        return X.index_copy(0, mt, X[mt] + dtk[:, None] * V)
+
+    def _patches(self, X, Xn, nk, newtick, swept, n, s, trace, avg, delta):
+        """Fluxes G (E, 4), outward from L, over the swept edges' bilinear
+        space-time patches; each side's predictor is read at its own rescaled
+        time (tick - n) / s of the patch point."""
+        M, cfg, topo = self.M, self.cfg, self.topo
+        nG = M + 1
+        chi, wc = tb.gauss_legendre01(nG)
+        en = topo.edge_nodes
+        a, b = en[swept, 0], en[swept, 1]
+        L, R = topo.edge_elems[swept, 0], topo.edge_elems[swept, 1]
+        el, er = topo.edge_local[swept, 0], topo.edge_local[swept, 1]
+        hasR = R >= 0
+        Rs = np.where(hasR, R, L)
+        ers = np.where(hasR, er, el)
+        if (s[L] <= 0).any() or (hasR & (s[Rs] <= 0)).any():
+            raise AssertionError("patch neighbour without a valid predictor")
+        ta, tbn = torch.as_tensor(a, dtype=torch.long), torch.as_tensor(b, dtype=torch.long)
+
+        def col(v):
+            return _t(v * delta)[:, None]
+
+        P1 = torch.cat([X[ta], col(nk[a])], 1)
+        P2 = torch.cat([X[tbn], col(nk[b])], 1)
+        P3 = torch.cat([Xn[tbn], col(newtick[b])], 1)
+        P4 = torch.cat([Xn[ta], col(newtick[a])], 1)
+        ticks = np.stack([nk[a], nk[b], newtick[b], newtick[a]], 1).astype(float)
+        lt_ = torch.as_tensor(L, dtype=torch.long)
+        trL = trace[lt_, torch.as_tensor(el, dtype=torch.long)]
+        trR = trace[torch.as_tensor(Rs, dtype=torch.long), torch.as_tensor(ers, dtype=torch.long)]
+        avL = avg[lt_]
+        slip_np = topo.bc_tag[swept] == BC_SLIP
+        slip = torch.as_tensor(slip_np)
+        open_ = torch.as_tensor(~hasR & ~slip_np)
+        hasRt = torch.as_tensor(hasR)
+        sRs = np.where(hasR, s[Rs], 1)
+        G = torch.zeros((len(swept), 4), dtype=_F64)
+        for gg in range(nG):
+            for h in range(nG):
+                c, t = float(chi[gg]), float(chi[h])
+                dchi = (1 - t) * (P2 - P1) + t * (P3 - P4)
+                dtau = (1 - c) * (P4 - P1) + c * (P3 - P2)
+                N = torch.linalg.cross(dchi, dtau, dim=-1)
+                tk = ((1 - c) * (1 - t) * ticks[:, 0] + c * (1 - t) * ticks[:, 1] + c * t * ticks[:, 2]
+                      + (1 - c) * t * ticks[:, 3])
+                lL = _t(tb.lagrange_time(M, (tk - n[L]) / s[L]))
+                lR = _t(tb.lagrange_time(M, (tk - n[Rs]) / sRs))
+                ql = torch.einsum("eq,eqv->ev", lL, trL[:, gg])
+                qr = torch.where(slip[:, None], mirror(ql, N),
+                                 torch.where(open_[:, None], torch.einsum("eq,eqv->ev", lL, avL), ql))
+                qr = torch.where(hasRt[:, None], torch.einsum("eq,eqv->ev", lR, trR[:, nG - 1 - gg]), qr)
+                G = G + (wc[gg] * wc[h]) * FLUX_FUNCTIONS[cfg.flux](ql, qr, N, cfg.gamma)
+        return G, L, R, hasR
+
+    # -- the macro step --------------------------------------------------------
+    def macro(self, Q, X, W, delta, steps):
+        """(Q', X', W') after one macro step of tick length delta from (Q, X, W)
+        (torch: averages (NE, 4), positions (NV, 2), nodal reconstruction
+        (NE, nb, 4) at the macro-step start); steps[i]: element i's steps."""
+        from .scheme import MACRO_TICKS
+        g, topo = self.g, self.topo
+        NE, N = self.NE, MACRO_TICKS
+        tris = topo.tris
+        n = np.zeros(NE, np.int64)
+        nk = np.zeros(self.NV, np.int64)
+        pos = np.ones(NE, np.int64)
+        s = np.array([st[0] for st in steps], np.int64)
+        Xe = X[g.tris]
+        A = _tri_area_t(Xe)
+        trace, avg, vvel = g.predict(W, Xe, s * delta)
+        QM = torch.zeros((NE, 4), dtype=_F64)
+        en = topo.edge_nodes
+        while (n < N).any():
+            fut = n + s
+            act = np.array([i for i in range(NE) if n[i] < N
+                            and n[topo.sched[i]].max() <= fut[i] <= fut[topo.sched[i]].min()], np.int64)
+            if act.size == 0:
+                raise RuntimeError("deadlock: no element satisfies the update criterion")
+            newtick = nk.copy()
+            for i in act:
+                for k in tris[i]:
+                    if nk[k] < fut[i]:
+                        newtick[k] = fut[i]
+            moved = np.nonzero(newtick != nk)[0]
+            Xn = self._move(X, Q, A, vvel, n, s, nk, newtick, moved, delta)
+            is_moved = newtick != nk
+            swept = np.nonzero(is_moved[en[:, 0]] | is_moved[en[:, 1]])[0]
+            if swept.size:
+                G, L, R, hasR = self._patches(X, Xn, nk, newtick, swept, n, s, trace, avg, delta)
+                QM = QM.index_add(0, torch.as_tensor(L, dtype=torch.long), -G)
+                QM = QM.index_add(0, torch.as_tensor(R[hasR], dtype=torch.long), G[torch.as_tensor(hasR)])
+            X, nk = Xn, newtick
+            ta = torch.as_tensor(act, dtype=torch.long)
+            Xna = X[g.tris[ta]]
+            An = _tri_area_t(Xna)
+            Q = Q.index_copy(0, ta, (A[ta, None] * Q[ta] + QM[ta]) / An[:, None])
+            QM = QM.index_copy(0, ta, torch.zeros((act.size, 4), dtype=_F64))
+            A = A.index_copy(0, ta, An)
+            Xe = Xe.index_copy(0, ta, Xna)
+            n[act] = fut[act]
+            W = W.index_copy(0, ta, self._reconstruct(act, Q, Xe, avg, vvel, n, s, delta))
+            going = act[n[act] < N]
+            s[act[n[act] >= N]] = 0
+            for i in going:
+                s[i] = steps[i][pos[i]]
+                pos[i] += 1
+            if going.size:
+                tg = torch.as_tensor(going, dtype=torch.long)
+                tr, av, vv = g.predict(W[tg], Xe[tg], s[going] * delta)
+                trace = trace.index_copy(0, tg, tr)
+                avg = avg.index_copy(0, tg, av)
+                vvel = vvel.index_copy(0, tg, vv)
+        if any(pos[i] != len(steps[i]) for i in range(NE)):
+            raise ValueError("the schedule does not match the macro step")
+        return Q, X, W
+
+    def initial(self, Q, X):
+        """The reconstruction of the pre-processing (real neighbours)."""
+        return self.g.reconstruct(Q, X[self.g.tris])
+
+    def run(self, Q0, X0, schedule):
+        """(Q, X) after the macro steps of `schedule` from (Q0, X0), NumPy in and out."""
+        with torch.no_grad():
+            Q, X = _t(Q0), _t(X0)
+            W = self.initial(Q, X)
+            for delta, steps in schedule:
+                Q, X, W = self.macro(Q, X, W, delta, steps)
+        return Q.numpy(), X.numpy()
+
+    def vjp(self, Q0, X0, schedule, Qbar, Xbar):
+        """Adjoints of (Q0, X0) (through the pre-processing reconstruction too)
+        for the adjoints (Qbar, Xbar) of the final (Q, X); NumPy in and out."""
+        q = _t(Q0).requires_grad_(True)
+        x = _t(X0).requires_grad_(True)
+        Q, X, W = q, x, self.initial(q, x)
+        for delta, steps in schedule:
+            Q, X, W = self.macro(Q, X, W, delta, steps)
+        gq, gx = torch.autograd.grad((Q, X), (q, x), (_t(Qbar), _t(Xbar)))
+        return gq.detach().numpy(), gx.detach().numpy()

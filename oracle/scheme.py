@@ -576,6 +576,9 @@ class Solver:
         # k-th step p that the level rule chose for element i
         self.step_log = [[] for _ in range(NE)]
         self.step_hook = None
+        # delta_hook(m) may replace the tick length of macro step m (held fixed
+        # when a schedule is replayed under perturbed data)
+        self.delta_hook = None
         # pre-processing (Sec. 2.6): first reconstruction without projection and first CFL step
         allel = np.arange(NE)
         self._reconstruct(allel)
@@ -659,6 +662,8 @@ class Solver:
     def macro_begin(self, t_end):
         st = self.st
         st.delta = macro_tick(self.cfg.levels, float(st.dtcfl.min()), st.T, t_end, self.cfg.lts_fraction)
+        if self.delta_hook is not None:
+            st.delta = float(self.delta_hook(st.macro_steps))
         allel = np.arange(self.topo.n_elems)
         st.n[:] = 0
         st.nk[:] = 0
