@@ -315,6 +315,37 @@ int ader_adjoint_lagrangian_step(ader_ctx* ctx, double dt, const double* Q_dev, 
                                  double* Xbar_dev, double* Q_next_dev, double* X_next_dev, void* work_dev,
                                  size_t work_bytes);
 
+/* ---- Gradient through macro steps of the local time stepping -------------
+ * Dyadic LTS (Sec. 2.6) on the mesh moving with the fluid (mesh_velocity = 0)
+ * with the Rusanov or HLL flux, differentiated with its schedule held fixed:
+ * the tick length of every macro step and every element's sequence of steps
+ * are those the forward run takes (with ader_set_schedule_replay, the
+ * replayed ones), so the update sets and the moved nodes and swept edges of
+ * every cycle are fixed; the averages and node positions are differentiated
+ * through the pre-processing reconstruction, the virtual projection of the
+ * stencils in space and time (eqs. eqn.virtGeom, eqn.virtCellaverage), the
+ * predictor with the mesh ODE (eqs. CGfinal, VCG, newVertPos), the node
+ * solver over each node's own interval (eqs. eqn.dtau, NodesVel, eqnNScs,
+ * eqn.NScs.weights, eqn.newVertex), the swept patches with corners at
+ * different times (eqs. eqn.spacetimenodes, eqn.STint), the memory variables
+ * (eq. eqn.Qm2) and the updates (eq. PDEfinal).  From the uploaded state
+ * (Q_0, X_0) (no step may have been taken since ader_upload_state*), runs up
+ * to n_macro macro steps towards t_end (fewer when t_end is reached first:
+ * *n_done) and writes Qbar0 = (dQ_end/dQ_0)^T Qbar + (dX_end/dQ_0)^T Xbar and
+ * Xbar0 likewise with respect to X_0; subgradients as for
+ * ader_adjoint_gts_step.  The context ends at the state after the macro steps,
+ * as ader_step_lts would leave it.
+ *   Qbar_dev, Qbar0_dev: device [4][n_elems] SoA; Xbar_dev, Xbar0_dev:
+ *   device [n_nodes][2]; no output may overlap an input.
+ * Memory: the library allocates (and frees before returning) one copy of the
+ * changing simulation state per macro step and per cycle of one macro step,
+ * and scratch of about 1.6 KB per element at M = 2.  Synchronises.
+ * ADER_E_ARG for a fixed mesh, free steps, the Osher flux, a batch of
+ * instances or n_macro < 1; ADER_E_ORDER before a state upload or after a
+ * step; the forward run's own errors as ader_step_lts. */
+int ader_adjoint_lts(ader_ctx* ctx, int32_t n_macro, double t_end, const double* Qbar_dev, const double* Xbar_dev,
+                     double* Qbar0_dev, double* Xbar0_dev, int32_t* n_done);
+
 /* ---- Measurement: the predictor's derivative contraction -----------------
  * Not a step of the scheme: runs, in one timed launch on the context's
  * stream, `iters` rounds of the space-time predictor's spatial-derivative

@@ -1210,6 +1210,180 @@ int ader_adjoint_lagrangian_step(ader_ctx* c, double dt, const double* Q_dev, co
   return ADER_OK;
 }
 
+namespace {
+// The arrays of the simulation state that a time step changes, in a fixed
+// order: the saved copies of the LTS adjoint hold them one after another,
+// each 256-byte aligned.
+std::vector<std::pair<void*, size_t>> state_arrays(const ader_ctx* c) {
+  const aw::Dev& d = c->dev;
+  const size_t NE = d.NE, NV = d.NV, M = d.M, D = sizeof(double), I = sizeof(int);
+  std::vector<std::pair<void*, size_t>> a = {{d.scal, sizeof(aw::Scal)},
+                                             {d.inst, size_t(d.K) * sizeof(aw::Inst)},
+                                             {d.ts, NE * sizeof(aw::TickStep)},
+                                             {d.rec, NE * aw::rec_stride(int(M)) * D},
+                                             {d.trace, NE * aw::trace_stride(int(M)) * D},
+                                             {d.wnod, NE * aw::wnod_stride(int(M)) * D},
+                                             {d.dtcfl, NE * D},
+                                             {d.mem, NE * 3 * aw::MEM_W * D},
+                                             {d.act_stamp, NE * I},
+                                             {d.act_list, NE * I},
+                                             {d.live_list, NE * I},
+                                             {d.X, 2 * NV * D},
+                                             {d.Xnew, 2 * NV * D},
+                                             {d.ntick, NV * I},
+                                             {d.ntick_new, NV * I},
+                                             {d.node_stamp, NV * I}};
+  if (d.replay_pos) a.push_back({d.replay_pos, NE * I});
+  return a;
+}
+
+size_t al256(size_t n) { return (n + 255) & ~size_t(255); }
+
+size_t state_bytes(const ader_ctx* c) {
+  size_t n = 0;
+  for (const auto& a : state_arrays(c)) n += al256(a.second);
+  return n;
+}
+
+int state_copy(ader_ctx* c, char* saved, bool save) {
+  size_t off = 0;
+  for (const auto& a : state_arrays(c)) {
+    if (save)
+      HIPCHK(c, hipMemcpyAsync(saved + off, a.first, a.second, hipMemcpyDeviceToDevice, c->stream));
+    else
+      HIPCHK(c, hipMemcpyAsync(a.first, saved + off, a.second, hipMemcpyDeviceToDevice, c->stream));
+    off += al256(a.second);
+  }
+  return 0;
+}
+
+// The parts of a saved state that the adjoint kernels read.
+aw::LtsView state_view(const ader_ctx* c, const char* saved) {
+  const auto arr = state_arrays(c);
+  std::vector<const char*> at;
+  size_t off = 0;
+  for (const auto& a : arr) {
+    at.push_back(saved + off);
+    off += al256(a.second);
+  }
+  aw::LtsView v;
+  v.ts = (const aw::TickStep*)at[2];
+  v.rec = (const double*)at[3];
+  v.trace = (const double*)at[4];
+  v.wnod = (const double*)at[5];
+  v.X = (const double*)at[11];
+  v.ntick = (const int*)at[13];
+  return v;
+}
+
+// Forward over up to n_macro macro steps with the state saved at every
+// macro-step start, then the reverse sweep: per macro step (last first) a
+// replay from its saved start keeping the state after every cycle, the
+// cycles in reverse, the start's predictors in reverse; finally the
+// pre-processing reconstruction. The context ends at the forward's end state.
+int adjoint_lts_run(ader_ctx* c, int n_macro, double t_end, const double* Qbar, const double* Xbar, double* Qbar0,
+                    double* Xbar0, int* n_done, std::vector<char*>& bufs) {
+  const aw::Dev& d = c->dev;
+  const int M = c->cfg.M, L = c->cfg.lts_levels, nominal = 1 << (L - 1);
+  const size_t sb = state_bytes(c);
+  auto take = [&](char** out, size_t bytes) -> int {
+    HIPCHK(c, hipMalloc((void**)out, bytes));
+    bufs.push_back(*out);
+    return 0;
+  };
+  int r;
+  std::vector<char*> start;   // states at the macro-step starts, then the end state
+  char* b = nullptr;
+  if ((r = take(&b, sb))) return r;
+  start.push_back(b);
+  if ((r = state_copy(c, b, true))) return r;
+  int done = 0;
+  for (int m = 0; m < n_macro; ++m) {
+    const int64_t before = c->macro_steps;
+    if ((r = run_macro(c, t_end, 1, L))) return r;
+    if (c->macro_steps == before) break;   // t_end reached
+    if ((r = take(&b, sb))) return r;
+    start.push_back(b);
+    if ((r = state_copy(c, b, true))) return r;
+    ++done;
+  }
+  char* wb = nullptr;
+  const size_t wbytes = aw::lts_work_bytes(M, d.NE, d.NV, d.NF, c->prm.npic);
+  if ((r = take(&wb, wbytes))) return r;
+  aw::LtsWork w;
+  aw::lts_carve(M, d.NE, d.NV, d.NF, c->prm.npic, wb, w);
+  LCHK(c, aw::launch_lts_init(d, w, Qbar, Xbar, c->stream));
+  std::vector<char*> cyc;   // states after the macro-step start and after each cycle
+  for (int m = done - 1; m >= 0; --m) {
+    if ((r = state_copy(c, start[m], false))) return r;
+    LCHK(c, aw::launch_set_target(d, t_end, c->stream));
+    LCHK(c, aw::launch_open(d, c->stream));
+    if ((r = issue_macro_begin(c, nominal, c->stream))) return r;
+    if (cyc.empty()) {
+      if ((r = take(&b, sb))) return r;
+      cyc.push_back(b);
+    }
+    if ((r = state_copy(c, cyc[0], true))) return r;
+    aw::Inst in0;
+    HIPCHK(c, hipMemcpyAsync(&in0, d.inst, sizeof(in0), hipMemcpyDeviceToHost, c->stream));
+    aw::Scal s;
+    int nc = 0;
+    for (;;) {
+      if ((r = issue_cycles(c, 1, c->stream))) return r;
+      LCHK(c, aw::launch_status(d, c->stream));
+      if (int(cyc.size()) < nc + 2) {
+        if ((r = take(&b, sb))) return r;
+        cyc.push_back(b);
+      }
+      if ((r = state_copy(c, cyc[nc + 1], true))) return r;
+      if ((r = read_scal(c, s))) return r;
+      if ((r = check_err(c, s))) return r;
+      ++nc;
+      if (s.n_unfinished == 0) break;
+      if (nc > (1 << 20)) return fail(c, ADER_E_DEADLOCK, "LTS adjoint: the macro step does not end");
+    }
+    w.delta = in0.delta;
+    for (int k = nc - 1; k >= 0; --k) {
+      w.s0 = state_view(c, cyc[k]);
+      w.s1 = state_view(c, cyc[k + 1]);
+      LCHK(c, aw::launch_lts_cycle_rev(d, c->prm, M, w, c->stream));
+    }
+    w.s1 = state_view(c, cyc[0]);
+    LCHK(c, aw::launch_lts_macro_begin_rev(d, c->prm, M, w, c->stream));
+  }
+  w.s1 = state_view(c, start[0]);
+  LCHK(c, aw::launch_lts_initial_rev(d, c->prm, M, w, c->stream));
+  LCHK(c, aw::launch_lts_out(d, w, Qbar0, Xbar0, c->stream));
+  if ((r = state_copy(c, start[done], false))) return r;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->synced = true;
+  *n_done = done;
+  return 0;
+}
+}  // namespace
+
+int ader_adjoint_lts(ader_ctx* c, int32_t n_macro, double t_end, const double* Qbar_dev, const double* Xbar_dev,
+                     double* Qbar0_dev, double* Xbar0_dev, int32_t* n_done) {
+  if (!c || !Qbar_dev || !Xbar_dev || !Qbar0_dev || !Xbar0_dev || !n_done || n_macro < 1) return ADER_E_ARG;
+  if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
+  if (c->cycles != 0 || c->macro_steps != 0)
+    return fail(c, ADER_E_ORDER, "the LTS adjoint starts from an uploaded state with no step taken since");
+  if (c->cfg.mesh_velocity != 0) return fail(c, ADER_E_ARG, "the LTS adjoint needs the mesh moving with the fluid");
+  if (c->cfg.lts_levels < 1) return fail(c, ADER_E_ARG, "the LTS adjoint needs dyadic levels (lts_levels >= 1)");
+  if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the LTS adjoint runs one instance");
+  if (c->prm.flux != ADER_FLUX_RUSANOV && c->prm.flux != ADER_FLUX_HLL)
+    return fail(c, ADER_E_ARG, "the LTS adjoint covers the Rusanov and HLL fluxes");
+  if (!std::isfinite(t_end)) return fail(c, ADER_E_ARG, "t_end is not finite");
+  std::vector<char*> bufs;
+  int done = 0;
+  const int r = adjoint_lts_run(c, n_macro, t_end, Qbar_dev, Xbar_dev, Qbar0_dev, Xbar0_dev, &done, bufs);
+  (void)hipStreamSynchronize(c->stream);
+  for (char* p : bufs) (void)hipFree(p);
+  if (r) return r;
+  *n_done = done;
+  return ADER_OK;
+}
+
 int ader_probe_contraction(ader_ctx* c, int32_t use_mfma, int64_t n_elems, int32_t iters, const double* F_dev,
                            double* out_dev, float* ms) {
   if (!c || !F_dev || !out_dev || n_elems <= 0 || n_elems > INT32_MAX || iters < 1) return ADER_E_ARG;

@@ -35,6 +35,8 @@
 // not be kept.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <mutex>
 #include <vector>
 
@@ -369,23 +371,36 @@ __global__ void __launch_bounds__(TPB) k_adj_gather(Dev d, AdjWork w) {
 // the adjoint of row a_c is sum over the variables of r_c z - (a_c . z) w, pulled
 // back to the vertices of the stencil element (its slot) and of element i
 // (row 0 of the lane).
-template <int M, bool REV, bool GEO = false>
+// VIRT (local time stepping): the elements of lw.act_list, their own data
+// from the state lw.s1, the stencil rows from lw.vrows (the stencil elements
+// placed at the element's tick: real or projected).
+template <int M, bool REV, bool GEO = false, bool VIRT = false>
 __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restrict__ tb, Params P,
-                                                   AdjWork w) {
+                                                   AdjWork w, LtsWork lw) {
   using S = AZ<M>;
   constexpr int nb = S::nb, ne = S::ne, nu = S::nu, WS = S::WS;
   const int NE = d.NE;
   const int sl = threadIdx.x & 7;
   const int ngroups = (gridDim.x * blockDim.x) >> 3;
-  const double* gbase = w.geo ? w.geo : d.rec + XE;
-  const size_t gs = w.geo ? size_t(w.geo_stride) : size_t(S::RS);
-  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < NE; i += ngroups) {
+  const double* gbase = VIRT ? lw.s1.rec + XE : (w.geo ? w.geo : d.rec + XE);
+  const size_t gs = VIRT ? size_t(S::RS) : (w.geo ? size_t(w.geo_stride) : size_t(S::RS));
+  const int n_el = VIRT ? lw.counts[0] : NE;
+  for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; idx < n_el; idx += ngroups) {
+    const int i = VIRT ? lw.act_list[idx] : idx;
     const double* ri = gbase + size_t(i) * gs;
     double Xi[6], Qi[4];
 #pragma unroll
     for (int c = 0; c < 6; ++c) Xi[c] = ri[c];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Qi[v] = w.q[size_t(v) * NE + i];
+    for (int v = 0; v < 4; ++v) Qi[v] = VIRT ? lw.s1.rec[size_t(i) * S::RS + QO + v] : w.q[size_t(v) * NE + i];
+    // stencil row c of this lane: the element's vertices and average
+    auto row_x = [&](int c) -> const double* {
+      return VIRT ? lw.vrows + ((size_t(i) * ne + c) * 8 + sl) * 10 : gbase + size_t(d.sten[size_t(sl * ne + c) * NE + i]) * gs;
+    };
+    auto row_q = [&](int c, int v) -> double {
+      return VIRT ? lw.vrows[((size_t(i) * ne + c) * 8 + sl) * 10 + 6 + v]
+                  : w.q[size_t(v) * NE + d.sten[size_t(sl * ne + c) * NE + i]];
+    };
     const double e1x = Xi[2] - Xi[0], e1y = Xi[3] - Xi[1];
     const double e2x = Xi[4] - Xi[0], e2y = Xi[5] - Xi[1];
     const double idet = 1.0 / (e1x * e2y - e2x * e1y);
@@ -423,11 +438,11 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         for (int v = 0; v < 4; ++v) z[a][v] = 0.0;
 #pragma unroll 1
       for (int c = 1; c < ne; ++c) {
-        const double* rj = gbase + size_t(sidx[c * NE]) * gs;
+        const double* rj = row_x(c);
         double a[nu], b[4];
         ls_row<M>(rj, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) b[v] = w.q[size_t(v) * NE + sidx[c * NE]] - Qi[v];
+        for (int v = 0; v < 4; ++v) b[v] = row_q(c, v) - Qi[v];
 #pragma unroll
         for (int k = 0; k < nu; ++k) {
           const double rkk = R[k][k], ak = a[k];
@@ -578,8 +593,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
     double Xib[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int c = 1; c < ne; ++c) {
-      const int j = sidx[c * NE];
-      const double* Xj = gbase + size_t(j) * gs;
+      const double* Xj = row_x(c);
       double a[nu], bb[4];
       ls_row<M>(Xj, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
@@ -597,7 +611,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         for (int l = 0; l < nu; ++l) ab[l] = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          double r = w.q[size_t(v) * NE + j] - Qi[v];
+          double r = row_q(c, v) - Qi[v];
 #pragma unroll
           for (int l = 0; l < nu; ++l) r -= a[l] * ws[l][v];
 #pragma unroll
@@ -1082,9 +1096,11 @@ __device__ inline size_t keep_at(int k, int t, int v, int i, int m, int NE) {
 // lane, the spatial derivatives at a node take the element's other nodes
 // through LDS. Every iterate is kept (element-minor) for the reverse sweeps;
 // traces, means and vertex velocities as in the forward step.
-template <int M>
+// LTS: the elements of lw.going_list, each with its own step (ticks x
+// tick length) from the state lw.s1; only the iterates are kept.
+template <int M, bool LTS = false>
 __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __restrict__ tb, Params P,
-                                                      LagWork w, double dt) {
+                                                      LagWork w, double dt_all, LtsWork lz) {
   using S = AZ<M>;
   using L = LP<M>;
   constexpr int nb = L::nb, T = L::T, nG = L::nG, G = L::G, EPW = L::EPW, SLOTS = L::SLOTS;
@@ -1105,15 +1121,18 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __res
   }
   double nxi, neta;
   lag::lattice<M>(m, nxi, neta);
-  for (int base = blockIdx.x * SLOTS; base < NE; base += gridDim.x * SLOTS) {
-    const int i = spare ? -1 : base + slot;
-    const bool live = i >= 0 && i < NE;
+  const int n_el = LTS ? lz.counts[1] : NE;
+  for (int base = blockIdx.x * SLOTS; base < n_el; base += gridDim.x * SLOTS) {
+    const int idx = spare ? -1 : base + slot;
+    const bool live = idx >= 0 && idx < n_el;
+    const int i = !live ? -1 : (LTS ? lz.going_list[idx] : idx);
+    const double dt = LTS ? (live ? double(lz.s1.ts[i].step) * lz.delta : 1.0) : dt_all;
     double q[T][4], x[T][2], x0[2];
     if (live) {
-      const double* X = w.xe + size_t(i) * 6;
+      const double* X = LTS ? lz.s1.rec + size_t(i) * S::RS + XE : w.xe + size_t(i) * 6;
       x0[0] = X[0] + (X[2] - X[0]) * nxi + (X[4] - X[0]) * neta;
       x0[1] = X[1] + (X[3] - X[1]) * nxi + (X[5] - X[1]) * neta;
-      const double* wn = w.a.wnod + size_t(i) * S::WS + m * 4;
+      const double* wn = (LTS ? lz.s1.wnod : w.a.wnod) + size_t(i) * S::WS + m * 4;
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -1213,6 +1232,9 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __res
       for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) w.keep[keep_at<M>(P.npic, t, v, i, m, NE)] = q[t][v];
+    }
+    if (LTS) continue;   // traces, means and velocities are in the saved state
+    if (live) {
 #pragma unroll
       for (int kv = 0; kv < 3; ++kv) {
         if (tb->vtx[kv] != m) continue;
@@ -1466,9 +1488,13 @@ __global__ void __launch_bounds__(TPB) k_lag_node_rev(Dev d, const Tables* __res
 // area). Per sweep and time node the lanes exchange their forward fields,
 // then the products their node's equation sends to the other nodes (the
 // transposed spatial derivatives).
-template <int M>
+// LTS: the elements of lw.going_list with their own steps (state lw.s1); the
+// adjoints of the traces (g.a.tbar), means (avb) and vertex velocities (vvb)
+// are the element's own, added to the reconstruction's and the vertices'
+// adjoints and then cleared (the predictor's outputs are overwritten here).
+template <int M, bool LTS = false>
 __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __restrict__ tb, Params P,
-                                                      LagWork w, double dt) {
+                                                      LagWork w, double dt_all, LtsWork lz) {
   using S = AZ<M>;
   using L = LP<M>;
   constexpr int nb = L::nb, T = L::T, nG = L::nG, G = L::G, EPW = L::EPW, SLOTS = L::SLOTS;
@@ -1493,9 +1519,12 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
   lag::tint01<M>(*tb, I);
   double nxi, neta;
   lag::lattice<M>(m, nxi, neta);
-  for (int base = blockIdx.x * SLOTS; base < NE; base += gridDim.x * SLOTS) {
-    const int i = spare ? -1 : base + slot;
-    const bool live = i >= 0 && i < NE;
+  const int n_el = LTS ? lz.counts[1] : NE;
+  for (int base = blockIdx.x * SLOTS; base < n_el; base += gridDim.x * SLOTS) {
+    const int idx = spare ? -1 : base + slot;
+    const bool live = idx >= 0 && idx < n_el;
+    const int i = !live ? -1 : (LTS ? lz.going_list[idx] : idx);
+    const double dt = LTS ? (live ? double(lz.s1.ts[i].step) * lz.delta : 1.0) : dt_all;
     // the element's trace adjoints into LDS, a share per lane, then every lane
     // reads the ones its node contributes to
     constexpr int NTB = 3 * nG * T * 4;
@@ -1506,7 +1535,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
     lag_wave_sync();
     double x0[2], qb[T][4];
     if (live) {
-      const double* X = w.xe + size_t(i) * 6;
+      const double* X = LTS ? lz.s1.rec + size_t(i) * S::RS + XE : w.xe + size_t(i) * 6;
       x0[0] = X[0] + (X[2] - X[0]) * nxi + (X[4] - X[0]) * neta;
       x0[1] = X[1] + (X[3] - X[1]) * nxi + (X[5] - X[1]) * neta;
       // adjoint of the final iterate at this node: traces, means, vertex velocity
@@ -1514,9 +1543,9 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ab[t][v] = 0.0;
+        for (int v = 0; v < 4; ++v) ab[t][v] = LTS ? lz.avb[(size_t(i) * T + t) * 4 + v] : 0.0;
 #pragma unroll
-      for (int le = 0; le < 3; ++le) {
+      for (int le = 0; le < 3 && !LTS; ++le) {
         const int e = d.elem_edges[le * NE + i];
         if (d.e_R[e] < 0 && d.e_bc[e] != 2) {
           const double* a = w.a.abar + size_t(e) * T * 4;
@@ -1541,12 +1570,13 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
       for (int kv = 0; kv < 3; ++kv) {
         if (tb->vtx[kv] != m) continue;
         const double* o = w.nslot + (size_t(i) * 3 + kv) * 3;
+        const double* ov = lz.vvb + (size_t(i) * 3 + kv) * T * 2;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
           const double q0 = w.keep[keep_at<M>(P.npic, t, 0, i, m, NE)];
           const double q1 = w.keep[keep_at<M>(P.npic, t, 1, i, m, NE)];
           const double q2 = w.keep[keep_at<M>(P.npic, t, 2, i, m, NE)];
-          const double vxb = I[t] * o[0], vyb = I[t] * o[1];
+          const double vxb = LTS ? ov[2 * t] : I[t] * o[0], vyb = LTS ? ov[2 * t + 1] : I[t] * o[1];
           qb[t][0] -= (vxb * q1 + vyb * q2) / (q0 * q0);
           qb[t][1] += vxb / q0;
           qb[t][2] += vyb / q0;
@@ -1758,7 +1788,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
         double s = 0.0;
 #pragma unroll
         for (int t = 0; t < T; ++t) s += qb[t][v];
-        wb[v] = s;
+        wb[v] = LTS ? wb[v] + s : s;
       }
     }
     // x0 = (1 - xi - eta) X0 + xi X1 + eta X2: the element's vertex adjoints,
@@ -1770,7 +1800,27 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
       my[(2 * c + 1) * G + m] = bw[c] * x0b[1];
     }
     lag_wave_sync();
-    if (live && m == 0) {
+    if (LTS && live && m == 0) {
+      double* xo = w.a.xeb + size_t(i) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < nb; ++kk) s += my[c * G + kk];
+        xo[c] += s;
+      }
+      double* av = lz.avb + size_t(i) * T * 4;
+#pragma unroll
+      for (int k = 0; k < T * 4; ++k) av[k] = 0.0;
+      double* vv = lz.vvb + size_t(i) * 3 * T * 2;
+#pragma unroll
+      for (int k = 0; k < 3 * T * 2; ++k) vv[k] = 0.0;
+    }
+    if (LTS && live) {
+      double* tbi = w.a.tbar + size_t(i) * S::TS;
+      for (int c = m; c < NTB; c += G) tbi[c] = 0.0;
+    }
+    if (!LTS && live && m == 0) {
       double xb6[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
@@ -1834,11 +1884,11 @@ int grid_for(long n) {
 template <int M>
 int adjoint_gts(const Dev& d, const Params& p, const AdjWork& w, double dt, bool from_ctx, void* s) {
   if (from_ctx) AD_LAUNCH(k_adj_state<M>, d.NE, s, d, w);
-  AD_LAUNCH((k_adj_recon<M, false>), 8L * d.NE, s, d, d.tab, p, w);
+  AD_LAUNCH((k_adj_recon<M, false>), 8L * d.NE, s, d, d.tab, p, w, LtsWork{});
   AD_LAUNCH(k_adj_pred_fwd<M>, d.NE, s, d, d.tab, p, w, dt);
   AD_LAUNCH(k_adj_patch<M>, d.NF, s, d, d.tab, p, w, dt);
   AD_LAUNCH(k_adj_pred_rev<M>, d.NE, s, d, d.tab, p, w, dt);
-  AD_LAUNCH((k_adj_recon<M, true>), 8L * d.NE, s, d, d.tab, p, w);
+  AD_LAUNCH((k_adj_recon<M, true>), 8L * d.NE, s, d, d.tab, p, w, LtsWork{});
   AD_LAUNCH(k_adj_gather<M>, 8L * d.NE, s, d, w);
   return 0;
 }
@@ -1857,19 +1907,509 @@ int adjoint_lagrangian(const Dev& d, const Params& p, LagWork w, double dt, bool
   if (qctx) w.a.q = w.a.qcopy;
   if (xctx) w.x = w.xcopy;
   AD_LAUNCH(k_lag_geom<M>, d.NE > d.NV ? d.NE : d.NV, s, d, w, int(xctx), int(qctx));
-  AD_LAUNCH((k_adj_recon<M, false, true>), 8L * d.NE, s, d, d.tab, p, w.a);
-  AD_LAUNCH_BLOCKS(k_lag_pred_fwd<M>, pb, s, d, d.tab, p, w, dt);
+  AD_LAUNCH((k_adj_recon<M, false, true>), 8L * d.NE, s, d, d.tab, p, w.a, LtsWork{});
+  AD_LAUNCH_BLOCKS(k_lag_pred_fwd<M>, pb, s, d, d.tab, p, w, dt, LtsWork{});
   AD_LAUNCH(k_lag_node_fwd<M>, d.NV, s, d, d.tab, w, dt);
   AD_LAUNCH(k_lag_area_new<M>, d.NE, s, d, w);
   AD_LAUNCH(k_lag_patch<M>, d.NF, s, d, d.tab, p, w, dt);
   AD_LAUNCH(k_lag_update_rev<M>, d.NE, s, d, w);
   AD_LAUNCH(k_lag_node_rev<M>, d.NV, s, d, d.tab, w, dt);
-  AD_LAUNCH_BLOCKS(k_lag_pred_rev<M>, pb, s, d, d.tab, p, w, dt);
-  AD_LAUNCH((k_adj_recon<M, true, true>), 8L * d.NE, s, d, d.tab, p, w.a);
+  AD_LAUNCH_BLOCKS(k_lag_pred_rev<M>, pb, s, d, d.tab, p, w, dt, LtsWork{});
+  AD_LAUNCH((k_adj_recon<M, true, true>), 8L * d.NE, s, d, d.tab, p, w.a, LtsWork{});
   AdjWork g = w.a;
   g.qbar_next = w.qdir;
   AD_LAUNCH((k_adj_gather<M, true>), 8L * d.NE, s, d, g);
   AD_LAUNCH(k_lag_node_gather<M>, d.NV, s, d, w);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Local time stepping in reverse, schedule frozen: one cycle (update criterion
+// already decided) is the node motion, the swept patches, the update of the
+// active elements, their reconstruction from the stencil placed at their new
+// tick, and the predictors of those that stay short of the macro-step end.
+// Its reverse reads the saved states before (s0) and after (s1) the cycle.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(TPB) k_lts_clear_counts(LtsWork lw) {
+  if (blockIdx.x == 0 && threadIdx.x < 2) lw.counts[threadIdx.x] = 0;
+}
+
+// Flags and lists of the cycle from the ticks on both sides of it; all = 1:
+// every element updated and predicted, no node moved.
+__global__ void __launch_bounds__(TPB) k_lts_marks(Dev d, LtsWork lw, int all) {
+  const int NE = d.NE, NV = d.NV;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    int f = 3;
+    if (!all) {
+      const int t0 = lw.s0.ts[i].tick, t1 = lw.s1.ts[i].tick;
+      f = t1 != t0 ? (1 | (t1 < MACRO_TICKS ? 2 : 0)) : 0;
+    }
+    lw.eflag[i] = f;
+    if (f & 1) lw.act_list[atomicAdd(&lw.counts[0], 1)] = i;
+    if (f & 2) lw.going_list[atomicAdd(&lw.counts[1], 1)] = i;
+  }
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x)
+    lw.nflag[k] = all ? 0 : int(lw.s1.ntick[k] != lw.s0.ntick[k]);
+}
+
+// Rows of every updated element's stencils: the stencil element at the
+// element's new tick (eqs. eqn.virtGeom and eqn.virtCellaverage), its stored
+// vertices and average when it is at that tick, else its predictor's vertex
+// trajectories and cell means at the rescaled time. 8 lanes per element.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lts_vrows(Dev d, const Tables* __restrict__ tb, LtsWork lw) {
+  using S = AZ<M>;
+  constexpr int ne = S::ne, T = M + 1, AVG = rec_off_avg(), VV = rec_off_vv(M);
+  const int NE = d.NE;
+  const int sl = threadIdx.x & 7;
+  const int ngroups = (gridDim.x * blockDim.x) >> 3;
+  const int n_el = lw.counts[0];
+  for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; idx < n_el; idx += ngroups) {
+    const int i = lw.act_list[idx];
+    if (sl >= NSTEN) continue;
+    const int* sidx = d.sten + size_t(sl * ne) * NE + i;
+    if (sidx[0] < 0) continue;
+    const int nt = lw.s1.ts[i].tick;
+    for (int c = 1; c < ne; ++c) {
+      const int j = sidx[c * NE];
+      const TickStep tj = lw.s1.ts[j];
+      const double* rj = lw.s1.rec + size_t(j) * S::RS;
+      double* o = lw.vrows + ((size_t(i) * ne + c) * 8 + sl) * 10;
+      if (tj.tick == nt) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o[k] = rj[XE + k];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[6 + v] = rj[QO + v];
+        continue;
+      }
+      const double tau = double(nt - tj.tick) / double(tj.step);
+      const double dtj = double(tj.step) * lw.delta;
+      double L[T], l[T];
+      lag::tanti<M>(*tb, tau, L);
+      lag::tbasis<M>(*tb, tau, l);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < T; ++q) s += L[q] * rj[VV + ((k / 2) * T + q) * 2 + (k % 2)];
+        o[k] = rj[XE + k] + dtj * s;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < T; ++q) s += l[q] * rj[AVG + q * 4 + v];
+        o[6 + v] = s;
+      }
+    }
+  }
+}
+
+// Per element j, 8 lanes: the own terms of its reconstruction (updated j) and
+// the rows of updated elements' stencils that name j, through the placement
+// in reverse: into j's average and vertices (same tick) or into its
+// predictor's means and vertex velocities and its vertices (projected). The
+// updated elements' reconstruction adjoints are consumed.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lts_gather(Dev d, const Tables* __restrict__ tb, LtsWork lw) {
+  using S = AZ<M>;
+  constexpr int ne = S::ne, T = M + 1, WS = S::WS;
+  constexpr int OA = 10, OV = 10 + 4 * T, NACC = 10 + 10 * T;
+  const int NE = d.NE;
+  const int sl = threadIdx.x & 7;
+  const int ngroups = (gridDim.x * blockDim.x) >> 3;
+  const double* rowbar = lw.g.a.rowbar;
+  for (int j = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; j < NE; j += ngroups) {
+    double acc[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
+    const int fj = lw.eflag[j];
+    if (fj & 1) {
+      const double* r = rowbar + (size_t(j) * ne * 8 + sl) * 10;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) acc[k] += r[k];
+    }
+    const TickStep tj = lw.s1.ts[j];
+    const int k1 = d.tsten_ptr[j + 1];
+    for (int k = d.tsten_ptr[j] + sl; k < k1; k += 8) {
+      const int slot = d.tsten_idx[k];
+      const int i = slot / (ne * 8);
+      if (!(lw.eflag[i] & 1)) continue;
+      const double* r = rowbar + size_t(slot) * 10;
+      double rv[10];
+#pragma unroll
+      for (int c = 0; c < 10; ++c) rv[c] = r[c];
+      const int ti = lw.s1.ts[i].tick;
+#pragma unroll
+      for (int c = 4; c < 10; ++c) acc[c] += rv[c];
+      if (ti == tj.tick) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += rv[v];
+      } else {
+        const double tau = double(ti - tj.tick) / double(tj.step);
+        const double dtj = double(tj.step) * lw.delta;
+        double L[T], l[T];
+        lag::tanti<M>(*tb, tau, L);
+        lag::tbasis<M>(*tb, tau, l);
+#pragma unroll
+        for (int q = 0; q < T; ++q) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[OA + q * 4 + v] += l[q] * rv[v];
+#pragma unroll
+          for (int kc = 0; kc < 6; ++kc) acc[OV + ((kc / 2) * T + q) * 2 + (kc % 2)] += dtj * L[q] * rv[4 + kc];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) acc[k] = group8_sum(acc[k]);
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+      if ((k & 7) != sl) continue;
+      if (k < 4)
+        lw.qb[size_t(j) * 4 + k] += acc[k];
+      else if (k < 10)
+        lw.g.a.xeb[size_t(j) * 6 + k - 4] += acc[k];
+      else if (k < OV)
+        lw.avb[size_t(j) * T * 4 + k - OA] += acc[k];
+      else
+        lw.vvb[size_t(j) * 3 * T * 2 + k - OV] += acc[k];
+    }
+    if (fj & 1)
+      for (int c = sl; c < WS; c += 8) lw.g.a.wbar[size_t(j) * WS + c] = 0.0;
+  }
+}
+
+// Update of each updated element in reverse: Q' = (|T| Q + sum of its memory
+// variables) / |T'|, |T'| the area of its new vertices, which it stores with
+// |T'|. Its new vertices' adjoints go to (element, vertex) slots for the nodes.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lts_update_rev(Dev d, LtsWork lw) {
+  using S = AZ<M>;
+  const int NE = d.NE;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+    if (!(lw.eflag[i] & 1)) continue;
+    const double* r0 = lw.s0.rec + size_t(i) * S::RS;
+    const double* r1 = lw.s1.rec + size_t(i) * S::RS;
+    const double A0 = r0[AO], An = r1[AO];
+    double Anb = lw.ab[i], A0b = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double qb = lw.qb[size_t(i) * 4 + v];
+      Anb -= qb * r1[QO + v] / An;
+      A0b += qb * r0[QO + v] / An;
+      lw.qb[size_t(i) * 4 + v] = (A0 / An) * qb;
+      lw.mb[size_t(i) * 4 + v] = qb / An;
+    }
+    lw.ab[i] = A0b;
+    double xn[6], g[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      xn[c] = r1[XE + c];
+      g[c] = lw.g.a.xeb[size_t(i) * 6 + c];
+      lw.g.a.xeb[size_t(i) * 6 + c] = 0.0;
+    }
+    lag::area3_grad(xn, Anb, g);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) lw.g.xnbe[size_t(i) * 6 + c] = g[c];
+  }
+}
+
+// Swept patches in reverse, one lane per edge with a moved node: the flux's
+// adjoint is that of the memory variables it was added to (inflow positive
+// into R, outflow from L); onto both sides' traces (added), the inner mean
+// (transmissive, per edge) and the four corners (per edge).
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lts_patch(Dev d, const Tables* __restrict__ tb, Params P, LtsWork lw) {
+  using S = AZ<M>;
+  constexpr int T = S::T, nG = S::nG, TS = S::TS, NT = nG * T * 4;
+  const int NV = d.NV, NF = d.NF;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
+    const int a = d.e_a[e], b = d.e_b[e];
+    const bool ma = lw.nflag[a] != 0, mvb = lw.nflag[b] != 0;
+    if (!ma && !mvb) continue;
+    const double* X0 = lw.s0.X;
+    const double* X1 = lw.s1.X;
+    const double xa[2] = {X0[a], X0[NV + a]}, xb[2] = {X0[b], X0[NV + b]};
+    const double xan[2] = {ma ? X1[a] : xa[0], ma ? X1[NV + a] : xa[1]};
+    const double xbn[2] = {mvb ? X1[b] : xb[0], mvb ? X1[NV + b] : xb[1]};
+    const int L = d.e_L[e], el = d.e_el[e], R = d.e_R[e], er = d.e_er[e];
+    const bool hasR = R >= 0;
+    const int kind = hasR ? lag::INTERIOR : (d.e_bc[e] == 2 ? lag::SLIP : lag::TRANSMISSIVE);
+    lag::PatchTimes pt;
+    pt.tk[0] = double(lw.s0.ntick[a]);
+    pt.tk[1] = double(lw.s0.ntick[b]);
+    pt.tk[2] = double(lw.s1.ntick[b]);
+    pt.tk[3] = double(lw.s1.ntick[a]);
+    const TickStep tL = lw.s0.ts[L];
+    const TickStep tR = hasR ? lw.s0.ts[R] : tL;
+    pt.nL = double(tL.tick);
+    pt.sL = double(tL.step);
+    pt.nR = double(tR.tick);
+    pt.sR = double(tR.step);
+    pt.delta = lw.delta;
+    const double* trL = lw.s0.trace + size_t(L) * TS + el * NT;
+    const double* trR = hasR ? lw.s0.trace + size_t(R) * TS + er * NT : trL;
+    const double* avL = lw.s0.rec + size_t(L) * S::RS + rec_off_avg();
+    double Gb[4], G[4] = {0.0, 0.0, 0.0, 0.0}, bA[T * 4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Gb[v] = -lw.mb[size_t(L) * 4 + v] + (hasR ? lw.mb[size_t(R) * 4 + v] : 0.0);
+#pragma unroll
+    for (int k = 0; k < T * 4; ++k) bA[k] = 0.0;
+    double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double* oL = lw.g.a.tbar + size_t(L) * TS + el * NT;
+    double* oR = hasR ? lw.g.a.tbar + size_t(R) * TS + er * NT : oL;
+    lag::patch_flux_vjp_lts<M>(*tb, P.gamma, xa, xb, xan, xbn, pt, trL, trR, avL, kind, Gb, G, oL, oR, bA, c,
+                               c + 2, c + 4, c + 6, P.flux == ADER_FLUX_HLL);
+    if (kind == lag::TRANSMISSIVE) {
+      double* aL = lw.abar_e + size_t(e) * T * 4;
+#pragma unroll
+      for (int k = 0; k < T * 4; ++k) aL[k] = bA[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) lw.g.xs[size_t(e) * 8 + k] = c[k];
+  }
+}
+
+// Per node: the adjoint of its position after the cycle (carried, the updated
+// ring elements' new vertices, the swept patches' end corners) and, for a
+// moved node, the node solver over its own interval in reverse (eqs.
+// eqn.dtau, NodesVel, eqnNScs, eqn.NScs.weights, eqn.newVertex): into the
+// ring's vertex velocities (each (element, vertex) written by its node only)
+// and masses ((element, vertex) slots); the patches' start corners.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lts_node_rev(Dev d, const Tables* __restrict__ tb, LtsWork lw) {
+  using S = AZ<M>;
+  constexpr int T = M + 1, VV = rec_off_vv(M);
+  const int NV = d.NV;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
+    double xn[2] = {lw.xb[2 * k], lw.xb[2 * k + 1]};
+    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      if (lw.eflag[j] & 1) {
+        xn[0] += lw.g.xnbe[size_t(j) * 6 + 2 * lv];
+        xn[1] += lw.g.xnbe[size_t(j) * 6 + 2 * lv + 1];
+      }
+    }
+    double xo[2] = {0.0, 0.0};
+    node_edges(d, k, [&](int e, int isb) {
+      if (!lw.nflag[d.e_a[e]] && !lw.nflag[d.e_b[e]]) return;
+      xn[0] += lw.g.xs[size_t(e) * 8 + 4 + 2 * isb];
+      xn[1] += lw.g.xs[size_t(e) * 8 + 5 + 2 * isb];
+      xo[0] += lw.g.xs[size_t(e) * 8 + 2 * isb];
+      xo[1] += lw.g.xs[size_t(e) * 8 + 1 + 2 * isb];
+    });
+    lw.xb[2 * k] = xn[0] + xo[0];
+    lw.xb[2 * k + 1] = xn[1] + xo[1];
+    if (!lw.nflag[k]) continue;
+    const int nk = lw.s0.ntick[k], newt = lw.s1.ntick[k];
+    // the ring mean, recomputed from the state before the cycle
+    double num[2] = {0.0, 0.0}, den = 0.0;
+    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      const TickStep tj = lw.s0.ts[j];
+      const double tau0 = double(nk - tj.tick) / double(tj.step), tau1 = double(newt - tj.tick) / double(tj.step);
+      double L0[T], L1[T];
+      lag::tanti<M>(*tb, tau0, L0);
+      lag::tanti<M>(*tb, tau1, L1);
+      const double* rj = lw.s0.rec + size_t(j) * S::RS;
+      const double inv = 1.0 / (tau1 - tau0);
+      double vx = 0.0, vy = 0.0;
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        vx += (L1[q] - L0[q]) * rj[VV + (lv * T + q) * 2];
+        vy += (L1[q] - L0[q]) * rj[VV + (lv * T + q) * 2 + 1];
+      }
+      const double mu = rj[QO] * rj[AO];
+      num[0] += mu * (vx * inv);
+      num[1] += mu * (vy * inv);
+      den += mu;
+    }
+    const double V[2] = {num[0] / den, num[1] / den};
+    const double dtk = double(newt - nk) * lw.delta;
+    double Vb[2] = {dtk * xn[0], dtk * xn[1]};
+    if (d.wall_pin[k]) {
+      Vb[0] = Vb[1] = 0.0;
+    } else {
+      const double nx = d.wall_n[k], ny = d.wall_n[NV + k];
+      const double vn = Vb[0] * nx + Vb[1] * ny;
+      Vb[0] -= vn * nx;
+      Vb[1] -= vn * ny;
+    }
+    const double numb[2] = {Vb[0] / den, Vb[1] / den};
+    const double denb = -(numb[0] * V[0] + numb[1] * V[1]);
+    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      const TickStep tj = lw.s0.ts[j];
+      const double tau0 = double(nk - tj.tick) / double(tj.step), tau1 = double(newt - tj.tick) / double(tj.step);
+      double L0[T], L1[T];
+      lag::tanti<M>(*tb, tau0, L0);
+      lag::tanti<M>(*tb, tau1, L1);
+      const double* rj = lw.s0.rec + size_t(j) * S::RS;
+      const double inv = 1.0 / (tau1 - tau0);
+      double vx = 0.0, vy = 0.0;
+      double* vo = lw.vvb + (size_t(j) * 3 + lv) * T * 2;
+      const double mu = rj[QO] * rj[AO];
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        const double I = L1[q] - L0[q];
+        vx += I * rj[VV + (lv * T + q) * 2];
+        vy += I * rj[VV + (lv * T + q) * 2 + 1];
+        vo[2 * q] += mu * numb[0] * I * inv;
+        vo[2 * q + 1] += mu * numb[1] * I * inv;
+      }
+      lw.g.nslot[(size_t(j) * 3 + lv) * 3] = numb[0] * (vx * inv) + numb[1] * (vy * inv) + denb;
+    }
+  }
+}
+
+// Per element: the ring masses rho |T| of its moved vertices (state before
+// the cycle) and the means' adjoints of its transmissive swept edges.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lts_elem(Dev d, LtsWork lw) {
+  using S = AZ<M>;
+  constexpr int T = M + 1;
+  const int NE = d.NE;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < NE; j += gridDim.x * blockDim.x) {
+    const double* r0 = lw.s0.rec + size_t(j) * S::RS;
+#pragma unroll
+    for (int lv = 0; lv < 3; ++lv) {
+      if (!lw.nflag[d.tri[lv * NE + j]]) continue;
+      const double mub = lw.g.nslot[(size_t(j) * 3 + lv) * 3];
+      lw.qb[size_t(j) * 4] += mub * r0[AO];
+      lw.ab[j] += mub * r0[QO];
+    }
+#pragma unroll
+    for (int le = 0; le < 3; ++le) {
+      const int e = d.elem_edges[le * NE + j];
+      if (d.e_L[e] != j || d.e_R[e] >= 0 || d.e_bc[e] == 2) continue;
+      if (!lw.nflag[d.e_a[e]] && !lw.nflag[d.e_b[e]]) continue;
+#pragma unroll
+      for (int k = 0; k < T * 4; ++k) lw.avb[size_t(j) * T * 4 + k] += lw.abar_e[size_t(e) * T * 4 + k];
+    }
+  }
+}
+
+// Where the stored vertices and areas are those of the node positions (a
+// macro-step boundary, the uploaded state): their adjoints added to the
+// nodes' (view s1), then cleared by k_lts_clear_geo.
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lts_fold(Dev d, LtsWork lw) {
+  using S = AZ<M>;
+  const int NV = d.NV;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
+    double x[2] = {0.0, 0.0};
+    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      double xe[6], g[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        xe[c] = lw.s1.rec[size_t(j) * S::RS + XE + c];
+        g[c] = lw.g.a.xeb[size_t(j) * 6 + c];
+      }
+      lag::area3_grad(xe, lw.ab[j], g);
+      x[0] += g[2 * lv];
+      x[1] += g[2 * lv + 1];
+    }
+    lw.xb[2 * k] += x[0];
+    lw.xb[2 * k + 1] += x[1];
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_lts_clear_geo(Dev d, LtsWork lw) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x) {
+    lw.ab[i] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) lw.g.a.xeb[size_t(i) * 6 + c] = 0.0;
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(TPB) k_lts_init(Dev d, LtsWork lw, const double* Qbar, const double* Xbar) {
+  using S = AZ<M>;
+  constexpr int T = M + 1;
+  const int NE = d.NE, NV = d.NV;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      lw.qb[size_t(i) * 4 + v] = Qbar[size_t(v) * NE + i];
+      lw.mb[size_t(i) * 4 + v] = 0.0;
+    }
+    lw.ab[i] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) lw.g.a.xeb[size_t(i) * 6 + c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < S::WS; ++c) lw.g.a.wbar[size_t(i) * S::WS + c] = 0.0;
+    for (int c = 0; c < S::TS; ++c) lw.g.a.tbar[size_t(i) * S::TS + c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < T * 4; ++c) lw.avb[size_t(i) * T * 4 + c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6 * T; ++c) lw.vvb[size_t(i) * 6 * T + c] = 0.0;
+  }
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
+    lw.xb[2 * k] = Xbar[2 * k];
+    lw.xb[2 * k + 1] = Xbar[2 * k + 1];
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_lts_out(Dev d, LtsWork lw, double* Qbar, double* Xbar) {
+  const int NE = d.NE, NV = d.NV;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Qbar[size_t(v) * NE + i] = lw.qb[size_t(i) * 4 + v];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * NV; k += gridDim.x * blockDim.x) Xbar[k] = lw.xb[k];
+}
+
+template <int M>
+int lts_pred_rev(const Dev& d, const Params& p, const LtsWork& w, void* s) {
+  long pb = (long(d.NE) + LP<M>::SLOTS - 1) / LP<M>::SLOTS;
+  if (pb > 16384) pb = 16384;
+  AD_LAUNCH_BLOCKS((k_lag_pred_fwd<M, true>), pb, s, d, d.tab, p, w.g, 0.0, w);
+  AD_LAUNCH_BLOCKS((k_lag_pred_rev<M, true>), pb, s, d, d.tab, p, w.g, 0.0, w);
+  return 0;
+}
+
+template <int M>
+int lts_recon_rev(const Dev& d, const Params& p, const LtsWork& w, void* s) {
+  AD_LAUNCH(k_lts_vrows<M>, 8L * d.NE, s, d, d.tab, w);
+  AD_LAUNCH((k_adj_recon<M, false, true, true>), 8L * d.NE, s, d, d.tab, p, w.g.a, w);
+  AD_LAUNCH((k_adj_recon<M, true, true, true>), 8L * d.NE, s, d, d.tab, p, w.g.a, w);
+  AD_LAUNCH(k_lts_gather<M>, 8L * d.NE, s, d, d.tab, w);
+  return 0;
+}
+
+template <int M>
+int lts_cycle_rev(const Dev& d, const Params& p, const LtsWork& w, void* s) {
+  AD_LAUNCH(k_lts_clear_counts, 1, s, w);
+  AD_LAUNCH(k_lts_marks, d.NE > d.NV ? d.NE : d.NV, s, d, w, 0);
+  int r;
+  if ((r = lts_pred_rev<M>(d, p, w, s))) return r;
+  if ((r = lts_recon_rev<M>(d, p, w, s))) return r;
+  AD_LAUNCH(k_lts_update_rev<M>, d.NE, s, d, w);
+  AD_LAUNCH(k_lts_patch<M>, d.NF, s, d, d.tab, p, w);
+  AD_LAUNCH(k_lts_node_rev<M>, d.NV, s, d, d.tab, w);
+  AD_LAUNCH(k_lts_elem<M>, d.NE, s, d, w);
+  return 0;
+}
+
+template <int M>
+int lts_macro_begin_rev(const Dev& d, const Params& p, const LtsWork& w, void* s) {
+  AD_LAUNCH(k_lts_clear_counts, 1, s, w);
+  AD_LAUNCH(k_lts_marks, d.NE > d.NV ? d.NE : d.NV, s, d, w, 1);
+  int r;
+  if ((r = lts_pred_rev<M>(d, p, w, s))) return r;
+  AD_LAUNCH(k_lts_fold<M>, d.NV, s, d, w);
+  AD_LAUNCH(k_lts_clear_geo, d.NE, s, d, w);
+  return 0;
+}
+
+template <int M>
+int lts_initial_rev(const Dev& d, const Params& p, const LtsWork& w, void* s) {
+  AD_LAUNCH(k_lts_clear_counts, 1, s, w);
+  AD_LAUNCH(k_lts_marks, d.NE > d.NV ? d.NE : d.NV, s, d, w, 1);
+  int r;
+  if ((r = lts_recon_rev<M>(d, p, w, s))) return r;
+  AD_LAUNCH(k_lts_fold<M>, d.NV, s, d, w);
+  AD_LAUNCH(k_lts_clear_geo, d.NE, s, d, w);
   return 0;
 }
 
@@ -1960,7 +2500,109 @@ LagPlan lag_plan(int M, int NE, int NV, int NF, int npic) {
   p.add(ne * NE * 80 * D);                         // 23 row slots (10 doubles)
   return p;
 }
+
+// Buffers of the local-time-stepping adjoint, in carve order.
+LagPlan lts_plan(int M, int NE, int NV, int NF, int npic) {
+  const size_t D = sizeof(double), I = sizeof(int), nb = size_t(M + 1) * (M + 2) / 2, T = M + 1, ne = 2 * nb;
+  LagPlan p;
+  p.add(size_t(NE) * wnod_stride(M) * D);          // 0 recomputed reconstruction
+  p.add(size_t(NE) * wnod_stride(M) * D);          // 1 wbar
+  p.add(size_t(NE) * trace_stride(M) * D);         // 2 tbar
+  p.add(size_t(npic + 1) * nb * T * 4 * NE * D);   // 3 keep
+  p.add(size_t(lsq_slots(M)) * 8 * NE * D);        // 4 lsq
+  p.add(ne * NE * 80 * D);                         // 5 row slots
+  p.add(size_t(NF) * 8 * D);                       // 6 xs
+  p.add(size_t(NE) * 6 * D);                       // 7 xnbe
+  p.add(size_t(NE) * 9 * D);                       // 8 nslot
+  p.add(size_t(NE) * 6 * D);                       // 9 xeb
+  p.add(size_t(NE) * 4 * D);                       // 10 qb
+  p.add(size_t(NE) * D);                           // 11 ab
+  p.add(size_t(NE) * 4 * D);                       // 12 mb
+  p.add(size_t(NE) * T * 4 * D);                   // 13 avb
+  p.add(size_t(NE) * 6 * T * D);                   // 14 vvb
+  p.add(size_t(NV) * 2 * D);                       // 15 xb
+  p.add(size_t(NF) * T * 4 * D);                   // 16 abar_e
+  p.add(ne * NE * 80 * D);                         // 17 vrows
+  p.add(size_t(NE) * I);                           // 18 eflag
+  p.add(size_t(NV) * I);                           // 19 nflag
+  p.add(size_t(NE) * I);                           // 20 act_list
+  p.add(size_t(NE) * I);                           // 21 going_list
+  p.add(2 * I);                                    // 22 counts
+  return p;
+}
 }  // namespace
+
+size_t lts_work_bytes(int M, int NE, int NV, int NF, int npic) { return lts_plan(M, NE, NV, NF, npic).total; }
+
+void lts_carve(int M, int NE, int NV, int NF, int npic, char* base, LtsWork& w) {
+  const LagPlan p = lts_plan(M, NE, NV, NF, npic);
+  auto at = [&](int k) { return reinterpret_cast<double*>(base + p.off[k]); };
+  auto ai = [&](int k) { return reinterpret_cast<int*>(base + p.off[k]); };
+  w = LtsWork{};
+  w.g.a.wnod = at(0);
+  w.g.a.wbar = at(1);
+  w.g.a.tbar = at(2);
+  w.g.keep = at(3);
+  w.g.a.lsq = at(4);
+  w.g.a.rowbar = at(5);
+  w.g.xs = at(6);
+  w.g.xnbe = at(7);
+  w.g.nslot = at(8);
+  w.g.a.xeb = at(9);
+  w.qb = at(10);
+  w.ab = at(11);
+  w.mb = at(12);
+  w.avb = at(13);
+  w.vvb = at(14);
+  w.xb = at(15);
+  w.abar_e = at(16);
+  w.vrows = at(17);
+  w.eflag = ai(18);
+  w.nflag = ai(19);
+  w.act_list = ai(20);
+  w.going_list = ai(21);
+  w.counts = ai(22);
+}
+
+#define LTS_DISPATCH(fn, ...)                          \
+  switch (M) {                                         \
+    case 1: return fn<1>(__VA_ARGS__);                 \
+    case 2: return fn<2>(__VA_ARGS__);                 \
+    case 3: return fn<3>(__VA_ARGS__);                 \
+    default: return int(hipErrorInvalidValue);         \
+  }
+
+int launch_lts_init(const Dev& d, const LtsWork& w, const double* Qbar, const double* Xbar, void* s) {
+  const int M = d.M;
+  auto go = [&](auto tag) -> int {
+    constexpr int MM = decltype(tag)::value;
+    AD_LAUNCH(k_lts_init<MM>, d.NE > d.NV ? d.NE : d.NV, s, d, w, Qbar, Xbar);
+    return 0;
+  };
+  switch (M) {
+    case 1: return go(std::integral_constant<int, 1>{});
+    case 2: return go(std::integral_constant<int, 2>{});
+    case 3: return go(std::integral_constant<int, 3>{});
+    default: return int(hipErrorInvalidValue);
+  }
+}
+
+int launch_lts_cycle_rev(const Dev& d, const Params& p, int M, const LtsWork& w, void* s) {
+  LTS_DISPATCH(lts_cycle_rev, d, p, w, s)
+}
+
+int launch_lts_macro_begin_rev(const Dev& d, const Params& p, int M, const LtsWork& w, void* s) {
+  LTS_DISPATCH(lts_macro_begin_rev, d, p, w, s)
+}
+
+int launch_lts_initial_rev(const Dev& d, const Params& p, int M, const LtsWork& w, void* s) {
+  LTS_DISPATCH(lts_initial_rev, d, p, w, s)
+}
+
+int launch_lts_out(const Dev& d, const LtsWork& w, double* Qbar, double* Xbar, void* s) {
+  AD_LAUNCH(k_lts_out, d.NE > 2 * d.NV ? d.NE : 2 * d.NV, s, d, w, Qbar, Xbar);
+  return 0;
+}
 
 size_t lagadj_work_bytes(int M, int NE, int NV, int NF, int npic) {
   return lag_plan(M, NE, NV, NF, npic).total;

@@ -212,6 +212,45 @@ struct LagWork {
   double* qdir;              // [4][NE] adjoint of the averages not through the reconstruction
 };
 
+// A saved copy of the simulation state as the adjoint of the local time
+// stepping reads it: element records, traces, reconstructions, ticks and
+// steps, node positions and node ticks.
+struct LtsView {
+  const double* rec;      // [NE][rec_stride]
+  const double* trace;    // [NE][trace_stride]
+  const double* wnod;     // [NE][wnod_stride]
+  const TickStep* ts;     // [NE]
+  const double* X;        // [2][NV]
+  const int* ntick;       // [NV]
+};
+
+// Adjoint state and scratch of the reverse sweep through the cycles of a
+// macro step of the local time stepping (adjoint.hip). The adjoints are those
+// of the stored state: averages qb, areas ab, element vertices g.a.xeb, the
+// reconstruction g.a.wbar, the predictor's traces g.a.tbar, cell means avb and
+// vertex velocities vvb, the memory variables mb (one per element: the update
+// sums its three edge slots), node positions xb. s0 / s1: the state before /
+// after the cycle being reversed.
+struct LtsWork {
+  LagWork g;          // g.a.lsq, g.a.rowbar, g.a.wnod (recomputed reconstruction), g.keep,
+                      // g.xs [NF][8] patch corners, g.xnbe [NE][6] new vertices, g.nslot [NE][3][3]
+  double* qb;         // [NE][4]
+  double* ab;         // [NE]
+  double* mb;         // [NE][4]
+  double* avb;        // [NE][M+1][4]
+  double* vvb;        // [NE][3][M+1][2]
+  double* xb;         // [NV][2]
+  double* abar_e;     // [NF][M+1][4] means' adjoint from a transmissive patch
+  double* vrows;      // [NE][ne][8][10] stencil rows placed at the element's tick (vertices, average)
+  int* eflag;         // [NE] bit 0: updated in the cycle; bit 1: takes a new predictor
+  int* nflag;         // [NV] moved in the cycle
+  int* act_list;      // [NE]
+  int* going_list;    // [NE]
+  int* counts;        // [2] lengths of the two lists
+  double delta;       // tick length of the macro step
+  LtsView s0, s1;
+};
+
 // Device address of the library's fixed adjoint scratch on the current GPU
 // and its size (adjoint.hip); looked up once per device.
 int static_scratch(void** ptr, size_t* bytes);
@@ -227,6 +266,23 @@ void adjoint_carve(int M, int NE, int NF, int npic, char* base, AdjWork& w);
 // step of length dt on a fixed mesh (adjoint.hip).
 int launch_adjoint_gts(const Dev& d, const Params& p, int M, const AdjWork& w, double dt,
                        bool state_from_context, void* stream);
+// Reverse mode of the local time stepping (adjoint.hip), schedule frozen.
+// Bytes of the scratch (each buffer 256-byte aligned) and its carving.
+size_t lts_work_bytes(int M, int NE, int NV, int NF, int npic);
+void lts_carve(int M, int NE, int NV, int NF, int npic, char* base, LtsWork& w);
+// The adjoint state from (Qbar [4][NE], Xbar [NV][2]) with every other part zero.
+int launch_lts_init(const Dev& d, const LtsWork& w, const double* Qbar, const double* Xbar, void* stream);
+// Reverse of one cycle from the states before (w.s0) and after (w.s1) it.
+int launch_lts_cycle_rev(const Dev& d, const Params& p, int M, const LtsWork& w, void* stream);
+// Reverse of the predictors of every element at a macro-step start (w.s1: the
+// state after the start), then the element vertices' and areas' adjoints
+// folded into the node positions'.
+int launch_lts_macro_begin_rev(const Dev& d, const Params& p, int M, const LtsWork& w, void* stream);
+// Reverse of the pre-processing reconstruction (real neighbours, w.s1: the
+// state after upload), folded into the node positions' adjoints.
+int launch_lts_initial_rev(const Dev& d, const Params& p, int M, const LtsWork& w, void* stream);
+// (Qbar [4][NE], Xbar [NV][2]) from the adjoint state.
+int launch_lts_out(const Dev& d, const LtsWork& w, double* Qbar, double* Xbar, void* stream);
 
 // The derivative-contraction measurement (probe.hip): one launch, M = 2
 // tables, F and out [n][10][6]; blocks <= 0: one block per 40 elements.

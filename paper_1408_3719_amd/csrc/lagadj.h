@@ -47,6 +47,16 @@ AWHD inline void tbasis(const Tables& tb, double tau, double l[M + 1]) {
   }
 }
 
+// int_0^tau l_q
+template <int M>
+AWHD inline void tanti(const Tables& tb, double tau, double L[M + 1]) {
+  for (int q = 0; q <= M; ++q) {
+    double s = tb.Lint[q][M + 1];
+    for (int k = M; k >= 0; --k) s = s * tau + tb.Lint[q][k];
+    L[q] = s;
+  }
+}
+
 // int_0^1 l_q
 template <int M>
 AWHD inline void tint01(const Tables& tb, double I[M + 1]) {
@@ -392,6 +402,95 @@ AWHD inline void patch_flux_vjp(const Tables& tb, double gam, const double xa[2]
       for (int v = 0; v < 4; ++v) {
         trLb[(gq * T + s) * 4 + v] = rl[s][v];
         if (kind == INTERIOR) trRb[((nG - 1 - gq) * T + s) * 4 + v] = rr[s][v];
+      }
+  }
+  for (int c = 0; c < 2; ++c) {
+    xab[c] += Pb[0][c];
+    xbb[c] += Pb[1][c];
+    xbnb[c] += Pb[2][c];
+    xanb[c] += Pb[3][c];
+  }
+}
+
+// Times of a patch swept in a cycle of the local time stepping: its corners
+// (old a, old b, new b, new a) at ticks tk, and each side's predictor slab
+// [n, n + s) in ticks (the right side unused on boundary edges); delta the
+// tick length.
+struct PatchTimes {
+  double tk[4];
+  double nL, sL, nR, sR;
+  double delta;
+};
+
+// patch_flux_vjp for a patch with corners at different times: each side's
+// traces are read at the rescaled time (tick - n) / s of the point.
+template <int M>
+AWHD inline void patch_flux_vjp_lts(const Tables& tb, double gam, const double xa[2], const double xb[2],
+                                    const double xan[2], const double xbn[2], const PatchTimes& pt,
+                                    const double* trL, const double* trR, const double* avL, int kind,
+                                    const double Gb[4], double G[4], double* trLb, double* trRb, double* avLb,
+                                    double xab[2], double xbb[2], double xanb[2], double xbnb[2], bool hll) {
+  constexpr int T = M + 1, nG = M + 1;
+  double P[4][3], Pb[4][3] = {};
+  P[0][0] = xa[0];  P[0][1] = xa[1];  P[0][2] = pt.tk[0] * pt.delta;
+  P[1][0] = xb[0];  P[1][1] = xb[1];  P[1][2] = pt.tk[1] * pt.delta;
+  P[2][0] = xbn[0]; P[2][1] = xbn[1]; P[2][2] = pt.tk[2] * pt.delta;
+  P[3][0] = xan[0]; P[3][1] = xan[1]; P[3][2] = pt.tk[3] * pt.delta;
+  for (int gq = 0; gq < nG; ++gq) {
+    double rl[T][4] = {}, rr[T][4] = {};
+    for (int h = 0; h < nG; ++h) {
+      double N[3], lt[M + 1], dc[3], dtau[3], ql[4], qr[4];
+      patch_point<M>(tb, gq, h, P, N, lt, dc, dtau);
+      const double c = tb.gchi[gq], t = tb.gchi[h];
+      const double tkp = (1.0 - c) * (1.0 - t) * pt.tk[0] + c * (1.0 - t) * pt.tk[1] + c * t * pt.tk[2] +
+                         (1.0 - c) * t * pt.tk[3];
+      double lL[T], lR[T];
+      tbasis<M>(tb, (tkp - pt.nL) / pt.sL, lL);
+      tbasis<M>(tb, kind == INTERIOR ? (tkp - pt.nR) / pt.sR : 0.0, lR);
+      for (int v = 0; v < 4; ++v) {
+        double a = 0.0, b = 0.0;
+        for (int s = 0; s < T; ++s) {
+          a += lL[s] * trL[(gq * T + s) * 4 + v];
+          if (kind == INTERIOR) b += lR[s] * trR[((nG - 1 - gq) * T + s) * 4 + v];
+          if (kind == TRANSMISSIVE) b += lL[s] * avL[s * 4 + v];
+        }
+        ql[v] = a;
+        qr[v] = b;
+      }
+      if (kind == SLIP) mirror(ql, N, qr);
+      const double w = tb.gw[gq] * tb.gw[h];
+      double Fb[4], F[4], qlb[4] = {}, qrb[4] = {}, Nb[3] = {};
+      for (int v = 0; v < 4; ++v) Fb[v] = w * Gb[v];
+      if (hll)
+        hll_flux_vjp(ql, qr, N, gam, Fb, qlb, qrb, Nb, F);
+      else
+        rusanov_flux_vjp(ql, qr, N, gam, Fb, qlb, qrb, Nb, F);
+      for (int v = 0; v < 4; ++v) G[v] += w * F[v];
+      if (kind == SLIP) mirror_vjp(ql, N, qrb, qlb, Nb);
+      for (int s = 0; s < T; ++s)
+        for (int v = 0; v < 4; ++v) {
+          rl[s][v] += lL[s] * qlb[v];
+          if (kind == INTERIOR) rr[s][v] += lR[s] * qrb[v];
+          if (kind == TRANSMISSIVE) avLb[s * 4 + v] += lL[s] * qrb[v];
+        }
+      double dcb[3], dtb[3];
+      dcb[0] = dtau[1] * Nb[2] - dtau[2] * Nb[1];
+      dcb[1] = dtau[2] * Nb[0] - dtau[0] * Nb[2];
+      dcb[2] = dtau[0] * Nb[1] - dtau[1] * Nb[0];
+      dtb[0] = Nb[1] * dc[2] - Nb[2] * dc[1];
+      dtb[1] = Nb[2] * dc[0] - Nb[0] * dc[2];
+      dtb[2] = Nb[0] * dc[1] - Nb[1] * dc[0];
+      for (int k = 0; k < 3; ++k) {
+        Pb[1][k] += (1.0 - t) * dcb[k] - c * dtb[k];
+        Pb[0][k] -= (1.0 - t) * dcb[k] + (1.0 - c) * dtb[k];
+        Pb[2][k] += t * dcb[k] + c * dtb[k];
+        Pb[3][k] += -t * dcb[k] + (1.0 - c) * dtb[k];
+      }
+    }
+    for (int s = 0; s < T; ++s)
+      for (int v = 0; v < 4; ++v) {
+        trLb[(gq * T + s) * 4 + v] += rl[s][v];
+        if (kind == INTERIOR) trRb[((nG - 1 - gq) * T + s) * 4 + v] += rr[s][v];
       }
   }
   for (int c = 0; c < 2; ++c) {

@@ -94,6 +94,32 @@ static void run(const Tables& tb) {
                       an.data(), an.data() + NT, an.data() + 2 * NT, ac, ac + 2, ac + 4, ac + 6, hll);
     const char* name[3] = {"interior", "transmissive", "slip"};
     std::printf("patch_%s%s M=%d %.3e\n", hll ? "hll_" : "", name[kind], M, check(x, an, L, 1e-6));
+    // the same patch swept in a cycle of the local time stepping: corners at
+    // different ticks, each side read over its own slab
+    PatchTimes pt;
+    pt.tk[0] = 0.0;
+    pt.tk[1] = 2.0;
+    pt.tk[2] = 4.0;
+    pt.tk[3] = 3.0;
+    pt.nL = 0.0;
+    pt.sL = 4.0;
+    pt.nR = 2.0;
+    pt.sR = 2.0;
+    pt.delta = dt / 4.0;
+    auto Lt = [&](const std::vector<double>& y) {
+      const double* cc = &y[2 * NT + T * 4];
+      double G[4] = {0, 0, 0, 0}, c8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      std::vector<double> t1(NT), t2(NT), t3(T * 4);
+      patch_flux_vjp_lts<M>(tb, gam, cc, cc + 2, cc + 4, cc + 6, pt, y.data(), y.data() + NT, y.data() + 2 * NT,
+                            kind, Gb, G, t1.data(), t2.data(), t3.data(), c8, c8 + 2, c8 + 4, c8 + 6, hll);
+      return Gb[0] * G[0] + Gb[1] * G[1] + Gb[2] * G[2] + Gb[3] * G[3];
+    };
+    std::vector<double> at(x.size(), 0.0);
+    double* act = &at[2 * NT + T * 4];
+    double Gt[4] = {0, 0, 0, 0};
+    patch_flux_vjp_lts<M>(tb, gam, c, c + 2, c + 4, c + 6, pt, x.data(), x.data() + NT, x.data() + 2 * NT, kind, Gb,
+                          Gt, at.data(), at.data() + NT, at.data() + 2 * NT, act, act + 2, act + 4, act + 6, hll);
+    std::printf("patch_lts_%s%s M=%d %.3e\n", hll ? "hll_" : "", name[kind], M, check(x, at, Lt, 1e-6));
   }
   // ---- least-squares row geometry ------------------------------------------
   {

@@ -1,0 +1,92 @@
+"""Gradient through macro steps of the local time stepping on the mesh moving
+with the fluid, through the C ABI (ader_adjoint_lts), the schedule held fixed:
+averages and node positions of the uploaded state, element by element and node
+by node against the reverse-mode oracle (torch.autograd through the oracle's
+LTS macro steps replaying the same tick lengths and steps) on small meshes with
+three levels (vortex, explosion; Rusanov and HLL); the context's end state
+against the oracle's forward run; with one level against the adjoint of the
+global Lagrangian step (ader_adjoint_lagrangian_step)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from test_oracle_adjoint_lts import _case  # noqa: E402
+
+from oracle.adjoint import LagrangianLTS, lts_schedule  # noqa: E402
+from oracle.scheme import Config as OConfig  # noqa: E402
+from oracle.scheme import Solver as OSolver  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _gpu(mesh, Q0, levels, flux):
+    from paper_1408_3719_amd import Config, Solver
+    return Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
+                  Config(M=2, levels=levels, mesh_velocity="lagrangian", flux=flux))
+
+
+@pytest.mark.parametrize("name,flux", [("vortex", "rusanov"), ("explosion", "rusanov"), ("explosion", "hll")])
+def test_lts_adjoint_matches_reverse_mode_oracle(name, flux):
+    mesh, Q0 = _case(name)
+    print(f"lts adjoint {name} {flux} {mesh.n_elems} triangles, 3 levels, 2 macro steps", flush=True)
+    cfg = OConfig(M=2, levels=3, mesh_velocity="lagrangian", flux=flux)
+    o = OSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+    sched = lts_schedule(o, 10.0, 2)
+    lt = LagrangianLTS(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+    rng = np.random.default_rng(6)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    ref_q, ref_x = lt.vjp(Q0, mesh.nodes, sched, qb, xb)
+    g = _gpu(mesh, Q0, 3, flux)
+    g.set_schedule_replay(o.step_log)
+    gq, gx, done = g.adjoint_lts(2, 10.0, qb, xb)
+    assert done == 2
+    gq, gx = gq.cpu().numpy().T, gx.cpu().numpy()
+    for v in range(4):
+        assert _rel(gq[:, v], ref_q[:, v]) < TOL, (v, _rel(gq[:, v], ref_q[:, v]))
+    assert _rel(gx, ref_x) < TOL, _rel(gx, ref_x)
+    # the context ends where the forward run ends
+    Q, X, _ = g.download()
+    assert _rel(Q, o.st.Q) < 1e-12 and np.abs(X - o.st.X).max() < 1e-12 * np.ptp(mesh.nodes)
+    assert g.stats()["element_updates"] == o.st.updates
+
+
+def test_lts_adjoint_one_level_is_the_global_step_adjoint():
+    """One level: a macro step is one global step of length N delta, whose
+    reconstruction is the pre-processing one; the two adjoints agree."""
+    mesh, Q0 = _case("explosion")
+    rng = np.random.default_rng(7)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    g = _gpu(mesh, Q0, 1, "rusanov")
+    gq, gx, done = g.adjoint_lts(1, 10.0, qb, xb)
+    assert done == 1
+    T1 = g.stats()["t"]
+    h = _gpu(mesh, Q0, 1, "rusanov")
+    hq, hx, _, _ = h.adjoint_lagrangian_step(T1, qb, xb)
+    assert _rel(gq.cpu().numpy(), hq.cpu().numpy()) < 1e-11
+    assert _rel(gx.cpu().numpy(), hx.cpu().numpy()) < 1e-11
+
+
+def test_lts_adjoint_errors():
+    from paper_1408_3719_amd import AderError
+    mesh, Q0 = _case("vortex")
+    g = _gpu(mesh, Q0, 3, "rusanov")
+    qb = np.zeros(Q0.shape)
+    xb = np.zeros(mesh.nodes.shape)
+    g.step_lts(10.0, 1)
+    with pytest.raises(AderError, match="uploaded state"):
+        g.adjoint_lts(1, 10.0, qb, xb)
+    with pytest.raises(AderError, match="fixed mesh|moving with the fluid"):
+        from paper_1408_3719_amd import Config, Solver
+        Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
+               Config(M=2, levels=3, mesh_velocity="eulerian")).adjoint_lts(1, 10.0, qb, xb)
