@@ -17,8 +17,9 @@ recipe; one adjoint step against one forward step of the adjoint workload.
 
 Other workloads (separate lines): --workload vortex (isentropic vortex, 80k
 triangles, M=2, 3 levels), sod (RP1 shock tube, 2k triangles, M=1, GTS),
-batched (256 independent instances in the same launches) or adjoint
-(gradient through 100 steps with checkpoints, against the run).
+batched (256 independent instances in the same launches), adjoint
+(gradient through 100 global steps with checkpoints, against the run) or
+adjoint_lts (gradient through 100 LTS macro steps, 3 levels, against the run).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload explosion]
                        [--n-elems N] [--M M] [--levels L]
@@ -219,6 +220,133 @@ def bench_adjoint(a):
         "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline_adjoint(a.mesh_velocity, M=M),
     }
     print(json.dumps(line))
+
+
+def bench_adjoint_lts(a):
+    """Gradient through macro steps of the local time stepping on the mesh
+    moving with the fluid: EP1 explosion on a 50k-triangle 8:1 graded disk,
+    M=2, 3 dyadic levels, Rusanov flux, 100 macro steps from t = 0; J = energy
+    carried at the end by the elements that start inside r < 0.3 (their moved
+    areas included), gradient with respect to the initial averages and node
+    positions through ader_adjoint_lts (schedule held fixed). value = time of
+    the gradient call (its own forward run saving every macro-step start, a
+    replay of every macro step saving the state after each cycle, and the
+    reverse sweep) / time of the forward run alone (ader_step_lts over the same
+    macro steps). States resident in HBM."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3719_amd import Config, Solver
+    from workloads import explosion_case
+
+    n = a.n_elems or 50_000
+    M = a.M or 2
+    L = a.levels or 3
+    n_macro = 100
+    mesh, Q0 = explosion_case(n, seed=7)
+    NE = mesh.n_elems
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=L, mesh_velocity="lagrangian"))
+    sync = torch.cuda.synchronize
+    c = mesh.nodes[mesh.tris].mean(axis=1)
+    inner = torch.tensor(np.nonzero(np.hypot(c[:, 0], c[:, 1]) < 0.3)[0], device="cuda")
+    tris = torch.tensor(mesh.tris, dtype=torch.long, device="cuda")[inner]
+
+    def area(x):
+        p = x[tris]
+        return 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                      - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+
+    runs = max(1, min(a.steps, 3))
+    t_f, st = 0.0, None
+    for k in range(1 + runs):
+        s.upload_state(Q0)
+        sync()
+        t0 = time.perf_counter()
+        s.step_lts(1e9, n_macro)
+        sync()
+        if k:
+            t_f += time.perf_counter() - t0
+        st = s.stats()
+    q = s.download_q().clone().requires_grad_(True)
+    x = s.download_x().clone().requires_grad_(True)
+    (area(x) * q[3][inner]).sum().backward()
+    qb, xb = q.grad.detach(), x.grad.detach()
+    t_g, done = 0.0, 0
+    for k in range(1 + runs):
+        s.upload_state(Q0)
+        sync()
+        t0 = time.perf_counter()
+        gq, gx, done = s.adjoint_lts(n_macro, 1e9, qb, xb)
+        sync()
+        if k:
+            t_g += time.perf_counter() - t0
+    assert done == n_macro and bool(torch.isfinite(gq).all()) and bool(torch.isfinite(gx).all())
+    line = {
+        "metric": "adjoint/forward time (gradient of J through 100 LTS macro steps)",
+        "value": t_g / t_f,
+        "unit": "ratio",
+        "n_gpus": 1, "steps": runs, "warmup": 1,
+        "ms_per_step": t_g / runs * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"EP1 explosion, {NE}-triangle 8:1 radially graded disk, M={M}, {L} dyadic levels, "
+                               f"mesh moving with the fluid, {n_macro} macro steps from t = 0, J = energy carried by "
+                               "the elements starting in r < 0.3, gradient w.r.t. initial averages and node "
+                               "positions, schedule held fixed, Rusanov",
+                   "n_elems": NE, "M": M, "levels": L, "n_macro": n_macro, "parallelism": "single GPU"},
+        "forward_s_per_run": t_f / runs,
+        "gradient_s_per_run": t_g / runs,
+        "element_updates_per_run": int(st["element_updates"]),
+        "cycles_per_run": int(st["cycles"]) if "cycles" in st else None,
+        "t_end": float(st["t"]),
+        "note": "ms_per_step is the gradient time of one run; the gradient call includes its own forward run",
+        "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline_adjoint_lts(M=M, levels=L),
+    }
+    print(json.dumps(line))
+
+
+def cpu_baseline_adjoint_lts(n_elems: int = 2000, M: int = 2, levels: int = 3):
+    """The reverse-mode oracle of the local time stepping (torch.autograd
+    through the oracle's LTS macro step, CPU, one thread) on a bounded sample
+    of the workload's recipe: one macro step's vector-Jacobian product against
+    the same macro step forward, in a single-threaded subprocess."""
+    code = f"""
+import json, sys, time
+sys.path.insert(0, {ROOT!r})
+import numpy as np, torch
+torch.set_num_threads(1)
+from oracle.adjoint import LagrangianLTS, lts_schedule
+from oracle.scheme import Config, Solver
+from workloads import explosion_case
+mesh, Q0 = explosion_case({n_elems}, seed=7)
+cfg = Config(M={M}, levels={levels}, mesh_velocity="lagrangian")
+o = Solver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+sched = lts_schedule(o, 1e9, 1)
+lt = LagrangianLTS(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+rng = np.random.default_rng(0)
+qb, xb = rng.standard_normal(Q0.shape), rng.standard_normal(mesh.nodes.shape)
+t = time.perf_counter()
+lt.vjp(Q0, mesh.nodes, sched, qb, xb)
+ta = time.perf_counter() - t
+t = time.perf_counter()
+lt.run(Q0, mesh.nodes, sched)
+tf = time.perf_counter() - t
+print(json.dumps(dict(adjoint_s=ta, forward_s=tf, n_elems=mesh.n_elems, updates=int(o.st.updates))))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    cpu = host_cpu()
+    return dict(value=r["adjoint_s"] / r["forward_s"], unit="ratio", cores=1, kind="oracle",
+                adjoint_element_updates_per_s=r["updates"] / r["adjoint_s"],
+                sample=f"explosion recipe at {r['n_elems']} triangles, M={M}, {levels} levels, mesh moving with "
+                       f"the fluid, one macro step ({r['updates']} element updates): the oracle's reverse mode "
+                       f"{r['adjoint_s']:.2f} s (its forward included) against its forward {r['forward_s']:.2f} s "
+                       "(one host thread)",
+                host_cpu_model=cpu["model"], host_logical_cpus=cpu["logical_cpus"],
+                host_cpus_available=cpu["cpus_available"])
 
 
 def bench_batched(a):
@@ -530,7 +658,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["explosion", "vortex", "sod", "batched", "adjoint"],
+    ap.add_argument("--workload", choices=["explosion", "vortex", "sod", "batched", "adjoint", "adjoint_lts"],
                     default="explosion")
     ap.add_argument("--instances", type=int, default=256, help="batched workload: instances")
     ap.add_argument("--n-elems", type=int, default=None)
@@ -566,6 +694,8 @@ def main():
         return bench_batched(a)
     if a.workload == "adjoint":
         return bench_adjoint(a)
+    if a.workload == "adjoint_lts":
+        return bench_adjoint_lts(a)
 
     import numpy as np  # noqa: F401
     import torch

@@ -337,14 +337,20 @@ int ader_adjoint_lagrangian_step(ader_ctx* ctx, double dt, const double* Q_dev, 
  * as ader_step_lts would leave it.
  *   Qbar_dev, Qbar0_dev: device [4][n_elems] SoA; Xbar_dev, Xbar0_dev:
  *   device [n_nodes][2]; no output may overlap an input.
- * Memory: the library allocates (and frees before returning) one copy of the
- * changing simulation state per macro step and per cycle of one macro step,
- * and scratch of about 1.6 KB per element at M = 2.  Synchronises.
+ * Memory (allocated by the library and freed before returning): for the last
+ * keep_macro_steps macro steps (-1: as many as 60% of the free device memory
+ * holds, counting 2^(L-1) + 3 states each) the forward keeps the state the
+ * reverse sweep reads (ticks, element records, traces, reconstructions, node
+ * positions and ticks; about 1.5 KB per element at M = 2) after the
+ * macro-step start and after every cycle; every earlier macro step keeps its
+ * full state at the start only and is replayed cycle by cycle when the sweep
+ * reaches it (one more forward pass over those steps).  Scratch of about
+ * 1.2 KB per element at M = 2.  Synchronises.
  * ADER_E_ARG for a fixed mesh, free steps, the Osher flux, a batch of
  * instances or n_macro < 1; ADER_E_ORDER before a state upload or after a
  * step; the forward run's own errors as ader_step_lts. */
-int ader_adjoint_lts(ader_ctx* ctx, int32_t n_macro, double t_end, const double* Qbar_dev, const double* Xbar_dev,
-                     double* Qbar0_dev, double* Xbar0_dev, int32_t* n_done);
+int ader_adjoint_lts(ader_ctx* ctx, int32_t n_macro, int32_t keep_macro_steps, double t_end, const double* Qbar_dev,
+                     const double* Xbar_dev, double* Qbar0_dev, double* Xbar0_dev, int32_t* n_done);
 
 /* ---- Measurement: the predictor's derivative contraction -----------------
  * Not a step of the scheme: runs, in one timed launch on the context's

@@ -107,7 +107,7 @@ def load():
     lib.ader_probe_contraction.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P, P, P]
     lib.ader_adjoint_lagrangian_step.argtypes = [P, dbl, P, P, P, P, P, P, P, P, P, ctypes.c_size_t]
     lib.ader_set_schedule_replay.argtypes = [P, P, P, ctypes.c_int64]
-    lib.ader_adjoint_lts.argtypes = [P, i32, dbl, P, P, P, P, ctypes.POINTER(i32)]
+    lib.ader_adjoint_lts.argtypes = [P, i32, i32, dbl, P, P, P, P, ctypes.POINTER(i32)]
     lib.ader_last_error.argtypes = [P]
     lib.ader_last_error.restype = ctypes.c_char_p
     lib.ader_destroy.argtypes = [P]

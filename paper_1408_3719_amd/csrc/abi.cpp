@@ -2,6 +2,7 @@
 // host side of the time stepping loops.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -1210,6 +1211,8 @@ int ader_adjoint_lagrangian_step(ader_ctx* c, double dt, const double* Q_dev, co
   return ADER_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // The arrays of the simulation state that a time step changes, in a fixed
 // order: the saved copies of the LTS adjoint hold them one after another,
@@ -1257,104 +1260,228 @@ int state_copy(ader_ctx* c, char* saved, bool save) {
   return 0;
 }
 
-// The parts of a saved state that the adjoint kernels read.
-aw::LtsView state_view(const ader_ctx* c, const char* saved) {
-  const auto arr = state_arrays(c);
+// The parts of the state that the adjoint kernels read (ticks and steps,
+// element records, traces, reconstructions, node positions and ticks): a
+// view snapshot holds them one after another, each 256-byte aligned.
+std::vector<std::pair<void*, size_t>> view_arrays(const ader_ctx* c) {
+  const auto a = state_arrays(c);
+  return {a[2], a[3], a[4], a[5], a[11], a[13]};
+}
+
+size_t view_bytes(const ader_ctx* c) {
+  size_t n = 0;
+  for (const auto& a : view_arrays(c)) n += al256(a.second);
+  return n;
+}
+
+int view_save(ader_ctx* c, char* dst) {
+  size_t off = 0;
+  for (const auto& a : view_arrays(c)) {
+    HIPCHK(c, hipMemcpyAsync(dst + off, a.first, a.second, hipMemcpyDeviceToDevice, c->stream));
+    off += al256(a.second);
+  }
+  return 0;
+}
+
+aw::LtsView view_at(const ader_ctx* c, const char* saved) {
   std::vector<const char*> at;
   size_t off = 0;
-  for (const auto& a : arr) {
+  for (const auto& a : view_arrays(c)) {
     at.push_back(saved + off);
     off += al256(a.second);
   }
   aw::LtsView v;
-  v.ts = (const aw::TickStep*)at[2];
-  v.rec = (const double*)at[3];
-  v.trace = (const double*)at[4];
-  v.wnod = (const double*)at[5];
-  v.X = (const double*)at[11];
-  v.ntick = (const int*)at[13];
+  v.ts = (const aw::TickStep*)at[0];
+  v.rec = (const double*)at[1];
+  v.trace = (const double*)at[2];
+  v.wnod = (const double*)at[3];
+  v.X = (const double*)at[4];
+  v.ntick = (const int*)at[5];
   return v;
 }
 
-// Forward over up to n_macro macro steps with the state saved at every
-// macro-step start, then the reverse sweep: per macro step (last first) a
-// replay from its saved start keeping the state after every cycle, the
-// cycles in reverse, the start's predictors in reverse; finally the
-// pre-processing reconstruction. The context ends at the forward's end state.
-int adjoint_lts_run(ader_ctx* c, int n_macro, double t_end, const double* Qbar, const double* Xbar, double* Qbar0,
-                    double* Xbar0, int* n_done, std::vector<char*>& bufs) {
+// Device memory handed out in order from large chunks (freed together).
+struct Pool {
+  std::vector<char*> chunks;
+  size_t chunk = 0, used = 0;
+  int take(ader_ctx* c, size_t bytes, char** out) {
+    bytes = al256(bytes);
+    if (chunks.empty() || used + bytes > chunk) {
+      const size_t n = bytes > chunk ? bytes : chunk;
+      char* p = nullptr;
+      HIPCHK(c, hipMalloc((void**)&p, n));
+      chunks.push_back(p);
+      chunk = n > chunk ? n : chunk;
+      used = 0;
+    }
+    *out = chunks.back() + used;
+    used += bytes;
+    return 0;
+  }
+  void release() {
+    for (char* p : chunks) (void)hipFree(p);
+    chunks.clear();
+  }
+};
+
+// One macro step cycle by cycle: after(k) runs after the macro-step start
+// (k = 0) and after each cycle k (the cycle count read back each time);
+// *ran = 0 when every instance had already reached t_end. Leaves the context
+// as run_macro does.
+template <class F>
+int macro_by_cycles(ader_ctx* c, double t_end, int nominal, F after, int* ran, double* delta) {
+  const aw::Dev& d = c->dev;
+  aw::Scal s;
+  int r;
+  *ran = 0;
+  c->synced = false;
+  set_free(c, false);
+  LCHK(c, aw::launch_set_target(d, t_end, c->stream));
+  LCHK(c, aw::launch_open(d, c->stream));
+  if ((r = read_scal(c, s))) return r;
+  if ((r = check_err(c, s))) return r;
+  if (s.n_open == 0) {
+    c->synced = true;
+    return 0;
+  }
+  if ((r = issue_macro_begin(c, nominal, c->stream))) return r;
+  aw::Inst in0;
+  HIPCHK(c, hipMemcpyAsync(&in0, d.inst, sizeof(in0), hipMemcpyDeviceToHost, c->stream));
+  if ((r = after(0))) return r;
+  int k = 0;
+  for (;;) {
+    if ((r = issue_cycles(c, 1, c->stream))) return r;
+    LCHK(c, aw::launch_status(d, c->stream));
+    if ((r = after(k + 1))) return r;
+    if ((r = read_scal(c, s))) return r;
+    if ((r = check_err(c, s))) return r;
+    ++k;
+    if (s.n_unfinished == 0) break;
+    if (k > (1 << 20)) return fail(c, ADER_E_DEADLOCK, "no element satisfies the update criterion");
+  }
+  LCHK(c, aw::launch_macro_end(d, 0, c->stream));
+  LCHK(c, aw::launch_open(d, c->stream));
+  if ((r = read_scal(c, s))) return r;
+  c->cycles += k;
+  if (k > nominal) {
+    c->extra_cycles += k - nominal;
+    c->long_macro_steps++;
+  }
+  c->macro_steps++;
+  c->synced = true;
+  *delta = in0.delta;
+  *ran = 1;
+  return 0;
+}
+
+// Forward over up to n_macro macro steps, then the reverse sweep. The last
+// macro steps (as many as a budget of 60% of the free device memory allows)
+// run cycle by cycle with the state after the macro-step start and after
+// every cycle kept; each earlier one runs as in ader_step_lts with the full
+// state saved at its start, and is replayed cycle by cycle when the sweep
+// reaches it. Per macro step (last first): the cycles in reverse, then the
+// start's predictors; finally the pre-processing reconstruction. The context
+// ends at the forward's end state.
+int adjoint_lts_run(ader_ctx* c, int n_macro, int keep_req, double t_end, const double* Qbar, const double* Xbar,
+                    double* Qbar0, double* Xbar0, int* n_done, Pool& pool, std::vector<char*>& bufs) {
   const aw::Dev& d = c->dev;
   const int M = c->cfg.M, L = c->cfg.lts_levels, nominal = 1 << (L - 1);
-  const size_t sb = state_bytes(c);
+  const size_t sb = state_bytes(c), vb = view_bytes(c);
   auto take = [&](char** out, size_t bytes) -> int {
     HIPCHK(c, hipMalloc((void**)out, bytes));
     bufs.push_back(*out);
     return 0;
   };
   int r;
-  std::vector<char*> start;   // states at the macro-step starts, then the end state
-  char* b = nullptr;
-  if ((r = take(&b, sb))) return r;
-  start.push_back(b);
-  if ((r = state_copy(c, b, true))) return r;
-  int done = 0;
-  for (int m = 0; m < n_macro; ++m) {
-    const int64_t before = c->macro_steps;
-    if ((r = run_macro(c, t_end, 1, L))) return r;
-    if (c->macro_steps == before) break;   // t_end reached
-    if ((r = take(&b, sb))) return r;
-    start.push_back(b);
-    if ((r = state_copy(c, b, true))) return r;
-    ++done;
-  }
   char* wb = nullptr;
   const size_t wbytes = aw::lts_work_bytes(M, d.NE, d.NV, d.NF, c->prm.npic);
   if ((r = take(&wb, wbytes))) return r;
   aw::LtsWork w;
   aw::lts_carve(M, d.NE, d.NV, d.NF, c->prm.npic, wb, w);
+  char* v0 = nullptr;   // the uploaded state
+  if ((r = take(&v0, vb))) return r;
+  if ((r = view_save(c, v0))) return r;
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+  const size_t per_macro = size_t(nominal + 3) * vb;
+  const long fits = long(std::min<size_t>(size_t(n_macro), size_t(0.6 * double(free_b)) / per_macro));
+  const long kept = keep_req < 0 ? fits : std::min<long>(keep_req, n_macro);
+  pool.chunk = std::max<size_t>(vb, size_t(64) * vb);
+  std::vector<std::vector<char*>> views(n_macro);   // kept macro steps: start, then each cycle
+  std::vector<char*> start(n_macro, nullptr);       // replayed macro steps: full state at the start
+  std::vector<double> delta(n_macro, 0.0);
+  int done = 0;
+  for (int m = 0; m < n_macro; ++m) {
+    int ran = 0;
+    if (m >= n_macro - kept) {
+      auto keep = [&](int k) -> int {
+        char* p = nullptr;
+        int e = pool.take(c, vb, &p);
+        if (e) return e;
+        views[m].push_back(p);
+        (void)k;
+        return view_save(c, p);
+      };
+      if ((r = macro_by_cycles(c, t_end, nominal, keep, &ran, &delta[m]))) return r;
+    } else {
+      if ((r = take(&start[m], sb))) return r;
+      if ((r = state_copy(c, start[m], true))) return r;
+      const int64_t before = c->macro_steps;
+      if ((r = run_macro(c, t_end, 1, L))) return r;
+      ran = c->macro_steps != before;
+    }
+    if (!ran) break;
+    ++done;
+  }
+  char* end_state = nullptr;
+  if (done > 0 && start[0]) {   // a replay will change the state: keep the end state
+    if ((r = take(&end_state, sb))) return r;
+    if ((r = state_copy(c, end_state, true))) return r;
+  }
   LCHK(c, aw::launch_lts_init(d, w, Qbar, Xbar, c->stream));
-  std::vector<char*> cyc;   // states after the macro-step start and after each cycle
+  std::vector<char*> replay;   // views of a replayed macro step (buffers reused)
+  std::vector<char*> cur;
   for (int m = done - 1; m >= 0; --m) {
-    if ((r = state_copy(c, start[m], false))) return r;
-    LCHK(c, aw::launch_set_target(d, t_end, c->stream));
-    LCHK(c, aw::launch_open(d, c->stream));
-    if ((r = issue_macro_begin(c, nominal, c->stream))) return r;
-    if (cyc.empty()) {
-      if ((r = take(&b, sb))) return r;
-      cyc.push_back(b);
+    std::vector<char*>* vs = &views[m];
+    if (start[m]) {
+      if ((r = state_copy(c, start[m], false))) return r;
+      size_t n = 0;
+      auto keep = [&](int k) -> int {
+        if (replay.size() < n + 1) {
+          char* p = nullptr;
+          int e = take(&p, vb);
+          if (e) return e;
+          replay.push_back(p);
+        }
+        (void)k;
+        return view_save(c, replay[n++]);
+      };
+      int ran = 0;
+      const int64_t steps = c->macro_steps, cycles = c->cycles, extra = c->extra_cycles,
+                    longm = c->long_macro_steps;
+      if ((r = macro_by_cycles(c, t_end, nominal, keep, &ran, &delta[m]))) return r;
+      c->macro_steps = steps;
+      c->cycles = cycles;
+      c->extra_cycles = extra;
+      c->long_macro_steps = longm;
+      if (!ran) return fail(c, ADER_E_STATE, "LTS adjoint: a replayed macro step did not run");
+      cur.assign(replay.begin(), replay.begin() + n);
+      vs = &cur;
     }
-    if ((r = state_copy(c, cyc[0], true))) return r;
-    aw::Inst in0;
-    HIPCHK(c, hipMemcpyAsync(&in0, d.inst, sizeof(in0), hipMemcpyDeviceToHost, c->stream));
-    aw::Scal s;
-    int nc = 0;
-    for (;;) {
-      if ((r = issue_cycles(c, 1, c->stream))) return r;
-      LCHK(c, aw::launch_status(d, c->stream));
-      if (int(cyc.size()) < nc + 2) {
-        if ((r = take(&b, sb))) return r;
-        cyc.push_back(b);
-      }
-      if ((r = state_copy(c, cyc[nc + 1], true))) return r;
-      if ((r = read_scal(c, s))) return r;
-      if ((r = check_err(c, s))) return r;
-      ++nc;
-      if (s.n_unfinished == 0) break;
-      if (nc > (1 << 20)) return fail(c, ADER_E_DEADLOCK, "LTS adjoint: the macro step does not end");
-    }
-    w.delta = in0.delta;
+    const int nc = int(vs->size()) - 1;
+    w.delta = delta[m];
     for (int k = nc - 1; k >= 0; --k) {
-      w.s0 = state_view(c, cyc[k]);
-      w.s1 = state_view(c, cyc[k + 1]);
+      w.s0 = view_at(c, (*vs)[k]);
+      w.s1 = view_at(c, (*vs)[k + 1]);
       LCHK(c, aw::launch_lts_cycle_rev(d, c->prm, M, w, c->stream));
     }
-    w.s1 = state_view(c, cyc[0]);
+    w.s1 = view_at(c, (*vs)[0]);
     LCHK(c, aw::launch_lts_macro_begin_rev(d, c->prm, M, w, c->stream));
   }
-  w.s1 = state_view(c, start[0]);
+  w.s1 = view_at(c, v0);
   LCHK(c, aw::launch_lts_initial_rev(d, c->prm, M, w, c->stream));
   LCHK(c, aw::launch_lts_out(d, w, Qbar0, Xbar0, c->stream));
-  if ((r = state_copy(c, start[done], false))) return r;
+  if (end_state && (r = state_copy(c, end_state, false))) return r;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->synced = true;
   *n_done = done;
@@ -1362,8 +1489,10 @@ int adjoint_lts_run(ader_ctx* c, int n_macro, double t_end, const double* Qbar, 
 }
 }  // namespace
 
-int ader_adjoint_lts(ader_ctx* c, int32_t n_macro, double t_end, const double* Qbar_dev, const double* Xbar_dev,
-                     double* Qbar0_dev, double* Xbar0_dev, int32_t* n_done) {
+extern "C" {
+
+int ader_adjoint_lts(ader_ctx* c, int32_t n_macro, int32_t keep_macro_steps, double t_end, const double* Qbar_dev,
+                     const double* Xbar_dev, double* Qbar0_dev, double* Xbar0_dev, int32_t* n_done) {
   if (!c || !Qbar_dev || !Xbar_dev || !Qbar0_dev || !Xbar0_dev || !n_done || n_macro < 1) return ADER_E_ARG;
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (c->cycles != 0 || c->macro_steps != 0)
@@ -1375,10 +1504,13 @@ int ader_adjoint_lts(ader_ctx* c, int32_t n_macro, double t_end, const double* Q
     return fail(c, ADER_E_ARG, "the LTS adjoint covers the Rusanov and HLL fluxes");
   if (!std::isfinite(t_end)) return fail(c, ADER_E_ARG, "t_end is not finite");
   std::vector<char*> bufs;
+  Pool pool;
   int done = 0;
-  const int r = adjoint_lts_run(c, n_macro, t_end, Qbar_dev, Xbar_dev, Qbar0_dev, Xbar0_dev, &done, bufs);
+  const int r =
+      adjoint_lts_run(c, n_macro, keep_macro_steps, t_end, Qbar_dev, Xbar_dev, Qbar0_dev, Xbar0_dev, &done, pool, bufs);
   (void)hipStreamSynchronize(c->stream);
   for (char* p : bufs) (void)hipFree(p);
+  pool.release();
   if (r) return r;
   *n_done = done;
   return ADER_OK;

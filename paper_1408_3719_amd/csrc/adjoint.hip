@@ -364,6 +364,44 @@ __global__ void __launch_bounds__(TPB) k_adj_gather(Dev d, AdjWork w) {
   }
 }
 
+// Element j of the saved state s placed at tick nt (eqs. eqn.virtGeom and
+// eqn.virtCellaverage): its stored vertices and average when it is at that
+// tick, else its predictor's vertex trajectories and cell means at the
+// rescaled time (nt - tick) / step.
+template <int M>
+__device__ inline void lts_place(const Tables* __restrict__ tb, const LtsView& s, int j, int nt, double delta,
+                                 double X[6], double Q[4]) {
+  constexpr int T = M + 1, RS = AZ<M>::RS, AVG = rec_off_avg(), VV = rec_off_vv(M);
+  const TickStep tj = s.ts[j];
+  const double* rj = s.rec + size_t(j) * RS;
+  if (tj.tick == nt) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = rj[XE + k];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Q[v] = rj[QO + v];
+    return;
+  }
+  const double tau = double(nt - tj.tick) / double(tj.step);
+  const double dtj = double(tj.step) * delta;
+  double L[T], l[T];
+  lag::tanti<M>(*tb, tau, L);
+  lag::tbasis<M>(*tb, tau, l);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < T; ++q) sum += L[q] * rj[VV + ((k / 2) * T + q) * 2 + (k % 2)];
+    X[k] = rj[XE + k] + dtj * sum;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < T; ++q) sum += l[q] * rj[AVG + q * 4 + v];
+    Q[v] = sum;
+  }
+}
+
 // Reconstruction (REV = false: write the nodal values) or its adjoint (REV =
 // true: read their adjoint, add to qbar). 8 lanes per element. GEO: the rows
 // depend on vertices that are differentiated too (a moving mesh): with w = the
@@ -372,8 +410,8 @@ __global__ void __launch_bounds__(TPB) k_adj_gather(Dev d, AdjWork w) {
 // back to the vertices of the stencil element (its slot) and of element i
 // (row 0 of the lane).
 // VIRT (local time stepping): the elements of lw.act_list, their own data
-// from the state lw.s1, the stencil rows from lw.vrows (the stencil elements
-// placed at the element's tick: real or projected).
+// from the state lw.s1, the stencil elements placed at the element's tick
+// (real or projected, lts_place).
 template <int M, bool REV, bool GEO = false, bool VIRT = false>
 __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restrict__ tb, Params P,
                                                    AdjWork w, LtsWork lw) {
@@ -393,13 +431,17 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
     for (int c = 0; c < 6; ++c) Xi[c] = ri[c];
 #pragma unroll
     for (int v = 0; v < 4; ++v) Qi[v] = VIRT ? lw.s1.rec[size_t(i) * S::RS + QO + v] : w.q[size_t(v) * NE + i];
-    // stencil row c of this lane: the element's vertices and average
-    auto row_x = [&](int c) -> const double* {
-      return VIRT ? lw.vrows + ((size_t(i) * ne + c) * 8 + sl) * 10 : gbase + size_t(d.sten[size_t(sl * ne + c) * NE + i]) * gs;
-    };
-    auto row_q = [&](int c, int v) -> double {
-      return VIRT ? lw.vrows[((size_t(i) * ne + c) * 8 + sl) * 10 + 6 + v]
-                  : w.q[size_t(v) * NE + d.sten[size_t(sl * ne + c) * NE + i]];
+    const int nt = VIRT ? lw.s1.ts[i].tick : 0;
+    // stencil row c of this lane: the element's vertices (xv when placed) and average
+    auto row = [&](int c, double xv[6], double qv[4]) -> const double* {
+      const int j = d.sten[size_t(sl * ne + c) * NE + i];
+      if (VIRT) {
+        lts_place<M>(tb, lw.s1, j, nt, lw.delta, xv, qv);
+        return xv;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qv[v] = w.q[size_t(v) * NE + j];
+      return gbase + size_t(j) * gs;
     };
     const double e1x = Xi[2] - Xi[0], e1y = Xi[3] - Xi[1];
     const double e2x = Xi[4] - Xi[0], e2y = Xi[5] - Xi[1];
@@ -438,11 +480,12 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         for (int v = 0; v < 4; ++v) z[a][v] = 0.0;
 #pragma unroll 1
       for (int c = 1; c < ne; ++c) {
-        const double* rj = row_x(c);
+        double xv[6], qv[4];
+        const double* rj = row(c, xv, qv);
         double a[nu], b[4];
         ls_row<M>(rj, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) b[v] = row_q(c, v) - Qi[v];
+        for (int v = 0; v < 4; ++v) b[v] = qv[v] - Qi[v];
 #pragma unroll
         for (int k = 0; k < nu; ++k) {
           const double rkk = R[k][k], ak = a[k];
@@ -593,7 +636,8 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
     double Xib[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int c = 1; c < ne; ++c) {
-      const double* Xj = row_x(c);
+      double xv[6], qv[4];
+      const double* Xj = row(c, xv, qv);
       double a[nu], bb[4];
       ls_row<M>(Xj, Xi, e1x, e1y, e2x, e2y, idet, a);
 #pragma unroll
@@ -611,7 +655,7 @@ __global__ void __launch_bounds__(TPB) k_adj_recon(Dev d, const Tables* __restri
         for (int l = 0; l < nu; ++l) ab[l] = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          double r = row_q(c, v) - Qi[v];
+          double r = qv[v] - Qi[v];
 #pragma unroll
           for (int l = 0; l < nu; ++l) r -= a[l] * ws[l][v];
 #pragma unroll
@@ -1952,59 +1996,6 @@ __global__ void __launch_bounds__(TPB) k_lts_marks(Dev d, LtsWork lw, int all) {
     lw.nflag[k] = all ? 0 : int(lw.s1.ntick[k] != lw.s0.ntick[k]);
 }
 
-// Rows of every updated element's stencils: the stencil element at the
-// element's new tick (eqs. eqn.virtGeom and eqn.virtCellaverage), its stored
-// vertices and average when it is at that tick, else its predictor's vertex
-// trajectories and cell means at the rescaled time. 8 lanes per element.
-template <int M>
-__global__ void __launch_bounds__(TPB) k_lts_vrows(Dev d, const Tables* __restrict__ tb, LtsWork lw) {
-  using S = AZ<M>;
-  constexpr int ne = S::ne, T = M + 1, AVG = rec_off_avg(), VV = rec_off_vv(M);
-  const int NE = d.NE;
-  const int sl = threadIdx.x & 7;
-  const int ngroups = (gridDim.x * blockDim.x) >> 3;
-  const int n_el = lw.counts[0];
-  for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; idx < n_el; idx += ngroups) {
-    const int i = lw.act_list[idx];
-    if (sl >= NSTEN) continue;
-    const int* sidx = d.sten + size_t(sl * ne) * NE + i;
-    if (sidx[0] < 0) continue;
-    const int nt = lw.s1.ts[i].tick;
-    for (int c = 1; c < ne; ++c) {
-      const int j = sidx[c * NE];
-      const TickStep tj = lw.s1.ts[j];
-      const double* rj = lw.s1.rec + size_t(j) * S::RS;
-      double* o = lw.vrows + ((size_t(i) * ne + c) * 8 + sl) * 10;
-      if (tj.tick == nt) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) o[k] = rj[XE + k];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) o[6 + v] = rj[QO + v];
-        continue;
-      }
-      const double tau = double(nt - tj.tick) / double(tj.step);
-      const double dtj = double(tj.step) * lw.delta;
-      double L[T], l[T];
-      lag::tanti<M>(*tb, tau, L);
-      lag::tbasis<M>(*tb, tau, l);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < T; ++q) s += L[q] * rj[VV + ((k / 2) * T + q) * 2 + (k % 2)];
-        o[k] = rj[XE + k] + dtj * s;
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < T; ++q) s += l[q] * rj[AVG + q * 4 + v];
-        o[6 + v] = s;
-      }
-    }
-  }
-}
-
 // Per element j, 8 lanes: the own terms of its reconstruction (updated j) and
 // the rows of updated elements' stencils that name j, through the placement
 // in reverse: into j's average and vertices (same tick) or into its
@@ -2370,7 +2361,6 @@ int lts_pred_rev(const Dev& d, const Params& p, const LtsWork& w, void* s) {
 
 template <int M>
 int lts_recon_rev(const Dev& d, const Params& p, const LtsWork& w, void* s) {
-  AD_LAUNCH(k_lts_vrows<M>, 8L * d.NE, s, d, d.tab, w);
   AD_LAUNCH((k_adj_recon<M, false, true, true>), 8L * d.NE, s, d, d.tab, p, w.g.a, w);
   AD_LAUNCH((k_adj_recon<M, true, true, true>), 8L * d.NE, s, d, d.tab, p, w.g.a, w);
   AD_LAUNCH(k_lts_gather<M>, 8L * d.NE, s, d, d.tab, w);
@@ -2522,7 +2512,7 @@ LagPlan lts_plan(int M, int NE, int NV, int NF, int npic) {
   p.add(size_t(NE) * 6 * T * D);                   // 14 vvb
   p.add(size_t(NV) * 2 * D);                       // 15 xb
   p.add(size_t(NF) * T * 4 * D);                   // 16 abar_e
-  p.add(ne * NE * 80 * D);                         // 17 vrows
+  p.add(8);                                        // 17 (unused)
   p.add(size_t(NE) * I);                           // 18 eflag
   p.add(size_t(NV) * I);                           // 19 nflag
   p.add(size_t(NE) * I);                           // 20 act_list
@@ -2556,7 +2546,6 @@ void lts_carve(int M, int NE, int NV, int NF, int npic, char* base, LtsWork& w) 
   w.vvb = at(14);
   w.xb = at(15);
   w.abar_e = at(16);
-  w.vrows = at(17);
   w.eflag = ai(18);
   w.nflag = ai(19);
   w.act_list = ai(20);

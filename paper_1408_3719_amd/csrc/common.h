@@ -241,7 +241,6 @@ struct LtsWork {
   double* vvb;        // [NE][3][M+1][2]
   double* xb;         // [NV][2]
   double* abar_e;     // [NF][M+1][4] means' adjoint from a transmissive patch
-  double* vrows;      // [NE][ne][8][10] stencil rows placed at the element's tick (vertices, average)
   int* eflag;         // [NE] bit 0: updated in the cycle; bit 1: takes a new predictor
   int* nflag;         // [NV] moved in the cycle
   int* act_list;      // [NE]

@@ -241,19 +241,20 @@ class Solver(_Base):
             ctypes.c_void_p(aligned), n))
         return qbar, xbar, q_next, x_next
 
-    def adjoint_lts(self, n_macro: int, t_end: float, qbar, xbar):
+    def adjoint_lts(self, n_macro: int, t_end: float, qbar, xbar, keep: int = -1):
         """Gradient through up to n_macro LTS macro steps towards t_end from
         the uploaded state, the schedule held fixed (ader_adjoint_lts): qbar
         (NE, 4) or device [4][NE] and xbar (NV, 2) the adjoints of the final
-        averages and positions.  Returns device tensors (qbar0 [4][NE],
-        xbar0 (NV, 2)) and the number of macro steps taken; the context ends
-        at the final state."""
+        averages and positions; keep: macro steps whose cycle states the
+        forward keeps (-1: as memory allows; the others are replayed).
+        Returns device tensors (qbar0 [4][NE], xbar0 (NV, 2)) and the number
+        of macro steps taken; the context ends at the final state."""
         qb = self._dev4(qbar, "qbar")
         xb = self._devxy(xbar, "xbar")
         q0, x0 = self.torch.empty_like(qb), self.torch.empty_like(xb)
         done = ctypes.c_int32()
         _check(self.lib, self.ctx, self.lib.ader_adjoint_lts(
-            self.ctx, int(n_macro), float(t_end), ctypes.c_void_p(qb.data_ptr()), ctypes.c_void_p(xb.data_ptr()),
+            self.ctx, int(n_macro), int(keep), float(t_end), ctypes.c_void_p(qb.data_ptr()), ctypes.c_void_p(xb.data_ptr()),
             ctypes.c_void_p(q0.data_ptr()), ctypes.c_void_p(x0.data_ptr()), ctypes.byref(done)))
         return q0, x0, done.value
 

@@ -4,8 +4,9 @@ averages and node positions of the uploaded state, element by element and node
 by node against the reverse-mode oracle (torch.autograd through the oracle's
 LTS macro steps replaying the same tick lengths and steps) on small meshes with
 three levels (vortex, explosion; Rusanov and HLL); the context's end state
-against the oracle's forward run; with one level against the adjoint of the
-global Lagrangian step (ader_adjoint_lagrangian_step)."""
+against the oracle's forward run; macro steps with their cycle states kept and
+macro steps replayed from their start against each other; with one level
+against the adjoint of the global Lagrangian step (ader_adjoint_lagrangian_step)."""
 import os
 import sys
 
@@ -58,6 +59,25 @@ def test_lts_adjoint_matches_reverse_mode_oracle(name, flux):
     Q, X, _ = g.download()
     assert _rel(Q, o.st.Q) < 1e-12 and np.abs(X - o.st.X).max() < 1e-12 * np.ptp(mesh.nodes)
     assert g.stats()["element_updates"] == o.st.updates
+
+
+def test_lts_adjoint_replayed_and_kept_macro_steps_agree():
+    """Macro steps whose cycle states are kept and macro steps replayed from
+    their saved start give the same gradient (and the same end state)."""
+    mesh, Q0 = _case("explosion")
+    rng = np.random.default_rng(8)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    out = []
+    for keep in (-1, 0, 1):
+        g = _gpu(mesh, Q0, 3, "rusanov")
+        gq, gx, done = g.adjoint_lts(3, 10.0, qb, xb, keep=keep)
+        assert done == 3
+        Q, X, _ = g.download()
+        out.append((gq.cpu().numpy(), gx.cpu().numpy(), Q, X))
+    for o in out[1:]:
+        assert _rel(o[0], out[0][0]) < 1e-13 and _rel(o[1], out[0][1]) < 1e-13
+        assert np.array_equal(o[2], out[0][2]) and np.array_equal(o[3], out[0][3])
 
 
 def test_lts_adjoint_one_level_is_the_global_step_adjoint():
