@@ -1348,14 +1348,19 @@ int macro_by_cycles(ader_ctx* c, double t_end, int nominal, F after, int* ran, d
   aw::Inst in0;
   HIPCHK(c, hipMemcpyAsync(&in0, d.inst, sizeof(in0), hipMemcpyDeviceToHost, c->stream));
   if ((r = after(0))) return r;
+  // the first 2^(L-1) cycles without a host check (as run_macro), then one
+  // cycle per check
   int k = 0;
   for (;;) {
-    if ((r = issue_cycles(c, 1, c->stream))) return r;
-    LCHK(c, aw::launch_status(d, c->stream));
-    if ((r = after(k + 1))) return r;
+    const int batch = k == 0 ? nominal : 1;
+    for (int b = 0; b < batch; ++b) {
+      if ((r = issue_cycles(c, 1, c->stream))) return r;
+      if (b == batch - 1) LCHK(c, aw::launch_status(d, c->stream));
+      if ((r = after(k + 1))) return r;
+      ++k;
+    }
     if ((r = read_scal(c, s))) return r;
     if ((r = check_err(c, s))) return r;
-    ++k;
     if (s.n_unfinished == 0) break;
     if (k > (1 << 20)) return fail(c, ADER_E_DEADLOCK, "no element satisfies the update criterion");
   }

@@ -1975,7 +1975,7 @@ int adjoint_lagrangian(const Dev& d, const Params& p, LagWork w, double dt, bool
 // Its reverse reads the saved states before (s0) and after (s1) the cycle.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(TPB) k_lts_clear_counts(LtsWork lw) {
-  if (blockIdx.x == 0 && threadIdx.x < 2) lw.counts[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 3) lw.counts[threadIdx.x] = 0;
 }
 
 // Flags and lists of the cycle from the ticks on both sides of it; all = 1:
@@ -1994,6 +1994,12 @@ __global__ void __launch_bounds__(TPB) k_lts_marks(Dev d, LtsWork lw, int all) {
   }
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x)
     lw.nflag[k] = all ? 0 : int(lw.s1.ntick[k] != lw.s0.ntick[k]);
+}
+
+// The swept edges (a moved end) listed.
+__global__ void __launch_bounds__(TPB) k_lts_edges(Dev d, LtsWork lw) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < d.NF; e += gridDim.x * blockDim.x)
+    if (lw.nflag[d.e_a[e]] || lw.nflag[d.e_b[e]]) lw.edge_list[atomicAdd(&lw.counts[2], 1)] = e;
 }
 
 // Per element j, 8 lanes: the own terms of its reconstruction (updated j) and
@@ -2113,11 +2119,11 @@ template <int M>
 __global__ void __launch_bounds__(TPB) k_lts_patch(Dev d, const Tables* __restrict__ tb, Params P, LtsWork lw) {
   using S = AZ<M>;
   constexpr int T = S::T, nG = S::nG, TS = S::TS, NT = nG * T * 4;
-  const int NV = d.NV, NF = d.NF;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
+  const int NV = d.NV, n_e = lw.counts[2];
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_e; idx += gridDim.x * blockDim.x) {
+    const int e = lw.edge_list[idx];
     const int a = d.e_a[e], b = d.e_b[e];
     const bool ma = lw.nflag[a] != 0, mvb = lw.nflag[b] != 0;
-    if (!ma && !mvb) continue;
     const double* X0 = lw.s0.X;
     const double* X1 = lw.s1.X;
     const double xa[2] = {X0[a], X0[NV + a]}, xb[2] = {X0[b], X0[NV + b]};
@@ -2371,6 +2377,7 @@ template <int M>
 int lts_cycle_rev(const Dev& d, const Params& p, const LtsWork& w, void* s) {
   AD_LAUNCH(k_lts_clear_counts, 1, s, w);
   AD_LAUNCH(k_lts_marks, d.NE > d.NV ? d.NE : d.NV, s, d, w, 0);
+  AD_LAUNCH(k_lts_edges, d.NF, s, d, w);
   int r;
   if ((r = lts_pred_rev<M>(d, p, w, s))) return r;
   if ((r = lts_recon_rev<M>(d, p, w, s))) return r;
@@ -2517,7 +2524,8 @@ LagPlan lts_plan(int M, int NE, int NV, int NF, int npic) {
   p.add(size_t(NV) * I);                           // 19 nflag
   p.add(size_t(NE) * I);                           // 20 act_list
   p.add(size_t(NE) * I);                           // 21 going_list
-  p.add(2 * I);                                    // 22 counts
+  p.add(3 * I);                                    // 22 counts
+  p.add(size_t(NF) * I);                           // 23 edge_list
   return p;
 }
 }  // namespace
@@ -2551,6 +2559,7 @@ void lts_carve(int M, int NE, int NV, int NF, int npic, char* base, LtsWork& w) 
   w.act_list = ai(20);
   w.going_list = ai(21);
   w.counts = ai(22);
+  w.edge_list = ai(23);
 }
 
 #define LTS_DISPATCH(fn, ...)                          \

@@ -245,7 +245,8 @@ struct LtsWork {
   int* nflag;         // [NV] moved in the cycle
   int* act_list;      // [NE]
   int* going_list;    // [NE]
-  int* counts;        // [2] lengths of the two lists
+  int* edge_list;     // [NF] edges swept in the cycle
+  int* counts;        // [3] lengths of the three lists
   double delta;       // tick length of the macro step
   LtsView s0, s1;
 };
