@@ -623,6 +623,44 @@ def lagrangian_adjoint_step_ratio(n_elems: int = 50_000, M: int = 2, reps: int =
             "workload": f"one global step on the {mesh.n_elems}-triangle explosion, Lagrangian mesh, M={M}"}
 
 
+def lts_gradient_ratio(n_elems: int = 50_000, M: int = 2, levels: int = 3, n_macro: int = 20, reps: int = 2):
+    """The gradient through n_macro LTS macro steps on the mesh moving with
+    the fluid (ader_adjoint_lts, its own forward included) against the forward
+    run over the same macro steps (ader_step_lts), explosion recipe from t = 0."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3719_amd import Config, Solver
+    from workloads import explosion_case
+    mesh, Q0 = explosion_case(n_elems, seed=7)
+    s = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=M, levels=levels, mesh_velocity="lagrangian"))
+    rng = np.random.default_rng(0)
+    qb = torch.tensor(rng.standard_normal((4, mesh.n_elems)), device="cuda")
+    xb = torch.tensor(rng.standard_normal((mesh.n_nodes, 2)), device="cuda")
+    sync = torch.cuda.synchronize
+    t_f = t_g = 0.0
+    for k in range(reps + 1):
+        s.upload_state(Q0)
+        sync()
+        t0 = time.perf_counter()
+        s.step_lts(1e9, n_macro)
+        sync()
+        t1 = time.perf_counter()
+        s.upload_state(Q0)
+        sync()
+        t2 = time.perf_counter()
+        _, _, done = s.adjoint_lts(n_macro, 1e9, qb, xb)
+        sync()
+        t3 = time.perf_counter()
+        assert done == n_macro
+        if k:
+            t_f += t1 - t0
+            t_g += t3 - t2
+    return {"value": t_g / t_f, "gradient_ms": t_g / reps * 1e3, "forward_ms": t_f / reps * 1e3,
+            "workload": f"{n_macro} LTS macro steps ({levels} levels) from t = 0 on the {mesh.n_elems}-triangle "
+                        f"explosion, Lagrangian mesh, M={M}; the gradient call includes its own forward"}
+
+
 def mfma_probe(n_elems: int = 400_000, iters: int = 64, reps: int = 5):
     """The predictor's derivative contraction (D_xi, D_eta of the M=2 nodal
     basis on ten fields at six nodes, fed back `iters` times) on the vector
@@ -866,12 +904,14 @@ def main():
         sync()
     del s
 
-    adj = adj_lag = None
+    adj = adj_lag = adj_lts = None
     if a.adjoint:
         adj = adjoint_step_ratio()
         note(f"adjoint/forward per step {adj['value']:.3f}")
         adj_lag = lagrangian_adjoint_step_ratio()
         note(f"moving-mesh adjoint/forward per step {adj_lag['value']:.3f}")
+        adj_lts = lts_gradient_ratio()
+        note(f"LTS gradient/forward over {adj_lts['workload'].split()[0]} macro steps {adj_lts['value']:.3f}")
 
     probe = mfma_probe() if a.mfma_probe else None
     if probe:
@@ -911,6 +951,7 @@ def main():
         "free_steps": free,
         "adjoint_forward": adj,
         "adjoint_lagrangian_forward": adj_lag,
+        "adjoint_lts_forward": adj_lts,
         "autotune": tune,
         "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},

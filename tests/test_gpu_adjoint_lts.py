@@ -3,7 +3,8 @@ with the fluid, through the C ABI (ader_adjoint_lts), the schedule held fixed:
 averages and node positions of the uploaded state, element by element and node
 by node against the reverse-mode oracle (torch.autograd through the oracle's
 LTS macro steps replaying the same tick lengths and steps) on small meshes with
-three levels (vortex, explosion; Rusanov and HLL); the context's end state
+three levels (vortex M = 1, 2, 3, explosion, shock tube with slip walls; Rusanov, and HLL on the
+explosion); the context's end state
 against the oracle's forward run; macro steps with their cycle states kept and
 macro steps replayed from their start against each other; with one level
 against the adjoint of the global Lagrangian step (ader_adjoint_lagrangian_step)."""
@@ -29,17 +30,19 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-def _gpu(mesh, Q0, levels, flux):
+def _gpu(mesh, Q0, levels, flux, M=2):
     from paper_1408_3719_amd import Config, Solver
     return Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
-                  Config(M=2, levels=levels, mesh_velocity="lagrangian", flux=flux))
+                  Config(M=M, levels=levels, mesh_velocity="lagrangian", flux=flux))
 
 
-@pytest.mark.parametrize("name,flux", [("vortex", "rusanov"), ("explosion", "rusanov"), ("explosion", "hll")])
-def test_lts_adjoint_matches_reverse_mode_oracle(name, flux):
+@pytest.mark.parametrize("name,M,flux", [("vortex", 2, "rusanov"), ("explosion", 2, "rusanov"),
+                                         ("explosion", 2, "hll"), ("vortex", 1, "rusanov"),
+                                         ("vortex", 3, "rusanov"), ("sod", 2, "rusanov")])
+def test_lts_adjoint_matches_reverse_mode_oracle(name, M, flux):
     mesh, Q0 = _case(name)
-    print(f"lts adjoint {name} {flux} {mesh.n_elems} triangles, 3 levels, 2 macro steps", flush=True)
-    cfg = OConfig(M=2, levels=3, mesh_velocity="lagrangian", flux=flux)
+    print(f"lts adjoint {name} M={M} {flux} {mesh.n_elems} triangles, 3 levels, 2 macro steps", flush=True)
+    cfg = OConfig(M=M, levels=3, mesh_velocity="lagrangian", flux=flux)
     o = OSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
     sched = lts_schedule(o, 10.0, 2)
     lt = LagrangianLTS(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
@@ -47,7 +50,7 @@ def test_lts_adjoint_matches_reverse_mode_oracle(name, flux):
     qb = rng.standard_normal(Q0.shape)
     xb = rng.standard_normal(mesh.nodes.shape)
     ref_q, ref_x = lt.vjp(Q0, mesh.nodes, sched, qb, xb)
-    g = _gpu(mesh, Q0, 3, flux)
+    g = _gpu(mesh, Q0, 3, flux, M)
     g.set_schedule_replay(o.step_log)
     gq, gx, done = g.adjoint_lts(2, 10.0, qb, xb)
     assert done == 2
