@@ -222,6 +222,30 @@ int ader_autotune(ader_ctx* ctx, int32_t trial_macro_steps, ader_tune* chosen);
  * Synchronises the stream. */
 int ader_set_schedule_replay(ader_ctx* ctx, const int32_t* step_ptr, const int32_t* steps, int64_t n_steps);
 
+/* Tick-length replay: macro step m (counted from the last state upload)
+ * takes deltas[m] as its tick length instead of the one computed from the
+ * smallest CFL step (still clamped so that the macro step does not pass the
+ * target time); with ader_set_schedule_replay this fixes the whole schedule,
+ * e.g. to take differences of runs from perturbed data.  deltas: host
+ * array of n positive tick lengths (copied); n = 0 turns it off.  One
+ * instance only (ADER_E_ARG otherwise).  A run past the last entry stops with
+ * ADER_E_ARG. */
+int ader_set_delta_replay(ader_ctx* ctx, const double* deltas, int32_t n);
+
+/* Schedule record: from this call on, every step an element takes (its level
+ * rule's, or the replayed one) is appended to that element's record, at most
+ * steps_per_element of them, and the tick length of each macro step (counted
+ * from the last state upload) is kept, at most macro_steps of them; a run
+ * that exceeds a capacity stops with ADER_E_ARG.  steps_per_element = 0 turns
+ * it off.  One instance only.  ader_get_schedule_record copies the record to
+ * host memory: step_ptr [n_elems + 1] (CSR offsets, always written), steps
+ * [steps_cap] and deltas [deltas_cap] (either may be NULL: then only the
+ * counts *n_steps and *n_deltas are returned), in the layout that
+ * ader_set_schedule_replay and ader_set_delta_replay take.  Synchronises. */
+int ader_set_schedule_record(ader_ctx* ctx, int32_t steps_per_element, int32_t macro_steps);
+int ader_get_schedule_record(ader_ctx* ctx, int32_t* step_ptr, int32_t* steps, int64_t steps_cap, double* deltas,
+                             int32_t deltas_cap, int64_t* n_steps, int32_t* n_deltas);
+
 /* Launch mode of ader_step_gts / ader_step_lts.  on != 0 (the default): each
  * macro step (levels and predictors, its 2^(L-1) cycles, the unfinished count
  * and the macro-step end) is one HIP graph, captured on a private stream of

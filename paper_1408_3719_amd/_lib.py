@@ -30,7 +30,8 @@ EXPORTED = ["ader_create", "ader_upload_mesh", "ader_workspace_size", "ader_bind
             "ader_kernel_times", "ader_adjoint_workspace_size", "ader_adjoint_gts_step",
             "ader_adjoint_gts_step_static", "ader_set_schedule_replay",
             "ader_adjoint_lagrangian_workspace_size", "ader_adjoint_lagrangian_step", "ader_upload_state_xy",
-            "ader_probe_contraction", "ader_adjoint_lts",
+            "ader_probe_contraction", "ader_adjoint_lts", "ader_set_delta_replay", "ader_set_schedule_record",
+            "ader_get_schedule_record",
             "ader_last_error", "ader_destroy"]
 KERNELS = ["sched", "node", "patch", "update", "recon", "predict", "macro", "status", "adjoint"]
 
@@ -108,6 +109,10 @@ def load():
     lib.ader_adjoint_lagrangian_step.argtypes = [P, dbl, P, P, P, P, P, P, P, P, P, ctypes.c_size_t]
     lib.ader_set_schedule_replay.argtypes = [P, P, P, ctypes.c_int64]
     lib.ader_adjoint_lts.argtypes = [P, i32, i32, dbl, P, P, P, P, ctypes.POINTER(i32)]
+    lib.ader_set_delta_replay.argtypes = [P, P, i32]
+    lib.ader_set_schedule_record.argtypes = [P, i32, i32]
+    lib.ader_get_schedule_record.argtypes = [P, P, P, ctypes.c_int64, P, i32, ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(i32)]
     lib.ader_last_error.argtypes = [P]
     lib.ader_last_error.restype = ctypes.c_char_p
     lib.ader_destroy.argtypes = [P]

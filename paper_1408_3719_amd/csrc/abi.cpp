@@ -39,6 +39,9 @@ struct ader_ctx {
   int64_t extra_cycles = 0, long_macro_steps = 0;   // beyond 2^(L-1) cycles
   // schedule replay tables (device memory owned by the context)
   int* replay_buf = nullptr;
+  double* delta_buf = nullptr;     // tick-length replay
+  int* rec_buf = nullptr;          // schedule record: steps, then positions
+  double* rec_delta_buf = nullptr; // schedule record: tick lengths
   // the library's fixed adjoint scratch on this context's GPU (ader_bind_workspace)
   void* static_work = nullptr;
   size_t static_bytes = 0;
@@ -198,7 +201,9 @@ int check_err(ader_ctx* c, const aw::Scal& s) {
   if (s.err & aw::ERR_PRED) return fail(c, ADER_E_STATE, "a predictor was read outside its time slab");
   if (s.err & aw::ERR_DT) return fail(c, ADER_E_STATE, "time step is not positive");
   if (s.err & aw::ERR_REPLAY)
-    return fail(c, ADER_E_ARG, "schedule replay: an element ran out of recorded steps or a step leaves its macro step");
+    return fail(c, ADER_E_ARG, "schedule replay: an element ran out of recorded steps, a step leaves its macro step, "
+                               "or the tick lengths ran out");
+  if (s.err & aw::ERR_RECORD) return fail(c, ADER_E_ARG, "schedule record: capacity exceeded");
   return 0;
 }
 
@@ -1237,6 +1242,7 @@ std::vector<std::pair<void*, size_t>> state_arrays(const ader_ctx* c) {
                                              {d.ntick_new, NV * I},
                                              {d.node_stamp, NV * I}};
   if (d.replay_pos) a.push_back({d.replay_pos, NE * I});
+  if (d.rec_pos) a.push_back({d.rec_pos, NE * I});
   return a;
 }
 
@@ -1599,10 +1605,102 @@ const char* ader_last_error(const ader_ctx* c) {
   return c->err.c_str();
 }
 
+int ader_set_delta_replay(ader_ctx* c, const double* deltas, int32_t n) {
+  if (!c) return ADER_E_ARG;
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  if (n < 0 || (n > 0 && !deltas)) return fail(c, ADER_E_ARG, "tick-length replay: bad count");
+  if (n > 0 && c->dev.K != 1) return fail(c, ADER_E_ARG, "tick-length replay runs one instance");
+  for (int32_t m = 0; m < n; ++m)
+    if (!(deltas[m] > 0.0) || !std::isfinite(deltas[m]))
+      return fail(c, ADER_E_ARG, "tick-length replay: tick lengths must be positive and finite");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->delta_buf) {
+    HIPCHK(c, hipFree(c->delta_buf));
+    c->delta_buf = nullptr;
+  }
+  c->dev.replay_delta = nullptr;
+  c->dev.replay_delta_n = 0;
+  drop_graphs(c);
+  if (n == 0) return ADER_OK;
+  HIPCHK(c, hipMalloc(&c->delta_buf, size_t(n) * sizeof(double)));
+  HIPCHK(c, hipMemcpyAsync(c->delta_buf, deltas, size_t(n) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->dev.replay_delta = c->delta_buf;
+  c->dev.replay_delta_n = n;
+  return ADER_OK;
+}
+
+int ader_set_schedule_record(ader_ctx* c, int32_t steps_per_element, int32_t macro_steps) {
+  if (!c) return ADER_E_ARG;
+  if (!c->bound) return fail(c, ADER_E_ORDER, "no workspace bound");
+  if (steps_per_element < 0 || macro_steps < 0) return fail(c, ADER_E_ARG, "schedule record: negative capacity");
+  if (steps_per_element > 0 && c->dev.K != 1) return fail(c, ADER_E_ARG, "schedule record runs one instance");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->rec_buf) (void)hipFree(c->rec_buf);
+  if (c->rec_delta_buf) (void)hipFree(c->rec_delta_buf);
+  c->rec_buf = nullptr;
+  c->rec_delta_buf = nullptr;
+  aw::Dev& d = c->dev;
+  d.rec_steps = d.rec_pos = nullptr;
+  d.rec_cap = 0;
+  d.rec_delta = nullptr;
+  d.rec_delta_cap = 0;
+  drop_graphs(c);
+  if (steps_per_element == 0) return ADER_OK;
+  const size_t NE = c->topo.NE;
+  HIPCHK(c, hipMalloc(&c->rec_buf, (NE * size_t(steps_per_element) + NE) * sizeof(int)));
+  HIPCHK(c, hipMemsetAsync(c->rec_buf + NE * size_t(steps_per_element), 0, NE * sizeof(int), c->stream));
+  const size_t nd = size_t(macro_steps > 0 ? macro_steps : 1);
+  HIPCHK(c, hipMalloc(&c->rec_delta_buf, nd * sizeof(double)));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  d.rec_steps = c->rec_buf;
+  d.rec_pos = c->rec_buf + NE * size_t(steps_per_element);
+  d.rec_cap = steps_per_element;
+  d.rec_delta = c->rec_delta_buf;
+  d.rec_delta_cap = macro_steps;
+  return ADER_OK;
+}
+
+int ader_get_schedule_record(ader_ctx* c, int32_t* step_ptr, int32_t* steps, int64_t steps_cap, double* deltas,
+                             int32_t deltas_cap, int64_t* n_steps, int32_t* n_deltas) {
+  if (!c || !step_ptr || !n_steps || !n_deltas) return ADER_E_ARG;
+  if (!c->dev.rec_steps) return fail(c, ADER_E_ORDER, "no schedule record");
+  const aw::Dev& d = c->dev;
+  const size_t NE = c->topo.NE;
+  std::vector<int> pos(NE);
+  aw::Scal sc;
+  HIPCHK(c, hipMemcpyAsync(pos.data(), d.rec_pos, NE * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&sc, d.scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (sc.err & aw::ERR_RECORD) return fail(c, ADER_E_ARG, "schedule record: capacity exceeded");
+  step_ptr[0] = 0;
+  for (size_t i = 0; i < NE; ++i) step_ptr[i + 1] = step_ptr[i] + pos[i];
+  *n_steps = step_ptr[NE];
+  *n_deltas = std::min(sc.macro_index, d.rec_delta_cap);
+  if (steps) {
+    if (steps_cap < *n_steps) return fail(c, ADER_E_ARG, "schedule record: steps buffer too small");
+    std::vector<int> all(NE * size_t(d.rec_cap));
+    HIPCHK(c, hipMemcpyAsync(all.data(), d.rec_steps, all.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < NE; ++i)
+      std::memcpy(steps + step_ptr[i], all.data() + i * size_t(d.rec_cap), size_t(pos[i]) * sizeof(int));
+  }
+  if (deltas) {
+    if (deltas_cap < *n_deltas) return fail(c, ADER_E_ARG, "schedule record: tick-length buffer too small");
+    HIPCHK(c, hipMemcpyAsync(deltas, d.rec_delta, size_t(*n_deltas) * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return ADER_OK;
+}
+
 void ader_destroy(ader_ctx* c) {
   if (!c) return;
   if (c->bound) (void)hipStreamSynchronize(c->stream);
   if (c->replay_buf) (void)hipFree(c->replay_buf);
+  if (c->delta_buf) (void)hipFree(c->delta_buf);
+  if (c->rec_buf) (void)hipFree(c->rec_buf);
+  if (c->rec_delta_buf) (void)hipFree(c->rec_delta_buf);
   drop_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   for (int k = 0; k < ADER_K_COUNT; ++k)

@@ -77,13 +77,15 @@ struct Scal {
   unsigned long long n_patch;   // space-time patches integrated
   unsigned long long n_node;    // node moves
   unsigned long long replay_overrides;   // replayed steps that differ from the level rule's
+  int macro_index;  // macro steps ended since the state upload
+  int pad2;
 };
 
 static_assert(offsetof(Scal, n_live) == offsetof(Scal, n_active) + sizeof(int) &&
                   offsetof(Scal, n_active) % 8 == 0,
               "n_active and n_live must form one aligned 8-byte word");
 
-enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8, ERR_DT = 16, ERR_REPLAY = 32 };
+enum : int { ERR_GEOM = 1, ERR_STATE = 2, ERR_GCL = 4, ERR_PRED = 8, ERR_DT = 16, ERR_REPLAY = 32, ERR_RECORD = 64 };
 
 // Ticks per macro step. Free local time steps: the interval to the target
 // time is one macro step of FREE_TICKS ticks; every element steps
@@ -157,6 +159,18 @@ struct Dev {
   // replay_steps[replay_ptr[i] .. replay_ptr[i+1]); replay_pos[i] counts them
   const int *replay_ptr, *replay_steps;
   int* replay_pos;
+  // tick-length replay (null when off; one instance): macro step m takes
+  // replay_delta[m] (clamped to the target time as the computed one)
+  const double* replay_delta;
+  int replay_delta_n;
+  // schedule record (null when off): element i's k-th step at
+  // rec_steps[i * rec_cap + k], rec_pos[i] of them; macro step m's tick length
+  // at rec_delta[m] (m < rec_delta_cap; one instance)
+  int* rec_steps;
+  int* rec_pos;
+  int rec_cap;
+  double* rec_delta;
+  int rec_delta_cap;
 };
 
 // Buffers of the reverse-mode step (adjoint.hip), carved from the caller's

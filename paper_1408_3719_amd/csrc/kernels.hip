@@ -324,9 +324,22 @@ __device__ inline int level_step(double dtcfl, double delta, int N, int tick, in
 // replay the next recorded step of the element (counted when it differs from
 // `own`; a missing or out-of-range entry raises ERR_REPLAY and keeps `own`).
 // *over is set for the step taken.
+__device__ inline void record_step(const Dev& d, int i, int p) {
+  if (!d.rec_steps) return;
+  const int k = d.rec_pos[i];
+  if (k < d.rec_cap)
+    d.rec_steps[size_t(i) * d.rec_cap + k] = p;
+  else
+    set_err(d, ERR_RECORD);
+  d.rec_pos[i] = k + 1;
+}
+
 __device__ inline int take_step(const Dev& d, int i, int own, int tick, int N, double dtcfl, double delta,
                                 int* over) {
-  if (!d.replay_steps) return own;
+  if (!d.replay_steps) {
+    record_step(d, i, own);
+    return own;
+  }
   const int pos = d.replay_ptr[i] + d.replay_pos[i];
   if (pos >= d.replay_ptr[i + 1]) {
     set_err(d, ERR_REPLAY);
@@ -342,6 +355,7 @@ __device__ inline int take_step(const Dev& d, int i, int own, int tick, int N, d
     atomicAdd(&d.scal->replay_overrides, 1ull);
     *over = double(p) * delta > dtcfl;
   }
+  record_step(d, i, p);
   return p;
 }
 
@@ -1343,6 +1357,19 @@ __global__ void __launch_bounds__(TPB) k_macro_setup(Dev d, int N, double fracti
     } else {
       in->delta = fmin((__longlong_as_double((long long)in->min_dt_bits) * fraction) * dscale, rest);
     }
+    const int m = d.scal->macro_index;
+    if (d.replay_delta) {
+      if (m < d.replay_delta_n)
+        in->delta = fmin(d.replay_delta[m], rest);
+      else
+        set_err(d, ERR_REPLAY);
+    }
+    if (d.rec_delta) {
+      if (m < d.rec_delta_cap)
+        d.rec_delta[m] = in->delta;
+      else
+        set_err(d, ERR_RECORD);
+    }
     if (!(in->delta > 0.0)) set_err(d, ERR_DT);
   }
 }
@@ -1378,6 +1405,7 @@ __global__ void __launch_bounds__(TPB) k_levels(Dev d) {
 __global__ void __launch_bounds__(TPB) k_macro_end(Dev d, int only_if_done) {
   if (only_if_done && d.scal->n_unfinished != 0) return;
   const int N = d.scal->N;
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.scal->macro_index += 1;
   const int n = max(max(d.NE, d.NV), d.K);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     if (i < d.K) {

@@ -272,6 +272,37 @@ class Solver(_Base):
             ctypes.c_void_p(out.data_ptr()), ctypes.byref(ms)))
         return out, ms.value
 
+    def set_delta_replay(self, deltas):
+        """Macro step m (from the last upload) takes tick length deltas[m]
+        (None: the computed ones again)."""
+        if deltas is None or len(deltas) == 0:
+            _check(self.lib, self.ctx, self.lib.ader_set_delta_replay(self.ctx, None, 0))
+            return
+        a = np.ascontiguousarray(np.asarray(deltas, np.float64))
+        _check(self.lib, self.ctx, self.lib.ader_set_delta_replay(self.ctx, a.ctypes.data_as(ctypes.c_void_p), len(a)))
+
+    def record_schedule(self, steps_per_element: int, macro_steps: int):
+        """Record every step each element takes from now on, and each macro
+        step's tick length (0: off)."""
+        _check(self.lib, self.ctx, self.lib.ader_set_schedule_record(self.ctx, int(steps_per_element),
+                                                                     int(macro_steps)))
+
+    def recorded_schedule(self):
+        """(step_log, deltas): the steps each element took since recording
+        started, and the tick length of every macro step since the upload."""
+        ptr = np.zeros(self.NE + 1, np.int32)
+        n_steps, n_deltas = ctypes.c_int64(), ctypes.c_int32()
+        _check(self.lib, self.ctx, self.lib.ader_get_schedule_record(
+            self.ctx, ptr.ctypes.data_as(ctypes.c_void_p), None, 0, None, 0, ctypes.byref(n_steps),
+            ctypes.byref(n_deltas)))
+        steps = np.zeros(max(n_steps.value, 1), np.int32)
+        deltas = np.zeros(max(n_deltas.value, 1), np.float64)
+        _check(self.lib, self.ctx, self.lib.ader_get_schedule_record(
+            self.ctx, ptr.ctypes.data_as(ctypes.c_void_p), steps.ctypes.data_as(ctypes.c_void_p), len(steps),
+            deltas.ctypes.data_as(ctypes.c_void_p), len(deltas), ctypes.byref(n_steps), ctypes.byref(n_deltas)))
+        log = [steps[ptr[i]:ptr[i + 1]].tolist() for i in range(self.NE)]
+        return log, deltas[:n_deltas.value].tolist()
+
     def set_schedule_replay(self, step_log):
         """Replay recorded steps: step_log[i] lists the steps (in ticks)
         element i takes, in order (None: the level rule again)."""

@@ -113,3 +113,69 @@ def test_lts_adjoint_errors():
         from paper_1408_3719_amd import Config, Solver
         Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
                Config(M=2, levels=3, mesh_velocity="eulerian")).adjoint_lts(1, 10.0, qb, xb)
+
+
+def test_lts_gradient_of_the_adjoint_workload_against_central_differences():
+    """The adjoint workload with LTS: explosion recipe at 50k triangles (data
+    times 1 + 1e-3 seeded noise, so that density moves pressure and
+    velocity), M=2, 3 levels, 100 macro steps from t = 0, J = energy carried
+    at the end by the elements that start inside r < 0.3; the gradient with
+    respect to the initial densities on 32 seeded directions and the initial
+    node positions on 8, against central differences (h = 1e-6 relative) of
+    the library's own forward run, and again with h = 1e-7 on the four
+    directions that deviate most (the deviation is the differences'
+    truncation error, falling as h^2); the perturbed runs replay the recorded
+    steps and tick lengths (the schedule held fixed)."""
+    from test_gpu_adjoint_lagrangian import _inner_energy
+    from workloads import explosion_case
+    mesh, Q0 = explosion_case(50_000, seed=7)
+    rng = np.random.default_rng(12)
+    Q0 = Q0 * (1.0 + 1e-3 * rng.standard_normal(Q0.shape))
+    n_macro = 100
+    J = _inner_energy(mesh)
+    g = _gpu(mesh, Q0, 3, "rusanov")
+    g.record_schedule(4096, n_macro)
+    g.step_lts(1e9, n_macro)
+    log, deltas = g.recorded_schedule()
+    assert len(deltas) == n_macro
+    q = g.download_q().clone().requires_grad_(True)
+    x = g.download_x().clone().requires_grad_(True)
+    J(q, x).backward()
+    g.record_schedule(0, 0)
+    g.set_schedule_replay(log)
+    g.set_delta_replay(deltas)
+    g.upload_state(Q0, 0.0)
+    gq, gx, done = g.adjoint_lts(n_macro, 1e9, q.grad, x.grad)
+    assert done == n_macro
+    grad_rho, gx = gq[0].cpu().numpy(), gx.cpu().numpy()
+
+    def run(Q, X):
+        g.set_schedule_replay(log)
+        g.upload_state(Q, 0.0, X=X)
+        g.step_lts(1e9, n_macro)
+        assert g.stats()["macro_steps"] == n_macro
+        return float(J(g.download_q(), g.download_x()))
+
+    def dev(v, h):
+        Qp, Qm = Q0.copy(), Q0.copy()
+        Qp[:, 0] += h * v
+        Qm[:, 0] -= h * v
+        fd = (run(Qp, mesh.nodes) - run(Qm, mesh.nodes)) / (2 * h)
+        return abs(fd - float((grad_rho * v).sum())) / float(np.abs(grad_rho * v).sum())
+
+    h = 1e-6
+    dirs = [rng.standard_normal(mesh.n_elems) * Q0[:, 0] for _ in range(32)]
+    devs = [dev(v, h) for v in dirs]
+    worst = max(devs)
+    # the deviation is the differences' truncation error: it falls as h^2
+    # (measured: ~1e-4 at h = 1e-5, ~1e-6 at 1e-6, ~1e-7 at 1e-7, rounding)
+    finer = [dev(dirs[k], 1e-7) for k in np.argsort(devs)[-4:]]
+    span = np.ptp(mesh.nodes)
+    worst_x = 0.0
+    for k in range(8):
+        y = rng.standard_normal(mesh.nodes.shape) * 1e-3 * span
+        fd = (run(Q0, mesh.nodes + h * y) - run(Q0, mesh.nodes - h * y)) / (2 * h)
+        worst_x = max(worst_x, abs(fd - float((gx * y).sum())) / float(np.abs(gx * y).sum()))
+    print(f"LTS adjoint workload: density 32 directions, worst {worst:.2e} (h = 1e-7 on the worst four: "
+          f"{max(finer):.2e}); positions 8 directions, worst {worst_x:.2e}", flush=True)
+    assert worst < 3e-5 and max(finer) < 1e-6 and worst_x < 1e-5

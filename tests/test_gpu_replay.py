@@ -4,7 +4,9 @@ floating point on both sides (a CFL step at a level boundary, the floor of a
 free step) cannot flip between them. Checked with the oracle's own schedule
 (no step differs from the kernels' rule) and with a schedule the oracle was
 forced into (every replayed change shows up as an override and the results
-still agree)."""
+still agree). The schedule record (ader_set_schedule_record) gives back a
+replayed schedule exactly, and a recorded run with its tick lengths
+(ader_set_delta_replay) replays bit for bit."""
 import os
 import sys
 
@@ -90,3 +92,58 @@ def test_replay_errors_on_a_short_schedule():
         g.step_lts(10.0, 1)
     with pytest.raises(ValueError):
         g.set_schedule_replay([[1]])
+
+
+def test_record_of_a_replayed_oracle_schedule():
+    """Recording while replaying the oracle's schedule gives back the oracle's
+    steps exactly and its tick lengths to rounding."""
+    from oracle.adjoint import lts_schedule
+    make, M = CASES["explosion_M2"]
+    mesh, Q0 = make()
+    o = _oracle(mesh, Q0, M, 3)
+    sched = lts_schedule(o, 10.0, 2)
+    g = _gpu_solver(mesh, Q0, M, 3)
+    g.set_schedule_replay(o.step_log)
+    g.record_schedule(64, 4)
+    g.step_lts(10.0, 2)
+    log, deltas = g.recorded_schedule()
+    assert log == [list(x) for x in o.step_log]
+    assert len(deltas) == 2
+    for d, (od, _) in zip(deltas, sched):
+        assert abs(d - od) <= 1e-14 * od
+
+
+def test_recorded_schedule_replays_bit_for_bit():
+    """A run's recorded steps and tick lengths, replayed from the same data,
+    give the same run bit for bit with no step overridden; from perturbed data
+    the replayed schedule is the one taken (the record of the second run equals
+    the first's), and running past the recorded tick lengths is refused."""
+    from paper_1408_3719_amd import AderError
+    make, M = CASES["explosion_M2"]
+    mesh, Q0 = make()
+    g = _gpu_solver(mesh, Q0, M, 3)
+    g.record_schedule(64, 4)
+    g.step_lts(10.0, 3)
+    log, deltas = g.recorded_schedule()
+    QA, XA, _ = g.download()
+    assert len(deltas) == 3 and sum(len(x) for x in log) > 3 * mesh.n_elems
+    g.set_schedule_replay(log)
+    g.set_delta_replay(deltas)
+    g.upload_state(Q0, 0.0)
+    g.record_schedule(64, 4)
+    g.step_lts(10.0, 3)
+    QB, XB, _ = g.download()
+    assert np.array_equal(QA, QB) and np.array_equal(XA, XB)
+    assert g.stats()["replay_overrides"] == 0
+    Qp = Q0 * (1.0 + 1e-4 * np.random.default_rng(9).standard_normal(Q0.shape))
+    g.set_schedule_replay(log)
+    g.upload_state(Qp, 0.0)
+    g.record_schedule(64, 4)
+    g.step_lts(10.0, 3)
+    log2, deltas2 = g.recorded_schedule()
+    assert log2 == log and deltas2 == deltas
+    g.set_schedule_replay(log)
+    g.upload_state(Q0, 0.0)
+    g.record_schedule(0, 0)
+    with pytest.raises(AderError, match="tick lengths"):
+        g.step_lts(10.0, 4)
