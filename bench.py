@@ -54,12 +54,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in 
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
     "workload": "explosion",
-    "source_sha256": "639d3100074d865237df690f93eff5c86c86973fc14bf713a4d16ad9222de5fa",
-    "k_reconstruct": {0: 1728, 4: 1778, 8: 1751, 16: 1736, 32: 1736},
-    "k_predict": {0: 1503, 4: 1504, 8: 1503, 16: 1503, 32: 1503},
-    "k_patch": {w: 1046 for w in TRAFFIC_SWEEP},
-    "k_update": {w: 735 for w in TRAFFIC_SWEEP},
-    "k_node": {w: 1778 for w in TRAFFIC_SWEEP},
+    "source_sha256": "7237b550ff26fd18436592740bb46bb4f542c46b17e632634fb5652f399443be",
+    "k_reconstruct": {0: 1727, 4: 1780, 8: 1751, 16: 1740, 32: 1733},
+    "k_predict": {0: 1502, 4: 1503, 8: 1502, 16: 1502, 32: 1502},
+    "k_patch": {0: 1046, 4: 1046, 8: 1047, 16: 1046, 32: 1047},
+    "k_update": {0: 735, 4: 737, 8: 735, 16: 735, 32: 735},
+    "k_node": {w: 1776 for w in TRAFFIC_SWEEP},
     "k_sched": {w: 89 for w in TRAFFIC_SWEEP},
 }
 
