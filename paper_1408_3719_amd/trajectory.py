@@ -1,5 +1,6 @@
 """Reverse mode over a run of global time steps, on a fixed mesh or on the
-mesh moving with the fluid.
+mesh moving with the fluid, and over macro steps of the local time stepping
+on the moving mesh.
 
 torch.autograd.Functions whose forward runs n global time steps of fixed
 length dt (ader_step_gts) and whose backward runs the adjoint of each step
@@ -11,8 +12,10 @@ segment are recomputed from its checkpoint during the backward pass
 doubles (1.6 MB at 50k triangles; with a moving mesh also the node
 positions, 0.4 MB: every = 1, keeping all states, is the cheapest choice
 unless n * NE is very large).  The solver is left at some
-state of the run.  This module only schedules the library's calls: every
-step and every adjoint runs in the HIP kernels.
+state of the run.  lts_trajectory runs LTS macro steps recording their
+schedule, and its backward replays that schedule through ader_adjoint_lts
+(which keeps its own states).  This module only schedules the library's
+calls: every step and every adjoint runs in the HIP kernels.
 """
 from __future__ import annotations
 
@@ -123,3 +126,56 @@ def lagrangian_trajectory(solver, Q0, X0, dt: float, n_steps: int, every: int = 
             return qbar, xbar
 
     return _LAG.apply(Q0, X0)
+
+
+def lts_trajectory(solver, Q0, X0, n_macro: int, t_end: float = 1e9, steps_per_element: int = 4096):
+    """(Q, X) after n_macro macro steps of the solver's dyadic local time
+    stepping (mesh moving with the fluid) from (Q0 [4][NE], X0 (NV, 2)),
+    differentiable with respect to both with the schedule held fixed.  The
+    forward pass records every element's steps and every macro step's tick
+    length (ader_set_schedule_record); the backward pass uploads (Q0, X0),
+    replays that schedule (ader_set_schedule_replay, ader_set_delta_replay)
+    and runs ader_adjoint_lts, then turns the replays off.  The solver is left
+    at the end state of the run."""
+    import torch
+
+    if n_macro < 1:
+        raise ValueError("n_macro must be positive")
+    if solver.cfg.mesh_velocity != "lagrangian" or solver.cfg.levels < 1:
+        raise ValueError("lts_trajectory differentiates dyadic LTS macro steps on the moving mesh")
+
+    class _LTS(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, q0, x0):
+            q = q0.detach().to(dtype=torch.float64).contiguous()
+            x = x0.detach().to(dtype=torch.float64).contiguous()
+            solver.set_schedule_replay(None)
+            solver.set_delta_replay(None)
+            solver.upload_state(q, 0.0, X=x)
+            solver.record_schedule(steps_per_element, n_macro)
+            st = solver.step_lts(t_end, n_macro)
+            log, deltas = solver.recorded_schedule()
+            solver.record_schedule(0, 0)
+            ctx.save_for_backward(q, x)
+            ctx.schedule = (log, deltas, int(st["macro_steps"]))
+            return solver.download_q(), solver.download_x()
+
+        @staticmethod
+        def backward(ctx, qbar, xbar):
+            q0, x0 = ctx.saved_tensors
+            log, deltas, n = ctx.schedule
+            qbar = torch.zeros_like(q0) if qbar is None else qbar.detach().to(torch.float64).contiguous()
+            xbar = torch.zeros_like(x0) if xbar is None else xbar.detach().to(torch.float64).contiguous()
+            solver.set_schedule_replay(log)
+            solver.set_delta_replay(deltas)
+            try:
+                solver.upload_state(q0, 0.0, X=x0)
+                gq, gx, done = solver.adjoint_lts(n, t_end, qbar, xbar)
+                if done != n:
+                    raise RuntimeError("the replayed run took a different number of macro steps")
+            finally:
+                solver.set_schedule_replay(None)
+                solver.set_delta_replay(None)
+            return gq, gx
+
+    return _LTS.apply(Q0, X0)

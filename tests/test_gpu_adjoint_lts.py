@@ -179,3 +179,47 @@ def test_lts_gradient_of_the_adjoint_workload_against_central_differences():
     print(f"LTS adjoint workload: density 32 directions, worst {worst:.2e} (h = 1e-7 on the worst four: "
           f"{max(finer):.2e}); positions 8 directions, worst {worst_x:.2e}", flush=True)
     assert worst < 3e-5 and max(finer) < 1e-6 and worst_x < 1e-5
+
+
+def test_lts_trajectory_autograd_and_linearity():
+    """paper_1408_3719_amd.trajectory.lts_trajectory: its forward is the
+    library's LTS run, its gradient (torch.autograd through the recorded and
+    replayed schedule) equals ader_adjoint_lts with that schedule, and the
+    adjoint is linear in (Qbar, Xbar): adj(a w1 + b w2) = a adj(w1) + b adj(w2)."""
+    import torch
+
+    from paper_1408_3719_amd.trajectory import lts_trajectory
+    mesh, Q0 = _case("explosion")
+    g = _gpu(mesh, Q0, 3, "rusanov")
+    rng = np.random.default_rng(10)
+    w1 = torch.tensor(rng.standard_normal((4, mesh.n_elems)), device="cuda")
+    y1 = torch.tensor(rng.standard_normal(mesh.nodes.shape), device="cuda")
+    w2 = torch.tensor(rng.standard_normal((4, mesh.n_elems)), device="cuda")
+    y2 = torch.tensor(rng.standard_normal(mesh.nodes.shape), device="cuda")
+    q0 = torch.tensor(Q0.T.copy(), device="cuda", requires_grad=True)
+    x0 = torch.tensor(mesh.nodes, device="cuda", requires_grad=True)
+    qn, xn = lts_trajectory(g, q0, x0, 2, t_end=10.0)
+    ((w1 * qn).sum() + (y1 * xn).sum()).backward()
+    h = _gpu(mesh, Q0, 3, "rusanov")
+    h.step_lts(10.0, 2)
+    Q, X, _ = h.download()
+    assert np.array_equal(qn.detach().cpu().numpy().T, Q) and np.array_equal(xn.detach().cpu().numpy(), X)
+    h.record_schedule(64, 4)
+    h.upload_state(Q0, 0.0)
+    h.step_lts(10.0, 2)
+    log, deltas = h.recorded_schedule()
+    h.record_schedule(0, 0)
+
+    def adj(qb, xb):
+        h.set_schedule_replay(log)
+        h.set_delta_replay(deltas)
+        h.upload_state(Q0, 0.0)
+        gq, gx, done = h.adjoint_lts(2, 10.0, qb, xb)
+        assert done == 2
+        return gq.cpu().numpy(), gx.cpu().numpy()
+
+    gq1, gx1 = adj(w1, y1)
+    assert _rel(q0.grad.cpu().numpy(), gq1) < 1e-13 and _rel(x0.grad.cpu().numpy(), gx1) < 1e-13
+    gq2, gx2 = adj(w2, y2)
+    gq3, gx3 = adj(2.0 * w1 - 0.5 * w2, 2.0 * y1 - 0.5 * y2)
+    assert _rel(gq3, 2.0 * gq1 - 0.5 * gq2) < 1e-12 and _rel(gx3, 2.0 * gx1 - 0.5 * gx2) < 1e-12
