@@ -341,7 +341,9 @@ int ader_adjoint_lagrangian_step(ader_ctx* ctx, double dt, const double* Q_dev, 
 
 /* ---- Gradient through macro steps of the local time stepping -------------
  * Dyadic LTS (Sec. 2.6) on the mesh moving with the fluid (mesh_velocity = 0)
- * with the Rusanov or HLL flux, differentiated with its schedule held fixed:
+ * or on a fixed mesh (mesh_velocity = 1: V = 0 in eq. ODEmesh, the node
+ * positions still differentiated through the geometry) with the Rusanov or
+ * HLL flux, differentiated with its schedule held fixed:
  * the tick length of every macro step and every element's sequence of steps
  * are those the forward run takes (with ader_set_schedule_replay, the
  * replayed ones), so the update sets and the moved nodes and swept edges of
@@ -370,9 +372,9 @@ int ader_adjoint_lagrangian_step(ader_ctx* ctx, double dt, const double* Q_dev, 
  * full state at the start only and is replayed cycle by cycle when the sweep
  * reaches it (one more forward pass over those steps).  Scratch of about
  * 1.2 KB per element at M = 2.  Synchronises.
- * ADER_E_ARG for a fixed mesh, free steps, the Osher flux, a batch of
- * instances or n_macro < 1; ADER_E_ORDER before a state upload or after a
- * step; the forward run's own errors as ader_step_lts. */
+ * ADER_E_ARG for free steps, the Osher flux, a batch of instances or
+ * n_macro < 1; ADER_E_ORDER before a state upload or after a step; the
+ * forward run's own errors as ader_step_lts. */
 int ader_adjoint_lts(ader_ctx* ctx, int32_t n_macro, int32_t keep_macro_steps, double t_end, const double* Qbar_dev,
                      const double* Xbar_dev, double* Qbar0_dev, double* Xbar0_dev, int32_t* n_done);
 

@@ -337,10 +337,12 @@ class LagrangianStep:
     def __init__(self, nodes, tris, cfg: Config, bedges=None, topo=None):
         if cfg.flux not in FLUX_FUNCTIONS:
             raise ValueError("the reverse-mode oracle covers the Rusanov and HLL fluxes")
-        if cfg.mesh_velocity != "lagrangian":
-            raise ValueError("LagrangianStep moves the mesh with the fluid")
+        if cfg.mesh_velocity not in ("lagrangian", "eulerian"):
+            raise ValueError("a prescribed mesh velocity is not covered")
         from .scheme import wall_constraints
         self.cfg = cfg
+        # V = v (the mesh moves with the fluid) or V = 0 (a fixed mesh, eq. ODEmesh)
+        self.vscale = 1.0 if cfg.mesh_velocity == "lagrangian" else 0.0
         M = cfg.M
         self.M = M
         self.topo = topo if topo is not None else build_topology(nodes, tris, M, bedges)
@@ -455,7 +457,7 @@ class LagrangianStep:
         x = x0[:, :, None, :].expand(-1, -1, T, -1)
         d = lambda D, a: torch.einsum("km,nmtv->nktv", D, a)   # noqa: E731
         for _ in range(cfg.npic):
-            V = q[..., 1:3] / q[..., 0:1]
+            V = self.vscale * (q[..., 1:3] / q[..., 0:1])
             xu = self.Bt[None, None, :, None] * x[:, :, 0:1, :] + dt4 * torch.einsum("qr,nmrc->nmqc", self.At, V)
             x = torch.cat([x[:, :, 0:1, :], xu], dim=2)
             x_xi, x_eta = d(self.Dxi, x), d(self.Deta, x)
@@ -472,7 +474,7 @@ class LagrangianStep:
                   + d(self.Dxi, g) * xi_y[..., None] + d(self.Deta, g) * eta_y[..., None])
             qu = self.Bt[None, None, :, None] * q[:, :, 0:1, :] + dt4 * torch.einsum("qr,nmrv->nmqv", self.At, P)
             q = torch.cat([q[:, :, 0:1, :], qu], dim=2)
-        V = q[..., 1:3] / q[..., 0:1]
+        V = self.vscale * (q[..., 1:3] / q[..., 0:1])
         return (torch.einsum("egm,nmtv->negtv", self.edge_tab, q),
                 torch.einsum("m,nmtv->ntv", self.amean, q), V[:, self.vtx])
 
@@ -564,7 +566,7 @@ class LagrangianLTS:
     the node solver over each node's own interval, eqs. eqn.dtau .. eqn.newVertex;
     swept space-time patches with corners at different times, eqs.
     eqn.spacetimenodes and eqn.STint; memory variables, eq. eqn.Qm2) with the
-    mesh moving with the fluid, written with PyTorch CPU operations in FP64
+    mesh moving with the fluid (or held fixed: V = 0), written with PyTorch CPU operations in FP64
     after the NumPy oracle's Solver, cycle by cycle, with the schedule held
     fixed: the tick length of every macro step and every element's sequence of
     steps are inputs (taken from a run of the NumPy oracle), so the update

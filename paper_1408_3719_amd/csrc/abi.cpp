@@ -1508,7 +1508,8 @@ int ader_adjoint_lts(ader_ctx* c, int32_t n_macro, int32_t keep_macro_steps, dou
   if (!c->has_state) return fail(c, ADER_E_ORDER, "no state uploaded");
   if (c->cycles != 0 || c->macro_steps != 0)
     return fail(c, ADER_E_ORDER, "the LTS adjoint starts from an uploaded state with no step taken since");
-  if (c->cfg.mesh_velocity != 0) return fail(c, ADER_E_ARG, "the LTS adjoint needs the mesh moving with the fluid");
+  if (c->cfg.mesh_velocity != 0 && c->cfg.mesh_velocity != 1)
+    return fail(c, ADER_E_ARG, "the LTS adjoint covers the mesh moving with the fluid and the fixed mesh");
   if (c->cfg.lts_levels < 1) return fail(c, ADER_E_ARG, "the LTS adjoint needs dyadic levels (lts_levels >= 1)");
   if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the LTS adjoint runs one instance");
   if (c->prm.flux != ADER_FLUX_RUSANOV && c->prm.flux != ADER_FLUX_HLL)

@@ -1152,6 +1152,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __res
   __shared__ double lds[(SLOTS + L::WPB) * L::LSTR];
   const int NE = d.NE;
   const double gam = P.gamma;
+  const double vs = P.lagrangian ? 1.0 : 0.0;   // mesh velocity V = v, or V = 0 (fixed mesh)
   const int wv = threadIdx.x / 64, lw = threadIdx.x % 64;
   const bool spare = lw >= EPW * G;
   const int slot = spare ? SLOTS + wv : wv * EPW + lw / G;
@@ -1209,7 +1210,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_fwd(Dev d, const Tables* __res
           double s = 0.0;
 #pragma unroll
           for (int t = 0; t < T; ++t) s += tb->At[r][t] * q[t][1 + c] / q[t][0];
-          x[r + 1][c] = tb->Bt[r] * x0[c] + dt * s;
+          x[r + 1][c] = tb->Bt[r] * x0[c] + dt * (vs * s);
         }
       }
       double qn[M][4];
@@ -1545,6 +1546,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
   __shared__ double lds[(SLOTS + L::WPB) * L::LSTR];
   const int NE = d.NE;
   const double gam = P.gamma;
+  const double vs = P.lagrangian ? 1.0 : 0.0;   // mesh velocity V = v, or V = 0 (fixed mesh)
   const int wv = threadIdx.x / 64, lw = threadIdx.x % 64;
   const bool spare = lw >= EPW * G;
   const int slot = spare ? SLOTS + wv : wv * EPW + lw / G;
@@ -1620,7 +1622,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
           const double q0 = w.keep[keep_at<M>(P.npic, t, 0, i, m, NE)];
           const double q1 = w.keep[keep_at<M>(P.npic, t, 1, i, m, NE)];
           const double q2 = w.keep[keep_at<M>(P.npic, t, 2, i, m, NE)];
-          const double vxb = LTS ? ov[2 * t] : I[t] * o[0], vyb = LTS ? ov[2 * t + 1] : I[t] * o[1];
+          const double vxb = vs * (LTS ? ov[2 * t] : I[t] * o[0]), vyb = vs * (LTS ? ov[2 * t + 1] : I[t] * o[1]);
           qb[t][0] -= (vxb * q1 + vyb * q2) / (q0 * q0);
           qb[t][1] += vxb / q0;
           qb[t][2] += vyb / q0;
@@ -1662,7 +1664,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
           double s = 0.0;
 #pragma unroll
           for (int t = 0; t < T; ++t) s += tb->At[r][t] * q[t][1 + c] / q[t][0];
-          x[r + 1][c] = tb->Bt[r] * x0[c] + dt * s;
+          x[r + 1][c] = tb->Bt[r] * x0[c] + dt * (vs * s);
         }
       }
       // q_out[0] = q[0]; q_out[r+1] = Bt[r] q[0] + dt sum_t At[r][t] P[t]
@@ -1813,7 +1815,7 @@ __global__ void __launch_bounds__(TPB) k_lag_pred_rev(Dev d, const Tables* __res
           double s = 0.0;
 #pragma unroll
           for (int r = 0; r < M; ++r) s += tb->At[r][t] * xb[r + 1][c];
-          vb[c] = dt * s;
+          vb[c] = vs * (dt * s);
         }
         qi[t][0] -= (vb[0] * q[t][1] + vb[1] * q[t][2]) / (q[t][0] * q[t][0]);
         qi[t][1] += vb[0] / q[t][0];

@@ -4,7 +4,7 @@ averages and node positions of the uploaded state, element by element and node
 by node against the reverse-mode oracle (torch.autograd through the oracle's
 LTS macro steps replaying the same tick lengths and steps) on small meshes with
 three levels (vortex M = 1, 2, 3, explosion, shock tube with slip walls; Rusanov, and HLL on the
-explosion); the context's end state
+explosion; also on a fixed mesh); the context's end state
 against the oracle's forward run; macro steps with their cycle states kept and
 macro steps replayed from their start against each other; with one level
 against the adjoint of the global Lagrangian step (ader_adjoint_lagrangian_step)."""
@@ -30,19 +30,24 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-def _gpu(mesh, Q0, levels, flux, M=2):
+def _gpu(mesh, Q0, levels, flux, M=2, mode="lagrangian"):
     from paper_1408_3719_amd import Config, Solver
     return Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
-                  Config(M=M, levels=levels, mesh_velocity="lagrangian", flux=flux))
+                  Config(M=M, levels=levels, mesh_velocity=mode, flux=flux))
 
 
-@pytest.mark.parametrize("name,M,flux", [("vortex", 2, "rusanov"), ("explosion", 2, "rusanov"),
-                                         ("explosion", 2, "hll"), ("vortex", 1, "rusanov"),
-                                         ("vortex", 3, "rusanov"), ("sod", 2, "rusanov")])
-def test_lts_adjoint_matches_reverse_mode_oracle(name, M, flux):
+@pytest.mark.parametrize("name,M,flux,mode", [("vortex", 2, "rusanov", "lagrangian"),
+                                              ("explosion", 2, "rusanov", "lagrangian"),
+                                              ("explosion", 2, "hll", "lagrangian"),
+                                              ("vortex", 1, "rusanov", "lagrangian"),
+                                              ("vortex", 3, "rusanov", "lagrangian"),
+                                              ("sod", 2, "rusanov", "lagrangian"),
+                                              ("vortex", 2, "rusanov", "eulerian"),
+                                              ("explosion", 2, "hll", "eulerian")])
+def test_lts_adjoint_matches_reverse_mode_oracle(name, M, flux, mode):
     mesh, Q0 = _case(name)
-    print(f"lts adjoint {name} M={M} {flux} {mesh.n_elems} triangles, 3 levels, 2 macro steps", flush=True)
-    cfg = OConfig(M=M, levels=3, mesh_velocity="lagrangian", flux=flux)
+    print(f"lts adjoint {name} M={M} {flux} {mode} {mesh.n_elems} triangles, 3 levels, 2 macro steps", flush=True)
+    cfg = OConfig(M=M, levels=3, mesh_velocity=mode, flux=flux)
     o = OSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
     sched = lts_schedule(o, 10.0, 2)
     lt = LagrangianLTS(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
@@ -50,7 +55,7 @@ def test_lts_adjoint_matches_reverse_mode_oracle(name, M, flux):
     qb = rng.standard_normal(Q0.shape)
     xb = rng.standard_normal(mesh.nodes.shape)
     ref_q, ref_x = lt.vjp(Q0, mesh.nodes, sched, qb, xb)
-    g = _gpu(mesh, Q0, 3, flux, M)
+    g = _gpu(mesh, Q0, 3, flux, M, mode)
     g.set_schedule_replay(o.step_log)
     gq, gx, done = g.adjoint_lts(2, 10.0, qb, xb)
     assert done == 2
@@ -109,10 +114,10 @@ def test_lts_adjoint_errors():
     g.step_lts(10.0, 1)
     with pytest.raises(AderError, match="uploaded state"):
         g.adjoint_lts(1, 10.0, qb, xb)
-    with pytest.raises(AderError, match="fixed mesh|moving with the fluid"):
-        from paper_1408_3719_amd import Config, Solver
-        Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0,
-               Config(M=2, levels=3, mesh_velocity="eulerian")).adjoint_lts(1, 10.0, qb, xb)
+    with pytest.raises(AderError, match="Rusanov and HLL"):
+        _gpu(mesh, Q0, 3, "osher").adjoint_lts(1, 10.0, qb, xb)
+    with pytest.raises(AderError, match="dyadic levels"):
+        _gpu(mesh, Q0, 0, "rusanov").adjoint_lts(1, 10.0, qb, xb)
 
 
 def test_lts_gradient_of_the_adjoint_workload_against_central_differences():
@@ -223,3 +228,28 @@ def test_lts_trajectory_autograd_and_linearity():
     gq2, gx2 = adj(w2, y2)
     gq3, gx3 = adj(2.0 * w1 - 0.5 * w2, 2.0 * y1 - 0.5 * y2)
     assert _rel(gq3, 2.0 * gq1 - 0.5 * gq2) < 1e-12 and _rel(gx3, 2.0 * gx1 - 0.5 * gx2) < 1e-12
+
+
+def test_lts_adjoint_stops_at_the_target_time():
+    """With t_end reached after fewer macro steps than asked, the gradient is
+    the one through the macro steps taken (the oracle's over the same run)."""
+    mesh, Q0 = _case("vortex")
+    cfg = OConfig(M=2, levels=3, mesh_velocity="lagrangian")
+    o = OSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+    sched = lts_schedule(o, 10.0, 1)
+    t1 = o.st.T
+    o2 = OSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges, topo=o.topo)
+    sched = lts_schedule(o2, 1.5 * t1, 2)       # the second macro step is cut at 1.5 t1
+    assert abs(o2.st.T - 1.5 * t1) <= 1e-12 * t1
+    lt = LagrangianLTS(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+    rng = np.random.default_rng(11)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    ref_q, ref_x = lt.vjp(Q0, mesh.nodes, sched, qb, xb)
+    g = _gpu(mesh, Q0, 3, "rusanov")
+    g.set_schedule_replay(o2.step_log)
+    gq, gx, done = g.adjoint_lts(5, 1.5 * t1, qb, xb)
+    assert done == 2
+    assert abs(g.stats()["t"] - 1.5 * t1) <= 1e-12 * t1
+    gq, gx = gq.cpu().numpy().T, gx.cpu().numpy()
+    assert _rel(gq, ref_q) < TOL and _rel(gx, ref_x) < TOL

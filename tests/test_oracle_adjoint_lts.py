@@ -1,6 +1,6 @@
 """Pins of the reverse-mode oracle of the local time stepping scheme
 (oracle/adjoint.py: LagrangianLTS): dyadic macro steps on a mesh moving with
-the fluid, with the schedule held fixed (tick length and every element's
+the fluid (and on a fixed mesh), with the schedule held fixed (tick length and every element's
 steps).  Its forward map must equal the NumPy oracle's LTS solver, one level
 must reduce to global steps, its vector-Jacobian product must match central
 differences of the NumPy solver replaying the same schedule, and a translation
@@ -25,9 +25,9 @@ def _case(name):
     return mesh, Q0 * (1.0 + 1e-3 * rng.standard_normal(Q0.shape))
 
 
-def _setup(name, levels=3, n_macro=2, flux="rusanov", M=2):
+def _setup(name, levels=3, n_macro=2, flux="rusanov", M=2, mode="lagrangian"):
     mesh, Q0 = _case(name)
-    cfg = Config(M=M, levels=levels, mesh_velocity="lagrangian", flux=flux)
+    cfg = Config(M=M, levels=levels, mesh_velocity=mode, flux=flux)
     o = Solver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
     sched = lts_schedule(o, 10.0, n_macro)
     lt = LagrangianLTS(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
@@ -52,6 +52,30 @@ def test_lts_forward_equals_numpy_solver(name, M):
     Q, X = lt.run(Q0, mesh.nodes, sched)
     assert np.abs(Q - o.st.Q).max() <= 1e-14 * np.abs(o.st.Q).max()
     assert np.abs(X - o.st.X).max() <= 1e-14 * np.abs(o.st.X).max()
+
+
+@pytest.mark.parametrize("name", ["vortex", "explosion"])
+def test_lts_fixed_mesh_forward_and_central_differences(name):
+    """The same macro step on a fixed mesh (V = 0 in the mesh ODE, nodes at
+    rest, their ticks still advancing): the forward equals the NumPy LTS
+    solver in Eulerian mode, and the product matches central differences of
+    the NumPy solver replaying the schedule (averages and node positions)."""
+    mesh, Q0, cfg, o, sched, lt = _setup(name, mode="eulerian")
+    Q, X = lt.run(Q0, mesh.nodes, sched)
+    assert np.abs(Q - o.st.Q).max() <= 1e-14 * np.abs(o.st.Q).max()
+    assert np.array_equal(X, mesh.nodes) and np.array_equal(o.st.X, mesh.nodes)
+    rng = np.random.default_rng(4)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    gq, gx = lt.vjp(Q0, mesh.nodes, sched, qb, xb)
+    h = 1e-8
+    v = rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=0)
+    y = rng.standard_normal(mesh.nodes.shape) * np.ptp(mesh.nodes) * 1e-1
+    Qp, Xp = _replay(mesh, cfg, o.topo, sched, Q0 + h * v, mesh.nodes + h * y)
+    Qm, Xm = _replay(mesh, cfg, o.topo, sched, Q0 - h * v, mesh.nodes - h * y)
+    fd = (((Qp - Qm) * qb).sum() + ((Xp - Xm) * xb).sum()) / (2 * h)
+    ad = (gq * v).sum() + (gx * y).sum()
+    assert abs(fd - ad) <= 1e-6 * (np.abs(gq * v).sum() + np.abs(gx * y).sum()), (fd, ad)
 
 
 def test_lts_one_level_is_the_global_step():
