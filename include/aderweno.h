@@ -340,7 +340,8 @@ int ader_adjoint_lagrangian_step(ader_ctx* ctx, double dt, const double* Q_dev, 
                                  size_t work_bytes);
 
 /* ---- Gradient through macro steps of the local time stepping -------------
- * Dyadic LTS (Sec. 2.6) on the mesh moving with the fluid (mesh_velocity = 0)
+ * Dyadic LTS (Sec. 2.6; lts_levels >= 1) or free local steps (lts_levels = 0:
+ * one macro step to t_end) on the mesh moving with the fluid (mesh_velocity = 0)
  * or on a fixed mesh (mesh_velocity = 1: V = 0 in eq. ODEmesh, the node
  * positions still differentiated through the geometry) with the Rusanov or
  * HLL flux, differentiated with its schedule held fixed:
@@ -372,8 +373,7 @@ int ader_adjoint_lagrangian_step(ader_ctx* ctx, double dt, const double* Q_dev, 
  * full state at the start only and is replayed cycle by cycle when the sweep
  * reaches it (one more forward pass over those steps).  Scratch of about
  * 1.2 KB per element at M = 2.  Synchronises.
- * ADER_E_ARG for free steps, the Osher flux, a batch of instances or
- * n_macro < 1; ADER_E_ORDER before a state upload or after a step; the
+ * ADER_E_ARG for the Osher flux, a batch of instances or n_macro < 1; ADER_E_ORDER before a state upload or after a step; the
  * forward run's own errors as ader_step_lts. */
 int ader_adjoint_lts(ader_ctx* ctx, int32_t n_macro, int32_t keep_macro_steps, double t_end, const double* Qbar_dev,
                      const double* Xbar_dev, double* Qbar0_dev, double* Xbar0_dev, int32_t* n_done);

@@ -560,7 +560,8 @@ def lts_schedule(solver, t_end, n_macro):
 
 
 class LagrangianLTS:
-    """Macro steps of the local time stepping scheme (Sec. 2.6: dyadic levels,
+    """Macro steps of the local time stepping scheme (Sec. 2.6: dyadic levels or
+    free steps (levels = 0: one macro step of 2^30 ticks to the target time),
     the update criterion over the scheduling stencil, virtual projection of
     the stencil in space and time, eqs. eqn.virtGeom and eqn.virtCellaverage;
     the node solver over each node's own interval, eqs. eqn.dtau .. eqn.newVertex;
@@ -577,8 +578,6 @@ class LagrangianLTS:
     (nodal values wnod): element vertices and areas then follow from X."""
 
     def __init__(self, nodes, tris, cfg: Config, bedges=None, topo=None):
-        if cfg.levels < 1:
-            raise ValueError("the frozen-schedule macro step covers dyadic levels (levels >= 1)")
         self.g = LagrangianStep(nodes, tris, cfg, bedges=bedges, topo=topo)
         g = self.g
         self.cfg, self.M, self.topo = cfg, cfg.M, g.topo

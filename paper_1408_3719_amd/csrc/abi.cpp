@@ -1341,7 +1341,7 @@ int macro_by_cycles(ader_ctx* c, double t_end, int nominal, F after, int* ran, d
   int r;
   *ran = 0;
   c->synced = false;
-  set_free(c, false);
+  set_free(c, nominal == 0);
   LCHK(c, aw::launch_set_target(d, t_end, c->stream));
   LCHK(c, aw::launch_open(d, c->stream));
   if ((r = read_scal(c, s))) return r;
@@ -1355,10 +1355,10 @@ int macro_by_cycles(ader_ctx* c, double t_end, int nominal, F after, int* ran, d
   HIPCHK(c, hipMemcpyAsync(&in0, d.inst, sizeof(in0), hipMemcpyDeviceToHost, c->stream));
   if ((r = after(0))) return r;
   // the first 2^(L-1) cycles without a host check (as run_macro), then one
-  // cycle per check
+  // cycle per check; free steps: FREE_BATCH cycles per check (as run_free)
   int k = 0;
   for (;;) {
-    const int batch = k == 0 ? nominal : 1;
+    const int batch = nominal == 0 ? FREE_BATCH : (k == 0 ? nominal : 1);
     for (int b = 0; b < batch; ++b) {
       if ((r = issue_cycles(c, 1, c->stream))) return r;
       if (b == batch - 1) LCHK(c, aw::launch_status(d, c->stream));
@@ -1374,7 +1374,7 @@ int macro_by_cycles(ader_ctx* c, double t_end, int nominal, F after, int* ran, d
   LCHK(c, aw::launch_open(d, c->stream));
   if ((r = read_scal(c, s))) return r;
   c->cycles += k;
-  if (k > nominal) {
+  if (nominal > 0 && k > nominal) {
     c->extra_cycles += k - nominal;
     c->long_macro_steps++;
   }
@@ -1396,7 +1396,7 @@ int macro_by_cycles(ader_ctx* c, double t_end, int nominal, F after, int* ran, d
 int adjoint_lts_run(ader_ctx* c, int n_macro, int keep_req, double t_end, const double* Qbar, const double* Xbar,
                     double* Qbar0, double* Xbar0, int* n_done, Pool& pool, std::vector<char*>& bufs) {
   const aw::Dev& d = c->dev;
-  const int M = c->cfg.M, L = c->cfg.lts_levels, nominal = 1 << (L - 1);
+  const int M = c->cfg.M, L = c->cfg.lts_levels, nominal = L > 0 ? 1 << (L - 1) : 0;
   const size_t sb = state_bytes(c), vb = view_bytes(c);
   auto take = [&](char** out, size_t bytes) -> int {
     HIPCHK(c, hipMalloc((void**)out, bytes));
@@ -1414,7 +1414,7 @@ int adjoint_lts_run(ader_ctx* c, int n_macro, int keep_req, double t_end, const 
   if ((r = view_save(c, v0))) return r;
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
-  const size_t per_macro = size_t(nominal + 3) * vb;
+  const size_t per_macro = size_t(nominal > 0 ? nominal + 3 : 4 * FREE_BATCH) * vb;
   const long fits = long(std::min<size_t>(size_t(n_macro), size_t(0.6 * double(free_b)) / per_macro));
   const long kept = keep_req < 0 ? fits : std::min<long>(keep_req, n_macro);
   pool.chunk = std::max<size_t>(vb, size_t(64) * vb);
@@ -1438,7 +1438,7 @@ int adjoint_lts_run(ader_ctx* c, int n_macro, int keep_req, double t_end, const 
       if ((r = take(&start[m], sb))) return r;
       if ((r = state_copy(c, start[m], true))) return r;
       const int64_t before = c->macro_steps;
-      if ((r = run_macro(c, t_end, 1, L))) return r;
+      if ((r = L > 0 ? run_macro(c, t_end, 1, L) : run_free(c, t_end, 1))) return r;
       ran = c->macro_steps != before;
     }
     if (!ran) break;
@@ -1510,7 +1510,6 @@ int ader_adjoint_lts(ader_ctx* c, int32_t n_macro, int32_t keep_macro_steps, dou
     return fail(c, ADER_E_ORDER, "the LTS adjoint starts from an uploaded state with no step taken since");
   if (c->cfg.mesh_velocity != 0 && c->cfg.mesh_velocity != 1)
     return fail(c, ADER_E_ARG, "the LTS adjoint covers the mesh moving with the fluid and the fixed mesh");
-  if (c->cfg.lts_levels < 1) return fail(c, ADER_E_ARG, "the LTS adjoint needs dyadic levels (lts_levels >= 1)");
   if (c->dev.K != 1) return fail(c, ADER_E_ARG, "the LTS adjoint runs one instance");
   if (c->prm.flux != ADER_FLUX_RUSANOV && c->prm.flux != ADER_FLUX_HLL)
     return fail(c, ADER_E_ARG, "the LTS adjoint covers the Rusanov and HLL fluxes");

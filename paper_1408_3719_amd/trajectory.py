@@ -129,8 +129,9 @@ def lagrangian_trajectory(solver, Q0, X0, dt: float, n_steps: int, every: int = 
 
 
 def lts_trajectory(solver, Q0, X0, n_macro: int, t_end: float = 1e9, steps_per_element: int = 4096):
-    """(Q, X) after n_macro macro steps of the solver's dyadic local time
-    stepping (mesh moving with the fluid, or fixed) from (Q0 [4][NE], X0 (NV, 2)),
+    """(Q, X) after n_macro macro steps of the solver's local time stepping
+    (dyadic levels or free steps; mesh moving with the fluid, or fixed) from
+    (Q0 [4][NE], X0 (NV, 2)),
     differentiable with respect to both with the schedule held fixed.  The
     forward pass records every element's steps and every macro step's tick
     length (ader_set_schedule_record); the backward pass uploads (Q0, X0),
@@ -141,8 +142,6 @@ def lts_trajectory(solver, Q0, X0, n_macro: int, t_end: float = 1e9, steps_per_e
 
     if n_macro < 1:
         raise ValueError("n_macro must be positive")
-    if solver.cfg.levels < 1:
-        raise ValueError("lts_trajectory differentiates dyadic LTS macro steps (levels >= 1)")
 
     class _LTS(torch.autograd.Function):
         @staticmethod

@@ -116,8 +116,7 @@ def test_lts_adjoint_errors():
         g.adjoint_lts(1, 10.0, qb, xb)
     with pytest.raises(AderError, match="Rusanov and HLL"):
         _gpu(mesh, Q0, 3, "osher").adjoint_lts(1, 10.0, qb, xb)
-    with pytest.raises(AderError, match="dyadic levels"):
-        _gpu(mesh, Q0, 0, "rusanov").adjoint_lts(1, 10.0, qb, xb)
+
 
 
 def test_lts_gradient_of_the_adjoint_workload_against_central_differences():
@@ -253,3 +252,27 @@ def test_lts_adjoint_stops_at_the_target_time():
     assert abs(g.stats()["t"] - 1.5 * t1) <= 1e-12 * t1
     gq, gx = gq.cpu().numpy().T, gx.cpu().numpy()
     assert _rel(gq, ref_q) < TOL and _rel(gx, ref_x) < TOL
+
+
+@pytest.mark.parametrize("mode", ["lagrangian", "eulerian"])
+def test_lts_adjoint_with_free_steps(mode):
+    """Free local steps (levels = 0: one macro step to the target time, each
+    element at its own CFL step, reading of the paper's LTS) against the
+    reverse-mode oracle with the oracle's schedule replayed."""
+    mesh, Q0 = _case("vortex")
+    cfg = OConfig(M=2, levels=0, mesh_velocity=mode)
+    o = OSolver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+    sched = lts_schedule(o, 0.05, 1)
+    lt = LagrangianLTS(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+    rng = np.random.default_rng(13)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    ref_q, ref_x = lt.vjp(Q0, mesh.nodes, sched, qb, xb)
+    g = _gpu(mesh, Q0, 0, "rusanov", mode=mode)
+    g.set_schedule_replay(o.step_log)
+    gq, gx, done = g.adjoint_lts(1, 0.05, qb, xb)
+    assert done == 1 and abs(g.stats()["t"] - 0.05) <= 1e-14
+    gq, gx = gq.cpu().numpy().T, gx.cpu().numpy()
+    assert _rel(gq, ref_q) < TOL and _rel(gx, ref_x) < TOL
+    Q, X, _ = g.download()
+    assert _rel(Q, o.st.Q) < 1e-12 and np.abs(X - o.st.X).max() < 1e-12 * np.ptp(mesh.nodes)

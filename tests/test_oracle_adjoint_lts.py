@@ -34,14 +34,14 @@ def _setup(name, levels=3, n_macro=2, flux="rusanov", M=2, mode="lagrangian"):
     return mesh, Q0, cfg, o, sched, lt
 
 
-def _replay(mesh, cfg, topo, sched, Q, X):
+def _replay(mesh, cfg, topo, sched, Q, X, t_end=10.0):
     """The NumPy solver from (Q, X) taking the recorded steps and tick lengths."""
     steps = [sum((list(s[i]) for _, s in sched), []) for i in range(len(Q))]
     s = Solver(X, mesh.tris, Q, cfg, bedges=mesh.bedges, topo=topo)
     s.step_hook = lambda i, k, p: steps[i][k]
     s.delta_hook = lambda m: sched[m][0]
     for _ in sched:
-        s.macro_step(10.0)
+        s.macro_step(t_end)
     return s.st.Q, s.st.X
 
 
@@ -73,6 +73,34 @@ def test_lts_fixed_mesh_forward_and_central_differences(name):
     y = rng.standard_normal(mesh.nodes.shape) * np.ptp(mesh.nodes) * 1e-1
     Qp, Xp = _replay(mesh, cfg, o.topo, sched, Q0 + h * v, mesh.nodes + h * y)
     Qm, Xm = _replay(mesh, cfg, o.topo, sched, Q0 - h * v, mesh.nodes - h * y)
+    fd = (((Qp - Qm) * qb).sum() + ((Xp - Xm) * xb).sum()) / (2 * h)
+    ad = (gq * v).sum() + (gx * y).sum()
+    assert abs(fd - ad) <= 1e-6 * (np.abs(gq * v).sum() + np.abs(gx * y).sum()), (fd, ad)
+
+
+def test_lts_free_steps_forward_and_central_differences():
+    """Free local steps (levels = 0: one macro step of 2^30 ticks to the
+    target time, every element at its own CFL step): the forward equals the
+    NumPy solver, and the product matches central differences of the NumPy
+    solver replaying the schedule."""
+    mesh, Q0 = _case("vortex")
+    cfg = Config(M=2, levels=0, mesh_velocity="lagrangian")
+    o = Solver(mesh.nodes, mesh.tris, Q0, cfg, bedges=mesh.bedges)
+    sched = lts_schedule(o, 0.05, 1)
+    assert o.st.cycles > 4 and o.st.updates > len(Q0)       # elements at different steps
+    lt = LagrangianLTS(mesh.nodes, mesh.tris, cfg, bedges=mesh.bedges, topo=o.topo)
+    Q, X = lt.run(Q0, mesh.nodes, sched)
+    assert np.abs(Q - o.st.Q).max() <= 1e-14 * np.abs(o.st.Q).max()
+    assert np.abs(X - o.st.X).max() <= 1e-14 * np.abs(o.st.X).max()
+    rng = np.random.default_rng(5)
+    qb = rng.standard_normal(Q0.shape)
+    xb = rng.standard_normal(mesh.nodes.shape)
+    gq, gx = lt.vjp(Q0, mesh.nodes, sched, qb, xb)
+    h = 1e-8
+    v = rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=0)
+    y = rng.standard_normal(mesh.nodes.shape) * np.ptp(mesh.nodes) * 1e-1
+    Qp, Xp = _replay(mesh, cfg, o.topo, sched, Q0 + h * v, mesh.nodes + h * y, t_end=0.05)
+    Qm, Xm = _replay(mesh, cfg, o.topo, sched, Q0 - h * v, mesh.nodes - h * y, t_end=0.05)
     fd = (((Qp - Qm) * qb).sum() + ((Xp - Xm) * xb).sum()) / (2 * h)
     ad = (gq * v).sum() + (gx * y).sum()
     assert abs(fd - ad) <= 1e-6 * (np.abs(gq * v).sum() + np.abs(gx * y).sum()), (fd, ad)
