@@ -3,8 +3,8 @@
 levels at 30k triangles over two macro steps in the launch configuration the
 benchmark times (autotuned settings, captured graphs) and with persistent
 grids that stride the active list; the explosion at its full 400k triangles
-on sampled elements, and the timed configuration bit-identical to launches
-one by one there."""
+on sampled elements, at t = 0 and in a cycle in the middle of the run, and the
+timed configuration bit-identical to launches one by one there."""
 import os
 import sys
 
@@ -161,3 +161,103 @@ def test_explosion_full_size_sampled_parity_and_conservation():
     assert st_t["element_updates"] == st_e["element_updates"] == st["element_updates"]
     assert np.array_equal(Qt, Qe) and np.array_equal(Xt, Xe2) and np.array_equal(tt, te)
     assert np.array_equal(Qe, Q) and np.array_equal(Xe2, X)
+
+
+def test_explosion_full_size_mid_run_cycle_on_samples():
+    """The explosion workload at its full size (400k triangles, M=2, 4 levels)
+    in the middle of a run: one macro step, then the second macro step's
+    start and three cycles; the fourth cycle is checked on seeded samples,
+    each quantity recomputed by the oracle from the library's own state before
+    (S0) or after (S1) the cycle: node motion of moved nodes over their own
+    intervals (S0), the flux of every swept patch of elements not updated in
+    the cycle through their memory variables (S0 and the new node positions),
+    the reconstruction of updated elements from their stencils placed at their
+    new tick (S1), and the new predictors (S1)."""
+    from types import SimpleNamespace
+
+    from oracle.scheme import Config as OConfig
+    from oracle.scheme import (MACRO_TICKS, Solver, node_velocity, patch_batch, predictor_batch,
+                               reconstruct_batch)
+    from oracle.topology import build_edges, stencils_of
+    mesh, Q0 = explosion_case(400_000, seed=7)
+    NE, tris = mesh.n_elems, mesh.tris
+    print(f"explosion mesh {NE} triangles", flush=True)
+    cfg = OConfig(M=2, levels=4)
+    g = _gpu_solver(mesh, Q0, 2, 4)
+    g.step_lts(1.0, 1)
+    g.debug_macro_begin(1.0, 4)
+    g.debug_cycles(3)
+
+    def state():
+        return dict(Q=g.dump("Q").T.copy(), A=g.dump("A").copy(), Xe=g.dump("XE").T.reshape(NE, 3, 2).copy(),
+                    n=g.dump("TICK").astype(np.int64), s=g.dump("STEP").astype(np.int64),
+                    QM=g.dump("QM").T.copy(), wnod=np.transpose(g.dump("WNOD"), (2, 0, 1)).copy(),
+                    avg=np.transpose(g.dump("AVG"), (2, 0, 1)).copy(),
+                    trace=np.moveaxis(g.dump("TRACE"), -1, 0).copy(),
+                    vvel=np.moveaxis(g.dump("VVEL"), -1, 0).copy(), X=g.dump("X").T.copy(),
+                    nk=g.dump("NTICK").astype(np.int64))
+    S0 = state()
+    delta = float(g.dump("SCAL")[1])
+    g.debug_cycles(1)
+    S1 = state()
+    rng = np.random.default_rng(404)
+    act = np.nonzero(S1["n"] != S0["n"])[0]
+    moved = np.nonzero(S1["nk"] != S0["nk"])[0]
+    print(f"cycle: {act.size} updated, {moved.size} nodes moved", flush=True)
+    assert act.size > 1000 and moved.size > 1000
+    # node motion (eqs. eqn.dtau, NodesVel, eqnNScs, eqn.NScs.weights, eqn.newVertex)
+    kk = np.sort(rng.choice(moved, 500, replace=False))
+    dev = 0.0
+    for k in kk:
+        j, lv = np.nonzero(tris == k)
+        tau0 = (S0["nk"][k] - S0["n"][j]) / S0["s"][j]
+        tau1 = (S1["nk"][k] - S0["n"][j]) / S0["s"][j]
+        V = node_velocity(2, S0["vvel"][j, lv], tau0, tau1, S0["Q"][j, 0] * S0["A"][j])
+        x = S0["X"][k] + (S1["nk"][k] - S0["nk"][k]) * delta * V
+        dev = max(dev, np.abs(x - S1["X"][k]).max())
+    assert dev <= TOL * _span(mesh), dev
+    # swept patches through the memory variables of elements not updated
+    edge_nodes, edge_elems, edge_local, elem_edges = build_edges(tris)
+    is_moved = S1["nk"] != S0["nk"]
+    swept = is_moved[edge_nodes[:, 0]] | is_moved[edge_nodes[:, 1]]
+    idle = np.setdiff1d(np.nonzero(swept[elem_edges].any(axis=1))[0], act)
+    els = np.sort(rng.choice(idle, min(500, idle.size), replace=False))
+    es = np.unique(elem_edges[els][swept[elem_edges[els]]])
+    a, b = edge_nodes[es, 0], edge_nodes[es, 1]
+    L, R = edge_elems[es, 0], edge_elems[es, 1]
+    hasR = R >= 0
+    Rs = np.where(hasR, R, L)
+    ers = np.where(hasR, edge_local[es, 1], edge_local[es, 0])
+    P = np.stack([np.column_stack([S0["X"][a], S0["nk"][a] * delta]),
+                  np.column_stack([S0["X"][b], S0["nk"][b] * delta]),
+                  np.column_stack([S1["X"][b], S1["nk"][b] * delta]),
+                  np.column_stack([S1["X"][a], S1["nk"][a] * delta])], axis=1)
+    ticks = np.stack([S0["nk"][a], S0["nk"][b], S1["nk"][b], S1["nk"][a]], 1).astype(float)
+    bc = np.where(hasR, 0, 1)
+    G, _ = patch_batch(2, cfg, P, ticks, S0["n"][L], S0["s"][L], S0["trace"][L, edge_local[es, 0]],
+                       S0["n"][Rs], S0["s"][Rs], S0["trace"][Rs, ers], hasR, bc, S0["avg"][L])
+    dQM = np.zeros((NE, 4))
+    np.subtract.at(dQM, L, G)
+    np.add.at(dQM, R[hasR], G[hasR])
+    got = S1["QM"][els] - S0["QM"][els]
+    assert np.abs(got - dQM[els]).max() <= TOL * np.abs(S1["QM"][els]).max()
+    assert np.abs(got).max() > 0
+    # reconstruction of updated elements from their placed stencils
+    samp = np.sort(rng.choice(act, 1000, replace=False))
+    sten = stencils_of(mesh.nodes, tris, 2, samp)
+    valid = sten[:, :, 0] >= 0
+    ss = np.where(sten >= 0, sten, samp[:, None, None])
+    fake = SimpleNamespace(cfg=cfg, st=SimpleNamespace(n=S1["n"], s=S1["s"], delta=delta, Xe=S1["Xe"],
+                                                       vvel=S1["vvel"], avg=S1["avg"], Q=S1["Q"]))
+    Xs, Qs = Solver._virtual(fake, ss, np.broadcast_to(S1["n"][samp][:, None, None], ss.shape))
+    wnod_o, _, _, _ = reconstruct_batch(2, cfg, S1["Xe"][samp], S1["Q"][samp], Xs, Qs, valid)
+    assert rel(S1["wnod"][samp], wnod_o) < TOL
+    # the new predictors of the updated elements that stay short of the macro-step end
+    going = samp[S1["n"][samp] < MACRO_TICKS]
+    pr = predictor_batch(2, cfg, S1["wnod"][going], S1["Xe"][going], S1["s"][going] * delta,
+                         np.zeros(going.size))
+    assert rel(S1["trace"][going], pr["trace"]) < TOL
+    assert rel(S1["avg"][going], pr["avg"]) < TOL
+    assert rel(S1["vvel"][going], pr["vvel"]) < TOL
+    print(f"checked {kk.size} nodes, {es.size} patches of {els.size} elements, {samp.size} reconstructions, "
+          f"{going.size} predictors", flush=True)
