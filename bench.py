@@ -43,8 +43,9 @@ PEAK_HBM_GBS = 8000.0              # MI355X HBM3E, published
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in ("kernels.hip", "basis.h")]
 
 # HBM bytes per unit of work of the step kernels for each persistent-grid
-# setting of the list-driven kernels (workgroups per CU; 0 = one grid over all
-# elements): the rocprofv3 FETCH_SIZE and WRITE_SIZE of the profiled LTS pass's
+# setting (workgroups per CU; 0 = one grid over all items) of the list-driven
+# kernels (k_reconstruct, k_predict, k_update, k_sched) and of the node and
+# edge sweeps (k_node, k_patch): the rocprofv3 FETCH_SIZE and WRITE_SIZE of the profiled LTS pass's
 # launches on the 400k explosion mesh at M=2 (4 levels), scaled by what the
 # same counters read for a plain 256 MiB copy, divided by the units those
 # launches processed (element updates; patches; moved nodes; for the scheduler
@@ -54,12 +55,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in 
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
     "workload": "explosion",
-    "source_sha256": "7237b550ff26fd18436592740bb46bb4f542c46b17e632634fb5652f399443be",
-    "k_reconstruct": {0: 1727, 4: 1780, 8: 1751, 16: 1740, 32: 1733},
-    "k_predict": {0: 1502, 4: 1503, 8: 1502, 16: 1502, 32: 1502},
-    "k_patch": {0: 1046, 4: 1046, 8: 1047, 16: 1046, 32: 1047},
+    "source_sha256": "46357417cfe568bf5b680a6d40fd974f505fe5582b6aa68ceb511b1fd439c10d",
+    "k_reconstruct": {0: 1728, 4: 1778, 8: 1752, 16: 1737, 32: 1731},
+    "k_predict": {0: 1501, 4: 1502, 8: 1502, 16: 1501, 32: 1501},
+    "k_patch": {0: 1046, 4: 1073, 8: 1052, 16: 1046, 32: 1046},
     "k_update": {0: 735, 4: 737, 8: 735, 16: 735, 32: 735},
-    "k_node": {w: 1776 for w in TRAFFIC_SWEEP},
+    "k_node": {0: 1776, 4: 1776, 8: 1776, 16: 1775, 32: 1776},
     "k_sched": {w: 89 for w in TRAFFIC_SWEEP},
 }
 
@@ -805,7 +806,8 @@ def main():
     if a.free:
         f = Solver(mesh.nodes, mesh.tris, mesh.bedges, Q0, Config(M=a.M, levels=0, flux=a.flux))
         if tune:
-            f.set_tune(sched_chunk=tune["sched_chunk"], list_wg_per_cu=tune["list_wg_per_cu"])
+            f.set_tune(sched_chunk=tune["sched_chunk"], list_wg_per_cu=tune["list_wg_per_cu"],
+                       sweep_wg_per_cu=tune["sweep_wg_per_cu"])
         f.step_lts(T_a)
         f0 = f.stats()
         sync()
@@ -845,7 +847,8 @@ def main():
              "sched": "k_sched", "node": "k_node", "update": "k_update"}
 
     def traffic(kernel, units_per_launch):
-        per = MEASURED_TRAFFIC.get(kernel, {}).get(tune["list_wg_per_cu"] if tune else 0)
+        axis = "sweep_wg_per_cu" if kernel in ("k_node", "k_patch") else "list_wg_per_cu"
+        per = MEASURED_TRAFFIC.get(kernel, {}).get(tune[axis] if tune else 0)
         if (per is None or MEASURED_TRAFFIC["source_sha256"] != source_sha or a.M != 2
                 or MEASURED_TRAFFIC.get("workload") != a.workload or a.flux != "rusanov"):
             return None
@@ -874,10 +877,11 @@ def main():
 
     if a.traffic_sweep:
         # the profiled pass again for every persistent-grid setting of the
-        # list-driven kernels, in this order, one JSON line each (counter runs)
+        # list-driven kernels and the sweeps (both at the same setting), in
+        # this order, one JSON line each (counter runs)
         chunk = tune["sched_chunk"] if tune else 0
         for w in TRAFFIC_SWEEP:
-            s.set_tune(sched_chunk=chunk, list_wg_per_cu=w)
+            s.set_tune(sched_chunk=chunk, list_wg_per_cu=w, sweep_wg_per_cu=w)
             s.upload_state(Q0, 0.0)
             s.step_lts(t_end, a.warmup)
             q0 = s.stats()
@@ -893,7 +897,8 @@ def main():
                                         "node": q1["node_moves"] - q0["node_moves"]}}),
                   flush=True)
         if tune:
-            s.set_tune(sched_chunk=tune["sched_chunk"], list_wg_per_cu=tune["list_wg_per_cu"])
+            s.set_tune(sched_chunk=tune["sched_chunk"], list_wg_per_cu=tune["list_wg_per_cu"],
+                       sweep_wg_per_cu=tune["sweep_wg_per_cu"])
 
     if a.calib_copy_mib:
         n = a.calib_copy_mib * (1 << 20) // 8

@@ -185,13 +185,17 @@ int ader_step_lts(ader_ctx* ctx, double t_target, int32_t max_macro_steps, ader_
 int ader_instance_times(ader_ctx* ctx, int32_t n, double* T_host);
 
 /* Launch choices that leave every result bit-identical: elements per
- * workgroup of the scheduler (0: built-in rule) and workgroups per CU of the
+ * workgroup of the scheduler (0: built-in rule), workgroups per CU of the
  * reconstruction and predictor launches over the active list (0: one grid
- * covering every element). */
+ * covering every element), and workgroups per CU of the node and patch
+ * launches that sweep every node and edge (0: one grid over all of them;
+ * else a persistent grid whose workgroups stride them). */
 typedef struct {
   int32_t sched_chunk;        /* 0 or 32..1024 */
   int32_t list_wg_per_cu;     /* 0 or 1..64    */
   double ms_per_macro_step;   /* ader_autotune: time of the chosen setting     */
+  int32_t sweep_wg_per_cu;    /* 0 or 1..64    */
+  int32_t reserved;           /* 0             */
 } ader_tune;
 
 /* Set the launch choices explicitly. */
@@ -201,8 +205,9 @@ int ader_set_tune(ader_ctx* ctx, const ader_tune* tune);
  * `trial_macro_steps` LTS macro steps (levels of the configuration, 3 under
  * free steps; no target time) for each candidate setting, one coordinate at a
  * time (scheduler chunk in {rule, 64, 128, 256, 512, 1024}, then workgroups
- * per CU in {all, 4, 8, 16, 32}), keeps the fastest, and restores the state, so the simulation does
- * not advance.  Allocates a device copy of the workspace for the duration
+ * per CU of the list launches in {all, 4, 8, 16, 32}, then of the node and
+ * edge sweeps in {all, 4, 8, 16}), keeps the fastest, and restores the state,
+ * so the simulation does not advance.  Allocates a device copy of the workspace for the duration
  * (hipMalloc).  The choice is written to *chosen when not null. */
 int ader_autotune(ader_ctx* ctx, int32_t trial_macro_steps, ader_tune* chosen);
 

@@ -46,7 +46,8 @@ class AderConfig(ctypes.Structure):
 
 class AderTune(ctypes.Structure):
     _fields_ = [("sched_chunk", ctypes.c_int32), ("list_wg_per_cu", ctypes.c_int32),
-                ("ms_per_macro_step", ctypes.c_double)]
+                ("ms_per_macro_step", ctypes.c_double), ("sweep_wg_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class AderStats(ctypes.Structure):

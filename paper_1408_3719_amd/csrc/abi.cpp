@@ -1010,8 +1010,10 @@ int ader_set_tune(ader_ctx* c, const ader_tune* t) {
   if (!c || !t) return ADER_E_ARG;
   if (t->sched_chunk != 0 && (t->sched_chunk < 32 || t->sched_chunk > 1024)) return ADER_E_ARG;
   if (t->list_wg_per_cu < 0 || t->list_wg_per_cu > 64) return ADER_E_ARG;
+  if (t->sweep_wg_per_cu < 0 || t->sweep_wg_per_cu > 64) return ADER_E_ARG;
   c->dev.sched_chunk = t->sched_chunk;
   c->dev.list_wg_per_cu = t->list_wg_per_cu;
+  c->dev.sweep_wg_per_cu = t->sweep_wg_per_cu;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   drop_graphs(c);
   return ADER_OK;
@@ -1071,11 +1073,13 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
     }
     const int chunks[] = {0, 64, 128, 256, 512, 1024};
     const int wgs[] = {0, 4, 8, 16, 32};
+    const int sweeps[] = {0, 4, 8, 16};
     double best = 1e300, ms = 0.0;
-    int bc = c->dev.sched_chunk, bw = c->dev.list_wg_per_cu;
+    int bc = c->dev.sched_chunk, bw = c->dev.list_wg_per_cu, bs = c->dev.sweep_wg_per_cu;
     for (int ch : chunks) {
       c->dev.sched_chunk = ch;
       c->dev.list_wg_per_cu = bw;
+      c->dev.sweep_wg_per_cu = bs;
       if ((r = trial(ms))) break;
       if (ms < best) best = ms, bc = ch;
     }
@@ -1087,8 +1091,16 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
       if (ms < best) best = ms, bw = w;
     }
     if (r) break;
+    for (int w : sweeps) {
+      c->dev.list_wg_per_cu = bw;
+      c->dev.sweep_wg_per_cu = w;
+      if ((r = trial(ms))) break;
+      if (ms < best) best = ms, bs = w;
+    }
+    if (r) break;
     c->dev.sched_chunk = bc;
     c->dev.list_wg_per_cu = bw;
+    c->dev.sweep_wg_per_cu = bs;
     if ((r = restore())) break;
     if ((he = hipStreamSynchronize(c->stream)) != hipSuccess) {
       r = hip_fail(c, int(he), "hipStreamSynchronize");
@@ -1098,6 +1110,8 @@ int ader_autotune(ader_ctx* c, int32_t trials, ader_tune* chosen) {
     if (chosen) {
       chosen->sched_chunk = bc;
       chosen->list_wg_per_cu = bw;
+      chosen->sweep_wg_per_cu = bs;
+      chosen->reserved = 0;
       chosen->ms_per_macro_step = best;
     }
   } while (false);

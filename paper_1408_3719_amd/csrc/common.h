@@ -128,6 +128,9 @@ struct Dev {
   // workgroup, and workgroups per CU of the list-driven reconstruction and
   // predictor launches (0: one workgroup per slice of the whole element range)
   int sched_chunk, list_wg_per_cu, n_cu;
+  // workgroups per CU of the node and patch launches, which sweep every node
+  // and edge (0: one grid over all of them; else a persistent grid striding them)
+  int sweep_wg_per_cu;
   int free_steps;   // 1: free local steps (one macro step of FREE_TICKS to the target)
   Scal* scal;
   Inst* inst;                        // [K]

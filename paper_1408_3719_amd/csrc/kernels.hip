@@ -1640,13 +1640,24 @@ int launch_sched(const Dev& d, void* s) {
 // The update kernel runs over the cycle's active list, whose length only the
 // device knows: a grid sized for every element (or the persistent grid of the
 // launch settings), blocks beyond the list exit at once.
+static int sweep_grid(const Dev& d, long n) {
+  long b = (n + TPB - 1) / TPB;
+  if (d.sweep_wg_per_cu > 0) {
+    const long cap = long(d.sweep_wg_per_cu) * (d.n_cu > 0 ? d.n_cu : 256);
+    if (b > cap) b = cap;
+  }
+  if (b < 1) b = 1;
+  if (b > 16384) b = 16384;
+  return int(b);
+}
+
 int launch_node(const Dev& d, const Params& p, int M, void* s) {
-  AW_DISPATCH(M, AW_LAUNCH(k_node<MM>, d.NV, s, d, d.tab, p));
+  AW_DISPATCH(M, AW_LAUNCH_G(k_node<MM>, sweep_grid(d, d.NV), s, d, d.tab, p));
   return 0;
 }
 
 int launch_patch(const Dev& d, const Params& p, int M, void* s) {
-  AW_DISPATCH(M, AW_LAUNCH(k_patch<MM>, d.NF, s, d, d.tab, p));
+  AW_DISPATCH(M, AW_LAUNCH_G(k_patch<MM>, sweep_grid(d, d.NF), s, d, d.tab, p));
   return 0;
 }
 

@@ -366,10 +366,10 @@ class Solver(_Base):
         and keep the fastest; returns the choice."""
         t = _lib.AderTune()
         _check(self.lib, self.ctx, self.lib.ader_autotune(self.ctx, trial_macro_steps, ctypes.byref(t)))
-        return {f: getattr(t, f) for f, _ in _lib.AderTune._fields_}
+        return {f: getattr(t, f) for f, _ in _lib.AderTune._fields_ if f != "reserved"}
 
-    def set_tune(self, sched_chunk: int = 0, list_wg_per_cu: int = 0):
-        t = _lib.AderTune(sched_chunk, list_wg_per_cu, 0.0)
+    def set_tune(self, sched_chunk: int = 0, list_wg_per_cu: int = 0, sweep_wg_per_cu: int = 0):
+        t = _lib.AderTune(sched_chunk, list_wg_per_cu, 0.0, sweep_wg_per_cu, 0)
         _check(self.lib, self.ctx, self.lib.ader_set_tune(self.ctx, ctypes.byref(t)))
 
     def instance_times(self):

@@ -147,11 +147,12 @@ def test_explosion_full_size_sampled_parity_and_conservation():
     assert st["max_gcl_residual"] < 1e-12
     assert st["element_updates"] < 2 * 8 * NE
     # the timed configuration at full size: persistent grids of one workgroup
-    # per CU (the active lists are ~8x one pass), captured graphs, against
-    # default settings launched one by one: bit-identical
+    # per CU (the active lists are ~8x one pass, the node and edge sweeps
+    # ~4x and ~18x), captured graphs, against default settings launched one
+    # by one: bit-identical
     del g
     tg = _gpu_solver(mesh, Q0, 2, 4)
-    tg.set_tune(sched_chunk=256, list_wg_per_cu=1)
+    tg.set_tune(sched_chunk=256, list_wg_per_cu=1, sweep_wg_per_cu=1)
     eg = _gpu_solver(mesh, Q0, 2, 4)
     eg.set_graphs(False)
     st_t, st_e = tg.step_lts(1.0, 2), eg.step_lts(1.0, 2)

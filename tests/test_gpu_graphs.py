@@ -72,8 +72,8 @@ def test_autotune_keeps_state_and_results():
     for f in COUNTERS + ("t",):
         assert sa[f] == sb[f], f
     # explicit extreme settings as well
-    b.set_tune(sched_chunk=32, list_wg_per_cu=1)
-    a.set_tune(sched_chunk=1024, list_wg_per_cu=64)
+    b.set_tune(sched_chunk=32, list_wg_per_cu=1, sweep_wg_per_cu=1)
+    a.set_tune(sched_chunk=1024, list_wg_per_cu=64, sweep_wg_per_cu=64)
     a.step_lts(10.0, 2), b.step_lts(10.0, 2)
     assert _same(a, b)
 
