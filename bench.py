@@ -55,13 +55,13 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in 
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
     "workload": "explosion",
-    "source_sha256": "46357417cfe568bf5b680a6d40fd974f505fe5582b6aa68ceb511b1fd439c10d",
-    "k_reconstruct": {0: 1728, 4: 1778, 8: 1752, 16: 1737, 32: 1731},
-    "k_predict": {0: 1501, 4: 1502, 8: 1502, 16: 1501, 32: 1501},
-    "k_patch": {0: 1046, 4: 1073, 8: 1052, 16: 1046, 32: 1046},
-    "k_update": {0: 735, 4: 737, 8: 735, 16: 735, 32: 735},
+    "source_sha256": "204977192aed5a1a41e47034d5746c3a4eb3caa450e85016419ca3b1757a3cc5",
+    "k_reconstruct": {0: 1715, 4: 1772, 8: 1750, 16: 1732, 32: 1719},
+    "k_predict": {0: 1500, 4: 1501, 8: 1501, 16: 1501, 32: 1501},
+    "k_patch": {0: 1047, 4: 1074, 8: 1053, 16: 1047, 32: 1047},
+    "k_update": {0: 734, 4: 735, 8: 733, 16: 733, 32: 733},
     "k_node": {0: 1776, 4: 1776, 8: 1776, 16: 1775, 32: 1776},
-    "k_sched": {w: 89 for w in TRAFFIC_SWEEP},
+    "k_sched": {w: 88 for w in TRAFFIC_SWEEP},
 }
 
 

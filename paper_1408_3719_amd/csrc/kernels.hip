@@ -954,29 +954,58 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
   __syncthreads();
   const int begin = xcd_block() * chunk;
   const int end = min(NE, begin + chunk);
+  // The element's own tick and the bounds of its stencil are loaded one pass
+  // ahead, and a lane's first SCAN_U stencil entries (of ~80 at M=2) are
+  // gathered together, so that a pass waits on two dependent loads (stencil
+  // index, then tick) instead of one such pair per 32 entries.
+  constexpr int SCAN_U = 12;
+  auto head = [&](int i, TickStep& me, int& r0, int& r1) {
+    me = i < end ? d.ts[i] : TickStep{N, 0};
+    r0 = r1 = 0;
+    if (me.tick < N) {
+      r0 = d.sched_ptr[i];
+      r1 = d.sched_ptr[i + 1];
+    }
+  };
+  TickStep me_n;
+  int r0_n, r1_n;
+  head(begin + (threadIdx.x >> 3), me_n, r0_n, r1_n);
   for (int base = begin; base < end; base += PER_PASS) {
     const int i = base + (threadIdx.x >> 3);
+    const TickStep me = me_n;
+    const int r0 = r0_n, r1 = r1_n;
+    if (base + PER_PASS < end) head(base + PER_PASS + (threadIdx.x >> 3), me_n, r0_n, r1_n);
     int fut = 0, mx = 0, mn = FREE_TICKS;   // no tick count exceeds FREE_TICKS
     bool unf = false;
-    if (i < end) {
-      const TickStep me = d.ts[i];
-      if (me.tick < N) {
-        unf = true;
-        fut = me.tick + me.step;
-        const int r1 = d.sched_ptr[i + 1];
-        // four entries per lane in flight before any is used
-        for (int r = d.sched_ptr[i] + sub; r < r1; r += 32) {
-          int jx[4];
+    if (i < end && me.tick < N) {
+      unf = true;
+      fut = me.tick + me.step;
+      int jx[SCAN_U];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) jx[u] = r + 8 * u < r1 ? d.sched_idx[r + 8 * u] : -1;
-          TickStep o[4];
+      for (int u = 0; u < SCAN_U; ++u) {
+        const int r = r0 + sub + 8 * u;
+        jx[u] = r < r1 ? d.sched_idx[r] : -1;
+      }
+      TickStep o[SCAN_U];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) o[u] = jx[u] >= 0 ? d.ts[jx[u]] : TickStep{0, FREE_TICKS};
+      for (int u = 0; u < SCAN_U; ++u) o[u] = jx[u] >= 0 ? d.ts[jx[u]] : TickStep{0, FREE_TICKS};
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            mx = max(mx, o[u].tick);
-            mn = min(mn, o[u].tick + o[u].step);
-          }
+      for (int u = 0; u < SCAN_U; ++u) {
+        mx = max(mx, o[u].tick);
+        mn = min(mn, o[u].tick + o[u].step);
+      }
+      // longer stencils: the rest four entries per lane at a time
+      for (int r = r0 + 8 * SCAN_U + sub; r < r1; r += 32) {
+        int jy[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) jy[u] = r + 8 * u < r1 ? d.sched_idx[r + 8 * u] : -1;
+        TickStep o4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) o4[u] = jy[u] >= 0 ? d.ts[jy[u]] : TickStep{0, FREE_TICKS};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          mx = max(mx, o4[u].tick);
+          mn = min(mn, o4[u].tick + o4[u].step);
         }
       }
     }
