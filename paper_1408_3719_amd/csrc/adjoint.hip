@@ -279,6 +279,23 @@ __device__ inline double group8_sum(double v) {
   return v;
 }
 
+// The same sum with the lane moves done by DPP inside the VALU (no LDS round
+// trip); each step adds two equal partial sums, so the bits are those of
+// group8_sum. Every lane of the 8-lane group must be active.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ inline double group8_sum_dpp(double v) {
+  v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);   // row_half_mirror: lane i <-> 7 - i within 8
+  return v;
+}
+
 // Row of the least-squares system for stencil element j seen from element i:
 // the means over T_j, mapped into the reference frame of T_i (vertices Xi,
 // inverse edge matrix through e1, e2, idet), of the monomials shifted by their
@@ -2028,12 +2045,39 @@ __global__ void __launch_bounds__(TPB) k_lts_gather(Dev d, const Tables* __restr
 #pragma unroll
       for (int k = 0; k < 10; ++k) acc[k] += r[k];
     }
+    bool touched = (fj & 1) != 0;
     const TickStep tj = lw.s1.ts[j];
-    const int k1 = d.tsten_ptr[j + 1];
-    for (int k = d.tsten_ptr[j] + sl; k < k1; k += 8) {
-      const int slot = d.tsten_idx[k];
+    const int k0 = d.tsten_ptr[j], k1 = d.tsten_ptr[j + 1];
+    // a lane's first GU entries (of ~80 per element at M=2) and their
+    // elements' flags are loaded together; the rows of the updated ones follow
+    constexpr int GU = 12;
+    int gslot[GU], gflag[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int k = k0 + sl + 8 * u;
+      gslot[u] = k < k1 ? d.tsten_idx[k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) gflag[u] = gslot[u] >= 0 ? lw.eflag[gslot[u] / (ne * 8)] : 0;
+    for (int k = k0 + sl, u = 0; k < k1; k += 8, ++u) {
+      int slot, fi;
+      if (u < GU) {
+        // constant-index selects keep the batch in registers
+        slot = gslot[0];
+        fi = gflag[0];
+#pragma unroll
+        for (int q = 1; q < GU; ++q)
+          if (u == q) {
+            slot = gslot[q];
+            fi = gflag[q];
+          }
+      } else {
+        slot = d.tsten_idx[k];
+        fi = lw.eflag[slot / (ne * 8)];
+      }
+      if (!(fi & 1)) continue;
+      touched = true;
       const int i = slot / (ne * 8);
-      if (!(lw.eflag[i] & 1)) continue;
       const double* r = rowbar + size_t(slot) * 10;
       double rv[10];
 #pragma unroll
@@ -2059,8 +2103,12 @@ __global__ void __launch_bounds__(TPB) k_lts_gather(Dev d, const Tables* __restr
         }
       }
     }
+    // an element that no updated element's stencil names (and not updated
+    // itself) receives nothing: its 8 lanes skip the sums and the writes
+    const unsigned long long tmask = __ballot(touched);
+    if (((tmask >> (__lane_id() & 56)) & 0xffull) == 0ull) continue;
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) acc[k] = group8_sum(acc[k]);
+    for (int k = 0; k < NACC; ++k) acc[k] = group8_sum_dpp(acc[k]);
 #pragma unroll
     for (int k = 0; k < NACC; ++k) {
       if ((k & 7) != sl) continue;
