@@ -55,12 +55,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in 
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
     "workload": "explosion",
-    "source_sha256": "204977192aed5a1a41e47034d5746c3a4eb3caa450e85016419ca3b1757a3cc5",
-    "k_reconstruct": {0: 1715, 4: 1772, 8: 1750, 16: 1732, 32: 1719},
-    "k_predict": {0: 1500, 4: 1501, 8: 1501, 16: 1501, 32: 1501},
-    "k_patch": {0: 1047, 4: 1074, 8: 1053, 16: 1047, 32: 1047},
-    "k_update": {0: 734, 4: 735, 8: 733, 16: 733, 32: 733},
-    "k_node": {0: 1776, 4: 1776, 8: 1776, 16: 1775, 32: 1776},
+    "source_sha256": "937aac397ce7f29ab3f0706f4b9ccaec5a8b6d5739234da8a99013e69ca6e079",
+    "k_reconstruct": {0: 1713, 4: 1775, 8: 1747, 16: 1727, 32: 1720},
+    "k_predict": {0: 1499, 4: 1500, 8: 1500, 16: 1499, 32: 1499},
+    "k_patch": {0: 1047, 4: 1073, 8: 1053, 16: 1046, 32: 1047},
+    "k_update": {0: 731, 4: 733, 8: 732, 16: 731, 32: 731},
+    "k_node": {0: 1776, 4: 1776, 8: 1777, 16: 1776, 32: 1776},
     "k_sched": {w: 88 for w in TRAFFIC_SWEEP},
 }
 

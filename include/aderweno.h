@@ -442,8 +442,10 @@ int ader_debug_inject(ader_ctx* ctx, int32_t what, const void* host, size_t byte
 int ader_debug_cycles(ader_ctx* ctx, int32_t n);
 int ader_debug_macro_begin(ader_ctx* ctx, double t_end, int32_t levels);
 
-/* Per-kernel timing for benchmarks: HIP events recorded around every kernel
- * launch on the context's stream.  ader_set_profiling(ctx, 1) clears the
+/* Per-kernel timing for benchmarks: a stage of one kernel launch is timed by
+ * start and stop events attached to that launch (the kernel's own execution);
+ * a stage of several launches (macro-step boundary, status, adjoint) by HIP
+ * events recorded before and after it on the context's stream.  ader_set_profiling(ctx, 1) clears the
  * totals and starts recording, 0 stops.  ader_kernel_times synchronises and
  * writes, for each kernel id k < n (ADER_K_*), the summed milliseconds and
  * the number of launches since profiling was switched on. */

@@ -172,18 +172,28 @@ void flush_events(ader_ctx* c) {
   }
 }
 
+// Under profiling, a stage of one grid launch is timed by that kernel's own
+// start and end (events attached to the launch); a stage of several launches
+// by events recorded before and after it on the stream.
 template <class F>
 int timed(ader_ctx* c, int k, hipStream_t st, F launch) {
+  if (!c->prof) return launch();
   hipEvent_t a = nullptr, b = nullptr;
-  if (c->prof) {
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return int(hipErrorOutOfMemory);
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return int(hipErrorOutOfMemory);
+  const bool one = k != ADER_K_MACRO && k != ADER_K_STATUS && k != ADER_K_ADJOINT;
+  if (one)
+    aw::set_next_launch_events(a, b);
+  else
     (void)hipEventRecord(a, st);
-  }
-  int r = launch();
-  if (c->prof) {
+  const int r = launch();
+  if (!one) {
     (void)hipEventRecord(b, st);
-    c->ev[k].push_back({a, b});
+  } else if (aw::next_launch_events_pending()) {   // no grid launch took them
+    aw::set_next_launch_events(nullptr, nullptr);
+    (void)hipEventRecord(a, st);
+    (void)hipEventRecord(b, st);
   }
+  c->ev[k].push_back({a, b});
   return r;
 }
 

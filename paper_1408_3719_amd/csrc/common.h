@@ -316,6 +316,10 @@ int launch_macro_begin(const Dev& d, int N, int nominal, double fraction, void* 
 int launch_set_target(const Dev& d, double t_end, void* stream);
 int launch_cycle_begin(const Dev& d, void* stream);
 int launch_sched(const Dev& d, void* stream);
+// Start and stop events (hipEvent_t) for the next grid launch of this host
+// thread: its timestamps are the kernel's own start and end.
+void set_next_launch_events(void* start, void* stop);
+bool next_launch_events_pending();
 int launch_node(const Dev& d, const Params& p, int M, void* stream);
 int launch_patch(const Dev& d, const Params& p, int M, void* stream);
 int launch_update(const Dev& d, const Params& p, void* stream);

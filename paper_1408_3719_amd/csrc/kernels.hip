@@ -34,6 +34,7 @@
 //   others:        one lane per node, edge or element.
 // Blocks are renumbered so that each XCD works on a contiguous index range.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cfloat>
 
@@ -1575,11 +1576,23 @@ int grid_for(long n) {
   return int(b);
 }
 
-#define AW_LAUNCH_G(kern, grid, stream, ...)                                                \
-  do {                                                                                      \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(TPB), 0, (hipStream_t)(stream), __VA_ARGS__); \
-    hipError_t _e = hipGetLastError();                                                      \
-    if (_e != hipSuccess) return int(_e);                                                   \
+// Start and stop events for the next grid launch (per-kernel timing): that
+// launch then takes its two timestamps from the kernel's own execution rather
+// than from markers queued before and after it.
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+#define AW_LAUNCH_G(kern, grid, stream, ...)                                                        \
+  do {                                                                                              \
+    if (t_ev_start) {                                                                               \
+      hipEvent_t _a = t_ev_start, _b = t_ev_stop;                                                   \
+      t_ev_start = t_ev_stop = nullptr;                                                             \
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(TPB), 0, (hipStream_t)(stream), _a, _b, 0,       \
+                            __VA_ARGS__);                                                           \
+    } else {                                                                                        \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(TPB), 0, (hipStream_t)(stream), __VA_ARGS__);       \
+    }                                                                                               \
+    hipError_t _e = hipGetLastError();                                                              \
+    if (_e != hipSuccess) return int(_e);                                                           \
   } while (0)
 
 #define AW_LAUNCH(kern, n, stream, ...) AW_LAUNCH_G(kern, grid_for(n), stream, __VA_ARGS__)
@@ -1600,6 +1613,12 @@ int grid_for(long n) {
   }
 
 }  // namespace
+
+void set_next_launch_events(void* start, void* stop) {
+  t_ev_start = static_cast<hipEvent_t>(start);
+  t_ev_stop = static_cast<hipEvent_t>(stop);
+}
+bool next_launch_events_pending() { return t_ev_start != nullptr; }
 
 int launch_init_geometry(const Dev& d, void* s) {
   int n = d.NE > d.NV ? d.NE : d.NV;
@@ -1666,9 +1685,9 @@ int launch_sched(const Dev& d, void* s) {
   return 0;
 }
 
-// The update kernel runs over the cycle's active list, whose length only the
-// device knows: a grid sized for every element (or the persistent grid of the
-// launch settings), blocks beyond the list exit at once.
+// Grid of a launch that sweeps every node or edge: one lane per item, or the
+// persistent grid of the launch settings (workgroups per CU), whose
+// workgroups stride the items.
 static int sweep_grid(const Dev& d, long n) {
   long b = (n + TPB - 1) / TPB;
   if (d.sweep_wg_per_cu > 0) {
@@ -1690,6 +1709,9 @@ int launch_patch(const Dev& d, const Params& p, int M, void* s) {
   return 0;
 }
 
+// The update kernel runs over the cycle's active list, whose length only the
+// device knows: a grid sized for every element (or the persistent grid of the
+// launch settings), blocks beyond the list exit at once.
 int launch_update(const Dev& d, const Params& p, void* s) {
   const int g = list_grid(d, (long(d.NE) + TPB - 1) / TPB, 1);
   AW_DISPATCH(d.M, AW_LAUNCH_G(k_update<MM>, g, s, d, p));
