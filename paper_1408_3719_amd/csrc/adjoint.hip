@@ -2227,24 +2227,75 @@ template <int M>
 __global__ void __launch_bounds__(TPB) k_lts_node_rev(Dev d, const Tables* __restrict__ tb, LtsWork lw) {
   using S = AZ<M>;
   constexpr int T = M + 1, VV = rec_off_vv(M);
-  const int NV = d.NV;
+  const int NV = d.NV, NE = d.NE;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
     double xn[2] = {lw.xb[2 * k], lw.xb[2 * k + 1]};
-    for (int r = d.ring_ptr[k]; r < d.ring_ptr[k + 1]; ++r) {
-      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
-      if (lw.eflag[j] & 1) {
-        xn[0] += lw.g.xnbe[size_t(j) * 6 + 2 * lv];
-        xn[1] += lw.g.xnbe[size_t(j) * 6 + 2 * lv + 1];
-      }
-    }
     double xo[2] = {0.0, 0.0};
-    node_edges(d, k, [&](int e, int isb) {
-      if (!lw.nflag[d.e_a[e]] && !lw.nflag[d.e_b[e]]) return;
+    const int r0 = d.ring_ptr[k], r1 = d.ring_ptr[k + 1];
+    const int fk = lw.nflag[k];
+    // the ring element's corner slots (new vertex), then the edges leaving
+    // this node in that element (local edges lv and lv + 2, whose L side
+    // holds the edge's corner adjoints; an edge is swept when one of its two
+    // nodes moved), in ring order; the first RING_U entries' indices and flags
+    // are loaded together
+    auto corner = [&](int j, int lv) {
+      xn[0] += lw.g.xnbe[size_t(j) * 6 + 2 * lv];
+      xn[1] += lw.g.xnbe[size_t(j) * 6 + 2 * lv + 1];
+    };
+    auto edge_end = [&](int e, int isb) {
       xn[0] += lw.g.xs[size_t(e) * 8 + 4 + 2 * isb];
       xn[1] += lw.g.xs[size_t(e) * 8 + 5 + 2 * isb];
       xo[0] += lw.g.xs[size_t(e) * 8 + 2 * isb];
       xo[1] += lw.g.xs[size_t(e) * 8 + 1 + 2 * isb];
-    });
+    };
+    constexpr int RING_U = 8;
+    int ent[RING_U], ef[RING_U], ea[RING_U], eb[RING_U], oa[RING_U], ob[RING_U];
+#pragma unroll
+    for (int u = 0; u < RING_U; ++u) ent[u] = r0 + u < r1 ? d.ring_ent[r0 + u] : -1;
+#pragma unroll
+    for (int u = 0; u < RING_U; ++u) {
+      ef[u] = ea[u] = eb[u] = oa[u] = ob[u] = 0;
+      if (ent[u] >= 0) {
+        const int j = ent[u] >> 2, lv = ent[u] & 3, l1 = lv == 2 ? 0 : lv + 1, l2 = lv == 0 ? 2 : lv - 1;
+        ef[u] = lw.eflag[j];
+        ea[u] = d.elem_edges[lv * NE + j];
+        eb[u] = d.elem_edges[l2 * NE + j];
+        oa[u] = d.tri[l1 * NE + j];
+        ob[u] = d.tri[l2 * NE + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RING_U; ++u)
+      if (ent[u] >= 0 && (ef[u] & 1)) corner(ent[u] >> 2, ent[u] & 3);
+    for (int r = r0 + RING_U; r < r1; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      if (lw.eflag[j] & 1) corner(j, lv);
+    }
+    int la[RING_U], lb[RING_U], fa[RING_U], fb[RING_U];
+#pragma unroll
+    for (int u = 0; u < RING_U; ++u) {
+      la[u] = lb[u] = -1;
+      fa[u] = fb[u] = 0;
+      if (ent[u] >= 0) {
+        la[u] = d.e_L[ea[u]];
+        lb[u] = d.e_L[eb[u]];
+        fa[u] = fk | lw.nflag[oa[u]];
+        fb[u] = fk | lw.nflag[ob[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RING_U; ++u) {
+      if (ent[u] < 0) continue;
+      const int j = ent[u] >> 2;
+      if (la[u] == j && fa[u]) edge_end(ea[u], 0);
+      if (lb[u] == j && fb[u]) edge_end(eb[u], 1);
+    }
+    for (int r = r0 + RING_U; r < r1; ++r) {
+      const int j = d.ring_ent[r] >> 2, lv = d.ring_ent[r] & 3;
+      const int e1 = d.elem_edges[lv * NE + j], e2 = d.elem_edges[((lv + 2) % 3) * NE + j];
+      if (d.e_L[e1] == j && (lw.nflag[d.e_a[e1]] || lw.nflag[d.e_b[e1]])) edge_end(e1, 0);
+      if (d.e_L[e2] == j && (lw.nflag[d.e_a[e2]] || lw.nflag[d.e_b[e2]])) edge_end(e2, 1);
+    }
     lw.xb[2 * k] = xn[0] + xo[0];
     lw.xb[2 * k + 1] = xn[1] + xo[1];
     if (!lw.nflag[k]) continue;
