@@ -2,8 +2,9 @@
 nonlinear WENO weights (eqs. weights, weno), the mass weights and time
 averages of the node solver (eqs. eqnNScs, eqn.NScs.weights, NodesVel), the
 time interpolation of non-constant predictor data under local time stepping
-(eqs. eqn.virtGeom, eqn.virtCellaverage, eqn.spacetimenodes, eqn.Qm2), and the
-design order of accuracy on a smooth flow (Sec. 3.1)."""
+(eqs. eqn.virtGeom, eqn.virtCellaverage, eqn.spacetimenodes, eqn.Qm2). The
+design order of accuracy on a smooth flow (Sec. 3.1) is pinned by
+test_oracle_scheme.py::test_vortex_convergence_order."""
 import math
 
 import numpy as np
