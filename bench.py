@@ -55,12 +55,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in 
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
     "workload": "explosion",
-    "source_sha256": "937aac397ce7f29ab3f0706f4b9ccaec5a8b6d5739234da8a99013e69ca6e079",
-    "k_reconstruct": {0: 1713, 4: 1775, 8: 1747, 16: 1727, 32: 1720},
-    "k_predict": {0: 1499, 4: 1500, 8: 1500, 16: 1499, 32: 1499},
-    "k_patch": {0: 1047, 4: 1073, 8: 1053, 16: 1046, 32: 1047},
-    "k_update": {0: 731, 4: 733, 8: 732, 16: 731, 32: 731},
-    "k_node": {0: 1776, 4: 1776, 8: 1777, 16: 1776, 32: 1776},
+    "source_sha256": "42297c306aff194ee9474217a410ef05cb3a2eb46fb64e2383c39661a72ef1b4",
+    "k_reconstruct": {0: 1713, 4: 1774, 8: 1746, 16: 1727, 32: 1720},
+    "k_predict": {0: 1504, 4: 1506, 8: 1506, 16: 1505, 32: 1505},
+    "k_patch": {0: 1042, 4: 1071, 8: 1049, 16: 1041, 32: 1042},
+    "k_update": {0: 734, 4: 735, 8: 734, 16: 734, 32: 733},
+    "k_node": {0: 1774, 4: 1775, 8: 1775, 16: 1775, 32: 1775},
     "k_sched": {w: 88 for w in TRAFFIC_SWEEP},
 }
 

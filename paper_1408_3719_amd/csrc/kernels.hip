@@ -75,14 +75,37 @@ __device__ inline double node_delta(const Dev& d, int k) {
   return d.K == 1 ? d.inst[0].delta : d.inst[d.v_inst[k]].delta;
 }
 
-// count the calling lanes of the wavefront with one atomic
-__device__ inline void wave_count(unsigned long long* ctr) {
-  unsigned long long m = __ballot(1);
-  if ((int)__lane_id() == __ffsll((long long)m) - 1) atomicAdd(ctr, (unsigned long long)__popcll(m));
-}
-
+// atomic maximum of a non-negative double through its bit pattern
 __device__ inline void atomic_max_pos(unsigned long long* a, double v) {
   atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+// Workgroup totals for the statistics counters: one atomic per workgroup
+// instead of one per wavefront (atomics on one address serialise, ~12 ns
+// each). Every thread of the workgroup calls them, once per kernel.
+__device__ inline void block_add(unsigned long long* ctr, unsigned long long v) {
+  __shared__ unsigned long long part_add[TPB / 64];
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) v += __shfl_xor(v, s);
+  if (__lane_id() == 0) part_add[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < int(blockDim.x / 64); ++w) t += part_add[w];
+    if (t) atomicAdd(ctr, t);
+  }
+}
+__device__ inline void block_max_pos(unsigned long long* ctr, double v) {
+  __shared__ double part_max[TPB / 64];
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) v = fmax(v, __shfl_xor(v, s));
+  if (__lane_id() == 0) part_max[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < int(blockDim.x / 64); ++w) t = fmax(t, part_max[w]);
+    if (t > 0.0) atomic_max_pos(ctr, t);
+  }
 }
 
 __device__ inline double pressure(const double q[4], double g) {
@@ -628,6 +651,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
   const int NE = d.NE;
   const int nitems = use_list ? d.scal->n_live : NE;
   const double g = P.gamma;
+  unsigned long long npred = 0;    // predictors evaluated (counted on node 0)
   const int wv = threadIdx.x / 64, lw = threadIdx.x % 64;
   const bool spare = lw >= EPW * G;
   const int slot = spare ? SLOTS + wv : wv * EPW + lw / G;
@@ -656,7 +680,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
     const int st = i >= 0 ? d.ts[i].step : 0;
     const bool live = st > 0;           // uniform across the lanes of the element
     const bool act = live && node;
-    if (live && m == 0) wave_count(&d.scal->n_pred);
+    if (live && m == 0) ++npred;
     const double dt = live ? double(st) * elem_delta(d, i) : 1.0;
     const double idt = 1.0 / dt;
     double q[T][4], x[T][2];
@@ -920,6 +944,7 @@ __global__ void __launch_bounds__(TPB) k_predict(Dev d, const Tables* __restrict
       }
     }
   }
+  block_add(&d.scal->n_pred, npred);
 }
 
 // ---------------------------------------------------------------------------
@@ -1058,6 +1083,7 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
   const int cycle = d.scal->cycle;
   constexpr int T = M + 1, VV = Sz<M>::VV;
   const int NV = d.NV;
+  unsigned long long nmoved = 0;   // nodes moved by this lane
   if (blockIdx.x == 0 && threadIdx.x == 0) d.scal->updates += (unsigned long long)d.scal->n_active;
   for (int k = xcd_block() * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x) {
     const int r0 = d.ring_ptr[k], r1 = d.ring_ptr[k + 1];
@@ -1118,8 +1144,9 @@ __global__ void __launch_bounds__(TPB) k_node(Dev d, const Tables* __restrict__ 
     d.Xnew[NV + k] = d.X[NV + k] + dtk * Vy;
     d.ntick_new[k] = newt;
     d.node_stamp[k] = cycle;
-    wave_count(&d.scal->n_node);
+    ++nmoved;
   }
+  block_add(&d.scal->n_node, nmoved);
 }
 
 // ---------------------------------------------------------------------------
@@ -1134,6 +1161,7 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
   constexpr int T = M + 1, nG = M + 1, TS = Sz<M>::TS;
   const int NV = d.NV, NF = d.NF;
   const double g = P.gamma;
+  unsigned long long npatch = 0;   // patches integrated by this lane
   for (int e = xcd_block() * blockDim.x + threadIdx.x; e < NF; e += gridDim.x * blockDim.x) {
     const int a = d.e_a[e], b = d.e_b[e];
     const bool ma = d.node_stamp[a] == cycle, mb = d.node_stamp[b] == cycle;
@@ -1262,8 +1290,9 @@ __global__ void __launch_bounds__(TPB) k_patch(Dev d, const Tables* __restrict__
 #pragma unroll
       for (int k = 0; k < 3; ++k) sr[4 + k] = mR[4 + k] + Nn[k];
     }
-    wave_count(&d.scal->n_patch);
+    ++npatch;
   }
+  block_add(&d.scal->n_patch, npatch);
 }
 
 // ---------------------------------------------------------------------------
@@ -1327,10 +1356,7 @@ __global__ void __launch_bounds__(TPB) k_update(Dev d, Params P) {
         d.ntick[nd[k]] = d.ntick_new[nd[k]];
       }
   }
-  // one atomic per wavefront
-#pragma unroll
-  for (int s = 1; s < 64; s <<= 1) gmax = fmax(gmax, __shfl_xor(gmax, s));
-  if (__lane_id() == 0 && gmax > 0.0) atomic_max_pos(&d.scal->max_gcl_bits, gmax);
+  block_max_pos(&d.scal->max_gcl_bits, gmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -1342,25 +1368,73 @@ __global__ void __launch_bounds__(TPB) k_reset_min(Dev d) {
 }
 
 // Smallest CFL step per instance. Instances own contiguous element ranges, so
-// a wavefront spans one instance except at range ends: one atomic per
-// wavefront then, one per lane otherwise.
+// a wavefront's 64 consecutive elements belong to one instance except at range
+// ends: their minimum then, else each lane's, goes to the instance. A
+// workgroup takes MIN_U such rows per wavefront and merges its wavefronts'
+// minima first, so a single instance takes one atomic per workgroup (atomics
+// on one address serialise).
+constexpr int MIN_U = 4;
 __global__ void __launch_bounds__(TPB) k_min_dt(Dev d) {
-  for (int base = blockIdx.x * blockDim.x; base < d.NE; base += gridDim.x * blockDim.x) {
-    const int i = base + threadIdx.x;
-    const bool in = i < d.NE;
-    const int k = in ? d.e_inst[i] : -1;
-    // a lane without a finite positive step takes no part (and raised ERR_DT)
-    double m = in ? d.dtcfl[i] : DBL_MAX;
-    if (!(m > 0.0 && m < DBL_MAX)) m = DBL_MAX;
-    const int k0 = __shfl(k, 0), klast = __shfl(k, 63);
-    if (k0 == klast) {
+  constexpr int WPB = TPB / 64;
+  __shared__ int wk[WPB];
+  __shared__ double wm[WPB];
+  const int NE = d.NE, lane = __lane_id(), wv = threadIdx.x / 64;
+  for (int base = blockIdx.x * blockDim.x * MIN_U; base < NE; base += gridDim.x * blockDim.x * MIN_U) {
+    int ku[MIN_U];
+    double mu[MIN_U];
 #pragma unroll
-      for (int s = 1; s < 64; s <<= 1) m = fmin(m, __shfl_xor(m, s));
-      if (__lane_id() == 0 && k0 >= 0 && m < DBL_MAX)
-        atomicMin(&d.inst[k0].min_dt_bits, (unsigned long long)__double_as_longlong(m));
-    } else if (in && m < DBL_MAX) {
-      atomicMin(&d.inst[k].min_dt_bits, (unsigned long long)__double_as_longlong(m));
+    for (int u = 0; u < MIN_U; ++u) {
+      const int i = base + (u * WPB + wv) * 64 + lane;
+      ku[u] = i < NE ? d.e_inst[i] : -1;
+      // a lane without a finite positive step takes no part (and raised ERR_DT)
+      const double m = i < NE ? d.dtcfl[i] : DBL_MAX;
+      mu[u] = m > 0.0 && m < DBL_MAX ? m : DBL_MAX;
     }
+    int kw = -1;          // the wavefront's instance and minimum over its uniform rows
+    double mw = DBL_MAX;
+#pragma unroll
+    for (int u = 0; u < MIN_U; ++u) {
+      const int k0 = __shfl(ku[u], 0), klast = __shfl(ku[u], 63);
+      double m = mu[u];
+      if (k0 == klast) {
+#pragma unroll
+        for (int s = 1; s < 64; s <<= 1) m = fmin(m, __shfl_xor(m, s));
+        if (k0 < 0) continue;
+        if (k0 != kw) {
+          if (lane == 0 && kw >= 0 && mw < DBL_MAX)
+            atomicMin(&d.inst[kw].min_dt_bits, (unsigned long long)__double_as_longlong(mw));
+          kw = k0;
+          mw = m;
+        } else {
+          mw = fmin(mw, m);
+        }
+      } else if (ku[u] >= 0 && m < DBL_MAX) {
+        atomicMin(&d.inst[ku[u]].min_dt_bits, (unsigned long long)__double_as_longlong(m));
+      }
+    }
+    if (lane == 0) {
+      wk[wv] = kw;
+      wm[wv] = mw;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int kc = -1;
+      double mc = DBL_MAX;
+      for (int w = 0; w < WPB; ++w) {
+        if (wk[w] < 0) continue;
+        if (wk[w] != kc) {
+          if (kc >= 0 && mc < DBL_MAX)
+            atomicMin(&d.inst[kc].min_dt_bits, (unsigned long long)__double_as_longlong(mc));
+          kc = wk[w];
+          mc = wm[w];
+        } else {
+          mc = fmin(mc, wm[w]);
+        }
+      }
+      if (kc >= 0 && mc < DBL_MAX)
+        atomicMin(&d.inst[kc].min_dt_bits, (unsigned long long)__double_as_longlong(mc));
+    }
+    __syncthreads();
   }
 }
 
@@ -1476,12 +1550,20 @@ __global__ void __launch_bounds__(TPB) k_count_open(Dev d) {
 __global__ void k_count_reset(Dev d) { d.scal->n_unfinished = 0; }
 
 __global__ void __launch_bounds__(TPB) k_count(Dev d) {
+  __shared__ int part[TPB / 64];
   const int N = d.scal->N;
-  for (int base = blockIdx.x * blockDim.x; base < d.NE; base += gridDim.x * blockDim.x) {
-    const int i = base + threadIdx.x;
-    const bool unf = i < d.NE && d.ts[i].tick < N;
-    const unsigned long long m = __ballot(unf);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&d.scal->n_unfinished, __popcll(m));
+  int c = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.NE; i += gridDim.x * blockDim.x)
+    c += d.ts[i].tick < N ? 1 : 0;
+  // one atomic per workgroup
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) c += __shfl_xor(c, s);
+  if (__lane_id() == 0) part[threadIdx.x / 64] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < TPB / 64; ++w) t += part[w];
+    if (t) atomicAdd(&d.scal->n_unfinished, t);
   }
 }
 
@@ -1664,7 +1746,7 @@ int launch_set_target(const Dev& d, double t_end, void* s) {
 
 int launch_macro_begin(const Dev& d, int N, int nominal, double fraction, void* s) {
   AW_LAUNCH(k_reset_min, d.K, s, d);
-  AW_LAUNCH(k_min_dt, d.NE, s, d);
+  AW_LAUNCH(k_min_dt, (long(d.NE) + MIN_U - 1) / MIN_U, s, d);
   AW_LAUNCH(k_macro_setup, d.K, s, d, N, fraction, double(nominal) / double(N));
   AW_LAUNCH(k_levels, d.NE > d.NV ? d.NE : d.NV, s, d);
   return 0;
@@ -1720,7 +1802,10 @@ int launch_update(const Dev& d, const Params& p, void* s) {
 
 int launch_status(const Dev& d, void* s) {
   AW_LAUNCH1(k_count_reset, s, d);
-  AW_LAUNCH(k_count, d.NE, s, d);
+  {
+    const int g = grid_for(d.NE), cap = 2 * (d.n_cu > 0 ? d.n_cu : 256);
+    AW_LAUNCH_G(k_count, g < cap ? g : cap, s, d);
+  }
   return 0;
 }
 
