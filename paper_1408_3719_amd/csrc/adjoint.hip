@@ -1997,19 +1997,41 @@ __global__ void __launch_bounds__(TPB) k_lts_clear_counts(LtsWork lw) {
   if (blockIdx.x == 0 && threadIdx.x < 3) lw.counts[threadIdx.x] = 0;
 }
 
+// Appends the flagged items of one workgroup pass to a global list with one
+// atomic per workgroup (atomics on one address serialise); every thread of the
+// workgroup calls it. The order of a list is free: each item is processed on
+// its own. sh: TPB + 2 ints of LDS.
+__device__ inline void block_append(int* list, int* counter, bool flag, int item, int* sh) {
+  if (threadIdx.x == 0) sh[TPB] = 0;
+  __syncthreads();
+  if (flag) sh[atomicAdd(&sh[TPB], 1)] = item;
+  __syncthreads();
+  const int cnt = sh[TPB];
+  if (threadIdx.x == 0) sh[TPB + 1] = cnt ? atomicAdd(counter, cnt) : 0;
+  __syncthreads();
+  const int base = sh[TPB + 1];
+  for (int k = threadIdx.x; k < cnt; k += blockDim.x) list[base + k] = sh[k];
+  __syncthreads();
+}
+
 // Flags and lists of the cycle from the ticks on both sides of it; all = 1:
 // every element updated and predicted, no node moved.
 __global__ void __launch_bounds__(TPB) k_lts_marks(Dev d, LtsWork lw, int all) {
+  __shared__ int sh[TPB + 2];
   const int NE = d.NE, NV = d.NV;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += gridDim.x * blockDim.x) {
-    int f = 3;
-    if (!all) {
-      const int t0 = lw.s0.ts[i].tick, t1 = lw.s1.ts[i].tick;
-      f = t1 != t0 ? (1 | (t1 < MACRO_TICKS ? 2 : 0)) : 0;
+  for (int base = blockIdx.x * blockDim.x; base < NE; base += gridDim.x * blockDim.x) {
+    const int i = base + threadIdx.x;
+    int f = 0;
+    if (i < NE) {
+      f = 3;
+      if (!all) {
+        const int t0 = lw.s0.ts[i].tick, t1 = lw.s1.ts[i].tick;
+        f = t1 != t0 ? (1 | (t1 < MACRO_TICKS ? 2 : 0)) : 0;
+      }
+      lw.eflag[i] = f;
     }
-    lw.eflag[i] = f;
-    if (f & 1) lw.act_list[atomicAdd(&lw.counts[0], 1)] = i;
-    if (f & 2) lw.going_list[atomicAdd(&lw.counts[1], 1)] = i;
+    block_append(lw.act_list, &lw.counts[0], (f & 1) != 0, i, sh);
+    block_append(lw.going_list, &lw.counts[1], (f & 2) != 0, i, sh);
   }
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NV; k += gridDim.x * blockDim.x)
     lw.nflag[k] = all ? 0 : int(lw.s1.ntick[k] != lw.s0.ntick[k]);
@@ -2017,8 +2039,13 @@ __global__ void __launch_bounds__(TPB) k_lts_marks(Dev d, LtsWork lw, int all) {
 
 // The swept edges (a moved end) listed.
 __global__ void __launch_bounds__(TPB) k_lts_edges(Dev d, LtsWork lw) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < d.NF; e += gridDim.x * blockDim.x)
-    if (lw.nflag[d.e_a[e]] || lw.nflag[d.e_b[e]]) lw.edge_list[atomicAdd(&lw.counts[2], 1)] = e;
+  __shared__ int sh[TPB + 2];
+  const int NF = d.NF;
+  for (int base = blockIdx.x * blockDim.x; base < NF; base += gridDim.x * blockDim.x) {
+    const int e = base + threadIdx.x;
+    const bool swept = e < NF && (lw.nflag[d.e_a[e]] || lw.nflag[d.e_b[e]]);
+    block_append(lw.edge_list, &lw.counts[2], swept, e, sh);
+  }
 }
 
 // Per element j, 8 lanes: the own terms of its reconstruction (updated j) and
