@@ -965,9 +965,10 @@ __global__ void k_cycle_begin(Dev d) {
 // next one at the macro-step start, and no stage reads it before).
 constexpr int SCHED_CHUNK = 1024;
 
-__global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
+constexpr int SCHED_TPB = 1024;   // 16 wavefronts: a chunk of 1024 elements in 8 passes
+__global__ void __launch_bounds__(SCHED_TPB) k_sched(Dev d, int chunk) {
   const int cycle = d.scal->cycle;
-  constexpr int PER_PASS = TPB / 8;
+  constexpr int PER_PASS = SCHED_TPB / 8;
   __shared__ int local[SCHED_CHUNK], local_live[SCHED_CHUNK];
   __shared__ int count, gbase, count_live, gbase_live;
   const int NE = d.NE;
@@ -1071,8 +1072,8 @@ __global__ void __launch_bounds__(TPB) k_sched(Dev d, int chunk) {
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < count; k += TPB) d.act_list[gbase + k] = local[k];
-  for (int k = threadIdx.x; k < count_live; k += TPB) d.live_list[gbase_live + k] = local_live[k];
+  for (int k = threadIdx.x; k < count; k += SCHED_TPB) d.act_list[gbase + k] = local[k];
+  for (int k = threadIdx.x; k < count_live; k += SCHED_TPB) d.live_list[gbase_live + k] = local_live[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -1663,19 +1664,20 @@ int grid_for(long n) {
 // than from markers queued before and after it.
 thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
 
-#define AW_LAUNCH_G(kern, grid, stream, ...)                                                        \
+#define AW_LAUNCH_GB(kern, grid, block, stream, ...)                                                \
   do {                                                                                              \
     if (t_ev_start) {                                                                               \
       hipEvent_t _a = t_ev_start, _b = t_ev_stop;                                                   \
       t_ev_start = t_ev_stop = nullptr;                                                             \
-      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(TPB), 0, (hipStream_t)(stream), _a, _b, 0,       \
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), _a, _b, 0,     \
                             __VA_ARGS__);                                                           \
     } else {                                                                                        \
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(TPB), 0, (hipStream_t)(stream), __VA_ARGS__);       \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__);     \
     }                                                                                               \
     hipError_t _e = hipGetLastError();                                                              \
     if (_e != hipSuccess) return int(_e);                                                           \
   } while (0)
+#define AW_LAUNCH_G(kern, grid, stream, ...) AW_LAUNCH_GB(kern, grid, TPB, stream, __VA_ARGS__)
 
 #define AW_LAUNCH(kern, n, stream, ...) AW_LAUNCH_G(kern, grid_for(n), stream, __VA_ARGS__)
 
@@ -1759,11 +1761,13 @@ int launch_cycle_begin(const Dev& d, void* s) {
 
 int launch_sched(const Dev& d, void* s) {
   // chunks of at most SCHED_CHUNK elements, at least ~1024 blocks when possible,
-  // unless a chunk size was chosen
+  // unless a chunk size was chosen; at least one pass of SCHED_TPB / 8 elements.
+  // Each block reserves its list space with one atomic, and atomics on one
+  // address serialise, so larger chunks mean fewer of them.
   int chunk = d.sched_chunk > 0 ? d.sched_chunk : (d.NE + 1023) / 1024;
-  chunk = chunk < TPB / 8 ? TPB / 8 : (chunk > SCHED_CHUNK ? SCHED_CHUNK : chunk);
+  chunk = chunk < SCHED_TPB / 8 ? SCHED_TPB / 8 : (chunk > SCHED_CHUNK ? SCHED_CHUNK : chunk);
   const int blocks = (d.NE + chunk - 1) / chunk;
-  AW_LAUNCH_G(k_sched, blocks, s, d, chunk);
+  AW_LAUNCH_GB(k_sched, blocks, SCHED_TPB, s, d, chunk);
   return 0;
 }
 
