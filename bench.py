@@ -55,12 +55,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1408_3719_amd", "csrc", n) for n in 
 TRAFFIC_SWEEP = (0, 4, 8, 16, 32)
 MEASURED_TRAFFIC = {
     "workload": "explosion",
-    "source_sha256": "42297c306aff194ee9474217a410ef05cb3a2eb46fb64e2383c39661a72ef1b4",
-    "k_reconstruct": {0: 1713, 4: 1774, 8: 1746, 16: 1727, 32: 1720},
-    "k_predict": {0: 1504, 4: 1506, 8: 1506, 16: 1505, 32: 1505},
-    "k_patch": {0: 1042, 4: 1071, 8: 1049, 16: 1041, 32: 1042},
-    "k_update": {0: 734, 4: 735, 8: 734, 16: 734, 32: 733},
-    "k_node": {0: 1774, 4: 1775, 8: 1775, 16: 1775, 32: 1775},
+    "source_sha256": "9a8b6ba5a837561b330d64f70a288df398708a542e0cd68f2993f1ee46cb8014",
+    "k_reconstruct": {0: 1552, 4: 1606, 8: 1583, 16: 1564, 32: 1557},
+    "k_predict": {0: 1501, 4: 1502, 8: 1502, 16: 1502, 32: 1502},
+    "k_patch": {0: 1042, 4: 1072, 8: 1048, 16: 1042, 32: 1042},
+    "k_update": {0: 724, 4: 726, 8: 724, 16: 724, 32: 724},
+    "k_node": {w: 1775 for w in TRAFFIC_SWEEP},
     "k_sched": {w: 88 for w in TRAFFIC_SWEEP},
 }
 
